@@ -1,0 +1,645 @@
+/*
+ * FP64 oracle for the HEEPS/MARE facet-sum path (Monnier et al., "Synthetic
+ * RAW data generator for ESA HARMONY mission").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only tests/, __graft_entry__.smoke() and the
+ * cpu_baseline leg of bench.py may load this library.  The product (the HIP
+ * library and its Python binding) never links, imports or calls it, and this
+ * file shares no code, header, table or constant generator with it.
+ *
+ * Everything is the plain definition, evaluated directly in double precision
+ * with libm: no spatial blocks, no Taylor forms, no reordering.  Where the
+ * paper is silent the reading used is stated next to the code.
+ *
+ * Parity status of each function (see the tests under tests/test_oracle_*):
+ *   og_pulse_time, og_pulse_geometry   pinned (closed forms, lone target)
+ *   og_kappa, og_gain                  pinned (boresight, 3-dB point)
+ *   og_tap                             pinned (numpy.sinc * numpy.i0)
+ *   og_forward                         pinned (lone/off-grid target, Doppler
+ *                                      of eq. 4, linearity, mpmath brute force)
+ *   og_adjoint                         pinned (dot-product test, finite
+ *                                      differences of og_forward)
+ *   og_chirp, og_waveform[_adjoint]    pinned (numpy FFT convolution, matched
+ *                                      filter peak, adjoint identity)
+ *   og_philox4x32_10                   bit patterns: parity unpinned (no
+ *                                      external known-answer vectors);
+ *                                      statistical pins only
+ *   og_generate_facets                 pinned (closed-form moments, dispersion,
+ *                                      d(eta)/dt = w, chunk invariance)
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OG_MAXP 8
+#define OG_MAXA 8
+#define OG_MAXC 16
+
+typedef struct {
+    double c, f0, fs, prf;
+    int n_samples, n_pulses, n_ref;
+    double kaiser_beta, chirp_bw, chirp_T;
+    int n_plat;
+    double plat_p0[OG_MAXP][3];
+    double plat_v[OG_MAXP][3];
+    int n_ant;
+    int ant_plat[OG_MAXA];
+    double ant_beta_az[OG_MAXA];
+    double ant_beta_el[OG_MAXA];
+    int n_ch;
+    int ch_tx[OG_MAXC];
+    int ch_rx[OG_MAXC];
+    double ch_off[OG_MAXC][3];
+} og_config;
+
+static const double OG_PI = 3.14159265358979323846;
+
+static double dot3(const double *a, const double *b) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+static double norm3(const double *a) { return sqrt(dot3(a, a)); }
+
+/* ---- Pulse timing and platform motion --------------------------------- */
+
+/* Pulse time origin is silent in the paper; reading: centred on the dwell. */
+double og_pulse_time(const og_config *g, int p) {
+    return ((double)p - 0.5 * (double)(g->n_pulses - 1)) / g->prf;
+}
+
+static void plat_pos(const og_config *g, int plat, double t, double *out) {
+    for (int k = 0; k < 3; ++k) out[k] = g->plat_p0[plat][k] + g->plat_v[plat][k] * t;
+}
+
+/* Tx phase centre: the Tx antenna's platform. */
+static void tx_pos(const og_config *g, int ch, double t, double *out) {
+    plat_pos(g, g->ant_plat[g->ch_tx[ch]], t, out);
+}
+
+/* Rx phase centre: the Rx antenna's platform plus the channel's offset. */
+static void rx_pos(const og_config *g, int ch, double t, double *out) {
+    plat_pos(g, g->ant_plat[g->ch_rx[ch]], t, out);
+    for (int k = 0; k < 3; ++k) out[k] += g->ch_off[ch][k];
+}
+
+/*
+ * Per-pulse geometry (eq. 3 evaluates r_t at the transmit time and r_r at the
+ * reception time).  Reading: Tx at the pulse time t_p; Rx at t_p + tau_ref,
+ * where tau_ref is the echo delay of the scene origin O, found as the fixed
+ * point of  c*tau = |O - P_tx(t_p)| + |O - P_rx(t_p + tau)|.
+ */
+void og_pulse_geometry(const og_config *g, int ch, int p, double *t_out,
+                       double *ptx, double *prx, double *tau_out) {
+    double t = og_pulse_time(g, p);
+    tx_pos(g, ch, t, ptx);
+    double rt = norm3(ptx);                 /* |O - P_tx|, O = origin */
+    double tau = 2.0 * rt / g->c;
+    for (int it = 0; it < 50; ++it) {
+        rx_pos(g, ch, t + tau, prx);
+        double nt = (rt + norm3(prx)) / g->c;
+        if (nt == tau) break;
+        tau = nt;
+    }
+    rx_pos(g, ch, t + tau, prx);
+    *t_out = t;
+    *tau_out = tau;
+}
+
+/* ---- Antenna model ---------------------------------------------------- */
+
+static double sinc(double x) {
+    if (x == 0.0) return 1.0;
+    double px = OG_PI * x;
+    return sin(px) / px;
+}
+
+/* d sinc / dx */
+static double dsinc(double x) {
+    if (x == 0.0) return 0.0;
+    double px = OG_PI * x;
+    return (cos(px) - sin(px) / px) / x;
+}
+
+/* kappa such that sinc(kappa/2)^2 = 1/2: the sinc^2 power pattern then has
+ * its one-way 3-dB full width equal to beta. */
+double og_kappa(void) {
+    double lo = 0.0, hi = 1.0, target = sqrt(0.5);
+    for (int i = 0; i < 200; ++i) {
+        double mid = 0.5 * (lo + hi);
+        if (sinc(mid) > target) lo = mid; else hi = mid;
+    }
+    return lo + hi;  /* 2 * midpoint */
+}
+
+/*
+ * Antenna frame (reading of "all 3 antennas mechanically point to the same
+ * surface target", stripmap, frames fixed over the dwell): boresight b = unit
+ * vector from the platform position at t = 0 to O, azimuth axis = along-track
+ * x projected orthogonal to b, elevation axis = b x az.
+ */
+void og_antenna_frame(const og_config *g, int ant, double *b, double *az, double *el) {
+    double p[3];
+    plat_pos(g, g->ant_plat[ant], 0.0, p);
+    double r = norm3(p);
+    for (int k = 0; k < 3; ++k) b[k] = -p[k] / r;
+    double xh[3] = {1.0, 0.0, 0.0};
+    double d = dot3(xh, b);
+    for (int k = 0; k < 3; ++k) az[k] = xh[k] - d * b[k];
+    double na = norm3(az);
+    for (int k = 0; k < 3; ++k) az[k] /= na;
+    el[0] = b[1] * az[2] - b[2] * az[1];
+    el[1] = b[2] * az[0] - b[0] * az[2];
+    el[2] = b[0] * az[1] - b[1] * az[0];
+}
+
+/* Per-antenna constants: frame and pattern scale factors. */
+typedef struct {
+    double b[3], az[3], el[3];
+    double ka, ke;            /* kappa / beta_az, kappa / beta_el */
+} og_ant;
+
+static void make_ant(const og_config *g, int ant, double kap, og_ant *a) {
+    og_antenna_frame(g, ant, a->b, a->az, a->el);
+    a->ka = kap / g->ant_beta_az[ant];
+    a->ke = kap / g->ant_beta_el[ant];
+}
+
+/*
+ * One-way field pattern of an antenna (eq. 16 weights each facet by the Tx and
+ * Rx complex gains).  Reading of "sinc^2 antennas (az, el widths)": sinc^2 is
+ * the one-way power pattern with those 3-dB widths, so the field is
+ * F = sinc(kappa*u/beta_az) * sinc(kappa*v/beta_el), u, v the direction
+ * cosines of the unit vector antenna->facet on the az / el axes; F = 0 behind
+ * the antenna.  grad (optional) receives dF/dX.
+ */
+static double gain(const og_ant *a, const double *pa, const double *x, double *grad) {
+    double d[3] = {x[0] - pa[0], x[1] - pa[1], x[2] - pa[2]};
+    double r = norm3(d);
+    double rh[3] = {d[0] / r, d[1] / r, d[2] / r};
+    if (dot3(rh, a->b) <= 0.0) {
+        if (grad) grad[0] = grad[1] = grad[2] = 0.0;
+        return 0.0;
+    }
+    double u = dot3(rh, a->az), v = dot3(rh, a->el);
+    double su = sinc(a->ka * u), sv = sinc(a->ke * v);
+    if (grad) {
+        double dsu = a->ka * dsinc(a->ka * u), dsv = a->ke * dsinc(a->ke * v);
+        for (int k = 0; k < 3; ++k) {
+            double du = (a->az[k] - u * rh[k]) / r;   /* d(rh.az)/dX */
+            double dv = (a->el[k] - v * rh[k]) / r;
+            grad[k] = dsu * sv * du + su * dsv * dv;
+        }
+    }
+    return su * sv;
+}
+
+/* Public single-evaluation form (tests). */
+double og_gain(const og_config *g, int ant, const double *pa, const double *x,
+               double *grad) {
+    og_ant a;
+    make_ant(g, ant, og_kappa(), &a);
+    return gain(&a, pa, x, grad);
+}
+
+/* ---- Range interpolator (deposit into range slices, eq. 17) ----------- */
+
+/* Modified Bessel I0 by its power series. */
+static double bessel_i0(double x) {
+    double term = 1.0, sum = 1.0, q = 0.25 * x * x;
+    for (int k = 1; k < 500; ++k) {
+        term *= q / ((double)k * (double)k);
+        sum += term;
+        if (term < 1e-17 * sum) break;
+    }
+    return sum;
+}
+
+/* I1(x)/x by its power series (finite at x = 0). */
+static double bessel_i1_over_x(double x) {
+    double term = 0.5, sum = 0.5, q = 0.25 * x * x;
+    for (int k = 1; k < 500; ++k) {
+        term *= q / ((double)k * (double)(k + 1));
+        sum += term;
+        if (term < 1e-17 * sum) break;
+    }
+    return sum;
+}
+
+/*
+ * Reading of eq. 17's range slices: instead of a box, each contribution is
+ * spread over 8 samples with a Kaiser-windowed sinc of half-width 4:
+ * h(t) = sinc(t) * I0(beta*sqrt(1-(t/4)^2)) / I0(beta), |t| <= 4, else 0.
+ * i0b = I0(beta).
+ */
+static double tap(double t, double beta, double i0b) {
+    if (fabs(t) > 4.0) return 0.0;
+    double s = 1.0 - (t / 4.0) * (t / 4.0);
+    if (s < 0.0) s = 0.0;
+    return sinc(t) * bessel_i0(beta * sqrt(s)) / i0b;
+}
+
+/* dh/dt: sinc'(t) W(t) + sinc(t) W'(t), W'(t) = I1(beta s) beta ds/dt / I0(beta),
+ * s = sqrt(1 - (t/4)^2), ds/dt = -t / (16 s). */
+static double dtap(double t, double beta, double i0b) {
+    if (fabs(t) > 4.0) return 0.0;
+    double s2 = 1.0 - (t / 4.0) * (t / 4.0);
+    if (s2 < 0.0) s2 = 0.0;
+    double s = sqrt(s2);
+    double w = bessel_i0(beta * s) / i0b;
+    double dw = -bessel_i1_over_x(beta * s) * beta * beta * t / 16.0 / i0b;
+    return dsinc(t) * w + sinc(t) * dw;
+}
+
+double og_tap(double t, double beta) { return tap(t, beta, bessel_i0(beta)); }
+double og_dtap(double t, double beta) { return dtap(t, beta, bessel_i0(beta)); }
+
+/* ---- Per-(channel, pulse) row quantities ------------------------------ */
+
+typedef struct {
+    double t, tau, rref;
+    double ptx[3], prx[3];
+    double rt_mid, rr_mid;
+} og_row;
+
+/* Per-call constants: antenna frames and I0(beta). */
+typedef struct {
+    og_ant ant[OG_MAXA];
+    double i0b;
+} og_ctx;
+
+static void make_ctx(const og_config *g, og_ctx *cx) {
+    double kap = og_kappa();
+    for (int a = 0; a < g->n_ant; ++a) make_ant(g, a, kap, &cx->ant[a]);
+    cx->i0b = bessel_i0(g->kaiser_beta);
+}
+
+static void make_row(const og_config *g, int ch, int p, og_row *r) {
+    og_pulse_geometry(g, ch, p, &r->t, r->ptx, r->prx, &r->tau);
+    r->rref = g->c * r->tau;
+    double p0[3];
+    tx_pos(g, ch, 0.0, p0);
+    r->rt_mid = norm3(p0);
+    rx_pos(g, ch, 0.0, p0);
+    r->rr_mid = norm3(p0);
+}
+
+/*
+ * One facet's contribution to one (channel, pulse) row: eq. 3 / eq. 16.
+ * Outputs the complex weight W = a * Ftx * Frx * S * exp(j*phi) and the
+ * fractional sample position u of the bistatic range in the tracking window.
+ *   X = X0 + V t_p (linear facet motion over the dwell)
+ *   R = |X - P_tx| + |X - P_rx|,  phi = -2 pi f0 R / c   (e^{-i K0 (r_t + r_r)})
+ *   u = n_ref + (R - c tau_ref) fs / c
+ *   S = (R_t,mid R_r,mid) / (R_t R_r)   (1/(r_t r_r) spreading, normalised
+ *       to the scene-origin ranges at t = 0; other constants set to 1)
+ */
+static void contribution(const og_config *g, const og_ctx *cx, int ch, const og_row *r,
+                         const double *x0, const double *v, double are, double aim,
+                         double *wre, double *wim, double *u) {
+    double X[3];
+    for (int k = 0; k < 3; ++k) X[k] = x0[k] + v[k] * r->t;
+    double dt[3] = {X[0] - r->ptx[0], X[1] - r->ptx[1], X[2] - r->ptx[2]};
+    double dr[3] = {X[0] - r->prx[0], X[1] - r->prx[1], X[2] - r->prx[2]};
+    double Rt = norm3(dt), Rr = norm3(dr), R = Rt + Rr;
+    double ft = gain(&cx->ant[g->ch_tx[ch]], r->ptx, X, NULL);
+    double fr = gain(&cx->ant[g->ch_rx[ch]], r->prx, X, NULL);
+    double S = (r->rt_mid * r->rr_mid) / (Rt * Rr);
+    double phi = -2.0 * OG_PI * g->f0 * R / g->c;
+    double amp = ft * fr * S;
+    double c = cos(phi), s = sin(phi);
+    *wre = amp * (are * c - aim * s);
+    *wim = amp * (are * s + aim * c);
+    *u = (double)g->n_ref + (R - r->rref) * g->fs / g->c;
+}
+
+/*
+ * Forward sum: iq[c][p - p0][n] (interleaved re, im) for channels 0..n_ch-1,
+ * pulses [p0, p0 + np).  Each (c, p) row is independent (parallel, no races).
+ * Taps outside [0, N) are dropped.
+ */
+void og_forward(const og_config *g, long long nf, const double *x, const double *y,
+                const double *z, const double *vx, const double *vy, const double *vz,
+                const double *are, const double *aim, int p0, int np, double *iq) {
+    const int N = g->n_samples;
+    const long long rows = (long long)g->n_ch * np;
+    memset(iq, 0, sizeof(double) * 2 * (size_t)rows * (size_t)N);
+    og_ctx cx;
+    make_ctx(g, &cx);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long long row = 0; row < rows; ++row) {
+        int ch = (int)(row / np), p = p0 + (int)(row % np);
+        og_row r;
+        make_row(g, ch, p, &r);
+        double *out = iq + 2 * (size_t)row * (size_t)N;
+        for (long long i = 0; i < nf; ++i) {
+            double X0[3] = {x[i], y[i], z[i]}, V[3] = {vx[i], vy[i], vz[i]};
+            double wre, wim, u;
+            contribution(g, &cx, ch, &r, X0, V, are[i], aim[i], &wre, &wim, &u);
+            long long n0 = (long long)floor(u);
+            for (long long n = n0 - 3; n <= n0 + 4; ++n) {
+                if (n < 0 || n >= N) continue;
+                double h = tap((double)n - u, g->kaiser_beta, cx.i0b);
+                out[2 * n] += wre * h;
+                out[2 * n + 1] += wim * h;
+            }
+        }
+    }
+}
+
+/*
+ * Adjoint of og_forward with respect to facet height z, velocity V and
+ * complex amplitude a.  g_iq holds dL/dRe(IQ) + j dL/dIm(IQ) in the layout of
+ * og_forward's output.  Returns dL/dz, dL/dV (components), dL/dRe a and
+ * dL/dIm a.  Each facet is independent (parallel, deterministic).
+ *
+ * With B = sum_n conj(g_n) h(n - u), B' = sum_n conj(g_n) h'(n - u),
+ * T = Ftx Frx S, E = exp(j phi), P = B a E:
+ *   dL/da       = conj(B T E)
+ *   dL/dX       = Re(P) grad T + [Im(P) T K0 - Re(B' a T E) fs/c] grad R
+ *   dL/dz       = sum_p (dL/dX)_z,   dL/dV = sum_p t_p dL/dX
+ * where grad R = unit(X - P_tx) + unit(X - P_rx), K0 = 2 pi f0 / c.
+ */
+void og_adjoint(const og_config *g, long long nf, const double *x, const double *y,
+                const double *z, const double *vx, const double *vy, const double *vz,
+                const double *are, const double *aim, int p0, int np,
+                const double *giq, double *dz, double *dvx, double *dvy,
+                double *dvz, double *dare, double *daim) {
+    const int N = g->n_samples;
+    const int rows = g->n_ch * np;
+    og_row *rw = (og_row *)malloc(sizeof(og_row) * (size_t)rows);
+    for (int row = 0; row < rows; ++row) make_row(g, row / np, p0 + row % np, &rw[row]);
+    const double K0 = 2.0 * OG_PI * g->f0 / g->c;
+    og_ctx cx;
+    make_ctx(g, &cx);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long long i = 0; i < nf; ++i) {
+        double X0[3] = {x[i], y[i], z[i]}, V[3] = {vx[i], vy[i], vz[i]};
+        double gz = 0, gv[3] = {0, 0, 0}, gar = 0, gai = 0;
+        for (int row = 0; row < rows; ++row) {
+            const og_row *r = &rw[row];
+            int ch = row / np;
+            double X[3];
+            for (int k = 0; k < 3; ++k) X[k] = X0[k] + V[k] * r->t;
+            double dt[3] = {X[0] - r->ptx[0], X[1] - r->ptx[1], X[2] - r->ptx[2]};
+            double dr[3] = {X[0] - r->prx[0], X[1] - r->prx[1], X[2] - r->prx[2]};
+            double Rt = norm3(dt), Rr = norm3(dr), R = Rt + Rr;
+            double gft[3], gfr[3];
+            double ft = gain(&cx.ant[g->ch_tx[ch]], r->ptx, X, gft);
+            double fr = gain(&cx.ant[g->ch_rx[ch]], r->prx, X, gfr);
+            double S = (r->rt_mid * r->rr_mid) / (Rt * Rr);
+            double T = ft * fr * S;
+            double phi = -2.0 * OG_PI * g->f0 * R / g->c;
+            double Er = cos(phi), Ei = sin(phi);
+            double u = (double)g->n_ref + (R - r->rref) * g->fs / g->c;
+            const double *grow = giq + 2 * (size_t)row * (size_t)N;
+            double Br = 0, Bi = 0, Bpr = 0, Bpi = 0;
+            long long n0 = (long long)floor(u);
+            for (long long n = n0 - 3; n <= n0 + 4; ++n) {
+                if (n < 0 || n >= N) continue;
+                double h = tap((double)n - u, g->kaiser_beta, cx.i0b);
+                double hp = dtap((double)n - u, g->kaiser_beta, cx.i0b);
+                /* conj(g_n) = (gr, -gi) */
+                Br += grow[2 * n] * h;
+                Bi += -grow[2 * n + 1] * h;
+                Bpr += grow[2 * n] * hp;
+                Bpi += -grow[2 * n + 1] * hp;
+            }
+            /* Z = B T E ; grad_a += conj(Z) */
+            double Zr = T * (Br * Er - Bi * Ei), Zi = T * (Br * Ei + Bi * Er);
+            gar += Zr;
+            gai += -Zi;
+            /* P = B a E */
+            double aEr = are[i] * Er - aim[i] * Ei, aEi = are[i] * Ei + aim[i] * Er;
+            double Pr = Br * aEr - Bi * aEi, Pi = Br * aEi + Bi * aEr;
+            /* Re(B' a T E) */
+            double BpW = T * (Bpr * aEr - Bpi * aEi);
+            double cR = Pi * T * K0 - BpW * g->fs / g->c;
+            double gX[3];
+            for (int k = 0; k < 3; ++k) {
+                double rt_k = dt[k] / Rt, rr_k = dr[k] / Rr;
+                double gS = -S * (rt_k / Rt + rr_k / Rr);
+                double gT = fr * S * gft[k] + ft * S * gfr[k] + ft * fr * gS;
+                gX[k] = Pr * gT + cR * (rt_k + rr_k);
+            }
+            gz += gX[2];
+            for (int k = 0; k < 3; ++k) gv[k] += r->t * gX[k];
+        }
+        dz[i] = gz;
+        dvx[i] = gv[0];
+        dvy[i] = gv[1];
+        dvz[i] = gv[2];
+        dare[i] = gar;
+        daim[i] = gai;
+    }
+    free(rw);
+}
+
+/* ---- Waveform (the impulse response is convolved by the waveform) ------ */
+
+/* Reading: unit-amplitude up-chirp centred on the pulse,
+ * chirp[k] = exp(j pi K (k/fs - T/2)^2), k = 0..L-1, L = round(T fs), K = B/T. */
+int og_chirp_len(const og_config *g) { return (int)llround(g->chirp_T * g->fs); }
+
+void og_chirp(const og_config *g, double *out) {
+    int L = og_chirp_len(g);
+    double K = g->chirp_bw / g->chirp_T;
+    for (int k = 0; k < L; ++k) {
+        double t = (double)k / g->fs - 0.5 * g->chirp_T;
+        double ph = OG_PI * K * t * t;
+        out[2 * k] = cos(ph);
+        out[2 * k + 1] = sin(ph);
+    }
+}
+
+/* "Same"-mode linear convolution, raw[n] = sum_m rc[m] chirp[n - m + L/2],
+ * evaluated directly, line by line. */
+void og_waveform(const og_config *g, long long nlines, const double *rc, double *raw) {
+    const int N = g->n_samples, L = og_chirp_len(g), h = L / 2;
+    double *ch = (double *)malloc(sizeof(double) * 2 * (size_t)L);
+    og_chirp(g, ch);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long long l = 0; l < nlines; ++l) {
+        const double *x = rc + 2 * (size_t)l * N;
+        double *y = raw + 2 * (size_t)l * N;
+        for (int n = 0; n < N; ++n) {
+            double sr = 0, si = 0;
+            for (int m = 0; m < N; ++m) {
+                int k = n - m + h;
+                if (k < 0 || k >= L) continue;
+                sr += x[2 * m] * ch[2 * k] - x[2 * m + 1] * ch[2 * k + 1];
+                si += x[2 * m] * ch[2 * k + 1] + x[2 * m + 1] * ch[2 * k];
+            }
+            y[2 * n] = sr;
+            y[2 * n + 1] = si;
+        }
+    }
+    free(ch);
+}
+
+/* Adjoint of og_waveform: g_rc[m] = sum_n g_raw[n] conj(chirp[n - m + L/2]). */
+void og_waveform_adjoint(const og_config *g, long long nlines, const double *graw,
+                         double *grc) {
+    const int N = g->n_samples, L = og_chirp_len(g), h = L / 2;
+    double *ch = (double *)malloc(sizeof(double) * 2 * (size_t)L);
+    og_chirp(g, ch);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long long l = 0; l < nlines; ++l) {
+        const double *x = graw + 2 * (size_t)l * N;
+        double *y = grc + 2 * (size_t)l * N;
+        for (int m = 0; m < N; ++m) {
+            double sr = 0, si = 0;
+            for (int n = 0; n < N; ++n) {
+                int k = n - m + h;
+                if (k < 0 || k >= L) continue;
+                sr += x[2 * n] * ch[2 * k] + x[2 * n + 1] * ch[2 * k + 1];
+                si += x[2 * n + 1] * ch[2 * k] - x[2 * n] * ch[2 * k + 1];
+            }
+            y[2 * m] = sr;
+            y[2 * m + 1] = si;
+        }
+    }
+    free(ch);
+}
+
+/* ---- Counter-based RNG: Philox4x32-10 (Salmon et al., SC'11) ---------- */
+
+/* One Philox round: two 32x32->64 multiplies, the high halves XORed with the
+ * other counter words and the key, words permuted. */
+static void philox_round(uint32_t *ctr, const uint32_t *key) {
+    uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)ctr[0];
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)ctr[2];
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ ctr[1] ^ key[0];
+    uint32_t n1 = lo1;
+    uint32_t n2 = hi0 ^ ctr[3] ^ key[1];
+    uint32_t n3 = lo0;
+    ctr[0] = n0; ctr[1] = n1; ctr[2] = n2; ctr[3] = n3;
+}
+
+void og_philox4x32_10(const uint32_t *ctr_in, const uint32_t *key_in, uint32_t *out) {
+    uint32_t ctr[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
+    uint32_t key[2] = {key_in[0], key_in[1]};
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {               /* Weyl key schedule */
+            key[0] += 0x9E3779B9u;
+            key[1] += 0xBB67AE85u;
+        }
+        philox_round(ctr, key);
+    }
+    memcpy(out, ctr, sizeof(ctr));
+}
+
+/* Four standard normals for facet `index`, stream `stream`: Philox output
+ * words mapped to (0,1) as (w + 1/2) 2^-32, then two Box-Muller pairs. */
+static void normals4(uint64_t seed, uint64_t index, uint32_t stream, double *n) {
+    uint32_t ctr[4] = {(uint32_t)index, (uint32_t)(index >> 32), stream, 0u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    og_philox4x32_10(ctr, key, w);
+    const double sc = 1.0 / 4294967296.0;
+    for (int j = 0; j < 2; ++j) {
+        double u1 = ((double)w[2 * j] + 0.5) * sc;
+        double u2 = ((double)w[2 * j + 1] + 0.5) * sc;
+        double r = sqrt(-2.0 * log(u1));
+        n[2 * j] = r * cos(2.0 * OG_PI * u2);
+        n[2 * j + 1] = r * sin(2.0 * OG_PI * u2);
+    }
+}
+
+/* ---- Sea-surface facets (Sec. III: resolved waves move the grid) ------- */
+
+typedef struct {
+    int nx, ny;            /* full grid, cell centres centred on O */
+    double dx, dy;
+    int mode;              /* 0 flat (iid velocities), 1 linear waves + current */
+    double sigma_v;
+    int n_comp;
+    double k_min, k_max, slope, hs, g;
+    const double *dirs;    /* [n_comp] propagation directions */
+    const double *phases;  /* [n_comp] initial phases */
+    double cur[2];         /* uniform current */
+} og_sea;
+
+/*
+ * Component table (reading of the tile spectrum for a linear surface):
+ * wavenumbers log-spaced over [k_min, k_max]; omnidirectional spectrum
+ * Psi(k) proportional to k^slope; amplitude A_m = sqrt(2 Psi(k_m) dk_m) with
+ * dk_m the local log spacing, scaled so that sum A_m^2 / 2 = (Hs/4)^2;
+ * deep-water dispersion omega^2 = g k.
+ */
+void og_wave_table(const og_sea *s, double *k, double *amp, double *omega) {
+    int n = s->n_comp;
+    double dl = (n > 1) ? log(s->k_max / s->k_min) / (double)(n - 1) : 1.0;
+    double e = 0.0;
+    for (int m = 0; m < n; ++m) {
+        k[m] = (n > 1) ? s->k_min * exp(dl * (double)m) : s->k_min;
+        amp[m] = sqrt(2.0 * pow(k[m], s->slope) * k[m] * dl);
+        e += 0.5 * amp[m] * amp[m];
+        omega[m] = sqrt(s->g * k[m]);
+    }
+    double sig = s->hs / 4.0, f = sig / sqrt(e);
+    for (int m = 0; m < n; ++m) amp[m] *= f;
+}
+
+/*
+ * Facets of the sub-rectangle [ix0, ix0+cnx) x [iy0, iy0+cny), row-major.
+ * Global index = iy*nx + ix is the Philox counter, so any chunking of the grid
+ * yields the same facets.
+ *   a ~ CN(0,1): (n0, n1)/sqrt(2) from stream 0.
+ *   mode 0: z = 0, V = sigma_v (n2, n3, n4), n4 from stream 1.
+ *   mode 1: z = sum A cos(theta), theta = k (cos psi x + sin psi y) + phase,
+ *           horizontal orbital velocity sum A omega (cos psi, sin psi) cos(theta)
+ *           plus the current, vertical velocity sum A omega sin(theta)
+ *           (= d(eta)/dt at the surface).
+ * out: 8 arrays of cnx*cny doubles: x, y, z, vx, vy, vz, a_re, a_im.
+ */
+void og_generate_facets(const og_sea *s, uint64_t seed, int ix0, int iy0, int cnx,
+                        int cny, double *x, double *y, double *z, double *vx,
+                        double *vy, double *vz, double *are, double *aim) {
+    int nc = s->n_comp > 0 ? s->n_comp : 1;
+    double *k = (double *)malloc(sizeof(double) * nc);
+    double *amp = (double *)malloc(sizeof(double) * nc);
+    double *om = (double *)malloc(sizeof(double) * nc);
+    if (s->mode == 1) og_wave_table(s, k, amp, om);
+    long long n = (long long)cnx * cny;
+#pragma omp parallel for schedule(static)
+    for (long long j = 0; j < n; ++j) {
+        int ix = ix0 + (int)(j % cnx), iy = iy0 + (int)(j / cnx);
+        uint64_t gidx = (uint64_t)iy * (uint64_t)s->nx + (uint64_t)ix;
+        double X = ((double)ix - 0.5 * (double)(s->nx - 1)) * s->dx;
+        double Y = ((double)iy - 0.5 * (double)(s->ny - 1)) * s->dy;
+        double nr[4];
+        normals4(seed, gidx, 0u, nr);
+        x[j] = X;
+        y[j] = Y;
+        are[j] = nr[0] / sqrt(2.0);
+        aim[j] = nr[1] / sqrt(2.0);
+        if (s->mode == 0) {
+            double n2[4];
+            normals4(seed, gidx, 1u, n2);
+            z[j] = 0.0;
+            vx[j] = s->sigma_v * nr[2];
+            vy[j] = s->sigma_v * nr[3];
+            vz[j] = s->sigma_v * n2[0];
+        } else {
+            double h = 0, ux = 0, uy = 0, w = 0;
+            for (int m = 0; m < s->n_comp; ++m) {
+                double cp = cos(s->dirs[m]), sp = sin(s->dirs[m]);
+                double th = k[m] * (cp * X + sp * Y) + s->phases[m];
+                double ct = cos(th), st = sin(th);
+                h += amp[m] * ct;
+                ux += amp[m] * om[m] * cp * ct;
+                uy += amp[m] * om[m] * sp * ct;
+                w += amp[m] * om[m] * st;
+            }
+            z[j] = h;
+            vx[j] = ux + s->cur[0];
+            vy[j] = uy + s->cur[1];
+            vz[j] = w;
+        }
+    }
+    free(k);
+    free(amp);
+    free(om);
+}
