@@ -1,0 +1,264 @@
+/*
+ * heeps_sim.h -- C ABI of the MI355X (gfx950) facet-sum raw-data generator.
+ *
+ * The library computes the hot path of a SAR/ATI raw-data generator of the
+ * HEEPS/MARE kind (Monnier et al., "Synthetic RAW data generator for ESA
+ * HARMONY mission"): for every pulse and receive channel, the coherent sum
+ * over independent moving sea-surface facets of their complex amplitudes,
+ * weighted by the transmit and receive antenna patterns, with the two-way
+ * bistatic phase and 1/(r_t r_r) spreading (Sec. III.A eq. 3, Sec. III.B
+ * eq. 16), deposited into range slices of the received line (eq. 17) and
+ * convolved with the waveform (the paragraph after eq. 17).  It also provides
+ * the adjoint of that sum with respect to facet height, velocity and complex
+ * amplitude, and on-device generation of facets on a regular grid (Sec. III,
+ * resolved linear waves; scene generated where and when it is sensed, Sec. II.B).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Frame: flat local Cartesian frame (metres), scene origin O = (0,0,0).
+ *  - Pulse p (0-based over the whole acquisition of n_pulses pulses) is
+ *    transmitted at t_p = (p - (n_pulses-1)/2) / prf seconds.
+ *  - A facet is (x, y, z, vx, vy, vz, a_re, a_im) in float32: position at
+ *    t = 0, constant velocity (its position at pulse p is X0 + V t_p), and
+ *    complex amplitude a.
+ *  - Tx position at t_p; Rx phase centre at t_p + tau_ref(p, c), where
+ *    tau_ref is the echo delay of O (fixed point of
+ *    c tau = |O - P_tx(t_p)| + |O - P_rx(t_p + tau)|).
+ *  - Range-compressed sample n of line (c, p) sits at delay
+ *    tau_ref(p, c) + (n - n_ref) / fs.  A facet with bistatic range R
+ *    contributes W * h(n - u) to samples n = floor(u)-3 .. floor(u)+4 inside
+ *    [0, N), with u = n_ref + (R - c tau_ref) fs / c, h the Kaiser-windowed
+ *    sinc of half-width 4, and
+ *    W = a * F_tx * F_rx * (R_t,mid R_r,mid / (R_t R_r)) * exp(-j 2 pi f0 R / c),
+ *    F the one-way field patterns sinc(kappa u/beta_az) sinc(kappa v/beta_el)
+ *    (sinc^2 power pattern with 3-dB widths beta), R_.,mid the ranges of O at
+ *    t = 0.
+ *  - Complex buffers are interleaved float32 (re, im) = complex64.
+ *    IQ layout: [channel][pulse - p0][sample], row-major, N samples per line.
+ *  - Gradient convention: g = dL/dRe(IQ) + j dL/dIm(IQ) for a real loss L
+ *    (PyTorch's convention for complex tensors).
+ *  - Device pointers are HIP device memory on the current device; host
+ *    pointers are marked "host".  The caller owns every buffer passed in.
+ *  - `stream` is a hipStream_t (NULL = default stream).  Every entry point
+ *    that takes a stream is asynchronous on it unless stated otherwise.
+ *  - Return value: SIM_OK (0) or a negative SIM_E* code; arguments are
+ *    validated before anything is written or launched.  sim_last_error()
+ *    returns a thread-local message describing the last failure.
+ *  - Calls that use the same handle or plan from several host threads at
+ *    once, or that overlap on the device through one plan's scratch (the
+ *    sorted facet copy), race; serialise them (one stream per plan).
+ */
+#ifndef HEEPS_SIM_H
+#define HEEPS_SIM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SIM_OK 0
+#define SIM_EINVAL (-1)        /* bad argument (null pointer, size, range, NaN geometry) */
+#define SIM_ENOMEM (-2)        /* device or host allocation failed */
+#define SIM_EHIP (-3)          /* HIP runtime / launch failure */
+#define SIM_EUNSUPPORTED (-4)  /* valid but unsupported request (e.g. too many cells) */
+
+#define SIM_MAX_PLATFORMS 8
+#define SIM_MAX_ANTENNAS 8
+#define SIM_MAX_CHANNELS 16
+
+typedef struct sim_handle sim_handle;   /* opaque, owned by the library */
+typedef struct sim_plan sim_plan;       /* opaque, owned by the library */
+
+/* Straight-line trajectory: position p0 (m) at t = 0, constant velocity v (m/s). */
+typedef struct {
+    double p0[3];
+    double v[3];
+} sim_traj;
+
+/*
+ * Antenna on a platform: one-way 3-dB widths (radians) of its sinc^2 power
+ * pattern.  Frame (stripmap, fixed over the dwell, all antennas pointing at
+ * the same surface target as in Sec. I / Fig. 1): boresight b from the
+ * platform position at t = 0 to O, azimuth axis = x projected orthogonal to
+ * b, elevation axis = b x az.  Facets behind the antenna (r.b <= 0) get 0.
+ */
+typedef struct {
+    int platform;
+    double beta_az;
+    double beta_el;
+} sim_antenna;
+
+/* Channel: transmit antenna, receive antenna and the receive phase-centre
+ * offset (m) from the receiving platform's position (eq. 16's channels). */
+typedef struct {
+    int tx_antenna;
+    int rx_antenna;
+    double pc_offset[3];
+} sim_channel;
+
+/* Acquisition, instrument and waveform description (Sec. II.B inputs). */
+typedef struct {
+    double c;            /* propagation speed (m/s); 0 selects 299792458 */
+    double f0;           /* carrier frequency (Hz) */
+    double fs;           /* range sampling rate (Hz) */
+    double prf;          /* pulse repetition frequency (Hz) */
+    int n_samples;       /* N, samples per range line (2..65536) */
+    int n_pulses;        /* total pulses of the acquisition */
+    int n_ref;           /* reference sample of the window; < 0 selects N/2 */
+    double kaiser_beta;  /* Kaiser beta of the 8-tap interpolator (0..20) */
+    double chirp_bw;     /* chirp bandwidth (Hz) */
+    double chirp_T;      /* chirp duration (s); 0 disables the waveform step */
+    int n_platforms;
+    const sim_traj *platforms;      /* host, [n_platforms] */
+    int n_antennas;
+    const sim_antenna *antennas;    /* host, [n_antennas] */
+    int n_channels;
+    const sim_channel *channels;    /* host, [n_channels] */
+} sim_config;
+
+/* Facets, structure of arrays, device float32 [n] each. */
+typedef struct {
+    long long n;
+    const float *x, *y, *z, *vx, *vy, *vz, *a_re, *a_im;
+} sim_facets;
+
+/* Output facets of the generator, device float32 [n] each. */
+typedef struct {
+    long long n;
+    float *x, *y, *z, *vx, *vy, *vz, *a_re, *a_im;
+} sim_facets_out;
+
+/* Facet gradients, device float32 [n] each; a NULL member is not computed. */
+typedef struct {
+    long long n;
+    float *dz, *dvx, *dvy, *dvz, *da_re, *da_im;
+} sim_facet_grads;
+
+/*
+ * Sea surface for on-device facet generation on a grid of nx x ny cells of
+ * dx x dy metres centred on O (cell centres x = (ix - (nx-1)/2) dx, grid index
+ * iy*nx + ix).
+ *  mode 0: flat sea, z = 0, velocities N(0, sigma_v^2) per axis.
+ *  mode 1: n_comp linear wave components (Sec. III, resolved waves of a
+ *          homogeneous tile without the choppy-wave option): wavenumbers
+ *          log-spaced on [k_min, k_max], spectrum ~ k^slope, amplitudes
+ *          scaled to significant height hs, deep-water dispersion with
+ *          gravity g; directions and phases are given (host arrays); the
+ *          facet moves with the first-order orbital velocity plus `current`.
+ *  Complex amplitudes are CN(0, 1) in both modes.
+ */
+typedef struct {
+    int nx, ny;
+    double dx, dy;
+    int mode;
+    double sigma_v;
+    int n_comp;
+    double k_min, k_max, slope, hs, g;
+    const double *dirs;     /* host, [n_comp] propagation directions (rad) */
+    const double *phases;   /* host, [n_comp] initial phases (rad) */
+    double current[2];      /* uniform surface current (m/s) */
+} sim_sea;
+
+/*
+ * Create a simulator: validates `cfg` and derives in FP64 on the host the
+ * per-(channel, pulse) geometry (t_p, P_tx, tau_ref, P_rx), antenna frames,
+ * the interpolator's polynomial form and, if chirp_T > 0, the waveform
+ * spectrum.  Host only: the tables are uploaded by the first call that uses
+ * the GPU, to the device current at that time, and every later call on the
+ * handle must run with that device current.
+ * out: receives the handle (freed by sim_destroy).
+ * Errors: SIM_EINVAL, SIM_ENOMEM, SIM_EUNSUPPORTED (antenna width below
+ * kappa/500 rad).
+ */
+int sim_create(const sim_config *cfg, sim_handle **out);
+
+/* Release a handle and its device tables.  NULL is ignored. */
+void sim_destroy(sim_handle *h);
+
+/* Thread-local text of the last error ("" if none). */
+const char *sim_last_error(void);
+
+/*
+ * Per-pulse window metadata (the raw data are output with their timing,
+ * after eq. 17): for channel ch and pulses [p0, p0+np), host outputs t[np]
+ * (pulse times, s) and tau_ref[np] (echo delay of O, s); sample n of that
+ * line is at delay tau_ref + (n - n_ref)/fs.  Either pointer may be NULL.
+ */
+int sim_pulse_info(const sim_handle *h, int ch, int p0, int np, double *t,
+                   double *tau_ref);
+
+/* Waveform length L and FFT size M used by sim_apply_waveform (0 if none). */
+int sim_waveform_info(const sim_handle *h, int *chirp_len, int *fft_len);
+
+/*
+ * Plan a facet set (the range-binned block sort): facets are binned into
+ * spatial blocks (cells of block_edge x block_edge metres on a lattice of
+ * the horizontal plane, at most 64 facets per block; each block carries an
+ * exact float32 centre used as its FP64 reference point), blocks are grouped
+ * into patches of cells that share a range window, and the permutation is
+ * kept in plan-owned device memory.  Depends only on x, y (device float32
+ * [n]).  block_edge in (0, 64] metres; 8 suits 1 m grids.  Synchronises the
+ * stream (it reads back the bounding box and block count).
+ * Errors: SIM_EINVAL, SIM_ENOMEM, SIM_EHIP, SIM_EUNSUPPORTED (lattice larger
+ * than 2^28 cells).
+ */
+int sim_plan_create(sim_handle *h, const float *x, const float *y, long long n,
+                    double block_edge, void *stream, sim_plan **out);
+
+/* Release a plan.  NULL is ignored. */
+void sim_plan_destroy(sim_plan *plan);
+
+/* Host outputs: number of facets, blocks and patches of a plan. */
+int sim_plan_info(const sim_plan *plan, long long *n_facets, long long *n_blocks,
+                  long long *n_patches);
+
+/*
+ * Generate facets of the grid sub-rectangle [ix0, ix0+cnx) x [iy0, iy0+cny)
+ * of `sea` (row-major in the sub-rectangle).  Random draws use Philox4x32-10
+ * keyed by `seed` with the global grid index as counter, so any chunking of
+ * the grid yields the same facets.  out->n must equal cnx*cny.
+ */
+int sim_generate_facets(sim_handle *h, const sim_sea *sea, unsigned long long seed,
+                        int ix0, int iy0, int cnx, int cny, const sim_facets_out *out,
+                        void *stream);
+
+/*
+ * Forward facet sum (eq. 3/16 summed into range slices, eq. 17) for pulses
+ * [p0, p0+np) of every channel, into iq_rc (device complex64
+ * [n_channels][np][N]).  accumulate = 0 overwrites iq_rc, 1 adds to it.
+ * `facets` must be the facet set `plan` was made from (same n, same x, y);
+ * z, V and a may change between calls.
+ */
+int sim_forward(sim_handle *h, sim_plan *plan, const sim_facets *facets, int p0,
+                int np, float *iq_rc, int accumulate, void *stream);
+
+/*
+ * Convolve n_lines range lines with the chirp (the waveform convolution that
+ * follows eq. 17): raw[n] = sum_m rc[m] chirp[n - m + L/2],
+ * chirp[k] = exp(j pi (B/T) (k/fs - T/2)^2), k < L = round(T fs), by
+ * zero-padded FFT of size M = 2^ceil(log2(N + L - 1)).  Device complex64
+ * [n_lines][N] in and out; in-place (iq_raw == iq_rc) is allowed.
+ * SIM_EUNSUPPORTED if the handle has no waveform or M > 16384.
+ */
+int sim_apply_waveform(sim_handle *h, const float *iq_rc, float *iq_raw,
+                       long long n_lines, void *stream);
+
+/* Adjoint of sim_apply_waveform: g_rc[m] = sum_n g_raw[n] conj(chirp[n - m + L/2]). */
+int sim_apply_waveform_adjoint(sim_handle *h, const float *g_raw, float *g_rc,
+                               long long n_lines, void *stream);
+
+/*
+ * Adjoint of sim_forward: given g_rc = dL/dRe(IQ_rc) + j dL/dIm(IQ_rc)
+ * (device complex64 [n_channels][np][N]) writes, per facet in the original
+ * order, dL/dz, dL/dV (= sum_p t_p dL/dX) and dL/dRe(a), dL/dIm(a)
+ * (device float32 [n]; NULL members skipped).  Facet geometry is recomputed,
+ * not stored.  accumulate = 1 adds to the outputs.
+ */
+int sim_backward(sim_handle *h, sim_plan *plan, const sim_facets *facets, int p0,
+                 int np, const float *g_rc, const sim_facet_grads *grads,
+                 int accumulate, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HEEPS_SIM_H */

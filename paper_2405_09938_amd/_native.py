@@ -1,0 +1,131 @@
+"""ctypes binding of include/heeps_sim.h (argument marshalling only).
+
+Loads the in-tree libheeps_sim.so.  There is no fallback: if the library is
+missing, loading raises, and every entry point runs on the GPU.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libheeps_sim.so")
+
+SIM_OK = 0
+SIM_EINVAL = -1
+SIM_ENOMEM = -2
+SIM_EHIP = -3
+SIM_EUNSUPPORTED = -4
+MAX_PLATFORMS, MAX_ANTENNAS, MAX_CHANNELS = 8, 8, 16
+
+_d3 = ctypes.c_double * 3
+_fp = ctypes.POINTER(ctypes.c_float)
+
+
+class SimTraj(ctypes.Structure):
+    _fields_ = [("p0", _d3), ("v", _d3)]
+
+
+class SimAntenna(ctypes.Structure):
+    _fields_ = [("platform", ctypes.c_int), ("beta_az", ctypes.c_double),
+                ("beta_el", ctypes.c_double)]
+
+
+class SimChannel(ctypes.Structure):
+    _fields_ = [("tx_antenna", ctypes.c_int), ("rx_antenna", ctypes.c_int),
+                ("pc_offset", _d3)]
+
+
+class SimConfig(ctypes.Structure):
+    _fields_ = [
+        ("c", ctypes.c_double), ("f0", ctypes.c_double), ("fs", ctypes.c_double),
+        ("prf", ctypes.c_double),
+        ("n_samples", ctypes.c_int), ("n_pulses", ctypes.c_int), ("n_ref", ctypes.c_int),
+        ("kaiser_beta", ctypes.c_double), ("chirp_bw", ctypes.c_double),
+        ("chirp_T", ctypes.c_double),
+        ("n_platforms", ctypes.c_int), ("platforms", ctypes.POINTER(SimTraj)),
+        ("n_antennas", ctypes.c_int), ("antennas", ctypes.POINTER(SimAntenna)),
+        ("n_channels", ctypes.c_int), ("channels", ctypes.POINTER(SimChannel)),
+    ]
+
+
+class SimFacets(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_longlong)] + [(k, _fp) for k in
+                                              ("x", "y", "z", "vx", "vy", "vz", "a_re", "a_im")]
+
+
+SimFacetsOut = SimFacets
+
+
+class SimFacetGrads(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_longlong)] + [(k, _fp) for k in
+                                              ("dz", "dvx", "dvy", "dvz", "da_re", "da_im")]
+
+
+class SimSea(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+        ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+        ("mode", ctypes.c_int), ("sigma_v", ctypes.c_double),
+        ("n_comp", ctypes.c_int),
+        ("k_min", ctypes.c_double), ("k_max", ctypes.c_double), ("slope", ctypes.c_double),
+        ("hs", ctypes.c_double), ("g", ctypes.c_double),
+        ("dirs", ctypes.POINTER(ctypes.c_double)), ("phases", ctypes.POINTER(ctypes.c_double)),
+        ("current", ctypes.c_double * 2),
+    ]
+
+
+EXPORTS = ("sim_create", "sim_destroy", "sim_last_error", "sim_pulse_info",
+           "sim_waveform_info", "sim_plan_create", "sim_plan_destroy", "sim_plan_info",
+           "sim_generate_facets", "sim_forward", "sim_apply_waveform",
+           "sim_apply_waveform_adjoint", "sim_backward")
+
+_lib = None
+
+
+class SimError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (the HIP runtime it needs is the one torch loaded)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(
+            f"{path} is missing: build it with `python -m paper_2405_09938_amd.build`")
+    L = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    i, ll = ctypes.c_int, ctypes.c_longlong
+    L.sim_create.argtypes = [P(SimConfig), P(vp)]
+    L.sim_destroy.argtypes = [vp]
+    L.sim_destroy.restype = None
+    L.sim_last_error.argtypes = []
+    L.sim_last_error.restype = ctypes.c_char_p
+    L.sim_pulse_info.argtypes = [vp, i, i, i, P(ctypes.c_double), P(ctypes.c_double)]
+    L.sim_waveform_info.argtypes = [vp, P(i), P(i)]
+    L.sim_plan_create.argtypes = [vp, vp, vp, ll, ctypes.c_double, vp, P(vp)]
+    L.sim_plan_destroy.argtypes = [vp]
+    L.sim_plan_destroy.restype = None
+    L.sim_plan_info.argtypes = [vp, P(ll), P(ll), P(ll)]
+    L.sim_generate_facets.argtypes = [vp, P(SimSea), ctypes.c_ulonglong, i, i, i, i,
+                                      P(SimFacetsOut), vp]
+    L.sim_forward.argtypes = [vp, vp, P(SimFacets), i, i, vp, i, vp]
+    L.sim_apply_waveform.argtypes = [vp, vp, vp, ll, vp]
+    L.sim_apply_waveform_adjoint.argtypes = [vp, vp, vp, ll, vp]
+    L.sim_backward.argtypes = [vp, vp, P(SimFacets), i, i, vp, P(SimFacetGrads), i, vp]
+    for name in EXPORTS:
+        if name not in ("sim_destroy", "sim_last_error", "sim_plan_destroy"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def check(rc: int, what: str):
+    if rc != SIM_OK:
+        msg = load().sim_last_error().decode(errors="replace")
+        raise SimError(rc, f"{what}: {msg}")

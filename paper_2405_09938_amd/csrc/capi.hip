@@ -1,0 +1,797 @@
+// C ABI of the facet-sum library: argument validation, FP64 host-side
+// geometry, the interpolator's polynomial form, the waveform spectrum, the
+// facet-set plan (range-binned block sort), and the stream-ordered launches.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sim_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+constexpr double kPi = 3.14159265358979323846;
+
+#define HS_FAIL(code, msg)          \
+    do {                            \
+        hs::set_error(msg);         \
+        return (code);              \
+    } while (0)
+
+#define HS_HIP(call, what)                                                              \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            HS_FAIL(SIM_EHIP, std::string(what) + ": " + hipGetErrorString(e_));        \
+    } while (0)
+
+bool finite3(const double *v) {
+    return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]);
+}
+
+double norm3(const double *v) { return std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); }
+
+double sinc(double x) {
+    if (x == 0.0) return 1.0;
+    const double px = kPi * x;
+    return std::sin(px) / px;
+}
+
+// Modified Bessel function I0 from its power series.
+double bessel_i0(double x) {
+    double term = 1.0, sum = 1.0;
+    const double q = 0.25 * x * x;
+    for (int k = 1; k < 400; ++k) {
+        term *= q / ((double)k * k);
+        sum += term;
+        if (term < 1e-18 * sum) break;
+    }
+    return sum;
+}
+
+// Kaiser-windowed sinc of half-width 4.
+double kaiser_sinc(double t, double beta, double i0b) {
+    if (std::fabs(t) > 4.0) return 0.0;
+    double s = 1.0 - (t / 4.0) * (t / 4.0);
+    if (s < 0.0) s = 0.0;
+    return sinc(t) * bessel_i0(beta * std::sqrt(s)) / i0b;
+}
+
+// Least-squares fit of a degree-3 polynomial in y to samples (y_i, v_i).
+void fit3(const std::vector<double> &ys, const std::vector<double> &vs, double c[4]) {
+    double A[4][5] = {};
+    for (size_t i = 0; i < ys.size(); ++i) {
+        double p[4] = {1.0, ys[i], ys[i] * ys[i], ys[i] * ys[i] * ys[i]};
+        for (int r = 0; r < 4; ++r) {
+            for (int k = 0; k < 4; ++k) A[r][k] += p[r] * p[k];
+            A[r][4] += p[r] * vs[i];
+        }
+    }
+    // Gaussian elimination with partial pivoting
+    for (int col = 0; col < 4; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < 4; ++r)
+            if (std::fabs(A[r][col]) > std::fabs(A[piv][col])) piv = r;
+        if (piv != col)
+            for (int k = 0; k < 5; ++k) std::swap(A[col][k], A[piv][k]);
+        for (int r = col + 1; r < 4; ++r) {
+            const double f = A[r][col] / A[col][col];
+            for (int k = col; k < 5; ++k) A[r][k] -= f * A[col][k];
+        }
+    }
+    for (int r = 3; r >= 0; --r) {
+        double s = A[r][4];
+        for (int k = r + 1; k < 4; ++k) s -= A[r][k] * c[k];
+        c[r] = s / A[r][r];
+    }
+}
+
+double poly3d(const double c[4], double y) { return c[0] + y * (c[1] + y * (c[2] + y * c[3])); }
+
+// Polynomial form of the 8 taps (see TapPoly); returns the max abs error of
+// the fitted taps on a dense grid of f.
+double fit_taps(double beta, hs::TapPoly &tp) {
+    const double i0b = bessel_i0(beta);
+    const int K = 256;
+    double e[4][4], o[4][4];
+    for (int j = 0; j < 4; ++j) {
+        const double J = j + 1;
+        std::vector<double> ys, ev, ov;
+        for (int i = 0; i < K; ++i) {
+            const double sg = std::cos(kPi * (i + 0.5) / (2.0 * K));   // in (0, 1)
+            const double qp = kaiser_sinc(J - 0.5 - 0.5 * sg, beta, i0b);
+            const double qm = kaiser_sinc(J - 0.5 + 0.5 * sg, beta, i0b);
+            ys.push_back(sg * sg);
+            ev.push_back(0.5 * (qp + qm));
+            ov.push_back(0.5 * (qp - qm) / sg);
+        }
+        fit3(ys, ev, e[j]);
+        fit3(ys, ov, o[j]);
+        for (int k = 0; k < 4; ++k) {
+            tp.e[j][k] = (float)e[j][k];
+            tp.o[j][k] = (float)o[j][k];
+            tp.ed[j][k] = (float)((2.0 + 4.0 * k) * o[j][k]);
+            tp.od[j][k] = (float)(k < 3 ? 4.0 * (k + 1) * e[j][k + 1] : 0.0);
+        }
+    }
+    double err = 0.0;
+    for (int i = 0; i <= 2000; ++i) {
+        const double f = std::min(i / 2000.0, 1.0 - 1e-12);
+        const double sg = 2.0 * f - 1.0, y = sg * sg;
+        for (int j = 0; j < 4; ++j) {
+            const double J = j + 1;
+            const double ep = poly3d(e[j], y), op = sg * poly3d(o[j], y);
+            err = std::max(err, std::fabs(ep + op - kaiser_sinc(J - f, beta, i0b)));
+            err = std::max(err, std::fabs(ep - op - kaiser_sinc(1.0 - J - f, beta, i0b)));
+        }
+    }
+    return err;
+}
+
+// kappa with sinc(kappa / 2)^2 = 1/2 (bisection on (0, 1)).
+double half_power_kappa() {
+    double lo = 0.0, hi = 1.0;
+    const double target = std::sqrt(0.5);
+    for (int i = 0; i < 200; ++i) {
+        const double mid = 0.5 * (lo + hi);
+        if (sinc(mid) > target) lo = mid; else hi = mid;
+    }
+    return lo + hi;
+}
+
+void plat_pos(const sim_handle *h, int plat, double t, double *out) {
+    const sim_traj &p = h->plats[plat];
+    for (int k = 0; k < 3; ++k) out[k] = p.p0[k] + p.v[k] * t;
+}
+
+void tx_pos(const sim_handle *h, int ch, double t, double *out) {
+    plat_pos(h, h->ants[h->chans[ch].tx_antenna].platform, t, out);
+}
+
+void rx_pos(const sim_handle *h, int ch, double t, double *out) {
+    plat_pos(h, h->ants[h->chans[ch].rx_antenna].platform, t, out);
+    for (int k = 0; k < 3; ++k) out[k] += h->chans[ch].pc_offset[k];
+}
+
+// Stripmap antenna frame pointing at O from the platform position at t = 0.
+void antenna_frame(const sim_handle *h, int a, hs::AntConst &ac) {
+    double p[3];
+    plat_pos(h, h->ants[a].platform, 0.0, p);
+    const double r = norm3(p);
+    for (int k = 0; k < 3; ++k) ac.b[k] = -p[k] / r;
+    const double d = ac.b[0];   // x . b
+    double az[3] = {1.0 - d * ac.b[0], -d * ac.b[1], -d * ac.b[2]};
+    const double na = norm3(az);
+    for (int k = 0; k < 3; ++k) ac.az[k] = az[k] / na;
+    ac.el[0] = ac.b[1] * ac.az[2] - ac.b[2] * ac.az[1];
+    ac.el[1] = ac.b[2] * ac.az[0] - ac.b[0] * ac.az[2];
+    ac.el[2] = ac.b[0] * ac.az[1] - ac.b[1] * ac.az[0];
+    ac.ka = h->kappa / h->ants[a].beta_az;
+    ac.ke = h->kappa / h->ants[a].beta_el;
+}
+
+template <typename T>
+hipError_t dalloc(T **p, size_t count) {
+    return hipMalloc((void **)p, sizeof(T) * (count > 0 ? count : 1));
+}
+
+struct DevBufs {   // frees on scope exit
+    std::vector<void *> ptrs;
+    ~DevBufs() {
+        for (void *p : ptrs)
+            if (p) (void)hipFree(p);
+    }
+    template <typename T>
+    hipError_t alloc(T **p, size_t count) {
+        hipError_t e = dalloc(p, count);
+        if (e == hipSuccess) ptrs.push_back(*p);
+        else *p = nullptr;
+        return e;
+    }
+};
+
+// Device tables are uploaded on the first call that needs the GPU, on the
+// device current at that time; later calls must run on the same device.
+int ensure_device(sim_handle *h) {
+    int d = -1;
+    if (hipGetDevice(&d) != hipSuccess) HS_FAIL(SIM_EHIP, "no HIP device");
+    if (h->uploaded) {
+        if (d != h->device)
+            HS_FAIL(SIM_EINVAL, "current HIP device differs from the handle's device");
+        return SIM_OK;
+    }
+    h->device = d;
+    hipError_t e = dalloc(&h->pulses_d, h->pulses_h.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(h->pulses_d, h->pulses_h.data(), sizeof(hs::PulseRec) * h->pulses_h.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = dalloc(&h->chc_d, h->chc.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(h->chc_d, h->chc.data(), sizeof(hs::ChanConst) * h->chc.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && h->fft_len > 0) {
+        e = dalloc(&h->chirp_spec_d, h->spec_h.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(h->chirp_spec_d, h->spec_h.data(), sizeof(float) * h->spec_h.size(),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = dalloc(&h->twiddle_d, h->tw_h.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(h->twiddle_d, h->tw_h.data(), sizeof(float) * h->tw_h.size(),
+                          hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        HS_FAIL(e == hipErrorOutOfMemory ? SIM_ENOMEM : SIM_EHIP,
+                std::string("device table upload: ") + hipGetErrorString(e));
+    }
+    h->uploaded = true;
+    return SIM_OK;
+}
+
+int facets_ok(const sim_facets *f, long long n) {
+    if (!f) HS_FAIL(SIM_EINVAL, "facets is NULL");
+    if (f->n != n) HS_FAIL(SIM_EINVAL, "facets->n differs from the plan's facet count");
+    if (!f->x || !f->y || !f->z || !f->vx || !f->vy || !f->vz || !f->a_re || !f->a_im)
+        HS_FAIL(SIM_EINVAL, "a facet array pointer is NULL");
+    return SIM_OK;
+}
+
+}  // namespace
+
+namespace hs {
+void set_error(const std::string &msg) { g_last_error = msg; }
+}  // namespace hs
+
+extern "C" {
+
+const char *sim_last_error(void) { return g_last_error.c_str(); }
+
+int sim_create(const sim_config *cfg, sim_handle **out) {
+    if (!cfg || !out) HS_FAIL(SIM_EINVAL, "cfg or out is NULL");
+    *out = nullptr;
+    const double c = cfg->c > 0 ? cfg->c : 299792458.0;
+    if (!(cfg->f0 > 0) || !(cfg->fs > 0) || !(cfg->prf > 0) || !std::isfinite(cfg->f0) ||
+        !std::isfinite(cfg->fs) || !std::isfinite(cfg->prf) || !std::isfinite(c))
+        HS_FAIL(SIM_EINVAL, "f0, fs, prf and c must be finite and positive");
+    if (cfg->n_samples < 2 || cfg->n_samples > 65536)
+        HS_FAIL(SIM_EINVAL, "n_samples must be in [2, 65536]");
+    if (cfg->n_pulses < 1 || cfg->n_pulses > (1 << 24))
+        HS_FAIL(SIM_EINVAL, "n_pulses must be in [1, 2^24]");
+    if (!(cfg->kaiser_beta >= 0) || cfg->kaiser_beta > 20)
+        HS_FAIL(SIM_EINVAL, "kaiser_beta must be in [0, 20]");
+    if (cfg->n_ref >= cfg->n_samples) HS_FAIL(SIM_EINVAL, "n_ref must be < n_samples");
+    if (!(cfg->chirp_T >= 0) || !std::isfinite(cfg->chirp_T) || !std::isfinite(cfg->chirp_bw))
+        HS_FAIL(SIM_EINVAL, "chirp_T must be >= 0 and finite");
+    if (cfg->n_platforms < 1 || cfg->n_platforms > SIM_MAX_PLATFORMS || !cfg->platforms)
+        HS_FAIL(SIM_EINVAL, "need 1..8 platforms");
+    if (cfg->n_antennas < 1 || cfg->n_antennas > SIM_MAX_ANTENNAS || !cfg->antennas)
+        HS_FAIL(SIM_EINVAL, "need 1..8 antennas");
+    if (cfg->n_channels < 1 || cfg->n_channels > SIM_MAX_CHANNELS || !cfg->channels)
+        HS_FAIL(SIM_EINVAL, "need 1..16 channels");
+    for (int i = 0; i < cfg->n_platforms; ++i)
+        if (!finite3(cfg->platforms[i].p0) || !finite3(cfg->platforms[i].v))
+            HS_FAIL(SIM_EINVAL, "platform trajectory is not finite");
+    for (int i = 0; i < cfg->n_antennas; ++i) {
+        const sim_antenna &a = cfg->antennas[i];
+        if (a.platform < 0 || a.platform >= cfg->n_platforms)
+            HS_FAIL(SIM_EINVAL, "antenna platform index out of range");
+        if (!(a.beta_az > 0) || !(a.beta_el > 0) || !std::isfinite(a.beta_az) ||
+            !std::isfinite(a.beta_el))
+            HS_FAIL(SIM_EINVAL, "antenna widths must be finite and positive");
+        double p[3];
+        for (int k = 0; k < 3; ++k) p[k] = cfg->platforms[a.platform].p0[k];
+        const double r = norm3(p);
+        if (!(r > 0)) HS_FAIL(SIM_EINVAL, "an antenna's platform sits on the scene origin");
+        if (std::fabs(p[0]) / r > 1.0 - 1e-9)
+            HS_FAIL(SIM_EINVAL, "boresight parallel to the along-track axis");
+    }
+    for (int i = 0; i < cfg->n_channels; ++i) {
+        const sim_channel &ch = cfg->channels[i];
+        if (ch.tx_antenna < 0 || ch.tx_antenna >= cfg->n_antennas || ch.rx_antenna < 0 ||
+            ch.rx_antenna >= cfg->n_antennas)
+            HS_FAIL(SIM_EINVAL, "channel antenna index out of range");
+        if (!finite3(ch.pc_offset)) HS_FAIL(SIM_EINVAL, "phase-centre offset is not finite");
+    }
+
+    sim_handle *h = new (std::nothrow) sim_handle();
+    if (!h) HS_FAIL(SIM_ENOMEM, "host allocation failed");
+    h->c = c;
+    h->f0 = cfg->f0;
+    h->fs = cfg->fs;
+    h->prf = cfg->prf;
+    h->N = cfg->n_samples;
+    h->Np = cfg->n_pulses;
+    h->n_ref = cfg->n_ref < 0 ? cfg->n_samples / 2 : cfg->n_ref;
+    h->beta = cfg->kaiser_beta;
+    h->chirp_bw = cfg->chirp_bw;
+    h->chirp_T = cfg->chirp_T;
+    h->plats.assign(cfg->platforms, cfg->platforms + cfg->n_platforms);
+    h->ants.assign(cfg->antennas, cfg->antennas + cfg->n_antennas);
+    h->chans.assign(cfg->channels, cfg->channels + cfg->n_channels);
+    h->C = cfg->n_channels;
+    h->kappa = half_power_kappa();
+
+    h->antc.resize(h->ants.size());
+    for (size_t a = 0; a < h->ants.size(); ++a) {
+        antenna_frame(h, (int)a, h->antc[a]);
+        if (h->antc[a].ka > 500.0 || h->antc[a].ke > 500.0) {
+            delete h;
+            HS_FAIL(SIM_EUNSUPPORTED, "antenna 3-dB width below kappa/500 rad is not supported");
+        }
+    }
+    h->chc.resize(h->C);
+    for (int ch = 0; ch < h->C; ++ch) {
+        hs::ChanConst &cc = h->chc[ch];
+        cc.tx = h->antc[h->chans[ch].tx_antenna];
+        cc.rx = h->antc[h->chans[ch].rx_antenna];
+        double pt[3], pr[3];
+        tx_pos(h, ch, 0.0, pt);
+        rx_pos(h, ch, 0.0, pr);
+        cc.rtrr_mid = norm3(pt) * norm3(pr);
+        for (int k = 0; k < 3; ++k) {
+            cc.kta[k] = (float)(cc.tx.ka * cc.tx.az[k]);
+            cc.kte[k] = (float)(cc.tx.ke * cc.tx.el[k]);
+            cc.kra[k] = (float)(cc.rx.ka * cc.rx.az[k]);
+            cc.kre[k] = (float)(cc.rx.ke * cc.rx.el[k]);
+            cc.bt[k] = (float)cc.tx.b[k];
+            cc.br[k] = (float)cc.rx.b[k];
+        }
+    }
+    // per (channel, pulse) geometry: echo delay of O by fixed-point iteration
+    h->pulses_h.resize((size_t)h->C * h->Np);
+    for (int ch = 0; ch < h->C; ++ch) {
+        for (int p = 0; p < h->Np; ++p) {
+            hs::PulseRec &r = h->pulses_h[(size_t)ch * h->Np + p];
+            r.t = ((double)p - 0.5 * (double)(h->Np - 1)) / h->prf;
+            tx_pos(h, ch, r.t, r.ptx);
+            const double rt = norm3(r.ptx);
+            double tau = 2.0 * rt / c;
+            for (int it = 0; it < 60; ++it) {
+                rx_pos(h, ch, r.t + tau, r.prx);
+                const double nt = (rt + norm3(r.prx)) / c;
+                if (nt == tau) break;
+                tau = nt;
+            }
+            rx_pos(h, ch, r.t + tau, r.prx);
+            r.rref = c * tau;
+            if (!std::isfinite(r.rref) || !(rt > 0)) {
+                delete h;
+                HS_FAIL(SIM_EINVAL, "pulse geometry is not finite");
+            }
+        }
+    }
+    h->tap_fit_err = fit_taps(h->beta, h->tp);
+
+    // waveform spectrum S = FFT_M(chirp) / M and twiddles, FP64 on the host
+    h->chirp_len = 0;
+    h->fft_len = 0;
+    std::vector<float> &spec = h->spec_h, &tw = h->tw_h;
+    if (h->chirp_T > 0) {
+        const long long L = std::llround(h->chirp_T * h->fs);
+        if (L < 1) {
+            delete h;
+            HS_FAIL(SIM_EINVAL, "chirp shorter than one sample");
+        }
+        long long M = 256;
+        while (M < (long long)h->N + L - 1) M <<= 1;
+        h->chirp_len = (int)L;
+        if (M <= 16384) {
+            h->fft_len = (int)M;
+            std::vector<double> wr(M), wi(M);
+            for (long long m = 0; m < M; ++m) {
+                const double a = -2.0 * kPi * (double)m / (double)M;
+                wr[m] = std::cos(a);
+                wi[m] = std::sin(a);
+            }
+            const double K = h->chirp_bw / h->chirp_T;
+            std::vector<double> cr(L), ci(L);
+            for (long long k = 0; k < L; ++k) {
+                const double t = (double)k / h->fs - 0.5 * h->chirp_T;
+                const double ph = kPi * K * t * t;
+                cr[k] = std::cos(ph);
+                ci[k] = std::sin(ph);
+            }
+            spec.resize(2 * M);
+            tw.resize(2 * M);
+            for (long long m = 0; m < M; ++m) {
+                double sr = 0.0, si = 0.0;
+                for (long long k = 0; k < L; ++k) {
+                    const long long q = (m * k) % M;
+                    sr += cr[k] * wr[q] - ci[k] * wi[q];
+                    si += cr[k] * wi[q] + ci[k] * wr[q];
+                }
+                spec[2 * m] = (float)(sr / (double)M);
+                spec[2 * m + 1] = (float)(si / (double)M);
+                tw[2 * m] = (float)wr[m];
+                tw[2 * m + 1] = (float)wi[m];
+            }
+        }
+    }
+
+    *out = h;
+    return SIM_OK;
+}
+
+void sim_destroy(sim_handle *h) {
+    if (!h) return;
+    if (h->pulses_d) (void)hipFree(h->pulses_d);
+    if (h->chc_d) (void)hipFree(h->chc_d);
+    if (h->chirp_spec_d) (void)hipFree(h->chirp_spec_d);
+    if (h->twiddle_d) (void)hipFree(h->twiddle_d);
+    if (h->gen_tab_d) (void)hipFree(h->gen_tab_d);
+    delete h;
+}
+
+int sim_pulse_info(const sim_handle *h, int ch, int p0, int np, double *t, double *tau_ref) {
+    if (!h) HS_FAIL(SIM_EINVAL, "handle is NULL");
+    if (ch < 0 || ch >= h->C) HS_FAIL(SIM_EINVAL, "channel out of range");
+    if (p0 < 0 || np < 0 || (long long)p0 + np > h->Np) HS_FAIL(SIM_EINVAL, "pulse range");
+    for (int i = 0; i < np; ++i) {
+        const hs::PulseRec &r = h->pulses_h[(size_t)ch * h->Np + p0 + i];
+        if (t) t[i] = r.t;
+        if (tau_ref) tau_ref[i] = r.rref / h->c;
+    }
+    return SIM_OK;
+}
+
+int sim_waveform_info(const sim_handle *h, int *chirp_len, int *fft_len) {
+    if (!h) HS_FAIL(SIM_EINVAL, "handle is NULL");
+    if (chirp_len) *chirp_len = h->chirp_len;
+    if (fft_len) *fft_len = h->fft_len;
+    return SIM_OK;
+}
+
+int sim_plan_create(sim_handle *h, const float *x, const float *y, long long n,
+                    double block_edge, void *stream, sim_plan **out) {
+    if (!h || !out) HS_FAIL(SIM_EINVAL, "handle or out is NULL");
+    *out = nullptr;
+    if (n < 1 || n >= (1LL << 31) - 64) HS_FAIL(SIM_EINVAL, "facet count must be in [1, 2^31 - 64)");
+    if (!x || !y) HS_FAIL(SIM_EINVAL, "x or y is NULL");
+    if (!(block_edge > 0) || block_edge > 64) HS_FAIL(SIM_EINVAL, "block_edge must be in (0, 64]");
+    if (int rc = ensure_device(h)) return rc;
+    hipStream_t s = (hipStream_t)stream;
+
+    DevBufs tmp;
+    float *bb = nullptr;
+    HS_HIP(tmp.alloc(&bb, 4), "plan alloc");
+    {
+        const int init[4] = {std::numeric_limits<int>::max(), std::numeric_limits<int>::min(),
+                             std::numeric_limits<int>::max(), std::numeric_limits<int>::min()};
+        HS_HIP(hipMemcpyAsync(bb, init, sizeof(init), hipMemcpyHostToDevice, s), "plan bbox init");
+    }
+    HS_HIP(hs::launch_bbox(x, y, n, bb, s), "plan bbox");
+    int keyv[4];
+    HS_HIP(hipMemcpyAsync(keyv, bb, sizeof(keyv), hipMemcpyDeviceToHost, s), "plan bbox read");
+    HS_HIP(hipStreamSynchronize(s), "plan sync");
+    float box[4];
+    for (int k = 0; k < 4; ++k) {
+        const unsigned u = (unsigned)keyv[k];
+        const unsigned bits = keyv[k] >= 0 ? u : 0x80000000u - u;
+        std::memcpy(&box[k], &bits, 4);
+        if (!std::isfinite(box[k])) HS_FAIL(SIM_EINVAL, "facet positions must be finite");
+    }
+
+    hs::Lattice L;
+    L.edge = block_edge;
+    L.bx0 = (long long)std::floor((double)box[0] / block_edge);
+    L.by0 = (long long)std::floor((double)box[2] / block_edge);
+    const long long nbx = (long long)std::floor((double)box[1] / block_edge) - L.bx0 + 1;
+    const long long nby = (long long)std::floor((double)box[3] / block_edge) - L.by0 + 1;
+    if (nbx * nby > (1LL << 28) || nbx > (1 << 28) || nby > (1 << 28))
+        HS_FAIL(SIM_EUNSUPPORTED, "facet lattice exceeds 2^28 cells");
+    L.nbx = (int)nbx;
+    L.nby = (int)nby;
+
+    // Patch shape: gradients of the sample position along x and y over the
+    // scene corners and the first / middle / last pulses of every channel.
+    double gxm = 1e-12, gym = 1e-12, gzm = 0.0, gnm = 0.0;
+    const double xs[3] = {box[0], 0.5 * (box[0] + box[1]), box[1]};
+    const double ys[3] = {box[2], 0.5 * (box[2] + box[3]), box[3]};
+    const int ps[3] = {0, h->Np / 2, h->Np - 1};
+    for (int ch = 0; ch < h->C; ++ch)
+        for (int pi = 0; pi < 3; ++pi) {
+            const hs::PulseRec &r = h->pulses_h[(size_t)ch * h->Np + ps[pi]];
+            for (double xv : xs)
+                for (double yv : ys) {
+                    const double dt[3] = {xv - r.ptx[0], yv - r.ptx[1], -r.ptx[2]};
+                    const double dr[3] = {xv - r.prx[0], yv - r.prx[1], -r.prx[2]};
+                    const double nt = norm3(dt), nr = norm3(dr);
+                    double g[3];
+                    for (int k = 0; k < 3; ++k) g[k] = dt[k] / nt + dr[k] / nr;
+                    gxm = std::max(gxm, std::fabs(g[0]));
+                    gym = std::max(gym, std::fabs(g[1]));
+                    gzm = std::max(gzm, std::fabs(g[2]));
+                    gnm = std::max(gnm, norm3(g));
+                }
+        }
+    const double bins_per_m = h->fs / h->c;
+    const double tmax = 0.5 * (double)(h->Np - 1) / h->prf;
+    // halo: facet heights up to 4 m and drift at up to 2.5 m/s over the dwell
+    const int halo = (int)std::ceil((4.0 * gzm + 2.5 * tmax * gnm) * bins_per_m) + 1;
+    const int win = 64;
+    const double budget = std::max(2.0, (double)(win - 2 * halo - 11));
+    const double gxb = gxm * bins_per_m * block_edge, gyb = gym * bins_per_m * block_edge;
+    const double target = 128.0;   // cells per patch
+    double px = std::sqrt(target * gyb / gxb), py = target / px;
+    px = std::max(1.0, std::min(px, 4096.0));
+    py = std::max(1.0, std::min(py, 4096.0));
+    while (px * gxb + py * gyb > budget && (px > 1.0 || py > 1.0)) {
+        if (px * gxb >= py * gyb && px > 1.0) px = std::max(1.0, std::floor(px * 0.8));
+        else py = std::max(1.0, std::floor(py * 0.8));
+    }
+    L.px = std::max(1, std::min((int)px, L.nbx));
+    L.py = std::max(1, std::min((int)py, L.nby));
+    L.npx = (L.nbx + L.px - 1) / L.px;
+    L.npy = (L.nby + L.py - 1) / L.py;
+    const long long n_patches = (long long)L.npx * L.npy;
+    const long long n_keys = n_patches * L.px * L.py;
+    if (n_keys > (1LL << 28)) HS_FAIL(SIM_EUNSUPPORTED, "facet lattice exceeds 2^28 cells");
+
+    // counting sort by key
+    int *keys, *rank, *count, *offset, *nblk, *blk_offset, *scan_tmp;
+    const long long stl = hs::scan_tmp_len(n_keys);
+    HS_HIP(tmp.alloc(&keys, n), "plan alloc");
+    HS_HIP(tmp.alloc(&rank, n), "plan alloc");
+    HS_HIP(tmp.alloc(&count, n_keys), "plan alloc");
+    HS_HIP(tmp.alloc(&offset, n_keys + 1), "plan alloc");
+    HS_HIP(tmp.alloc(&nblk, n_keys), "plan alloc");
+    HS_HIP(tmp.alloc(&blk_offset, n_keys + 1), "plan alloc");
+    HS_HIP(tmp.alloc(&scan_tmp, stl), "plan alloc");
+
+    sim_plan *P = new (std::nothrow) sim_plan();
+    if (!P) HS_FAIL(SIM_ENOMEM, "host allocation failed");
+    P->h = h;
+    P->n = n;
+    P->lat = L;
+    P->n_patches = n_patches;
+    P->halo = halo;
+    auto fail = [&](int code, const std::string &msg) {
+        sim_plan_destroy(P);
+        hs::set_error(msg);
+        return code;
+    };
+    hipError_t e = hipSuccess;
+    if ((e = dalloc(&P->perm, n)) != hipSuccess ||
+        (e = dalloc(&P->patch_first, n_patches + 1)) != hipSuccess ||
+        (e = dalloc(&P->sorted, n + 1)) != hipSuccess)
+        return fail(SIM_ENOMEM, std::string("plan alloc: ") + hipGetErrorString(e));
+    if ((e = hs::launch_fill_zero((float *)count, n_keys, s)) != hipSuccess ||
+        (e = hs::launch_fill_zero((float *)(P->sorted + n), 8, s)) != hipSuccess ||
+        (e = hs::launch_cell_keys(x, y, n, L, keys, rank, count, s)) != hipSuccess ||
+        (e = hs::launch_exclusive_scan(count, offset, n_keys, scan_tmp, stl, s)) != hipSuccess ||
+        (e = hs::launch_scatter(keys, rank, offset, n, P->perm, s)) != hipSuccess ||
+        (e = hs::launch_block_counts(count, n_keys, nblk, s)) != hipSuccess ||
+        (e = hs::launch_exclusive_scan(nblk, blk_offset, n_keys, scan_tmp, stl, s)) != hipSuccess)
+        return fail(SIM_EHIP, std::string("plan sort: ") + hipGetErrorString(e));
+    int nb_total = 0;
+    if ((e = hipMemcpyAsync(&nb_total, blk_offset + n_keys, sizeof(int), hipMemcpyDeviceToHost,
+                            s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return fail(SIM_EHIP, std::string("plan sync: ") + hipGetErrorString(e));
+    P->n_blocks = nb_total;
+    if ((e = dalloc(&P->blocks, (size_t)nb_total)) != hipSuccess)
+        return fail(SIM_ENOMEM, std::string("plan alloc: ") + hipGetErrorString(e));
+    if ((e = hs::launch_make_blocks(count, offset, blk_offset, n_keys, L, P->blocks, s)) !=
+            hipSuccess ||
+        (e = hs::launch_patch_first(blk_offset, n_patches, L.px * L.py, n_keys, P->patch_first,
+                                    s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return fail(SIM_EHIP, std::string("plan blocks: ") + hipGetErrorString(e));
+    *out = P;
+    return SIM_OK;
+}
+
+void sim_plan_destroy(sim_plan *P) {
+    if (!P) return;
+    if (P->perm) (void)hipFree(P->perm);
+    if (P->blocks) (void)hipFree(P->blocks);
+    if (P->patch_first) (void)hipFree(P->patch_first);
+    if (P->sorted) (void)hipFree(P->sorted);
+    delete P;
+}
+
+int sim_plan_info(const sim_plan *P, long long *n_facets, long long *n_blocks,
+                  long long *n_patches) {
+    if (!P) HS_FAIL(SIM_EINVAL, "plan is NULL");
+    if (n_facets) *n_facets = P->n;
+    if (n_blocks) *n_blocks = P->n_blocks;
+    if (n_patches) *n_patches = P->n_patches;
+    return SIM_OK;
+}
+
+int sim_generate_facets(sim_handle *h, const sim_sea *sea, unsigned long long seed, int ix0,
+                        int iy0, int cnx, int cny, const sim_facets_out *out, void *stream) {
+    if (!h || !sea || !out) HS_FAIL(SIM_EINVAL, "handle, sea or out is NULL");
+    if (int rc = ensure_device(h)) return rc;
+    if (sea->nx < 1 || sea->ny < 1 || !(sea->dx > 0) || !(sea->dy > 0))
+        HS_FAIL(SIM_EINVAL, "grid size and spacing must be positive");
+    if (ix0 < 0 || iy0 < 0 || cnx < 0 || cny < 0 || (long long)ix0 + cnx > sea->nx ||
+        (long long)iy0 + cny > sea->ny)
+        HS_FAIL(SIM_EINVAL, "sub-rectangle outside the grid");
+    if (out->n != (long long)cnx * cny) HS_FAIL(SIM_EINVAL, "out->n must equal cnx*cny");
+    if (out->n > 0 && (!out->x || !out->y || !out->z || !out->vx || !out->vy || !out->vz ||
+                       !out->a_re || !out->a_im))
+        HS_FAIL(SIM_EINVAL, "an output array pointer is NULL");
+    if (sea->mode != 0 && sea->mode != 1) HS_FAIL(SIM_EINVAL, "sea mode must be 0 or 1");
+    hs::GenArgs a{};
+    a.nx = sea->nx;
+    a.ny = sea->ny;
+    a.dx = sea->dx;
+    a.dy = sea->dy;
+    a.mode = sea->mode;
+    a.sigma_v = sea->sigma_v;
+    a.seed = seed;
+    a.ix0 = ix0;
+    a.iy0 = iy0;
+    a.cnx = cnx;
+    a.cny = cny;
+    a.out = *out;
+    a.cur0 = sea->current[0];
+    a.cur1 = sea->current[1];
+    a.n_comp = 0;
+    if (sea->mode == 1) {
+        const int nc = sea->n_comp;
+        if (nc < 1 || nc > 4096 || !sea->dirs || !sea->phases)
+            HS_FAIL(SIM_EINVAL, "mode 1 needs 1..4096 components with dirs and phases");
+        if (!(sea->k_min > 0) || !(sea->k_max >= sea->k_min) || !(sea->hs >= 0) || !(sea->g > 0))
+            HS_FAIL(SIM_EINVAL, "bad wave spectrum parameters");
+        // wavenumbers log-spaced on [k_min, k_max]; A_m^2 = 2 Psi(k_m) dk_m with
+        // Psi ~ k^slope and dk_m = k_m dlnk, scaled so sum A_m^2 / 2 = (hs/4)^2;
+        // omega^2 = g k (deep water)
+        std::vector<double> &tab = h->gen_tab_h;
+        tab.assign((size_t)6 * nc, 0.0);
+        const double dl = nc > 1 ? std::log(sea->k_max / sea->k_min) / (nc - 1) : 1.0;
+        double energy = 0.0;
+        for (int m = 0; m < nc; ++m) {
+            const double k = nc > 1 ? sea->k_min * std::exp(dl * m) : sea->k_min;
+            const double A = std::sqrt(2.0 * std::pow(k, sea->slope) * k * dl);
+            energy += 0.5 * A * A;
+            double *t = &tab[6 * m];
+            t[0] = k;
+            t[1] = A;
+            t[2] = std::sqrt(sea->g * k);
+            t[3] = std::cos(sea->dirs[m]);
+            t[4] = std::sin(sea->dirs[m]);
+            t[5] = sea->phases[m];
+        }
+        const double scale = energy > 0 ? (sea->hs / 4.0) / std::sqrt(energy) : 0.0;
+        for (int m = 0; m < nc; ++m) tab[6 * m + 1] *= scale;
+        hipStream_t s = (hipStream_t)stream;
+        if (h->gen_tab_cap < tab.size()) {
+            // the previous table may still be read by queued work on this stream
+            HS_HIP(hipStreamSynchronize(s), "generate sync");
+            if (h->gen_tab_d) (void)hipFree(h->gen_tab_d);
+            h->gen_tab_d = nullptr;
+            h->gen_tab_cap = 0;
+            HS_HIP(dalloc(&h->gen_tab_d, tab.size()), "generate alloc");
+            h->gen_tab_cap = tab.size();
+        }
+        HS_HIP(hipMemcpyAsync(h->gen_tab_d, tab.data(), sizeof(double) * tab.size(),
+                              hipMemcpyHostToDevice, s),
+               "generate upload");
+        a.tab = h->gen_tab_d;
+        a.n_comp = nc;
+    }
+    HS_HIP(hs::launch_generate(a, (hipStream_t)stream), "generate launch");
+    return SIM_OK;
+}
+
+int sim_forward(sim_handle *h, sim_plan *P, const sim_facets *f, int p0, int np, float *iq,
+                int accumulate, void *stream) {
+    if (!h || !P) HS_FAIL(SIM_EINVAL, "handle or plan is NULL");
+    if (P->h != h) HS_FAIL(SIM_EINVAL, "plan belongs to another handle");
+    if (int rc = facets_ok(f, P->n)) return rc;
+    if (p0 < 0 || np < 0 || (long long)p0 + np > h->Np) HS_FAIL(SIM_EINVAL, "pulse range");
+    if (!iq) HS_FAIL(SIM_EINVAL, "iq is NULL");
+    if (int rc = ensure_device(h)) return rc;
+    if (np == 0) return SIM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    HS_HIP(hs::launch_gather(*f, P->perm, P->blocks, P->n_blocks, P->sorted, s), "gather");
+    if (!accumulate)
+        HS_HIP(hs::launch_fill_zero(iq, 2LL * h->C * np * h->N, s), "zero iq");
+    hs::FwdArgs a{};
+    a.facets = P->sorted;
+    a.blocks = P->blocks;
+    a.patch_first = P->patch_first;
+    a.pulses = h->pulses_d;
+    a.ch = h->chc_d;
+    a.iq = iq;
+    a.tp = h->tp;
+    a.lat = P->lat;
+    a.f0_c = h->f0 / h->c;
+    a.fs_c = h->fs / h->c;
+    a.n_ref = (double)h->n_ref;
+    a.linv_hi = (float)a.f0_c;
+    a.linv_lo = (float)(a.f0_c - (double)a.linv_hi);
+    a.fs_cf = (float)a.fs_c;
+    a.N = h->N;
+    a.Np = h->Np;
+    a.p0 = p0;
+    a.np = np;
+    a.n_patches = (int)P->n_patches;
+    a.halo = P->halo;
+    HS_HIP(hs::launch_forward(a, h->C, s), "forward");
+    return SIM_OK;
+}
+
+int sim_backward(sim_handle *h, sim_plan *P, const sim_facets *f, int p0, int np,
+                 const float *g, const sim_facet_grads *gr, int accumulate, void *stream) {
+    if (!h || !P) HS_FAIL(SIM_EINVAL, "handle or plan is NULL");
+    if (P->h != h) HS_FAIL(SIM_EINVAL, "plan belongs to another handle");
+    if (int rc = facets_ok(f, P->n)) return rc;
+    if (p0 < 0 || np < 0 || (long long)p0 + np > h->Np) HS_FAIL(SIM_EINVAL, "pulse range");
+    if (!g || !gr) HS_FAIL(SIM_EINVAL, "g or grads is NULL");
+    if (gr->n != P->n) HS_FAIL(SIM_EINVAL, "grads->n differs from the plan's facet count");
+    if (int rc = ensure_device(h)) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (np == 0) {
+        if (!accumulate) {
+            float *outs[6] = {gr->dz, gr->dvx, gr->dvy, gr->dvz, gr->da_re, gr->da_im};
+            for (float *o : outs)
+                if (o) HS_HIP(hs::launch_fill_zero(o, P->n, s), "zero grads");
+        }
+        return SIM_OK;
+    }
+    HS_HIP(hs::launch_gather(*f, P->perm, P->blocks, P->n_blocks, P->sorted, s), "gather");
+    hs::AdjArgs a{};
+    a.facets = P->sorted;
+    a.blocks = P->blocks;
+    a.perm = P->perm;
+    a.pulses = h->pulses_d;
+    a.ch = h->chc_d;
+    a.g = g;
+    a.dz = gr->dz;
+    a.dvx = gr->dvx;
+    a.dvy = gr->dvy;
+    a.dvz = gr->dvz;
+    a.dar = gr->da_re;
+    a.dai = gr->da_im;
+    a.tp = h->tp;
+    a.f0_c = h->f0 / h->c;
+    a.fs_c = h->fs / h->c;
+    a.n_ref = (double)h->n_ref;
+    a.linv_hi = (float)a.f0_c;
+    a.linv_lo = (float)(a.f0_c - (double)a.linv_hi);
+    a.fs_cf = (float)a.fs_c;
+    a.k0 = (float)(2.0 * kPi * a.f0_c);
+    a.N = h->N;
+    a.Np = h->Np;
+    a.p0 = p0;
+    a.np = np;
+    a.C = h->C;
+    a.n_blocks = P->n_blocks;
+    a.accumulate = accumulate ? 1 : 0;
+    HS_HIP(hs::launch_adjoint(a, s), "adjoint");
+    return SIM_OK;
+}
+
+static int waveform_common(sim_handle *h, const float *in, float *out, long long n_lines,
+                           void *stream, int adjoint) {
+    if (!h) HS_FAIL(SIM_EINVAL, "handle is NULL");
+    if (h->chirp_len == 0) HS_FAIL(SIM_EUNSUPPORTED, "the handle has no waveform (chirp_T = 0)");
+    if (h->fft_len == 0) HS_FAIL(SIM_EUNSUPPORTED, "waveform FFT longer than 16384");
+    if (n_lines < 0) HS_FAIL(SIM_EINVAL, "n_lines < 0");
+    if (n_lines > 0 && (!in || !out)) HS_FAIL(SIM_EINVAL, "in or out is NULL");
+    if (n_lines > (1LL << 31)) HS_FAIL(SIM_EINVAL, "too many lines");
+    if (int rc = ensure_device(h)) return rc;
+    HS_HIP(hs::launch_waveform(in, out, n_lines, h->N, h->fft_len, h->chirp_len / 2,
+                               h->chirp_spec_d, h->twiddle_d, adjoint, (hipStream_t)stream),
+           "waveform");
+    return SIM_OK;
+}
+
+int sim_apply_waveform(sim_handle *h, const float *iq_rc, float *iq_raw, long long n_lines,
+                       void *stream) {
+    return waveform_common(h, iq_rc, iq_raw, n_lines, stream, 0);
+}
+
+int sim_apply_waveform_adjoint(sim_handle *h, const float *g_raw, float *g_rc,
+                               long long n_lines, void *stream) {
+    return waveform_common(h, g_raw, g_rc, n_lines, stream, 1);
+}
+
+}  // extern "C"

@@ -1,0 +1,231 @@
+// Adjoint of the facet sum with respect to facet height, velocity and complex
+// amplitude, for gfx950.
+//
+// With g = dL/dRe(IQ) + j dL/dIm(IQ), one facet's contribution to line (c, p)
+// is W h(n - u), W = a T E, T = F_tx F_rx S, E = exp(j phi).  Writing
+// B = sum_n conj(g_n) h(n - u) and B_u = sum_n conj(g_n) dh(n - u)/du,
+//   dL/da = conj(B T E),
+//   dL/dX = Re(B a E) grad T + [Im(B a E) T K0 + Re(B_u a T E) fs/c] grad R,
+// with K0 = 2 pi f0 / c and grad R = d_tx + d_rx (unit vectors antenna ->
+// facet).  dL/dz = sum_p (dL/dX)_z and dL/dV = sum_p t_p dL/dX (X = X0 + V t_p).
+// grad T and grad R are taken at the block centre (their change across a
+// block is below 1e-5 relative); everything else is the facet's own value,
+// recomputed exactly as in the forward kernel.
+//
+// Work decomposition: one wave per spatial block, lane = facet (<= 64 per
+// block).  The wave loops over channels and over stages of 32 pulses; per
+// stage, lanes 0..31 compute the FP64 block references of one pulse each into
+// LDS, then the wave stages a 16-sample window of g around the block centre's
+// sample for each of those pulses, and finally every lane walks the 32 pulses
+// reading references and window rows as LDS broadcasts.  Each facet's
+// gradient accumulates in registers over all pulses and channels and is
+// written once: no atomics, deterministic.
+#include "sim_device.h"
+
+namespace hs {
+
+namespace {
+
+constexpr int kStage = 32;   // pulses per stage
+constexpr int kGW = 16;      // staged samples per pulse: centre - 7 .. centre + 8
+constexpr int kNRef = 32;    // floats per staged pulse record
+
+// staged record layout (floats)
+enum {
+    R_T = 0, R_DTX, R_DTY, R_DTZ, R_GX, R_GY, R_GZ, R_I2RT, R_I2RR, R_PHIB, R_FB, R_NB,
+    R_GTAZ, R_GTEL, R_GRAZ, R_GREL, R_IRT, R_IRT2, R_IRR, R_IRR2, R_SB, R_SBT, R_SBR, R_MASK,
+    R_DTGX, R_DTGY, R_DTGZ, R_DBT, R_DBR, R_GRAZE
+};
+
+// Gradient of one antenna's field pattern at the block centre (FP32 from the
+// FP64 geometry): dF/dX = ka sinc'(ka u) sinc(ke v) (az - u d)/R
+//                        + ke sinc(ka u) sinc'(ke v) (el - v d)/R.
+__device__ __forceinline__ float ant_grad(const AntConst &a, double d0, double d1, double d2,
+                                          double ir, float *gr) {
+    const double u0 = d0 * ir, u1 = d1 * ir, u2 = d2 * ir;
+    const double u = u0 * a.az[0] + u1 * a.az[1] + u2 * a.az[2];
+    const double v = u0 * a.el[0] + u1 * a.el[1] + u2 * a.el[2];
+    const float xa = (float)(a.ka * u), xe = (float)(a.ke * v);
+    const float su = sinc_f(xa), sv = sinc_f(xe);
+    const float dsu = (float)a.ka * dsinc_f(xa), dsv = (float)a.ke * dsinc_f(xe);
+    const float irf = (float)ir;
+    const double uu[3] = {u0, u1, u2};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float gu = (float)(a.az[k] - u * uu[k]) * irf;
+        const float gv = (float)(a.el[k] - v * uu[k]) * irf;
+        gr[k] = dsu * sv * gu + su * dsv * gv;
+    }
+    return su * sv;
+}
+
+__global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
+    __shared__ float4 refs[kStage * kNRef / 4];
+    __shared__ float2 gwin[kStage * kGW];
+
+    const long long b = blockIdx.x;
+    const BlockRec blk = A.blocks[b];
+    const int lane = threadIdx.x;
+    const bool have = lane < blk.count;
+    const FacetRec f = A.facets[blk.start + (have ? lane : 0)];
+    const double xb = (double)blk.xb, yb = (double)blk.yb;
+
+    float gz_acc = 0.f, gvx = 0.f, gvy = 0.f, gvz = 0.f, gar = 0.f, gai = 0.f;
+    float *rf = reinterpret_cast<float *>(refs);
+
+    for (int c = 0; c < A.C; ++c) {
+        const ChanConst &cc = A.ch[c];
+        const PulseRec *PR = A.pulses + (size_t)c * A.Np + A.p0;
+        const float *gline = A.g + 2 * (size_t)c * A.np * (size_t)A.N;
+        for (int ps = 0; ps < A.np; ps += kStage) {
+            __syncthreads();   // previous stage fully consumed
+            if (lane < kStage) {
+                const int pl = ps + lane;
+                const bool live = pl < A.np;
+                const PulseRec &P = PR[live ? pl : A.np - 1];
+                Refs r;
+                block_refs(xb, yb, P.ptx, P.prx, P.rref, cc, A.f0_c, A.fs_c, A.n_ref, live, r);
+                // grad T at the centre
+                const double dt0 = xb - P.ptx[0], dt1 = yb - P.ptx[1], dt2 = -P.ptx[2];
+                const double dr0 = xb - P.prx[0], dr1 = yb - P.prx[1], dr2 = -P.prx[2];
+                float gft[3], gfr[3];
+                const float ft = ant_grad(cc.tx, dt0, dt1, dt2, (double)r.irt, gft);
+                const float fr = ant_grad(cc.rx, dr0, dr1, dr2, (double)r.irr, gfr);
+                float *o = rf + lane * kNRef;
+                const float gs[3] = {-r.sb * (r.dtx * r.irt + (r.gx - r.dtx) * r.irr),
+                                     -r.sb * (r.dty * r.irt + (r.gy - r.dty) * r.irr),
+                                     -r.sb * (r.dtz * r.irt + (r.gz - r.dtz) * r.irr)};
+                const float m = r.mask;
+                o[R_DTGX] = m * (fr * r.sb * gft[0] + ft * r.sb * gfr[0] + ft * fr * gs[0]);
+                o[R_DTGY] = m * (fr * r.sb * gft[1] + ft * r.sb * gfr[1] + ft * fr * gs[1]);
+                o[R_DTGZ] = m * (fr * r.sb * gft[2] + ft * r.sb * gfr[2] + ft * fr * gs[2]);
+                o[R_T] = (float)P.t;
+                o[R_DTX] = r.dtx; o[R_DTY] = r.dty; o[R_DTZ] = r.dtz;
+                o[R_GX] = r.gx; o[R_GY] = r.gy; o[R_GZ] = r.gz;
+                o[R_I2RT] = r.i2rt; o[R_I2RR] = r.i2rr;
+                o[R_PHIB] = r.phib; o[R_FB] = r.fb;
+                o[R_NB] = __int_as_float(r.nb);
+                o[R_GTAZ] = r.gtaz; o[R_GTEL] = r.gtel; o[R_GRAZ] = r.graz; o[R_GREL] = r.grel;
+                o[R_IRT] = r.irt; o[R_IRT2] = r.irt2; o[R_IRR] = r.irr; o[R_IRR2] = r.irr2;
+                o[R_SB] = r.sb; o[R_SBT] = r.sbt; o[R_SBR] = r.sbr; o[R_MASK] = r.mask;
+                o[R_DBT] = r.dbt; o[R_DBR] = r.dbr;
+                o[R_GRAZE] = __int_as_float(r.graze);
+            }
+            __syncthreads();
+            // stage g: row = lane / 2 holds samples nb - 7 .. nb + 8 of its pulse
+            {
+                const int row = lane >> 1, half = lane & 1;
+                const int pl = ps + row;
+                const int nb = __float_as_int(rf[row * kNRef + R_NB]);
+                const int base = nb - 7 + half * 8;
+                const float *gl = gline + 2 * (size_t)(pl < A.np ? pl : 0) * A.N;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int n = base + k;
+                    float2 v = make_float2(0.f, 0.f);
+                    if (pl < A.np && n >= 0 && n < A.N) v = make_float2(gl[2 * n], gl[2 * n + 1]);
+                    gwin[row * kGW + half * 8 + k] = v;
+                }
+            }
+            __syncthreads();
+            const int nq = (A.np - ps) < kStage ? (A.np - ps) : kStage;
+            for (int q = 0; q < nq; ++q) {
+                const float *o = rf + q * kNRef;
+                Refs r;
+                r.dtx = o[R_DTX]; r.dty = o[R_DTY]; r.dtz = o[R_DTZ];
+                r.gx = o[R_GX]; r.gy = o[R_GY]; r.gz = o[R_GZ];
+                r.i2rt = o[R_I2RT]; r.i2rr = o[R_I2RR];
+                r.phib = o[R_PHIB]; r.fb = o[R_FB]; r.nb = __float_as_int(o[R_NB]);
+                r.gtaz = o[R_GTAZ]; r.gtel = o[R_GTEL]; r.graz = o[R_GRAZ]; r.grel = o[R_GREL];
+                r.irt = o[R_IRT]; r.irt2 = o[R_IRT2]; r.irr = o[R_IRR]; r.irr2 = o[R_IRR2];
+                r.sb = o[R_SB]; r.sbt = o[R_SBT]; r.sbr = o[R_SBR]; r.mask = o[R_MASK];
+                r.dbt = o[R_DBT]; r.dbr = o[R_DBR]; r.graze = __float_as_int(o[R_GRAZE]);
+                const float tf = o[R_T];
+                Geo g;
+                facet_geo(r, cc, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz, r.graze != 0, A.linv_hi,
+                          A.linv_lo, A.fs_cf, g);
+                float tap[8], dtap[8];
+                taps8(A.tp, g.f, tap);
+                dtaps8(A.tp, g.f, dtap);
+                // g at samples floor(u) - 3 .. floor(u) + 4
+                const int w0 = g.fl + 4;            // window index of the first tap
+                float br = 0.f, bi = 0.f, dr = 0.f, di = 0.f;
+                if ((unsigned)w0 <= (unsigned)(kGW - 8)) {
+                    const float2 *gw = gwin + q * kGW + w0;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const float2 v = gw[k];
+                        br = fmaf(v.x, tap[k], br);
+                        bi = fmaf(v.y, tap[k], bi);
+                        dr = fmaf(v.x, dtap[k], dr);
+                        di = fmaf(v.y, dtap[k], di);
+                    }
+                } else {
+                    const float *gl = gline + 2 * (size_t)(ps + q) * A.N;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const int n = r.nb + g.fl - 3 + k;
+                        if (n >= 0 && n < A.N) {
+                            const float vx = gl[2 * n], vy = gl[2 * n + 1];
+                            br = fmaf(vx, tap[k], br);
+                            bi = fmaf(vy, tap[k], bi);
+                            dr = fmaf(vx, dtap[k], dr);
+                            di = fmaf(vy, dtap[k], di);
+                        }
+                    }
+                }
+                bi = -bi;     // B = sum conj(g) h
+                di = -di;     // B_u = sum conj(g) dh/du
+                const float T = g.amp;
+                // a E
+                const float aer = fmaf(f.ar, g.cs, -(f.ai * g.sn));
+                const float aei = fmaf(f.ar, g.sn, f.ai * g.cs);
+                // P = B a E
+                const float pr = fmaf(br, aer, -(bi * aei));
+                const float pi = fmaf(br, aei, bi * aer);
+                // Re(B_u a E) T
+                const float bu = fmaf(dr, aer, -(di * aei)) * T;
+                const float cR = fmaf(pi * T, A.k0, bu * A.fs_cf);
+                const float gxv = fmaf(pr, o[R_DTGX], cR * r.gx);
+                const float gyv = fmaf(pr, o[R_DTGY], cR * r.gy);
+                const float gzv = fmaf(pr, o[R_DTGZ], cR * r.gz);
+                gz_acc += gzv;
+                gvx = fmaf(tf, gxv, gvx);
+                gvy = fmaf(tf, gyv, gvy);
+                gvz = fmaf(tf, gzv, gvz);
+                // dL/da = conj(B T E)
+                gar = fmaf(T, fmaf(br, g.cs, -(bi * g.sn)), gar);
+                gai = fmaf(-T, fmaf(br, g.sn, bi * g.cs), gai);
+            }
+        }
+    }
+
+    if (have) {
+        const int i = A.perm[blk.start + lane];
+        if (A.accumulate) {
+            if (A.dz) A.dz[i] += gz_acc;
+            if (A.dvx) A.dvx[i] += gvx;
+            if (A.dvy) A.dvy[i] += gvy;
+            if (A.dvz) A.dvz[i] += gvz;
+            if (A.dar) A.dar[i] += gar;
+            if (A.dai) A.dai[i] += gai;
+        } else {
+            if (A.dz) A.dz[i] = gz_acc;
+            if (A.dvx) A.dvx[i] = gvx;
+            if (A.dvy) A.dvy[i] = gvy;
+            if (A.dvz) A.dvz[i] = gvz;
+            if (A.dar) A.dar[i] = gar;
+            if (A.dai) A.dai[i] = gai;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_adjoint(const AdjArgs &a, hipStream_t s) {
+    if (a.n_blocks == 0 || a.np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adjoint, dim3((unsigned)a.n_blocks), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace hs

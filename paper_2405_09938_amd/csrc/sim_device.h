@@ -1,0 +1,195 @@
+// Device-side building blocks shared by the forward and adjoint kernels:
+// FP64 per-(block, pulse) references and the FP32 per-facet geometry.
+//
+// Precision scheme.  The carrier wavelength (5.5 cm) sits against ~1.7e6 m
+// of bistatic path, so a facet's range cannot be formed in FP32.  Per
+// (block, pulse) the block centre's leg ranges R_b, unit vectors d, phase in
+// cycles (integer part removed) and sample position (integer + fraction) are
+// computed in FP64.  Per facet only its offset e from the block centre
+// (|e| of a few metres: the block half-diagonal, the height and the drift
+// V t_p) enters FP32, through the expansion of each leg
+//   R - R_b = e.d + (|e|^2 - (e.d)^2) / (2 R_b) + O(|e|^3 / R_b^2),
+// whose neglected term is below 1e-8 m for |e| < 30 m.  The phase product
+// dR * f0/c uses a two-float split of f0/c and an FMA residual, so the
+// integer number of cycles is removed without rounding the large product.
+#pragma once
+
+#include "sim_internal.h"
+
+namespace hs {
+
+constexpr float kPiF = 3.14159265358979323846f;
+
+// sinc(x) = sin(pi x) / (pi x).  The hardware sine takes revolutions, so
+// sin(pi x) = v_sin(x / 2), valid while |x| / 2 <= 256; sim_create keeps
+// kappa / beta <= 500 (direction cosines are at most 1).
+__device__ __forceinline__ float sinc_f(float x) {
+    const float s = __builtin_amdgcn_sinf(0.5f * x);
+    const float r = s * __builtin_amdgcn_rcpf(kPiF * x);
+    return (fabsf(x) < 1e-6f) ? 1.0f : r;
+}
+
+// derivative of sinc: (cos(pi x) - sinc(x)) / x
+__device__ __forceinline__ float dsinc_f(float x) {
+    const float c = __builtin_amdgcn_cosf(0.5f * x);
+    const float r = (c - sinc_f(x)) * __builtin_amdgcn_rcpf(x);
+    return (fabsf(x) < 1e-6f) ? 0.0f : r;
+}
+
+__device__ __forceinline__ float poly3(const float *c, float y) {
+    return fmaf(fmaf(fmaf(c[3], y, c[2]), y, c[1]), y, c[0]);
+}
+
+// Per-(block, pulse) references of one lane (FP64 -> FP32).
+struct Refs {
+    float dtx, dty, dtz;            // unit vector Tx -> block centre
+    float gx, gy, gz;               // gradient of the bistatic range at the centre
+    float i2rt, i2rr;               // 1 / (2 R_b) per leg
+    float phib;                     // -frac(R_b f0 / c): phase of the centre (cycles)
+    float fb;                       // fractional part of the centre's sample
+    int nb;                         // integer part of the centre's sample
+    float gtaz, gtel, graz, grel;   // (kappa/beta) (D . axis) per antenna axis
+    float irt, irt2, irr, irr2;     // 1/R_b and 1/R_b^2 per leg
+    float sb, sbt, sbr;             // spreading at the centre, and over R per leg
+    float mask;                     // 1 if the lane's pulse is live and in front
+    float dbt, dbr;                 // D . b per leg (grazing blocks only)
+    int graze;                      // block straddles an antenna's back plane
+};
+
+__device__ __forceinline__ void block_refs(double xb, double yb, const double *ptx,
+                                           const double *prx, double rref,
+                                           const ChanConst &cc, double f0_c, double fs_c,
+                                           double n_ref, bool live, Refs &r) {
+    const double dt0 = xb - ptx[0], dt1 = yb - ptx[1], dt2 = -ptx[2];
+    const double dr0 = xb - prx[0], dr1 = yb - prx[1], dr2 = -prx[2];
+    const double rt = sqrt(dt0 * dt0 + dt1 * dt1 + dt2 * dt2);
+    const double rr = sqrt(dr0 * dr0 + dr1 * dr1 + dr2 * dr2);
+    const double irt = 1.0 / rt, irr = 1.0 / rr;
+    const double ut0 = dt0 * irt, ut1 = dt1 * irt, ut2 = dt2 * irt;
+    const double ur0 = dr0 * irr, ur1 = dr1 * irr, ur2 = dr2 * irr;
+    r.dtx = (float)ut0;
+    r.dty = (float)ut1;
+    r.dtz = (float)ut2;
+    r.gx = (float)(ut0 + ur0);
+    r.gy = (float)(ut1 + ur1);
+    r.gz = (float)(ut2 + ur2);
+    r.i2rt = (float)(0.5 * irt);
+    r.i2rr = (float)(0.5 * irr);
+    const double rb = rt + rr;
+    const double cyc = rb * f0_c;
+    r.phib = (float)(rint(cyc) - cyc);
+    const double ub = n_ref + (rb - rref) * fs_c;
+    const double fl = floor(ub);
+    r.fb = (float)(ub - fl);
+    r.nb = (int)fl;
+    const AntConst &t = cc.tx, &q = cc.rx;
+    r.gtaz = (float)(t.ka * (dt0 * t.az[0] + dt1 * t.az[1] + dt2 * t.az[2]));
+    r.gtel = (float)(t.ke * (dt0 * t.el[0] + dt1 * t.el[1] + dt2 * t.el[2]));
+    r.graz = (float)(q.ka * (dr0 * q.az[0] + dr1 * q.az[1] + dr2 * q.az[2]));
+    r.grel = (float)(q.ke * (dr0 * q.el[0] + dr1 * q.el[1] + dr2 * q.el[2]));
+    r.irt = (float)irt;
+    r.irt2 = (float)(irt * irt);
+    r.irr = (float)irr;
+    r.irr2 = (float)(irr * irr);
+    const double sb = cc.rtrr_mid * irt * irr;
+    r.sb = (float)sb;
+    r.sbt = (float)(sb * irt);
+    r.sbr = (float)(sb * irr);
+    const double dbt = dt0 * t.b[0] + dt1 * t.b[1] + dt2 * t.b[2];
+    const double dbr = dr0 * q.b[0] + dr1 * q.b[1] + dr2 * q.b[2];
+    r.dbt = (float)dbt;
+    r.dbr = (float)dbr;
+    // Facets lie within ~100 m of the centre, so their direction cosines with a
+    // boresight differ from the centre's by < 100 / R; a margin of 200 / R
+    // decides whole blocks, the rest is checked facet by facet.
+    const double mt = dbt * irt, mr = dbr * irr;
+    const double margin = 200.0 * (irt > irr ? irt : irr);
+    const bool front = mt > margin && mr > margin;
+    const bool behind = mt < -margin || mr < -margin;
+    r.graze = (live && !front && !behind) ? 1 : 0;
+    r.mask = (live && front) ? 1.0f : 0.0f;
+}
+
+// Per-facet geometry of one (facet, pulse) pair.
+struct Geo {
+    float dR;        // bistatic range minus the block centre's
+    float sn, cs;    // sin, cos of the carrier phase (2 pi cycles)
+    float amp;       // F_tx F_rx S (times the mask)
+    float f;         // fractional sample position
+    int fl;          // floor(fb + dR fs/c): sample offset from the centre's
+};
+
+__device__ __forceinline__ void facet_geo(const Refs &r, const ChanConst &cc, float tf,
+                                          float fdx, float fdy, float fz, float fvx, float fvy,
+                                          float fvz, bool graze_any, float linv_hi,
+                                          float linv_lo, float fs_c, Geo &o) {
+    const float ex = fmaf(fvx, tf, fdx);
+    const float ey = fmaf(fvy, tf, fdy);
+    const float ez = fmaf(fvz, tf, fz);
+    const float ee = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+    const float L = fmaf(ez, r.gz, fmaf(ey, r.gy, ex * r.gx));
+    const float at = fmaf(ez, r.dtz, fmaf(ey, r.dty, ex * r.dtx));
+    const float ar = L - at;
+    const float qt = fmaf(-at, at, ee) * r.i2rt;
+    const float qr = fmaf(-ar, ar, ee) * r.i2rr;
+    const float dR = L + (qt + qr);
+    // phase (cycles) = phib - dR f0/c, product split so the integer part of
+    // the cycle count is removed exactly
+    const float hi = dR * linv_hi;
+    float lo = fmaf(dR, linv_hi, -hi);
+    lo = fmaf(dR, linv_lo, lo);
+    const float ph = (r.phib - (hi - rintf(hi))) - lo;
+    o.sn = __builtin_amdgcn_sinf(ph);
+    o.cs = __builtin_amdgcn_cosf(ph);
+    // antenna field patterns; 1/R per leg to first order in the offset
+    const float irtf = fmaf(-at, r.irt2, r.irt);
+    const float irrf = fmaf(-ar, r.irr2, r.irr);
+    const float xta = fmaf(ez, cc.kta[2], fmaf(ey, cc.kta[1], fmaf(ex, cc.kta[0], r.gtaz))) * irtf;
+    const float xte = fmaf(ez, cc.kte[2], fmaf(ey, cc.kte[1], fmaf(ex, cc.kte[0], r.gtel))) * irtf;
+    const float xra = fmaf(ez, cc.kra[2], fmaf(ey, cc.kra[1], fmaf(ex, cc.kra[0], r.graz))) * irrf;
+    const float xre = fmaf(ez, cc.kre[2], fmaf(ey, cc.kre[1], fmaf(ex, cc.kre[0], r.grel))) * irrf;
+    const float ft = sinc_f(xta) * sinc_f(xte);
+    const float fr = sinc_f(xra) * sinc_f(xre);
+    // spreading R_mid^2 / (R_t R_r), first order in the offsets
+    const float s = fmaf(-ar, r.sbr, fmaf(-at, r.sbt, r.sb));
+    float m = r.mask;
+    if (graze_any) {
+        const float ct = fmaf(ez, cc.bt[2], fmaf(ey, cc.bt[1], fmaf(ex, cc.bt[0], r.dbt)));
+        const float cr = fmaf(ez, cc.br[2], fmaf(ey, cc.br[1], fmaf(ex, cc.br[0], r.dbr)));
+        if (r.graze) m = (ct > 0.0f && cr > 0.0f) ? 1.0f : 0.0f;
+    }
+    o.amp = ft * fr * s * m;
+    const float uu = fmaf(dR, fs_c, r.fb);
+    const float fl = floorf(uu);
+    o.f = uu - fl;
+    o.fl = (int)fl;
+    o.dR = dR;
+}
+
+// The 8 taps at samples floor(u) - 3 .. floor(u) + 4 for fractional part f.
+__device__ __forceinline__ void taps8(const TapPoly &tp, float f, float *tap) {
+    const float sg = fmaf(f, 2.0f, -1.0f);
+    const float y = sg * sg;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float e = poly3(tp.e[j], y);
+        const float od = sg * poly3(tp.o[j], y);
+        tap[4 + j] = e + od;        // sample floor(u) + 1 + j
+        tap[3 - j] = e - od;        // sample floor(u) - j
+    }
+}
+
+// Derivatives of the 8 taps with respect to u.
+__device__ __forceinline__ void dtaps8(const TapPoly &tp, float f, float *d) {
+    const float sg = fmaf(f, 2.0f, -1.0f);
+    const float y = sg * sg;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float e = poly3(tp.ed[j], y);
+        const float od = sg * poly3(tp.od[j], y);
+        d[4 + j] = e + od;
+        d[3 - j] = od - e;
+    }
+}
+
+}  // namespace hs

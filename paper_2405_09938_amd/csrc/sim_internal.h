@@ -1,0 +1,205 @@
+// Internal types and launcher declarations of the facet-sum library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "heeps_sim.h"
+
+namespace hs {
+
+// Per (channel, pulse) FP64 geometry, indexed by the global pulse index.
+struct PulseRec {
+    double t;        // pulse time t_p (s)
+    double ptx[3];   // Tx phase centre at t_p
+    double prx[3];   // Rx phase centre at t_p + tau_ref
+    double rref;     // c * tau_ref: bistatic range of O
+};
+
+// Sorted facet copy, one record per facet in block order (32 bytes, so one
+// scalar load brings a whole facet into SGPRs).  (dx, dy) = position minus the
+// block centre, exact in float32.
+struct alignas(32) FacetRec {
+    float dx, dy, z;
+    float vx, vy, vz;
+    float ar, ai;
+};
+
+// Spatial block: exact float32 centre (the FP64 reference point of its
+// facets) and the range [start, start + count) of its facets, count <= 64.
+struct alignas(16) BlockRec {
+    float xb, yb;
+    int start, count;
+};
+
+// Antenna pattern constants (FP64 frame + FP32 scaled axes for the facet part).
+struct AntConst {
+    double az[3], el[3], b[3];
+    double ka, ke;          // kappa / beta_az, kappa / beta_el
+};
+
+// Interpolator in polynomial form.  With sigma = 2f - 1 (f the fractional
+// sample position) the tap of offset j in {1,2,3,4} is
+//   Q_j(sigma) = E_j(sigma^2) + sigma O_j(sigma^2)  (samples floor(u)+j),
+// its mirror (samples floor(u)+1-j) is Q_j(-sigma), and the derivatives with
+// respect to u are  D_j = Ed_j(sigma^2) + sigma Od_j(sigma^2)  and
+// -(Ed_j - sigma Od_j).  Horner order: c[0] + y (c[1] + y (c[2] + y c[3])).
+struct TapPoly {
+    float e[4][4];
+    float o[4][4];
+    float ed[4][4];
+    float od[4][4];
+};
+
+// Lattice of spatial blocks and patches.
+struct Lattice {
+    double edge;            // block edge B (m)
+    long long bx0, by0;     // lattice origin in cells: x = (bx0 + cx) B
+    int nbx, nby;           // cells along x, y
+    int px, py;             // cells per patch along x, y
+    int npx, npy;           // patches along x, y
+};
+
+struct ChanConst {
+    AntConst tx, rx;
+    double rtrr_mid;        // R_t,mid * R_r,mid
+    // FP32 forms for the per-facet part: (kappa/beta) * axis, boresights
+    float kta[3], kte[3], kra[3], kre[3];
+    float bt[3], br[3];
+};
+
+// Arguments of the fused forward kernel.
+struct FwdArgs {
+    const FacetRec *facets;
+    const BlockRec *blocks;
+    const int *patch_first;     // [n_patches + 1] first block of each patch
+    const PulseRec *pulses;     // [C][Np]
+    const ChanConst *ch;        // [C]
+    float *iq;                  // [C][np][N] complex64 interleaved
+    TapPoly tp;
+    Lattice lat;
+    double f0_c, fs_c, n_ref;   // f0/c, fs/c, reference sample
+    float linv_hi, linv_lo;     // f0/c split so that linv_hi + linv_lo ~ f0/c
+    float fs_cf;                // fs/c in float
+    int N, Np, p0, np;
+    int n_patches;
+    int halo;                   // bins added on each side of the patch span
+};
+
+// Arguments of the adjoint kernel.
+struct AdjArgs {
+    const FacetRec *facets;
+    const BlockRec *blocks;
+    const int *perm;            // sorted position -> original facet index
+    const PulseRec *pulses;
+    const float *g;             // [C][np][N] complex64 interleaved
+    float *dz, *dvx, *dvy, *dvz, *dar, *dai;
+    const ChanConst *ch;        // [C]
+    TapPoly tp;
+    double f0_c, fs_c, n_ref;
+    float linv_hi, linv_lo, fs_cf, k0;
+    int N, Np, p0, np, C;
+    long long n_blocks;
+    int accumulate;
+};
+
+}  // namespace hs
+
+// ---- opaque handle / plan --------------------------------------------------
+
+struct sim_handle {
+    // configuration
+    double c, f0, fs, prf;
+    int N, Np, n_ref;
+    double beta;
+    double chirp_bw, chirp_T;
+    std::vector<sim_traj> plats;
+    std::vector<sim_antenna> ants;
+    std::vector<sim_channel> chans;
+    int C;
+    // derived on the host in FP64
+    double kappa;
+    std::vector<hs::AntConst> antc;
+    std::vector<hs::ChanConst> chc;
+    std::vector<hs::PulseRec> pulses_h;     // [C][Np]
+    hs::TapPoly tp;
+    double tap_fit_err;
+    int chirp_len, fft_len;
+    std::vector<float> spec_h, tw_h;    // waveform spectrum and twiddles (host copies)
+    bool uploaded = false;              // device tables exist (on `device`)
+    int device = -1;
+    // device tables
+    hs::PulseRec *pulses_d = nullptr;
+    hs::ChanConst *chc_d = nullptr;     // [C]
+    float *chirp_spec_d = nullptr;      // [M] complex64: FFT_M(chirp) / M
+    float *twiddle_d = nullptr;         // [M] complex64: exp(-2 pi i m / M)
+    double *gen_tab_d = nullptr;        // wave component table of the generator
+    size_t gen_tab_cap = 0;
+    std::vector<double> gen_tab_h;
+};
+
+struct sim_plan {
+    sim_handle *h;
+    long long n;                 // facets
+    long long n_blocks;
+    long long n_patches;
+    hs::Lattice lat;
+    int halo;                    // range-window halo in samples (heights, drift)
+    int *perm = nullptr;         // [n] sorted position -> facet index
+    hs::BlockRec *blocks = nullptr;     // [n_blocks]
+    int *patch_first = nullptr;  // [n_patches + 1]
+    hs::FacetRec *sorted = nullptr;     // [n] scratch refreshed by each call
+};
+
+// ---- launchers (each returns hipError_t of the launch) --------------------
+namespace hs {
+
+void set_error(const std::string &msg);
+
+hipError_t launch_fill_zero(float *p, long long n_floats, hipStream_t s);
+
+// Plan construction kernels.
+hipError_t launch_bbox(const float *x, const float *y, long long n, float *out4,
+                       hipStream_t s);
+hipError_t launch_cell_keys(const float *x, const float *y, long long n, const Lattice &L,
+                            int *keys, int *rank, int *count, hipStream_t s);
+hipError_t launch_exclusive_scan(const int *in, int *out, long long n, int *tmp,
+                                 long long tmp_len, hipStream_t s);
+long long scan_tmp_len(long long n);
+hipError_t launch_scatter(const int *keys, const int *rank, const int *offset, long long n,
+                          int *perm, hipStream_t s);
+hipError_t launch_block_counts(const int *count, long long n_keys, int *nblk, hipStream_t s);
+hipError_t launch_make_blocks(const int *count, const int *offset, const int *blk_offset,
+                              long long n_keys, const Lattice &L, BlockRec *blocks,
+                              hipStream_t s);
+hipError_t launch_patch_first(const int *blk_offset, long long n_patches, int keys_per_patch,
+                              long long n_keys, int *patch_first, hipStream_t s);
+hipError_t launch_gather(const sim_facets &f, const int *perm, const BlockRec *blocks,
+                         long long n_blocks, FacetRec *sorted, hipStream_t s);
+
+// Hot path.
+hipError_t launch_forward(const FwdArgs &a, int C, hipStream_t s);
+hipError_t launch_adjoint(const AdjArgs &a, hipStream_t s);
+hipError_t launch_waveform(const float *in, float *out, long long n_lines, int N, int M,
+                           int shift, const float *spec, const float *tw, int adjoint,
+                           hipStream_t s);
+
+// Facet generation.
+struct GenArgs {
+    int nx, ny;
+    double dx, dy;
+    int mode;
+    double sigma_v;
+    int n_comp;
+    const double *tab;          // [n_comp][6]: k, A, omega, cos psi, sin psi, phase
+    double cur0, cur1;
+    unsigned long long seed;
+    int ix0, iy0, cnx, cny;
+    sim_facets_out out;
+};
+hipError_t launch_generate(const GenArgs &a, hipStream_t s);
+
+}  // namespace hs

@@ -1,0 +1,246 @@
+"""PyTorch-facing API over the C ABI (include/heeps_sim.h).
+
+PyTorch supplies device memory and the current HIP stream; every step of the
+facet sum, its adjoint, the waveform convolution and the facet generation
+runs in the library's own gfx950 kernels.  Nothing here computes any part of
+the method: functions only marshal arguments, allocate outputs and call the
+library.  If the library cannot be loaded, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, Iterable, Optional
+
+import numpy as np
+import torch
+
+from . import _native as N
+
+FACET_KEYS = ("x", "y", "z", "vx", "vy", "vz", "a_re", "a_im")
+GRAD_KEYS = ("z", "vx", "vy", "vz", "a_re", "a_im")
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _fptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return ctypes.cast(None, ctypes.POINTER(ctypes.c_float))
+    return ctypes.cast(t.data_ptr(), ctypes.POINTER(ctypes.c_float))
+
+
+def _check_f32(t: torch.Tensor, n: int, name: str, device) -> torch.Tensor:
+    if t.dtype != torch.float32 or t.device != device or t.numel() != n:
+        raise ValueError(f"{name}: need a float32 tensor of {n} elements on {device}")
+    return t.contiguous()
+
+
+class Simulator:
+    """One acquisition (geometry, antennas, channels, waveform) on one GPU.
+
+    ``geometry`` is any object with the attributes f0, fs, prf, n_samples,
+    n_pulses, n_ref, kaiser_beta, chirp_bw, chirp_T, c and the sequences
+    platforms (p0, v), antennas (platform, beta_az, beta_el) and channels
+    (tx, rx, pc_offset).
+    """
+
+    def __init__(self, geometry):
+        self.lib = N.load()
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        g = geometry
+        self._plats = (N.SimTraj * len(g.platforms))()
+        for i, p in enumerate(g.platforms):
+            self._plats[i].p0 = N._d3(*p.p0)
+            self._plats[i].v = N._d3(*p.v)
+        self._ants = (N.SimAntenna * len(g.antennas))()
+        for i, a in enumerate(g.antennas):
+            self._ants[i] = N.SimAntenna(a.platform, a.beta_az, a.beta_el)
+        self._chans = (N.SimChannel * len(g.channels))()
+        for i, ch in enumerate(g.channels):
+            self._chans[i] = N.SimChannel(ch.tx, ch.rx, N._d3(*ch.pc_offset))
+        cfg = N.SimConfig()
+        cfg.c, cfg.f0, cfg.fs, cfg.prf = g.c, g.f0, g.fs, g.prf
+        cfg.n_samples, cfg.n_pulses, cfg.n_ref = g.n_samples, g.n_pulses, g.n_ref
+        cfg.kaiser_beta, cfg.chirp_bw, cfg.chirp_T = g.kaiser_beta, g.chirp_bw, g.chirp_T
+        cfg.n_platforms, cfg.platforms = len(g.platforms), self._plats
+        cfg.n_antennas, cfg.antennas = len(g.antennas), self._ants
+        cfg.n_channels, cfg.channels = len(g.channels), self._chans
+        h = ctypes.c_void_p()
+        N.check(self.lib.sim_create(ctypes.byref(cfg), ctypes.byref(h)), "sim_create")
+        self.handle = h
+        self.n_channels = len(g.channels)
+        self.n_samples = g.n_samples
+        self.n_pulses = g.n_pulses
+        L, M = ctypes.c_int(), ctypes.c_int()
+        N.check(self.lib.sim_waveform_info(h, ctypes.byref(L), ctypes.byref(M)),
+                "sim_waveform_info")
+        self.chirp_len, self.fft_len = L.value, M.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.sim_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- metadata ----------------------------------------------------------
+    def pulse_info(self, ch: int, p0: int = 0, np_: Optional[int] = None):
+        np_ = self.n_pulses - p0 if np_ is None else np_
+        t = np.zeros(np_)
+        tau = np.zeros(np_)
+        dp = ctypes.POINTER(ctypes.c_double)
+        N.check(self.lib.sim_pulse_info(self.handle, ch, p0, np_, t.ctypes.data_as(dp),
+                                        tau.ctypes.data_as(dp)), "sim_pulse_info")
+        return t, tau
+
+    # -- facets ------------------------------------------------------------
+    def _facets_struct(self, facets: Dict[str, torch.Tensor], n: int):
+        keep = [_check_f32(facets[k], n, k, self.device) for k in FACET_KEYS]
+        s = N.SimFacets(n, *[_fptr(t) for t in keep])
+        return s, keep
+
+    def plan(self, x: torch.Tensor, y: torch.Tensor, block_edge: float = 8.0) -> "Plan":
+        n = x.numel()
+        x = _check_f32(x, n, "x", self.device)
+        y = _check_f32(y, n, "y", self.device)
+        p = ctypes.c_void_p()
+        N.check(self.lib.sim_plan_create(self.handle, ctypes.c_void_p(x.data_ptr()),
+                                         ctypes.c_void_p(y.data_ptr()), n, float(block_edge),
+                                         _stream(), ctypes.byref(p)), "sim_plan_create")
+        return Plan(self, p, n)
+
+    def generate(self, sea, seed: int, ix0: int = 0, iy0: int = 0, cnx: Optional[int] = None,
+                 cny: Optional[int] = None) -> Dict[str, torch.Tensor]:
+        """Facets of the grid sub-rectangle [ix0, ix0+cnx) x [iy0, iy0+cny)."""
+        cnx = sea.nx - ix0 if cnx is None else cnx
+        cny = sea.ny - iy0 if cny is None else cny
+        n = cnx * cny
+        out = {k: torch.empty(n, dtype=torch.float32, device=self.device) for k in FACET_KEYS}
+        s = N.SimSea()
+        s.nx, s.ny, s.dx, s.dy = sea.nx, sea.ny, sea.dx, sea.dy
+        s.mode, s.sigma_v, s.n_comp = sea.mode, sea.sigma_v, sea.n_comp
+        s.k_min, s.k_max, s.slope, s.hs, s.g = sea.k_min, sea.k_max, sea.slope, sea.hs, sea.g
+        keep = []
+        if sea.mode == 1:
+            d = np.ascontiguousarray(sea.dirs, np.float64)
+            ph = np.ascontiguousarray(sea.phases, np.float64)
+            keep = [d, ph]
+            dp = ctypes.POINTER(ctypes.c_double)
+            s.dirs, s.phases = d.ctypes.data_as(dp), ph.ctypes.data_as(dp)
+        s.current[0], s.current[1] = sea.current
+        fo = N.SimFacetsOut(n, *[_fptr(out[k]) for k in FACET_KEYS])
+        N.check(self.lib.sim_generate_facets(self.handle, ctypes.byref(s), int(seed), ix0, iy0,
+                                             cnx, cny, ctypes.byref(fo), _stream()),
+                "sim_generate_facets")
+        del keep
+        return out
+
+    # -- the facet sum and its adjoint -----------------------------------------
+    def forward(self, plan: "Plan", facets: Dict[str, torch.Tensor], p0: int = 0,
+                np_: Optional[int] = None, out: Optional[torch.Tensor] = None,
+                accumulate: bool = False) -> torch.Tensor:
+        """Range-compressed IQ, complex64 [C, np, N]."""
+        np_ = self.n_pulses - p0 if np_ is None else np_
+        fs, keep = self._facets_struct(facets, plan.n)
+        shape = (self.n_channels, np_, self.n_samples)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.complex64, device=self.device)
+            accumulate = False
+        elif out.shape != shape or out.dtype != torch.complex64 or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous complex64 tensor of shape {shape}")
+        N.check(self.lib.sim_forward(self.handle, plan.ptr, ctypes.byref(fs), p0, np_,
+                                     ctypes.c_void_p(out.data_ptr()), int(accumulate),
+                                     _stream()), "sim_forward")
+        return out
+
+    def backward(self, plan: "Plan", facets: Dict[str, torch.Tensor], g_rc: torch.Tensor,
+                 p0: int = 0, np_: Optional[int] = None,
+                 need: Iterable[str] = GRAD_KEYS) -> Dict[str, torch.Tensor]:
+        """Facet gradients from g = dL/dRe(IQ_rc) + j dL/dIm(IQ_rc)."""
+        np_ = self.n_pulses - p0 if np_ is None else np_
+        fs, keep = self._facets_struct(facets, plan.n)
+        shape = (self.n_channels, np_, self.n_samples)
+        if g_rc.shape != shape or g_rc.dtype != torch.complex64:
+            raise ValueError(f"g_rc must be complex64 of shape {shape}")
+        g_rc = g_rc.contiguous()
+        need = set(need)
+        out = {k: torch.empty(plan.n, dtype=torch.float32, device=self.device)
+               for k in GRAD_KEYS if k in need}
+        gs = N.SimFacetGrads(plan.n, *[_fptr(out.get(k)) for k in GRAD_KEYS])
+        N.check(self.lib.sim_backward(self.handle, plan.ptr, ctypes.byref(fs), p0, np_,
+                                      ctypes.c_void_p(g_rc.data_ptr()), ctypes.byref(gs), 0,
+                                      _stream()), "sim_backward")
+        return out
+
+    def apply_waveform(self, iq: torch.Tensor, out: Optional[torch.Tensor] = None,
+                       adjoint: bool = False) -> torch.Tensor:
+        if iq.dtype != torch.complex64 or iq.shape[-1] != self.n_samples:
+            raise ValueError("iq must be complex64 [..., N]")
+        iq = iq.contiguous()
+        out = torch.empty_like(iq) if out is None else out
+        n_lines = iq.numel() // self.n_samples
+        fn = self.lib.sim_apply_waveform_adjoint if adjoint else self.lib.sim_apply_waveform
+        N.check(fn(self.handle, ctypes.c_void_p(iq.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                   n_lines, _stream()), "sim_apply_waveform")
+        return out
+
+
+class Plan:
+    """Block decomposition of one facet set (depends on x, y only)."""
+
+    def __init__(self, sim: Simulator, ptr: ctypes.c_void_p, n: int):
+        self.sim, self.ptr, self.n = sim, ptr, n
+        a, b, c = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_longlong()
+        N.check(sim.lib.sim_plan_info(ptr, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+                "sim_plan_info")
+        self.n_blocks, self.n_patches = b.value, c.value
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            self.sim.lib.sim_plan_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SimForward(torch.autograd.Function):
+    """IQ = sum over facets (optionally convolved with the chirp), with the
+    hand-written adjoint as backward.  Differentiable inputs: z, vx, vy, vz,
+    a_re, a_im (x, y fix the plan).  Geometry is recomputed in backward; only
+    the input tensors are saved."""
+
+    @staticmethod
+    def forward(ctx, sim, plan, p0, np_, waveform, x, y, z, vx, vy, vz, a_re, a_im):
+        facets = dict(zip(FACET_KEYS, (x, y, z, vx, vy, vz, a_re, a_im)))
+        iq = sim.forward(plan, facets, p0, np_)
+        if waveform:
+            iq = sim.apply_waveform(iq, out=iq)
+        ctx.sim, ctx.plan, ctx.p0, ctx.np_, ctx.waveform = sim, plan, p0, np_, waveform
+        ctx.save_for_backward(x, y, z, vx, vy, vz, a_re, a_im)
+        return iq
+
+    @staticmethod
+    def backward(ctx, g):
+        sim = ctx.sim
+        facets = dict(zip(FACET_KEYS, ctx.saved_tensors))
+        g = g.contiguous()
+        if ctx.waveform:
+            g = sim.apply_waveform(g, adjoint=True)
+        need = [k for k, f in zip(GRAD_KEYS, ctx.needs_input_grad[7:]) if f]
+        grads = sim.backward(ctx.plan, facets, g, ctx.p0, ctx.np_, need=need) if need else {}
+        return (None, None, None, None, None, None, None) + tuple(grads.get(k) for k in GRAD_KEYS)
+
+
+def simulate(sim: Simulator, plan: Plan, facets: Dict[str, torch.Tensor], p0: int = 0,
+             np_: Optional[int] = None, waveform: bool = False) -> torch.Tensor:
+    np_ = sim.n_pulses - p0 if np_ is None else np_
+    return SimForward.apply(sim, plan, p0, np_, waveform, *[facets[k] for k in FACET_KEYS])

@@ -1,0 +1,132 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function the
+header declares, validates its arguments before touching a device, and its
+host-side FP64 geometry (pulse times, echo delays) and waveform sizing agree
+with the oracle.  No kernel is launched here."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "heeps_sim.h")
+LIB = os.path.join(ROOT, "paper_2405_09938_amd", "libheeps_sim.so")
+
+
+@pytest.fixture(scope="module")
+def native():
+    if not os.path.exists(LIB):
+        from paper_2405_09938_amd.build import build
+        build()
+    from paper_2405_09938_amd import _native as N
+    N.load()
+    return N
+
+
+def _config(N, geom):
+    plats = (N.SimTraj * len(geom.platforms))()
+    for i, p in enumerate(geom.platforms):
+        plats[i].p0 = N._d3(*p.p0)
+        plats[i].v = N._d3(*p.v)
+    ants = (N.SimAntenna * len(geom.antennas))()
+    for i, a in enumerate(geom.antennas):
+        ants[i] = N.SimAntenna(a.platform, a.beta_az, a.beta_el)
+    chans = (N.SimChannel * len(geom.channels))()
+    for i, ch in enumerate(geom.channels):
+        chans[i] = N.SimChannel(ch.tx, ch.rx, N._d3(*ch.pc_offset))
+    cfg = N.SimConfig()
+    cfg.c, cfg.f0, cfg.fs, cfg.prf = geom.c, geom.f0, geom.fs, geom.prf
+    cfg.n_samples, cfg.n_pulses, cfg.n_ref = geom.n_samples, geom.n_pulses, geom.n_ref
+    cfg.kaiser_beta, cfg.chirp_bw, cfg.chirp_T = geom.kaiser_beta, geom.chirp_bw, geom.chirp_T
+    cfg.n_platforms, cfg.platforms = len(geom.platforms), plats
+    cfg.n_antennas, cfg.antennas = len(geom.antennas), ants
+    cfg.n_channels, cfg.channels = len(geom.channels), chans
+    return cfg, (plats, ants, chans)
+
+
+def test_exports_match_header(native):
+    text = open(HEADER).read()
+    declared = set(re.findall(r"^\s*(?:int|void|const char \*)\s*(sim_\w+)\s*\(", text, re.M))
+    assert declared == set(native.EXPORTS)
+    lib = ctypes.CDLL(LIB)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_create_validates_before_any_device_call(native):
+    L = native.load()
+    h = ctypes.c_void_p()
+    assert L.sim_create(None, ctypes.byref(h)) == native.SIM_EINVAL
+    assert b"NULL" in L.sim_last_error()
+    g = W.harmony_geometry(8, 64)
+    for field, bad in (("n_samples", 1), ("prf", -1.0), ("f0", float("nan")),
+                       ("kaiser_beta", 50.0), ("n_ref", 64), ("n_pulses", 0)):
+        cfg, keep = _config(native, g)
+        setattr(cfg, field, bad)
+        assert L.sim_create(ctypes.byref(cfg), ctypes.byref(h)) == native.SIM_EINVAL, field
+        assert len(L.sim_last_error()) > 0
+    cfg, keep = _config(native, g)
+    keep[2][0].rx_antenna = 7
+    assert L.sim_create(ctypes.byref(cfg), ctypes.byref(h)) == native.SIM_EINVAL
+    # an antenna narrower than kappa/500 rad is refused
+    cfg, keep = _config(native, g)
+    keep[1][0].beta_az = 1e-4
+    assert L.sim_create(ctypes.byref(cfg), ctypes.byref(h)) == native.SIM_EUNSUPPORTED
+
+
+def test_entry_points_reject_null(native):
+    L = native.load()
+    p = ctypes.c_void_p()
+    assert L.sim_plan_create(None, None, None, 10, 8.0, None, ctypes.byref(p)) == native.SIM_EINVAL
+    assert L.sim_forward(None, None, None, 0, 1, None, 0, None) == native.SIM_EINVAL
+    assert L.sim_backward(None, None, None, 0, 1, None, None, 0, None) == native.SIM_EINVAL
+    assert L.sim_apply_waveform(None, None, None, 1, None) == native.SIM_EINVAL
+    L.sim_destroy(None)
+    L.sim_plan_destroy(None)
+
+
+def test_host_geometry_matches_oracle(native):
+    """The library's FP64 per-pulse geometry (host side) against the oracle."""
+    L = native.load()
+    g = W.harmony_geometry(300, 256, receivers="AB", n_pc=3, chirp=True)
+    cfg, keep = _config(native, g)
+    h = ctypes.c_void_p()
+    assert L.sim_create(ctypes.byref(cfg), ctypes.byref(h)) == native.SIM_OK
+    try:
+        dp = ctypes.POINTER(ctypes.c_double)
+        for ch in range(g.n_channels):
+            t = np.zeros(300)
+            tau = np.zeros(300)
+            assert L.sim_pulse_info(h, ch, 0, 300, t.ctypes.data_as(dp),
+                                    tau.ctypes.data_as(dp)) == native.SIM_OK
+            for p in (0, 1, 150, 299):
+                to, _, _, tauo = O.pulse_geometry(g, ch, p)
+                assert abs(t[p] - to) <= 1e-15 * max(1.0, abs(to))
+                assert abs(tau[p] - tauo) <= 1e-15 * tauo
+        # pulse range validation
+        assert L.sim_pulse_info(h, 0, 250, 100, None, None) == native.SIM_EINVAL
+        assert L.sim_pulse_info(h, 6, 0, 1, None, None) == native.SIM_EINVAL
+        Lc, M = ctypes.c_int(), ctypes.c_int()
+        assert L.sim_waveform_info(h, ctypes.byref(Lc), ctypes.byref(M)) == native.SIM_OK
+        assert Lc.value == O.chirp(g).size
+        assert M.value == 1 << int(math.ceil(math.log2(256 + Lc.value - 1)))
+    finally:
+        L.sim_destroy(h)
+
+
+def test_waveform_sizes_for_workloads(native):
+    L = native.load()
+    for k, (Lexp, Mexp) in ((2, (2000, 8192)), (3, (2000, 16384))):
+        g = W.with_pulses(W.workload(k).geometry, 4)
+        cfg, keep = _config(native, g)
+        h = ctypes.c_void_p()
+        assert L.sim_create(ctypes.byref(cfg), ctypes.byref(h)) == native.SIM_OK
+        Lc, M = ctypes.c_int(), ctypes.c_int()
+        L.sim_waveform_info(h, ctypes.byref(Lc), ctypes.byref(M))
+        assert (Lc.value, M.value) == (Lexp, Mexp)
+        L.sim_destroy(h)

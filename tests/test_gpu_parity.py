@@ -1,0 +1,276 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Bars: IQ relative L2 <= 1e-4 (the stated target for the forward sum);
+gradients relative L2 <= 1e-3 per parameter group; waveform convolution and
+its adjoint <= 1e-5 (FP32 FFT); generated facets within one float32 ulp.
+Every test prints the measured error.
+"""
+import math
+import sys
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+import workloads as W
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+FKEYS = ("x", "y", "z", "vx", "vy", "vz", "a_re", "a_im")
+IQ_TOL = 1e-4
+GRAD_TOL = 1e-3
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def hs(torch_cuda):
+    import paper_2405_09938_amd as hs
+    hs.load()
+    return hs
+
+
+def to_dev(torch, facets):
+    return {k: torch.from_numpy(np.ascontiguousarray(facets[k], np.float32)).cuda()
+            for k in FKEYS}
+
+
+def f64(facets):
+    return {k: np.asarray(facets[k], np.float32).astype(np.float64) for k in FKEYS}
+
+
+def run_forward(torch, hs, geom, facets, block_edge, p0=0, np_=None, waveform=False):
+    sim = hs.Simulator(geom)
+    d = to_dev(torch, facets)
+    plan = sim.plan(d["x"], d["y"], block_edge)
+    iq = sim.forward(plan, d, p0, np_)
+    if waveform:
+        iq = sim.apply_waveform(iq)
+    torch.cuda.synchronize()
+    return iq.cpu().numpy().astype(np.complex128), sim, plan, d
+
+
+def test_lone_target(torch_cuda, hs):
+    say("case: lone target at O, config-1 geometry")
+    g = W.workload(1).geometry
+    one = {k: np.zeros(1, np.float32) for k in FKEYS}
+    one["a_re"][:] = 1.0
+    got, *_ = run_forward(torch_cuda, hs, g, one, 10.0)
+    ref = O.forward(g, f64(one))
+    err = O.rel_l2(got, ref)
+    say(f"lone target rel-L2 {err:.3e}")
+    assert err < IQ_TOL
+    assert np.all(np.abs(got[0]).argmax(axis=1) == g.ref_sample)
+
+
+def test_cfg1_forward(torch_cuda, hs):
+    say("case: config 1 (64x64 facets @5 m, 256 pulses, 512 samples)")
+    wl = W.workload(1)
+    f = W.iid_facets(64, 64, 5.0, seed=wl.seed)
+    got, sim, plan, _ = run_forward(torch_cuda, hs, wl.geometry, f, wl.block_edge)
+    ref = O.forward(wl.geometry, f64(f))
+    err = O.rel_l2(got, ref)
+    say(f"config 1 IQ rel-L2 {err:.3e} (blocks {plan.n_blocks}, patches {plan.n_patches})")
+    assert err < IQ_TOL
+
+
+def test_scattered_multichannel_ragged(torch_cuda, hs):
+    """Off-grid facets with heights, 6 channels (two receivers x 3 phase
+    centres), a ragged pulse range and an offset p0."""
+    say("case: scattered facets, 6 channels, pulses [37, 37+90)")
+    g = W.harmony_geometry(200, 512, receivers="AB", n_pc=3)
+    f = W.scattered_facets(3000, 150.0, seed=11, sigma_v=0.7, sigma_z=0.8)
+    got, *_ = run_forward(torch_cuda, hs, g, f, 8.0, p0=37, np_=90)
+    ref = O.forward(g, f64(f), 37, 90)
+    err = O.rel_l2(got, ref)
+    say(f"scattered 6-channel rel-L2 {err:.3e}")
+    assert err < IQ_TOL
+    for c in range(6):
+        ec = O.rel_l2(got[c], ref[c])
+        assert ec < IQ_TOL, (c, ec)
+
+
+def test_accumulate_and_edges(torch_cuda, hs):
+    """accumulate=1 adds; facets whose taps leave [0, N) lose those taps; a
+    wide scene exercises the out-of-window path."""
+    torch = torch_cuda
+    say("case: accumulate, window edges, wide scene")
+    g = W.harmony_geometry(64, 128)
+    rng = np.random.default_rng(3)
+    n = 2000
+    # spread far beyond the 128-sample window in range
+    f = dict(x=rng.uniform(-300, 300, n), y=rng.uniform(-700, 700, n),
+             z=rng.normal(0, 0.5, n), vx=rng.normal(0, 0.5, n), vy=rng.normal(0, 0.5, n),
+             vz=rng.normal(0, 0.5, n), a_re=rng.normal(0, 0.7, n), a_im=rng.normal(0, 0.7, n))
+    f = {k: v.astype(np.float32) for k, v in f.items()}
+    sim = hs.Simulator(g)
+    d = to_dev(torch, f)
+    plan = sim.plan(d["x"], d["y"], 8.0)
+    base = torch.full((1, 64, 128), 0.5 - 0.25j, dtype=torch.complex64, device="cuda")
+    sim.forward(plan, d, 0, 64, out=base, accumulate=True)
+    torch.cuda.synchronize()
+    got = base.cpu().numpy().astype(np.complex128) - (0.5 - 0.25j)
+    ref = O.forward(g, f64(f))
+    err = O.rel_l2(got, ref)
+    say(f"accumulate / edges rel-L2 {err:.3e}")
+    assert err < IQ_TOL
+
+
+def test_pulse_subrange_rows(torch_cuda, hs):
+    torch = torch_cuda
+    say("case: pulse sub-range equals rows of the full call")
+    g = W.harmony_geometry(128, 256)
+    f = W.iid_facets(40, 40, 2.0, seed=5, sigma_z=0.3)
+    sim = hs.Simulator(g)
+    d = to_dev(torch, f)
+    plan = sim.plan(d["x"], d["y"], 8.0)
+    full = sim.forward(plan, d).cpu().numpy()
+    part = sim.forward(plan, d, 50, 30).cpu().numpy()
+    diff = np.abs(part - full[:, 50:80]).max() / np.abs(full).max()
+    say(f"sub-range max rel diff {diff:.3e}")
+    assert diff < 1e-5
+
+
+def test_waveform_and_adjoint(torch_cuda, hs):
+    torch = torch_cuda
+    say("case: chirp convolution and adjoint, N=4096 (M=8192) and N=512")
+    for N in (4096, 512):
+        g = W.harmony_geometry(4, N, chirp=True)
+        sim = hs.Simulator(g)
+        rng = np.random.default_rng(N)
+        x = (rng.standard_normal((3, N)) + 1j * rng.standard_normal((3, N)))
+        xd = torch.from_numpy(x.astype(np.complex64)).cuda()
+        y = sim.apply_waveform(xd).cpu().numpy()
+        ref = O.waveform_fft(g, x.astype(np.complex64).astype(np.complex128))
+        e1 = O.rel_l2(y, ref)
+        ya = sim.apply_waveform(xd, adjoint=True).cpu().numpy()
+        refa = O.waveform_adjoint_fft(g, x.astype(np.complex64).astype(np.complex128))
+        e2 = O.rel_l2(ya, refa)
+        say(f"N={N}: waveform rel-L2 {e1:.3e}, adjoint rel-L2 {e2:.3e}")
+        assert e1 < 1e-5 and e2 < 1e-5
+    # the direct oracle sum on a short line
+    g = replace(W.harmony_geometry(2, 300, chirp=True), chirp_T=1e-6)
+    sim = hs.Simulator(g)
+    x = np.random.default_rng(1).standard_normal((2, 300)) + 0j
+    xd = torch.from_numpy(x.astype(np.complex64)).cuda()
+    e3 = O.rel_l2(sim.apply_waveform(xd).cpu().numpy(), O.waveform(g, x))
+    say(f"short chirp vs direct sum rel-L2 {e3:.3e}")
+    assert e3 < 1e-5
+
+
+def test_generator_matches_oracle(torch_cuda, hs):
+    torch = torch_cuda
+    say("case: facet generator, flat and wave seas, sub-rectangle")
+    g = W.harmony_geometry(4, 64)
+    sim = hs.Simulator(g)
+    for sea, seed in ((W.flat_sea(300, 200, 1.0), 7),
+                      (W.wave_sea(300, 200, 1.0, seed=3, current_speed=0.5), 9)):
+        got = sim.generate(sea, seed, 40, 30, 200, 120)
+        ref = O.generate_facets(sea, seed, 40, 30, 200, 120)
+        for k in FKEYS:
+            a = got[k].cpu().numpy()
+            b = ref[k].astype(np.float32)
+            ulps = np.abs(a.view(np.int32).astype(np.int64) - b.view(np.int32).astype(np.int64))
+            nbad = int(np.count_nonzero(ulps > 1))
+            say(f"mode {sea.mode} {k}: max ulp diff {int(ulps.max())}, "
+                f"exact {np.mean(ulps == 0):.6f}")
+            assert nbad == 0, k
+
+
+def test_generated_scene_end_to_end(torch_cuda, hs):
+    """Both sides run their own generator and forward from the same seed and
+    sea draws (config-2 style wave sea, reduced size)."""
+    torch = torch_cuda
+    say("case: end to end, wave sea 200x200 @1 m, 128 pulses, chirp")
+    g = replace(W.harmony_geometry(128, 1024, chirp=True))
+    sea = W.wave_sea(200, 200, 1.0, seed=2)
+    sim = hs.Simulator(g)
+    d = sim.generate(sea, 2)
+    plan = sim.plan(d["x"], d["y"], 8.0)
+    rc = sim.forward(plan, d)
+    raw = sim.apply_waveform(rc).cpu().numpy()
+    rc = rc.cpu().numpy()
+    fo = O.as_float32(O.generate_facets(sea, 2))
+    ref_rc = O.forward(g, f64(fo))
+    ref_raw = O.waveform_fft(g, ref_rc)
+    e1, e2 = O.rel_l2(rc, ref_rc), O.rel_l2(raw, ref_raw)
+    say(f"end-to-end rc rel-L2 {e1:.3e}, raw rel-L2 {e2:.3e}")
+    assert e1 < IQ_TOL and e2 < IQ_TOL
+
+
+def test_adjoint_vs_oracle(torch_cuda, hs):
+    """Seeded random g (the adjoint is linear in g); 6-channel geometry."""
+    torch = torch_cuda
+    say("case: adjoint vs oracle adjoint, 2000 scattered facets, 6 channels, 100 pulses")
+    g = W.harmony_geometry(100, 256, receivers="AB", n_pc=3)
+    f = W.scattered_facets(2000, 100.0, seed=21, sigma_v=0.5, sigma_z=0.5)
+    rng = np.random.default_rng(22)
+    gi = (rng.standard_normal((6, 100, 256)) + 1j * rng.standard_normal((6, 100, 256)))
+    gi = gi.astype(np.complex64)
+    sim = hs.Simulator(g)
+    d = to_dev(torch, f)
+    plan = sim.plan(d["x"], d["y"], 8.0)
+    gr = sim.backward(plan, d, torch.from_numpy(gi).cuda())
+    torch.cuda.synchronize()
+    ref = O.adjoint(g, f64(f), gi.astype(np.complex128))
+    for k in ("z", "vx", "vy", "vz", "a_re", "a_im"):
+        e = O.rel_l2(gr[k].cpu().numpy(), ref[k])
+        say(f"adjoint {k}: rel-L2 {e:.3e}")
+        assert e < GRAD_TOL, k
+
+
+def test_autograd_vs_oracle_fd(torch_cuda, hs):
+    """Loss ||IQ - T||^2 with T from a perturbed current (config-4 form),
+    reduced size; GPU autograd against the oracle adjoint and the oracle's
+    Richardson finite differences on sampled facets."""
+    torch = torch_cuda
+    say("case: autograd vs FD, 30x30 facets @1 m, 128 pulses, 512 samples")
+    g = W.harmony_geometry(128, 512)
+    f = W.iid_facets(30, 30, 1.0, seed=4)
+    psi = W.sea_draws(4)["perturb_heading"]
+    ft = dict(f)
+    ft["vx"] = (f["vx"] + 0.1 * math.cos(psi)).astype(np.float32)
+    ft["vy"] = (f["vy"] + 0.1 * math.sin(psi)).astype(np.float32)
+    sim = hs.Simulator(g)
+    d = to_dev(torch, f)
+    dt = to_dev(torch, ft)
+    plan = sim.plan(d["x"], d["y"], 8.0)
+    with torch.no_grad():
+        tgt = sim.forward(plan, dt)
+    for k in ("z", "vx", "vy", "vz", "a_re", "a_im"):
+        d[k].requires_grad_(True)
+    iq = hs.simulate(sim, plan, d)
+    loss = ((iq - tgt).abs() ** 2).sum()
+    loss.backward()
+    gpu = {k: d[k].grad.cpu().numpy() for k in ("z", "vx", "vy", "vz", "a_re", "a_im")}
+    F = f64(f)
+    T = O.forward(g, f64(ft))
+    resid = O.forward(g, F) - T
+    ref = O.adjoint(g, F, 2.0 * resid)
+    for k in gpu:
+        e = O.rel_l2(gpu[k], ref[k])
+        say(f"autograd {k} vs oracle adjoint: rel-L2 {e:.3e}")
+        assert e < GRAD_TOL, k
+    idx = np.random.default_rng(5).choice(900, 16, replace=False)
+    for k, h in (("z", 1e-3), ("vx", 1e-3), ("vz", 1e-3), ("a_re", 1e-3)):
+        fd = []
+        for i in idx:
+            d1 = O.fd_gradient(g, F, T, int(i), k, h, resid=resid)
+            d2 = O.fd_gradient(g, F, T, int(i), k, h / 2, resid=resid)
+            fd.append((4 * d2 - d1) / 3)
+        e = O.rel_l2(gpu[k][idx], np.array(fd))
+        say(f"autograd {k} vs Richardson FD (h={h}): rel-L2 {e:.3e}")
+        assert e < GRAD_TOL, k
