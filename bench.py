@@ -1,0 +1,224 @@
+"""Benchmark of the facet-sum hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 2]
+
+A step is one pass of the whole path over the workload's synthetic scene:
+facet generation on the device (Philox + linear waves), the range-binned
+block sort (plan), the fused forward sum and the per-pulse chirp
+convolution.  `value` is whole-job forward throughput in G facet-pulse
+contributions per second (facets x pulses x channels per step / step time),
+with every input generated in HBM inside the step.  A second timed loop of K
+forward+adjoint steps (loss ||raw - T||^2 against a target from a perturbed
+current, chirp adjoint, adjoint sum) gives `fwd_adj`.
+
+`roofline` reports the fused forward kernel against the VALU issue rate:
+achieved = W_alg lane-slots per contribution x contributions per launch /
+average launch time (HIP events on the launch stream), peak = 256 CUs x 64
+lanes x 2.4 GHz.  `cpu_baseline` times the FP64 oracle on a bounded pulse
+subset of the same scene on the host's cores, and `rel_l2_vs_fp64` compares
+those oracle lines with the GPU's.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Algorithmic VALU lane-slots per contribution of the forward sum at one
+# channel, frozen from the per-contribution operation listing (transcendentals
+# counted at the measured gfx950 half rate, 2 slots each).
+W_ALG_SLOTS = 165.0
+PEAK_SLOTS = 256 * 64 * 2.4e9          # lane-slots per second
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_forward_cfg2_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2405_09938_amd", "csrc", f)
+                  for f in ("k_forward.hip", "sim_device.h")]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2405_09938_amd as hs
+    import workloads as W
+
+    wl = W.workload(args.workload)
+    if wl.chunks:
+        print("bench.py times single-launch workloads; use workload 1-4", file=sys.stderr)
+        sys.exit(2)
+    geom, sea = wl.geometry, wl.sea
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    hs.load()
+    sim = hs.Simulator(geom)
+    chirp = geom.chirp_T > 0
+    contrib = wl.contributions
+    stream = torch.cuda.current_stream()
+
+    fwd_ev = []
+
+    def fwd_step(record=False):
+        f = sim.generate(sea, wl.seed)
+        plan = sim.plan(f["x"], f["y"], wl.block_edge)
+        if record:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+        rc = sim.forward(plan, f)
+        if record:
+            e1.record(stream)
+            fwd_ev.append((e0, e1))
+        out = sim.apply_waveform(rc, out=rc) if chirp else rc
+        return f, plan, out
+
+    print(f"workload {wl.name}: {contrib:.3e} contributions per step", flush=True)
+    for _ in range(args.warmup):
+        fwd_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        f, plan, out = fwd_step(record=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    step_s = (t1 - t0) / args.steps
+    value = contrib / step_s / 1e9
+    kern_ms = sum(a.elapsed_time(b) for a, b in fwd_ev) / len(fwd_ev)
+    print(f"forward step {step_s * 1e3:.3f} ms, {value:.2f} G/s; fused forward kernel "
+          f"{kern_ms:.3f} ms avg", flush=True)
+    gpu_iq = out
+
+    fwd_adj = None
+    if not args.no_adjoint:
+        # target: same scene, velocities perturbed by a 0.1 m/s current
+        psi = W.sea_draws(wl.seed)["perturb_heading"]
+        with torch.no_grad():
+            ft = dict(f)
+            ft["vx"] = f["vx"] + 0.1 * math.cos(psi)
+            ft["vy"] = f["vy"] + 0.1 * math.sin(psi)
+            tgt = sim.forward(plan, ft)
+            if chirp:
+                tgt = sim.apply_waveform(tgt, out=tgt)
+
+        def fa_step():
+            f2, plan2, o = fwd_step()
+            g = 2.0 * (o - tgt)
+            if chirp:
+                g = sim.apply_waveform(g, out=g, adjoint=True)
+            return sim.backward(plan2, f2, g)
+
+        for _ in range(max(1, args.warmup)):
+            fa_step()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(args.steps):
+            fa_step()
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        fa_s = (t3 - t2) / args.steps
+        fwd_adj = {"value": contrib / fa_s / 1e9, "unit": "G contributions/s",
+                   "ms_per_step": fa_s * 1e3}
+        print(f"forward+adjoint step {fa_s * 1e3:.3f} ms, {fwd_adj['value']:.2f} G/s",
+              flush=True)
+
+    achieved = W_ALG_SLOTS * contrib / (kern_ms * 1e-3) / 1e12
+    peak = PEAK_SLOTS / 1e12
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            tr = json.load(fh)
+        if tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == wl.name:
+            traffic = tr.get("bytes_per_launch")
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
+                "unit": "Tslot/s", "frac": round(achieved / peak, 4), "traffic": traffic,
+                "kernel": "k_forward", "w_alg_slots_per_contribution": W_ALG_SLOTS,
+                "contributions_per_launch": contrib, "avg_launch_ms": round(kern_ms, 4)}
+
+    cpu = None
+    rel = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        # bounded sample: the oracle's own scene (same seed and sea draws),
+        # all facets, pulses taken from the middle of the dwell until the
+        # time budget is spent
+        fo = O.as_float32(O.generate_facets(sea, wl.seed))
+        fo = {k: v.astype(np.float64) for k, v in fo.items()}
+        p_mid = geom.n_pulses // 2
+        chunk = 4
+        done = 0
+        t_cpu = 0.0
+        rows = []
+        while t_cpu < args.cpu_seconds and done + chunk <= geom.n_pulses // 2:
+            p0 = p_mid + done
+            ta = time.perf_counter()
+            rc = O.forward(geom, fo, p0, chunk)
+            line = O.waveform_fft(geom, rc) if chirp else rc
+            t_cpu += time.perf_counter() - ta
+            rows.append((p0, line))
+            done += chunk
+        n_contrib = wl.n_facets * done * geom.n_channels
+        cpu = {"value": n_contrib / t_cpu / 1e9, "unit": "G contributions/s",
+               "cores": O.num_threads(), "kind": "oracle",
+               "sample": f"{wl.n_facets} facets x {done} pulses (from pulse {p_mid}) x "
+                         f"{geom.n_channels} ch, FP64 direct sum + FFT waveform, {t_cpu:.1f} s"}
+        got = gpu_iq.cpu().numpy()
+        num = den = 0.0
+        for p0, line in rows:
+            d = got[:, p0:p0 + chunk] - line
+            num += float(np.sum(np.abs(d) ** 2))
+            den += float(np.sum(np.abs(line) ** 2))
+        rel = math.sqrt(num / den)
+        print(f"oracle: {cpu['value'] * 1e3:.3f} M/s on {cpu['cores']} threads; GPU vs FP64 "
+              f"rel-L2 on the sample {rel:.3e}", flush=True)
+
+    res = {
+        "metric": "G facet-pulse contributions/s (fwd) at <=1e-4 rel-L2 vs FP64",
+        "value": round(value, 3),
+        "unit": "G contributions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(step_s * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (on-device Philox facets, 64-component linear wave sea)",
+        "config": {"workload": wl.name, "facets": wl.n_facets, "pulses": geom.n_pulses,
+                   "samples": geom.n_samples, "channels": geom.n_channels, "chirp": chirp,
+                   "block_edge_m": wl.block_edge},
+        "fwd_adj": fwd_adj,
+        "rel_l2_vs_fp64": rel,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

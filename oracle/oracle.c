@@ -28,6 +28,7 @@
  *                                      d(eta)/dt = w, chunk invariance)
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -54,6 +55,9 @@ typedef struct {
 } og_config;
 
 static const double OG_PI = 3.14159265358979323846;
+
+/* Threads an OpenMP region of this library uses. */
+int og_num_threads(void) { return omp_get_max_threads(); }
 
 static double dot3(const double *a, const double *b) {
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];

@@ -69,6 +69,8 @@ def lib():
         P = ctypes.POINTER
         dp = P(ctypes.c_double)
         cfgp = P(OgConfig)
+        L.og_num_threads.argtypes = []
+        L.og_num_threads.restype = ctypes.c_int
         L.og_pulse_time.argtypes = [cfgp, ctypes.c_int]
         L.og_pulse_time.restype = ctypes.c_double
         L.og_pulse_geometry.argtypes = [cfgp, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp]
@@ -136,6 +138,10 @@ _FACET_KEYS = ("x", "y", "z", "vx", "vy", "vz", "a_re", "a_im")
 
 def _facet_arrays(facets: Dict[str, np.ndarray]):
     return [np.ascontiguousarray(facets[k], dtype=np.float64) for k in _FACET_KEYS]
+
+
+def num_threads() -> int:
+    return int(lib().og_num_threads())
 
 
 def pulse_time(geom, p: int) -> float:

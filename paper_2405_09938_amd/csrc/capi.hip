@@ -159,7 +159,7 @@ void rx_pos(const sim_handle *h, int ch, double t, double *out) {
 }
 
 // Stripmap antenna frame pointing at O from the platform position at t = 0.
-void antenna_frame(const sim_handle *h, int a, hs::AntConst &ac) {
+void antenna_frame(const sim_handle *h, int a, hs::AntArgs &ac) {
     double p[3];
     plat_pos(h, h->ants[a].platform, 0.0, p);
     const double r = norm3(p);
@@ -173,6 +173,12 @@ void antenna_frame(const sim_handle *h, int a, hs::AntConst &ac) {
     ac.el[2] = ac.b[0] * ac.az[1] - ac.b[1] * ac.az[0];
     ac.ka = h->kappa / h->ants[a].beta_az;
     ac.ke = h->kappa / h->ants[a].beta_el;
+    for (int k = 0; k < 3; ++k) {
+        ac.kaz[k] = (float)(ac.ka * ac.az[k]);
+        ac.kel[k] = (float)(ac.ke * ac.el[k]);
+        ac.b32[k] = (float)ac.b[k];
+    }
+    ac.pad = 0.0f;
 }
 
 template <typename T>
@@ -209,10 +215,6 @@ int ensure_device(sim_handle *h) {
     hipError_t e = dalloc(&h->pulses_d, h->pulses_h.size());
     if (e == hipSuccess)
         e = hipMemcpy(h->pulses_d, h->pulses_h.data(), sizeof(hs::PulseRec) * h->pulses_h.size(),
-                      hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = dalloc(&h->chc_d, h->chc.size());
-    if (e == hipSuccess)
-        e = hipMemcpy(h->chc_d, h->chc.data(), sizeof(hs::ChanConst) * h->chc.size(),
                       hipMemcpyHostToDevice);
     if (e == hipSuccess && h->fft_len > 0) {
         e = dalloc(&h->chirp_spec_d, h->spec_h.size());
@@ -325,21 +327,13 @@ int sim_create(const sim_config *cfg, sim_handle **out) {
     }
     h->chc.resize(h->C);
     for (int ch = 0; ch < h->C; ++ch) {
-        hs::ChanConst &cc = h->chc[ch];
-        cc.tx = h->antc[h->chans[ch].tx_antenna];
-        cc.rx = h->antc[h->chans[ch].rx_antenna];
+        hs::ChanArgs &cc = h->chc[ch];
+        cc.tx = h->chans[ch].tx_antenna;
+        cc.rx = h->chans[ch].rx_antenna;
         double pt[3], pr[3];
         tx_pos(h, ch, 0.0, pt);
         rx_pos(h, ch, 0.0, pr);
         cc.rtrr_mid = norm3(pt) * norm3(pr);
-        for (int k = 0; k < 3; ++k) {
-            cc.kta[k] = (float)(cc.tx.ka * cc.tx.az[k]);
-            cc.kte[k] = (float)(cc.tx.ke * cc.tx.el[k]);
-            cc.kra[k] = (float)(cc.rx.ka * cc.rx.az[k]);
-            cc.kre[k] = (float)(cc.rx.ke * cc.rx.el[k]);
-            cc.bt[k] = (float)cc.tx.b[k];
-            cc.br[k] = (float)cc.rx.b[k];
-        }
     }
     // per (channel, pulse) geometry: echo delay of O by fixed-point iteration
     h->pulses_h.resize((size_t)h->C * h->Np);
@@ -419,7 +413,6 @@ int sim_create(const sim_config *cfg, sim_handle **out) {
 void sim_destroy(sim_handle *h) {
     if (!h) return;
     if (h->pulses_d) (void)hipFree(h->pulses_d);
-    if (h->chc_d) (void)hipFree(h->chc_d);
     if (h->chirp_spec_d) (void)hipFree(h->chirp_spec_d);
     if (h->twiddle_d) (void)hipFree(h->twiddle_d);
     if (h->gen_tab_d) (void)hipFree(h->gen_tab_d);
@@ -456,7 +449,7 @@ int sim_plan_create(sim_handle *h, const float *x, const float *y, long long n,
     hipStream_t s = (hipStream_t)stream;
 
     DevBufs tmp;
-    float *bb = nullptr;
+    int *bb = nullptr;
     HS_HIP(tmp.alloc(&bb, 4), "plan alloc");
     {
         const int init[4] = {std::numeric_limits<int>::max(), std::numeric_limits<int>::min(),
@@ -512,7 +505,8 @@ int sim_plan_create(sim_handle *h, const float *x, const float *y, long long n,
     const double tmax = 0.5 * (double)(h->Np - 1) / h->prf;
     // halo: facet heights up to 4 m and drift at up to 2.5 m/s over the dwell
     const int halo = (int)std::ceil((4.0 * gzm + 2.5 * tmax * gnm) * bins_per_m) + 1;
-    const int win = 64;
+    // window of the forward kernel: 32 samples unless heights and drift need more
+    const int win = (2 * halo + 19 <= 32) ? 32 : (2 * halo + 19 <= 48 ? 48 : 64);
     const double budget = std::max(2.0, (double)(win - 2 * halo - 11));
     const double gxb = gxm * bins_per_m * block_edge, gyb = gym * bins_per_m * block_edge;
     const double target = 128.0;   // cells per patch
@@ -549,6 +543,7 @@ int sim_plan_create(sim_handle *h, const float *x, const float *y, long long n,
     P->lat = L;
     P->n_patches = n_patches;
     P->halo = halo;
+    P->win = win;
     auto fail = [&](int code, const std::string &msg) {
         sim_plan_destroy(P);
         hs::set_error(msg);
@@ -698,8 +693,9 @@ int sim_forward(sim_handle *h, sim_plan *P, const sim_facets *f, int p0, int np,
     a.blocks = P->blocks;
     a.patch_first = P->patch_first;
     a.pulses = h->pulses_d;
-    a.ch = h->chc_d;
     a.iq = iq;
+    for (size_t i = 0; i < h->antc.size(); ++i) a.ant[i] = h->antc[i];
+    for (int i = 0; i < h->C; ++i) a.ch[i] = h->chc[i];
     a.tp = h->tp;
     a.lat = P->lat;
     a.f0_c = h->f0 / h->c;
@@ -714,7 +710,7 @@ int sim_forward(sim_handle *h, sim_plan *P, const sim_facets *f, int p0, int np,
     a.np = np;
     a.n_patches = (int)P->n_patches;
     a.halo = P->halo;
-    HS_HIP(hs::launch_forward(a, h->C, s), "forward");
+    HS_HIP(hs::launch_forward(a, h->C, P->win, s), "forward");
     return SIM_OK;
 }
 
@@ -742,7 +738,8 @@ int sim_backward(sim_handle *h, sim_plan *P, const sim_facets *f, int p0, int np
     a.blocks = P->blocks;
     a.perm = P->perm;
     a.pulses = h->pulses_d;
-    a.ch = h->chc_d;
+    for (size_t i = 0; i < h->antc.size(); ++i) a.ant[i] = h->antc[i];
+    for (int i = 0; i < h->C; ++i) a.ch[i] = h->chc[i];
     a.g = g;
     a.dz = gr->dz;
     a.dvx = gr->dvx;

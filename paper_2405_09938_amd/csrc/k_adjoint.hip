@@ -40,7 +40,7 @@ enum {
 // Gradient of one antenna's field pattern at the block centre (FP32 from the
 // FP64 geometry): dF/dX = ka sinc'(ka u) sinc(ke v) (az - u d)/R
 //                        + ke sinc(ka u) sinc'(ke v) (el - v d)/R.
-__device__ __forceinline__ float ant_grad(const AntConst &a, double d0, double d1, double d2,
+__device__ __forceinline__ float ant_grad(const AntArgs &a, double d0, double d1, double d2,
                                           double ir, float *gr) {
     const double u0 = d0 * ir, u1 = d1 * ir, u2 = d2 * ir;
     const double u = u0 * a.az[0] + u1 * a.az[1] + u2 * a.az[2];
@@ -74,7 +74,10 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
     float *rf = reinterpret_cast<float *>(refs);
 
     for (int c = 0; c < A.C; ++c) {
-        const ChanConst &cc = A.ch[c];
+        const ChanArgs chn = A.ch[c];
+        const AntArgs &ta = A.ant[chn.tx], &ra = A.ant[chn.rx];
+        FacetConsts kc;
+        facet_consts(ta, ra, kc);
         const PulseRec *PR = A.pulses + (size_t)c * A.Np + A.p0;
         const float *gline = A.g + 2 * (size_t)c * A.np * (size_t)A.N;
         for (int ps = 0; ps < A.np; ps += kStage) {
@@ -84,13 +87,14 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                 const bool live = pl < A.np;
                 const PulseRec &P = PR[live ? pl : A.np - 1];
                 Refs r;
-                block_refs(xb, yb, P.ptx, P.prx, P.rref, cc, A.f0_c, A.fs_c, A.n_ref, live, r);
+                block_refs(xb, yb, P.ptx, P.prx, P.rref, ta, ra, chn.rtrr_mid, A.f0_c, A.fs_c,
+                           A.n_ref, live, r);
                 // grad T at the centre
                 const double dt0 = xb - P.ptx[0], dt1 = yb - P.ptx[1], dt2 = -P.ptx[2];
                 const double dr0 = xb - P.prx[0], dr1 = yb - P.prx[1], dr2 = -P.prx[2];
                 float gft[3], gfr[3];
-                const float ft = ant_grad(cc.tx, dt0, dt1, dt2, (double)r.irt, gft);
-                const float fr = ant_grad(cc.rx, dr0, dr1, dr2, (double)r.irr, gfr);
+                const float ft = ant_grad(ta, dt0, dt1, dt2, (double)r.irt, gft);
+                const float fr = ant_grad(ra, dr0, dr1, dr2, (double)r.irr, gfr);
                 float *o = rf + lane * kNRef;
                 const float gs[3] = {-r.sb * (r.dtx * r.irt + (r.gx - r.dtx) * r.irr),
                                      -r.sb * (r.dty * r.irt + (r.gy - r.dty) * r.irr),
@@ -142,7 +146,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                 r.dbt = o[R_DBT]; r.dbr = o[R_DBR]; r.graze = __float_as_int(o[R_GRAZE]);
                 const float tf = o[R_T];
                 Geo g;
-                facet_geo(r, cc, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz, r.graze != 0, A.linv_hi,
+                facet_geo(r, kc, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz, r.graze != 0, A.linv_hi,
                           A.linv_lo, A.fs_cf, g);
                 float tap[8], dtap[8];
                 taps8(A.tp, g.f, tap);

@@ -5,44 +5,76 @@
 // facet's fractional sample u = n_ref + (R - c tau_ref) fs / c by an 8-tap
 // Kaiser-windowed sinc (the range slices of eq. 17).
 //
-// Work decomposition (one workgroup = 4 waves):
+// Work decomposition (one workgroup = one wave):
 //   blockIdx.x = patch of spatial blocks, blockIdx.y = group of 64 pulses,
-//   blockIdx.z = channel.  Lane = pulse: every lane of a wave handles the same
-//   facet (its 32-byte record arrives through one scalar load) and deposits
-//   into its own pulse row of an LDS range window, so no two lanes of a wave
-//   touch the same LDS word.  The four waves take interleaved blocks of the
-//   patch and share the window (ds_add_f32).  At the end the window is
-//   flushed to the IQ lines with global float atomics, since neighbouring
-//   patches overlap in range.  A contribution whose taps leave the window
-//   (only for geometries the patch sizing did not foresee) goes straight to
-//   global memory.
+//   blockIdx.z = channel.  Lane = pulse: every lane handles the same facet
+//   (its 32-byte record arrives through one scalar load) and deposits into
+//   its own pulse row of an LDS range window.  Since no other lane or wave
+//   touches that row, the deposit is a plain read-modify-write (8 x 64-bit
+//   reads issued as soon as the sample index is known, 16 FMAs, 8 x 64-bit
+//   writes) instead of LDS atomics.  At the end the window is flushed to the
+//   IQ lines with global float atomics, since neighbouring patches overlap in
+//   range.  A contribution whose taps leave the window (only for geometries
+//   the patch sizing did not foresee) goes straight to global memory.
 #include "sim_device.h"
 
 namespace hs {
 
 namespace {
 
+// Read-only inputs of the kernel, accessed through the constant address
+// space: uniform indices then compile to scalar loads into SGPRs.
+template <typename T>
+using cptr = const T __attribute__((address_space(4))) *;
+
+__device__ __forceinline__ BlockRec load_block(cptr<BlockRec> p) {
+    BlockRec r;
+    r.xb = p->xb;
+    r.yb = p->yb;
+    r.start = p->start;
+    r.count = p->count;
+    return r;
+}
+
+__device__ __forceinline__ FacetRec load_facet(cptr<FacetRec> p) {
+    FacetRec r;
+    r.dx = p->dx;
+    r.dy = p->dy;
+    r.z = p->z;
+    r.vx = p->vx;
+    r.vy = p->vy;
+    r.vz = p->vz;
+    r.ar = p->ar;
+    r.ai = p->ai;
+    return r;
+}
+
 template <int WIN>
-__global__ __launch_bounds__(256) void k_forward(FwdArgs A) {
-    constexpr int STRIDE = 2 * WIN + 1;     // odd: the 64 rows start in distinct banks
-    __shared__ float acc[64 * STRIDE];
-    __shared__ int s_lo;
+__global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
+    constexpr int ROW = WIN + 1;            // complex samples per LDS row (one pad)
+    __shared__ float2 acc[64 * ROW];
 
     const int patch = blockIdx.x, grp = blockIdx.y, ch = blockIdx.z;
-    const int b0 = A.patch_first[patch], b1 = A.patch_first[patch + 1];
+    const cptr<int> patch_first = (cptr<int>)A.patch_first;
+    const cptr<BlockRec> blocks = (cptr<BlockRec>)A.blocks;
+    const cptr<FacetRec> facets = (cptr<FacetRec>)A.facets;
+    const int b0 = patch_first[patch], b1 = patch_first[patch + 1];
     if (b0 == b1) return;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x;
     const int pl = grp * 64 + lane;          // pulse relative to p0
     const bool live = pl < A.np;
     const int plc = live ? pl : (A.np - 1);
     const PulseRec *PR = A.pulses + (size_t)ch * A.Np + A.p0;
-    const ChanConst &cc = A.ch[ch];
+    const ChanArgs chn = A.ch[ch];
+    const AntArgs &ta = A.ant[chn.tx], &ra = A.ant[chn.rx];
+    FacetConsts kc;
+    facet_consts(ta, ra, kc);
 
     // Range window of this (patch, pulse group): sample positions of the
-    // patch corners at the group's first and last pulse, widened by the halo
-    // (facet heights and drift) and the taps.
-    if (wave == 0) {
+    // patch corners at the group's first and last pulse (lanes 0..7), widened
+    // by the halo (facet heights, drift) and the taps.
+    int lo;
+    {
         double umin = 1e300, umax = -1e300;
         if (lane < 8) {
             const Lattice &L = A.lat;
@@ -64,57 +96,56 @@ __global__ __launch_bounds__(256) void k_forward(FwdArgs A) {
             umin = fmin(umin, __shfl_xor(umin, off));
             umax = fmax(umax, __shfl_xor(umax, off));
         }
-        if (lane == 0) {
-            int lo = (int)floor(umin) - A.halo - 3;
-            const int hi = (int)ceil(umax) + A.halo + 4;
-            if (hi - lo + 1 > WIN) lo = ((lo + hi) >> 1) - WIN / 2;
-            s_lo = lo;
-        }
+        int l = (int)floor(umin) - A.halo - 3;
+        const int h = (int)ceil(umax) + A.halo + 4;
+        if (h - l + 1 > WIN) l = ((l + h) >> 1) - WIN / 2;
+        lo = __builtin_amdgcn_readfirstlane(l);
     }
-    for (int i = threadIdx.x; i < 64 * STRIDE; i += 256) acc[i] = 0.0f;
-    __syncthreads();
-    const int lo = s_lo;
+    float2 *row = acc + lane * ROW;
+    for (int i = 0; i < ROW; ++i) row[i] = make_float2(0.f, 0.f);
 
     const PulseRec &P = PR[plc];
     const double ptx[3] = {P.ptx[0], P.ptx[1], P.ptx[2]};
     const double prx[3] = {P.prx[0], P.prx[1], P.prx[2]};
     const double rref = P.rref;
     const float tf = (float)P.t;
-    float *row = acc + lane * STRIDE;
     float *iq_row = A.iq + 2 * ((size_t)ch * A.np + plc) * (size_t)A.N;
 
-    for (int b = b0 + wave; b < b1; b += 4) {
-        const BlockRec blk = A.blocks[b];
+    for (int b = b0; b < b1; ++b) {
+        const BlockRec blk = load_block(blocks + b);
         Refs r;
-        block_refs((double)blk.xb, (double)blk.yb, ptx, prx, rref, cc, A.f0_c, A.fs_c, A.n_ref,
-                   live, r);
+        block_refs((double)blk.xb, (double)blk.yb, ptx, prx, rref, ta, ra, chn.rtrr_mid, A.f0_c,
+                   A.fs_c, A.n_ref, live, r);
         const bool graze_any = __any(r.graze);
         const int nb0 = r.nb - lo - 3;
         const int j1 = blk.start + blk.count;
         // the sorted facet array carries one padding record, so the look-ahead
         // load of the next facet is always in bounds
-        FacetRec fn = A.facets[blk.start];
+        FacetRec fn = load_facet(facets + blk.start);
         for (int j = blk.start; j < j1; ++j) {
             const FacetRec f = fn;
-            fn = A.facets[j + 1];
+            fn = load_facet(facets + j + 1);
             Geo g;
-            facet_geo(r, cc, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz, graze_any, A.linv_hi,
+            facet_geo(r, kc, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz, graze_any, A.linv_hi,
                       A.linv_lo, A.fs_cf, g);
-            const float wr = g.amp * fmaf(f.ar, g.cs, -(f.ai * g.sn));
-            const float wi = g.amp * fmaf(f.ar, g.sn, f.ai * g.cs);
+            // Each lane owns its pulse row, so the deposit is a plain
+            // read-modify-write of 8 consecutive complex samples.
+            const int n0 = nb0 + g.fl;            // window index of the first tap
+            const bool inw = (unsigned)n0 <= (unsigned)(WIN - 8);
+            float2 *p = row + (inw ? n0 : 0);
+            float2 old[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) old[k] = p[k];
+            float wr = g.amp * fmaf(f.ar, g.cs, -(f.ai * g.sn));
+            float wi = g.amp * fmaf(f.ar, g.sn, f.ai * g.cs);
             float tap[8];
             taps8(A.tp, g.f, tap);
-            const int n0 = nb0 + g.fl;            // window index of the first tap
-            if ((unsigned)n0 <= (unsigned)(WIN - 8)) {
-                float *p = row + 2 * n0;
+            const float wrl = inw ? wr : 0.0f, wil = inw ? wi : 0.0f;
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    __hip_atomic_fetch_add(p + 2 * k, wr * tap[k], __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-                    __hip_atomic_fetch_add(p + 2 * k + 1, wi * tap[k], __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-                }
-            } else if (live) {
+            for (int k = 0; k < 8; ++k)
+                p[k] = make_float2(fmaf(wrl, tap[k], old[k].x), fmaf(wil, tap[k], old[k].y));
+            if (!inw && live) {
+                // outside the window: straight to the line, taps inside [0, N)
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     const int n = n0 + lo + k;
@@ -126,28 +157,32 @@ __global__ __launch_bounds__(256) void k_forward(FwdArgs A) {
             }
         }
     }
-    __syncthreads();
 
-    // flush the window into the lines (zeros skipped)
-    for (int i = threadIdx.x; i < 64 * WIN; i += 256) {
-        const int p = i / WIN, bin = i % WIN;
-        const int n = lo + bin;
-        const int pp = grp * 64 + p;
-        if (pp >= A.np || n < 0 || n >= A.N) continue;
-        const float vr = acc[p * STRIDE + 2 * bin], vi = acc[p * STRIDE + 2 * bin + 1];
-        if (vr == 0.0f && vi == 0.0f) continue;
-        float *dst = A.iq + 2 * (((size_t)ch * A.np + pp) * (size_t)A.N + n);
-        unsafeAtomicAdd(dst, vr);
-        unsafeAtomicAdd(dst + 1, vi);
+    // flush the window into the lines (zeros skipped); neighbouring patches
+    // overlap in range, hence the atomics
+    if (live) {
+        float *dst = A.iq + 2 * (((size_t)ch * A.np + pl) * (size_t)A.N);
+        for (int bin = 0; bin < WIN; ++bin) {
+            const int n = lo + bin;
+            const float2 v = row[bin];
+            if (n < 0 || n >= A.N || (v.x == 0.0f && v.y == 0.0f)) continue;
+            unsafeAtomicAdd(dst + 2 * n, v.x);
+            unsafeAtomicAdd(dst + 2 * n + 1, v.y);
+        }
     }
 }
 
 }  // namespace
 
-hipError_t launch_forward(const FwdArgs &a, int C, hipStream_t s) {
+hipError_t launch_forward(const FwdArgs &a, int C, int win, hipStream_t s) {
     if (a.n_patches == 0 || a.np == 0) return hipSuccess;
     dim3 grid((unsigned)a.n_patches, (unsigned)((a.np + 63) / 64), (unsigned)C);
-    hipLaunchKernelGGL(k_forward<64>, grid, dim3(256), 0, s, a);
+    switch (win) {
+        case 32: hipLaunchKernelGGL(k_forward<32>, grid, dim3(64), 0, s, a); break;
+        case 48: hipLaunchKernelGGL(k_forward<48>, grid, dim3(64), 0, s, a); break;
+        case 64: hipLaunchKernelGGL(k_forward<64>, grid, dim3(64), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

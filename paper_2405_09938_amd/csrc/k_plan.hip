@@ -19,8 +19,15 @@ __global__ void k_fill_zero(float *p, long long n) {
     for (; i < n; i += stride) p[i] = 0.0f;
 }
 
-// min x, max x, min y, max y; out4 must be pre-initialised to (+inf,-inf,+inf,-inf)
-__global__ void k_bbox(const float *x, const float *y, long long n, float *out4) {
+// Bounding box: out4 = (min x, max x, min y, max y) as order-preserving
+// integer keys of the float bit patterns; pre-initialised by the host to
+// (INT_MAX, INT_MIN, INT_MAX, INT_MIN).  One atomic per workgroup and value.
+__device__ __forceinline__ int order_key(float v) {
+    const int b = __float_as_int(v);
+    return b >= 0 ? b : (int)(0x80000000u - (unsigned)b);
+}
+
+__global__ void k_bbox(const float *x, const float *y, long long n, int *out4) {
     float mnx = INFINITY, mxx = -INFINITY, mny = INFINITY, mxy = -INFINITY;
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long stride = (long long)gridDim.x * blockDim.x;
@@ -38,18 +45,26 @@ __global__ void k_bbox(const float *x, const float *y, long long n, float *out4)
         mny = fminf(mny, __shfl_xor(mny, off));
         mxy = fmaxf(mxy, __shfl_xor(mxy, off));
     }
+    __shared__ float part[4][4];
+    const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        // float min/max through the ordered-int trick is not needed: values are
-        // finite (checked on the host); use CAS loops via atomicMin/Max on ints
-        // of the IEEE pattern mapped to a monotone order.
-        auto key = [](float v) {
-            int b = __float_as_int(v);
-            return b >= 0 ? b : (int)(0x80000000u - (unsigned)b);   // monotone map
-        };
-        atomicMin((int *)out4 + 0, key(mnx));
-        atomicMax((int *)out4 + 1, key(mxx));
-        atomicMin((int *)out4 + 2, key(mny));
-        atomicMax((int *)out4 + 3, key(mxy));
+        part[w][0] = mnx;
+        part[w][1] = mxx;
+        part[w][2] = mny;
+        part[w][3] = mxy;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < 4; ++k) {
+            mnx = fminf(mnx, part[k][0]);
+            mxx = fmaxf(mxx, part[k][1]);
+            mny = fminf(mny, part[k][2]);
+            mxy = fmaxf(mxy, part[k][3]);
+        }
+        atomicMin(out4 + 0, order_key(mnx));
+        atomicMax(out4 + 1, order_key(mxx));
+        atomicMin(out4 + 2, order_key(mny));
+        atomicMax(out4 + 3, order_key(mxy));
     }
 }
 
@@ -247,9 +262,9 @@ hipError_t launch_fill_zero(float *p, long long n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_bbox(const float *x, const float *y, long long n, float *out4, hipStream_t s) {
+hipError_t launch_bbox(const float *x, const float *y, long long n, int *out4, hipStream_t s) {
     long long g = (n + 255) / 256;
-    if (g > 4096) g = 4096;
+    if (g > 256) g = 256;
     if (g < 1) g = 1;
     hipLaunchKernelGGL(k_bbox, dim3((unsigned)g), dim3(256), 0, s, x, y, n, out4);
     return hipGetLastError();

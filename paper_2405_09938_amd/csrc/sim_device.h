@@ -57,9 +57,9 @@ struct Refs {
 };
 
 __device__ __forceinline__ void block_refs(double xb, double yb, const double *ptx,
-                                           const double *prx, double rref,
-                                           const ChanConst &cc, double f0_c, double fs_c,
-                                           double n_ref, bool live, Refs &r) {
+                                           const double *prx, double rref, const AntArgs &t,
+                                           const AntArgs &q, double rtrr_mid, double f0_c,
+                                           double fs_c, double n_ref, bool live, Refs &r) {
     const double dt0 = xb - ptx[0], dt1 = yb - ptx[1], dt2 = -ptx[2];
     const double dr0 = xb - prx[0], dr1 = yb - prx[1], dr2 = -prx[2];
     const double rt = sqrt(dt0 * dt0 + dt1 * dt1 + dt2 * dt2);
@@ -82,7 +82,6 @@ __device__ __forceinline__ void block_refs(double xb, double yb, const double *p
     const double fl = floor(ub);
     r.fb = (float)(ub - fl);
     r.nb = (int)fl;
-    const AntConst &t = cc.tx, &q = cc.rx;
     r.gtaz = (float)(t.ka * (dt0 * t.az[0] + dt1 * t.az[1] + dt2 * t.az[2]));
     r.gtel = (float)(t.ke * (dt0 * t.el[0] + dt1 * t.el[1] + dt2 * t.el[2]));
     r.graz = (float)(q.ka * (dr0 * q.az[0] + dr1 * q.az[1] + dr2 * q.az[2]));
@@ -91,7 +90,7 @@ __device__ __forceinline__ void block_refs(double xb, double yb, const double *p
     r.irt2 = (float)(irt * irt);
     r.irr = (float)irr;
     r.irr2 = (float)(irr * irr);
-    const double sb = cc.rtrr_mid * irt * irr;
+    const double sb = rtrr_mid * irt * irr;
     r.sb = (float)sb;
     r.sbt = (float)(sb * irt);
     r.sbr = (float)(sb * irr);
@@ -110,6 +109,25 @@ __device__ __forceinline__ void block_refs(double xb, double yb, const double *p
     r.mask = (live && front) ? 1.0f : 0.0f;
 }
 
+// FP32 antenna constants of one channel for the per-facet part.
+struct FacetConsts {
+    float kta[3], kte[3], kra[3], kre[3];   // (kappa/beta) * axis, Tx and Rx
+    float bt[3], br[3];                     // boresights
+};
+
+__device__ __forceinline__ void facet_consts(const AntArgs &t, const AntArgs &q,
+                                             FacetConsts &k) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        k.kta[i] = t.kaz[i];
+        k.kte[i] = t.kel[i];
+        k.kra[i] = q.kaz[i];
+        k.kre[i] = q.kel[i];
+        k.bt[i] = t.b32[i];
+        k.br[i] = q.b32[i];
+    }
+}
+
 // Per-facet geometry of one (facet, pulse) pair.
 struct Geo {
     float dR;        // bistatic range minus the block centre's
@@ -119,7 +137,7 @@ struct Geo {
     int fl;          // floor(fb + dR fs/c): sample offset from the centre's
 };
 
-__device__ __forceinline__ void facet_geo(const Refs &r, const ChanConst &cc, float tf,
+__device__ __forceinline__ void facet_geo(const Refs &r, const FacetConsts &cc, float tf,
                                           float fdx, float fdy, float fz, float fvx, float fvy,
                                           float fvz, bool graze_any, float linv_hi,
                                           float linv_lo, float fs_c, Geo &o) {

@@ -35,12 +35,6 @@ struct alignas(16) BlockRec {
     int start, count;
 };
 
-// Antenna pattern constants (FP64 frame + FP32 scaled axes for the facet part).
-struct AntConst {
-    double az[3], el[3], b[3];
-    double ka, ke;          // kappa / beta_az, kappa / beta_el
-};
-
 // Interpolator in polynomial form.  With sigma = 2f - 1 (f the fractional
 // sample position) the tap of offset j in {1,2,3,4} is
 //   Q_j(sigma) = E_j(sigma^2) + sigma O_j(sigma^2)  (samples floor(u)+j),
@@ -63,12 +57,19 @@ struct Lattice {
     int npx, npy;           // patches along x, y
 };
 
-struct ChanConst {
-    AntConst tx, rx;
-    double rtrr_mid;        // R_t,mid * R_r,mid
-    // FP32 forms for the per-facet part: (kappa/beta) * axis, boresights
-    float kta[3], kte[3], kra[3], kre[3];
-    float bt[3], br[3];
+// Per-antenna constants, passed inside the kernel arguments (constant
+// address space, so uniform reads become scalar loads).
+struct AntArgs {
+    double az[3], el[3], b[3];  // frame
+    double ka, ke;              // kappa / beta_az, kappa / beta_el
+    float kaz[3], kel[3];       // (kappa/beta) * axis, FP32 for the facet part
+    float b32[3];               // boresight, FP32
+    float pad;
+};
+
+struct ChanArgs {
+    int tx, rx;                 // antenna indices
+    double rtrr_mid;            // R_t,mid * R_r,mid
 };
 
 // Arguments of the fused forward kernel.
@@ -77,8 +78,9 @@ struct FwdArgs {
     const BlockRec *blocks;
     const int *patch_first;     // [n_patches + 1] first block of each patch
     const PulseRec *pulses;     // [C][Np]
-    const ChanConst *ch;        // [C]
     float *iq;                  // [C][np][N] complex64 interleaved
+    AntArgs ant[SIM_MAX_ANTENNAS];
+    ChanArgs ch[SIM_MAX_CHANNELS];
     TapPoly tp;
     Lattice lat;
     double f0_c, fs_c, n_ref;   // f0/c, fs/c, reference sample
@@ -97,7 +99,8 @@ struct AdjArgs {
     const PulseRec *pulses;
     const float *g;             // [C][np][N] complex64 interleaved
     float *dz, *dvx, *dvy, *dvz, *dar, *dai;
-    const ChanConst *ch;        // [C]
+    AntArgs ant[SIM_MAX_ANTENNAS];
+    ChanArgs ch[SIM_MAX_CHANNELS];
     TapPoly tp;
     double f0_c, fs_c, n_ref;
     float linv_hi, linv_lo, fs_cf, k0;
@@ -122,8 +125,8 @@ struct sim_handle {
     int C;
     // derived on the host in FP64
     double kappa;
-    std::vector<hs::AntConst> antc;
-    std::vector<hs::ChanConst> chc;
+    std::vector<hs::AntArgs> antc;
+    std::vector<hs::ChanArgs> chc;
     std::vector<hs::PulseRec> pulses_h;     // [C][Np]
     hs::TapPoly tp;
     double tap_fit_err;
@@ -133,7 +136,6 @@ struct sim_handle {
     int device = -1;
     // device tables
     hs::PulseRec *pulses_d = nullptr;
-    hs::ChanConst *chc_d = nullptr;     // [C]
     float *chirp_spec_d = nullptr;      // [M] complex64: FFT_M(chirp) / M
     float *twiddle_d = nullptr;         // [M] complex64: exp(-2 pi i m / M)
     double *gen_tab_d = nullptr;        // wave component table of the generator
@@ -148,6 +150,7 @@ struct sim_plan {
     long long n_patches;
     hs::Lattice lat;
     int halo;                    // range-window halo in samples (heights, drift)
+    int win;                     // LDS range-window width of the forward kernel
     int *perm = nullptr;         // [n] sorted position -> facet index
     hs::BlockRec *blocks = nullptr;     // [n_blocks]
     int *patch_first = nullptr;  // [n_patches + 1]
@@ -162,7 +165,7 @@ void set_error(const std::string &msg);
 hipError_t launch_fill_zero(float *p, long long n_floats, hipStream_t s);
 
 // Plan construction kernels.
-hipError_t launch_bbox(const float *x, const float *y, long long n, float *out4,
+hipError_t launch_bbox(const float *x, const float *y, long long n, int *out4,
                        hipStream_t s);
 hipError_t launch_cell_keys(const float *x, const float *y, long long n, const Lattice &L,
                             int *keys, int *rank, int *count, hipStream_t s);
@@ -181,7 +184,7 @@ hipError_t launch_gather(const sim_facets &f, const int *perm, const BlockRec *b
                          long long n_blocks, FacetRec *sorted, hipStream_t s);
 
 // Hot path.
-hipError_t launch_forward(const FwdArgs &a, int C, hipStream_t s);
+hipError_t launch_forward(const FwdArgs &a, int C, int win, hipStream_t s);
 hipError_t launch_adjoint(const AdjArgs &a, hipStream_t s);
 hipError_t launch_waveform(const float *in, float *out, long long n_lines, int N, int M,
                            int shift, const float *spec, const float *tw, int adjoint,
