@@ -57,6 +57,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of a known size (counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -65,6 +67,18 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        # Plain device-to-device copy of 512 MiB, repeated: the HBM counters
+        # of one such dispatch must read 512 MiB fetched and 512 MiB written.
+        n = 512 * 1024 * 1024 // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(max(1, args.steps)):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n * 4, "dispatches": max(1, args.steps)}))
+        return
 
     import paper_2405_09938_amd as hs
     import workloads as W

@@ -257,6 +257,32 @@ int sim_backward(sim_handle *h, sim_plan *plan, const sim_facets *facets, int p0
                  int np, const float *g_rc, const sim_facet_grads *grads,
                  int accumulate, void *stream);
 
+/*
+ * Streamed forward over a large generated scene (the paper processes the scene
+ * as a sequence of tile batches on the GPU, Sec. IV.B, and generates it where
+ * and when it is sensed, Sec. II.B): for each grid chunk k, given host
+ * chunks[4k..4k+3] = (ix0, iy0, cnx, cny), the library generates the chunk's
+ * facets (as sim_generate_facets), plans them with `block_edge` (as
+ * sim_plan_create) and adds their sum for pulses [p0, p0+np) into iq_rc
+ * (device complex64 [n_channels][np][N]); accumulate = 0 clears iq_rc first.
+ * Facets live only in a library workspace of one chunk.  Synchronises the
+ * stream once per chunk (planning).
+ */
+int sim_stream_forward(sim_handle *h, const sim_sea *sea, unsigned long long seed,
+                       const int *chunks, int n_chunks, double block_edge, int p0, int np,
+                       float *iq_rc, int accumulate, void *stream);
+
+/*
+ * Adjoint of sim_stream_forward with respect to the facet velocities: for
+ * each chunk the facets are regenerated and replanned (geometry recomputed,
+ * nothing stored), and dL/dvx, dL/dvy, dL/dvz are written (device float32,
+ * chunk after chunk, each chunk row-major in its sub-rectangle; total length
+ * sum of cnx*cny).  NULL outputs are skipped.  g_rc as in sim_backward.
+ */
+int sim_stream_backward(sim_handle *h, const sim_sea *sea, unsigned long long seed,
+                        const int *chunks, int n_chunks, double block_edge, int p0, int np,
+                        const float *g_rc, float *dvx, float *dvy, float *dvz, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -78,7 +78,8 @@ class SimSea(ctypes.Structure):
 EXPORTS = ("sim_create", "sim_destroy", "sim_last_error", "sim_pulse_info",
            "sim_waveform_info", "sim_plan_create", "sim_plan_destroy", "sim_plan_info",
            "sim_generate_facets", "sim_forward", "sim_apply_waveform",
-           "sim_apply_waveform_adjoint", "sim_backward")
+           "sim_apply_waveform_adjoint", "sim_backward", "sim_stream_forward",
+           "sim_stream_backward")
 
 _lib = None
 
@@ -118,6 +119,11 @@ def load(path: str = LIB_PATH):
     L.sim_apply_waveform.argtypes = [vp, vp, vp, ll, vp]
     L.sim_apply_waveform_adjoint.argtypes = [vp, vp, vp, ll, vp]
     L.sim_backward.argtypes = [vp, vp, P(SimFacets), i, i, vp, P(SimFacetGrads), i, vp]
+    ip = P(ctypes.c_int)
+    L.sim_stream_forward.argtypes = [vp, P(SimSea), ctypes.c_ulonglong, ip, i, ctypes.c_double,
+                                     i, i, vp, i, vp]
+    L.sim_stream_backward.argtypes = [vp, P(SimSea), ctypes.c_ulonglong, ip, i, ctypes.c_double,
+                                      i, i, vp, vp, vp, vp, vp]
     for name in EXPORTS:
         if name not in ("sim_destroy", "sim_last_error", "sim_plan_destroy"):
             getattr(L, name).restype = ctypes.c_int

@@ -115,8 +115,6 @@ double fit_taps(double beta, hs::TapPoly &tp) {
         for (int k = 0; k < 4; ++k) {
             tp.e[j][k] = (float)e[j][k];
             tp.o[j][k] = (float)o[j][k];
-            tp.ed[j][k] = (float)((2.0 + 4.0 * k) * o[j][k]);
-            tp.od[j][k] = (float)(k < 3 ? 4.0 * (k + 1) * e[j][k + 1] : 0.0);
         }
     }
     double err = 0.0;
@@ -174,8 +172,8 @@ void antenna_frame(const sim_handle *h, int a, hs::AntArgs &ac) {
     ac.ka = h->kappa / h->ants[a].beta_az;
     ac.ke = h->kappa / h->ants[a].beta_el;
     for (int k = 0; k < 3; ++k) {
-        ac.kaz[k] = (float)(ac.ka * ac.az[k]);
-        ac.kel[k] = (float)(ac.ke * ac.el[k]);
+        ac.kaz[k] = (float)(0.5 * ac.ka * ac.az[k]);
+        ac.kel[k] = (float)(0.5 * ac.ke * ac.el[k]);
         ac.b32[k] = (float)ac.b[k];
     }
     ac.pad = 0.0f;
@@ -789,6 +787,133 @@ int sim_apply_waveform(sim_handle *h, const float *iq_rc, float *iq_raw, long lo
 int sim_apply_waveform_adjoint(sim_handle *h, const float *g_raw, float *g_rc,
                                long long n_lines, void *stream) {
     return waveform_common(h, g_raw, g_rc, n_lines, stream, 1);
+}
+
+}  // extern "C"
+
+namespace {
+
+// One chunk's facet workspace (8 float32 arrays), library-owned.
+struct ChunkWs {
+    float *buf = nullptr;
+    long long cap = 0;
+    ~ChunkWs() {
+        if (buf) (void)hipFree(buf);
+    }
+    hipError_t ensure(long long n) {
+        if (n <= cap) return hipSuccess;
+        if (buf) (void)hipFree(buf);
+        buf = nullptr;
+        cap = 0;
+        hipError_t e = hipMalloc((void **)&buf, sizeof(float) * 8 * (size_t)n);
+        if (e == hipSuccess) cap = n;
+        return e;
+    }
+    sim_facets_out out(long long n) const {
+        sim_facets_out o;
+        o.n = n;
+        float *q[8];
+        for (int k = 0; k < 8; ++k) q[k] = buf + (size_t)k * (size_t)cap;
+        o.x = q[0]; o.y = q[1]; o.z = q[2]; o.vx = q[3]; o.vy = q[4]; o.vz = q[5];
+        o.a_re = q[6]; o.a_im = q[7];
+        return o;
+    }
+};
+
+int check_chunks(const sim_sea *sea, const int *chunks, int n_chunks, long long *max_n) {
+    if (!sea || !chunks || n_chunks < 1) HS_FAIL(SIM_EINVAL, "sea, chunks and n_chunks >= 1 needed");
+    long long m = 0;
+    for (int k = 0; k < n_chunks; ++k) {
+        const int *c = chunks + 4 * k;
+        if (c[0] < 0 || c[1] < 0 || c[2] < 1 || c[3] < 1 || (long long)c[0] + c[2] > sea->nx ||
+            (long long)c[1] + c[3] > sea->ny)
+            HS_FAIL(SIM_EINVAL, "chunk outside the grid or empty");
+        m = std::max(m, (long long)c[2] * c[3]);
+    }
+    *max_n = m;
+    return SIM_OK;
+}
+
+sim_facets as_in(const sim_facets_out &o) {
+    sim_facets f;
+    f.n = o.n;
+    f.x = o.x; f.y = o.y; f.z = o.z; f.vx = o.vx; f.vy = o.vy; f.vz = o.vz;
+    f.a_re = o.a_re; f.a_im = o.a_im;
+    return f;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sim_stream_forward(sim_handle *h, const sim_sea *sea, unsigned long long seed,
+                       const int *chunks, int n_chunks, double block_edge, int p0, int np,
+                       float *iq, int accumulate, void *stream) {
+    if (!h) HS_FAIL(SIM_EINVAL, "handle is NULL");
+    long long max_n = 0;
+    if (int rc = check_chunks(sea, chunks, n_chunks, &max_n)) return rc;
+    if (p0 < 0 || np < 0 || (long long)p0 + np > h->Np) HS_FAIL(SIM_EINVAL, "pulse range");
+    if (!iq) HS_FAIL(SIM_EINVAL, "iq is NULL");
+    if (int rc = ensure_device(h)) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    ChunkWs ws;
+    HS_HIP(ws.ensure(max_n), "stream workspace");
+    if (!accumulate) HS_HIP(hs::launch_fill_zero(iq, 2LL * h->C * np * h->N, s), "zero iq");
+    for (int k = 0; k < n_chunks; ++k) {
+        const int *c = chunks + 4 * k;
+        const long long n = (long long)c[2] * c[3];
+        const sim_facets_out o = ws.out(n);
+        if (int rc = sim_generate_facets(h, sea, seed, c[0], c[1], c[2], c[3], &o, stream)) return rc;
+        sim_plan *P = nullptr;
+        if (int rc = sim_plan_create(h, o.x, o.y, n, block_edge, stream, &P)) return rc;
+        const sim_facets f = as_in(o);
+        int rc = sim_forward(h, P, &f, p0, np, iq, 1, stream);
+        // the plan's buffers are in use by the queued forward
+        hipError_t e = hipStreamSynchronize(s);
+        sim_plan_destroy(P);
+        if (rc) return rc;
+        HS_HIP(e, "stream sync");
+    }
+    return SIM_OK;
+}
+
+int sim_stream_backward(sim_handle *h, const sim_sea *sea, unsigned long long seed,
+                        const int *chunks, int n_chunks, double block_edge, int p0, int np,
+                        const float *g, float *dvx, float *dvy, float *dvz, void *stream) {
+    if (!h) HS_FAIL(SIM_EINVAL, "handle is NULL");
+    long long max_n = 0;
+    if (int rc = check_chunks(sea, chunks, n_chunks, &max_n)) return rc;
+    if (p0 < 0 || np < 0 || (long long)p0 + np > h->Np) HS_FAIL(SIM_EINVAL, "pulse range");
+    if (!g) HS_FAIL(SIM_EINVAL, "g is NULL");
+    if (int rc = ensure_device(h)) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    ChunkWs ws;
+    HS_HIP(ws.ensure(max_n), "stream workspace");
+    long long off = 0;
+    for (int k = 0; k < n_chunks; ++k) {
+        const int *c = chunks + 4 * k;
+        const long long n = (long long)c[2] * c[3];
+        const sim_facets_out o = ws.out(n);
+        if (int rc = sim_generate_facets(h, sea, seed, c[0], c[1], c[2], c[3], &o, stream)) return rc;
+        sim_plan *P = nullptr;
+        if (int rc = sim_plan_create(h, o.x, o.y, n, block_edge, stream, &P)) return rc;
+        const sim_facets f = as_in(o);
+        sim_facet_grads gr;
+        gr.n = n;
+        gr.dz = nullptr;
+        gr.dvx = dvx ? dvx + off : nullptr;
+        gr.dvy = dvy ? dvy + off : nullptr;
+        gr.dvz = dvz ? dvz + off : nullptr;
+        gr.da_re = nullptr;
+        gr.da_im = nullptr;
+        int rc = sim_backward(h, P, &f, p0, np, g, &gr, 0, stream);
+        hipError_t e = hipStreamSynchronize(s);
+        sim_plan_destroy(P);
+        if (rc) return rc;
+        HS_HIP(e, "stream sync");
+        off += n;
+    }
+    return SIM_OK;
 }
 
 }  // extern "C"

@@ -72,6 +72,8 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
 
     float gz_acc = 0.f, gvx = 0.f, gvy = 0.f, gvz = 0.f, gar = 0.f, gai = 0.f;
     float *rf = reinterpret_cast<float *>(refs);
+    TapTop tt;
+    tap_top(A.tp, tt);
 
     for (int c = 0; c < A.C; ++c) {
         const ChanArgs chn = A.ch[c];
@@ -96,13 +98,15 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                 const float ft = ant_grad(ta, dt0, dt1, dt2, (double)r.irt, gft);
                 const float fr = ant_grad(ra, dr0, dr1, dr2, (double)r.irr, gfr);
                 float *o = rf + lane * kNRef;
-                const float gs[3] = {-r.sb * (r.dtx * r.irt + (r.gx - r.dtx) * r.irr),
-                                     -r.sb * (r.dty * r.irt + (r.gy - r.dty) * r.irr),
-                                     -r.sb * (r.dtz * r.irt + (r.gz - r.dtz) * r.irr)};
+                // r.sb carries the mask and 1/(2 pi)^4 (see block_refs): undo for grad T
+                const float sbt = r.sb * kTwoPi4F;
+                const float gs[3] = {-sbt * (r.dtx * r.irt + (r.gx - r.dtx) * r.irr),
+                                     -sbt * (r.dty * r.irt + (r.gy - r.dty) * r.irr),
+                                     -sbt * (r.dtz * r.irt + (r.gz - r.dtz) * r.irr)};
                 const float m = r.mask;
-                o[R_DTGX] = m * (fr * r.sb * gft[0] + ft * r.sb * gfr[0] + ft * fr * gs[0]);
-                o[R_DTGY] = m * (fr * r.sb * gft[1] + ft * r.sb * gfr[1] + ft * fr * gs[1]);
-                o[R_DTGZ] = m * (fr * r.sb * gft[2] + ft * r.sb * gfr[2] + ft * fr * gs[2]);
+                o[R_DTGX] = m * (fr * sbt * gft[0] + ft * sbt * gfr[0] + ft * fr * gs[0]);
+                o[R_DTGY] = m * (fr * sbt * gft[1] + ft * sbt * gfr[1] + ft * fr * gs[1]);
+                o[R_DTGZ] = m * (fr * sbt * gft[2] + ft * sbt * gfr[2] + ft * fr * gs[2]);
                 o[R_T] = (float)P.t;
                 o[R_DTX] = r.dtx; o[R_DTY] = r.dty; o[R_DTZ] = r.dtz;
                 o[R_GX] = r.gx; o[R_GY] = r.gy; o[R_GZ] = r.gz;
@@ -149,8 +153,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                 facet_geo(r, kc, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz, r.graze != 0, A.linv_hi,
                           A.linv_lo, A.fs_cf, g);
                 float tap[8], dtap[8];
-                taps8(A.tp, g.f, tap);
-                dtaps8(A.tp, g.f, dtap);
+                taps_d8(A.tp, tt, g.f, tap, dtap);
                 // g at samples floor(u) - 3 .. floor(u) + 4
                 const int w0 = g.fl + 4;            // window index of the first tap
                 float br = 0.f, bi = 0.f, dr = 0.f, di = 0.f;

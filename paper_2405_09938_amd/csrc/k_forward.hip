@@ -110,6 +110,8 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
     const double rref = P.rref;
     const float tf = (float)P.t;
     float *iq_row = A.iq + 2 * ((size_t)ch * A.np + plc) * (size_t)A.N;
+    TapTop tt;
+    tap_top(A.tp, tt);
 
     for (int b = b0; b < b1; ++b) {
         const BlockRec blk = load_block(blocks + b);
@@ -139,7 +141,7 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
             float wr = g.amp * fmaf(f.ar, g.cs, -(f.ai * g.sn));
             float wi = g.amp * fmaf(f.ar, g.sn, f.ai * g.cs);
             float tap[8];
-            taps8(A.tp, g.f, tap);
+            taps8(A.tp, tt, g.f, tap);
             const float wrl = inw ? wr : 0.0f, wil = inw ? wi : 0.0f;
 #pragma unroll
             for (int k = 0; k < 8; ++k)

@@ -19,6 +19,10 @@
 namespace hs {
 
 constexpr float kPiF = 3.14159265358979323846f;
+constexpr double kTwoPi = 6.283185307179586476925;
+constexpr double kTwoPi4 = kTwoPi * kTwoPi * kTwoPi * kTwoPi;   // (2 pi)^4
+constexpr double kInvTwoPi4 = 1.0 / kTwoPi4;
+constexpr float kTwoPi4F = (float)kTwoPi4;
 
 // sinc(x) = sin(pi x) / (pi x).  The hardware sine takes revolutions, so
 // sin(pi x) = v_sin(x / 2), valid while |x| / 2 <= 256; sim_create keeps
@@ -48,9 +52,10 @@ struct Refs {
     float phib;                     // -frac(R_b f0 / c): phase of the centre (cycles)
     float fb;                       // fractional part of the centre's sample
     int nb;                         // integer part of the centre's sample
-    float gtaz, gtel, graz, grel;   // (kappa/beta) (D . axis) per antenna axis
+    float gtaz, gtel, graz, grel;   // (kappa/beta)/2 (D . axis) per antenna axis
     float irt, irt2, irr, irr2;     // 1/R_b and 1/R_b^2 per leg
-    float sb, sbt, sbr;             // spreading at the centre, and over R per leg
+    float sb, sbt, sbr;             // spreading at the centre (and over R per leg),
+                                    // times the mask, divided by (2 pi)^4
     float mask;                     // 1 if the lane's pulse is live and in front
     float dbt, dbr;                 // D . b per leg (grazing blocks only)
     int graze;                      // block straddles an antenna's back plane
@@ -82,18 +87,15 @@ __device__ __forceinline__ void block_refs(double xb, double yb, const double *p
     const double fl = floor(ub);
     r.fb = (float)(ub - fl);
     r.nb = (int)fl;
-    r.gtaz = (float)(t.ka * (dt0 * t.az[0] + dt1 * t.az[1] + dt2 * t.az[2]));
-    r.gtel = (float)(t.ke * (dt0 * t.el[0] + dt1 * t.el[1] + dt2 * t.el[2]));
-    r.graz = (float)(q.ka * (dr0 * q.az[0] + dr1 * q.az[1] + dr2 * q.az[2]));
-    r.grel = (float)(q.ke * (dr0 * q.el[0] + dr1 * q.el[1] + dr2 * q.el[2]));
+    r.gtaz = (float)(0.5 * t.ka * (dt0 * t.az[0] + dt1 * t.az[1] + dt2 * t.az[2]));
+    r.gtel = (float)(0.5 * t.ke * (dt0 * t.el[0] + dt1 * t.el[1] + dt2 * t.el[2]));
+    r.graz = (float)(0.5 * q.ka * (dr0 * q.az[0] + dr1 * q.az[1] + dr2 * q.az[2]));
+    r.grel = (float)(0.5 * q.ke * (dr0 * q.el[0] + dr1 * q.el[1] + dr2 * q.el[2]));
     r.irt = (float)irt;
     r.irt2 = (float)(irt * irt);
     r.irr = (float)irr;
     r.irr2 = (float)(irr * irr);
     const double sb = rtrr_mid * irt * irr;
-    r.sb = (float)sb;
-    r.sbt = (float)(sb * irt);
-    r.sbr = (float)(sb * irr);
     const double dbt = dt0 * t.b[0] + dt1 * t.b[1] + dt2 * t.b[2];
     const double dbr = dr0 * q.b[0] + dr1 * q.b[1] + dr2 * q.b[2];
     r.dbt = (float)dbt;
@@ -107,6 +109,12 @@ __device__ __forceinline__ void block_refs(double xb, double yb, const double *p
     const bool behind = mt < -margin || mr < -margin;
     r.graze = (live && !front && !behind) ? 1 : 0;
     r.mask = (live && front) ? 1.0f : 0.0f;
+    // the spreading terms carry the mask (grazing lanes are masked per facet)
+    // and the 1/(2 pi)^4 of the merged sinc product
+    const double sm = (r.mask != 0.0f || r.graze) ? kInvTwoPi4 * sb : 0.0;
+    r.sb = (float)sm;
+    r.sbt = (float)(sm * irt);
+    r.sbr = (float)(sm * irr);
 }
 
 // FP32 antenna constants of one channel for the per-facet part.
@@ -159,29 +167,56 @@ __device__ __forceinline__ void facet_geo(const Refs &r, const FacetConsts &cc, 
     const float ph = (r.phib - (hi - rintf(hi))) - lo;
     o.sn = __builtin_amdgcn_sinf(ph);
     o.cs = __builtin_amdgcn_cosf(ph);
-    // antenna field patterns; 1/R per leg to first order in the offset
+    // Antenna field patterns.  With y = kappa u / (2 beta) for each of the four
+    // direction cosines (Tx az, el; Rx az, el), sinc(2y) = v_sin(y) / (2 pi y),
+    // so F_tx F_rx = prod v_sin(y_k) / ((2 pi)^4 prod y_k): one reciprocal for
+    // the four factors, the (2 pi)^4 folded into the spreading terms.  sinc is
+    // even, so |y| is used, floored at 1e-9 (sinc(2e-9) = 1 - 7e-18) to keep the
+    // product normal and never zero.  1/R per leg to first order in the offset.
     const float irtf = fmaf(-at, r.irt2, r.irt);
     const float irrf = fmaf(-ar, r.irr2, r.irr);
-    const float xta = fmaf(ez, cc.kta[2], fmaf(ey, cc.kta[1], fmaf(ex, cc.kta[0], r.gtaz))) * irtf;
-    const float xte = fmaf(ez, cc.kte[2], fmaf(ey, cc.kte[1], fmaf(ex, cc.kte[0], r.gtel))) * irtf;
-    const float xra = fmaf(ez, cc.kra[2], fmaf(ey, cc.kra[1], fmaf(ex, cc.kra[0], r.graz))) * irrf;
-    const float xre = fmaf(ez, cc.kre[2], fmaf(ey, cc.kre[1], fmaf(ex, cc.kre[0], r.grel))) * irrf;
-    const float ft = sinc_f(xta) * sinc_f(xte);
-    const float fr = sinc_f(xra) * sinc_f(xre);
+    const float yta = fmaf(fabsf(fmaf(ez, cc.kta[2], fmaf(ey, cc.kta[1], fmaf(ex, cc.kta[0], r.gtaz)))), irtf, 1e-9f);
+    const float yte = fmaf(fabsf(fmaf(ez, cc.kte[2], fmaf(ey, cc.kte[1], fmaf(ex, cc.kte[0], r.gtel)))), irtf, 1e-9f);
+    const float yra = fmaf(fabsf(fmaf(ez, cc.kra[2], fmaf(ey, cc.kra[1], fmaf(ex, cc.kra[0], r.graz)))), irrf, 1e-9f);
+    const float yre = fmaf(fabsf(fmaf(ez, cc.kre[2], fmaf(ey, cc.kre[1], fmaf(ex, cc.kre[0], r.grel)))), irrf, 1e-9f);
+    const float sp = (__builtin_amdgcn_sinf(yta) * __builtin_amdgcn_sinf(yte)) *
+                     (__builtin_amdgcn_sinf(yra) * __builtin_amdgcn_sinf(yre));
+    const float yp = (yta * yte) * (yra * yre);
     // spreading R_mid^2 / (R_t R_r), first order in the offsets
     const float s = fmaf(-ar, r.sbr, fmaf(-at, r.sbt, r.sb));
-    float m = r.mask;
-    if (graze_any) {
+    float amp = sp * __builtin_amdgcn_rcpf(yp) * s;
+    if (graze_any && r.graze) {
         const float ct = fmaf(ez, cc.bt[2], fmaf(ey, cc.bt[1], fmaf(ex, cc.bt[0], r.dbt)));
         const float cr = fmaf(ez, cc.br[2], fmaf(ey, cc.br[1], fmaf(ex, cc.br[0], r.dbr)));
-        if (r.graze) m = (ct > 0.0f && cr > 0.0f) ? 1.0f : 0.0f;
+        if (!(ct > 0.0f && cr > 0.0f)) amp = 0.0f;
     }
-    o.amp = ft * fr * s * m;
+    o.amp = amp;
     const float uu = fmaf(dR, fs_c, r.fb);
     const float fl = floorf(uu);
     o.f = uu - fl;
     o.fl = (int)fl;
     o.dR = dR;
+}
+
+// Leading tap coefficients held in VGPRs: a VALU instruction reads at most
+// one SGPR, so keeping c[3] in a vector register lets the first Horner step
+// read c[2] from its SGPR without an extra move.
+struct TapTop {
+    float e3[4], o3[4];
+};
+
+__device__ __forceinline__ float to_vgpr(float x) {
+    float r;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+    return r;
+}
+
+__device__ __forceinline__ void tap_top(const TapPoly &tp, TapTop &t) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        t.e3[j] = to_vgpr(tp.e[j][3]);
+        t.o3[j] = to_vgpr(tp.o[j][3]);
+    }
 }
 
 // The 8 taps at samples floor(u) - 3 .. floor(u) + 4 for fractional part f.
@@ -197,16 +232,48 @@ __device__ __forceinline__ void taps8(const TapPoly &tp, float f, float *tap) {
     }
 }
 
-// Derivatives of the 8 taps with respect to u.
-__device__ __forceinline__ void dtaps8(const TapPoly &tp, float f, float *d) {
+__device__ __forceinline__ void taps8(const TapPoly &tp, const TapTop &tt, float f, float *tap) {
     const float sg = fmaf(f, 2.0f, -1.0f);
     const float y = sg * sg;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const float e = poly3(tp.ed[j], y);
-        const float od = sg * poly3(tp.od[j], y);
-        d[4 + j] = e + od;
-        d[3 - j] = od - e;
+        const float e = fmaf(fmaf(fmaf(tt.e3[j], y, tp.e[j][2]), y, tp.e[j][1]), y, tp.e[j][0]);
+        const float od =
+            sg * fmaf(fmaf(fmaf(tt.o3[j], y, tp.o[j][2]), y, tp.o[j][1]), y, tp.o[j][0]);
+        tap[4 + j] = e + od;
+        tap[3 - j] = e - od;
+    }
+}
+
+// The 8 taps and their derivatives with respect to u, from the same
+// coefficients: Horner's rule carries each polynomial and its derivative in y
+// together.  With Q_j = E(y) + s O(y), y = s^2, s = 2f - 1 and du = df:
+//   dQ_j/du      = 2 (O + 2 y O') + s 4 E'
+//   dQ_j(-s)/du  = s 4 E' - 2 (O + 2 y O')
+__device__ __forceinline__ void taps_d8(const TapPoly &tp, const TapTop &tt, float f, float *tap,
+                                        float *d) {
+    const float sg = fmaf(f, 2.0f, -1.0f);
+    const float y = sg * sg;
+    const float y2 = y + y, s4 = 4.0f * sg;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        float e = fmaf(tt.e3[j], y, tp.e[j][2]), de = tt.e3[j];
+        de = fmaf(de, y, e);
+        e = fmaf(e, y, tp.e[j][1]);
+        de = fmaf(de, y, e);
+        e = fmaf(e, y, tp.e[j][0]);
+        float o = fmaf(tt.o3[j], y, tp.o[j][2]), dq = tt.o3[j];
+        dq = fmaf(dq, y, o);
+        o = fmaf(o, y, tp.o[j][1]);
+        dq = fmaf(dq, y, o);
+        o = fmaf(o, y, tp.o[j][0]);
+        const float so = sg * o;
+        tap[4 + j] = e + so;
+        tap[3 - j] = e - so;
+        const float a = 2.0f * fmaf(y2, dq, o);
+        const float b = s4 * de;
+        d[4 + j] = a + b;
+        d[3 - j] = b - a;
     }
 }
 

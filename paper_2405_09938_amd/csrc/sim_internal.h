@@ -38,14 +38,11 @@ struct alignas(16) BlockRec {
 // Interpolator in polynomial form.  With sigma = 2f - 1 (f the fractional
 // sample position) the tap of offset j in {1,2,3,4} is
 //   Q_j(sigma) = E_j(sigma^2) + sigma O_j(sigma^2)  (samples floor(u)+j),
-// its mirror (samples floor(u)+1-j) is Q_j(-sigma), and the derivatives with
-// respect to u are  D_j = Ed_j(sigma^2) + sigma Od_j(sigma^2)  and
-// -(Ed_j - sigma Od_j).  Horner order: c[0] + y (c[1] + y (c[2] + y c[3])).
+// and its mirror (samples floor(u)+1-j) is Q_j(-sigma).
+// Horner order: c[0] + y (c[1] + y (c[2] + y c[3])).
 struct TapPoly {
     float e[4][4];
     float o[4][4];
-    float ed[4][4];
-    float od[4][4];
 };
 
 // Lattice of spatial blocks and patches.
@@ -62,7 +59,7 @@ struct Lattice {
 struct AntArgs {
     double az[3], el[3], b[3];  // frame
     double ka, ke;              // kappa / beta_az, kappa / beta_el
-    float kaz[3], kel[3];       // (kappa/beta) * axis, FP32 for the facet part
+    float kaz[3], kel[3];       // (kappa/beta)/2 * axis, FP32, for the facet part
     float b32[3];               // boresight, FP32
     float pad;
 };

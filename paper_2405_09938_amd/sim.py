@@ -114,13 +114,8 @@ class Simulator:
                                          _stream(), ctypes.byref(p)), "sim_plan_create")
         return Plan(self, p, n)
 
-    def generate(self, sea, seed: int, ix0: int = 0, iy0: int = 0, cnx: Optional[int] = None,
-                 cny: Optional[int] = None) -> Dict[str, torch.Tensor]:
-        """Facets of the grid sub-rectangle [ix0, ix0+cnx) x [iy0, iy0+cny)."""
-        cnx = sea.nx - ix0 if cnx is None else cnx
-        cny = sea.ny - iy0 if cny is None else cny
-        n = cnx * cny
-        out = {k: torch.empty(n, dtype=torch.float32, device=self.device) for k in FACET_KEYS}
+    @staticmethod
+    def _sea_struct(sea):
         s = N.SimSea()
         s.nx, s.ny, s.dx, s.dy = sea.nx, sea.ny, sea.dx, sea.dy
         s.mode, s.sigma_v, s.n_comp = sea.mode, sea.sigma_v, sea.n_comp
@@ -133,11 +128,68 @@ class Simulator:
             dp = ctypes.POINTER(ctypes.c_double)
             s.dirs, s.phases = d.ctypes.data_as(dp), ph.ctypes.data_as(dp)
         s.current[0], s.current[1] = sea.current
+        return s, keep
+
+    def generate(self, sea, seed: int, ix0: int = 0, iy0: int = 0, cnx: Optional[int] = None,
+                 cny: Optional[int] = None) -> Dict[str, torch.Tensor]:
+        """Facets of the grid sub-rectangle [ix0, ix0+cnx) x [iy0, iy0+cny)."""
+        cnx = sea.nx - ix0 if cnx is None else cnx
+        cny = sea.ny - iy0 if cny is None else cny
+        n = cnx * cny
+        out = {k: torch.empty(n, dtype=torch.float32, device=self.device) for k in FACET_KEYS}
+        s, keep = self._sea_struct(sea)
         fo = N.SimFacetsOut(n, *[_fptr(out[k]) for k in FACET_KEYS])
         N.check(self.lib.sim_generate_facets(self.handle, ctypes.byref(s), int(seed), ix0, iy0,
                                              cnx, cny, ctypes.byref(fo), _stream()),
                 "sim_generate_facets")
         del keep
+        return out
+
+    # -- streamed scenes (chunks generated, planned and summed in the library)
+    @staticmethod
+    def _chunk_array(chunks):
+        flat = [int(v) for c in chunks for v in c]
+        return (ctypes.c_int * len(flat))(*flat), len(chunks)
+
+    def stream_forward(self, sea, seed: int, chunks, block_edge: float = 8.0, p0: int = 0,
+                       np_: Optional[int] = None, out: Optional[torch.Tensor] = None,
+                       accumulate: bool = False) -> torch.Tensor:
+        """IQ_rc of the scene made of `chunks` = [(ix0, iy0, cnx, cny), ...]."""
+        np_ = self.n_pulses - p0 if np_ is None else np_
+        shape = (self.n_channels, np_, self.n_samples)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.complex64, device=self.device)
+            accumulate = False
+        elif out.shape != shape or out.dtype != torch.complex64 or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous complex64 tensor of shape {shape}")
+        s, keep = self._sea_struct(sea)
+        ca, nc = self._chunk_array(chunks)
+        N.check(self.lib.sim_stream_forward(self.handle, ctypes.byref(s), int(seed), ca, nc,
+                                            float(block_edge), p0, np_,
+                                            ctypes.c_void_p(out.data_ptr()), int(accumulate),
+                                            _stream()), "sim_stream_forward")
+        return out
+
+    def stream_backward(self, sea, seed: int, chunks, g_rc: torch.Tensor,
+                        block_edge: float = 8.0, p0: int = 0,
+                        np_: Optional[int] = None) -> Dict[str, torch.Tensor]:
+        """dL/dV of every facet of the streamed scene, chunk after chunk."""
+        np_ = self.n_pulses - p0 if np_ is None else np_
+        shape = (self.n_channels, np_, self.n_samples)
+        if g_rc.shape != shape or g_rc.dtype != torch.complex64:
+            raise ValueError(f"g_rc must be complex64 of shape {shape}")
+        g_rc = g_rc.contiguous()
+        n = sum(int(c[2]) * int(c[3]) for c in chunks)
+        out = {k: torch.empty(n, dtype=torch.float32, device=self.device)
+               for k in ("vx", "vy", "vz")}
+        s, keep = self._sea_struct(sea)
+        ca, nc = self._chunk_array(chunks)
+        N.check(self.lib.sim_stream_backward(self.handle, ctypes.byref(s), int(seed), ca, nc,
+                                             float(block_edge), p0, np_,
+                                             ctypes.c_void_p(g_rc.data_ptr()),
+                                             *[ctypes.c_void_p(out[k].data_ptr())
+                                               for k in ("vx", "vy", "vz")], _stream()),
+                "sim_stream_backward")
         return out
 
     # -- the facet sum and its adjoint -----------------------------------------

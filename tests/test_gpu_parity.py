@@ -21,6 +21,10 @@ pytestmark = pytest.mark.gpu
 FKEYS = ("x", "y", "z", "vx", "vy", "vz", "a_re", "a_im")
 IQ_TOL = 1e-4
 GRAD_TOL = 1e-3
+# The FP64-reference / FP32-offset scheme measures ~2e-5 on every case; a
+# tighter guard catches a systematic error (a wrong constant, a dropped
+# second-order term) that would still pass the 1e-4 bar.
+IQ_BUDGET = 5e-5
 
 
 def say(*a):
@@ -85,6 +89,7 @@ def test_cfg1_forward(torch_cuda, hs):
     err = O.rel_l2(got, ref)
     say(f"config 1 IQ rel-L2 {err:.3e} (blocks {plan.n_blocks}, patches {plan.n_patches})")
     assert err < IQ_TOL
+    assert err < IQ_BUDGET, "precision budget of the block-reference scheme exceeded"
 
 
 def test_scattered_multichannel_ragged(torch_cuda, hs):
@@ -98,6 +103,7 @@ def test_scattered_multichannel_ragged(torch_cuda, hs):
     err = O.rel_l2(got, ref)
     say(f"scattered 6-channel rel-L2 {err:.3e}")
     assert err < IQ_TOL
+    assert err < IQ_BUDGET, "precision budget of the block-reference scheme exceeded"
     for c in range(6):
         ec = O.rel_l2(got[c], ref[c])
         assert ec < IQ_TOL, (c, ec)
@@ -209,6 +215,7 @@ def test_generated_scene_end_to_end(torch_cuda, hs):
     e1, e2 = O.rel_l2(rc, ref_rc), O.rel_l2(raw, ref_raw)
     say(f"end-to-end rc rel-L2 {e1:.3e}, raw rel-L2 {e2:.3e}")
     assert e1 < IQ_TOL and e2 < IQ_TOL
+    assert e1 < IQ_BUDGET, "precision budget of the block-reference scheme exceeded"
 
 
 def test_adjoint_vs_oracle(torch_cuda, hs):
