@@ -31,9 +31,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 # Algorithmic VALU lane-slots per contribution of the forward sum at one
-# channel, frozen from the per-contribution operation listing (transcendentals
-# counted at the measured gfx950 half rate, 2 slots each).
-W_ALG_SLOTS = 165.0
+# channel, frozen from the per-contribution operation listing of the
+# reformulated arithmetic (offset expansion of the range, one reciprocal for
+# the four pattern factors, even/odd tap polynomials): 116 VALU operations and
+# 7 transcendentals, each transcendental one issue slot as measured on gfx950
+# in this instruction mix.  Loop control, window tests and LDS addressing are
+# overhead, not counted.
+W_ALG_SLOTS = 123.0
 PEAK_SLOTS = 256 * 64 * 2.4e9          # lane-slots per second
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_forward_cfg2_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2405_09938_amd", "csrc", f)
@@ -84,9 +88,6 @@ def main():
     import workloads as W
 
     wl = W.workload(args.workload)
-    if wl.chunks:
-        print("bench.py times single-launch workloads; use workload 1-4", file=sys.stderr)
-        sys.exit(2)
     geom, sea = wl.geometry, wl.sea
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
@@ -97,14 +98,23 @@ def main():
     stream = torch.cuda.current_stream()
 
     fwd_ev = []
+    streamed = bool(wl.chunks)
 
     def fwd_step(record=False):
-        f = sim.generate(sea, wl.seed)
-        plan = sim.plan(f["x"], f["y"], wl.block_edge)
         if record:
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-        rc = sim.forward(plan, f)
+        if streamed:
+            # chunks generated, planned and summed inside the library
+            if record:
+                e0.record(stream)
+            rc = sim.stream_forward(sea, wl.seed, wl.chunks, wl.block_edge)
+            f = plan = None
+        else:
+            f = sim.generate(sea, wl.seed)
+            plan = sim.plan(f["x"], f["y"], wl.block_edge)
+            if record:
+                e0.record(stream)
+            rc = sim.forward(plan, f)
         if record:
             e1.record(stream)
             fwd_ev.append((e0, e1))
@@ -116,42 +126,56 @@ def main():
         fwd_step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
         f, plan, out = fwd_step(record=True)
+        if streamed:
+            torch.cuda.synchronize()
+            print(f"  forward step {i} done", flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     step_s = (t1 - t0) / args.steps
     value = contrib / step_s / 1e9
     kern_ms = sum(a.elapsed_time(b) for a, b in fwd_ev) / len(fwd_ev)
-    print(f"forward step {step_s * 1e3:.3f} ms, {value:.2f} G/s; fused forward kernel "
+    print(f"forward step {step_s * 1e3:.3f} ms, {value:.2f} G/s; forward sum "
           f"{kern_ms:.3f} ms avg", flush=True)
     gpu_iq = out
 
     fwd_adj = None
     if not args.no_adjoint:
-        # target: same scene, velocities perturbed by a 0.1 m/s current
-        psi = W.sea_draws(wl.seed)["perturb_heading"]
-        with torch.no_grad():
-            ft = dict(f)
-            ft["vx"] = f["vx"] + 0.1 * math.cos(psi)
-            ft["vy"] = f["vy"] + 0.1 * math.sin(psi)
-            tgt = sim.forward(plan, ft)
-            if chirp:
-                tgt = sim.apply_waveform(tgt, out=tgt)
+        if streamed:
+            # loss 1/2 ||raw||^2: g = raw (the adjoint's cost does not depend
+            # on g); adjoint w.r.t. the facet velocities, chunk by chunk
+            def fa_step():
+                _, _, o = fwd_step()
+                g = sim.apply_waveform(o, adjoint=True) if chirp else o
+                return sim.stream_backward(sea, wl.seed, wl.chunks, g, wl.block_edge)
+        else:
+            # target: same scene, velocities perturbed by a 0.1 m/s current
+            psi = W.sea_draws(wl.seed)["perturb_heading"]
+            with torch.no_grad():
+                ft = dict(f)
+                ft["vx"] = f["vx"] + 0.1 * math.cos(psi)
+                ft["vy"] = f["vy"] + 0.1 * math.sin(psi)
+                tgt = sim.forward(plan, ft)
+                if chirp:
+                    tgt = sim.apply_waveform(tgt, out=tgt)
 
-        def fa_step():
-            f2, plan2, o = fwd_step()
-            g = 2.0 * (o - tgt)
-            if chirp:
-                g = sim.apply_waveform(g, out=g, adjoint=True)
-            return sim.backward(plan2, f2, g)
+            def fa_step():
+                f2, plan2, o = fwd_step()
+                g = 2.0 * (o - tgt)
+                if chirp:
+                    g = sim.apply_waveform(g, out=g, adjoint=True)
+                return sim.backward(plan2, f2, g)
 
-        for _ in range(max(1, args.warmup)):
+        for _ in range(args.warmup):
             fa_step()
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        for _ in range(args.steps):
+        for i in range(args.steps):
             fa_step()
+            if streamed:
+                torch.cuda.synchronize()
+                print(f"  forward+adjoint step {i} done", flush=True)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         fa_s = (t3 - t2) / args.steps
@@ -163,15 +187,21 @@ def main():
     achieved = W_ALG_SLOTS * contrib / (kern_ms * 1e-3) / 1e12
     peak = PEAK_SLOTS / 1e12
     traffic = None
+    valu = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
         if tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == wl.name:
             traffic = tr.get("bytes_per_launch")
+            valu = tr.get("valu_insts_per_launch")
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
                 "unit": "Tslot/s", "frac": round(achieved / peak, 4), "traffic": traffic,
                 "kernel": "k_forward", "w_alg_slots_per_contribution": W_ALG_SLOTS,
                 "contributions_per_launch": contrib, "avg_launch_ms": round(kern_ms, 4)}
+    if valu:
+        # issued wave64 VALU instructions (rocprof SQ_INSTS_VALU of the same
+        # kernel source) against one per CU per cycle at 2.4 GHz
+        roofline["valu_issue_frac"] = round(valu / (256 * 2.4e9 * kern_ms * 1e-3), 4)
 
     cpu = None
     rel = None
@@ -180,7 +210,15 @@ def main():
         # bounded sample: the oracle's own scene (same seed and sea draws),
         # all facets, pulses taken from the middle of the dwell until the
         # time budget is spent
-        fo = O.as_float32(O.generate_facets(sea, wl.seed))
+        if streamed:
+            # the sample is the scene's first chunk; for the comparison the GPU
+            # recomputes that chunk's lines over the same pulses
+            sub = wl.chunks[0]
+            fo = O.as_float32(O.generate_facets(sea, wl.seed, *sub))
+            n_fac = sub[2] * sub[3]
+        else:
+            fo = O.as_float32(O.generate_facets(sea, wl.seed))
+            n_fac = wl.n_facets
         fo = {k: v.astype(np.float64) for k, v in fo.items()}
         p_mid = geom.n_pulses // 2
         chunk = 4
@@ -195,11 +233,16 @@ def main():
             t_cpu += time.perf_counter() - ta
             rows.append((p0, line))
             done += chunk
-        n_contrib = wl.n_facets * done * geom.n_channels
+        n_contrib = n_fac * done * geom.n_channels
         cpu = {"value": n_contrib / t_cpu / 1e9, "unit": "G contributions/s",
                "cores": O.num_threads(), "kind": "oracle",
-               "sample": f"{wl.n_facets} facets x {done} pulses (from pulse {p_mid}) x "
+               "sample": f"{n_fac} facets x {done} pulses (from pulse {p_mid}) x "
                          f"{geom.n_channels} ch, FP64 direct sum + FFT waveform, {t_cpu:.1f} s"}
+        if streamed:
+            gpu_iq = sim.stream_forward(sea, wl.seed, [wl.chunks[0]], wl.block_edge, p_mid, done)
+            if chirp:
+                gpu_iq = sim.apply_waveform(gpu_iq, out=gpu_iq)
+            rows = [(p0 - p_mid, line) for p0, line in rows]
         got = gpu_iq.cpu().numpy()
         num = den = 0.0
         for p0, line in rows:
@@ -222,10 +265,11 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic (on-device Philox facets, 64-component linear wave sea)",
+        "data": ("synthetic (on-device Philox facets, 64-component linear wave sea)"
+                 if sea.mode == 1 else "synthetic (on-device Philox facets, flat sea)"),
         "config": {"workload": wl.name, "facets": wl.n_facets, "pulses": geom.n_pulses,
                    "samples": geom.n_samples, "channels": geom.n_channels, "chirp": chirp,
-                   "block_edge_m": wl.block_edge},
+                   "block_edge_m": wl.block_edge, "chunks": len(wl.chunks) or 1},
         "fwd_adj": fwd_adj,
         "rel_l2_vs_fp64": rel,
         "roofline": roofline,

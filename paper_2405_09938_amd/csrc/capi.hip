@@ -11,6 +11,15 @@
 
 #include "sim_internal.h"
 
+// Forward-kernel tuning: smallest LDS range window (samples) and the target
+// number of lattice cells per patch.
+#ifndef HEEPS_WIN_MIN
+#define HEEPS_WIN_MIN 24
+#endif
+#ifndef HEEPS_PATCH_CELLS
+#define HEEPS_PATCH_CELLS 24.0
+#endif
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -503,11 +512,17 @@ int sim_plan_create(sim_handle *h, const float *x, const float *y, long long n,
     const double tmax = 0.5 * (double)(h->Np - 1) / h->prf;
     // halo: facet heights up to 4 m and drift at up to 2.5 m/s over the dwell
     const int halo = (int)std::ceil((4.0 * gzm + 2.5 * tmax * gnm) * bins_per_m) + 1;
-    // window of the forward kernel: 32 samples unless heights and drift need more
-    const int win = (2 * halo + 19 <= 32) ? 32 : (2 * halo + 19 <= 48 ? 48 : 64);
+    // window of the forward kernel: the smallest instantiated width that
+    // leaves room for a patch span after the halo and the taps
+    int win = 64;
+    for (int w : {HEEPS_WIN_MIN, 24, 32, 48, 64})
+        if (w >= HEEPS_WIN_MIN && 2 * halo + 13 <= w) {
+            win = w;
+            break;
+        }
     const double budget = std::max(2.0, (double)(win - 2 * halo - 11));
     const double gxb = gxm * bins_per_m * block_edge, gyb = gym * bins_per_m * block_edge;
-    const double target = 128.0;   // cells per patch
+    const double target = HEEPS_PATCH_CELLS;   // cells per patch
     double px = std::sqrt(target * gyb / gxb), py = target / px;
     px = std::max(1.0, std::min(px, 4096.0));
     py = std::max(1.0, std::min(py, 4096.0));
@@ -679,9 +694,9 @@ int sim_forward(sim_handle *h, sim_plan *P, const sim_facets *f, int p0, int np,
     if (P->h != h) HS_FAIL(SIM_EINVAL, "plan belongs to another handle");
     if (int rc = facets_ok(f, P->n)) return rc;
     if (p0 < 0 || np < 0 || (long long)p0 + np > h->Np) HS_FAIL(SIM_EINVAL, "pulse range");
+    if (np == 0) return SIM_OK;   // nothing to write (an empty IQ may have a NULL pointer)
     if (!iq) HS_FAIL(SIM_EINVAL, "iq is NULL");
     if (int rc = ensure_device(h)) return rc;
-    if (np == 0) return SIM_OK;
     hipStream_t s = (hipStream_t)stream;
     HS_HIP(hs::launch_gather(*f, P->perm, P->blocks, P->n_blocks, P->sorted, s), "gather");
     if (!accumulate)
@@ -718,7 +733,8 @@ int sim_backward(sim_handle *h, sim_plan *P, const sim_facets *f, int p0, int np
     if (P->h != h) HS_FAIL(SIM_EINVAL, "plan belongs to another handle");
     if (int rc = facets_ok(f, P->n)) return rc;
     if (p0 < 0 || np < 0 || (long long)p0 + np > h->Np) HS_FAIL(SIM_EINVAL, "pulse range");
-    if (!g || !gr) HS_FAIL(SIM_EINVAL, "g or grads is NULL");
+    if (!gr) HS_FAIL(SIM_EINVAL, "grads is NULL");
+    if (!g && np > 0) HS_FAIL(SIM_EINVAL, "g is NULL");
     if (gr->n != P->n) HS_FAIL(SIM_EINVAL, "grads->n differs from the plan's facet count");
     if (int rc = ensure_device(h)) return rc;
     hipStream_t s = (hipStream_t)stream;

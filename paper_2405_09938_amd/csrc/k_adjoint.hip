@@ -8,9 +8,11 @@
 //   dL/dX = Re(B a E) grad T + [Im(B a E) T K0 + Re(B_u a T E) fs/c] grad R,
 // with K0 = 2 pi f0 / c and grad R = d_tx + d_rx (unit vectors antenna ->
 // facet).  dL/dz = sum_p (dL/dX)_z and dL/dV = sum_p t_p dL/dX (X = X0 + V t_p).
-// grad T and grad R are taken at the block centre (their change across a
-// block is below 1e-5 relative); everything else is the facet's own value,
-// recomputed exactly as in the forward kernel.
+// grad R is the facet's own to first order in its offset e from the block
+// centre (d_leg + (e - (e.d_leg) d_leg) / R_leg per leg, which matters at
+// airborne ranges where e/R reaches 1e-4); grad T, whose share of dL/dX is
+// ~1e-4 at 15 km and ~1e-6 at 850 km, is taken at the block centre;
+// everything else is recomputed exactly as in the forward kernel.
 //
 // Work decomposition: one wave per spatial block, lane = facet (<= 64 per
 // block).  The wave loops over channels and over stages of 32 pulses; per
@@ -103,7 +105,8 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                 const float gs[3] = {-sbt * (r.dtx * r.irt + (r.gx - r.dtx) * r.irr),
                                      -sbt * (r.dty * r.irt + (r.gy - r.dty) * r.irr),
                                      -sbt * (r.dtz * r.irt + (r.gz - r.dtz) * r.irr)};
-                const float m = r.mask;
+                // grazing blocks keep grad T; each facet's own flag applies below
+                const float m = (r.mask != 0.0f || r.graze) ? 1.0f : 0.0f;
                 o[R_DTGX] = m * (fr * sbt * gft[0] + ft * sbt * gfr[0] + ft * fr * gs[0]);
                 o[R_DTGY] = m * (fr * sbt * gft[1] + ft * sbt * gfr[1] + ft * fr * gs[1]);
                 o[R_DTGZ] = m * (fr * sbt * gft[2] + ft * sbt * gfr[2] + ft * fr * gs[2]);
@@ -193,9 +196,17 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                 // Re(B_u a E) T
                 const float bu = fmaf(dr, aer, -(di * aei)) * T;
                 const float cR = fmaf(pi * T, A.k0, bu * A.fs_cf);
-                const float gxv = fmaf(pr, o[R_DTGX], cR * r.gx);
-                const float gyv = fmaf(pr, o[R_DTGY], cR * r.gy);
-                const float gzv = fmaf(pr, o[R_DTGZ], cR * r.gz);
+                // grad R = g (1 - c2) + e (1/R_t + 1/R_r) - d_t (c1 - c2),
+                // c1 = (e.d_t)/R_t, c2 = (e.d_r)/R_r, d_r = g - d_t
+                const float c1 = g.at * r.irt, c2 = g.ar * r.irr;
+                const float s1 = r.irt + r.irr, u1 = 1.0f - c2, w1 = c1 - c2;
+                const float grx = fmaf(g.ex, s1, fmaf(r.gx, u1, -(r.dtx * w1)));
+                const float gry = fmaf(g.ey, s1, fmaf(r.gy, u1, -(r.dty * w1)));
+                const float grz = fmaf(g.ez, s1, fmaf(r.gz, u1, -(r.dtz * w1)));
+                const float pm = pr * g.mf;
+                const float gxv = fmaf(pm, o[R_DTGX], cR * grx);
+                const float gyv = fmaf(pm, o[R_DTGY], cR * gry);
+                const float gzv = fmaf(pm, o[R_DTGZ], cR * grz);
                 gz_acc += gzv;
                 gvx = fmaf(tf, gxv, gvx);
                 gvy = fmaf(tf, gyv, gvy);

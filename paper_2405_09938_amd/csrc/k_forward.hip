@@ -138,15 +138,18 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
             float2 old[8];
 #pragma unroll
             for (int k = 0; k < 8; ++k) old[k] = p[k];
-            float wr = g.amp * fmaf(f.ar, g.cs, -(f.ai * g.sn));
-            float wi = g.amp * fmaf(f.ar, g.sn, f.ai * g.cs);
+            // a lane outside the window adds zero to its row (and goes below)
+            const float al = inw ? g.amp : 0.0f;
+            const float wrl = al * fmaf(f.ar, g.cs, -(f.ai * g.sn));
+            const float wil = al * fmaf(f.ar, g.sn, f.ai * g.cs);
             float tap[8];
             taps8(A.tp, tt, g.f, tap);
-            const float wrl = inw ? wr : 0.0f, wil = inw ? wi : 0.0f;
 #pragma unroll
             for (int k = 0; k < 8; ++k)
                 p[k] = make_float2(fmaf(wrl, tap[k], old[k].x), fmaf(wil, tap[k], old[k].y));
             if (!inw && live) {
+                const float wr = g.amp * fmaf(f.ar, g.cs, -(f.ai * g.sn));
+                const float wi = g.amp * fmaf(f.ar, g.sn, f.ai * g.cs);
                 // outside the window: straight to the line, taps inside [0, N)
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
@@ -180,6 +183,7 @@ hipError_t launch_forward(const FwdArgs &a, int C, int win, hipStream_t s) {
     if (a.n_patches == 0 || a.np == 0) return hipSuccess;
     dim3 grid((unsigned)a.n_patches, (unsigned)((a.np + 63) / 64), (unsigned)C);
     switch (win) {
+        case 24: hipLaunchKernelGGL(k_forward<24>, grid, dim3(64), 0, s, a); break;
         case 32: hipLaunchKernelGGL(k_forward<32>, grid, dim3(64), 0, s, a); break;
         case 48: hipLaunchKernelGGL(k_forward<48>, grid, dim3(64), 0, s, a); break;
         case 64: hipLaunchKernelGGL(k_forward<64>, grid, dim3(64), 0, s, a); break;

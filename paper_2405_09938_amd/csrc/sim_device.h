@@ -138,6 +138,9 @@ __device__ __forceinline__ void facet_consts(const AntArgs &t, const AntArgs &q,
 
 // Per-facet geometry of one (facet, pulse) pair.
 struct Geo {
+    float mf;            // 1, or 0 for a facet behind an antenna in a straddling block
+    float ex, ey, ez;    // offset from the block centre at the pulse time
+    float at, ar;        // its projections on the Tx and Rx unit vectors
     float dR;        // bistatic range minus the block centre's
     float sn, cs;    // sin, cos of the carrier phase (2 pi cycles)
     float amp;       // F_tx F_rx S (times the mask)
@@ -164,7 +167,7 @@ __device__ __forceinline__ void facet_geo(const Refs &r, const FacetConsts &cc, 
     const float hi = dR * linv_hi;
     float lo = fmaf(dR, linv_hi, -hi);
     lo = fmaf(dR, linv_lo, lo);
-    const float ph = (r.phib - (hi - rintf(hi))) - lo;
+    const float ph = (r.phib - __builtin_amdgcn_fractf(hi)) - lo;
     o.sn = __builtin_amdgcn_sinf(ph);
     o.cs = __builtin_amdgcn_cosf(ph);
     // Antenna field patterns.  With y = kappa u / (2 beta) for each of the four
@@ -185,17 +188,27 @@ __device__ __forceinline__ void facet_geo(const Refs &r, const FacetConsts &cc, 
     // spreading R_mid^2 / (R_t R_r), first order in the offsets
     const float s = fmaf(-ar, r.sbr, fmaf(-at, r.sbt, r.sb));
     float amp = sp * __builtin_amdgcn_rcpf(yp) * s;
+    o.mf = 1.0f;
     if (graze_any && r.graze) {
         const float ct = fmaf(ez, cc.bt[2], fmaf(ey, cc.bt[1], fmaf(ex, cc.bt[0], r.dbt)));
         const float cr = fmaf(ez, cc.br[2], fmaf(ey, cc.br[1], fmaf(ex, cc.br[0], r.dbr)));
-        if (!(ct > 0.0f && cr > 0.0f)) amp = 0.0f;
+        if (!(ct > 0.0f && cr > 0.0f)) {
+            amp = 0.0f;
+            o.mf = 0.0f;
+        }
     }
     o.amp = amp;
     const float uu = fmaf(dR, fs_c, r.fb);
-    const float fl = floorf(uu);
-    o.f = uu - fl;
-    o.fl = (int)fl;
+    o.f = __builtin_amdgcn_fractf(uu);
+    int fl;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(fl) : "v"(uu));   // floor and convert
+    o.fl = fl;
     o.dR = dR;
+    o.ex = ex;
+    o.ey = ey;
+    o.ez = ez;
+    o.at = at;
+    o.ar = ar;
 }
 
 // Leading tap coefficients held in VGPRs: a VALU instruction reads at most

@@ -130,3 +130,31 @@ def test_waveform_sizes_for_workloads(native):
         L.sim_waveform_info(h, ctypes.byref(Lc), ctypes.byref(M))
         assert (Lc.value, M.value) == (Lexp, Mexp)
         L.sim_destroy(h)
+
+
+def test_stream_entry_points_validate(native):
+    """Chunks outside the grid or empty, a NULL sea and a bad pulse range are
+    refused before any device work."""
+    L = native.load()
+    g = W.harmony_geometry(8, 64)
+    cfg, keep = _config(native, g)
+    h = ctypes.c_void_p()
+    assert L.sim_create(ctypes.byref(cfg), ctypes.byref(h)) == native.SIM_OK
+    try:
+        sea = native.SimSea()
+        sea.nx, sea.ny, sea.dx, sea.dy, sea.mode = 100, 50, 1.0, 1.0, 0
+        bad = [(90, 0, 20, 10), (0, 0, 0, 10), (-1, 0, 5, 5), (0, 45, 10, 10)]
+        for c in bad:
+            arr = (ctypes.c_int * 4)(*c)
+            rc = L.sim_stream_forward(h, ctypes.byref(sea), 1, arr, 1, 8.0, 0, 8,
+                                      ctypes.c_void_p(16), 0, None)
+            assert rc == native.SIM_EINVAL, c
+        ok = (ctypes.c_int * 4)(0, 0, 10, 10)
+        assert L.sim_stream_forward(h, None, 1, ok, 1, 8.0, 0, 8, ctypes.c_void_p(16), 0,
+                                    None) == native.SIM_EINVAL
+        assert L.sim_stream_forward(h, ctypes.byref(sea), 1, ok, 1, 8.0, 4, 8,
+                                    ctypes.c_void_p(16), 0, None) == native.SIM_EINVAL
+        assert L.sim_stream_backward(h, ctypes.byref(sea), 1, ok, 0, 8.0, 0, 8, None, None,
+                                     None, None, None) == native.SIM_EINVAL
+    finally:
+        L.sim_destroy(h)
