@@ -36,7 +36,7 @@ constexpr int kNRef = 32;    // floats per staged pulse record
 enum {
     R_T = 0, R_DTX, R_DTY, R_DTZ, R_GX, R_GY, R_GZ, R_I2RT, R_I2RR, R_PHIB, R_FB, R_NB,
     R_GTAZ, R_GTEL, R_GRAZ, R_GREL, R_IRT, R_IRT2, R_IRR, R_IRR2, R_SB, R_SBT, R_SBR, R_MASK,
-    R_DTGX, R_DTGY, R_DTGZ, R_DBT, R_DBR, R_GRAZE
+    R_DTGX, R_DTGY, R_DTGZ, R_DBT, R_DBR, R_GRAZE, R_I2S
 };
 
 // Gradient of one antenna's field pattern at the block centre (FP32 from the
@@ -113,7 +113,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                 o[R_T] = (float)P.t;
                 o[R_DTX] = r.dtx; o[R_DTY] = r.dty; o[R_DTZ] = r.dtz;
                 o[R_GX] = r.gx; o[R_GY] = r.gy; o[R_GZ] = r.gz;
-                o[R_I2RT] = r.i2rt; o[R_I2RR] = r.i2rr;
+                o[R_I2RT] = r.i2rt; o[R_I2RR] = r.i2rr; o[R_I2S] = r.i2s;
                 o[R_PHIB] = r.phib; o[R_FB] = r.fb;
                 o[R_NB] = __int_as_float(r.nb);
                 o[R_GTAZ] = r.gtaz; o[R_GTEL] = r.gtel; o[R_GRAZ] = r.graz; o[R_GREL] = r.grel;
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                 Refs r;
                 r.dtx = o[R_DTX]; r.dty = o[R_DTY]; r.dtz = o[R_DTZ];
                 r.gx = o[R_GX]; r.gy = o[R_GY]; r.gz = o[R_GZ];
-                r.i2rt = o[R_I2RT]; r.i2rr = o[R_I2RR];
+                r.i2rt = o[R_I2RT]; r.i2rr = o[R_I2RR]; r.i2s = o[R_I2S];
                 r.phib = o[R_PHIB]; r.fb = o[R_FB]; r.nb = __float_as_int(o[R_NB]);
                 r.gtaz = o[R_GTAZ]; r.gtel = o[R_GTEL]; r.graz = o[R_GRAZ]; r.grel = o[R_GREL];
                 r.irt = o[R_IRT]; r.irt2 = o[R_IRT2]; r.irr = o[R_IRR]; r.irr2 = o[R_IRR2];

@@ -119,7 +119,9 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
         block_refs((double)blk.xb, (double)blk.yb, ptx, prx, rref, ta, ra, chn.rtrr_mid, A.f0_c,
                    A.fs_c, A.n_ref, live, r);
         const bool graze_any = __any(r.graze);
-        const int nb0 = r.nb - lo - 3;
+        // the window offset of the first tap rides in the sample fraction, so
+        // the floor of the sample position is the window index directly
+        r.fb += (float)(r.nb - lo - 3);
         const int j1 = blk.start + blk.count;
         // the sorted facet array carries one padding record, so the look-ahead
         // load of the next facet is always in bounds
@@ -132,7 +134,7 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
                       A.linv_lo, A.fs_cf, g);
             // Each lane owns its pulse row, so the deposit is a plain
             // read-modify-write of 8 consecutive complex samples.
-            const int n0 = nb0 + g.fl;            // window index of the first tap
+            const int n0 = g.fl;                  // window index of the first tap
             const bool inw = (unsigned)n0 <= (unsigned)(WIN - 8);
             float2 *p = row + (inw ? n0 : 0);
             float2 old[8];

@@ -49,6 +49,7 @@ struct Refs {
     float dtx, dty, dtz;            // unit vector Tx -> block centre
     float gx, gy, gz;               // gradient of the bistatic range at the centre
     float i2rt, i2rr;               // 1 / (2 R_b) per leg
+    float i2s;                      // i2rt + i2rr
     float phib;                     // -frac(R_b f0 / c): phase of the centre (cycles)
     float fb;                       // fractional part of the centre's sample
     int nb;                         // integer part of the centre's sample
@@ -80,6 +81,7 @@ __device__ __forceinline__ void block_refs(double xb, double yb, const double *p
     r.gz = (float)(ut2 + ur2);
     r.i2rt = (float)(0.5 * irt);
     r.i2rr = (float)(0.5 * irr);
+    r.i2s = (float)(0.5 * (irt + irr));
     const double rb = rt + rr;
     const double cyc = rb * f0_c;
     r.phib = (float)(rint(cyc) - cyc);
@@ -159,9 +161,11 @@ __device__ __forceinline__ void facet_geo(const Refs &r, const FacetConsts &cc, 
     const float L = fmaf(ez, r.gz, fmaf(ey, r.gy, ex * r.gx));
     const float at = fmaf(ez, r.dtz, fmaf(ey, r.dty, ex * r.dtx));
     const float ar = L - at;
-    const float qt = fmaf(-at, at, ee) * r.i2rt;
-    const float qr = fmaf(-ar, ar, ee) * r.i2rr;
-    const float dR = L + (qt + qr);
+    // second-order terms (|e|^2 - at^2) / (2 R_t) + (|e|^2 - ar^2) / (2 R_r),
+    // summed before they meet L
+    const float s1 = at * r.i2rt, s2 = ar * r.i2rr;
+    const float h2 = fmaf(at, s1, ar * s2);
+    const float dR = L + fmaf(ee, r.i2s, -h2);
     // phase (cycles) = phib - dR f0/c, product split so the integer part of
     // the cycle count is removed exactly
     const float hi = dR * linv_hi;
