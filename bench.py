@@ -11,10 +11,12 @@ with every input generated in HBM inside the step.  A second timed loop of K
 forward+adjoint steps (loss ||raw - T||^2 against a target from a perturbed
 current, chirp adjoint, adjoint sum) gives `fwd_adj`.
 
-`roofline` reports the fused forward kernel against the VALU issue rate:
-achieved = W_alg lane-slots per contribution x contributions per launch /
-average launch time (HIP events on the launch stream), peak = 256 CUs x 64
-lanes x 2.4 GHz.  `cpu_baseline` times the FP64 oracle on a bounded pulse
+`roofline` reports the fused forward kernel against the FP32 vector ALU:
+achieved = W_alg slots per contribution x contributions per launch / average
+launch time (HIP events on the launch stream), where a slot is one FP32
+lane-operation of the full-rate FMA pipe and a transcendental costs four;
+peak = 256 CUs x 128 lanes x 2.4 GHz (the 157.3 TFLOP/s FP32 figure counted
+in FMAs).  `cpu_baseline` times the FP64 oracle on a bounded pulse
 subset of the same scene on the host's cores, and `rel_l2_vs_fp64` compares
 those oracle lines with the GPU's.
 """
@@ -30,15 +32,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Algorithmic VALU lane-slots per contribution of the forward sum at one
-# channel, frozen from the per-contribution operation listing of the
-# reformulated arithmetic (offset expansion of the range, one reciprocal for
-# the four pattern factors, even/odd tap polynomials): 116 VALU operations and
-# 7 transcendentals, each transcendental one issue slot as measured on gfx950
-# in this instruction mix.  Loop control, window tests and LDS addressing are
-# overhead, not counted.
-W_ALG_SLOTS = 123.0
-PEAK_SLOTS = 256 * 64 * 2.4e9          # lane-slots per second
+# Algorithmic ALU slots per contribution of the forward sum at one channel,
+# frozen from the per-contribution operation listing of the reformulated
+# arithmetic (offset expansion of the range, one reciprocal for the four
+# pattern factors, even/odd tap polynomials): 116 FP32 operations at one slot
+# and 7 transcendentals (sin, cos, rcp), which gfx950 issues at a quarter of
+# the FP32 FMA rate, at four slots each.  Loop control, window tests and LDS
+# addressing are overhead, not counted.
+W_ALG_SLOTS = 116.0 + 7 * 4.0
+PEAK_SLOTS = 256 * 128 * 2.4e9         # FP32 lane-operations per second (157.3 TFLOP/s / 2)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_forward_cfg2_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2405_09938_amd", "csrc", f)
                   for f in ("k_forward.hip", "sim_device.h")]
@@ -200,8 +202,9 @@ def main():
                 "contributions_per_launch": contrib, "avg_launch_ms": round(kern_ms, 4)}
     if valu:
         # issued wave64 VALU instructions (rocprof SQ_INSTS_VALU of the same
-        # kernel source) against one per CU per cycle at 2.4 GHz
-        roofline["valu_issue_frac"] = round(valu / (256 * 2.4e9 * kern_ms * 1e-3), 4)
+        # kernel source) against the FP32 issue peak of two per CU per cycle
+        # at 2.4 GHz
+        roofline["valu_issue_frac"] = round(valu / (256 * 2 * 2.4e9 * kern_ms * 1e-3), 4)
 
     cpu = None
     rel = None

@@ -8,11 +8,14 @@
 // Work decomposition (one workgroup = one wave):
 //   blockIdx.x = patch of spatial blocks, blockIdx.y = group of 64 pulses,
 //   blockIdx.z = channel.  Lane = pulse: every lane handles the same facet
-//   (its 32-byte record arrives through one scalar load) and deposits into
-//   its own pulse row of an LDS range window.  Since no other lane or wave
-//   touches that row, the deposit is a plain read-modify-write (8 x 64-bit
+//   (its 32-byte record arrives by two uniform buffer loads) and deposits into
+//   its own pulse column of an LDS range window.  Since no other lane or wave
+//   touches that column, the deposit is a plain read-modify-write (8 x 64-bit
 //   reads issued as soon as the sample index is known, 16 FMAs, 8 x 64-bit
-//   writes) instead of LDS atomics.  At the end the window is flushed to the
+//   writes) instead of LDS atomics, which serialise per lane on gfx950.  The
+//   window is stored sample-major ([sample][lane]), so the 64 lanes of one
+//   access always fall on distinct bank pairs whatever their sample indices:
+//   a lane-major layout conflicts as soon as the lanes' sample indices differ.  At the end the window is flushed to the
 //   IQ lines with global float atomics, since neighbouring patches overlap in
 //   range.  A contribution whose taps leave the window (only for geometries
 //   the patch sizing did not foresee) goes straight to global memory.
@@ -36,28 +39,44 @@ __device__ __forceinline__ BlockRec load_block(cptr<BlockRec> p) {
     return r;
 }
 
-__device__ __forceinline__ FacetRec load_facet(cptr<FacetRec> p) {
-    FacetRec r;
-    r.dx = p->dx;
-    r.dy = p->dy;
-    r.z = p->z;
-    r.vx = p->vx;
-    r.vy = p->vy;
-    r.vz = p->vz;
-    r.ar = p->ar;
-    r.ai = p->ai;
-    return r;
+// Facet records are read with vector-memory buffer loads at a uniform
+// offset: every lane receives the same 32 bytes in VGPRs.  Scalar loads
+// would share the lgkm counter with the LDS deposit, so each wait for the
+// deposit's reads would also wait for the next record's scalar-cache miss;
+// buffer loads are counted by vmcnt instead.  The resource covers one
+// block's records (plus the padding record after the last block), and a
+// load past its end returns zeros.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t facet_rsrc(const FacetRec *base, int count) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, 0, (count + 1) * (int)sizeof(FacetRec),
+                                             0x00020000);
+}
+
+struct FacetV {
+    float dx, dy, z, vx, vy, vz, ar, ai;
+};
+
+__device__ __forceinline__ FacetV load_facet(__amdgpu_buffer_rsrc_t rs, int j) {
+    const auto a = __builtin_amdgcn_raw_buffer_load_b128(rs, 0, j * (int)sizeof(FacetRec), 0);
+    const auto b = __builtin_amdgcn_raw_buffer_load_b128(rs, 16, j * (int)sizeof(FacetRec), 0);
+    FacetV f;
+    f.dx = __uint_as_float(a[0]);
+    f.dy = __uint_as_float(a[1]);
+    f.z = __uint_as_float(a[2]);
+    f.vx = __uint_as_float(a[3]);
+    f.vy = __uint_as_float(b[0]);
+    f.vz = __uint_as_float(b[1]);
+    f.ar = __uint_as_float(b[2]);
+    f.ai = __uint_as_float(b[3]);
+    return f;
 }
 
 template <int WIN>
 __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
-    constexpr int ROW = WIN + 1;            // complex samples per LDS row (one pad)
-    __shared__ float2 acc[64 * ROW];
+    __shared__ float2 acc[WIN * 64];        // [sample][lane]
 
     const int patch = blockIdx.x, grp = blockIdx.y, ch = blockIdx.z;
     const cptr<int> patch_first = (cptr<int>)A.patch_first;
     const cptr<BlockRec> blocks = (cptr<BlockRec>)A.blocks;
-    const cptr<FacetRec> facets = (cptr<FacetRec>)A.facets;
     const int b0 = patch_first[patch], b1 = patch_first[patch + 1];
     if (b0 == b1) return;
     const int lane = threadIdx.x;
@@ -101,8 +120,8 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
         if (h - l + 1 > WIN) l = ((l + h) >> 1) - WIN / 2;
         lo = __builtin_amdgcn_readfirstlane(l);
     }
-    float2 *row = acc + lane * ROW;
-    for (int i = 0; i < ROW; ++i) row[i] = make_float2(0.f, 0.f);
+    float2 *col = acc + lane;
+    for (int i = 0; i < WIN; ++i) col[64 * i] = make_float2(0.f, 0.f);
 
     const PulseRec &P = PR[plc];
     const double ptx[3] = {P.ptx[0], P.ptx[1], P.ptx[2]};
@@ -122,13 +141,11 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
         // the window offset of the first tap rides in the sample fraction, so
         // the floor of the sample position is the window index directly
         r.fb += (float)(r.nb - lo - 3);
-        const int j1 = blk.start + blk.count;
-        // the sorted facet array carries one padding record, so the look-ahead
-        // load of the next facet is always in bounds
-        FacetRec fn = load_facet(facets + blk.start);
-        for (int j = blk.start; j < j1; ++j) {
-            const FacetRec f = fn;
-            fn = load_facet(facets + j + 1);
+        const __amdgpu_buffer_rsrc_t rs = facet_rsrc(A.facets + blk.start, blk.count);
+        FacetV fn = load_facet(rs, 0);
+        for (int j = 0; j < blk.count; ++j) {
+            const FacetV f = fn;
+            fn = load_facet(rs, j + 1);
             Geo g;
             facet_geo(r, kc, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz, graze_any, A.linv_hi,
                       A.linv_lo, A.fs_cf, g);
@@ -136,10 +153,10 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
             // read-modify-write of 8 consecutive complex samples.
             const int n0 = g.fl;                  // window index of the first tap
             const bool inw = (unsigned)n0 <= (unsigned)(WIN - 8);
-            float2 *p = row + (inw ? n0 : 0);
+            float2 *p = col + 64 * (inw ? n0 : 0);
             float2 old[8];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) old[k] = p[k];
+            for (int k = 0; k < 8; ++k) old[k] = p[64 * k];
             // a lane outside the window adds zero to its row (and goes below)
             const float al = inw ? g.amp : 0.0f;
             const float wrl = al * fmaf(f.ar, g.cs, -(f.ai * g.sn));
@@ -148,7 +165,7 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
             taps8(A.tp, tt, g.f, tap);
 #pragma unroll
             for (int k = 0; k < 8; ++k)
-                p[k] = make_float2(fmaf(wrl, tap[k], old[k].x), fmaf(wil, tap[k], old[k].y));
+                p[64 * k] = make_float2(fmaf(wrl, tap[k], old[k].x), fmaf(wil, tap[k], old[k].y));
             if (!inw && live) {
                 const float wr = g.amp * fmaf(f.ar, g.cs, -(f.ai * g.sn));
                 const float wi = g.amp * fmaf(f.ar, g.sn, f.ai * g.cs);
@@ -171,7 +188,7 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
         float *dst = A.iq + 2 * (((size_t)ch * A.np + pl) * (size_t)A.N);
         for (int bin = 0; bin < WIN; ++bin) {
             const int n = lo + bin;
-            const float2 v = row[bin];
+            const float2 v = col[64 * bin];
             if (n < 0 || n >= A.N || (v.x == 0.0f && v.y == 0.0f)) continue;
             unsafeAtomicAdd(dst + 2 * n, v.x);
             unsafeAtomicAdd(dst + 2 * n + 1, v.y);
