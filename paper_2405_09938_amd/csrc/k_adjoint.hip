@@ -74,8 +74,8 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
 
     float gz_acc = 0.f, gvx = 0.f, gvy = 0.f, gvz = 0.f, gar = 0.f, gai = 0.f;
     float *rf = reinterpret_cast<float *>(refs);
-    TapTop tt;
-    tap_top(A.tp, tt);
+    TapV tv;
+    tap_all(A.tp, tv);
 
     for (int c = 0; c < A.C; ++c) {
         const ChanArgs chn = A.ch[c];
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                 facet_geo(r, kc, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz, r.graze != 0, A.linv_hi,
                           A.linv_lo, A.fs_cf, g);
                 float tap[8], dtap[8];
-                taps_d8(A.tp, tt, g.f, tap, dtap);
+                taps_d8(tv, g.f, tap, dtap);
                 // g at samples floor(u) - 3 .. floor(u) + 4
                 const int w0 = g.fl + 4;            // window index of the first tap
                 float br = 0.f, bi = 0.f, dr = 0.f, di = 0.f;

@@ -70,11 +70,27 @@ __device__ __forceinline__ FacetV load_facet(__amdgpu_buffer_rsrc_t rs, int j) {
     return f;
 }
 
+// The flush of windows up to this width goes through a transposed copy in
+// LDS, so that one atomic instruction covers contiguous samples of one line.
+constexpr int kFlushTransposeMax = 32;
+
 template <int WIN>
 __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
-    __shared__ float2 acc[WIN * 64];        // [sample][lane]
+    // [sample][lane] during the sum; [lane][WIN + 1] for the flush
+    constexpr int kAcc = WIN <= kFlushTransposeMax ? 64 * (WIN + 1) : 64 * WIN;
+    __shared__ float2 acc[kAcc];
 
-    const int patch = blockIdx.x, grp = blockIdx.y, ch = blockIdx.z;
+    // Workgroup -> (patch, pulse group).  Workgroups go to the 8 XCDs
+    // round-robin by linear index, so index L runs on XCD L % 8.  All pulse
+    // groups of one patch get the same L % 8 and consecutive L / 8: they run
+    // on one XCD close in time and read the patch's facet records from its
+    // L2 instead of HBM.
+    const int G = (A.np + 63) >> 6;
+    const unsigned L = blockIdx.x, r8 = L >> 3;
+    const int grp = (int)(r8 % (unsigned)G);
+    const int patch = (int)((r8 / (unsigned)G) * 8u + (L & 7u));
+    const int ch = blockIdx.y;
+    if (patch >= A.n_patches) return;
     const cptr<int> patch_first = (cptr<int>)A.patch_first;
     const cptr<BlockRec> blocks = (cptr<BlockRec>)A.blocks;
     const int b0 = patch_first[patch], b1 = patch_first[patch + 1];
@@ -129,8 +145,8 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
     const double rref = P.rref;
     const float tf = (float)P.t;
     float *iq_row = A.iq + 2 * ((size_t)ch * A.np + plc) * (size_t)A.N;
-    TapTop tt;
-    tap_top(A.tp, tt);
+    TapV tv;
+    tap_all(A.tp, tv);
 
     for (int b = b0; b < b1; ++b) {
         const BlockRec blk = load_block(blocks + b);
@@ -162,7 +178,7 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
             const float wrl = al * fmaf(f.ar, g.cs, -(f.ai * g.sn));
             const float wil = al * fmaf(f.ar, g.sn, f.ai * g.cs);
             float tap[8];
-            taps8(A.tp, tt, g.f, tap);
+            taps8(tv, g.f, tap);
 #pragma unroll
             for (int k = 0; k < 8; ++k)
                 p[64 * k] = make_float2(fmaf(wrl, tap[k], old[k].x), fmaf(wil, tap[k], old[k].y));
@@ -184,7 +200,27 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
 
     // flush the window into the lines (zeros skipped); neighbouring patches
     // overlap in range, hence the atomics
-    if (live) {
+    if constexpr (WIN <= kFlushTransposeMax) {
+        // each lane takes its pulse row into registers, then writes it back
+        // lane-major with one pad sample (conflict-free both ways); line p is
+        // then flushed by lanes 0 .. 2 WIN - 1, one float each
+        float2 v[WIN];
+#pragma unroll
+        for (int i = 0; i < WIN; ++i) v[i] = col[64 * i];
+        float2 *rowp = acc + lane * (WIN + 1);
+#pragma unroll
+        for (int i = 0; i < WIN; ++i) rowp[i] = v[i];
+        const float *accf = reinterpret_cast<const float *>(acc);
+        const int n = lo + (lane >> 1);
+        const bool lane_in = lane < 2 * WIN && n >= 0 && n < A.N;
+        const int pend = (A.np - grp * 64) < 64 ? (A.np - grp * 64) : 64;
+        float *line = A.iq + 2 * (((size_t)ch * A.np + (size_t)grp * 64) * (size_t)A.N) +
+                      2 * (ptrdiff_t)lo + lane;
+        for (int p = 0; p < pend; ++p) {
+            const float x = lane < 2 * WIN ? accf[p * 2 * (WIN + 1) + lane] : 0.0f;
+            if (lane_in && x != 0.0f) unsafeAtomicAdd(line + 2 * (size_t)p * A.N, x);
+        }
+    } else if (live) {
         float *dst = A.iq + 2 * (((size_t)ch * A.np + pl) * (size_t)A.N);
         for (int bin = 0; bin < WIN; ++bin) {
             const int n = lo + bin;
@@ -200,7 +236,11 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
 
 hipError_t launch_forward(const FwdArgs &a, int C, int win, hipStream_t s) {
     if (a.n_patches == 0 || a.np == 0) return hipSuccess;
-    dim3 grid((unsigned)a.n_patches, (unsigned)((a.np + 63) / 64), (unsigned)C);
+    // (patch, pulse group) pairs, patches padded to a multiple of the 8 XCDs
+    const unsigned long long groups = (unsigned long long)((a.np + 63) / 64);
+    const unsigned long long wgs = groups * (((unsigned long long)a.n_patches + 7) / 8 * 8);
+    if (wgs > 0xffffffffULL) return hipErrorInvalidConfiguration;
+    dim3 grid((unsigned)wgs, (unsigned)C);
     switch (win) {
         case 24: hipLaunchKernelGGL(k_forward<24>, grid, dim3(64), 0, s, a); break;
         case 32: hipLaunchKernelGGL(k_forward<32>, grid, dim3(64), 0, s, a); break;

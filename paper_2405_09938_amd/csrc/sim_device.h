@@ -262,6 +262,36 @@ __device__ __forceinline__ void taps8(const TapPoly &tp, const TapTop &tt, float
     }
 }
 
+// All tap coefficients held in VGPRs (uniform values).  Frees 32 SGPRs in
+// kernels whose scalar registers would otherwise spill, and keeps the tap
+// FMAs free of SGPR operands.
+struct TapV {
+    float e[4][4], o[4][4];
+};
+
+__device__ __forceinline__ void tap_all(const TapPoly &tp, TapV &t) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            t.e[j][m] = to_vgpr(tp.e[j][m]);
+            t.o[j][m] = to_vgpr(tp.o[j][m]);
+        }
+}
+
+__device__ __forceinline__ void taps8(const TapV &tv, float f, float *tap) {
+    const float sg = fmaf(f, 2.0f, -1.0f);
+    const float y = sg * sg;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float e = fmaf(fmaf(fmaf(tv.e[j][3], y, tv.e[j][2]), y, tv.e[j][1]), y, tv.e[j][0]);
+        const float od =
+            sg * fmaf(fmaf(fmaf(tv.o[j][3], y, tv.o[j][2]), y, tv.o[j][1]), y, tv.o[j][0]);
+        tap[4 + j] = e + od;
+        tap[3 - j] = e - od;
+    }
+}
+
 // The 8 taps and their derivatives with respect to u, from the same
 // coefficients: Horner's rule carries each polynomial and its derivative in y
 // together.  With Q_j = E(y) + s O(y), y = s^2, s = 2f - 1 and du = df:
@@ -284,6 +314,33 @@ __device__ __forceinline__ void taps_d8(const TapPoly &tp, const TapTop &tt, flo
         o = fmaf(o, y, tp.o[j][1]);
         dq = fmaf(dq, y, o);
         o = fmaf(o, y, tp.o[j][0]);
+        const float so = sg * o;
+        tap[4 + j] = e + so;
+        tap[3 - j] = e - so;
+        const float a = 2.0f * fmaf(y2, dq, o);
+        const float b = s4 * de;
+        d[4 + j] = a + b;
+        d[3 - j] = b - a;
+    }
+}
+
+__device__ __forceinline__ void taps_d8(const TapV &tv, float f, float *tap,
+                                        float *d) {
+    const float sg = fmaf(f, 2.0f, -1.0f);
+    const float y = sg * sg;
+    const float y2 = y + y, s4 = 4.0f * sg;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        float e = fmaf(tv.e[j][3], y, tv.e[j][2]), de = tv.e[j][3];
+        de = fmaf(de, y, e);
+        e = fmaf(e, y, tv.e[j][1]);
+        de = fmaf(de, y, e);
+        e = fmaf(e, y, tv.e[j][0]);
+        float o = fmaf(tv.o[j][3], y, tv.o[j][2]), dq = tv.o[j][3];
+        dq = fmaf(dq, y, o);
+        o = fmaf(o, y, tv.o[j][1]);
+        dq = fmaf(dq, y, o);
+        o = fmaf(o, y, tv.o[j][0]);
         const float so = sg * o;
         tap[4 + j] = e + so;
         tap[3 - j] = e - so;
