@@ -65,7 +65,12 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
     __shared__ float4 refs[kStage * kNRef / 4];
     __shared__ float2 gwin[kStage * kGW];
 
-    const long long b = blockIdx.x;
+    // Workgroups go to the 8 XCDs round-robin by linear index; XCD x takes
+    // the contiguous x-th eighth of the (patch-ordered) blocks, so blocks
+    // reading the same range samples of g share that XCD's L2.
+    const unsigned per = gridDim.x >> 3;
+    const long long b = (long long)(blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+    if (b >= A.n_blocks) return;
     const BlockRec blk = A.blocks[b];
     const int lane = threadIdx.x;
     const bool have = lane < blk.count;
@@ -242,7 +247,9 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
 
 hipError_t launch_adjoint(const AdjArgs &a, hipStream_t s) {
     if (a.n_blocks == 0 || a.np == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_adjoint, dim3((unsigned)a.n_blocks), dim3(64), 0, s, a);
+    const unsigned long long wgs = ((unsigned long long)a.n_blocks + 7) / 8 * 8;
+    if (wgs > 0xffffffffULL) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_adjoint, dim3((unsigned)wgs), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
