@@ -197,7 +197,10 @@ int sim_waveform_info(const sim_handle *h, int *chirp_len, int *fft_len);
  * into patches of cells that share a range window, and the permutation is
  * kept in plan-owned device memory.  Depends only on x, y (device float32
  * [n]).  block_edge in (0, 64] metres; 8 suits 1 m grids.  Synchronises the
- * stream (it reads back the bounding box and block count).
+ * stream (it reads back the bounding box and block count).  Its temporary
+ * device buffers are kept by the handle and reused by later calls (at most
+ * 16 of them, released by sim_destroy); calls on one handle must not run
+ * concurrently.
  * Errors: SIM_EINVAL, SIM_ENOMEM, SIM_EHIP, SIM_EUNSUPPORTED (lattice larger
  * than 2^28 cells).
  */

@@ -193,18 +193,55 @@ hipError_t dalloc(T **p, size_t count) {
     return hipMalloc((void **)p, sizeof(T) * (count > 0 ? count : 1));
 }
 
-struct DevBufs {   // frees on scope exit
-    std::vector<void *> ptrs;
+// Temporaries of one sim_plan_create call.  They come from (and go back to)
+// the handle's pool, so steady-state planning makes no hipMalloc / hipFree
+// (hipFree synchronises the device).  Buffers return to the pool only after
+// the call's final stream synchronisation (`done()`); on an error path they
+// are freed instead, which waits for any kernel still using them.
+struct DevBufs {
+    sim_handle *h;
+    std::vector<std::pair<void *, size_t>> bufs;
+    bool finished = false;
+    explicit DevBufs(sim_handle *hh) : h(hh) {}
     ~DevBufs() {
-        for (void *p : ptrs)
-            if (p) (void)hipFree(p);
+        for (auto &b : bufs) {
+            if (finished) h->scratch_pool.push_back(b);
+            else (void)hipFree(b.first);
+        }
+        // keep the pool small: drop the smallest buffers beyond 16
+        auto &pool = h->scratch_pool;
+        while (pool.size() > 16) {
+            size_t k = 0;
+            for (size_t i = 1; i < pool.size(); ++i)
+                if (pool[i].second < pool[k].second) k = i;
+            (void)hipFree(pool[k].first);
+            pool.erase(pool.begin() + (long)k);
+        }
     }
+    void done() { finished = true; }
     template <typename T>
     hipError_t alloc(T **p, size_t count) {
-        hipError_t e = dalloc(p, count);
-        if (e == hipSuccess) ptrs.push_back(*p);
-        else *p = nullptr;
-        return e;
+        const size_t bytes = sizeof(T) * (count > 0 ? count : 1);
+        auto &pool = h->scratch_pool;
+        size_t best = pool.size();
+        for (size_t i = 0; i < pool.size(); ++i)
+            if (pool[i].second >= bytes && (best == pool.size() || pool[i].second < pool[best].second))
+                best = i;
+        if (best < pool.size()) {
+            bufs.push_back(pool[best]);
+            pool.erase(pool.begin() + (long)best);
+            *p = (T *)bufs.back().first;
+            return hipSuccess;
+        }
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, bytes);
+        if (e != hipSuccess) {
+            *p = nullptr;
+            return e;
+        }
+        bufs.emplace_back(q, bytes);
+        *p = (T *)q;
+        return hipSuccess;
     }
 };
 
@@ -423,6 +460,7 @@ void sim_destroy(sim_handle *h) {
     if (h->chirp_spec_d) (void)hipFree(h->chirp_spec_d);
     if (h->twiddle_d) (void)hipFree(h->twiddle_d);
     if (h->gen_tab_d) (void)hipFree(h->gen_tab_d);
+    for (auto &b : h->scratch_pool) (void)hipFree(b.first);
     delete h;
 }
 
@@ -455,7 +493,7 @@ int sim_plan_create(sim_handle *h, const float *x, const float *y, long long n,
     if (int rc = ensure_device(h)) return rc;
     hipStream_t s = (hipStream_t)stream;
 
-    DevBufs tmp;
+    DevBufs tmp(h);
     int *bb = nullptr;
     HS_HIP(tmp.alloc(&bb, 4), "plan alloc");
     {
@@ -589,6 +627,7 @@ int sim_plan_create(sim_handle *h, const float *x, const float *y, long long n,
                                     s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess)
         return fail(SIM_EHIP, std::string("plan blocks: ") + hipGetErrorString(e));
+    tmp.done();
     *out = P;
     return SIM_OK;
 }

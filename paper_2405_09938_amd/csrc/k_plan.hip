@@ -78,13 +78,32 @@ __device__ __forceinline__ int cell_key(float xv, float yv, const Lattice &L) {
     return (int)((patch * L.py + (cy - py * L.py)) * L.px + (cx - px * L.px));
 }
 
+// Lanes of a wave holding the same key take their ranks from one atomic:
+// facets arrive in grid order, so a wave covers only a few cells and the
+// per-facet atomics would serialise on the same counters.
 __global__ void k_cell_keys(const float *x, const float *y, long long n, Lattice L, int *keys,
                             int *rank, int *count) {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int k = cell_key(x[i], y[i], L);
-    keys[i] = k;
-    rank[i] = atomicAdd(count + k, 1);
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = i < n;
+    const int k = valid ? cell_key(x[i], y[i], L) : -1;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    unsigned long long pending = __ballot(valid);
+    int r = 0;
+    while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const int kl = __shfl(k, leader);
+        const unsigned long long same = __ballot(valid && k == kl);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(count + kl, __popcll(same));
+        base = __shfl(base, leader);
+        if (valid && k == kl) r = base + __popcll(same & below);
+        pending &= ~same;
+    }
+    if (valid) {
+        keys[i] = k;
+        rank[i] = r;
+    }
 }
 
 // ---- exclusive scan (int32), three passes ---------------------------------

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "heeps_sim.h"
@@ -138,6 +139,8 @@ struct sim_handle {
     double *gen_tab_d = nullptr;        // wave component table of the generator
     size_t gen_tab_cap = 0;
     std::vector<double> gen_tab_h;
+    // device buffers reused by sim_plan_create for its temporaries
+    std::vector<std::pair<void *, size_t>> scratch_pool;
 };
 
 struct sim_plan {
