@@ -34,12 +34,16 @@ if ROOT not in sys.path:
 
 # Algorithmic ALU slots per contribution of the forward sum at one channel,
 # frozen from the per-contribution operation listing of the reformulated
-# arithmetic (offset expansion of the range, one reciprocal for the four
-# pattern factors, even/odd tap polynomials): 116 FP32 operations at one slot
-# and 7 transcendentals (sin, cos, rcp), which gfx950 issues at a quarter of
-# the FP32 FMA rate, at four slots each.  Loop control, window tests and LDS
-# addressing are overhead, not counted.
+# arithmetic (offset expansion of the range, one reciprocal for the pattern
+# factors, even/odd tap polynomials): 116 FP32 operations at one slot and 7
+# transcendentals (sin, cos, rcp), which gfx950 issues at a quarter of the
+# FP32 FMA rate, at four slots each.  Where the plan takes the elevation
+# pattern factors at block centres, two direction cosines, their two sines
+# and four products leave the listing: 104 FP32 operations, 5
+# transcendentals.  Loop control, window tests and LDS addressing are
+# overhead, not counted.
 W_ALG_SLOTS = 116.0 + 7 * 4.0
+W_ALG_SLOTS_EL_CONST = 104.0 + 5 * 4.0
 PEAK_SLOTS = 256 * 128 * 2.4e9         # FP32 lane-operations per second (157.3 TFLOP/s / 2)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_forward_cfg2_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2405_09938_amd", "csrc", f)
@@ -186,7 +190,17 @@ def main():
         print(f"forward+adjoint step {fa_s * 1e3:.3f} ms, {fwd_adj['value']:.2f} G/s",
               flush=True)
 
-    achieved = W_ALG_SLOTS * contrib / (kern_ms * 1e-3) / 1e12
+    if streamed:
+        # evaluation mode of the first chunk's plan (the library plans each
+        # chunk the same way inside the streamed call)
+        c0 = wl.chunks[0]
+        f0 = sim.generate(sea, wl.seed, *c0)
+        el_const = sim.plan(f0["x"], f0["y"], wl.block_edge).el_const
+        del f0
+    else:
+        el_const = plan.el_const
+    w_alg = W_ALG_SLOTS_EL_CONST if el_const else W_ALG_SLOTS
+    achieved = w_alg * contrib / (kern_ms * 1e-3) / 1e12
     peak = PEAK_SLOTS / 1e12
     traffic = None
     valu = None
@@ -198,7 +212,8 @@ def main():
             valu = tr.get("valu_insts_per_launch")
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
                 "unit": "Tslot/s", "frac": round(achieved / peak, 4), "traffic": traffic,
-                "kernel": "k_forward", "w_alg_slots_per_contribution": W_ALG_SLOTS,
+                "kernel": "k_forward", "w_alg_slots_per_contribution": w_alg,
+                "elevation_at_block_centres": el_const,
                 "contributions_per_launch": contrib, "avg_launch_ms": round(kern_ms, 4)}
     if valu:
         # issued wave64 VALU instructions (rocprof SQ_INSTS_VALU of the same

@@ -215,6 +215,20 @@ int sim_plan_info(const sim_plan *plan, long long *n_facets, long long *n_blocks
                   long long *n_patches);
 
 /*
+ * Host outputs: the plan's evaluation mode of the antenna elevation factors
+ * (Sec. III.B eq. 16 gains).  The field pattern of each antenna is the
+ * product of an azimuth and an elevation sinc factor.  When *el_const = 1
+ * the forward and adjoint sums take both legs' elevation factors at each
+ * block centre (per pulse) instead of per facet: sim_plan_create chooses
+ * this only when its bound on the relative error of doing so, *el_bound,
+ * is at most 5e-6 for every facet within reach of its block centre (half a
+ * block diagonal plus 4 m of height and 2.5 m/s of drift over the dwell).
+ * Otherwise *el_const = 0 and every factor is evaluated per facet.
+ * Either output pointer may be NULL.  Errors: SIM_EINVAL (NULL plan).
+ */
+int sim_plan_mode(const sim_plan *plan, int *el_const, double *el_bound);
+
+/*
  * Generate facets of the grid sub-rectangle [ix0, ix0+cnx) x [iy0, iy0+cny)
  * of `sea` (row-major in the sub-rectangle).  Random draws use Philox4x32-10
  * keyed by `seed` with the global grid index as counter, so any chunking of

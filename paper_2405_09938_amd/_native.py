@@ -77,6 +77,7 @@ class SimSea(ctypes.Structure):
 
 EXPORTS = ("sim_create", "sim_destroy", "sim_last_error", "sim_pulse_info",
            "sim_waveform_info", "sim_plan_create", "sim_plan_destroy", "sim_plan_info",
+           "sim_plan_mode",
            "sim_generate_facets", "sim_forward", "sim_apply_waveform",
            "sim_apply_waveform_adjoint", "sim_backward", "sim_stream_forward",
            "sim_stream_backward")
@@ -113,6 +114,7 @@ def load(path: str = LIB_PATH):
     L.sim_plan_destroy.argtypes = [vp]
     L.sim_plan_destroy.restype = None
     L.sim_plan_info.argtypes = [vp, P(ll), P(ll), P(ll)]
+    L.sim_plan_mode.argtypes = [vp, P(i), P(ctypes.c_double)]
     L.sim_generate_facets.argtypes = [vp, P(SimSea), ctypes.c_ulonglong, i, i, i, i,
                                       P(SimFacetsOut), vp]
     L.sim_forward.argtypes = [vp, vp, P(SimFacets), i, i, vp, i, vp]

@@ -16,6 +16,9 @@
 #ifndef HEEPS_WIN_MIN
 #define HEEPS_WIN_MIN 24
 #endif
+#ifndef HEEPS_EL_CONST_TOL
+#define HEEPS_EL_CONST_TOL 5e-6
+#endif
 #ifndef HEEPS_PATCH_CELLS
 #define HEEPS_PATCH_CELLS 24.0
 #endif
@@ -244,6 +247,58 @@ struct DevBufs {
         return hipSuccess;
     }
 };
+
+// Bound on the relative error of taking each antenna's elevation pattern
+// factor sinc(kappa v / beta_el) at the block centre instead of per facet.
+// Over the scene rectangle (z = 0) and the first, middle and last pulses,
+// x = kappa v / beta_el spans [x_lo, x_hi] and the range is at least R_min;
+// a facet within e_max of its block centre moves x by at most
+// dx = (kappa / beta_el) e_max / R_min.  The first-order error is then at
+// most dx max|sinc'| / min sinc over [x_lo - dx, x_hi + dx], plus the
+// second-order term dx^2 max|sinc''| / 2 / min sinc (|sinc''| <= pi^2 / 3).
+// Returns +inf when the interval reaches |x| >= 0.9 (near the first null).
+double elevation_bound(const sim_handle *h, const float box[4], double e_max) {
+    double worst = 0.0;
+    const double xs[3] = {box[0], 0.5 * (box[0] + box[1]), box[1]};
+    const double ys[3] = {box[2], 0.5 * (box[2] + box[3]), box[3]};
+    const int ps[3] = {0, h->Np / 2, h->Np - 1};
+    for (int ch = 0; ch < h->C; ++ch)
+        for (int leg = 0; leg < 2; ++leg) {
+            const hs::AntArgs &a = h->antc[leg == 0 ? h->chc[ch].tx : h->chc[ch].rx];
+            double x_lo = 1e300, x_hi = -1e300, r_min = 1e300;
+            for (int pi = 0; pi < 3; ++pi) {
+                const hs::PulseRec &r = h->pulses_h[(size_t)ch * h->Np + ps[pi]];
+                const double *P = leg == 0 ? r.ptx : r.prx;
+                for (double xv : xs)
+                    for (double yv : ys) {
+                        const double d[3] = {xv - P[0], yv - P[1], -P[2]};
+                        const double R = norm3(d);
+                        const double x = a.ke * (d[0] * a.el[0] + d[1] * a.el[1] + d[2] * a.el[2]) / R;
+                        x_lo = std::min(x_lo, x);
+                        x_hi = std::max(x_hi, x);
+                        r_min = std::min(r_min, R);
+                    }
+            }
+            const double dx = a.ke * e_max / r_min;
+            const double lo = x_lo - dx - 0.1 * (x_hi - x_lo), hi = x_hi + dx + 0.1 * (x_hi - x_lo);
+            if (std::max(std::fabs(lo), std::fabs(hi)) >= 0.9)
+                return std::numeric_limits<double>::infinity();
+            double max_d = 0.0, min_f = 1.0;
+            for (int k = 0; k <= 2000; ++k) {
+                const double x = lo + (hi - lo) * k / 2000.0;
+                const double px = M_PI * x;
+                const double f = std::fabs(px) < 1e-8 ? 1.0 : std::sin(px) / px;
+                const double df = std::fabs(x) < 1e-8 ? 0.0 : (std::cos(px) - f) / x;
+                max_d = std::max(max_d, std::fabs(df));
+                min_f = std::min(min_f, f);
+            }
+            // |sinc''| <= pi^2 / 3 bounds how much sinc' moves between samples
+            max_d += M_PI * M_PI / 3.0 * (hi - lo) / 2000.0;
+            const double b = (dx * max_d + 0.5 * dx * dx * M_PI * M_PI / 3.0) / min_f;
+            worst = std::max(worst, b);
+        }
+    return worst;
+}
 
 // Device tables are uploaded on the first call that needs the GPU, on the
 // device current at that time; later calls must run on the same device.
@@ -595,6 +650,10 @@ int sim_plan_create(sim_handle *h, const float *x, const float *y, long long n,
     P->n_patches = n_patches;
     P->halo = halo;
     P->win = win;
+    // facets lie within half a block diagonal of their block centre, moved by
+    // heights up to 4 m and drift at up to 2.5 m/s over the dwell (as the halo)
+    P->el_bound = elevation_bound(h, box, 0.5 * std::sqrt(2.0) * block_edge + 4.0 + 2.5 * tmax);
+    P->el_const = P->el_bound <= HEEPS_EL_CONST_TOL;
     auto fail = [&](int code, const std::string &msg) {
         sim_plan_destroy(P);
         hs::set_error(msg);
@@ -647,6 +706,13 @@ int sim_plan_info(const sim_plan *P, long long *n_facets, long long *n_blocks,
     if (n_facets) *n_facets = P->n;
     if (n_blocks) *n_blocks = P->n_blocks;
     if (n_patches) *n_patches = P->n_patches;
+    return SIM_OK;
+}
+
+int sim_plan_mode(const sim_plan *P, int *el_const, double *el_bound) {
+    if (!P) HS_FAIL(SIM_EINVAL, "plan is NULL");
+    if (el_const) *el_const = P->el_const ? 1 : 0;
+    if (el_bound) *el_bound = P->el_bound;
     return SIM_OK;
 }
 
@@ -762,7 +828,7 @@ int sim_forward(sim_handle *h, sim_plan *P, const sim_facets *f, int p0, int np,
     a.np = np;
     a.n_patches = (int)P->n_patches;
     a.halo = P->halo;
-    HS_HIP(hs::launch_forward(a, h->C, P->win, s), "forward");
+    HS_HIP(hs::launch_forward(a, h->C, P->win, P->el_const, s), "forward");
     return SIM_OK;
 }
 
@@ -815,7 +881,7 @@ int sim_backward(sim_handle *h, sim_plan *P, const sim_facets *f, int p0, int np
     a.C = h->C;
     a.n_blocks = P->n_blocks;
     a.accumulate = accumulate ? 1 : 0;
-    HS_HIP(hs::launch_adjoint(a, s), "adjoint");
+    HS_HIP(hs::launch_adjoint(a, P->el_const, s), "adjoint");
     return SIM_OK;
 }
 

@@ -61,6 +61,7 @@ __device__ __forceinline__ float ant_grad(const AntArgs &a, double d0, double d1
     return su * sv;
 }
 
+template <bool ELC>
 __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
     __shared__ float4 refs[kStage * kNRef / 4];
     __shared__ float2 gwin[kStage * kGW];
@@ -96,7 +97,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                 const bool live = pl < A.np;
                 const PulseRec &P = PR[live ? pl : A.np - 1];
                 Refs r;
-                block_refs(xb, yb, P.ptx, P.prx, P.rref, ta, ra, chn.rtrr_mid, A.f0_c, A.fs_c,
+                block_refs<ELC>(xb, yb, P.ptx, P.prx, P.rref, ta, ra, chn.rtrr_mid, A.f0_c, A.fs_c,
                            A.n_ref, live, r);
                 // grad T at the centre
                 const double dt0 = xb - P.ptx[0], dt1 = yb - P.ptx[1], dt2 = -P.ptx[2];
@@ -105,8 +106,10 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                 const float ft = ant_grad(ta, dt0, dt1, dt2, (double)r.irt, gft);
                 const float fr = ant_grad(ra, dr0, dr1, dr2, (double)r.irr, gfr);
                 float *o = rf + lane * kNRef;
-                // r.sb carries the mask and 1/(2 pi)^4 (see block_refs): undo for grad T
-                const float sbt = r.sb * kTwoPi4F;
+                // spreading at the centre (r.sb also carries the sinc normalisation)
+                const float sbt = (r.mask != 0.0f || r.graze)
+                                      ? (float)(chn.rtrr_mid * (double)r.irt * (double)r.irr)
+                                      : 0.0f;
                 const float gs[3] = {-sbt * (r.dtx * r.irt + (r.gx - r.dtx) * r.irr),
                                      -sbt * (r.dty * r.irt + (r.gy - r.dty) * r.irr),
                                      -sbt * (r.dtz * r.irt + (r.gz - r.dtz) * r.irr)};
@@ -158,7 +161,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                 r.dbt = o[R_DBT]; r.dbr = o[R_DBR]; r.graze = __float_as_int(o[R_GRAZE]);
                 const float tf = o[R_T];
                 Geo g;
-                facet_geo(r, kc, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz, r.graze != 0, A.linv_hi,
+                facet_geo<ELC>(r, kc, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz, r.graze != 0, A.linv_hi,
                           A.linv_lo, A.fs_cf, g);
                 float tap[8], dtap[8];
                 taps_d8(tv, g.f, tap, dtap);
@@ -245,11 +248,12 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
 
 }  // namespace
 
-hipError_t launch_adjoint(const AdjArgs &a, hipStream_t s) {
+hipError_t launch_adjoint(const AdjArgs &a, bool el_const, hipStream_t s) {
     if (a.n_blocks == 0 || a.np == 0) return hipSuccess;
     const unsigned long long wgs = ((unsigned long long)a.n_blocks + 7) / 8 * 8;
     if (wgs > 0xffffffffULL) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(k_adjoint, dim3((unsigned)wgs), dim3(64), 0, s, a);
+    if (el_const) hipLaunchKernelGGL(k_adjoint<true>, dim3((unsigned)wgs), dim3(64), 0, s, a);
+    else hipLaunchKernelGGL(k_adjoint<false>, dim3((unsigned)wgs), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 

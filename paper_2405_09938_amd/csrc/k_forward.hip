@@ -74,7 +74,7 @@ __device__ __forceinline__ FacetV load_facet(__amdgpu_buffer_rsrc_t rs, int j) {
 // LDS, so that one atomic instruction covers contiguous samples of one line.
 constexpr int kFlushTransposeMax = 32;
 
-template <int WIN>
+template <int WIN, bool ELC>
 __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
     // [sample][lane] during the sum; [lane][WIN + 1] for the flush
     constexpr int kAcc = WIN <= kFlushTransposeMax ? 64 * (WIN + 1) : 64 * WIN;
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
     for (int b = b0; b < b1; ++b) {
         const BlockRec blk = load_block(blocks + b);
         Refs r;
-        block_refs((double)blk.xb, (double)blk.yb, ptx, prx, rref, ta, ra, chn.rtrr_mid, A.f0_c,
+        block_refs<ELC>((double)blk.xb, (double)blk.yb, ptx, prx, rref, ta, ra, chn.rtrr_mid, A.f0_c,
                    A.fs_c, A.n_ref, live, r);
         const bool graze_any = __any(r.graze);
         // the window offset of the first tap rides in the sample fraction, so
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
             const FacetV f = fn;
             fn = load_facet(rs, j + 1);
             Geo g;
-            facet_geo(r, kc, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz, graze_any, A.linv_hi,
+            facet_geo<ELC>(r, kc, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz, graze_any, A.linv_hi,
                       A.linv_lo, A.fs_cf, g);
             // Each lane owns its pulse row, so the deposit is a plain
             // read-modify-write of 8 consecutive complex samples.
@@ -234,20 +234,26 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
 
 }  // namespace
 
-hipError_t launch_forward(const FwdArgs &a, int C, int win, hipStream_t s) {
+hipError_t launch_forward(const FwdArgs &a, int C, int win, bool el_const, hipStream_t s) {
     if (a.n_patches == 0 || a.np == 0) return hipSuccess;
     // (patch, pulse group) pairs, patches padded to a multiple of the 8 XCDs
     const unsigned long long groups = (unsigned long long)((a.np + 63) / 64);
     const unsigned long long wgs = groups * (((unsigned long long)a.n_patches + 7) / 8 * 8);
     if (wgs > 0xffffffffULL) return hipErrorInvalidConfiguration;
     dim3 grid((unsigned)wgs, (unsigned)C);
+#define HS_FWD(W)                                                                          \
+    case W:                                                                                \
+        if (el_const) hipLaunchKernelGGL((k_forward<W, true>), grid, dim3(64), 0, s, a);   \
+        else hipLaunchKernelGGL((k_forward<W, false>), grid, dim3(64), 0, s, a);           \
+        break;
     switch (win) {
-        case 24: hipLaunchKernelGGL(k_forward<24>, grid, dim3(64), 0, s, a); break;
-        case 32: hipLaunchKernelGGL(k_forward<32>, grid, dim3(64), 0, s, a); break;
-        case 48: hipLaunchKernelGGL(k_forward<48>, grid, dim3(64), 0, s, a); break;
-        case 64: hipLaunchKernelGGL(k_forward<64>, grid, dim3(64), 0, s, a); break;
+        HS_FWD(24)
+        HS_FWD(32)
+        HS_FWD(48)
+        HS_FWD(64)
         default: return hipErrorInvalidValue;
     }
+#undef HS_FWD
     return hipGetLastError();
 }
 

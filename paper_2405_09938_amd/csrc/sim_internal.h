@@ -151,6 +151,8 @@ struct sim_plan {
     hs::Lattice lat;
     int halo;                    // range-window halo in samples (heights, drift)
     int win;                     // LDS range-window width of the forward kernel
+    bool el_const = false;       // elevation factors taken at block centres
+    double el_bound = 0.0;       // bound on the relative error of doing so
     int *perm = nullptr;         // [n] sorted position -> facet index
     hs::BlockRec *blocks = nullptr;     // [n_blocks]
     int *patch_first = nullptr;  // [n_patches + 1]
@@ -184,8 +186,8 @@ hipError_t launch_gather(const sim_facets &f, const int *perm, const BlockRec *b
                          long long n_blocks, FacetRec *sorted, hipStream_t s);
 
 // Hot path.
-hipError_t launch_forward(const FwdArgs &a, int C, int win, hipStream_t s);
-hipError_t launch_adjoint(const AdjArgs &a, hipStream_t s);
+hipError_t launch_forward(const FwdArgs &a, int C, int win, bool el_const, hipStream_t s);
+hipError_t launch_adjoint(const AdjArgs &a, bool el_const, hipStream_t s);
 hipError_t launch_waveform(const float *in, float *out, long long n_lines, int N, int M,
                            int shift, const float *spec, const float *tw, int adjoint,
                            hipStream_t s);

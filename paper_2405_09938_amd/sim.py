@@ -251,6 +251,10 @@ class Plan:
         N.check(sim.lib.sim_plan_info(ptr, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
                 "sim_plan_info")
         self.n_blocks, self.n_patches = b.value, c.value
+        m, bound = ctypes.c_int(), ctypes.c_double()
+        N.check(sim.lib.sim_plan_mode(ptr, ctypes.byref(m), ctypes.byref(bound)), "sim_plan_mode")
+        # elevation factors taken at block centres (error bound el_bound)
+        self.el_const, self.el_bound = bool(m.value), bound.value
 
     def close(self):
         if getattr(self, "ptr", None):

@@ -86,6 +86,7 @@ def test_entry_points_reject_null(native):
     assert L.sim_forward(None, None, None, 0, 1, None, 0, None) == native.SIM_EINVAL
     assert L.sim_backward(None, None, None, 0, 1, None, None, 0, None) == native.SIM_EINVAL
     assert L.sim_apply_waveform(None, None, None, 1, None) == native.SIM_EINVAL
+    assert L.sim_plan_mode(None, None, None) == native.SIM_EINVAL
     L.sim_destroy(None)
     L.sim_plan_destroy(None)
 

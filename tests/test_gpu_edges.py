@@ -63,6 +63,9 @@ def test_back_plane_masking(env):
     sim = hs.Simulator(g)
     d = dev(torch, f)
     plan = sim.plan(d["x"], d["y"], 2.0)
+    # at 15 km range the elevation factors vary across a block: exact mode
+    say(f"elevation mode: const {plan.el_const}, bound {plan.el_bound:.2e}")
+    assert not plan.el_const
     got = sim.forward(plan, d).cpu().numpy()
     ref = O.forward(g, F)
     e = O.rel_l2(got, ref)

@@ -46,13 +46,15 @@ def sampled_pulses(n_pulses, k, seed):
     return sorted({0, n_pulses - 1, *mid.tolist()})
 
 
-def check_rows(hs, k, n_rows):
+def check_rows(hs, k, n_rows, expect_el_const):
     import torch
     wl = W.workload(k)
     g = wl.geometry
     sim = hs.Simulator(g)
     f = sim.generate(wl.sea, wl.seed)
     plan = sim.plan(f["x"], f["y"], wl.block_edge)
+    say(f"elevation mode: const {plan.el_const}, bound {plan.el_bound:.2e}")
+    assert plan.el_const == expect_el_const
     rc = sim.forward(plan, f)
     raw = sim.apply_waveform(rc) if g.chirp_T > 0 else None
     torch.cuda.synchronize()
@@ -77,13 +79,13 @@ def check_rows(hs, k, n_rows):
 
 def test_workload2_full_rows(hs):
     say("case: workload 2 at full size (1e6 facets, 2048 pulses, 4096 samples), 5 rows")
-    check_rows(hs, 2, 5)
+    check_rows(hs, 2, 5, True)
 
 
 def test_workload3_full_rows(hs):
     say("case: workload 3 at full size (1.6e7 facets, 4096 pulses, 8192 samples, "
         "6 channels), 2 pulses")
-    check_rows(hs, 3, 2)
+    check_rows(hs, 3, 2, True)
 
 
 def test_workload4_full_adjoint_sampled_facets(hs):
