@@ -11,8 +11,11 @@
 // grad R is the facet's own to first order in its offset e from the block
 // centre (d_leg + (e - (e.d_leg) d_leg) / R_leg per leg, which matters at
 // airborne ranges where e/R reaches 1e-4); grad T, whose share of dL/dX is
-// ~1e-4 at 15 km and ~1e-6 at 850 km, is taken at the block centre;
-// everything else is recomputed exactly as in the forward kernel.
+// ~1e-4 at 15 km and ~1e-6 at 850 km, is taken at the block centre, with a
+// first-order correction J e (J its Jacobian there, by central differences
+// in the stage prologue) where the plan evaluates every pattern factor per
+// facet (near-field geometries); everything else is recomputed exactly as in
+// the forward kernel.
 //
 // Work decomposition: one wave per spatial block, lane = facet (<= 64 per
 // block).  The wave loops over channels and over stages of 32 pulses; per
@@ -30,13 +33,14 @@ namespace {
 
 constexpr int kStage = 32;   // pulses per stage
 constexpr int kGW = 16;      // staged samples per pulse: centre - 7 .. centre + 8
-constexpr int kNRef = 32;    // floats per staged pulse record
+constexpr int kNRef = 40;    // floats per staged pulse record
 
 // staged record layout (floats)
 enum {
     R_T = 0, R_DTX, R_DTY, R_DTZ, R_GX, R_GY, R_GZ, R_I2RT, R_I2RR, R_PHIB, R_FB, R_NB,
     R_GTAZ, R_GTEL, R_GRAZ, R_GREL, R_IRT, R_IRT2, R_IRR, R_IRR2, R_SB, R_SBT, R_SBR, R_MASK,
-    R_DTGX, R_DTGY, R_DTGZ, R_DBT, R_DBR, R_GRAZE, R_I2S
+    R_DTGX, R_DTGY, R_DTGZ, R_DBT, R_DBR, R_GRAZE, R_I2S,
+    R_J0   // 9 floats: J[i][j] = d(grad T)_i / dx_j at R_J0 + 3 i + j
 };
 
 // Gradient of one antenna's field pattern at the block centre (FP32 from the
@@ -59,6 +63,27 @@ __device__ __forceinline__ float ant_grad(const AntArgs &a, double d0, double d1
         gr[k] = dsu * sv * gu + su * dsv * gv;
     }
     return su * sv;
+}
+
+// grad T = grad(F_tx F_rx S) at the point (X, Y, Z), S = R_t,mid R_r,mid /
+// (R_t R_r) the spreading (without the mask).
+__device__ __forceinline__ void grad_t(const AntArgs &ta, const AntArgs &ra, double rtrr_mid,
+                                       double X, double Y, double Z, const double *ptx,
+                                       const double *prx, float *out) {
+    const double dt0 = X - ptx[0], dt1 = Y - ptx[1], dt2 = Z - ptx[2];
+    const double dr0 = X - prx[0], dr1 = Y - prx[1], dr2 = Z - prx[2];
+    const double irt = 1.0 / sqrt(dt0 * dt0 + dt1 * dt1 + dt2 * dt2);
+    const double irr = 1.0 / sqrt(dr0 * dr0 + dr1 * dr1 + dr2 * dr2);
+    float gft[3], gfr[3];
+    const float ft = ant_grad(ta, dt0, dt1, dt2, irt, gft);
+    const float fr = ant_grad(ra, dr0, dr1, dr2, irr, gfr);
+    const double sb = rtrr_mid * irt * irr;
+    const double d[3][2] = {{dt0, dr0}, {dt1, dr1}, {dt2, dr2}};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float gs = (float)(-sb * (d[k][0] * irt * irt + d[k][1] * irr * irr));
+        out[k] = fr * (float)sb * gft[k] + ft * (float)sb * gfr[k] + ft * fr * gs;
+    }
 }
 
 template <bool ELC>
@@ -118,6 +143,23 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                 o[R_DTGX] = m * (fr * sbt * gft[0] + ft * sbt * gfr[0] + ft * fr * gs[0]);
                 o[R_DTGY] = m * (fr * sbt * gft[1] + ft * sbt * gfr[1] + ft * fr * gs[1]);
                 o[R_DTGZ] = m * (fr * sbt * gft[2] + ft * sbt * gfr[2] + ft * fr * gs[2]);
+                if constexpr (!ELC) {
+                    // Jacobian of grad T at the centre, central differences over
+                    // +-0.5 m (one direction at a time to keep registers low)
+                    constexpr double h = 0.5;
+                    const float s2h = m * (float)(0.5 / h);
+#pragma unroll 1
+                    for (int j = 0; j < 3; ++j) {
+                        const double ox = j == 0 ? h : 0.0, oy = j == 1 ? h : 0.0,
+                                     oz = j == 2 ? h : 0.0;
+                        float gp[3], gm[3];
+                        grad_t(ta, ra, chn.rtrr_mid, xb + ox, yb + oy, oz, P.ptx, P.prx, gp);
+                        grad_t(ta, ra, chn.rtrr_mid, xb - ox, yb - oy, -oz, P.ptx, P.prx, gm);
+                        o[R_J0 + j] = s2h * (gp[0] - gm[0]);
+                        o[R_J0 + 3 + j] = s2h * (gp[1] - gm[1]);
+                        o[R_J0 + 6 + j] = s2h * (gp[2] - gm[2]);
+                    }
+                }
                 o[R_T] = (float)P.t;
                 o[R_DTX] = r.dtx; o[R_DTY] = r.dty; o[R_DTZ] = r.dtz;
                 o[R_GX] = r.gx; o[R_GY] = r.gy; o[R_GZ] = r.gz;
@@ -212,9 +254,16 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                 const float gry = fmaf(g.ey, s1, fmaf(r.gy, u1, -(r.dty * w1)));
                 const float grz = fmaf(g.ez, s1, fmaf(r.gz, u1, -(r.dtz * w1)));
                 const float pm = pr * g.mf;
-                const float gxv = fmaf(pm, o[R_DTGX], cR * grx);
-                const float gyv = fmaf(pm, o[R_DTGY], cR * gry);
-                const float gzv = fmaf(pm, o[R_DTGZ], cR * grz);
+                float tgx = o[R_DTGX], tgy = o[R_DTGY], tgz = o[R_DTGZ];
+                if constexpr (!ELC) {
+                    // grad T at the facet, first order in its offset
+                    tgx = fmaf(o[R_J0 + 0], g.ex, fmaf(o[R_J0 + 1], g.ey, fmaf(o[R_J0 + 2], g.ez, tgx)));
+                    tgy = fmaf(o[R_J0 + 3], g.ex, fmaf(o[R_J0 + 4], g.ey, fmaf(o[R_J0 + 5], g.ez, tgy)));
+                    tgz = fmaf(o[R_J0 + 6], g.ex, fmaf(o[R_J0 + 7], g.ey, fmaf(o[R_J0 + 8], g.ez, tgz)));
+                }
+                const float gxv = fmaf(pm, tgx, cR * grx);
+                const float gyv = fmaf(pm, tgy, cR * gry);
+                const float gzv = fmaf(pm, tgz, cR * grz);
                 gz_acc += gzv;
                 gvx = fmaf(tf, gxv, gvx);
                 gvy = fmaf(tf, gyv, gvy);
