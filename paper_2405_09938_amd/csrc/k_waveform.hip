@@ -3,7 +3,7 @@
 // zero-padded FFT in LDS, one workgroup per range line.
 //
 //   forward: raw[n]  = sum_m rc[m] chirp[n - m + L/2]
-//            buf = pad(rc); X = FFT(buf); Y = X * S; raw[n] = IFFT(Y)[n + L/2]
+//            buf = zero-padded rc; X = FFT(buf); Y = X * S; raw[n] = IFFT(Y)[n + L/2]
 //   adjoint: g_rc[m] = sum_n g_raw[n] conj(chirp[n - m + L/2])
 //            buf[L/2 + n] = g_raw[n]; X = FFT(buf); Y = X * conj(S);
 //            g_rc[m] = IFFT(Y)[m]
@@ -11,10 +11,15 @@
 // The inverse is taken as conj(FFT(conj(Y))), the 1/M being folded into S.
 // M >= N + L - 1 keeps both circular products free of wrap-around.
 //
-// FFT: radix-4 Stockham passes (plus one radix-2 pass when log2 M is odd),
-// in place in LDS: every pass first reads all of its butterfly inputs into
-// registers, then (after a barrier) writes all outputs.  Twiddles come from an
-// FP64-accurate table exp(-2 pi i m / M).
+// FFT: Stockham autosort passes in LDS, radix 16 while the remaining length
+// allows (three passes for M = 4096 .. 16384), then radix 4 and 2.  Each
+// thread takes whole butterflies: it reads all inputs of a pass into
+// registers, and after a barrier writes all outputs.  LDS indices are
+// swizzled (i -> i xor ((i / 32) mod 32), a permutation within each 1024
+// elements), which keeps the stride-16 writes of the first passes free of
+// bank conflicts without growing the array (M = 16384 fills 128 KB).  Twiddles come
+// from an FP64-accurate table exp(-2 pi i m / M): a radix-16 butterfly loads
+// W, W^2, W^4, W^8 and forms the other powers by at most three products.
 #include "sim_internal.h"
 
 namespace hs {
@@ -24,58 +29,145 @@ namespace {
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// -i z
+__device__ __forceinline__ float2 cmi(float2 z) { return make_float2(z.y, -z.x); }
+
+__device__ __forceinline__ int swz(int i) { return i ^ ((i >> 5) & 31); }
+
+// in-place forward 4-point DFT of (a, b, c, d)
+__device__ __forceinline__ void dft4(float2 &a, float2 &b, float2 &c, float2 &d) {
+    const float2 s0 = cadd(a, c), s1 = csub(a, c), s2 = cadd(b, d), s3 = cmi(csub(b, d));
+    a = cadd(s0, s2);
+    b = cadd(s1, s3);
+    c = csub(s0, s2);
+    d = csub(s1, s3);
+}
+
+// forward 16-point DFT in registers: v[n] -> X[k], n = n2 + 4 n1, k = k1 + 4 k2
+__device__ __forceinline__ void dft16(float2 *v) {
+    // 4-point DFTs over n1 for each n2 (inputs v[n2], v[n2+4], v[n2+8], v[n2+12])
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) dft4(v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]);
+    // now v[n2 + 4 k1] = A[n2][k1]; twiddle by W16^(n2 k1)
+    const float c1 = 0.92387953251128674f, s1 = 0.38268343236508977f, h = 0.70710678118654752f;
+    const float2 w1 = make_float2(c1, -s1), w2 = make_float2(h, -h), w3 = make_float2(s1, -c1);
+    const float2 w6 = make_float2(-h, -h), w9 = make_float2(-c1, s1);
+    v[1 + 4] = cmul(v[1 + 4], w1);
+    v[1 + 8] = cmul(v[1 + 8], w2);
+    v[1 + 12] = cmul(v[1 + 12], w3);
+    v[2 + 4] = cmul(v[2 + 4], w2);
+    v[2 + 8] = cmi(v[2 + 8]);                 // W16^4 = -i
+    v[2 + 12] = cmul(v[2 + 12], w6);
+    v[3 + 4] = cmul(v[3 + 4], w3);
+    v[3 + 8] = cmul(v[3 + 8], w6);
+    v[3 + 12] = cmul(v[3 + 12], w9);
+    // 4-point DFTs over n2 for each k1: X[k1 + 4 k2]
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) dft4(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+    // v[4 k1 + k2] = X[k1 + 4 k2]: transpose to natural order
+    float2 t[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) t[k1 + 4 * k2] = v[4 * k1 + k2];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = t[i];
+}
 
 template <int M, int NT>
 __device__ void fft_lds(float2 *buf, const float2 *__restrict__ tw) {
     int ns = 1;
+    // radix-16 passes
+#pragma unroll 1
+    for (; ns * 16 <= M; ns *= 16) {
+        constexpr int NB = (M / 16 + NT - 1) / NT;
+        float2 v[NB][16];
+#pragma unroll
+        for (int bb = 0; bb < NB; ++bb) {
+            const int j = threadIdx.x + bb * NT;
+            if (j < M / 16) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) v[bb][r] = buf[swz(j + r * (M / 16))];
+            }
+        }
+        __syncthreads();
+        const int step = M / (16 * ns);
+#pragma unroll
+        for (int bb = 0; bb < NB; ++bb) {
+            const int j = threadIdx.x + bb * NT;
+            if (j < M / 16) {
+                const int k = j & (ns - 1);
+                if (ns > 1) {
+                    const float2 w1 = tw[k * step], w2 = tw[2 * k * step];
+                    const float2 w4 = tw[4 * k * step], w8 = tw[8 * k * step];
+                    const float2 w3 = cmul(w1, w2), w5 = cmul(w1, w4), w6 = cmul(w2, w4);
+                    const float2 w7 = cmul(w3, w4);
+                    const float2 w[16] = {make_float2(1.f, 0.f), w1, w2, w3, w4, w5, w6, w7, w8,
+                                          cmul(w1, w8), cmul(w2, w8), cmul(w3, w8), cmul(w4, w8),
+                                          cmul(w5, w8), cmul(w6, w8), cmul(w7, w8)};
+#pragma unroll
+                    for (int r = 1; r < 16; ++r) v[bb][r] = cmul(v[bb][r], w[r]);
+                }
+                dft16(v[bb]);
+                const int base = (j - k) * 16 + k;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) buf[swz(base + r * ns)] = v[bb][r];
+            }
+        }
+        __syncthreads();
+    }
+    // radix-4 passes
 #pragma unroll 1
     for (; ns * 4 <= M; ns *= 4) {
-        constexpr int NB = M / 4 / NT;
+        constexpr int NB = (M / 4 + NT - 1) / NT;
         float2 v[NB][4];
 #pragma unroll
         for (int bb = 0; bb < NB; ++bb) {
             const int j = threadIdx.x + bb * NT;
+            if (j < M / 4) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) v[bb][r] = buf[j + r * (M / 4)];
+                for (int r = 0; r < 4; ++r) v[bb][r] = buf[swz(j + r * (M / 4))];
+            }
         }
         __syncthreads();
         const int step = M / (4 * ns);
 #pragma unroll
         for (int bb = 0; bb < NB; ++bb) {
             const int j = threadIdx.x + bb * NT;
-            const int k = j & (ns - 1);
-            const float2 x0 = v[bb][0];
-            const float2 x1 = cmul(v[bb][1], tw[k * step]);
-            const float2 x2 = cmul(v[bb][2], tw[2 * k * step]);
-            const float2 x3 = cmul(v[bb][3], tw[3 * k * step]);
-            const float2 a0 = make_float2(x0.x + x2.x, x0.y + x2.y);
-            const float2 a1 = make_float2(x0.x - x2.x, x0.y - x2.y);
-            const float2 a2 = make_float2(x1.x + x3.x, x1.y + x3.y);
-            const float2 a3 = make_float2(x1.y - x3.y, x3.x - x1.x);   // -i (x1 - x3)
-            const int base = (j - k) * 4 + k;
-            buf[base] = make_float2(a0.x + a2.x, a0.y + a2.y);
-            buf[base + ns] = make_float2(a1.x + a3.x, a1.y + a3.y);
-            buf[base + 2 * ns] = make_float2(a0.x - a2.x, a0.y - a2.y);
-            buf[base + 3 * ns] = make_float2(a1.x - a3.x, a1.y - a3.y);
+            if (j < M / 4) {
+                const int k = j & (ns - 1);
+                float2 x0 = v[bb][0];
+                float2 x1 = cmul(v[bb][1], tw[k * step]);
+                float2 x2 = cmul(v[bb][2], tw[2 * k * step]);
+                float2 x3 = cmul(v[bb][3], tw[3 * k * step]);
+                dft4(x0, x1, x2, x3);
+                const int base = (j - k) * 4 + k;
+                buf[swz(base)] = x0;
+                buf[swz(base + ns)] = x1;
+                buf[swz(base + 2 * ns)] = x2;
+                buf[swz(base + 3 * ns)] = x3;
+            }
         }
         __syncthreads();
     }
     if (ns < M) {   // one radix-2 pass, ns = M / 2
-        constexpr int NB = M / 2 / NT;
+        constexpr int NB = (M / 2 + NT - 1) / NT;
         float2 v[NB][2];
 #pragma unroll
         for (int bb = 0; bb < NB; ++bb) {
             const int j = threadIdx.x + bb * NT;
-            v[bb][0] = buf[j];
-            v[bb][1] = buf[j + M / 2];
+            v[bb][0] = buf[swz(j)];
+            v[bb][1] = buf[swz(j + M / 2)];
         }
         __syncthreads();
 #pragma unroll
         for (int bb = 0; bb < NB; ++bb) {
             const int j = threadIdx.x + bb * NT;     // k = j, since j < ns
             const float2 x1 = cmul(v[bb][1], tw[j]);
-            buf[j] = make_float2(v[bb][0].x + x1.x, v[bb][0].y + x1.y);
-            buf[j + M / 2] = make_float2(v[bb][0].x - x1.x, v[bb][0].y - x1.y);
+            buf[swz(j)] = cadd(v[bb][0], x1);
+            buf[swz(j + M / 2)] = csub(v[bb][0], x1);
         }
         __syncthreads();
     }
@@ -91,20 +183,20 @@ __global__ __launch_bounds__(NT) void k_waveform(const float2 *in, float2 *out, 
     float2 *dst = out + line * N;
     for (int i = threadIdx.x; i < M; i += NT) {
         const int m = adjoint ? i - shift : i;
-        buf[i] = (m >= 0 && m < N) ? src[m] : make_float2(0.f, 0.f);
+        buf[swz(i)] = (m >= 0 && m < N) ? src[m] : make_float2(0.f, 0.f);
     }
     __syncthreads();
     fft_lds<M, NT>(buf, tw);
     for (int i = threadIdx.x; i < M; i += NT) {
         float2 s = spec[i];
         if (adjoint) s.y = -s.y;
-        const float2 y = cmul(buf[i], s);
-        buf[i] = make_float2(y.x, -y.y);          // conj for the inverse transform
+        const float2 y = cmul(buf[swz(i)], s);
+        buf[swz(i)] = make_float2(y.x, -y.y);          // conj for the inverse transform
     }
     __syncthreads();
     fft_lds<M, NT>(buf, tw);
     for (int n = threadIdx.x; n < N; n += NT) {
-        const float2 v = buf[adjoint ? n : n + shift];
+        const float2 v = buf[swz(adjoint ? n : n + shift)];
         dst[n] = make_float2(v.x, -v.y);
     }
 }
@@ -123,10 +215,10 @@ hipError_t launch_waveform(const float *in, float *out, long long n_lines, int N
     switch (M) {
         case 256: hipLaunchKernelGGL((k_waveform<256, 64>), grid, dim3(64), 0, s, i2, o2, N, shift, s2, t2, adjoint); break;
         case 512: hipLaunchKernelGGL((k_waveform<512, 64>), grid, dim3(64), 0, s, i2, o2, N, shift, s2, t2, adjoint); break;
-        case 1024: hipLaunchKernelGGL((k_waveform<1024, 128>), grid, dim3(128), 0, s, i2, o2, N, shift, s2, t2, adjoint); break;
+        case 1024: hipLaunchKernelGGL((k_waveform<1024, 64>), grid, dim3(64), 0, s, i2, o2, N, shift, s2, t2, adjoint); break;
         case 2048: hipLaunchKernelGGL((k_waveform<2048, 128>), grid, dim3(128), 0, s, i2, o2, N, shift, s2, t2, adjoint); break;
         case 4096: hipLaunchKernelGGL((k_waveform<4096, 256>), grid, dim3(256), 0, s, i2, o2, N, shift, s2, t2, adjoint); break;
-        case 8192: hipLaunchKernelGGL((k_waveform<8192, 256>), grid, dim3(256), 0, s, i2, o2, N, shift, s2, t2, adjoint); break;
+        case 8192: hipLaunchKernelGGL((k_waveform<8192, 512>), grid, dim3(512), 0, s, i2, o2, N, shift, s2, t2, adjoint); break;
         case 16384: hipLaunchKernelGGL((k_waveform<16384, 512>), grid, dim3(512), 0, s, i2, o2, N, shift, s2, t2, adjoint); break;
         default: return hipErrorInvalidValue;
     }

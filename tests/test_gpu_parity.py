@@ -177,6 +177,25 @@ def test_waveform_and_adjoint(torch_cuda, hs):
     assert e3 < 1e-5
 
 
+def test_waveform_every_fft_size(torch_cuda, hs):
+    """Every FFT length the library instantiates, M = 256 .. 16384 (each pass
+    sequence: radix 16 only, 16 + 2, 16 + 4), forward and adjoint."""
+    torch = torch_cuda
+    say("case: waveform FFT sizes 256 .. 16384")
+    for N, T in ((64, 2e-6), (256, 2e-6), (512, 4e-6), (1024, 8e-6), (2048, 8e-6),
+                 (4096, 40e-6), (8192, 40e-6)):
+        g = replace(W.harmony_geometry(2, N, chirp=True), chirp_T=T)
+        sim = hs.Simulator(g)
+        rng = np.random.default_rng(N + 7)
+        x = (rng.standard_normal((1, 2, N)) + 1j * rng.standard_normal((1, 2, N))).astype(np.complex64)
+        xd = torch.from_numpy(x).cuda()
+        e1 = O.rel_l2(sim.apply_waveform(xd).cpu().numpy(), O.waveform_fft(g, x.astype(np.complex128)))
+        e2 = O.rel_l2(sim.apply_waveform(xd, adjoint=True).cpu().numpy(),
+                      O.waveform_adjoint_fft(g, x.astype(np.complex128)))
+        say(f"N={N} L={sim.chirp_len} M={sim.fft_len}: waveform {e1:.3e}, adjoint {e2:.3e}")
+        assert e1 < 1e-5 and e2 < 1e-5, sim.fft_len
+
+
 def test_generator_matches_oracle(torch_cuda, hs):
     torch = torch_cuda
     say("case: facet generator, flat and wave seas, sub-rectangle")
