@@ -7,7 +7,9 @@ facet generation on the device (Philox + linear waves), the range-binned
 block sort (plan), the fused forward sum and the per-pulse chirp
 convolution.  `value` is whole-job forward throughput in G facet-pulse
 contributions per second (facets x pulses x channels per step / step time),
-with every input generated in HBM inside the step.  A second timed loop of K
+with every input generated in HBM inside the step.  Consecutive steps are
+pipelined: step i+1's generation and plan run on a side stream while step
+i's sum runs; every step still does all of its work.  A second timed loop of K
 forward+adjoint steps (loss ||raw - T||^2 against a target from a perturbed
 current, chirp adjoint, adjoint sum) gives `fwd_adj`.
 
@@ -105,8 +107,21 @@ def main():
 
     fwd_ev = []
     streamed = bool(wl.chunks)
+    # Consecutive steps are pipelined: the scene generation and plan of step
+    # i + 1 run on a side stream (default priority) while step i's sum runs,
+    # so the plan's host synchronisations do not idle the GPU.  Every step
+    # still does all of its work.
+    side = torch.cuda.Stream(device=dev)
 
-    def fwd_step(record=False):
+    def prepare():
+        with torch.cuda.stream(side):
+            f = sim.generate(sea, wl.seed)
+            plan = sim.plan(f["x"], f["y"], wl.block_edge)
+        for v in f.values():
+            v.record_stream(stream)
+        return f, plan
+
+    def fwd_step(record=False, prep=None):
         if record:
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         if streamed:
@@ -116,8 +131,8 @@ def main():
             rc = sim.stream_forward(sea, wl.seed, wl.chunks, wl.block_edge)
             f = plan = None
         else:
-            f = sim.generate(sea, wl.seed)
-            plan = sim.plan(f["x"], f["y"], wl.block_edge)
+            f, plan = prep if prep is not None else prepare()
+            stream.wait_stream(side)
             if record:
                 e0.record(stream)
             rc = sim.forward(plan, f)
@@ -127,16 +142,25 @@ def main():
         out = sim.apply_waveform(rc, out=rc) if chirp else rc
         return f, plan, out
 
+    def fwd_steps(n, record=False):
+        res = None
+        nxt = None if streamed else prepare()
+        for i in range(n):
+            cur, nxt = nxt, None
+            res = fwd_step(record, cur)
+            if not streamed and i + 1 < n:
+                nxt = prepare()
+            if streamed:
+                torch.cuda.synchronize()
+                print(f"  forward step {i} done", flush=True)
+        return res
+
     print(f"workload {wl.name}: {contrib:.3e} contributions per step", flush=True)
-    for _ in range(args.warmup):
-        fwd_step()
+    if args.warmup:
+        fwd_steps(args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        f, plan, out = fwd_step(record=True)
-        if streamed:
-            torch.cuda.synchronize()
-            print(f"  forward step {i} done", flush=True)
+    f, plan, out = fwd_steps(args.steps, record=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     step_s = (t1 - t0) / args.steps
@@ -151,7 +175,7 @@ def main():
         if streamed:
             # loss 1/2 ||raw||^2: g = raw (the adjoint's cost does not depend
             # on g); adjoint w.r.t. the facet velocities, chunk by chunk
-            def fa_step():
+            def fa_step(prep=None):
                 _, _, o = fwd_step()
                 g = sim.apply_waveform(o, adjoint=True) if chirp else o
                 return sim.stream_backward(sea, wl.seed, wl.chunks, g, wl.block_edge)
@@ -166,22 +190,29 @@ def main():
                 if chirp:
                     tgt = sim.apply_waveform(tgt, out=tgt)
 
-            def fa_step():
-                f2, plan2, o = fwd_step()
+            def fa_step(prep=None):
+                f2, plan2, o = fwd_step(prep=prep)
                 g = 2.0 * (o - tgt)
                 if chirp:
                     g = sim.apply_waveform(g, out=g, adjoint=True)
                 return sim.backward(plan2, f2, g)
 
-        for _ in range(args.warmup):
-            fa_step()
+        def fa_steps(n):
+            nxt = None if streamed else prepare()
+            for i in range(n):
+                cur, nxt = nxt, None
+                fa_step(cur)
+                if not streamed and i + 1 < n:
+                    nxt = prepare()
+                if streamed:
+                    torch.cuda.synchronize()
+                    print(f"  forward+adjoint step {i} done", flush=True)
+
+        if args.warmup:
+            fa_steps(args.warmup)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        for i in range(args.steps):
-            fa_step()
-            if streamed:
-                torch.cuda.synchronize()
-                print(f"  forward+adjoint step {i} done", flush=True)
+        fa_steps(args.steps)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         fa_s = (t3 - t2) / args.steps

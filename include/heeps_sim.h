@@ -171,7 +171,9 @@ typedef struct {
  */
 int sim_create(const sim_config *cfg, sim_handle **out);
 
-/* Release a handle and its device tables.  NULL is ignored. */
+/* Release a handle and its device tables.  NULL is ignored.  If plans of
+ * the handle are still alive, the handle is released when the last of them
+ * is destroyed (sim_plan_destroy). */
 void sim_destroy(sim_handle *h);
 
 /* Thread-local text of the last error ("" if none). */
@@ -207,7 +209,12 @@ int sim_waveform_info(const sim_handle *h, int *chirp_len, int *fft_len);
 int sim_plan_create(sim_handle *h, const float *x, const float *y, long long n,
                     double block_edge, void *stream, sim_plan **out);
 
-/* Release a plan.  NULL is ignored. */
+/* Release a plan.  NULL is ignored.  Its device buffers go back to the
+ * handle, which reuses them for later plans: the stream of a later
+ * sim_plan_create waits, on the device, for the last work of this plan on
+ * every stream that used it (events recorded by each call), so destroying a
+ * plan does not synchronise and never lets a later plan overwrite data a
+ * pending kernel still reads.  At most 16 buffers are kept. */
 void sim_plan_destroy(sim_plan *plan);
 
 /* Host outputs: number of facets, blocks and patches of a plan. */

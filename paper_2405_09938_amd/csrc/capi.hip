@@ -300,6 +300,73 @@ double elevation_bound(const sim_handle *h, const float box[4], double e_max) {
     return worst;
 }
 
+// Plan buffers: from the handle's pool when one is large enough (the stream
+// then waits, on the device, for the work that used it under its previous
+// plan), otherwise from hipMalloc.
+template <typename T>
+hipError_t plan_alloc(sim_handle *h, T **p, size_t count, size_t *cap, hipStream_t s) {
+    const size_t bytes = sizeof(T) * (count > 0 ? count : 1);
+    auto &pool = h->plan_pool;
+    size_t best = pool.size();
+    for (size_t i = 0; i < pool.size(); ++i)
+        if (pool[i].bytes >= bytes && (best == pool.size() || pool[i].bytes < pool[best].bytes))
+            best = i;
+    if (best < pool.size()) {
+        for (hipEvent_t ev : *pool[best].after) {
+            hipError_t e = hipStreamWaitEvent(s, ev, 0);
+            if (e != hipSuccess) return e;
+        }
+        *p = (T *)pool[best].p;
+        *cap = pool[best].bytes;
+        pool.erase(pool.begin() + (long)best);
+        return hipSuccess;
+    }
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return e;
+    }
+    *p = (T *)q;
+    *cap = bytes;
+    return hipSuccess;
+}
+
+// Record, on stream s, the end of the work just enqueued on the plan's
+// buffers (one event per stream, re-recorded at each use).  UseGuard does it
+// when a call returns, whatever path it returns by.
+void note_use(sim_plan *P, hipStream_t s) {
+    for (auto &u : P->uses)
+        if (u.first == s) {
+            if (hipEventRecord(u.second, s) != hipSuccess) P->uses_ok = false;
+            return;
+        }
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        P->uses_ok = false;
+        return;
+    }
+    if (hipEventRecord(ev, s) != hipSuccess) P->uses_ok = false;
+    P->uses.emplace_back(s, ev);
+}
+
+struct UseGuard {
+    sim_plan *P;
+    hipStream_t s;
+    ~UseGuard() { note_use(P, s); }
+};
+
+void release_handle(sim_handle *h) {
+    if (h->pulses_d) (void)hipFree(h->pulses_d);
+    if (h->chirp_spec_d) (void)hipFree(h->chirp_spec_d);
+    if (h->twiddle_d) (void)hipFree(h->twiddle_d);
+    if (h->gen_tab_d) (void)hipFree(h->gen_tab_d);
+    for (auto &b : h->scratch_pool) (void)hipFree(b.first);
+    for (auto &b : h->plan_pool) (void)hipFree(b.p);   // hipFree waits for the device
+    h->plan_pool.clear();
+    delete h;
+}
+
 // Device tables are uploaded on the first call that needs the GPU, on the
 // device current at that time; later calls must run on the same device.
 int ensure_device(sim_handle *h) {
@@ -511,12 +578,11 @@ int sim_create(const sim_config *cfg, sim_handle **out) {
 
 void sim_destroy(sim_handle *h) {
     if (!h) return;
-    if (h->pulses_d) (void)hipFree(h->pulses_d);
-    if (h->chirp_spec_d) (void)hipFree(h->chirp_spec_d);
-    if (h->twiddle_d) (void)hipFree(h->twiddle_d);
-    if (h->gen_tab_d) (void)hipFree(h->gen_tab_d);
-    for (auto &b : h->scratch_pool) (void)hipFree(b.first);
-    delete h;
+    if (h->live_plans > 0) {   // freed when its last plan is destroyed
+        h->destroy_pending = true;
+        return;
+    }
+    release_handle(h);
 }
 
 int sim_pulse_info(const sim_handle *h, int ch, int p0, int np, double *t, double *tau_ref) {
@@ -645,6 +711,7 @@ int sim_plan_create(sim_handle *h, const float *x, const float *y, long long n,
     sim_plan *P = new (std::nothrow) sim_plan();
     if (!P) HS_FAIL(SIM_ENOMEM, "host allocation failed");
     P->h = h;
+    ++h->live_plans;
     P->n = n;
     P->lat = L;
     P->n_patches = n_patches;
@@ -655,14 +722,16 @@ int sim_plan_create(sim_handle *h, const float *x, const float *y, long long n,
     P->el_bound = elevation_bound(h, box, 0.5 * std::sqrt(2.0) * block_edge + 4.0 + 2.5 * tmax);
     P->el_const = P->el_bound <= HEEPS_EL_CONST_TOL;
     auto fail = [&](int code, const std::string &msg) {
+        P->uses_ok = false;   // kernels may still use the buffers: free them
         sim_plan_destroy(P);
         hs::set_error(msg);
         return code;
     };
     hipError_t e = hipSuccess;
-    if ((e = dalloc(&P->perm, n)) != hipSuccess ||
-        (e = dalloc(&P->patch_first, n_patches + 1)) != hipSuccess ||
-        (e = dalloc(&P->sorted, n + 1)) != hipSuccess)
+    if ((e = plan_alloc(h, &P->perm, n, &P->perm_cap, s)) != hipSuccess ||
+        (e = plan_alloc(h, &P->patch_first, n_patches + 1, &P->patch_first_cap, s)) !=
+            hipSuccess ||
+        (e = plan_alloc(h, &P->sorted, n + 1, &P->sorted_cap, s)) != hipSuccess)
         return fail(SIM_ENOMEM, std::string("plan alloc: ") + hipGetErrorString(e));
     if ((e = hs::launch_fill_zero((float *)count, n_keys, s)) != hipSuccess ||
         (e = hs::launch_fill_zero((float *)(P->sorted + n), 8, s)) != hipSuccess ||
@@ -678,7 +747,7 @@ int sim_plan_create(sim_handle *h, const float *x, const float *y, long long n,
         (e = hipStreamSynchronize(s)) != hipSuccess)
         return fail(SIM_EHIP, std::string("plan sync: ") + hipGetErrorString(e));
     P->n_blocks = nb_total;
-    if ((e = dalloc(&P->blocks, (size_t)nb_total)) != hipSuccess)
+    if ((e = plan_alloc(h, &P->blocks, (size_t)nb_total, &P->blocks_cap, s)) != hipSuccess)
         return fail(SIM_ENOMEM, std::string("plan alloc: ") + hipGetErrorString(e));
     if ((e = hs::launch_make_blocks(count, offset, blk_offset, n_keys, L, P->blocks, s)) !=
             hipSuccess ||
@@ -687,17 +756,46 @@ int sim_plan_create(sim_handle *h, const float *x, const float *y, long long n,
         (e = hipStreamSynchronize(s)) != hipSuccess)
         return fail(SIM_EHIP, std::string("plan blocks: ") + hipGetErrorString(e));
     tmp.done();
+    note_use(P, s);
     *out = P;
     return SIM_OK;
 }
 
 void sim_plan_destroy(sim_plan *P) {
     if (!P) return;
-    if (P->perm) (void)hipFree(P->perm);
-    if (P->blocks) (void)hipFree(P->blocks);
-    if (P->patch_first) (void)hipFree(P->patch_first);
-    if (P->sorted) (void)hipFree(P->sorted);
+    sim_handle *h = P->h;
+    // The buffers go back to the handle's pool with the events that mark
+    // their last use on every stream; a later plan's stream waits for them.
+    // If a use could not be recorded, the buffers are freed instead (hipFree
+    // waits for the device).
+    std::shared_ptr<std::vector<hipEvent_t>> keep(new std::vector<hipEvent_t>(),
+                                                  [](std::vector<hipEvent_t> *v) {
+                                                      for (hipEvent_t ev : *v)
+                                                          (void)hipEventDestroy(ev);
+                                                      delete v;
+                                                  });
+    for (auto &u : P->uses) keep->push_back(u.second);
+    if (!P->uses_ok) keep.reset();
+    const std::pair<void *, size_t> bufs[4] = {{P->perm, P->perm_cap},
+                                               {P->blocks, P->blocks_cap},
+                                               {P->patch_first, P->patch_first_cap},
+                                               {P->sorted, P->sorted_cap}};
+    for (const auto &b : bufs) {
+        if (!b.first) continue;
+        if (keep) h->plan_pool.push_back({b.first, b.second, keep});
+        else (void)hipFree(b.first);
+    }
+    // keep the pool small: free the smallest buffers beyond 16
+    auto &pool = h->plan_pool;
+    while (pool.size() > 16) {
+        size_t k = 0;
+        for (size_t i = 1; i < pool.size(); ++i)
+            if (pool[i].bytes < pool[k].bytes) k = i;
+        (void)hipFree(pool[k].p);
+        pool.erase(pool.begin() + (long)k);
+    }
     delete P;
+    if (--h->live_plans == 0 && h->destroy_pending) release_handle(h);
 }
 
 int sim_plan_info(const sim_plan *P, long long *n_facets, long long *n_blocks,
@@ -803,6 +901,7 @@ int sim_forward(sim_handle *h, sim_plan *P, const sim_facets *f, int p0, int np,
     if (!iq) HS_FAIL(SIM_EINVAL, "iq is NULL");
     if (int rc = ensure_device(h)) return rc;
     hipStream_t s = (hipStream_t)stream;
+    UseGuard use{P, s};
     HS_HIP(hs::launch_gather(*f, P->perm, P->blocks, P->n_blocks, P->sorted, s), "gather");
     if (!accumulate)
         HS_HIP(hs::launch_fill_zero(iq, 2LL * h->C * np * h->N, s), "zero iq");
@@ -851,6 +950,7 @@ int sim_backward(sim_handle *h, sim_plan *P, const sim_facets *f, int p0, int np
         }
         return SIM_OK;
     }
+    UseGuard use{P, s};
     HS_HIP(hs::launch_gather(*f, P->perm, P->blocks, P->n_blocks, P->sorted, s), "gather");
     hs::AdjArgs a{};
     a.facets = P->sorted;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <utility>
 #include <vector>
@@ -141,6 +142,17 @@ struct sim_handle {
     std::vector<double> gen_tab_h;
     // device buffers reused by sim_plan_create for its temporaries
     std::vector<std::pair<void *, size_t>> scratch_pool;
+    // device buffers of destroyed plans, reusable by later plans once the
+    // events recorded at their destruction (on every stream that read them)
+    // have completed; a later plan's stream waits for those events
+    struct PooledBuf {
+        void *p;
+        size_t bytes;
+        std::shared_ptr<std::vector<hipEvent_t>> after;
+    };
+    std::vector<PooledBuf> plan_pool;
+    int live_plans = 0;          // plans not yet destroyed
+    bool destroy_pending = false;   // sim_destroy called while plans were alive
 };
 
 struct sim_plan {
@@ -157,6 +169,11 @@ struct sim_plan {
     hs::BlockRec *blocks = nullptr;     // [n_blocks]
     int *patch_first = nullptr;  // [n_patches + 1]
     hs::FacetRec *sorted = nullptr;     // [n] scratch refreshed by each call
+    // byte capacity of each buffer (they may come from the handle's pool)
+    size_t perm_cap = 0, blocks_cap = 0, patch_first_cap = 0, sorted_cap = 0;
+    // per stream that used the buffers, an event recorded after its last use
+    std::vector<std::pair<hipStream_t, hipEvent_t>> uses;
+    bool uses_ok = true;         // every use could be recorded
 };
 
 // ---- launchers (each returns hipError_t of the launch) --------------------
