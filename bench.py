@@ -9,7 +9,8 @@ convolution.  `value` is whole-job forward throughput in G facet-pulse
 contributions per second (facets x pulses x channels per step / step time),
 with every input generated in HBM inside the step.  Consecutive steps are
 pipelined: step i+1's generation and plan run on a side stream while step
-i's sum runs; every step still does all of its work.  A second timed loop of K
+i's sum runs, and step i's chirp convolution runs on a third stream beside
+step i+1's sum; every step still does all of its work.  A second timed loop of K
 forward+adjoint steps (loss ||raw - T||^2 against a target from a perturbed
 current, chirp adjoint, adjoint sum) gives `fwd_adj`.
 
@@ -112,6 +113,9 @@ def main():
     # so the plan's host synchronisations do not idle the GPU.  Every step
     # still does all of its work.
     side = torch.cuda.Stream(device=dev)
+    # the chirp convolution of step i runs on its own stream, beside step
+    # i+1's sum (the sum of step i+1 writes a fresh IQ buffer)
+    wave = torch.cuda.Stream(device=dev)
 
     def prepare():
         with torch.cuda.stream(side):
@@ -121,7 +125,7 @@ def main():
             v.record_stream(stream)
         return f, plan
 
-    def fwd_step(record=False, prep=None):
+    def fwd_step(record=False, prep=None, overlap=False):
         if record:
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         if streamed:
@@ -139,7 +143,13 @@ def main():
         if record:
             e1.record(stream)
             fwd_ev.append((e0, e1))
-        out = sim.apply_waveform(rc, out=rc) if chirp else rc
+        if chirp and overlap and not streamed:
+            wave.wait_stream(stream)
+            with torch.cuda.stream(wave):
+                out = sim.apply_waveform(rc, out=rc)
+            rc.record_stream(wave)
+        else:
+            out = sim.apply_waveform(rc, out=rc) if chirp else rc
         return f, plan, out
 
     def fwd_steps(n, record=False):
@@ -147,7 +157,7 @@ def main():
         nxt = None if streamed else prepare()
         for i in range(n):
             cur, nxt = nxt, None
-            res = fwd_step(record, cur)
+            res = fwd_step(record, cur, overlap=True)
             if not streamed and i + 1 < n:
                 nxt = prepare()
             if streamed:
