@@ -40,10 +40,6 @@ __device__ __forceinline__ float dsinc_f(float x) {
     return (fabsf(x) < 1e-6f) ? 0.0f : r;
 }
 
-__device__ __forceinline__ float poly3(const float *c, float y) {
-    return fmaf(fmaf(fmaf(c[3], y, c[2]), y, c[1]), y, c[0]);
-}
-
 // Per-(block, pulse) references of one lane (FP64 -> FP32).
 struct Refs {
     float dtx, dty, dtz;            // unit vector Tx -> block centre
@@ -234,51 +230,12 @@ __device__ __forceinline__ void facet_geo(const Refs &r, const FacetConsts &cc, 
     o.ar = ar;
 }
 
-// Leading tap coefficients held in VGPRs: a VALU instruction reads at most
-// one SGPR, so keeping c[3] in a vector register lets the first Horner step
-// read c[2] from its SGPR without an extra move.
-struct TapTop {
-    float e3[4], o3[4];
-};
-
+// A uniform value copied into a VGPR (a VALU instruction reads at most one
+// SGPR operand on gfx9, so coefficients kept in VGPRs cost no extra moves).
 __device__ __forceinline__ float to_vgpr(float x) {
     float r;
     asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
     return r;
-}
-
-__device__ __forceinline__ void tap_top(const TapPoly &tp, TapTop &t) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        t.e3[j] = to_vgpr(tp.e[j][3]);
-        t.o3[j] = to_vgpr(tp.o[j][3]);
-    }
-}
-
-// The 8 taps at samples floor(u) - 3 .. floor(u) + 4 for fractional part f.
-__device__ __forceinline__ void taps8(const TapPoly &tp, float f, float *tap) {
-    const float sg = fmaf(f, 2.0f, -1.0f);
-    const float y = sg * sg;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const float e = poly3(tp.e[j], y);
-        const float od = sg * poly3(tp.o[j], y);
-        tap[4 + j] = e + od;        // sample floor(u) + 1 + j
-        tap[3 - j] = e - od;        // sample floor(u) - j
-    }
-}
-
-__device__ __forceinline__ void taps8(const TapPoly &tp, const TapTop &tt, float f, float *tap) {
-    const float sg = fmaf(f, 2.0f, -1.0f);
-    const float y = sg * sg;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const float e = fmaf(fmaf(fmaf(tt.e3[j], y, tp.e[j][2]), y, tp.e[j][1]), y, tp.e[j][0]);
-        const float od =
-            sg * fmaf(fmaf(fmaf(tt.o3[j], y, tp.o[j][2]), y, tp.o[j][1]), y, tp.o[j][0]);
-        tap[4 + j] = e + od;
-        tap[3 - j] = e - od;
-    }
 }
 
 // All tap coefficients held in VGPRs (uniform values).  Frees 32 SGPRs in
@@ -298,6 +255,7 @@ __device__ __forceinline__ void tap_all(const TapPoly &tp, TapV &t) {
         }
 }
 
+// The 8 taps at samples floor(u) - 3 .. floor(u) + 4 for fractional part f.
 __device__ __forceinline__ void taps8(const TapV &tv, float f, float *tap) {
     const float sg = fmaf(f, 2.0f, -1.0f);
     const float y = sg * sg;
@@ -316,33 +274,6 @@ __device__ __forceinline__ void taps8(const TapV &tv, float f, float *tap) {
 // together.  With Q_j = E(y) + s O(y), y = s^2, s = 2f - 1 and du = df:
 //   dQ_j/du      = 2 (O + 2 y O') + s 4 E'
 //   dQ_j(-s)/du  = s 4 E' - 2 (O + 2 y O')
-__device__ __forceinline__ void taps_d8(const TapPoly &tp, const TapTop &tt, float f, float *tap,
-                                        float *d) {
-    const float sg = fmaf(f, 2.0f, -1.0f);
-    const float y = sg * sg;
-    const float y2 = y + y, s4 = 4.0f * sg;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        float e = fmaf(tt.e3[j], y, tp.e[j][2]), de = tt.e3[j];
-        de = fmaf(de, y, e);
-        e = fmaf(e, y, tp.e[j][1]);
-        de = fmaf(de, y, e);
-        e = fmaf(e, y, tp.e[j][0]);
-        float o = fmaf(tt.o3[j], y, tp.o[j][2]), dq = tt.o3[j];
-        dq = fmaf(dq, y, o);
-        o = fmaf(o, y, tp.o[j][1]);
-        dq = fmaf(dq, y, o);
-        o = fmaf(o, y, tp.o[j][0]);
-        const float so = sg * o;
-        tap[4 + j] = e + so;
-        tap[3 - j] = e - so;
-        const float a = 2.0f * fmaf(y2, dq, o);
-        const float b = s4 * de;
-        d[4 + j] = a + b;
-        d[3 - j] = b - a;
-    }
-}
-
 __device__ __forceinline__ void taps_d8(const TapV &tv, float f, float *tap,
                                         float *d) {
     const float sg = fmaf(f, 2.0f, -1.0f);
