@@ -69,6 +69,8 @@ def main():
     ap.add_argument("--workload", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--serial", action="store_true",
+                    help="no step pipelining (one kernel at a time, for per-kernel counters)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of a known size (counter scale)")
@@ -152,13 +154,15 @@ def main():
             out = sim.apply_waveform(rc, out=rc) if chirp else rc
         return f, plan, out
 
+    pipelined = not streamed and not args.serial
+
     def fwd_steps(n, record=False):
         res = None
-        nxt = None if streamed else prepare()
+        nxt = prepare() if pipelined else None
         for i in range(n):
             cur, nxt = nxt, None
-            res = fwd_step(record, cur, overlap=True)
-            if not streamed and i + 1 < n:
+            res = fwd_step(record, cur, overlap=pipelined)
+            if pipelined and i + 1 < n:
                 nxt = prepare()
             if streamed:
                 torch.cuda.synchronize()
@@ -208,11 +212,11 @@ def main():
                 return sim.backward(plan2, f2, g)
 
         def fa_steps(n):
-            nxt = None if streamed else prepare()
+            nxt = prepare() if pipelined else None
             for i in range(n):
                 cur, nxt = nxt, None
                 fa_step(cur)
-                if not streamed and i + 1 < n:
+                if pipelined and i + 1 < n:
                     nxt = prepare()
                 if streamed:
                     torch.cuda.synchronize()
