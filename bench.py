@@ -189,7 +189,7 @@ def main():
         if streamed:
             # loss 1/2 ||raw||^2: g = raw (the adjoint's cost does not depend
             # on g); adjoint w.r.t. the facet velocities, chunk by chunk
-            def fa_step(prep=None):
+            def fa_step(prep=None, k=0):
                 _, _, o = fwd_step()
                 g = sim.apply_waveform(o, adjoint=True) if chirp else o
                 return sim.stream_backward(sea, wl.seed, wl.chunks, g, wl.block_edge)
@@ -204,7 +204,7 @@ def main():
                 if chirp:
                     tgt = sim.apply_waveform(tgt, out=tgt)
 
-            def fa_step(prep=None):
+            def fa_step(prep=None, k=0):
                 f2, plan2, o = fwd_step(prep=prep)
                 g = 2.0 * (o - tgt)
                 if chirp:
@@ -215,7 +215,7 @@ def main():
             nxt = prepare() if pipelined else None
             for i in range(n):
                 cur, nxt = nxt, None
-                fa_step(cur)
+                fa_step(cur, i)
                 if pipelined and i + 1 < n:
                     nxt = prepare()
                 if streamed:

@@ -117,3 +117,45 @@ def test_empty_pulse_range(env):
     torch.cuda.synchronize()
     for k, v in gr.items():
         assert float(v.abs().max()) == 0.0, k
+
+
+def test_plan_buffers_reused_across_streams(env):
+    """A plan destroyed while a sum that reads it is still pending on another
+    stream: the next plan of the handle reuses its buffers only after that
+    sum (the library makes the new plan's stream wait on recorded events).
+    Both sums must equal single-stream results."""
+    torch, hs = env
+    say("case: plan destroyed while its sum is pending on another stream, buffers reused")
+    g = W.harmony_geometry(256, 2048)
+    sim = hs.Simulator(g)
+    fa = dev(torch, W.iid_facets(200, 200, 1.0, seed=11))
+    fb = dev(torch, W.iid_facets(200, 200, 1.0, seed=12))
+    # references, one stream, nothing reused early
+    pa = sim.plan(fa["x"], fa["y"], 8.0)
+    ref_a = sim.forward(pa, fa).cpu().numpy()
+    pa.close()
+    pb = sim.plan(fb["x"], fb["y"], 8.0)
+    ref_b = sim.forward(pb, fb).cpu().numpy()
+    pb.close()
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs_a, outs_b = [], []
+    for rep in range(3):
+        with torch.cuda.stream(s1):
+            pa = sim.plan(fa["x"], fa["y"], 8.0)
+        s2.wait_stream(s1)
+        with torch.cuda.stream(s2):
+            ia = sim.forward(pa, fa)
+        pa.close()                      # no synchronisation: the sum on s2 may still run
+        with torch.cuda.stream(s1):
+            pb = sim.plan(fb["x"], fb["y"], 8.0)   # reuses pa's buffers
+            ib = sim.forward(pb, fb)
+        torch.cuda.synchronize()
+        pb.close()
+        outs_a.append(ia.cpu().numpy())
+        outs_b.append(ib.cpu().numpy())
+    for a, b in zip(outs_a, outs_b):
+        ea = float(np.abs(a - ref_a).max() / np.abs(ref_a).max())
+        eb = float(np.abs(b - ref_b).max() / np.abs(ref_b).max())
+        say(f"stream reuse: max rel diff a {ea:.2e}, b {eb:.2e}")
+        assert ea < 1e-5 and eb < 1e-5
