@@ -26,6 +26,18 @@
  *                                      statistical pins only
  *   og_generate_facets                 pinned (closed-form moments, dispersion,
  *                                      d(eta)/dt = w, chunk invariance)
+ *   og_speckle_anchors, og_speckle_groups
+ *                                      pinned (exact covariance of the
+ *                                      construction = the AR(1) law of eq. 10;
+ *                                      frozen and white limits)
+ *   og_speckle_draw, og_philox2x32_10  bit patterns: parity unpinned;
+ *                                      statistical pins (Exp(1) power,
+ *                                      uniform angle, avalanche)
+ *   og_forward_speckle, og_adjoint_speckle
+ *                                      pinned (lone facet closed form of
+ *                                      eq. 7, id-keeping split, row slices,
+ *                                      eq. 9 autocorrelation, dot-product
+ *                                      test, finite differences)
  */
 #include <math.h>
 #include <omp.h>
@@ -289,8 +301,10 @@ static void make_row(const og_config *g, int ch, int p, og_row *r) {
 
 /*
  * One facet's contribution to one (channel, pulse) row: eq. 3 / eq. 16.
- * Outputs the complex weight W = a * Ftx * Frx * S * exp(j*phi) and the
- * fractional sample position u of the bistatic range in the tracking window.
+ * Outputs the complex weight W = a * Ftx * Frx * S * exp(j*(phi + dphi)) and
+ * the fractional sample position u of the bistatic range in the tracking
+ * window (dphi: the intra-facet Doppler phase of eq. 7, 0 without speckle;
+ * a then carries the speckle factor x of eq. 7 as well).
  *   X = X0 + V t_p (linear facet motion over the dwell)
  *   R = |X - P_tx| + |X - P_rx|,  phi = -2 pi f0 R / c   (e^{-i K0 (r_t + r_r)})
  *   u = n_ref + (R - c tau_ref) fs / c
@@ -299,7 +313,7 @@ static void make_row(const og_config *g, int ch, int p, og_row *r) {
  */
 static void contribution(const og_config *g, const og_ctx *cx, int ch, const og_row *r,
                          const double *x0, const double *v, double are, double aim,
-                         double *wre, double *wim, double *u) {
+                         double dphi, double *wre, double *wim, double *u) {
     double X[3];
     for (int k = 0; k < 3; ++k) X[k] = x0[k] + v[k] * r->t;
     double dt[3] = {X[0] - r->ptx[0], X[1] - r->ptx[1], X[2] - r->ptx[2]};
@@ -308,7 +322,7 @@ static void contribution(const og_config *g, const og_ctx *cx, int ch, const og_
     double ft = gain(&cx->ant[g->ch_tx[ch]], r->ptx, X, NULL);
     double fr = gain(&cx->ant[g->ch_rx[ch]], r->prx, X, NULL);
     double S = (r->rt_mid * r->rr_mid) / (Rt * Rr);
-    double phi = -2.0 * OG_PI * g->f0 * R / g->c;
+    double phi = -2.0 * OG_PI * g->f0 * R / g->c + dphi;
     double amp = ft * fr * S;
     double c = cos(phi), s = sin(phi);
     *wre = amp * (are * c - aim * s);
@@ -319,11 +333,14 @@ static void contribution(const og_config *g, const og_ctx *cx, int ch, const og_
 /*
  * Forward sum: iq[c][p - p0][n] (interleaved re, im) for channels 0..n_ch-1,
  * pulses [p0, p0 + np).  Each (c, p) row is independent (parallel, no races).
- * Taps outside [0, N) are dropped.
+ * Taps outside [0, N) are dropped.  With xs != NULL, facet i's amplitude at
+ * pulse p is a_i x_i(p) (xs[i][p - p0], complex) and its phase gains
+ * 2 pi f_s,i t_p: the intra-facet speckle s(t) of eq. 7.
  */
-void og_forward(const og_config *g, long long nf, const double *x, const double *y,
-                const double *z, const double *vx, const double *vy, const double *vz,
-                const double *are, const double *aim, int p0, int np, double *iq) {
+static void forward_impl(const og_config *g, long long nf, const double *x, const double *y,
+                         const double *z, const double *vx, const double *vy,
+                         const double *vz, const double *are, const double *aim,
+                         const double *xs, const double *fs, int p0, int np, double *iq) {
     const int N = g->n_samples;
     const long long rows = (long long)g->n_ch * np;
     memset(iq, 0, sizeof(double) * 2 * (size_t)rows * (size_t)N);
@@ -337,8 +354,15 @@ void og_forward(const og_config *g, long long nf, const double *x, const double 
         double *out = iq + 2 * (size_t)row * (size_t)N;
         for (long long i = 0; i < nf; ++i) {
             double X0[3] = {x[i], y[i], z[i]}, V[3] = {vx[i], vy[i], vz[i]};
+            double ar = are[i], ai = aim[i], dphi = 0.0;
+            if (xs) {
+                const double *s = xs + 2 * ((size_t)i * (size_t)np + (size_t)(p - p0));
+                ar = are[i] * s[0] - aim[i] * s[1];
+                ai = are[i] * s[1] + aim[i] * s[0];
+                dphi = fs ? 2.0 * OG_PI * fs[i] * r.t : 0.0;
+            }
             double wre, wim, u;
-            contribution(g, &cx, ch, &r, X0, V, are[i], aim[i], &wre, &wim, &u);
+            contribution(g, &cx, ch, &r, X0, V, ar, ai, dphi, &wre, &wim, &u);
             long long n0 = (long long)floor(u);
             for (long long n = n0 - 3; n <= n0 + 4; ++n) {
                 if (n < 0 || n >= N) continue;
@@ -350,6 +374,12 @@ void og_forward(const og_config *g, long long nf, const double *x, const double 
     }
 }
 
+void og_forward(const og_config *g, long long nf, const double *x, const double *y,
+                const double *z, const double *vx, const double *vy, const double *vz,
+                const double *are, const double *aim, int p0, int np, double *iq) {
+    forward_impl(g, nf, x, y, z, vx, vy, vz, are, aim, NULL, NULL, p0, np, iq);
+}
+
 /*
  * Adjoint of og_forward with respect to facet height z, velocity V and
  * complex amplitude a.  g_iq holds dL/dRe(IQ) + j dL/dIm(IQ) in the layout of
@@ -359,15 +389,18 @@ void og_forward(const og_config *g, long long nf, const double *x, const double 
  * With B = sum_n conj(g_n) h(n - u), B' = sum_n conj(g_n) h'(n - u),
  * T = Ftx Frx S, E = exp(j phi), P = B a E:
  *   dL/da       = conj(B T E)
+ * (with speckle, a is replaced by a s and dL/da = conj(B T E s), phi
+ * including the Doppler phase; s does not depend on z, V or a)
  *   dL/dX       = Re(P) grad T + [Im(P) T K0 - Re(B' a T E) fs/c] grad R
  *   dL/dz       = sum_p (dL/dX)_z,   dL/dV = sum_p t_p dL/dX
  * where grad R = unit(X - P_tx) + unit(X - P_rx), K0 = 2 pi f0 / c.
  */
-void og_adjoint(const og_config *g, long long nf, const double *x, const double *y,
-                const double *z, const double *vx, const double *vy, const double *vz,
-                const double *are, const double *aim, int p0, int np,
-                const double *giq, double *dz, double *dvx, double *dvy,
-                double *dvz, double *dare, double *daim) {
+static void adjoint_impl(const og_config *g, long long nf, const double *x, const double *y,
+                         const double *z, const double *vx, const double *vy,
+                         const double *vz, const double *are, const double *aim,
+                         const double *xs, const double *fs, int p0, int np,
+                         const double *giq, double *dz, double *dvx, double *dvy,
+                         double *dvz, double *dare, double *daim) {
     const int N = g->n_samples;
     const int rows = g->n_ch * np;
     og_row *rw = (og_row *)malloc(sizeof(og_row) * (size_t)rows);
@@ -382,6 +415,15 @@ void og_adjoint(const og_config *g, long long nf, const double *x, const double 
         for (int row = 0; row < rows; ++row) {
             const og_row *r = &rw[row];
             int ch = row / np;
+            /* speckle factor of this pulse (1 without speckle) and Doppler phase */
+            double sr = 1.0, si = 0.0, dphi = 0.0;
+            if (xs) {
+                const double *sp = xs + 2 * ((size_t)i * (size_t)np + (size_t)(row % np));
+                sr = sp[0];
+                si = sp[1];
+                dphi = fs ? 2.0 * OG_PI * fs[i] * r->t : 0.0;
+            }
+            double ar = are[i] * sr - aim[i] * si, ai = are[i] * si + aim[i] * sr;
             double X[3];
             for (int k = 0; k < 3; ++k) X[k] = X0[k] + V[k] * r->t;
             double dt[3] = {X[0] - r->ptx[0], X[1] - r->ptx[1], X[2] - r->ptx[2]};
@@ -392,7 +434,7 @@ void og_adjoint(const og_config *g, long long nf, const double *x, const double 
             double fr = gain(&cx.ant[g->ch_rx[ch]], r->prx, X, gfr);
             double S = (r->rt_mid * r->rr_mid) / (Rt * Rr);
             double T = ft * fr * S;
-            double phi = -2.0 * OG_PI * g->f0 * R / g->c;
+            double phi = -2.0 * OG_PI * g->f0 * R / g->c + dphi;
             double Er = cos(phi), Ei = sin(phi);
             double u = (double)g->n_ref + (R - r->rref) * g->fs / g->c;
             const double *grow = giq + 2 * (size_t)row * (size_t)N;
@@ -408,12 +450,13 @@ void og_adjoint(const og_config *g, long long nf, const double *x, const double 
                 Bpr += grow[2 * n] * hp;
                 Bpi += -grow[2 * n + 1] * hp;
             }
-            /* Z = B T E ; grad_a += conj(Z) */
-            double Zr = T * (Br * Er - Bi * Ei), Zi = T * (Br * Ei + Bi * Er);
+            /* Z = B T E s ; grad_a += conj(Z) */
+            double Zr0 = T * (Br * Er - Bi * Ei), Zi0 = T * (Br * Ei + Bi * Er);
+            double Zr = Zr0 * sr - Zi0 * si, Zi = Zr0 * si + Zi0 * sr;
             gar += Zr;
             gai += -Zi;
-            /* P = B a E */
-            double aEr = are[i] * Er - aim[i] * Ei, aEi = are[i] * Ei + aim[i] * Er;
+            /* P = B a s E */
+            double aEr = ar * Er - ai * Ei, aEi = ar * Ei + ai * Er;
             double Pr = Br * aEr - Bi * aEi, Pi = Br * aEi + Bi * aEr;
             /* Re(B' a T E) */
             double BpW = T * (Bpr * aEr - Bpi * aEi);
@@ -436,6 +479,15 @@ void og_adjoint(const og_config *g, long long nf, const double *x, const double 
         daim[i] = gai;
     }
     free(rw);
+}
+
+void og_adjoint(const og_config *g, long long nf, const double *x, const double *y,
+                const double *z, const double *vx, const double *vy, const double *vz,
+                const double *are, const double *aim, int p0, int np,
+                const double *giq, double *dz, double *dvx, double *dvy,
+                double *dvz, double *dare, double *daim) {
+    adjoint_impl(g, nf, x, y, z, vx, vy, vz, are, aim, NULL, NULL, p0, np, giq, dz, dvx,
+                 dvy, dvz, dare, daim);
 }
 
 /* ---- Waveform (the impulse response is convolved by the waveform) ------ */
@@ -646,4 +698,173 @@ void og_generate_facets(const og_sea *s, uint64_t seed, int ix0, int iy0, int cn
     free(k);
     free(amp);
     free(om);
+}
+
+/* ---- Intra-facet speckle (Sec. III.A eq. 7, eq. 9, eq. 10) ------------- */
+/*
+ * Each facet's reflection coefficient carries s(t_p) = x(p) exp(j 2 pi f_s t_p)
+ * (eq. 7), with x = R + jI an order-1 autoregressive process over the pulses
+ * (eq. 10):  x(p + 1) = b x(p) + sqrt(1 - b^2) e(p + 1),  b = exp(-dt / tau_s),
+ * dt = 1 / prf.  Readings: R and I are independent with variance 1/2 each at
+ * every pulse and in every innovation e (eq. 10 prints sigma = 1/2, which
+ * would make the process decay from its unit initial power; variance 1/2
+ * keeps it stationary, E|x|^2 = 1, as eq. 9 requires at t = 0); tau_s is one
+ * value per scene (the paper interpolates it, with f_s, from sea-state tables
+ * that are not part of this work); f_s is a per-facet input; one process per
+ * facet serves every channel.
+ *
+ * How the random numbers are drawn is not stated.  Reading: the pulses are cut
+ * into groups of 64 (absolute pulse index); the process is sampled at the
+ * group starts first (anchors, eq. 10 applied over 64 pulses), then inside each
+ * group by eq. 10 pulse by pulse from its anchor, the free path being
+ * conditioned on the next anchor (Gaussian conditioning on one value):
+ *   y_0 = eta_0,   y_g = b^64 y_{g-1} + sqrt(1 - b^128) eta_g,
+ *   z_0 = y_g,     z_k = b z_{k-1} + sqrt(1 - b^2) e_{64 g + k},  k = 1..64,
+ *   x(64 g + k) = z_k + K_k (y_{g+1} - z_64),   k = 0..63,
+ *   K_k = Cov(z_k, z_64 | z_0) / Var(z_64 | z_0) = b^(64-k) (1 - b^2k) / (1 - b^128).
+ * x then has exactly the law of the sequential recursion (E[x(p) conj x(q)] =
+ * b^|p-q|), and any group can be produced without the others.  Draws are
+ * counter based (facet id, slot): the anchor draw eta_g is slot 2^31 + g, the
+ * innovation e_p (p >= 1) is slot p.
+ */
+
+/* Philox2x32-10 (Salmon et al., SC'11), the two-word member of the family:
+ * each round multiplies the first word by 0xD256D193 (32 x 32 -> 64 bits);
+ * the new first word is the high half XOR the second word XOR the key, the
+ * new second word is the low half; the key grows by 0x9E3779B9 between
+ * rounds. */
+void og_philox2x32_10(const uint32_t *ctr_in, uint32_t key, uint32_t *out) {
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) key += 0x9E3779B9u;
+        uint64_t prod = (uint64_t)0xD256D193u * (uint64_t)c0;
+        uint32_t hi = (uint32_t)(prod >> 32), lo = (uint32_t)prod;
+        c0 = hi ^ c1 ^ key;
+        c1 = lo;
+    }
+    out[0] = c0;
+    out[1] = c1;
+}
+
+/* One complex normal with E|e|^2 = 1 for (id, slot): Philox2x32-10 of
+ * counter (id, slot) under key = low ^ high word of the seed gives w0, w1;
+ * u1 = (floor(w0 / 2^9) + 1/2) 2^-23 in (0, 1), u2 = floor(w1 / 2^9) 2^-23 in
+ * [0, 1) (both exact in float32); Box-Muller: radius sqrt(-ln u1), angle
+ * 2 pi u2. */
+void og_speckle_draw(uint64_t seed, uint32_t id, uint32_t slot, double *out) {
+    uint32_t ctr[2] = {id, slot}, w[2];
+    og_philox2x32_10(ctr, (uint32_t)seed ^ (uint32_t)(seed >> 32), w);
+    double u1 = ((double)(w[0] >> 9) + 0.5) * (1.0 / 8388608.0);
+    double u2 = (double)(w[1] >> 9) * (1.0 / 8388608.0);
+    double rho = sqrt(-log(u1));
+    out[0] = rho * cos(2.0 * OG_PI * u2);
+    out[1] = rho * sin(2.0 * OG_PI * u2);
+}
+
+/* b^m with b = exp(-a), a = dt / tau_s >= 0 */
+static double spk_pow(double a, int m) { return exp(-a * (double)m); }
+
+/* bridge gain K_k; its limit k / 64 for a = 0 (frozen speckle) */
+static double spk_gain(double a, int k) {
+    if (a == 0.0) return (double)k / 64.0;
+    return spk_pow(a, 64 - k) * expm1(-2.0 * a * (double)k) / expm1(-128.0 * a);
+}
+
+/* Anchors y_0 .. y_{ng-1} from the draws eta (complex, interleaved). */
+void og_speckle_anchors(double a, int ng, const double *eta, double *y) {
+    const double b64 = spk_pow(a, 64), c64 = sqrt(-expm1(-128.0 * a));
+    for (int g = 0; g < ng; ++g) {
+        if (g == 0) {
+            y[0] = eta[0];
+            y[1] = eta[1];
+        } else {
+            y[2 * g] = b64 * y[2 * g - 2] + c64 * eta[2 * g];
+            y[2 * g + 1] = b64 * y[2 * g - 1] + c64 * eta[2 * g + 1];
+        }
+    }
+}
+
+/* x at pulses 64 g0 .. 64 g1 - 1 (complex, interleaved) from the anchors
+ * y_{g0} .. y_{g1} (g1 - g0 + 1 values) and the innovations
+ * e[64 (g - g0) + k - 1] = e_{64 g + k}, k = 1..64. */
+void og_speckle_groups(double a, int g0, int g1, const double *y, const double *e, double *x) {
+    const double b = spk_pow(a, 1), c = sqrt(-expm1(-2.0 * a));
+    for (int g = g0; g < g1; ++g) {
+        const int j = g - g0;
+        double zr[65], zi[65];
+        zr[0] = y[2 * j];
+        zi[0] = y[2 * j + 1];
+        for (int k = 1; k <= 64; ++k) {
+            const double *ek = e + 2 * (64 * (size_t)j + (size_t)(k - 1));
+            zr[k] = b * zr[k - 1] + c * ek[0];
+            zi[k] = b * zi[k - 1] + c * ek[1];
+        }
+        const double dr = y[2 * j + 2] - zr[64], di = y[2 * j + 3] - zi[64];
+        for (int k = 0; k < 64; ++k) {
+            const double K = spk_gain(a, k);
+            x[2 * (64 * (size_t)j + k)] = zr[k] + K * dr;
+            x[2 * (64 * (size_t)j + k) + 1] = zi[k] + K * di;
+        }
+    }
+}
+
+/* x(p) of facet `id` for absolute pulses [pa, pb) (complex, interleaved),
+ * a = dt / tau_s. */
+void og_speckle_series(uint64_t seed, uint32_t id, double a, int pa, int pb, double *x) {
+    if (pb <= pa) return;
+    const int g0 = pa / 64, g1 = (pb - 1) / 64 + 1;
+    double *eta = (double *)malloc(sizeof(double) * 2 * (size_t)(g1 + 1));
+    double *y = (double *)malloc(sizeof(double) * 2 * (size_t)(g1 + 1));
+    double *e = (double *)malloc(sizeof(double) * 2 * 64 * (size_t)(g1 - g0));
+    double *xg = (double *)malloc(sizeof(double) * 2 * 64 * (size_t)(g1 - g0));
+    for (int g = 0; g <= g1; ++g) og_speckle_draw(seed, id, 0x80000000u + (uint32_t)g, eta + 2 * g);
+    og_speckle_anchors(a, g1 + 1, eta, y);
+    for (int g = g0; g < g1; ++g)
+        for (int k = 1; k <= 64; ++k)
+            og_speckle_draw(seed, id, (uint32_t)(64 * g + k),
+                            e + 2 * (64 * (size_t)(g - g0) + (size_t)(k - 1)));
+    og_speckle_groups(a, g0, g1, y + 2 * g0, e, xg);
+    memcpy(x, xg + 2 * (size_t)(pa - 64 * g0), sizeof(double) * 2 * (size_t)(pb - pa));
+    free(eta);
+    free(y);
+    free(e);
+    free(xg);
+}
+
+/* dt / tau_s; tau_s = +inf freezes the speckle (a = 0) */
+static double spk_a(const og_config *g, double tau_s) { return 1.0 / (g->prf * tau_s); }
+
+static double *speckle_table(const og_config *g, long long nf, const uint32_t *ids,
+                             double tau_s, uint64_t seed, int p0, int np) {
+    double *xs = (double *)malloc(sizeof(double) * 2 * (size_t)nf * (size_t)np);
+    const double a = spk_a(g, tau_s);
+#pragma omp parallel for schedule(static)
+    for (long long i = 0; i < nf; ++i)
+        og_speckle_series(seed, ids[i], a, p0, p0 + np, xs + 2 * (size_t)i * (size_t)np);
+    return xs;
+}
+
+/* og_forward with the intra-facet speckle of eq. 7: facet i uses counter id
+ * ids[i] and intra-facet Doppler fs[i] (Hz; NULL = 0). */
+void og_forward_speckle(const og_config *g, long long nf, const double *x, const double *y,
+                        const double *z, const double *vx, const double *vy,
+                        const double *vz, const double *are, const double *aim,
+                        const uint32_t *ids, const double *fs, double tau_s, uint64_t seed,
+                        int p0, int np, double *iq) {
+    double *xs = speckle_table(g, nf, ids, tau_s, seed, p0, np);
+    forward_impl(g, nf, x, y, z, vx, vy, vz, are, aim, xs, fs, p0, np, iq);
+    free(xs);
+}
+
+/* og_adjoint of og_forward_speckle (the speckle is a fixed factor). */
+void og_adjoint_speckle(const og_config *g, long long nf, const double *x, const double *y,
+                        const double *z, const double *vx, const double *vy,
+                        const double *vz, const double *are, const double *aim,
+                        const uint32_t *ids, const double *fs, double tau_s, uint64_t seed,
+                        int p0, int np, const double *giq, double *dz, double *dvx,
+                        double *dvy, double *dvz, double *dare, double *daim) {
+    double *xs = speckle_table(g, nf, ids, tau_s, seed, p0, np);
+    adjoint_impl(g, nf, x, y, z, vx, vy, vz, are, aim, xs, fs, p0, np, giq, dz, dvx, dvy,
+                 dvz, dare, daim);
+    free(xs);
 }

@@ -94,6 +94,17 @@ def lib():
         L.og_waveform_adjoint.argtypes = [cfgp, ctypes.c_longlong, dp, dp]
         u32p = P(ctypes.c_uint32)
         L.og_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.og_philox2x32_10.argtypes = [u32p, ctypes.c_uint32, u32p]
+        L.og_speckle_draw.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, dp]
+        L.og_speckle_anchors.argtypes = [ctypes.c_double, ctypes.c_int, dp, dp]
+        L.og_speckle_groups.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_int, dp, dp, dp]
+        L.og_speckle_series.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_double,
+                                        ctypes.c_int, ctypes.c_int, dp]
+        spk_args = [u32p, dp, ctypes.c_double, ctypes.c_uint64]
+        L.og_forward_speckle.argtypes = [cfgp, ctypes.c_longlong] + [dp] * 8 + spk_args + \
+            [ctypes.c_int, ctypes.c_int, dp]
+        L.og_adjoint_speckle.argtypes = [cfgp, ctypes.c_longlong] + [dp] * 8 + spk_args + \
+            [ctypes.c_int, ctypes.c_int, dp] + [dp] * 6
         L.og_wave_table.argtypes = [P(OgSea), dp, dp, dp]
         L.og_generate_facets.argtypes = [P(OgSea), ctypes.c_uint64, ctypes.c_int,
                                          ctypes.c_int, ctypes.c_int, ctypes.c_int] + [dp] * 8
@@ -188,22 +199,46 @@ def dtap(t: float, beta: float) -> float:
     return lib().og_dtap(float(t), float(beta))
 
 
+def _speckle_args(speckle, n: int, f_s, ids):
+    """(ids uint32 [n], f_s float64 [n] or None) of a speckle description."""
+    if ids is None:
+        ids = (int(speckle.first_index) + np.arange(n, dtype=np.int64)) & 0xFFFFFFFF
+    ids = np.ascontiguousarray(ids, np.uint32)
+    assert ids.size == n
+    fs = None if f_s is None else np.ascontiguousarray(f_s, np.float64)
+    assert fs is None or fs.size == n
+    return ids, fs
+
+
 def forward(geom, facets: Dict[str, np.ndarray], p0: int = 0,
-            np_: Optional[int] = None) -> np.ndarray:
-    """Range-compressed IQ, complex128 [C, np, N], pulses [p0, p0 + np)."""
+            np_: Optional[int] = None, speckle=None, f_s=None, ids=None) -> np.ndarray:
+    """Range-compressed IQ, complex128 [C, np, N], pulses [p0, p0 + np).
+
+    speckle (workloads.Speckle, optional): intra-facet speckle of eq. 7 with
+    per-facet Doppler f_s (Hz, default 0); facet i draws with counter id
+    ids[i] (default speckle.first_index + i)."""
     np_ = geom.n_pulses - p0 if np_ is None else np_
     cfg = make_config(geom)
     arrs = _facet_arrays(facets)
     n = arrs[0].size
     out = np.zeros((geom.n_channels, np_, geom.n_samples, 2), np.float64)
-    lib().og_forward(ctypes.byref(cfg), n, *[_dptr(a) for a in arrs], p0, np_,
-                     _dptr(out))
+    if speckle is None:
+        lib().og_forward(ctypes.byref(cfg), n, *[_dptr(a) for a in arrs], p0, np_,
+                         _dptr(out))
+    else:
+        idv, fs = _speckle_args(speckle, n, f_s, ids)
+        lib().og_forward_speckle(ctypes.byref(cfg), n, *[_dptr(a) for a in arrs],
+                                 idv.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                 None if fs is None else _dptr(fs), float(speckle.tau_s),
+                                 int(speckle.seed), p0, np_, _dptr(out))
     return out[..., 0] + 1j * out[..., 1]
 
 
 def adjoint(geom, facets: Dict[str, np.ndarray], g: np.ndarray, p0: int = 0,
-            np_: Optional[int] = None) -> Dict[str, np.ndarray]:
-    """dL/d(z, vx, vy, vz, a_re, a_im) given g = dL/dRe(IQ) + j dL/dIm(IQ)."""
+            np_: Optional[int] = None, speckle=None, f_s=None,
+            ids=None) -> Dict[str, np.ndarray]:
+    """dL/d(z, vx, vy, vz, a_re, a_im) given g = dL/dRe(IQ) + j dL/dIm(IQ)
+    (speckle arguments as in ``forward``)."""
     np_ = geom.n_pulses - p0 if np_ is None else np_
     cfg = make_config(geom)
     arrs = _facet_arrays(facets)
@@ -212,8 +247,16 @@ def adjoint(geom, facets: Dict[str, np.ndarray], g: np.ndarray, p0: int = 0,
     assert g.shape == (geom.n_channels, np_, geom.n_samples)
     gi = np.ascontiguousarray(np.stack([g.real, g.imag], -1))
     outs = [np.zeros(n) for _ in range(6)]
-    lib().og_adjoint(ctypes.byref(cfg), n, *[_dptr(a) for a in arrs], p0, np_,
-                     _dptr(gi), *[_dptr(o) for o in outs])
+    if speckle is None:
+        lib().og_adjoint(ctypes.byref(cfg), n, *[_dptr(a) for a in arrs], p0, np_,
+                         _dptr(gi), *[_dptr(o) for o in outs])
+    else:
+        idv, fs = _speckle_args(speckle, n, f_s, ids)
+        lib().og_adjoint_speckle(ctypes.byref(cfg), n, *[_dptr(a) for a in arrs],
+                                 idv.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                 None if fs is None else _dptr(fs), float(speckle.tau_s),
+                                 int(speckle.seed), p0, np_, _dptr(gi),
+                                 *[_dptr(o) for o in outs])
     return dict(zip(("z", "vx", "vy", "vz", "a_re", "a_im"), outs))
 
 
@@ -280,6 +323,46 @@ def philox4x32_10(ctr, key) -> np.ndarray:
     return np.array(list(o), dtype=np.uint32)
 
 
+def philox2x32_10(ctr, key) -> np.ndarray:
+    c = (ctypes.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    o = (ctypes.c_uint32 * 2)()
+    lib().og_philox2x32_10(c, int(key) & 0xFFFFFFFF, o)
+    return np.array(list(o), dtype=np.uint32)
+
+
+def speckle_draw(seed: int, fid: int, slot: int) -> complex:
+    o = np.zeros(2)
+    lib().og_speckle_draw(int(seed), int(fid) & 0xFFFFFFFF, int(slot) & 0xFFFFFFFF, _dptr(o))
+    return complex(o[0], o[1])
+
+
+def speckle_anchors(a: float, eta: np.ndarray) -> np.ndarray:
+    """Anchors y_0.. from complex draws eta (a = dt / tau_s)."""
+    e = np.ascontiguousarray(np.stack([np.real(eta), np.imag(eta)], -1), np.float64)
+    y = np.zeros_like(e)
+    lib().og_speckle_anchors(float(a), e.shape[0], _dptr(e), _dptr(y))
+    return y[:, 0] + 1j * y[:, 1]
+
+
+def speckle_groups(a: float, g0: int, g1: int, y: np.ndarray, e: np.ndarray) -> np.ndarray:
+    """x at pulses 64 g0 .. 64 g1 - 1 from anchors y_{g0..g1} and innovations
+    e[64 (g - g0) + k - 1] = e_{64 g + k} (complex arrays)."""
+    yy = np.ascontiguousarray(np.stack([np.real(y), np.imag(y)], -1), np.float64)
+    ee = np.ascontiguousarray(np.stack([np.real(e), np.imag(e)], -1), np.float64)
+    assert yy.shape[0] == g1 - g0 + 1 and ee.shape[0] == 64 * (g1 - g0)
+    x = np.zeros((64 * (g1 - g0), 2))
+    lib().og_speckle_groups(float(a), g0, g1, _dptr(yy), _dptr(ee), _dptr(x))
+    return x[:, 0] + 1j * x[:, 1]
+
+
+def speckle_series(seed: int, fid: int, a: float, pa: int, pb: int) -> np.ndarray:
+    """x(p) of facet id `fid` for absolute pulses [pa, pb)."""
+    x = np.zeros((max(pb - pa, 0), 2))
+    if pb > pa:
+        lib().og_speckle_series(int(seed), int(fid) & 0xFFFFFFFF, float(a), pa, pb, _dptr(x))
+    return x[:, 0] + 1j * x[:, 1]
+
+
 def _make_sea(sea):
     s = OgSea()
     s.nx, s.ny, s.dx, s.dy = sea.nx, sea.ny, sea.dx, sea.dy
@@ -333,22 +416,30 @@ def loss(iq: np.ndarray, target: np.ndarray) -> float:
 
 def fd_gradient(geom, facets: Dict[str, np.ndarray], target: np.ndarray, idx: int,
                 key: str, h: float, p0: int = 0, np_: Optional[int] = None,
-                resid: Optional[np.ndarray] = None) -> float:
+                resid: Optional[np.ndarray] = None, speckle=None, f_s=None) -> float:
     """Central finite difference of L = ||IQ - target||^2 w.r.t. facets[key][idx].
 
     Uses linearity of the sum: with r = IQ - target for all facets, changing
     one facet only changes its own contribution c_i, so
     L(theta) = ||r - c_i(theta0) + c_i(theta)||^2 and each evaluation costs one
-    facet's contributions.
+    facet's contributions.  With speckle the facet keeps its own counter id
+    and Doppler.
     """
     if resid is None:
-        resid = forward(geom, facets, p0, np_) - target
+        resid = forward(geom, facets, p0, np_, speckle, f_s)
+        resid = resid - target
     one = {k: np.array([np.float64(v[idx])]) for k, v in facets.items()}
-    c0 = forward(geom, one, p0, np_)
+    kw = {}
+    if speckle is not None:
+        n = next(iter(facets.values())).size
+        ids, fs = _speckle_args(speckle, n, f_s, None)
+        kw = dict(speckle=speckle, ids=ids[idx:idx + 1],
+                  f_s=None if fs is None else fs[idx:idx + 1])
+    c0 = forward(geom, one, p0, np_, **kw)
     base = resid - c0
     vals = []
     for s in (+1.0, -1.0):
         o = {k: v.copy() for k, v in one.items()}
         o[key][0] += s * h
-        vals.append(loss(base + forward(geom, o, p0, np_), 0.0))
+        vals.append(loss(base + forward(geom, o, p0, np_, **kw), 0.0))
     return (vals[0] - vals[1]) / (2.0 * h)

@@ -46,6 +46,15 @@ SEA_HS = 2.0
 SEA_G = 9.81
 SEA_DIR_SPREAD_DEG = 25.0
 
+# Intra-facet speckle (Sec. III.A eq. 7, 10).  tau_s = 20 ms is a correlation
+# time of the order of the facet Doppler widths of C-band sea echoes (a few
+# Hz); the intra-facet Doppler is drawn around +-5.7 Hz, the frequency of the
+# first-order Bragg waves at 35 deg incidence, for waves moving towards or
+# away from the radar.
+SPECKLE_TAU_S = 0.02
+SPECKLE_FD_HZ = 5.7
+SPECKLE_FD_SPREAD_HZ = 0.5
+
 
 @dataclass(frozen=True)
 class Platform:
@@ -265,6 +274,24 @@ def workload(k: int) -> Workload:
         return Workload("cfg5_streamed_1.28e8f_16384p_8192s_3ch_chirp", g, sea,
                         seed=5, block_edge=8.0, chunks=chunks)
     raise ValueError(f"no workload {k}")
+
+
+@dataclass(frozen=True)
+class Speckle:
+    """Intra-facet speckle inputs: correlation time tau_s (s; math.inf
+    freezes the process), the Philox seed, and the counter id of facet 0
+    (facet i draws with id first_index + i)."""
+    tau_s: float = SPECKLE_TAU_S
+    seed: int = 0
+    first_index: int = 0
+
+
+def speckle_doppler(n: int, seed: int) -> np.ndarray:
+    """Per-facet intra-facet Doppler f_s (Hz, float32 [n]): +-SPECKLE_FD_HZ
+    with equal odds plus N(0, SPECKLE_FD_SPREAD_HZ^2)."""
+    rng = np.random.default_rng(seed + 7919)
+    sign = np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    return (sign * SPECKLE_FD_HZ + rng.normal(0.0, SPECKLE_FD_SPREAD_HZ, n)).astype(np.float32)
 
 
 def with_pulses(g: Geometry, n_pulses: int) -> Geometry:
