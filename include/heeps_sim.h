@@ -256,6 +256,39 @@ int sim_forward(sim_handle *h, sim_plan *plan, const sim_facets *facets, int p0,
                 int np, float *iq_rc, int accumulate, void *stream);
 
 /*
+ * Intra-facet speckle (Sec. III.A eq. 7 and eq. 10).  Each facet's amplitude
+ * at pulse p is multiplied by s(t_p) = x(p) exp(j 2 pi f_s t_p), where x is a
+ * complex order-1 autoregressive process over the pulses with unit power and
+ * correlation b^|p - q|, b = exp(-1 / (prf tau_s)) (real and imaginary parts
+ * N(0, 1/2) each; one process per facet, shared by all channels).  Random
+ * draws are Philox2x32-10 with key = low ^ high word of `seed` and counter
+ * (facet id, slot), facet id = first_index + i for facet i of the arrays
+ * (mod 2^32): so a scene split into several facet sets draws the same
+ * speckle when each set passes its own first_index.  The process is sampled
+ * at every 64th absolute pulse (anchors, eq. 10 over 64 pulses; slot 2^31 + g)
+ * and pulse by pulse in between (eq. 10; slot p), each 64-pulse stretch
+ * conditioned on its closing anchor, which keeps the law of the recursion;
+ * so any pulse sub-range gives the rows of the full range.
+ */
+typedef struct {
+    double tau_s;              /* correlation time (s), > 0; +inf freezes x */
+    unsigned long long seed;
+    long long first_index;     /* id of facet 0, >= 0 */
+    const float *f_s;          /* device float32 [n] intra-facet Doppler (Hz); NULL = 0 */
+} sim_speckle;
+
+/*
+ * sim_forward with the intra-facet speckle `speckle` (same arguments
+ * otherwise).  The plan keeps speckle buffers of (n + 1) * 16 *
+ * (ceil(n_pulses / 64) + 1) bytes from its first speckle call on.
+ * Errors as sim_forward, and SIM_EINVAL for a NULL speckle, tau_s <= 0 or NaN,
+ * or first_index < 0.
+ */
+int sim_forward_speckle(sim_handle *h, sim_plan *plan, const sim_facets *facets,
+                        const sim_speckle *speckle, int p0, int np, float *iq_rc,
+                        int accumulate, void *stream);
+
+/*
  * Convolve n_lines range lines with the chirp (the waveform convolution that
  * follows eq. 17): raw[n] = sum_m rc[m] chirp[n - m + L/2],
  * chirp[k] = exp(j pi (B/T) (k/fs - T/2)^2), k < L = round(T fs), by
@@ -280,6 +313,13 @@ int sim_apply_waveform_adjoint(sim_handle *h, const float *g_raw, float *g_rc,
 int sim_backward(sim_handle *h, sim_plan *plan, const sim_facets *facets, int p0,
                  int np, const float *g_rc, const sim_facet_grads *grads,
                  int accumulate, void *stream);
+
+/* Adjoint of sim_forward_speckle (the speckle factor does not depend on z,
+ * V or a; dL/da = conj(sum B T E s) as for sim_backward).  Arguments and
+ * errors as sim_backward and sim_forward_speckle. */
+int sim_backward_speckle(sim_handle *h, sim_plan *plan, const sim_facets *facets,
+                         const sim_speckle *speckle, int p0, int np, const float *g_rc,
+                         const sim_facet_grads *grads, int accumulate, void *stream);
 
 /*
  * Streamed forward over a large generated scene (the paper processes the scene

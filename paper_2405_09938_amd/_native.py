@@ -75,12 +75,17 @@ class SimSea(ctypes.Structure):
     ]
 
 
+class SimSpeckle(ctypes.Structure):
+    _fields_ = [("tau_s", ctypes.c_double), ("seed", ctypes.c_ulonglong),
+                ("first_index", ctypes.c_longlong), ("f_s", _fp)]
+
+
 EXPORTS = ("sim_create", "sim_destroy", "sim_last_error", "sim_pulse_info",
            "sim_waveform_info", "sim_plan_create", "sim_plan_destroy", "sim_plan_info",
            "sim_plan_mode",
            "sim_generate_facets", "sim_forward", "sim_apply_waveform",
            "sim_apply_waveform_adjoint", "sim_backward", "sim_stream_forward",
-           "sim_stream_backward")
+           "sim_stream_backward", "sim_forward_speckle", "sim_backward_speckle")
 
 _lib = None
 
@@ -121,6 +126,9 @@ def load(path: str = LIB_PATH):
     L.sim_apply_waveform.argtypes = [vp, vp, vp, ll, vp]
     L.sim_apply_waveform_adjoint.argtypes = [vp, vp, vp, ll, vp]
     L.sim_backward.argtypes = [vp, vp, P(SimFacets), i, i, vp, P(SimFacetGrads), i, vp]
+    L.sim_forward_speckle.argtypes = [vp, vp, P(SimFacets), P(SimSpeckle), i, i, vp, i, vp]
+    L.sim_backward_speckle.argtypes = [vp, vp, P(SimFacets), P(SimSpeckle), i, i, vp,
+                                       P(SimFacetGrads), i, vp]
     ip = P(ctypes.c_int)
     L.sim_stream_forward.argtypes = [vp, P(SimSea), ctypes.c_ulonglong, ip, i, ctypes.c_double,
                                      i, i, vp, i, vp]

@@ -776,10 +776,12 @@ void sim_plan_destroy(sim_plan *P) {
                                                   });
     for (auto &u : P->uses) keep->push_back(u.second);
     if (!P->uses_ok) keep.reset();
-    const std::pair<void *, size_t> bufs[4] = {{P->perm, P->perm_cap},
+    const std::pair<void *, size_t> bufs[6] = {{P->perm, P->perm_cap},
                                                {P->blocks, P->blocks_cap},
                                                {P->patch_first, P->patch_first_cap},
-                                               {P->sorted, P->sorted_cap}};
+                                               {P->sorted, P->sorted_cap},
+                                               {P->spk, P->spk_cap},
+                                               {P->anch, P->anch_cap}};
     for (const auto &b : bufs) {
         if (!b.first) continue;
         if (keep) h->plan_pool.push_back({b.first, b.second, keep});
@@ -891,21 +893,79 @@ int sim_generate_facets(sim_handle *h, const sim_sea *sea, unsigned long long se
     return SIM_OK;
 }
 
-int sim_forward(sim_handle *h, sim_plan *P, const sim_facets *f, int p0, int np, float *iq,
-                int accumulate, void *stream) {
+// ---- intra-facet speckle (Sec. III.A eq. 7, eq. 10) ------------------------
+
+static int speckle_ok(const sim_handle *h, const sim_speckle *sp) {
+    if (!sp) return SIM_OK;
+    if (!(sp->tau_s > 0.0)) HS_FAIL(SIM_EINVAL, "speckle tau_s must be > 0 (or +inf)");
+    if (sp->first_index < 0) HS_FAIL(SIM_EINVAL, "speckle first_index < 0");
+    (void)h;
+    return SIM_OK;
+}
+
+// Host constants of the speckle process for one call (FP64, then float):
+// b = exp(-a), a = 1 / (prf tau_s) (0 for tau_s = inf), the powers b^m, the
+// bridge gains K_k = b^(64-k) (1 - b^2k) / (1 - b^128) (k / 64 at a = 0) and
+// the innovation scales sqrt(1 - b^2), sqrt(1 - b^128); then the per-facet
+// records and anchors of the groups the pulse range covers.
+static int speckle_prepare(sim_handle *h, sim_plan *P, const sim_speckle *sp, int p0, int np,
+                           bool with_d, hipStream_t s, hs::SpkArgs &k) {
+    const double a = std::isinf(sp->tau_s) ? 0.0 : 1.0 / (h->prf * sp->tau_s);
+    for (int m = 0; m <= 64; ++m) k.bpow[m] = (float)std::exp(-a * m);
+    for (int j = 0; j < 64; ++j)
+        k.gain[j] = a == 0.0 ? (float)(j / 64.0)
+                             : (float)(std::exp(-a * (64 - j)) * std::expm1(-2.0 * a * j) /
+                                       std::expm1(-128.0 * a));
+    k.b1 = k.bpow[1];
+    k.b2 = k.bpow[2];
+    k.b4 = k.bpow[4];
+    k.b8 = k.bpow[8];
+    k.b64 = k.bpow[64];
+    k.c1 = (float)std::sqrt(-std::expm1(-2.0 * a));
+    k.c64 = (float)std::sqrt(-std::expm1(-128.0 * a));
+    k.key = (uint32_t)sp->seed ^ (uint32_t)(sp->seed >> 32);
+    k.n_groups = (h->Np + 63) / 64;
+    const long long n = P->n;
+    hipError_t e = hipSuccess;
+    if (!P->spk && (e = plan_alloc(h, &P->spk, (size_t)n + 1, &P->spk_cap, s)) != hipSuccess)
+        HS_FAIL(SIM_ENOMEM, std::string("speckle records: ") + hipGetErrorString(e));
+    if (!P->anch &&
+        (e = plan_alloc(h, &P->anch, ((size_t)n + 1) * (size_t)(k.n_groups + 1), &P->anch_cap,
+                        s)) != hipSuccess)
+        HS_FAIL(SIM_ENOMEM, std::string("speckle anchors: ") + hipGetErrorString(e));
+    k.rec = P->spk;
+    k.anch = P->anch;
+    hs::SpkPrep pp{};
+    pp.n = n;
+    pp.perm = P->perm;
+    pp.fs = sp->f_s;
+    pp.first_index = sp->first_index;
+    pp.g_lo = p0 >> 6;
+    pp.g_hi = (p0 + np - 1) >> 6;
+    pp.with_d = with_d;
+    HS_HIP(hs::launch_speckle_prep(pp, k, P->spk, P->anch, s), "speckle preparation");
+    return SIM_OK;
+}
+
+static int forward_common(sim_handle *h, sim_plan *P, const sim_facets *f,
+                          const sim_speckle *sp, int p0, int np, float *iq, int accumulate,
+                          void *stream) {
     if (!h || !P) HS_FAIL(SIM_EINVAL, "handle or plan is NULL");
     if (P->h != h) HS_FAIL(SIM_EINVAL, "plan belongs to another handle");
     if (int rc = facets_ok(f, P->n)) return rc;
     if (p0 < 0 || np < 0 || (long long)p0 + np > h->Np) HS_FAIL(SIM_EINVAL, "pulse range");
+    if (int rc = speckle_ok(h, sp)) return rc;
     if (np == 0) return SIM_OK;   // nothing to write (an empty IQ may have a NULL pointer)
     if (!iq) HS_FAIL(SIM_EINVAL, "iq is NULL");
     if (int rc = ensure_device(h)) return rc;
     hipStream_t s = (hipStream_t)stream;
     UseGuard use{P, s};
     HS_HIP(hs::launch_gather(*f, P->perm, P->blocks, P->n_blocks, P->sorted, s), "gather");
+    hs::FwdArgs a{};
+    if (sp)
+        if (int rc = speckle_prepare(h, P, sp, p0, np, false, s, a.spk)) return rc;
     if (!accumulate)
         HS_HIP(hs::launch_fill_zero(iq, 2LL * h->C * np * h->N, s), "zero iq");
-    hs::FwdArgs a{};
     a.facets = P->sorted;
     a.blocks = P->blocks;
     a.patch_first = P->patch_first;
@@ -927,12 +987,25 @@ int sim_forward(sim_handle *h, sim_plan *P, const sim_facets *f, int p0, int np,
     a.np = np;
     a.n_patches = (int)P->n_patches;
     a.halo = P->halo;
-    HS_HIP(hs::launch_forward(a, h->C, P->win, P->el_const, s), "forward");
+    HS_HIP(hs::launch_forward(a, h->C, P->win, P->el_const, sp != nullptr, s), "forward");
     return SIM_OK;
 }
 
-int sim_backward(sim_handle *h, sim_plan *P, const sim_facets *f, int p0, int np,
-                 const float *g, const sim_facet_grads *gr, int accumulate, void *stream) {
+int sim_forward(sim_handle *h, sim_plan *P, const sim_facets *f, int p0, int np, float *iq,
+                int accumulate, void *stream) {
+    return forward_common(h, P, f, nullptr, p0, np, iq, accumulate, stream);
+}
+
+int sim_forward_speckle(sim_handle *h, sim_plan *P, const sim_facets *f,
+                        const sim_speckle *speckle, int p0, int np, float *iq, int accumulate,
+                        void *stream) {
+    if (!speckle) HS_FAIL(SIM_EINVAL, "speckle is NULL");
+    return forward_common(h, P, f, speckle, p0, np, iq, accumulate, stream);
+}
+
+static int backward_common(sim_handle *h, sim_plan *P, const sim_facets *f,
+                           const sim_speckle *sp, int p0, int np, const float *g,
+                           const sim_facet_grads *gr, int accumulate, void *stream) {
     if (!h || !P) HS_FAIL(SIM_EINVAL, "handle or plan is NULL");
     if (P->h != h) HS_FAIL(SIM_EINVAL, "plan belongs to another handle");
     if (int rc = facets_ok(f, P->n)) return rc;
@@ -940,6 +1013,7 @@ int sim_backward(sim_handle *h, sim_plan *P, const sim_facets *f, int p0, int np
     if (!gr) HS_FAIL(SIM_EINVAL, "grads is NULL");
     if (!g && np > 0) HS_FAIL(SIM_EINVAL, "g is NULL");
     if (gr->n != P->n) HS_FAIL(SIM_EINVAL, "grads->n differs from the plan's facet count");
+    if (int rc = speckle_ok(h, sp)) return rc;
     if (int rc = ensure_device(h)) return rc;
     hipStream_t s = (hipStream_t)stream;
     if (np == 0) {
@@ -953,6 +1027,8 @@ int sim_backward(sim_handle *h, sim_plan *P, const sim_facets *f, int p0, int np
     UseGuard use{P, s};
     HS_HIP(hs::launch_gather(*f, P->perm, P->blocks, P->n_blocks, P->sorted, s), "gather");
     hs::AdjArgs a{};
+    if (sp)
+        if (int rc = speckle_prepare(h, P, sp, p0, np, true, s, a.spk)) return rc;
     a.facets = P->sorted;
     a.blocks = P->blocks;
     a.perm = P->perm;
@@ -981,8 +1057,20 @@ int sim_backward(sim_handle *h, sim_plan *P, const sim_facets *f, int p0, int np
     a.C = h->C;
     a.n_blocks = P->n_blocks;
     a.accumulate = accumulate ? 1 : 0;
-    HS_HIP(hs::launch_adjoint(a, P->el_const, s), "adjoint");
+    HS_HIP(hs::launch_adjoint(a, P->el_const, sp != nullptr, s), "adjoint");
     return SIM_OK;
+}
+
+int sim_backward(sim_handle *h, sim_plan *P, const sim_facets *f, int p0, int np,
+                 const float *g, const sim_facet_grads *gr, int accumulate, void *stream) {
+    return backward_common(h, P, f, nullptr, p0, np, g, gr, accumulate, stream);
+}
+
+int sim_backward_speckle(sim_handle *h, sim_plan *P, const sim_facets *f,
+                         const sim_speckle *speckle, int p0, int np, const float *g,
+                         const sim_facet_grads *gr, int accumulate, void *stream) {
+    if (!speckle) HS_FAIL(SIM_EINVAL, "speckle is NULL");
+    return backward_common(h, P, f, speckle, p0, np, g, gr, accumulate, stream);
 }
 
 static int waveform_common(sim_handle *h, const float *in, float *out, long long n_lines,

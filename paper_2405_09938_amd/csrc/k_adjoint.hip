@@ -26,6 +26,7 @@
 // gradient accumulates in registers over all pulses and channels and is
 // written once: no atomics, deterministic.
 #include "sim_device.h"
+#include "spk_device.h"
 
 namespace hs {
 
@@ -33,15 +34,19 @@ namespace {
 
 constexpr int kStage = 32;   // pulses per stage
 constexpr int kGW = 16;      // staged samples per pulse: centre - 7 .. centre + 8
-constexpr int kNRef = 40;    // floats per staged pulse record
 
 // staged record layout (floats)
 enum {
     R_T = 0, R_DTX, R_DTY, R_DTZ, R_GX, R_GY, R_GZ, R_I2RT, R_I2RR, R_PHIB, R_FB, R_NB,
     R_GTAZ, R_GTEL, R_GRAZ, R_GREL, R_IRT, R_IRT2, R_IRR, R_IRR2, R_SB, R_SBT, R_SBR, R_MASK,
     R_DTGX, R_DTGY, R_DTGZ, R_DBT, R_DBR, R_GRAZE, R_I2S,
-    R_J0   // 9 floats: J[i][j] = d(grad T)_i / dx_j at R_J0 + 3 i + j
+    R_J0,        // 9 floats: J[i][j] = d(grad T)_i / dx_j at R_J0 + 3 i + j
+    R_TLO = 40   // t_p - float(t_p) (speckle: the Doppler phase)
 };
+
+// floats per staged pulse record (a multiple of 4)
+template <bool SPK>
+constexpr int kNRef = SPK ? 44 : 40;
 
 // Gradient of one antenna's field pattern at the block centre (FP32 from the
 // FP64 geometry): dF/dX = ka sinc'(ka u) sinc(ke v) (az - u d)/R
@@ -86,9 +91,14 @@ __device__ __forceinline__ void grad_t(const AntArgs &ta, const AntArgs &ra, dou
     }
 }
 
-template <bool ELC>
+// SPK: the facet amplitude carries the intra-facet speckle x(p) and its phase
+// the Doppler f_s t_p (eq. 7).  Each lane follows its facet's process pulse by
+// pulse: at a group start x = y_g, then z = b z + sqrt(1 - b^2) e_p and
+// x = z + K_k D_g with (y_g, D_g) from the preparation pass.
+template <bool ELC, bool SPK>
 __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
-    __shared__ float4 refs[kStage * kNRef / 4];
+    constexpr int kNR = kNRef<SPK>;
+    __shared__ float4 refs[kStage * kNR / 4];
     __shared__ float2 gwin[kStage * kGW];
 
     // Workgroups go to the 8 XCDs round-robin by linear index; XCD x takes
@@ -108,6 +118,18 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
     TapV tv;
     tap_all(A.tp, tv);
 
+    // speckle: the lane's facet id and Doppler, its anchors, the draw scale
+    const SpkArgs &S = A.spk;
+    const long long js = blk.start + (have ? lane : 0);
+    [[maybe_unused]] SpkRec sr{};
+    [[maybe_unused]] const float4 *an = nullptr;
+    [[maybe_unused]] float l1 = 0.f;
+    if constexpr (SPK) {
+        sr = S.rec[js];
+        an = S.anch + js * (long long)(S.n_groups + 1);
+        l1 = S.c1 * S.c1 * 0.69314718055994531f;
+    }
+
     for (int c = 0; c < A.C; ++c) {
         const ChanArgs chn = A.ch[c];
         const AntArgs &ta = A.ant[chn.tx], &ra = A.ant[chn.rx];
@@ -115,6 +137,24 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
         facet_consts(ta, ra, kc);
         const PulseRec *PR = A.pulses + (size_t)c * A.Np + A.p0;
         const float *gline = A.g + 2 * (size_t)c * A.np * (size_t)A.N;
+        // speckle state: z holds the free path at the previous pulse; a call
+        // starting inside a group first runs the group's path up to there
+        [[maybe_unused]] float zr = 0.f, zi = 0.f, dxr = 0.f, dxi = 0.f;
+        if constexpr (SPK) {
+            const int k0 = A.p0 & 63, g0 = A.p0 >> 6;
+            if (k0 != 0) {
+                const float4 yd = an[g0];
+                zr = yd.x;
+                zi = yd.y;
+                dxr = yd.z;
+                dxi = yd.w;
+                for (int k = 1; k < k0; ++k) {
+                    const float2 e = spk_draw(S.key, sr.id, (uint32_t)(64 * g0 + k), l1);
+                    zr = fmaf(S.b1, zr, e.x);
+                    zi = fmaf(S.b1, zi, e.y);
+                }
+            }
+        }
         for (int ps = 0; ps < A.np; ps += kStage) {
             __syncthreads();   // previous stage fully consumed
             if (lane < kStage) {
@@ -130,7 +170,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                 float gft[3], gfr[3];
                 const float ft = ant_grad(ta, dt0, dt1, dt2, (double)r.irt, gft);
                 const float fr = ant_grad(ra, dr0, dr1, dr2, (double)r.irr, gfr);
-                float *o = rf + lane * kNRef;
+                float *o = rf + lane * kNR;
                 // spreading at the centre (r.sb also carries the sinc normalisation)
                 const float sbt = (r.mask != 0.0f || r.graze)
                                       ? (float)(chn.rtrr_mid * (double)r.irt * (double)r.irr)
@@ -161,6 +201,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                     }
                 }
                 o[R_T] = (float)P.t;
+                if constexpr (SPK) o[R_TLO] = (float)(P.t - (double)(float)P.t);
                 o[R_DTX] = r.dtx; o[R_DTY] = r.dty; o[R_DTZ] = r.dtz;
                 o[R_GX] = r.gx; o[R_GY] = r.gy; o[R_GZ] = r.gz;
                 o[R_I2RT] = r.i2rt; o[R_I2RR] = r.i2rr; o[R_I2S] = r.i2s;
@@ -177,7 +218,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
             {
                 const int row = lane >> 1, half = lane & 1;
                 const int pl = ps + row;
-                const int nb = __float_as_int(rf[row * kNRef + R_NB]);
+                const int nb = __float_as_int(rf[row * kNR + R_NB]);
                 const int base = nb - 7 + half * 8;
                 const float *gl = gline + 2 * (size_t)(pl < A.np ? pl : 0) * A.N;
 #pragma unroll
@@ -191,7 +232,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
             __syncthreads();
             const int nq = (A.np - ps) < kStage ? (A.np - ps) : kStage;
             for (int q = 0; q < nq; ++q) {
-                const float *o = rf + q * kNRef;
+                const float *o = rf + q * kNR;
                 Refs r;
                 r.dtx = o[R_DTX]; r.dty = o[R_DTY]; r.dtz = o[R_DTZ];
                 r.gx = o[R_GX]; r.gy = o[R_GY]; r.gz = o[R_GZ];
@@ -202,9 +243,31 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                 r.sb = o[R_SB]; r.sbt = o[R_SBT]; r.sbr = o[R_SBR]; r.mask = o[R_MASK];
                 r.dbt = o[R_DBT]; r.dbr = o[R_DBR]; r.graze = __float_as_int(o[R_GRAZE]);
                 const float tf = o[R_T];
+                // speckle factor x(p) of this pulse and the Doppler phase (cycles)
+                float xr = 1.0f, xi = 0.0f, dop = 0.0f;
+                if constexpr (SPK) {
+                    const int pabs = A.p0 + ps + q, k = pabs & 63;
+                    if (k == 0) {
+                        const float4 yd = an[pabs >> 6];
+                        zr = yd.x;
+                        zi = yd.y;
+                        dxr = yd.z;
+                        dxi = yd.w;
+                    } else {
+                        const float2 e = spk_draw(S.key, sr.id, (uint32_t)pabs, l1);
+                        zr = fmaf(S.b1, zr, e.x);
+                        zi = fmaf(S.b1, zi, e.y);
+                    }
+                    const float K = S.gain[k];
+                    xr = fmaf(K, dxr, zr);
+                    xi = fmaf(K, dxi, zi);
+                    const float dh = sr.fs * tf;
+                    const float dl = fmaf(sr.fs, o[R_TLO], fmaf(sr.fs, tf, -dh));
+                    dop = __builtin_amdgcn_fractf(dh) + dl;
+                }
                 Geo g;
-                facet_geo<ELC>(r, kc, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz, r.graze != 0, A.linv_hi,
-                          A.linv_lo, A.fs_cf, g);
+                facet_geo<ELC, SPK>(r, kc, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz, r.graze != 0, A.linv_hi,
+                          A.linv_lo, A.fs_cf, dop, g);
                 float tap[8], dtap[8];
                 taps_d8(tv, g.f, tap, dtap);
                 // g at samples floor(u) - 3 .. floor(u) + 4
@@ -237,9 +300,11 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                 bi = -bi;     // B = sum conj(g) h
                 di = -di;     // B_u = sum conj(g) dh/du
                 const float T = g.amp;
-                // a E
-                const float aer = fmaf(f.ar, g.cs, -(f.ai * g.sn));
-                const float aei = fmaf(f.ar, g.sn, f.ai * g.cs);
+                // a x E (x = 1 without speckle)
+                const float axr = SPK ? fmaf(f.ar, xr, -(f.ai * xi)) : f.ar;
+                const float axi = SPK ? fmaf(f.ar, xi, f.ai * xr) : f.ai;
+                const float aer = fmaf(axr, g.cs, -(axi * g.sn));
+                const float aei = fmaf(axr, g.sn, axi * g.cs);
                 // P = B a E
                 const float pr = fmaf(br, aer, -(bi * aei));
                 const float pi = fmaf(br, aei, bi * aer);
@@ -268,9 +333,15 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                 gvx = fmaf(tf, gxv, gvx);
                 gvy = fmaf(tf, gyv, gvy);
                 gvz = fmaf(tf, gzv, gvz);
-                // dL/da = conj(B T E)
-                gar = fmaf(T, fmaf(br, g.cs, -(bi * g.sn)), gar);
-                gai = fmaf(-T, fmaf(br, g.sn, bi * g.cs), gai);
+                // dL/da = conj(B T E x)
+                const float zbr = fmaf(br, g.cs, -(bi * g.sn)), zbi = fmaf(br, g.sn, bi * g.cs);
+                if constexpr (SPK) {
+                    gar = fmaf(T, fmaf(zbr, xr, -(zbi * xi)), gar);
+                    gai = fmaf(-T, fmaf(zbr, xi, zbi * xr), gai);
+                } else {
+                    gar = fmaf(T, zbr, gar);
+                    gai = fmaf(-T, zbi, gai);
+                }
             }
         }
     }
@@ -297,12 +368,18 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
 
 }  // namespace
 
-hipError_t launch_adjoint(const AdjArgs &a, bool el_const, hipStream_t s) {
+hipError_t launch_adjoint(const AdjArgs &a, bool el_const, bool speckle, hipStream_t s) {
     if (a.n_blocks == 0 || a.np == 0) return hipSuccess;
     const unsigned long long wgs = ((unsigned long long)a.n_blocks + 7) / 8 * 8;
     if (wgs > 0xffffffffULL) return hipErrorInvalidConfiguration;
-    if (el_const) hipLaunchKernelGGL(k_adjoint<true>, dim3((unsigned)wgs), dim3(64), 0, s, a);
-    else hipLaunchKernelGGL(k_adjoint<false>, dim3((unsigned)wgs), dim3(64), 0, s, a);
+    const dim3 grid((unsigned)wgs);
+    if (speckle) {
+        if (el_const) hipLaunchKernelGGL((k_adjoint<true, true>), grid, dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_adjoint<false, true>), grid, dim3(64), 0, s, a);
+    } else {
+        if (el_const) hipLaunchKernelGGL((k_adjoint<true, false>), grid, dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_adjoint<false, false>), grid, dim3(64), 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -20,6 +20,7 @@
 //   range.  A contribution whose taps leave the window (only for geometries
 //   the patch sizing did not foresee) goes straight to global memory.
 #include "sim_device.h"
+#include "spk_device.h"
 
 namespace hs {
 
@@ -70,11 +71,40 @@ __device__ __forceinline__ FacetV load_facet(__amdgpu_buffer_rsrc_t rs, int j) {
     return f;
 }
 
+// Speckle record (id, f_s) and anchor pair of one facet, also uniform
+// buffer loads (zeros past the resource's end).
+struct SpkFacet {
+    uint32_t id;
+    float fs;
+    float ygr, ygi, y1r, y1i;   // y_g and y_{g+1}
+};
+
+__device__ __forceinline__ SpkFacet load_spk(__amdgpu_buffer_rsrc_t rr, __amdgpu_buffer_rsrc_t ra,
+                                             int j, int ng1, int g) {
+    const auto r = __builtin_amdgcn_raw_buffer_load_b64(rr, j * (int)sizeof(SpkRec), 0, 0);
+    const int off = (j * ng1 + g) * (int)sizeof(float4);
+    const auto a = __builtin_amdgcn_raw_buffer_load_b64(ra, off, 0, 0);
+    const auto b = __builtin_amdgcn_raw_buffer_load_b64(ra, off + (int)sizeof(float4), 0, 0);
+    SpkFacet s;
+    s.id = r[0];
+    s.fs = __uint_as_float(r[1]);
+    s.ygr = __uint_as_float(a[0]);
+    s.ygi = __uint_as_float(a[1]);
+    s.y1r = __uint_as_float(b[0]);
+    s.y1i = __uint_as_float(b[1]);
+    return s;
+}
+
 // The flush of windows up to this width goes through a transposed copy in
 // LDS, so that one atomic instruction covers contiguous samples of one line.
 constexpr int kFlushTransposeMax = 32;
 
-template <int WIN, bool ELC>
+// SPK: the intra-facet speckle of eq. 7 multiplies each facet's amplitude by
+// x(p) and adds f_s t_p cycles to its phase.  Pulse groups are then aligned
+// on absolute pulse indices (multiples of 64), so that a wave holds exactly
+// one group of the speckle process; lanes before p0 or past the last pulse
+// take part in the prefix sum but deposit nothing.
+template <int WIN, bool ELC, bool SPK>
 __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
     // [sample][lane] during the sum; [lane][WIN + 1] for the flush
     constexpr int kAcc = WIN <= kFlushTransposeMax ? 64 * (WIN + 1) : 64 * WIN;
@@ -85,7 +115,8 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
     // groups of one patch get the same L % 8 and consecutive L / 8: they run
     // on one XCD close in time and read the patch's facet records from its
     // L2 instead of HBM.
-    const int G = (A.np + 63) >> 6;
+    const int poff = SPK ? (A.p0 & 63) : 0;     // lanes before p0 in the first group
+    const int G = (poff + A.np + 63) >> 6;
     const unsigned L = blockIdx.x, r8 = L >> 3;
     const int grp = (int)(r8 % (unsigned)G);
     const int patch = (int)((r8 / (unsigned)G) * 8u + (L & 7u));
@@ -96,9 +127,9 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
     const int b0 = patch_first[patch], b1 = patch_first[patch + 1];
     if (b0 == b1) return;
     const int lane = threadIdx.x;
-    const int pl = grp * 64 + lane;          // pulse relative to p0
-    const bool live = pl < A.np;
-    const int plc = live ? pl : (A.np - 1);
+    const int pl = grp * 64 + lane - poff;   // pulse relative to p0
+    const bool live = pl >= 0 && pl < A.np;
+    const int plc = pl < 0 ? 0 : (pl < A.np ? pl : A.np - 1);
     const PulseRec *PR = A.pulses + (size_t)ch * A.Np + A.p0;
     const ChanArgs chn = A.ch[ch];
     const AntArgs &ta = A.ant[chn.tx], &ra = A.ant[chn.rx];
@@ -118,8 +149,8 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
             const double cy0 = (double)(L.by0 + (long long)py * L.py);
             const double xc = ((lane & 1) ? cx0 + L.px : cx0) * L.edge;
             const double yc = ((lane & 2) ? cy0 + L.py : cy0) * L.edge;
-            int pe = grp * 64 + ((lane & 4) ? 63 : 0);
-            pe = pe < A.np ? pe : A.np - 1;
+            int pe = grp * 64 - poff + ((lane & 4) ? 63 : 0);
+            pe = pe < 0 ? 0 : (pe < A.np ? pe : A.np - 1);
             const PulseRec &Q = PR[pe];
             const double a0 = xc - Q.ptx[0], a1 = yc - Q.ptx[1], a2 = -Q.ptx[2];
             const double c0 = xc - Q.prx[0], c1 = yc - Q.prx[1], c2 = -Q.prx[2];
@@ -148,6 +179,29 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
     TapV tv;
     tap_all(A.tp, tv);
 
+    // speckle: the lane's pulse, its time split in two floats, the scan weights
+    const SpkArgs &S = A.spk;
+    [[maybe_unused]] int gabs = 0;
+    [[maybe_unused]] uint32_t slot = 0;
+    [[maybe_unused]] float thi = 0.f, tlo = 0.f, bk = 0.f, kk = 0.f, b64 = 0.f, l1 = 0.f;
+    [[maybe_unused]] SpkScanW sw{};
+    if constexpr (SPK) {
+        gabs = (A.p0 - poff) / 64 + grp;
+        slot = (uint32_t)(64 * gabs + lane + 1);   // the lane draws e_{p + 1}
+        thi = (float)P.t;
+        tlo = (float)(P.t - (double)thi);
+        bk = S.bpow[lane];
+        kk = S.gain[lane];
+        sw.b1 = to_vgpr(S.b1);
+        sw.b2 = to_vgpr(S.b2);
+        sw.b4 = to_vgpr(S.b4);
+        sw.b8 = to_vgpr(S.b8);
+        sw.w15 = ((lane >> 4) & 1) ? S.bpow[(lane & 15) + 1] : 0.0f;
+        sw.w31 = lane >= 32 ? S.bpow[lane - 31] : 0.0f;
+        b64 = S.b64;
+        l1 = S.c1 * S.c1 * 0.69314718055994531f;
+    }
+
     for (int b = b0; b < b1; ++b) {
         const BlockRec blk = load_block(blocks + b);
         Refs r;
@@ -159,12 +213,41 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
         r.fb += (float)(r.nb - lo - 3);
         const __amdgpu_buffer_rsrc_t rs = facet_rsrc(A.facets + blk.start, blk.count);
         FacetV fn = load_facet(rs, 0);
+        // speckle records and anchors of the block (unused without speckle)
+        const int ng1 = S.n_groups + 1;
+        const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(S.rec + blk.start), 0, (blk.count + 1) * (int)sizeof(SpkRec), 0x00020000);
+        const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(S.anch + (size_t)blk.start * ng1), 0,
+            (blk.count + 1) * ng1 * (int)sizeof(float4), 0x00020000);
+        [[maybe_unused]] SpkFacet sn{};
+        if constexpr (SPK) sn = load_spk(rr, ra, 0, ng1, gabs);
         for (int j = 0; j < blk.count; ++j) {
             const FacetV f = fn;
             fn = load_facet(rs, j + 1);
+            float far = f.ar, fai = f.ai, dop = 0.0f;
+            if constexpr (SPK) {
+                const SpkFacet sp = sn;
+                sn = load_spk(rr, ra, j + 1, ng1, gabs);
+                // free path of the group: innovations, prefix sum, end value
+                const float2 e = spk_draw(S.key, sp.id, slot, l1);
+                const float wr = spk_scan(e.x, sw), wi = spk_scan(e.y, sw);
+                const float z64r = fmaf(b64, sp.ygr, spk_lane63(wr));
+                const float z64i = fmaf(b64, sp.ygi, spk_lane63(wi));
+                // x = b^k y_g + (sum up to lane k - 1) + K_k (y_{g+1} - z_64)
+                const float xr = fmaf(kk, sp.y1r - z64r, fmaf(bk, sp.ygr, spk_shr1(wr)));
+                const float xi = fmaf(kk, sp.y1i - z64i, fmaf(bk, sp.ygi, spk_shr1(wi)));
+                far = fmaf(f.ar, xr, -(f.ai * xi));
+                fai = fmaf(f.ar, xi, f.ai * xr);
+                // Doppler f_s t_p in cycles, the product split so that its
+                // integer part goes without rounding the fraction
+                const float dh = sp.fs * thi;
+                const float dl = fmaf(sp.fs, tlo, fmaf(sp.fs, thi, -dh));
+                dop = __builtin_amdgcn_fractf(dh) + dl;
+            }
             Geo g;
-            facet_geo<ELC>(r, kc, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz, graze_any, A.linv_hi,
-                      A.linv_lo, A.fs_cf, g);
+            facet_geo<ELC, SPK>(r, kc, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz, graze_any, A.linv_hi,
+                      A.linv_lo, A.fs_cf, dop, g);
             // Each lane owns its pulse row, so the deposit is a plain
             // read-modify-write of 8 consecutive complex samples.
             const int n0 = g.fl;                  // window index of the first tap
@@ -175,16 +258,16 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
             for (int k = 0; k < 8; ++k) old[k] = p[64 * k];
             // a lane outside the window adds zero to its row (and goes below)
             const float al = inw ? g.amp : 0.0f;
-            const float wrl = al * fmaf(f.ar, g.cs, -(f.ai * g.sn));
-            const float wil = al * fmaf(f.ar, g.sn, f.ai * g.cs);
+            const float wrl = al * fmaf(far, g.cs, -(fai * g.sn));
+            const float wil = al * fmaf(far, g.sn, fai * g.cs);
             float tap[8];
             taps8(tv, g.f, tap);
 #pragma unroll
             for (int k = 0; k < 8; ++k)
                 p[64 * k] = make_float2(fmaf(wrl, tap[k], old[k].x), fmaf(wil, tap[k], old[k].y));
             if (!inw && live) {
-                const float wr = g.amp * fmaf(f.ar, g.cs, -(f.ai * g.sn));
-                const float wi = g.amp * fmaf(f.ar, g.sn, f.ai * g.cs);
+                const float wr = g.amp * fmaf(far, g.cs, -(fai * g.sn));
+                const float wi = g.amp * fmaf(far, g.sn, fai * g.cs);
                 // outside the window: straight to the line, taps inside [0, N)
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
@@ -213,12 +296,13 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
         const float *accf = reinterpret_cast<const float *>(acc);
         const int n = lo + (lane >> 1);
         const bool lane_in = lane < 2 * WIN && n >= 0 && n < A.N;
-        const int pend = (A.np - grp * 64) < 64 ? (A.np - grp * 64) : 64;
-        float *line = A.iq + 2 * (((size_t)ch * A.np + (size_t)grp * 64) * (size_t)A.N) +
-                      2 * (ptrdiff_t)lo + lane;
-        for (int p = 0; p < pend; ++p) {
+        const int rbase = grp * 64 - poff;     // line (relative to p0) of lane 0
+        const int pbeg = rbase < 0 ? -rbase : 0;
+        const int pend = (A.np - rbase) < 64 ? (A.np - rbase) : 64;
+        float *line = A.iq + 2 * ((size_t)ch * A.np * (size_t)A.N) + 2 * (ptrdiff_t)lo + lane;
+        for (int p = pbeg; p < pend; ++p) {
             const float x = lane < 2 * WIN ? accf[p * 2 * (WIN + 1) + lane] : 0.0f;
-            if (lane_in && x != 0.0f) unsafeAtomicAdd(line + 2 * (size_t)p * A.N, x);
+            if (lane_in && x != 0.0f) unsafeAtomicAdd(line + 2 * (size_t)(rbase + p) * A.N, x);
         }
     } else if (live) {
         float *dst = A.iq + 2 * (((size_t)ch * A.np + pl) * (size_t)A.N);
@@ -234,17 +318,25 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
 
 }  // namespace
 
-hipError_t launch_forward(const FwdArgs &a, int C, int win, bool el_const, hipStream_t s) {
+hipError_t launch_forward(const FwdArgs &a, int C, int win, bool el_const, bool speckle,
+                          hipStream_t s) {
     if (a.n_patches == 0 || a.np == 0) return hipSuccess;
-    // (patch, pulse group) pairs, patches padded to a multiple of the 8 XCDs
-    const unsigned long long groups = (unsigned long long)((a.np + 63) / 64);
+    // (patch, pulse group) pairs, patches padded to a multiple of the 8 XCDs;
+    // speckle groups are aligned on absolute pulse indices
+    const int poff = speckle ? (a.p0 & 63) : 0;
+    const unsigned long long groups = (unsigned long long)((poff + a.np + 63) / 64);
     const unsigned long long wgs = groups * (((unsigned long long)a.n_patches + 7) / 8 * 8);
     if (wgs > 0xffffffffULL) return hipErrorInvalidConfiguration;
     dim3 grid((unsigned)wgs, (unsigned)C);
-#define HS_FWD(W)                                                                          \
-    case W:                                                                                \
-        if (el_const) hipLaunchKernelGGL((k_forward<W, true>), grid, dim3(64), 0, s, a);   \
-        else hipLaunchKernelGGL((k_forward<W, false>), grid, dim3(64), 0, s, a);           \
+#define HS_FWD(W)                                                                           \
+    case W:                                                                                 \
+        if (speckle) {                                                                      \
+            if (el_const) hipLaunchKernelGGL((k_forward<W, true, true>), grid, dim3(64), 0, s, a); \
+            else hipLaunchKernelGGL((k_forward<W, false, true>), grid, dim3(64), 0, s, a);  \
+        } else {                                                                            \
+            if (el_const) hipLaunchKernelGGL((k_forward<W, true, false>), grid, dim3(64), 0, s, a); \
+            else hipLaunchKernelGGL((k_forward<W, false, false>), grid, dim3(64), 0, s, a); \
+        }                                                                                   \
         break;
     switch (win) {
         HS_FWD(24)

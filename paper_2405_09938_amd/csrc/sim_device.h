@@ -158,11 +158,11 @@ struct Geo {
     int fl;          // floor(fb + dR fs/c): sample offset from the centre's
 };
 
-template <bool ELC>
+template <bool ELC, bool DOP = false>
 __device__ __forceinline__ void facet_geo(const Refs &r, const FacetConsts &cc, float tf,
                                           float fdx, float fdy, float fz, float fvx, float fvy,
                                           float fvz, bool graze_any, float linv_hi,
-                                          float linv_lo, float fs_c, Geo &o) {
+                                          float linv_lo, float fs_c, float dop, Geo &o) {
     const float ex = fmaf(fvx, tf, fdx);
     const float ey = fmaf(fvy, tf, fdy);
     const float ez = fmaf(fvz, tf, fz);
@@ -175,12 +175,14 @@ __device__ __forceinline__ void facet_geo(const Refs &r, const FacetConsts &cc, 
     const float s1 = at * r.i2rt, s2 = ar * r.i2rr;
     const float h2 = fmaf(at, s1, ar * s2);
     const float dR = L + fmaf(ee, r.i2s, -h2);
-    // phase (cycles) = phib - dR f0/c, product split so the integer part of
-    // the cycle count is removed exactly
+    // phase (cycles) = phib - dR f0/c (+ dop, the intra-facet Doppler of a
+    // speckle sum, if DOP), product split so the integer part of the cycle
+    // count is removed exactly
     const float hi = dR * linv_hi;
     float lo = fmaf(dR, linv_hi, -hi);
     lo = fmaf(dR, linv_lo, lo);
-    const float ph = (r.phib - __builtin_amdgcn_fractf(hi)) - lo;
+    float ph = (r.phib - __builtin_amdgcn_fractf(hi)) - lo;
+    if constexpr (DOP) ph += dop;
     o.sn = __builtin_amdgcn_sinf(ph);
     o.cs = __builtin_amdgcn_cosf(ph);
     // Antenna field patterns.  With y = kappa u / (2 beta) for each of the four

@@ -71,6 +71,25 @@ struct ChanArgs {
     double rtrr_mid;            // R_t,mid * R_r,mid
 };
 
+// Intra-facet speckle (Sec. III.A eq. 7, eq. 10).  Per sorted facet: the
+// counter id of its draws and its intra-facet Doppler f_s (Hz).
+struct alignas(8) SpkRec {
+    uint32_t id;
+    float fs;
+};
+
+// Speckle constants of one call, b = exp(-1 / (prf tau_s)).
+struct SpkArgs {
+    const SpkRec *rec;          // [n + 1] sorted order (last one zero)
+    const float4 *anch;         // [n + 1][n_groups + 1]: (y_g, D_g) per absolute group g
+    int n_groups;               // ceil(Np / 64)
+    uint32_t key;               // Philox2x32-10 key
+    float b1, b2, b4, b8, b64;  // b^m
+    float c1, c64;              // sqrt(1 - b^2), sqrt(1 - b^128)
+    float bpow[65];             // b^m, m = 0..64
+    float gain[64];             // bridge gains K_k = b^(64-k) (1 - b^2k) / (1 - b^128)
+};
+
 // Arguments of the fused forward kernel.
 struct FwdArgs {
     const FacetRec *facets;
@@ -88,6 +107,7 @@ struct FwdArgs {
     int N, Np, p0, np;
     int n_patches;
     int halo;                   // bins added on each side of the patch span
+    SpkArgs spk;                // speckle variant only
 };
 
 // Arguments of the adjoint kernel.
@@ -106,6 +126,7 @@ struct AdjArgs {
     int N, Np, p0, np, C;
     long long n_blocks;
     int accumulate;
+    SpkArgs spk;                // speckle variant only
 };
 
 }  // namespace hs
@@ -169,8 +190,11 @@ struct sim_plan {
     hs::BlockRec *blocks = nullptr;     // [n_blocks]
     int *patch_first = nullptr;  // [n_patches + 1]
     hs::FacetRec *sorted = nullptr;     // [n] scratch refreshed by each call
+    hs::SpkRec *spk = nullptr;          // [n + 1] speckle records (speckle calls only)
+    float4 *anch = nullptr;             // [n + 1][ceil(Np/64) + 1] speckle anchors
     // byte capacity of each buffer (they may come from the handle's pool)
     size_t perm_cap = 0, blocks_cap = 0, patch_first_cap = 0, sorted_cap = 0;
+    size_t spk_cap = 0, anch_cap = 0;
     // per stream that used the buffers, an event recorded after its last use
     std::vector<std::pair<hipStream_t, hipEvent_t>> uses;
     bool uses_ok = true;         // every use could be recorded
@@ -202,9 +226,23 @@ hipError_t launch_patch_first(const int *blk_offset, long long n_patches, int ke
 hipError_t launch_gather(const sim_facets &f, const int *perm, const BlockRec *blocks,
                          long long n_blocks, FacetRec *sorted, hipStream_t s);
 
+// Speckle records and anchors of the sorted facets for absolute pulse groups
+// [g_lo, g_hi] (anchors g_lo .. g_hi + 1; with_d adds D_g = y_{g+1} - z_64).
+struct SpkPrep {
+    long long n;
+    const int *perm;
+    const float *fs;            // caller's order, NULL = 0
+    long long first_index;
+    int g_lo, g_hi;
+    bool with_d;
+};
+hipError_t launch_speckle_prep(const SpkPrep &p, const SpkArgs &k, SpkRec *rec, float4 *anch,
+                               hipStream_t s);
+
 // Hot path.
-hipError_t launch_forward(const FwdArgs &a, int C, int win, bool el_const, hipStream_t s);
-hipError_t launch_adjoint(const AdjArgs &a, bool el_const, hipStream_t s);
+hipError_t launch_forward(const FwdArgs &a, int C, int win, bool el_const, bool speckle,
+                          hipStream_t s);
+hipError_t launch_adjoint(const AdjArgs &a, bool el_const, bool speckle, hipStream_t s);
 hipError_t launch_waveform(const float *in, float *out, long long n_lines, int N, int M,
                            int shift, const float *spec, const float *tw, int adjoint,
                            hipStream_t s);

@@ -193,10 +193,22 @@ class Simulator:
         return out
 
     # -- the facet sum and its adjoint -----------------------------------------
+    def _speckle_struct(self, speckle, f_s: Optional[torch.Tensor], n: int):
+        """C description of the intra-facet speckle (speckle: an object with
+        tau_s, seed and first_index, e.g. workloads.Speckle; f_s: float32
+        device [n] Doppler in Hz, or None)."""
+        if f_s is not None:
+            f_s = _check_f32(f_s, n, "f_s", self.device)
+        sp = N.SimSpeckle(float(speckle.tau_s), int(speckle.seed), int(speckle.first_index),
+                          _fptr(f_s))
+        return sp, f_s
+
     def forward(self, plan: "Plan", facets: Dict[str, torch.Tensor], p0: int = 0,
                 np_: Optional[int] = None, out: Optional[torch.Tensor] = None,
-                accumulate: bool = False) -> torch.Tensor:
-        """Range-compressed IQ, complex64 [C, np, N]."""
+                accumulate: bool = False, speckle=None,
+                f_s: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Range-compressed IQ, complex64 [C, np, N]; with `speckle` (and the
+        per-facet Doppler f_s) the intra-facet speckle sum."""
         np_ = self.n_pulses - p0 if np_ is None else np_
         fs, keep = self._facets_struct(facets, plan.n)
         shape = (self.n_channels, np_, self.n_samples)
@@ -205,14 +217,23 @@ class Simulator:
             accumulate = False
         elif out.shape != shape or out.dtype != torch.complex64 or not out.is_contiguous():
             raise ValueError(f"out must be a contiguous complex64 tensor of shape {shape}")
-        N.check(self.lib.sim_forward(self.handle, plan.ptr, ctypes.byref(fs), p0, np_,
-                                     ctypes.c_void_p(out.data_ptr()), int(accumulate),
-                                     _stream()), "sim_forward")
+        if speckle is None:
+            N.check(self.lib.sim_forward(self.handle, plan.ptr, ctypes.byref(fs), p0, np_,
+                                         ctypes.c_void_p(out.data_ptr()), int(accumulate),
+                                         _stream()), "sim_forward")
+        else:
+            sp, f_keep = self._speckle_struct(speckle, f_s, plan.n)
+            N.check(self.lib.sim_forward_speckle(self.handle, plan.ptr, ctypes.byref(fs),
+                                                 ctypes.byref(sp), p0, np_,
+                                                 ctypes.c_void_p(out.data_ptr()),
+                                                 int(accumulate), _stream()),
+                    "sim_forward_speckle")
         return out
 
     def backward(self, plan: "Plan", facets: Dict[str, torch.Tensor], g_rc: torch.Tensor,
                  p0: int = 0, np_: Optional[int] = None,
-                 need: Iterable[str] = GRAD_KEYS) -> Dict[str, torch.Tensor]:
+                 need: Iterable[str] = GRAD_KEYS, speckle=None,
+                 f_s: Optional[torch.Tensor] = None) -> Dict[str, torch.Tensor]:
         """Facet gradients from g = dL/dRe(IQ_rc) + j dL/dIm(IQ_rc)."""
         np_ = self.n_pulses - p0 if np_ is None else np_
         fs, keep = self._facets_struct(facets, plan.n)
@@ -224,9 +245,17 @@ class Simulator:
         out = {k: torch.empty(plan.n, dtype=torch.float32, device=self.device)
                for k in GRAD_KEYS if k in need}
         gs = N.SimFacetGrads(plan.n, *[_fptr(out.get(k)) for k in GRAD_KEYS])
-        N.check(self.lib.sim_backward(self.handle, plan.ptr, ctypes.byref(fs), p0, np_,
-                                      ctypes.c_void_p(g_rc.data_ptr()), ctypes.byref(gs), 0,
-                                      _stream()), "sim_backward")
+        if speckle is None:
+            N.check(self.lib.sim_backward(self.handle, plan.ptr, ctypes.byref(fs), p0, np_,
+                                          ctypes.c_void_p(g_rc.data_ptr()), ctypes.byref(gs),
+                                          0, _stream()), "sim_backward")
+        else:
+            sp, f_keep = self._speckle_struct(speckle, f_s, plan.n)
+            N.check(self.lib.sim_backward_speckle(self.handle, plan.ptr, ctypes.byref(fs),
+                                                  ctypes.byref(sp), p0, np_,
+                                                  ctypes.c_void_p(g_rc.data_ptr()),
+                                                  ctypes.byref(gs), 0, _stream()),
+                    "sim_backward_speckle")
         return out
 
     def apply_waveform(self, iq: torch.Tensor, out: Optional[torch.Tensor] = None,
@@ -275,12 +304,14 @@ class SimForward(torch.autograd.Function):
     the input tensors are saved."""
 
     @staticmethod
-    def forward(ctx, sim, plan, p0, np_, waveform, x, y, z, vx, vy, vz, a_re, a_im):
+    def forward(ctx, sim, plan, p0, np_, waveform, speckle, f_s, x, y, z, vx, vy, vz, a_re,
+                a_im):
         facets = dict(zip(FACET_KEYS, (x, y, z, vx, vy, vz, a_re, a_im)))
-        iq = sim.forward(plan, facets, p0, np_)
+        iq = sim.forward(plan, facets, p0, np_, speckle=speckle, f_s=f_s)
         if waveform:
             iq = sim.apply_waveform(iq, out=iq)
         ctx.sim, ctx.plan, ctx.p0, ctx.np_, ctx.waveform = sim, plan, p0, np_, waveform
+        ctx.speckle, ctx.f_s = speckle, f_s
         ctx.save_for_backward(x, y, z, vx, vy, vz, a_re, a_im)
         return iq
 
@@ -291,12 +322,17 @@ class SimForward(torch.autograd.Function):
         g = g.contiguous()
         if ctx.waveform:
             g = sim.apply_waveform(g, adjoint=True)
-        need = [k for k, f in zip(GRAD_KEYS, ctx.needs_input_grad[7:]) if f]
-        grads = sim.backward(ctx.plan, facets, g, ctx.p0, ctx.np_, need=need) if need else {}
-        return (None, None, None, None, None, None, None) + tuple(grads.get(k) for k in GRAD_KEYS)
+        need = [k for k, f in zip(GRAD_KEYS, ctx.needs_input_grad[9:]) if f]
+        grads = sim.backward(ctx.plan, facets, g, ctx.p0, ctx.np_, need=need,
+                             speckle=ctx.speckle, f_s=ctx.f_s) if need else {}
+        return (None,) * 9 + tuple(grads.get(k) for k in GRAD_KEYS)
 
 
 def simulate(sim: Simulator, plan: Plan, facets: Dict[str, torch.Tensor], p0: int = 0,
-             np_: Optional[int] = None, waveform: bool = False) -> torch.Tensor:
+             np_: Optional[int] = None, waveform: bool = False, speckle=None,
+             f_s: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Differentiable facet sum (optionally with the chirp and the intra-facet
+    speckle; the speckle inputs are not differentiated)."""
     np_ = sim.n_pulses - p0 if np_ is None else np_
-    return SimForward.apply(sim, plan, p0, np_, waveform, *[facets[k] for k in FACET_KEYS])
+    return SimForward.apply(sim, plan, p0, np_, waveform, speckle, f_s,
+                            *[facets[k] for k in FACET_KEYS])

@@ -87,6 +87,13 @@ def test_entry_points_reject_null(native):
     assert L.sim_backward(None, None, None, 0, 1, None, None, 0, None) == native.SIM_EINVAL
     assert L.sim_apply_waveform(None, None, None, 1, None) == native.SIM_EINVAL
     assert L.sim_plan_mode(None, None, None) == native.SIM_EINVAL
+    assert L.sim_forward_speckle(None, None, None, None, 0, 1, None, 0, None) == native.SIM_EINVAL
+    assert "speckle is NULL" in L.sim_last_error().decode()
+    assert L.sim_backward_speckle(None, None, None, None, 0, 1, None, None, 0,
+                                  None) == native.SIM_EINVAL
+    sp = native.SimSpeckle(0.02, 1, 0, None)
+    assert L.sim_forward_speckle(None, None, None, ctypes.byref(sp), 0, 1, None, 0,
+                                 None) == native.SIM_EINVAL
     L.sim_destroy(None)
     L.sim_plan_destroy(None)
 

@@ -1,0 +1,239 @@
+"""GPU parity of the intra-facet speckle sum (Sec. III.A eq. 7, eq. 10)
+against the FP64 oracle, through the C ABI (sim_forward_speckle,
+sim_backward_speckle).
+
+The oracle draws the same Philox2x32-10 numbers with its own code and builds
+the same anchors and bridges in FP64; the bars are those of the plain sum
+(IQ rel-L2 <= 1e-4, gradients <= 1e-3).  Cases: the config-1 scene, six
+channels over a pulse range that starts inside a 64-pulse group, the frozen
+and white limits, the exact elevation mode, the adjoint from a mid-group
+start, autograd against finite differences, and a full-size workload-2 scene
+on sampled rows.
+"""
+import math
+import sys
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+import workloads as W
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+FKEYS = ("x", "y", "z", "vx", "vy", "vz", "a_re", "a_im")
+GKEYS = ("z", "vx", "vy", "vz", "a_re", "a_im")
+IQ_TOL = 1e-4
+IQ_BUDGET = 5e-5
+GRAD_TOL = 1e-3
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2405_09938_amd as hs
+    hs.load()
+    return torch, hs
+
+
+def dev(torch, f):
+    return {k: torch.from_numpy(np.ascontiguousarray(f[k], np.float32)).cuda() for k in FKEYS}
+
+
+def f64(f):
+    return {k: np.asarray(f[k], np.float32).astype(np.float64) for k in FKEYS}
+
+
+def fs_pair(torch, n, seed):
+    fs = W.speckle_doppler(n, seed)
+    return torch.from_numpy(fs).cuda(), fs.astype(np.float64)
+
+
+def speckle_forward(torch, hs, g, f, edge, sp, fs_dev, p0=0, np_=None):
+    sim = hs.Simulator(g)
+    d = dev(torch, f)
+    plan = sim.plan(d["x"], d["y"], edge)
+    iq = sim.forward(plan, d, p0, np_, speckle=sp, f_s=fs_dev)
+    torch.cuda.synchronize()
+    return iq.cpu().numpy().astype(np.complex128), sim, plan, d
+
+
+def test_speckle_cfg1_forward(env):
+    torch, hs = env
+    say("case: speckle, config-1 scene (64x64 @5 m, 256 pulses), tau_s 20 ms, f_s +-5.7 Hz")
+    wl = W.workload(1)
+    f = W.iid_facets(64, 64, 5.0, seed=wl.seed)
+    sp = W.Speckle(tau_s=0.02, seed=101, first_index=0)
+    fsd, fsh = fs_pair(torch, 4096, 101)
+    got, sim, plan, _ = speckle_forward(torch, hs, wl.geometry, f, wl.block_edge, sp, fsd)
+    ref = O.forward(wl.geometry, f64(f), speckle=sp, f_s=fsh)
+    e = O.rel_l2(got, ref)
+    say(f"speckle config 1 rel-L2 {e:.3e} (el_const {plan.el_const})")
+    assert e < IQ_TOL and e < IQ_BUDGET
+    # the speckle changes the result (it is not silently skipped)
+    assert O.rel_l2(O.forward(wl.geometry, f64(f)), ref) > 0.3
+
+
+def test_speckle_multichannel_midgroup_subrange(env):
+    """6 channels, pulses [37, 127): the first wave's lanes 0..36 belong to
+    the group but not to the call; the rows equal those of the full call."""
+    torch, hs = env
+    say("case: speckle, scattered facets, 6 channels, pulses [37, 127), first_index 123456789")
+    g = W.harmony_geometry(200, 512, receivers="AB", n_pc=3)
+    f = W.scattered_facets(3000, 150.0, seed=11, sigma_v=0.7, sigma_z=0.8)
+    sp = W.Speckle(tau_s=0.015, seed=7, first_index=123456789)
+    fsd, fsh = fs_pair(torch, 3000, 7)
+    got, sim, plan, d = speckle_forward(torch, hs, g, f, 8.0, sp, fsd, 37, 90)
+    ref = O.forward(g, f64(f), 37, 90, speckle=sp, f_s=fsh)
+    e = O.rel_l2(got, ref)
+    say(f"speckle 6-channel sub-range rel-L2 {e:.3e}")
+    assert e < IQ_TOL and e < IQ_BUDGET
+    for c in range(6):
+        assert O.rel_l2(got[c], ref[c]) < IQ_TOL, c
+    full = sim.forward(plan, d, speckle=sp, f_s=fsd).cpu().numpy()
+    diff = np.abs(got - full[:, 37:127]).max() / np.abs(full).max()
+    say(f"sub-range vs full-range rows: max rel diff {diff:.3e}")
+    assert diff < 1e-5
+
+
+@pytest.mark.parametrize("tau", [math.inf, 1e-5])
+def test_speckle_limits(env, tau):
+    """Frozen speckle (x = y_0 for every pulse) and a nearly white one
+    (b = exp(-59): every pulse its own draw); no Doppler (f_s NULL)."""
+    torch, hs = env
+    say(f"case: speckle limit tau_s = {tau}, 1600 facets, 130 pulses")
+    g = W.harmony_geometry(130, 256)
+    f = W.iid_facets(40, 40, 2.0, seed=5, sigma_z=0.3)
+    sp = W.Speckle(tau_s=tau, seed=3, first_index=5)
+    got, *_ = speckle_forward(torch, hs, g, f, 8.0, sp, None)
+    ref = O.forward(g, f64(f), speckle=sp)
+    e = O.rel_l2(got, ref)
+    say(f"speckle limit tau_s = {tau}: rel-L2 {e:.3e}")
+    assert e < IQ_TOL
+
+
+def test_speckle_exact_elevation_mode_forward_adjoint(env):
+    """Airborne geometry whose plan evaluates every pattern factor per facet
+    (the non-constant-elevation kernels), forward and adjoint with speckle."""
+    torch, hs = env
+    say("case: speckle, airborne geometry (exact elevation mode), forward and adjoint")
+    plats = (W.Platform((0.0, -15000.0, 12000.0), (60.0, 0.0, 0.0)),
+             W.Platform((400.0, -15000.0, 12000.0), (60.0, 0.0, 0.0)))
+    g = replace(W.harmony_geometry(80, 4096), platforms=plats)
+    rng = np.random.default_rng(41)
+    n = 2000
+    f = dict(x=rng.uniform(-200, 200, n), y=rng.uniform(-24900, -24300, n),
+             z=rng.normal(0, 0.3, n), vx=rng.normal(0, 0.3, n), vy=rng.normal(0, 0.3, n),
+             vz=rng.normal(0, 0.3, n), a_re=rng.normal(0, 0.7, n), a_im=rng.normal(0, 0.7, n))
+    f = {k: v.astype(np.float32) for k, v in f.items()}
+    sp = W.Speckle(tau_s=0.01, seed=12, first_index=0)
+    fsd, fsh = fs_pair(torch, n, 12)
+    got, sim, plan, d = speckle_forward(torch, hs, g, f, 2.0, sp, fsd, 10, 70)
+    say(f"elevation mode: const {plan.el_const}")
+    assert not plan.el_const
+    F = f64(f)
+    ref = O.forward(g, F, 10, 70, speckle=sp, f_s=fsh)
+    e = O.rel_l2(got, ref)
+    say(f"speckle exact-mode forward rel-L2 {e:.3e}")
+    assert e < IQ_TOL
+    gi = (rng.standard_normal(got.shape) + 1j * rng.standard_normal(got.shape)).astype(np.complex64)
+    gr = sim.backward(plan, d, torch.from_numpy(gi).cuda(), 10, 70, speckle=sp, f_s=fsd)
+    refg = O.adjoint(g, F, gi.astype(np.complex128), 10, 70, speckle=sp, f_s=fsh)
+    for k in GKEYS:
+        ek = O.rel_l2(gr[k].cpu().numpy(), refg[k])
+        say(f"speckle exact-mode adjoint {k} rel-L2 {ek:.3e}")
+        assert ek < GRAD_TOL, k
+
+
+def test_speckle_adjoint_vs_oracle_midgroup(env):
+    """Adjoint over pulses [37, 137) (the lanes first run their facet's
+    process from the group start to pulse 36), 6 channels."""
+    torch, hs = env
+    say("case: speckle adjoint vs oracle, 2000 facets, 6 channels, pulses [37, 137)")
+    g = W.harmony_geometry(200, 256, receivers="AB", n_pc=3)
+    f = W.scattered_facets(2000, 100.0, seed=21, sigma_v=0.5, sigma_z=0.5)
+    sp = W.Speckle(tau_s=0.02, seed=21, first_index=1000)
+    fsd, fsh = fs_pair(torch, 2000, 21)
+    rng = np.random.default_rng(22)
+    gi = (rng.standard_normal((6, 100, 256)) + 1j * rng.standard_normal((6, 100, 256)))
+    gi = gi.astype(np.complex64)
+    sim = hs.Simulator(g)
+    d = dev(torch, f)
+    plan = sim.plan(d["x"], d["y"], 8.0)
+    gr = sim.backward(plan, d, torch.from_numpy(gi).cuda(), 37, 100, speckle=sp, f_s=fsd)
+    torch.cuda.synchronize()
+    ref = O.adjoint(g, f64(f), gi.astype(np.complex128), 37, 100, speckle=sp, f_s=fsh)
+    for k in GKEYS:
+        e = O.rel_l2(gr[k].cpu().numpy(), ref[k])
+        say(f"speckle adjoint {k}: rel-L2 {e:.3e}")
+        assert e < GRAD_TOL, k
+
+
+def test_speckle_autograd_vs_oracle_fd(env):
+    """Loss ||IQ - T||^2 (T: the same speckle scene with a 0.1 m/s current
+    added), GPU autograd against the oracle's Richardson finite differences."""
+    torch, hs = env
+    say("case: speckle autograd vs FD, 30x30 facets @1 m, 128 pulses, 512 samples")
+    g = W.harmony_geometry(128, 512)
+    f = W.iid_facets(30, 30, 1.0, seed=4)
+    ft = dict(f)
+    ft["vx"] = (f["vx"] + 0.1).astype(np.float32)
+    sp = W.Speckle(tau_s=0.02, seed=4, first_index=0)
+    fsd, fsh = fs_pair(torch, 900, 4)
+    sim = hs.Simulator(g)
+    d = dev(torch, f)
+    dt = dev(torch, ft)
+    plan = sim.plan(d["x"], d["y"], 8.0)
+    with torch.no_grad():
+        tgt = sim.forward(plan, dt, speckle=sp, f_s=fsd)
+    for k in GKEYS:
+        d[k].requires_grad_(True)
+    iq = hs.simulate(sim, plan, d, speckle=sp, f_s=fsd)
+    ((iq - tgt).abs() ** 2).sum().backward()
+    gpu = {k: d[k].grad.cpu().numpy() for k in GKEYS}
+    F = f64(f)
+    T = O.forward(g, f64(ft), speckle=sp, f_s=fsh)
+    resid = O.forward(g, F, speckle=sp, f_s=fsh) - T
+    idx = np.random.default_rng(5).choice(900, 12, replace=False)
+    for k, h in (("z", 1e-3), ("vx", 1e-3), ("a_im", 1e-3)):
+        fd = []
+        for i in idx:
+            d1 = O.fd_gradient(g, F, T, int(i), k, h, resid=resid, speckle=sp, f_s=fsh)
+            d2 = O.fd_gradient(g, F, T, int(i), k, h / 2, resid=resid, speckle=sp, f_s=fsh)
+            fd.append((4 * d2 - d1) / 3)
+        e = O.rel_l2(gpu[k][idx], np.array(fd))
+        say(f"speckle autograd {k} vs Richardson FD: rel-L2 {e:.3e}")
+        assert e < GRAD_TOL, k
+
+
+def test_speckle_workload2_full_rows(env):
+    """Workload 2's scene at full size (1e6 generated facets, 2048 pulses)
+    with speckle, as the benchmark's speckle mode launches it; three sampled
+    pulses (one at a group start, one at a group end) against the oracle."""
+    torch, hs = env
+    say("case: speckle, workload 2 at full size, pulses 0, 1023, 1600")
+    wl = W.workload(2)
+    g = wl.geometry
+    sim = hs.Simulator(g)
+    f = sim.generate(wl.sea, wl.seed)
+    plan = sim.plan(f["x"], f["y"], wl.block_edge)
+    sp = W.Speckle(tau_s=W.SPECKLE_TAU_S, seed=wl.seed, first_index=0)
+    n = f["x"].numel()
+    fsd, fsh = fs_pair(torch, n, wl.seed)
+    rc = sim.forward(plan, f, speckle=sp, f_s=fsd)
+    torch.cuda.synchronize()
+    fo = {k: v.astype(np.float32).astype(np.float64)
+          for k, v in O.generate_facets(wl.sea, wl.seed).items()}
+    for p in (0, 1023, 1600):
+        ref = O.forward(g, fo, p, 1, speckle=sp, f_s=fsh)
+        e = O.rel_l2(rc[:, p:p + 1].cpu().numpy(), ref)
+        say(f"workload 2 speckle row {p}: rel-L2 {e:.3e}")
+        assert e < IQ_TOL and e < IQ_BUDGET
