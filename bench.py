@@ -47,6 +47,15 @@ if ROOT not in sys.path:
 # overhead, not counted.
 W_ALG_SLOTS = 116.0 + 7 * 4.0
 W_ALG_SLOTS_EL_CONST = 104.0 + 5 * 4.0
+# With the intra-facet speckle of eq. 7 (--speckle), per contribution: one
+# Philox2x32-10 evaluation (10 rounds of two 32-bit integer multiplies, high
+# and low word, which gfx950 issues at half the FMA rate (measured), and two
+# XORs), the two uniforms (2 shifts, 2 conversions, 2 scalings), Box-Muller
+# (log2, sqrt, sin, cos at four slots; 3 products), the AR(1) step and the
+# bridge correction (2 + 2 FMAs), the amplitude times x (4) and the Doppler
+# phase (6): 99 slots.
+MUL32_SLOTS = 2.0
+W_SPK_SLOTS = 10 * (2 * MUL32_SLOTS + 2) + 6 + (4 * 4.0 + 3) + 4 + 4 + 6
 PEAK_SLOTS = 256 * 128 * 2.4e9         # FP32 lane-operations per second (157.3 TFLOP/s / 2)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_forward_cfg2_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2405_09938_amd", "csrc", f)
@@ -72,6 +81,8 @@ def main():
     ap.add_argument("--serial", action="store_true",
                     help="no step pipelining (one kernel at a time, for per-kernel counters)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--speckle", action="store_true",
+                    help="intra-facet speckle (eq. 7, 10): tau_s 20 ms, f_s +-5.7 Hz per facet")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of a known size (counter scale)")
     args = ap.parse_args()
@@ -110,6 +121,14 @@ def main():
 
     fwd_ev = []
     streamed = bool(wl.chunks)
+    if args.speckle and streamed:
+        print("--speckle: the streamed workload has no speckle path", file=sys.stderr)
+        sys.exit(2)
+    # speckle inputs: one process per facet, Doppler drawn per facet (input,
+    # resident in HBM for the whole run)
+    spk = W.Speckle(tau_s=W.SPECKLE_TAU_S, seed=wl.seed, first_index=0) if args.speckle else None
+    fs_dev = (torch.from_numpy(W.speckle_doppler(wl.n_facets, wl.seed)).to(dev)
+              if args.speckle else None)
     # Consecutive steps are pipelined: the scene generation and plan of step
     # i + 1 run on a side stream (default priority) while step i's sum runs,
     # so the plan's host synchronisations do not idle the GPU.  Every step
@@ -141,7 +160,7 @@ def main():
             stream.wait_stream(side)
             if record:
                 e0.record(stream)
-            rc = sim.forward(plan, f)
+            rc = sim.forward(plan, f, speckle=spk, f_s=fs_dev)
         if record:
             e1.record(stream)
             fwd_ev.append((e0, e1))
@@ -200,7 +219,7 @@ def main():
                 ft = dict(f)
                 ft["vx"] = f["vx"] + 0.1 * math.cos(psi)
                 ft["vy"] = f["vy"] + 0.1 * math.sin(psi)
-                tgt = sim.forward(plan, ft)
+                tgt = sim.forward(plan, ft, speckle=spk, f_s=fs_dev)
                 if chirp:
                     tgt = sim.apply_waveform(tgt, out=tgt)
 
@@ -209,7 +228,7 @@ def main():
                 g = 2.0 * (o - tgt)
                 if chirp:
                     g = sim.apply_waveform(g, out=g, adjoint=True)
-                return sim.backward(plan2, f2, g)
+                return sim.backward(plan2, f2, g, speckle=spk, f_s=fs_dev)
 
         def fa_steps(n):
             nxt = prepare() if pipelined else None
@@ -245,6 +264,8 @@ def main():
     else:
         el_const = plan.el_const
     w_alg = W_ALG_SLOTS_EL_CONST if el_const else W_ALG_SLOTS
+    if args.speckle:
+        w_alg += W_SPK_SLOTS
     achieved = w_alg * contrib / (kern_ms * 1e-3) / 1e12
     peak = PEAK_SLOTS / 1e12
     traffic = None
@@ -252,7 +273,8 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
-        if tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == wl.name:
+        if (tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == wl.name
+                and bool(tr.get("speckle", False)) == args.speckle):
             traffic = tr.get("bytes_per_launch")
             valu = tr.get("valu_insts_per_launch")
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
@@ -291,7 +313,11 @@ def main():
         while t_cpu < args.cpu_seconds and done + chunk <= geom.n_pulses // 2:
             p0 = p_mid + done
             ta = time.perf_counter()
-            rc = O.forward(geom, fo, p0, chunk)
+            if args.speckle:
+                rc = O.forward(geom, fo, p0, chunk, speckle=spk,
+                               f_s=W.speckle_doppler(wl.n_facets, wl.seed).astype(np.float64))
+            else:
+                rc = O.forward(geom, fo, p0, chunk)
             line = O.waveform_fft(geom, rc) if chirp else rc
             t_cpu += time.perf_counter() - ta
             rows.append((p0, line))
@@ -332,7 +358,9 @@ def main():
                  if sea.mode == 1 else "synthetic (on-device Philox facets, flat sea)"),
         "config": {"workload": wl.name, "facets": wl.n_facets, "pulses": geom.n_pulses,
                    "samples": geom.n_samples, "channels": geom.n_channels, "chirp": chirp,
-                   "block_edge_m": wl.block_edge, "chunks": len(wl.chunks) or 1},
+                   "block_edge_m": wl.block_edge, "chunks": len(wl.chunks) or 1,
+                   "speckle": ({"tau_s": W.SPECKLE_TAU_S, "f_s_hz": f"+-{W.SPECKLE_FD_HZ}"}
+                               if args.speckle else None)},
         "fwd_adj": fwd_adj,
         "rel_l2_vs_fp64": rel,
         "roofline": roofline,
