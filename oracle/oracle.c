@@ -26,6 +26,10 @@
  *                                      statistical pins only
  *   og_generate_facets                 pinned (closed-form moments, dispersion,
  *                                      d(eta)/dt = w, chunk invariance)
+ *   og_echo_time, rx_exact model       pinned (50-digit mpmath root of the echo
+ *                                      equation, static-receiver case, lone
+ *                                      facet phase/delay shift, finite
+ *                                      differences of the implicit gradient)
  *   og_speckle_anchors, og_speckle_groups
  *                                      pinned (exact covariance of the
  *                                      construction = the AR(1) law of eq. 10;
@@ -64,6 +68,7 @@ typedef struct {
     int ch_tx[OG_MAXC];
     int ch_rx[OG_MAXC];
     double ch_off[OG_MAXC][3];
+    int rx_exact;   /* 1: receiver at each facet's own echo time (see facet_rx) */
 } og_config;
 
 static const double OG_PI = 3.14159265358979323846;
@@ -300,6 +305,43 @@ static void make_row(const og_config *g, int ch, int p, og_row *r) {
 }
 
 /*
+ * Receiver position for the echo of point X (eq. 3 evaluates r_r at the
+ * reception time t_r): the fixed point of
+ *     c tau = |X - P_tx(t_p)| + |X - P_rx(t_p + tau)|,
+ * iterated from tau_ref until it stops changing.  Used when rx_exact is set;
+ * otherwise every facet of a row uses P_rx(t_p + tau_ref) (reading: the
+ * receiver position of the scene origin's echo).
+ */
+static double facet_rx(const og_config *g, int ch, const og_row *r, const double *X,
+                       double *prx) {
+    const double dt[3] = {X[0] - r->ptx[0], X[1] - r->ptx[1], X[2] - r->ptx[2]};
+    const double rt = norm3(dt);
+    double tau = r->tau;
+    for (int it = 0; it < 50; ++it) {
+        rx_pos(g, ch, r->t + tau, prx);
+        const double dr[3] = {X[0] - prx[0], X[1] - prx[1], X[2] - prx[2]};
+        const double nt = (rt + norm3(dr)) / g->c;
+        if (nt == tau) break;
+        tau = nt;
+    }
+    rx_pos(g, ch, r->t + tau, prx);
+    return tau;
+}
+
+/* Echo delay of point X in channel ch, pulse p (rx_exact model). */
+double og_echo_time(const og_config *g, int ch, int p, const double *X) {
+    og_row r;
+    og_pulse_geometry(g, ch, p, &r.t, r.ptx, r.prx, &r.tau);
+    double prx[3];
+    return facet_rx(g, ch, &r, X, prx);
+}
+
+/* Velocity of the receive phase centre of channel ch. */
+static void rx_vel(const og_config *g, int ch, double *v) {
+    for (int k = 0; k < 3; ++k) v[k] = g->plat_v[g->ant_plat[g->ch_rx[ch]]][k];
+}
+
+/*
  * One facet's contribution to one (channel, pulse) row: eq. 3 / eq. 16.
  * Outputs the complex weight W = a * Ftx * Frx * S * exp(j*(phi + dphi)) and
  * the fractional sample position u of the bistatic range in the tracking
@@ -316,11 +358,13 @@ static void contribution(const og_config *g, const og_ctx *cx, int ch, const og_
                          double dphi, double *wre, double *wim, double *u) {
     double X[3];
     for (int k = 0; k < 3; ++k) X[k] = x0[k] + v[k] * r->t;
+    double prx[3] = {r->prx[0], r->prx[1], r->prx[2]};
+    if (g->rx_exact) facet_rx(g, ch, r, X, prx);
     double dt[3] = {X[0] - r->ptx[0], X[1] - r->ptx[1], X[2] - r->ptx[2]};
-    double dr[3] = {X[0] - r->prx[0], X[1] - r->prx[1], X[2] - r->prx[2]};
+    double dr[3] = {X[0] - prx[0], X[1] - prx[1], X[2] - prx[2]};
     double Rt = norm3(dt), Rr = norm3(dr), R = Rt + Rr;
     double ft = gain(&cx->ant[g->ch_tx[ch]], r->ptx, X, NULL);
-    double fr = gain(&cx->ant[g->ch_rx[ch]], r->prx, X, NULL);
+    double fr = gain(&cx->ant[g->ch_rx[ch]], prx, X, NULL);
     double S = (r->rt_mid * r->rr_mid) / (Rt * Rr);
     double phi = -2.0 * OG_PI * g->f0 * R / g->c + dphi;
     double amp = ft * fr * S;
@@ -393,7 +437,8 @@ void og_forward(const og_config *g, long long nf, const double *x, const double 
  * including the Doppler phase; s does not depend on z, V or a)
  *   dL/dX       = Re(P) grad T + [Im(P) T K0 - Re(B' a T E) fs/c] grad R
  *   dL/dz       = sum_p (dL/dX)_z,   dL/dV = sum_p t_p dL/dX
- * where grad R = unit(X - P_tx) + unit(X - P_rx), K0 = 2 pi f0 / c.
+ * where grad R = unit(X - P_tx) + unit(X - P_rx), K0 = 2 pi f0 / c (with
+ * rx_exact, the implicit-function gradient of the facet's own echo time).
  */
 static void adjoint_impl(const og_config *g, long long nf, const double *x, const double *y,
                          const double *z, const double *vx, const double *vy,
@@ -426,12 +471,14 @@ static void adjoint_impl(const og_config *g, long long nf, const double *x, cons
             double ar = are[i] * sr - aim[i] * si, ai = are[i] * si + aim[i] * sr;
             double X[3];
             for (int k = 0; k < 3; ++k) X[k] = X0[k] + V[k] * r->t;
+            double prx[3] = {r->prx[0], r->prx[1], r->prx[2]};
+            if (g->rx_exact) facet_rx(g, ch, r, X, prx);
             double dt[3] = {X[0] - r->ptx[0], X[1] - r->ptx[1], X[2] - r->ptx[2]};
-            double dr[3] = {X[0] - r->prx[0], X[1] - r->prx[1], X[2] - r->prx[2]};
+            double dr[3] = {X[0] - prx[0], X[1] - prx[1], X[2] - prx[2]};
             double Rt = norm3(dt), Rr = norm3(dr), R = Rt + Rr;
             double gft[3], gfr[3];
             double ft = gain(&cx.ant[g->ch_tx[ch]], r->ptx, X, gft);
-            double fr = gain(&cx.ant[g->ch_rx[ch]], r->prx, X, gfr);
+            double fr = gain(&cx.ant[g->ch_rx[ch]], prx, X, gfr);
             double S = (r->rt_mid * r->rr_mid) / (Rt * Rr);
             double T = ft * fr * S;
             double phi = -2.0 * OG_PI * g->f0 * R / g->c + dphi;
@@ -461,12 +508,27 @@ static void adjoint_impl(const og_config *g, long long nf, const double *x, cons
             /* Re(B' a T E) */
             double BpW = T * (Bpr * aEr - Bpi * aEi);
             double cR = Pi * T * K0 - BpW * g->fs / g->c;
+            /* grad R; with the facet's own reception time R is implicit,
+             * R = R_t(X) + |X - P_rx(t_p + R/c)|, so grad R = (u_t + u_r) /
+             * (1 + u_r.V_rx/c), and a function h(X - P_rx) has the total
+             * gradient grad h - grad R (V_rx . grad h)/c */
+            double gR[3], vr[3] = {0, 0, 0}, q = 1.0;
+            if (g->rx_exact) {
+                rx_vel(g, ch, vr);
+                q = 1.0 / (1.0 + (dr[0] * vr[0] + dr[1] * vr[1] + dr[2] * vr[2]) / (Rr * g->c));
+            }
+            for (int k = 0; k < 3; ++k) gR[k] = q * (dt[k] / Rt + dr[k] / Rr);
+            double gSr[3];
+            for (int k = 0; k < 3; ++k) gSr[k] = dr[k] / (Rr * Rr);
+            const double vgfr = (vr[0] * gfr[0] + vr[1] * gfr[1] + vr[2] * gfr[2]) / g->c;
+            const double vgsr = (vr[0] * gSr[0] + vr[1] * gSr[1] + vr[2] * gSr[2]) / g->c;
             double gX[3];
             for (int k = 0; k < 3; ++k) {
-                double rt_k = dt[k] / Rt, rr_k = dr[k] / Rr;
-                double gS = -S * (rt_k / Rt + rr_k / Rr);
-                double gT = fr * S * gft[k] + ft * S * gfr[k] + ft * fr * gS;
-                gX[k] = Pr * gT + cR * (rt_k + rr_k);
+                double rt_k = dt[k] / Rt;
+                double gfr_k = gfr[k] - gR[k] * vgfr;
+                double gS = -S * (rt_k / Rt + gSr[k] - gR[k] * vgsr);
+                double gT = fr * S * gft[k] + ft * S * gfr_k + ft * fr * gS;
+                gX[k] = Pr * gT + cR * gR[k];
             }
             gz += gX[2];
             for (int k = 0; k < 3; ++k) gv[k] += r->t * gX[k];

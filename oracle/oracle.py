@@ -39,6 +39,7 @@ class OgConfig(ctypes.Structure):
         ("n_ch", ctypes.c_int),
         ("ch_tx", ctypes.c_int * MAXC), ("ch_rx", ctypes.c_int * MAXC),
         ("ch_off", _d3 * MAXC),
+        ("rx_exact", ctypes.c_int),
     ]
 
 
@@ -74,6 +75,8 @@ def lib():
         L.og_pulse_time.argtypes = [cfgp, ctypes.c_int]
         L.og_pulse_time.restype = ctypes.c_double
         L.og_pulse_geometry.argtypes = [cfgp, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp]
+        L.og_echo_time.argtypes = [cfgp, ctypes.c_int, ctypes.c_int, dp]
+        L.og_echo_time.restype = ctypes.c_double
         L.og_kappa.argtypes = []
         L.og_kappa.restype = ctypes.c_double
         L.og_antenna_frame.argtypes = [cfgp, ctypes.c_int, dp, dp, dp]
@@ -141,6 +144,7 @@ def make_config(geom) -> OgConfig:
         c.ch_tx[i], c.ch_rx[i] = ch.tx, ch.rx
         for k in range(3):
             c.ch_off[i][k] = ch.pc_offset[k]
+    c.rx_exact = 1 if getattr(geom, "rx_exact", False) else 0
     return c
 
 
@@ -168,6 +172,14 @@ def pulse_geometry(geom, ch: int, p: int):
     lib().og_pulse_geometry(ctypes.byref(cfg), ch, p, _dptr(t), _dptr(ptx), _dptr(prx),
                             _dptr(tau))
     return float(t[0]), ptx, prx, float(tau[0])
+
+
+def echo_time(geom, ch: int, p: int, X) -> float:
+    """Echo delay of point X with the receiver at the echo's own reception
+    time (the fixed point used when geom.rx_exact is set)."""
+    cfg = make_config(geom)
+    X = np.ascontiguousarray(X, np.float64)
+    return lib().og_echo_time(ctypes.byref(cfg), ch, p, _dptr(X))
 
 
 def kappa() -> float:

@@ -91,6 +91,9 @@ class Geometry:
     chirp_bw: float = 0.0
     chirp_T: float = 0.0                # 0 means range-compressed output only
     c: float = C_LIGHT
+    # receiver position: False = at the scene origin's echo time of each
+    # pulse (one position per pulse); True = at each facet's own echo time
+    rx_exact: bool = False
 
     @property
     def n_channels(self) -> int:
