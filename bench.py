@@ -81,6 +81,8 @@ def main():
     ap.add_argument("--serial", action="store_true",
                     help="no step pipelining (one kernel at a time, for per-kernel counters)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--rx-exact", action="store_true",
+                    help="receiver at each facet's own echo time (eq. 3's r_r(t_r))")
     ap.add_argument("--speckle", action="store_true",
                     help="intra-facet speckle (eq. 7, 10): tau_s 20 ms, f_s +-5.7 Hz per facet")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -110,6 +112,9 @@ def main():
     import workloads as W
 
     wl = W.workload(args.workload)
+    if args.rx_exact:
+        from dataclasses import replace as _replace
+        wl = _replace(wl, geometry=_replace(wl.geometry, rx_exact=True))
     geom, sea = wl.geometry, wl.sea
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
@@ -274,7 +279,7 @@ def main():
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
         if (tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == wl.name
-                and bool(tr.get("speckle", False)) == args.speckle):
+                and bool(tr.get("speckle", False)) == args.speckle and not args.rx_exact):
             traffic = tr.get("bytes_per_launch")
             valu = tr.get("valu_insts_per_launch")
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
@@ -360,7 +365,8 @@ def main():
                    "samples": geom.n_samples, "channels": geom.n_channels, "chirp": chirp,
                    "block_edge_m": wl.block_edge, "chunks": len(wl.chunks) or 1,
                    "speckle": ({"tau_s": W.SPECKLE_TAU_S, "f_s_hz": f"+-{W.SPECKLE_FD_HZ}"}
-                               if args.speckle else None)},
+                               if args.speckle else None),
+                   "rx_at_facet_echo_time": args.rx_exact},
         "fwd_adj": fwd_adj,
         "rel_l2_vs_fp64": rel,
         "roofline": roofline,

@@ -113,6 +113,13 @@ typedef struct {
     const sim_antenna *antennas;    /* host, [n_antennas] */
     int n_channels;
     const sim_channel *channels;    /* host, [n_channels] */
+    /* Receiver position (eq. 3 evaluates r_r at the reception time t_r):
+     * 0 = one position per pulse and channel, at the echo time of O;
+     * 1 = at each facet's own echo time, the fixed point of
+     *     c tau = |X - P_tx(t_p)| + |X - P_rx(t_p + tau)|
+     * (solved in FP64 per spatial block and pulse, first order in the
+     * facet's offset from the block centre, error < 1e-9 m). */
+    int rx_exact;
 } sim_config;
 
 /* Facets, structure of arrays, device float32 [n] each. */

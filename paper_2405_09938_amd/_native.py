@@ -46,6 +46,7 @@ class SimConfig(ctypes.Structure):
         ("n_platforms", ctypes.c_int), ("platforms", ctypes.POINTER(SimTraj)),
         ("n_antennas", ctypes.c_int), ("antennas", ctypes.POINTER(SimAntenna)),
         ("n_channels", ctypes.c_int), ("channels", ctypes.POINTER(SimChannel)),
+        ("rx_exact", ctypes.c_int),
     ]
 
 

@@ -481,6 +481,7 @@ int sim_create(const sim_config *cfg, sim_handle **out) {
     h->ants.assign(cfg->antennas, cfg->antennas + cfg->n_antennas);
     h->chans.assign(cfg->channels, cfg->channels + cfg->n_channels);
     h->C = cfg->n_channels;
+    h->rx_exact = cfg->rx_exact ? 1 : 0;
     h->kappa = half_power_kappa();
 
     h->antc.resize(h->ants.size());
@@ -500,6 +501,8 @@ int sim_create(const sim_config *cfg, sim_handle **out) {
         tx_pos(h, ch, 0.0, pt);
         rx_pos(h, ch, 0.0, pr);
         cc.rtrr_mid = norm3(pt) * norm3(pr);
+        const sim_traj &rt = h->plats[h->ants[cc.rx].platform];
+        for (int k = 0; k < 3; ++k) cc.vr[k] = rt.v[k];
     }
     // per (channel, pulse) geometry: echo delay of O by fixed-point iteration
     h->pulses_h.resize((size_t)h->C * h->Np);
@@ -987,6 +990,8 @@ static int forward_common(sim_handle *h, sim_plan *P, const sim_facets *f,
     a.np = np;
     a.n_patches = (int)P->n_patches;
     a.halo = P->halo;
+    a.rx_exact = h->rx_exact;
+    a.inv_c = 1.0 / h->c;
     HS_HIP(hs::launch_forward(a, h->C, P->win, P->el_const, sp != nullptr, s), "forward");
     return SIM_OK;
 }
@@ -1057,6 +1062,8 @@ static int backward_common(sim_handle *h, sim_plan *P, const sim_facets *f,
     a.C = h->C;
     a.n_blocks = P->n_blocks;
     a.accumulate = accumulate ? 1 : 0;
+    a.rx_exact = h->rx_exact;
+    a.inv_c = 1.0 / h->c;
     HS_HIP(hs::launch_adjoint(a, P->el_const, sp != nullptr, s), "adjoint");
     return SIM_OK;
 }

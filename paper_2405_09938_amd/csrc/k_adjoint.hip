@@ -41,12 +41,14 @@ enum {
     R_GTAZ, R_GTEL, R_GRAZ, R_GREL, R_IRT, R_IRT2, R_IRR, R_IRR2, R_SB, R_SBT, R_SBR, R_MASK,
     R_DTGX, R_DTGY, R_DTGZ, R_DBT, R_DBR, R_GRAZE, R_I2S,
     R_J0,        // 9 floats: J[i][j] = d(grad T)_i / dx_j at R_J0 + 3 i + j
-    R_TLO = 40   // t_p - float(t_p) (speckle: the Doppler phase)
+    R_LHI = 40, R_LLO, R_FSQ,   // q f0/c (two floats), q fs/c
+    R_Q,         // q: range-offset factor of the facet's own echo time (1 if off)
+    R_TLO        // t_p - float(t_p) (speckle: the Doppler phase)
 };
 
 // floats per staged pulse record (a multiple of 4)
 template <bool SPK>
-constexpr int kNRef = SPK ? 44 : 40;
+constexpr int kNRef = SPK ? 48 : 44;
 
 // Gradient of one antenna's field pattern at the block centre (FP32 from the
 // FP64 geometry): dF/dX = ka sinc'(ka u) sinc(ke v) (az - u d)/R
@@ -161,12 +163,16 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                 const int pl = ps + lane;
                 const bool live = pl < A.np;
                 const PulseRec &P = PR[live ? pl : A.np - 1];
+                // receiver at the block centre's own echo time (optional)
+                double prb[3] = {P.prx[0], P.prx[1], P.prx[2]};
+                double qr = 1.0;
+                if (A.rx_exact) rx_echo(xb, yb, P.ptx, P.prx, P.rref, chn.vr, A.inv_c, prb, qr);
                 Refs r;
-                block_refs<ELC>(xb, yb, P.ptx, P.prx, P.rref, ta, ra, chn.rtrr_mid, A.f0_c, A.fs_c,
-                           A.n_ref, live, r);
+                block_refs<ELC>(xb, yb, P.ptx, prb, P.rref, ta, ra, chn.rtrr_mid, A.f0_c, A.fs_c,
+                           A.n_ref, live, r, qr);
                 // grad T at the centre
                 const double dt0 = xb - P.ptx[0], dt1 = yb - P.ptx[1], dt2 = -P.ptx[2];
-                const double dr0 = xb - P.prx[0], dr1 = yb - P.prx[1], dr2 = -P.prx[2];
+                const double dr0 = xb - prb[0], dr1 = yb - prb[1], dr2 = -prb[2];
                 float gft[3], gfr[3];
                 const float ft = ant_grad(ta, dt0, dt1, dt2, (double)r.irt, gft);
                 const float fr = ant_grad(ra, dr0, dr1, dr2, (double)r.irr, gfr);
@@ -193,14 +199,18 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                         const double ox = j == 0 ? h : 0.0, oy = j == 1 ? h : 0.0,
                                      oz = j == 2 ? h : 0.0;
                         float gp[3], gm[3];
-                        grad_t(ta, ra, chn.rtrr_mid, xb + ox, yb + oy, oz, P.ptx, P.prx, gp);
-                        grad_t(ta, ra, chn.rtrr_mid, xb - ox, yb - oy, -oz, P.ptx, P.prx, gm);
+                        grad_t(ta, ra, chn.rtrr_mid, xb + ox, yb + oy, oz, P.ptx, prb, gp);
+                        grad_t(ta, ra, chn.rtrr_mid, xb - ox, yb - oy, -oz, P.ptx, prb, gm);
                         o[R_J0 + j] = s2h * (gp[0] - gm[0]);
                         o[R_J0 + 3 + j] = s2h * (gp[1] - gm[1]);
                         o[R_J0 + 6 + j] = s2h * (gp[2] - gm[2]);
                     }
                 }
                 o[R_T] = (float)P.t;
+                o[R_LHI] = r.lhi;
+                o[R_LLO] = r.llo;
+                o[R_FSQ] = r.fsq;
+                o[R_Q] = (float)qr;
                 if constexpr (SPK) o[R_TLO] = (float)(P.t - (double)(float)P.t);
                 o[R_DTX] = r.dtx; o[R_DTY] = r.dty; o[R_DTZ] = r.dtz;
                 o[R_GX] = r.gx; o[R_GY] = r.gy; o[R_GZ] = r.gz;
@@ -266,8 +276,8 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                     dop = __builtin_amdgcn_fractf(dh) + dl;
                 }
                 Geo g;
-                facet_geo<ELC, SPK>(r, kc, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz, r.graze != 0, A.linv_hi,
-                          A.linv_lo, A.fs_cf, dop, g);
+                facet_geo<ELC, SPK>(r, kc, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz, r.graze != 0,
+                               o[R_LHI], o[R_LLO], o[R_FSQ], dop, g);
                 float tap[8], dtap[8];
                 taps_d8(tv, g.f, tap, dtap);
                 // g at samples floor(u) - 3 .. floor(u) + 4
@@ -310,7 +320,8 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                 const float pi = fmaf(br, aei, bi * aer);
                 // Re(B_u a E) T
                 const float bu = fmaf(dr, aer, -(di * aei)) * T;
-                const float cR = fmaf(pi * T, A.k0, bu * A.fs_cf);
+                // grad R carries q with the facet's own echo time
+                const float cR = fmaf(pi * T, A.k0, bu * A.fs_cf) * o[R_Q];
                 // grad R = g (1 - c2) + e (1/R_t + 1/R_r) - d_t (c1 - c2),
                 // c1 = (e.d_t)/R_t, c2 = (e.d_r)/R_r, d_r = g - d_t
                 const float c1 = g.at * r.irt, c2 = g.ar * r.irr;

@@ -205,8 +205,13 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
     for (int b = b0; b < b1; ++b) {
         const BlockRec blk = load_block(blocks + b);
         Refs r;
-        block_refs<ELC>((double)blk.xb, (double)blk.yb, ptx, prx, rref, ta, ra, chn.rtrr_mid, A.f0_c,
-                   A.fs_c, A.n_ref, live, r);
+        // receiver at the block centre's own echo time (optional)
+        double prb[3] = {prx[0], prx[1], prx[2]};
+        double qr = 1.0;
+        if (A.rx_exact)
+            rx_echo((double)blk.xb, (double)blk.yb, ptx, prx, rref, A.ch[ch].vr, A.inv_c, prb, qr);
+        block_refs<ELC>((double)blk.xb, (double)blk.yb, ptx, prb, rref, ta, ra, chn.rtrr_mid, A.f0_c,
+                   A.fs_c, A.n_ref, live, r, qr);
         const bool graze_any = __any(r.graze);
         // the window offset of the first tap rides in the sample fraction, so
         // the floor of the sample position is the window index directly
@@ -246,8 +251,8 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
                 dop = __builtin_amdgcn_fractf(dh) + dl;
             }
             Geo g;
-            facet_geo<ELC, SPK>(r, kc, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz, graze_any, A.linv_hi,
-                      A.linv_lo, A.fs_cf, dop, g);
+            facet_geo<ELC, SPK>(r, kc, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz, graze_any, r.lhi,
+                      r.llo, r.fsq, dop, g);
             // Each lane owns its pulse row, so the deposit is a plain
             // read-modify-write of 8 consecutive complex samples.
             const int n0 = g.fl;                  // window index of the first tap

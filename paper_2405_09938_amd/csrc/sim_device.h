@@ -56,7 +56,36 @@ struct Refs {
     float mask;                     // 1 if the lane's pulse is live and in front
     float dbt, dbr;                 // D . b per leg (grazing blocks only)
     int graze;                      // block straddles an antenna's back plane
+    float lhi, llo;                 // q f0/c split in two floats (phase of dR)
+    float fsq;                      // q fs/c (sample shift of dR)
 };
+
+// Receiver at the echo time of the block centre x_b (eq. 3 takes r_r at the
+// reception time): fixed point of c tau = |x_b - P_tx| + |x_b - P_rx(t_p + tau)|
+// started from the origin's echo (prx = P_rx(t_p + tau_ref), rref = c
+// tau_ref), P_rx moving at vr.  Each step gains a factor ~|vr|/c ~ 3e-5, so
+// three leave ~1e-13 m.  A facet at offset e from x_b has its own echo time;
+// to first order its range offset is q times the one computed with the
+// centre's receiver position, q = 1 / (1 + u_r . vr / c) (u_r: receiver ->
+// centre), the neglected terms ~(e/R)(|vr|/c) e < 1e-9 m.
+__device__ __forceinline__ void rx_echo(double xb, double yb, const double *ptx,
+                                        const double *prx, double rref, const double *vr,
+                                        double inv_c, double *pr, double &q) {
+    const double a0 = xb - ptx[0], a1 = yb - ptx[1], a2 = -ptx[2];
+    const double rt = sqrt(a0 * a0 + a1 * a1 + a2 * a2);
+    double dtau = 0.0;
+#pragma unroll
+    for (int it = 0; it < 3; ++it) {
+        const double d0 = xb - (prx[0] + vr[0] * dtau), d1 = yb - (prx[1] + vr[1] * dtau);
+        const double d2 = -(prx[2] + vr[2] * dtau);
+        dtau = (rt + sqrt(d0 * d0 + d1 * d1 + d2 * d2) - rref) * inv_c;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) pr[k] = prx[k] + vr[k] * dtau;
+    const double d0 = xb - pr[0], d1 = yb - pr[1], d2 = -pr[2];
+    const double ir = 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    q = 1.0 / (1.0 + (d0 * vr[0] + d1 * vr[1] + d2 * vr[2]) * ir * inv_c);
+}
 
 // ELC: the elevation pattern factors of both legs are taken at the block
 // centre and folded into the spreading terms (chosen on the host only where
@@ -65,7 +94,8 @@ template <bool ELC>
 __device__ __forceinline__ void block_refs(double xb, double yb, const double *ptx,
                                            const double *prx, double rref, const AntArgs &t,
                                            const AntArgs &q, double rtrr_mid, double f0_c,
-                                           double fs_c, double n_ref, bool live, Refs &r) {
+                                           double fs_c, double n_ref, bool live, Refs &r,
+                                           double qr = 1.0) {
     const double dt0 = xb - ptx[0], dt1 = yb - ptx[1], dt2 = -ptx[2];
     const double dr0 = xb - prx[0], dr1 = yb - prx[1], dr2 = -prx[2];
     const double rt = sqrt(dt0 * dt0 + dt1 * dt1 + dt2 * dt2);
@@ -85,6 +115,10 @@ __device__ __forceinline__ void block_refs(double xb, double yb, const double *p
     const double rb = rt + rr;
     const double cyc = rb * f0_c;
     r.phib = (float)(rint(cyc) - cyc);
+    const double lq = qr * f0_c;
+    r.lhi = (float)lq;
+    r.llo = (float)(lq - (double)r.lhi);
+    r.fsq = (float)(qr * fs_c);
     const double ub = n_ref + (rb - rref) * fs_c;
     const double fl = floor(ub);
     r.fb = (float)(ub - fl);

@@ -69,6 +69,7 @@ struct AntArgs {
 struct ChanArgs {
     int tx, rx;                 // antenna indices
     double rtrr_mid;            // R_t,mid * R_r,mid
+    double vr[3];               // velocity of the receive phase centre
 };
 
 // Intra-facet speckle (Sec. III.A eq. 7, eq. 10).  Per sorted facet: the
@@ -107,6 +108,8 @@ struct FwdArgs {
     int N, Np, p0, np;
     int n_patches;
     int halo;                   // bins added on each side of the patch span
+    int rx_exact;               // receiver at each facet's own echo time
+    double inv_c;               // 1 / c
     SpkArgs spk;                // speckle variant only
 };
 
@@ -126,6 +129,8 @@ struct AdjArgs {
     int N, Np, p0, np, C;
     long long n_blocks;
     int accumulate;
+    int rx_exact;               // receiver at each facet's own echo time
+    double inv_c;               // 1 / c
     SpkArgs spk;                // speckle variant only
 };
 
@@ -143,6 +148,7 @@ struct sim_handle {
     std::vector<sim_antenna> ants;
     std::vector<sim_channel> chans;
     int C;
+    int rx_exact;
     // derived on the host in FP64
     double kappa;
     std::vector<hs::AntArgs> antc;
@@ -243,6 +249,7 @@ hipError_t launch_speckle_prep(const SpkPrep &p, const SpkArgs &k, SpkRec *rec, 
 hipError_t launch_forward(const FwdArgs &a, int C, int win, bool el_const, bool speckle,
                           hipStream_t s);
 hipError_t launch_adjoint(const AdjArgs &a, bool el_const, bool speckle, hipStream_t s);
+// (the adjoint picks its reception-time variant from a.rx_exact)
 hipError_t launch_waveform(const float *in, float *out, long long n_lines, int N, int M,
                            int shift, const float *spec, const float *tw, int adjoint,
                            hipStream_t s);

@@ -66,6 +66,7 @@ class Simulator:
         cfg.n_platforms, cfg.platforms = len(g.platforms), self._plats
         cfg.n_antennas, cfg.antennas = len(g.antennas), self._ants
         cfg.n_channels, cfg.channels = len(g.channels), self._chans
+        cfg.rx_exact = 1 if getattr(g, "rx_exact", False) else 0
         h = ctypes.c_void_p()
         N.check(self.lib.sim_create(ctypes.byref(cfg), ctypes.byref(h)), "sim_create")
         self.handle = h
