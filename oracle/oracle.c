@@ -25,7 +25,11 @@
  *                                      external known-answer vectors);
  *                                      statistical pins only
  *   og_generate_facets                 pinned (closed-form moments, dispersion,
- *                                      d(eta)/dt = w, chunk invariance)
+ *                                      d(eta)/dt = w, chunk invariance; tiles of
+ *                                      eq. 1-2: corner fields, squared weights
+ *                                      summing to one, variance kept; CWM:
+ *                                      trochoid mean level and excursion,
+ *                                      displacement rate = velocity)
  *   og_echo_time, rx_exact model       pinned (50-digit mpmath root of the echo
  *                                      equation, static-receiver case, lone
  *                                      facet phase/delay shift, finite
@@ -677,6 +681,17 @@ typedef struct {
     const double *dirs;    /* [n_comp] propagation directions */
     const double *phases;  /* [n_comp] initial phases */
     double cur[2];         /* uniform current */
+    /* mode 2, heterogeneous sea (eq. 1, 2): TL tiles of side tile_L, corner
+     * node (i, j) at (tile_x0 + i L, tile_y0 + j L), i <= ntx, j <= nty, each
+     * with its own homogeneous field (T2L tile): significant height
+     * node_hs[j (ntx+1) + i], directions and phases node_dirs / node_phases
+     * [node][n_comp]; k range, slope and g shared */
+    int ntx, nty;
+    double tile_L, tile_x0, tile_y0;
+    const double *node_hs;
+    const double *node_dirs;
+    const double *node_phases;
+    int cwm;               /* Choppy Wave Model horizontal displacement */
 } og_sea;
 
 /*
@@ -701,6 +716,31 @@ void og_wave_table(const og_sea *s, double *k, double *amp, double *omega) {
 }
 
 /*
+ * Linear wave field of one homogeneous tile at the point at rest (X, Y),
+ * added to D with weight Wt: height eta = sum A cos(theta), theta =
+ * k (cos psi X + sin psi Y) + phase; Choppy Wave Model horizontal
+ * displacement -sum A (cos psi, sin psi) sin(theta) (Sec. III: grid points
+ * follow the orbital motion); velocity = the time derivative of the
+ * displacement: sum A omega (cos psi, sin psi) cos(theta) horizontally and
+ * sum A omega sin(theta) vertically.
+ */
+static void wave_field(int n, const double *k, const double *amp, const double *om,
+                       const double *dirs, const double *phases, double X, double Y,
+                       double *D, double Wt) {
+    for (int m = 0; m < n; ++m) {
+        double cp = cos(dirs[m]), sp = sin(dirs[m]);
+        double th = k[m] * (cp * X + sp * Y) + phases[m];
+        double ct = cos(th), st = sin(th);
+        D[0] += Wt * amp[m] * ct;
+        D[1] -= Wt * amp[m] * cp * st;
+        D[2] -= Wt * amp[m] * sp * st;
+        D[3] += Wt * amp[m] * om[m] * cp * ct;
+        D[4] += Wt * amp[m] * om[m] * sp * ct;
+        D[5] += Wt * amp[m] * om[m] * st;
+    }
+}
+
+/*
  * Facets of the sub-rectangle [ix0, ix0+cnx) x [iy0, iy0+cny), row-major.
  * Global index = iy*nx + ix is the Philox counter, so any chunking of the grid
  * yields the same facets.
@@ -710,6 +750,11 @@ void og_wave_table(const og_sea *s, double *k, double *amp, double *omega) {
  *           horizontal orbital velocity sum A omega (cos psi, sin psi) cos(theta)
  *           plus the current, vertical velocity sum A omega sin(theta)
  *           (= d(eta)/dt at the surface).
+ *   mode 2: the heterogeneous surface of eq. 1: in the TL tile holding the
+ *           point, the fields of its four corner nodes weighted by eq. 2
+ *           (points outside the node lattice use its border tiles).
+ *   cwm:    the facet sits at its rest position plus the weighted horizontal
+ *           displacement (Choppy Wave Model); z and V as above.
  * out: 8 arrays of cnx*cny doubles: x, y, z, vx, vy, vz, a_re, a_im.
  */
 void og_generate_facets(const og_sea *s, uint64_t seed, int ix0, int iy0, int cnx,
@@ -719,7 +764,18 @@ void og_generate_facets(const og_sea *s, uint64_t seed, int ix0, int iy0, int cn
     double *k = (double *)malloc(sizeof(double) * nc);
     double *amp = (double *)malloc(sizeof(double) * nc);
     double *om = (double *)malloc(sizeof(double) * nc);
-    if (s->mode == 1) og_wave_table(s, k, amp, om);
+    double *namp = NULL;
+    if (s->mode >= 1) og_wave_table(s, k, amp, om);
+    if (s->mode == 2) {
+        /* each node's amplitudes: the same spectrum shape at its own Hs */
+        const int nn = (s->ntx + 1) * (s->nty + 1);
+        namp = (double *)malloc(sizeof(double) * (size_t)nn * (size_t)nc);
+        og_sea one = *s;
+        for (int q = 0; q < nn; ++q) {
+            one.hs = s->node_hs[q];
+            og_wave_table(&one, k, namp + (size_t)q * (size_t)nc, om);
+        }
+    }
     long long n = (long long)cnx * cny;
 #pragma omp parallel for schedule(static)
     for (long long j = 0; j < n; ++j) {
@@ -741,25 +797,42 @@ void og_generate_facets(const og_sea *s, uint64_t seed, int ix0, int iy0, int cn
             vy[j] = s->sigma_v * nr[3];
             vz[j] = s->sigma_v * n2[0];
         } else {
-            double h = 0, ux = 0, uy = 0, w = 0;
-            for (int m = 0; m < s->n_comp; ++m) {
-                double cp = cos(s->dirs[m]), sp = sin(s->dirs[m]);
-                double th = k[m] * (cp * X + sp * Y) + s->phases[m];
-                double ct = cos(th), st = sin(th);
-                h += amp[m] * ct;
-                ux += amp[m] * om[m] * cp * ct;
-                uy += amp[m] * om[m] * sp * ct;
-                w += amp[m] * om[m] * st;
+            /* displacement and velocity of the point at rest (X, Y): one
+             * homogeneous field (mode 1) or the weighted sum of eq. 1 */
+            double D[6] = {0, 0, 0, 0, 0, 0};   /* eta, dx, dy, u, v, w */
+            if (s->mode == 1) {
+                wave_field(s->n_comp, k, amp, om, s->dirs, s->phases, X, Y, D, 1.0);
+            } else {
+                int ti = (int)floor((X - s->tile_x0) / s->tile_L);
+                int tj = (int)floor((Y - s->tile_y0) / s->tile_L);
+                if (ti > s->ntx - 1) ti = s->ntx - 1;
+                if (tj > s->nty - 1) tj = s->nty - 1;
+                if (ti < 0) ti = 0;
+                if (tj < 0) tj = 0;
+                for (int c = 0; c < 4; ++c) {
+                    const int ni = ti + (c & 1), nj = tj + (c >> 1);
+                    const double xi = s->tile_x0 + ni * s->tile_L, yi = s->tile_y0 + nj * s->tile_L;
+                    /* eq. 2 */
+                    const double wx = fabs(xi - X) / s->tile_L, wy = fabs(yi - Y) / s->tile_L;
+                    const double Wt = sqrt(fmax(0.0, 1.0 - wx - wy + wx * wy));
+                    const int node = nj * (s->ntx + 1) + ni;
+                    const double *na = namp + (size_t)node * (size_t)nc;
+                    wave_field(s->n_comp, k, na, om, s->node_dirs + (size_t)node * s->n_comp,
+                               s->node_phases + (size_t)node * s->n_comp, X, Y, D, Wt);
+                }
             }
-            z[j] = h;
-            vx[j] = ux + s->cur[0];
-            vy[j] = uy + s->cur[1];
-            vz[j] = w;
+            x[j] = s->cwm ? X + D[1] : X;
+            y[j] = s->cwm ? Y + D[2] : Y;
+            z[j] = D[0];
+            vx[j] = D[3] + s->cur[0];
+            vy[j] = D[4] + s->cur[1];
+            vz[j] = D[5];
         }
     }
     free(k);
     free(amp);
     free(om);
+    free(namp);
 }
 
 /* ---- Intra-facet speckle (Sec. III.A eq. 7, eq. 9, eq. 10) ------------- */

@@ -54,6 +54,12 @@ class OgSea(ctypes.Structure):
         ("dirs", ctypes.POINTER(ctypes.c_double)),
         ("phases", ctypes.POINTER(ctypes.c_double)),
         ("cur", ctypes.c_double * 2),
+        ("ntx", ctypes.c_int), ("nty", ctypes.c_int),
+        ("tile_L", ctypes.c_double), ("tile_x0", ctypes.c_double), ("tile_y0", ctypes.c_double),
+        ("node_hs", ctypes.POINTER(ctypes.c_double)),
+        ("node_dirs", ctypes.POINTER(ctypes.c_double)),
+        ("node_phases", ctypes.POINTER(ctypes.c_double)),
+        ("cwm", ctypes.c_int),
     ]
 
 
@@ -386,6 +392,15 @@ def _make_sea(sea):
         ph = np.ascontiguousarray(sea.phases, np.float64)
         keep = [d, ph]
         s.dirs, s.phases = _dptr(d), _dptr(ph)
+    if sea.mode == 2:
+        hs = np.ascontiguousarray(sea.node_hs, np.float64).ravel()
+        d = np.ascontiguousarray(sea.node_dirs, np.float64).ravel()
+        ph = np.ascontiguousarray(sea.node_phases, np.float64).ravel()
+        keep = [hs, d, ph]
+        s.ntx, s.nty = sea.ntx, sea.nty
+        s.tile_L, s.tile_x0, s.tile_y0 = sea.tile_L, sea.tile_x0, sea.tile_y0
+        s.node_hs, s.node_dirs, s.node_phases = _dptr(hs), _dptr(d), _dptr(ph)
+    s.cwm = 1 if getattr(sea, "cwm", False) else 0
     s.cur[0], s.cur[1] = sea.current
     return s, keep
 

@@ -110,6 +110,10 @@ class Sea:
 
     ``mode`` 0: flat sea, z = 0, velocities N(0, sigma_v^2) per axis.
     ``mode`` 1: 64 linear wave components plus a uniform current.
+    ``mode`` 2: heterogeneous sea: square tiles of side ``tile_L`` whose
+    corner nodes (``ntx + 1`` x ``nty + 1``, from ``tile_x0, tile_y0``) each
+    carry their own significant height, component directions and phases.
+    ``cwm``: facets displaced horizontally (Choppy Wave Model).
     Random draws of the method (component directions and phases) are inputs.
     """
     nx: int
@@ -127,6 +131,15 @@ class Sea:
     dirs: Optional[np.ndarray] = None   # [n_comp] propagation directions (rad)
     phases: Optional[np.ndarray] = None  # [n_comp] initial phases (rad)
     current: Tuple[float, float] = (0.0, 0.0)
+    ntx: int = 0
+    nty: int = 0
+    tile_L: float = 0.0
+    tile_x0: float = 0.0
+    tile_y0: float = 0.0
+    node_hs: Optional[np.ndarray] = None      # [(ntx+1)(nty+1)]
+    node_dirs: Optional[np.ndarray] = None    # [(ntx+1)(nty+1), n_comp]
+    node_phases: Optional[np.ndarray] = None  # [(ntx+1)(nty+1), n_comp]
+    cwm: bool = False
 
 
 def harmony_geometry(n_pulses: int, n_samples: int, receivers: str = "A",
@@ -221,6 +234,39 @@ def wave_sea(nx: int, ny: int, dx: float, seed: int, current_speed: float = 0.0,
     cur = (current_speed * math.cos(h), current_speed * math.sin(h))
     return Sea(nx=nx, ny=ny, dx=dx, dy=dx, mode=1, n_comp=n_comp,
                dirs=d["dirs"], phases=d["phases"], current=cur)
+
+
+def hetero_sea(nx: int, ny: int, dx: float, seed: int, tile_L: float,
+               hs_range: Tuple[float, float] = (1.0, 3.0), turn_deg: float = 90.0,
+               current_speed: float = 0.0, cwm: bool = True,
+               n_comp: int = SEA_N_COMP) -> Sea:
+    """Heterogeneous sea over the grid: tiles of side tile_L covering it, the
+    node significant height growing linearly in x over hs_range and the mean
+    wave direction turning by turn_deg across the scene in y (the kind of
+    sharply varying swell field the tiling is meant for); every node draws its
+    own directions (mean + N(0, 25 deg)) and phases."""
+    ntx = max(1, math.ceil((nx - 1) * dx / tile_L))
+    nty = max(1, math.ceil((ny - 1) * dx / tile_L))
+    x0 = -0.5 * ntx * tile_L
+    y0 = -0.5 * nty * tile_L
+    rng = np.random.default_rng(20_000 + seed)
+    psi0 = rng.uniform(0.0, 2 * math.pi)
+    nn = (ntx + 1) * (nty + 1)
+    hs = np.empty(nn)
+    dirs = np.empty((nn, n_comp))
+    phases = np.empty((nn, n_comp))
+    for j in range(nty + 1):
+        for i in range(ntx + 1):
+            q = j * (ntx + 1) + i
+            hs[q] = hs_range[0] + (hs_range[1] - hs_range[0]) * i / ntx
+            mean = psi0 + math.radians(turn_deg) * j / nty
+            dirs[q] = mean + np.radians(SEA_DIR_SPREAD_DEG) * rng.standard_normal(n_comp)
+            phases[q] = rng.uniform(0.0, 2 * math.pi, n_comp)
+    h = rng.uniform(0.0, 2 * math.pi)
+    cur = (current_speed * math.cos(h), current_speed * math.sin(h))
+    return Sea(nx=nx, ny=ny, dx=dx, dy=dx, mode=2, n_comp=n_comp, current=cur,
+               ntx=ntx, nty=nty, tile_L=tile_L, tile_x0=x0, tile_y0=y0,
+               node_hs=hs, node_dirs=dirs, node_phases=phases, cwm=cwm)
 
 
 def flat_sea(nx: int, ny: int, dx: float, sigma_v: float = 0.5) -> Sea:
