@@ -151,7 +151,21 @@ typedef struct {
  *          scaled to significant height hs, deep-water dispersion with
  *          gravity g; directions and phases are given (host arrays); the
  *          facet moves with the first-order orbital velocity plus `current`.
- *  Complex amplitudes are CN(0, 1) in both modes.
+ *  mode 2: heterogeneous sea (Sec. III eq. 1, 2): the plane is cut into
+ *          square TL tiles of side tile_L whose corners form a lattice of
+ *          (ntx + 1) x (nty + 1) nodes, node (i, j) at (tile_x0 + i tile_L,
+ *          tile_y0 + j tile_L), index j (ntx + 1) + i.  Each node carries its
+ *          own homogeneous field as in mode 1 (a T2L tile: significant height
+ *          node_hs[node], directions node_dirs[node][m], phases
+ *          node_phases[node][m]; k range, slope and g shared).  A facet sums
+ *          the fields of the four corners of its TL tile with weights
+ *          W = sqrt((1 - |x_i - x| / L)(1 - |y_i - y| / L)).  The lattice
+ *          must cover the whole grid.
+ *  cwm:    (modes 1, 2) Choppy Wave Model: each facet is moved from its
+ *          grid point by the horizontal displacement
+ *          -sum A (cos psi, sin psi) sin(theta); z and V are those of the
+ *          point at rest (the facets follow the orbital motion).
+ *  Complex amplitudes are CN(0, 1) in every mode.
  */
 typedef struct {
     int nx, ny;
@@ -163,6 +177,12 @@ typedef struct {
     const double *dirs;     /* host, [n_comp] propagation directions (rad) */
     const double *phases;   /* host, [n_comp] initial phases (rad) */
     double current[2];      /* uniform surface current (m/s) */
+    int ntx, nty;           /* mode 2: TL tiles along x, y */
+    double tile_L, tile_x0, tile_y0;   /* mode 2: tile side (m), lattice origin (m) */
+    const double *node_hs;       /* mode 2, host [(ntx+1)(nty+1)] */
+    const double *node_dirs;     /* mode 2, host [(ntx+1)(nty+1)][n_comp] (rad) */
+    const double *node_phases;   /* mode 2, host [(ntx+1)(nty+1)][n_comp] (rad) */
+    int cwm;                /* 1: Choppy Wave Model horizontal displacement */
 } sim_sea;
 
 /*

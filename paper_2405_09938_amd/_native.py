@@ -73,6 +73,12 @@ class SimSea(ctypes.Structure):
         ("hs", ctypes.c_double), ("g", ctypes.c_double),
         ("dirs", ctypes.POINTER(ctypes.c_double)), ("phases", ctypes.POINTER(ctypes.c_double)),
         ("current", ctypes.c_double * 2),
+        ("ntx", ctypes.c_int), ("nty", ctypes.c_int),
+        ("tile_L", ctypes.c_double), ("tile_x0", ctypes.c_double), ("tile_y0", ctypes.c_double),
+        ("node_hs", ctypes.POINTER(ctypes.c_double)),
+        ("node_dirs", ctypes.POINTER(ctypes.c_double)),
+        ("node_phases", ctypes.POINTER(ctypes.c_double)),
+        ("cwm", ctypes.c_int),
     ]
 
 

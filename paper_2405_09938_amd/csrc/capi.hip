@@ -832,7 +832,7 @@ int sim_generate_facets(sim_handle *h, const sim_sea *sea, unsigned long long se
     if (out->n > 0 && (!out->x || !out->y || !out->z || !out->vx || !out->vy || !out->vz ||
                        !out->a_re || !out->a_im))
         HS_FAIL(SIM_EINVAL, "an output array pointer is NULL");
-    if (sea->mode != 0 && sea->mode != 1) HS_FAIL(SIM_EINVAL, "sea mode must be 0 or 1");
+    if (sea->mode < 0 || sea->mode > 2) HS_FAIL(SIM_EINVAL, "sea mode must be 0, 1 or 2");
     hs::GenArgs a{};
     a.nx = sea->nx;
     a.ny = sea->ny;
@@ -849,33 +849,67 @@ int sim_generate_facets(sim_handle *h, const sim_sea *sea, unsigned long long se
     a.cur0 = sea->current[0];
     a.cur1 = sea->current[1];
     a.n_comp = 0;
-    if (sea->mode == 1) {
+    a.cwm = sea->cwm ? 1 : 0;
+    if (sea->mode >= 1) {
         const int nc = sea->n_comp;
-        if (nc < 1 || nc > 4096 || !sea->dirs || !sea->phases)
-            HS_FAIL(SIM_EINVAL, "mode 1 needs 1..4096 components with dirs and phases");
-        if (!(sea->k_min > 0) || !(sea->k_max >= sea->k_min) || !(sea->hs >= 0) || !(sea->g > 0))
+        if (nc < 1 || nc > 4096)
+            HS_FAIL(SIM_EINVAL, "wave modes need 1..4096 components");
+        if (!(sea->k_min > 0) || !(sea->k_max >= sea->k_min) || !(sea->g > 0))
             HS_FAIL(SIM_EINVAL, "bad wave spectrum parameters");
-        // wavenumbers log-spaced on [k_min, k_max]; A_m^2 = 2 Psi(k_m) dk_m with
-        // Psi ~ k^slope and dk_m = k_m dlnk, scaled so sum A_m^2 / 2 = (hs/4)^2;
-        // omega^2 = g k (deep water)
-        std::vector<double> &tab = h->gen_tab_h;
-        tab.assign((size_t)6 * nc, 0.0);
-        const double dl = nc > 1 ? std::log(sea->k_max / sea->k_min) / (nc - 1) : 1.0;
-        double energy = 0.0;
-        for (int m = 0; m < nc; ++m) {
-            const double k = nc > 1 ? sea->k_min * std::exp(dl * m) : sea->k_min;
-            const double A = std::sqrt(2.0 * std::pow(k, sea->slope) * k * dl);
-            energy += 0.5 * A * A;
-            double *t = &tab[6 * m];
-            t[0] = k;
-            t[1] = A;
-            t[2] = std::sqrt(sea->g * k);
-            t[3] = std::cos(sea->dirs[m]);
-            t[4] = std::sin(sea->dirs[m]);
-            t[5] = sea->phases[m];
+        // one table per homogeneous field: mode 1 has one, mode 2 one per node
+        int nodes = 1;
+        const double *hs_of = &sea->hs;
+        const double *dirs = sea->dirs, *phases = sea->phases;
+        if (sea->mode == 1) {
+            if (!sea->dirs || !sea->phases || !(sea->hs >= 0))
+                HS_FAIL(SIM_EINVAL, "mode 1 needs dirs, phases and hs >= 0");
+        } else {
+            if (sea->ntx < 1 || sea->nty < 1 || !(sea->tile_L > 0) || !sea->node_hs ||
+                !sea->node_dirs || !sea->node_phases)
+                HS_FAIL(SIM_EINVAL, "mode 2 needs ntx, nty >= 1, tile_L > 0 and node arrays");
+            nodes = (sea->ntx + 1) * (sea->nty + 1);
+            if ((long long)nodes * nc > (1LL << 22)) HS_FAIL(SIM_EINVAL, "too many node components");
+            // the lattice must cover the grid
+            const double hx = 0.5 * (sea->nx - 1) * sea->dx, hy = 0.5 * (sea->ny - 1) * sea->dy;
+            if (sea->tile_x0 > -hx || sea->tile_y0 > -hy ||
+                sea->tile_x0 + sea->ntx * sea->tile_L < hx ||
+                sea->tile_y0 + sea->nty * sea->tile_L < hy)
+                HS_FAIL(SIM_EINVAL, "mode 2: the tile lattice does not cover the grid");
+            for (int q = 0; q < nodes; ++q)
+                if (!(sea->node_hs[q] >= 0)) HS_FAIL(SIM_EINVAL, "mode 2: node_hs must be >= 0");
+            hs_of = sea->node_hs;
+            dirs = sea->node_dirs;
+            phases = sea->node_phases;
+            a.ntx = sea->ntx;
+            a.nty = sea->nty;
+            a.tile_L = sea->tile_L;
+            a.tile_x0 = sea->tile_x0;
+            a.tile_y0 = sea->tile_y0;
         }
-        const double scale = energy > 0 ? (sea->hs / 4.0) / std::sqrt(energy) : 0.0;
-        for (int m = 0; m < nc; ++m) tab[6 * m + 1] *= scale;
+        // wavenumbers log-spaced on [k_min, k_max]; A_m^2 = 2 Psi(k_m) dk_m with
+        // Psi ~ k^slope and dk_m = k_m dlnk, scaled so sum A_m^2 / 2 = (hs/4)^2
+        // per field; omega^2 = g k (deep water)
+        std::vector<double> &tab = h->gen_tab_h;
+        tab.assign((size_t)6 * nc * nodes, 0.0);
+        const double dl = nc > 1 ? std::log(sea->k_max / sea->k_min) / (nc - 1) : 1.0;
+        for (int q = 0; q < nodes; ++q) {
+            double energy = 0.0;
+            double *tq = &tab[(size_t)6 * nc * q];
+            for (int m = 0; m < nc; ++m) {
+                const double k = nc > 1 ? sea->k_min * std::exp(dl * m) : sea->k_min;
+                const double A = std::sqrt(2.0 * std::pow(k, sea->slope) * k * dl);
+                energy += 0.5 * A * A;
+                double *t = tq + 6 * m;
+                t[0] = k;
+                t[1] = A;
+                t[2] = std::sqrt(sea->g * k);
+                t[3] = std::cos(dirs[(size_t)q * nc + m]);
+                t[4] = std::sin(dirs[(size_t)q * nc + m]);
+                t[5] = phases[(size_t)q * nc + m];
+            }
+            const double scale = energy > 0 ? (hs_of[q] / 4.0) / std::sqrt(energy) : 0.0;
+            for (int m = 0; m < nc; ++m) tq[6 * m + 1] *= scale;
+        }
         hipStream_t s = (hipStream_t)stream;
         if (h->gen_tab_cap < tab.size()) {
             // the previous table may still be read by queued work on this stream

@@ -1,8 +1,11 @@
 // On-device facet generation on a regular grid: the scene is produced where
 // and when it is sensed (Sec. II.B) instead of being stored, tile by tile
 // (Sec. IV.B).  The resolved sea surface is a sum of linear wave components
-// (Sec. III, CWM option off); facets follow its first-order orbital motion
-// plus a uniform current; complex amplitudes are circular Gaussian with
+// (Sec. III), either one homogeneous field or the heterogeneous combination
+// of eq. 1-2 (four overlapping fields per tile), optionally with the Choppy
+// Wave Model's horizontal displacement; facets follow the first-order
+// orbital motion plus a uniform current; complex amplitudes are circular
+// Gaussian with
 // <|a|^2> = 1 (the statistics of the intra-facet speckle of eq. 7 at t = 0,
 // held constant over the dwell).
 //
@@ -53,6 +56,28 @@ __device__ __forceinline__ void normals4(unsigned long long seed, unsigned long 
     }
 }
 
+// One homogeneous field (table rows k, A, omega, cos psi, sin psi, phase) at
+// the point at rest (X, Y), added with weight wgt: height sum A cos(theta),
+// theta = k (cos psi X + sin psi Y) + phase; horizontal displacement of the
+// Choppy Wave Model -sum A (cos psi, sin psi) sin(theta); velocity its time
+// derivative, sum A omega (cos psi, sin psi) cos(theta) and sum A omega
+// sin(theta).  FP64 throughout.
+__device__ void wave_field(const double *tab, int n, double X, double Y, double wgt, double *D) {
+    for (int m = 0; m < n; ++m) {
+        const double *t = tab + 6 * m;
+        const double th = t[0] * (t[3] * X + t[4] * Y) + t[5];
+        double st, ct;
+        sincos(th, &st, &ct);
+        const double a = wgt * t[1], aw = a * t[2];
+        D[0] += a * ct;
+        D[1] -= a * t[3] * st;
+        D[2] -= a * t[4] * st;
+        D[3] += aw * t[3] * ct;
+        D[4] += aw * t[4] * ct;
+        D[5] += aw * st;
+    }
+}
+
 __global__ void k_generate(GenArgs A) {
     const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long n = (long long)A.cnx * A.cny;
@@ -76,22 +101,32 @@ __global__ void k_generate(GenArgs A) {
         A.out.vy[j] = (float)(A.sigma_v * nr[3]);
         A.out.vz[j] = (float)(A.sigma_v * n2[0]);
     } else {
-        double h = 0.0, ux = 0.0, uy = 0.0, w = 0.0;
-        for (int m = 0; m < A.n_comp; ++m) {
-            const double *t = A.tab + 6 * m;   // k, A, omega, cos psi, sin psi, phase
-            const double th = t[0] * (t[3] * X + t[4] * Y) + t[5];
-            double st, ct;
-            sincos(th, &st, &ct);
-            const double aw = t[1] * t[2];
-            h += t[1] * ct;
-            ux += aw * t[3] * ct;
-            uy += aw * t[4] * ct;
-            w += aw * st;
+        // displacement (eta, horizontal) and velocity of the point at rest:
+        // one field (mode 1) or the four corner fields of its TL tile
+        // weighted by eq. 2 (mode 2)
+        double D[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (A.mode == 1) {
+            wave_field(A.tab, A.n_comp, X, Y, 1.0, D);
+        } else {
+            int ti = (int)floor((X - A.tile_x0) / A.tile_L);
+            int tj = (int)floor((Y - A.tile_y0) / A.tile_L);
+            ti = ti < 0 ? 0 : (ti > A.ntx - 1 ? A.ntx - 1 : ti);
+            tj = tj < 0 ? 0 : (tj > A.nty - 1 ? A.nty - 1 : tj);
+            for (int c = 0; c < 4; ++c) {
+                const int ni = ti + (c & 1), nj = tj + (c >> 1);
+                const double ux = fabs(A.tile_x0 + ni * A.tile_L - X) / A.tile_L;
+                const double uy = fabs(A.tile_y0 + nj * A.tile_L - Y) / A.tile_L;
+                const double wgt = sqrt(fmax(0.0, (1.0 - ux) * (1.0 - uy)));
+                const long long node = (long long)nj * (A.ntx + 1) + ni;
+                wave_field(A.tab + 6 * node * A.n_comp, A.n_comp, X, Y, wgt, D);
+            }
         }
-        A.out.z[j] = (float)h;
-        A.out.vx[j] = (float)(ux + A.cur0);
-        A.out.vy[j] = (float)(uy + A.cur1);
-        A.out.vz[j] = (float)w;
+        A.out.x[j] = (float)(A.cwm ? X + D[1] : X);
+        A.out.y[j] = (float)(A.cwm ? Y + D[2] : Y);
+        A.out.z[j] = (float)D[0];
+        A.out.vx[j] = (float)(D[3] + A.cur0);
+        A.out.vy[j] = (float)(D[4] + A.cur1);
+        A.out.vz[j] = (float)D[5];
     }
 }
 

@@ -261,8 +261,11 @@ struct GenArgs {
     int mode;
     double sigma_v;
     int n_comp;
-    const double *tab;          // [n_comp][6]: k, A, omega, cos psi, sin psi, phase
+    const double *tab;          // [nodes][n_comp][6]: k, A, omega, cos psi, sin psi, phase
     double cur0, cur1;
+    int ntx, nty;               // mode 2: tiles; nodes (ntx + 1) x (nty + 1)
+    double tile_L, tile_x0, tile_y0;
+    int cwm;                    // horizontal displacement of the facets
     unsigned long long seed;
     int ix0, iy0, cnx, cny;
     sim_facets_out out;

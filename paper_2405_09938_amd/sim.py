@@ -128,6 +128,17 @@ class Simulator:
             keep = [d, ph]
             dp = ctypes.POINTER(ctypes.c_double)
             s.dirs, s.phases = d.ctypes.data_as(dp), ph.ctypes.data_as(dp)
+        if sea.mode == 2:
+            dp = ctypes.POINTER(ctypes.c_double)
+            hs_ = np.ascontiguousarray(sea.node_hs, np.float64).ravel()
+            d = np.ascontiguousarray(sea.node_dirs, np.float64).ravel()
+            ph = np.ascontiguousarray(sea.node_phases, np.float64).ravel()
+            keep = [hs_, d, ph]
+            s.ntx, s.nty = sea.ntx, sea.nty
+            s.tile_L, s.tile_x0, s.tile_y0 = sea.tile_L, sea.tile_x0, sea.tile_y0
+            s.node_hs, s.node_dirs, s.node_phases = (hs_.ctypes.data_as(dp), d.ctypes.data_as(dp),
+                                                     ph.ctypes.data_as(dp))
+        s.cwm = 1 if getattr(sea, "cwm", False) else 0
         s.current[0], s.current[1] = sea.current
         return s, keep
 

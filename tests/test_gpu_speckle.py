@@ -237,3 +237,39 @@ def test_speckle_workload2_full_rows(env):
         e = O.rel_l2(rc[:, p:p + 1].cpu().numpy(), ref)
         say(f"workload 2 speckle row {p}: rel-L2 {e:.3e}")
         assert e < IQ_TOL and e < IQ_BUDGET
+
+
+def test_speckle_edges(env):
+    """f_s NULL equals f_s = 0 (to the atomics' summation order); facet ids
+    wrap modulo 2^32 (first_index near
+    2^32); accumulate adds to the output; an empty pulse range writes
+    nothing; the same plan alternates plain and speckle calls."""
+    torch, hs = env
+    say("case: speckle edges (f_s NULL vs 0, id wrap, accumulate, empty range)")
+    g = W.harmony_geometry(96, 256)
+    f = W.iid_facets(30, 30, 2.0, seed=9, sigma_z=0.3)
+    sim = hs.Simulator(g)
+    d = dev(torch, f)
+    plan = sim.plan(d["x"], d["y"], 8.0)
+    sp = W.Speckle(tau_s=0.02, seed=77, first_index=2 ** 32 - 450)
+    zero = torch.zeros(900, dtype=torch.float32, device="cuda")
+    a = sim.forward(plan, d, speckle=sp).cpu().numpy()
+    b = sim.forward(plan, d, speckle=sp, f_s=zero).cpu().numpy()
+    # same arithmetic; only the order of the flush's float atomics (patches
+    # overlapping in range) may differ between two launches
+    assert np.abs(a - b).max() <= 1e-6 * np.abs(a).max()
+    ref = O.forward(g, f64(f), speckle=sp)
+    e = O.rel_l2(a, ref)
+    say(f"id wrap rel-L2 {e:.3e}")
+    assert e < IQ_TOL
+    plain = sim.forward(plan, d).cpu().numpy()
+    assert O.rel_l2(plain, O.forward(g, f64(f))) < IQ_TOL
+    base = torch.full((1, 96, 256), 0.25 + 0.5j, dtype=torch.complex64, device="cuda")
+    sim.forward(plan, d, out=base, accumulate=True, speckle=sp)
+    got = base.cpu().numpy().astype(np.complex128) - (0.25 + 0.5j)
+    assert O.rel_l2(got, ref) < IQ_TOL
+    empty = sim.forward(plan, d, 10, 0, speckle=sp)
+    assert empty.numel() == 0
+    gr = sim.backward(plan, d, torch.zeros((1, 0, 256), dtype=torch.complex64, device="cuda"),
+                      10, 0, speckle=sp)
+    assert all(float(v.abs().max()) == 0.0 for v in gr.values())
