@@ -48,14 +48,13 @@ if ROOT not in sys.path:
 W_ALG_SLOTS = 116.0 + 7 * 4.0
 W_ALG_SLOTS_EL_CONST = 104.0 + 5 * 4.0
 # With the intra-facet speckle of eq. 7 (--speckle), per contribution: one
-# Philox2x32-10 evaluation (10 rounds of two 32-bit integer multiplies, high
-# and low word, which gfx950 issues at half the FMA rate (measured), and two
-# XORs), the two uniforms (2 shifts, 2 conversions, 2 scalings), Box-Muller
-# (log2, sqrt, sin, cos at four slots; 3 products), the AR(1) step and the
-# bridge correction (2 + 2 FMAs), the amplitude times x (4) and the Doppler
-# phase (6): 99 slots.
-MUL32_SLOTS = 2.0
-W_SPK_SLOTS = 10 * (2 * MUL32_SLOTS + 2) + 6 + (4 * 4.0 + 3) + 4 + 4 + 6
+# Philox2x32-10 evaluation (10 rounds of one 32 x 32 -> 64-bit product, which
+# gfx950 issues at about half the FMA rate (measured), and two XORs), the two
+# uniforms (2 shifts, 2 conversions, 2 scalings), Box-Muller (log2, sqrt, sin,
+# cos at four slots; 3 products), the AR(1) step and the bridge correction
+# (2 + 2 FMAs), the amplitude times x (4) and the Doppler phase (6): 79 slots.
+MUL64_SLOTS = 2.0
+W_SPK_SLOTS = 10 * (MUL64_SLOTS + 2) + 6 + (4 * 4.0 + 3) + 4 + 4 + 6
 PEAK_SLOTS = 256 * 128 * 2.4e9         # FP32 lane-operations per second (157.3 TFLOP/s / 2)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_forward_cfg2_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2405_09938_amd", "csrc", f)
