@@ -236,12 +236,13 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
                 sn = load_spk(rr, ra, j + 1, ng1, gabs);
                 // free path of the group: innovations, prefix sum, end value
                 const float2 e = spk_draw(S.key, sp.id, slot, l1);
-                const float wr = spk_scan(e.x, sw), wi = spk_scan(e.y, sw);
+                float wr = e.x, wi = e.y;
+                spk_scan2(wr, wi, sw);
                 const float z64r = fmaf(b64, sp.ygr, spk_lane63(wr));
                 const float z64i = fmaf(b64, sp.ygi, spk_lane63(wi));
                 // x = b^k y_g + (sum up to lane k - 1) + K_k (y_{g+1} - z_64)
-                const float xr = fmaf(kk, sp.y1r - z64r, fmaf(bk, sp.ygr, spk_shr1(wr)));
-                const float xi = fmaf(kk, sp.y1i - z64i, fmaf(bk, sp.ygi, spk_shr1(wi)));
+                const float xr = fmaf(kk, sp.y1r - z64r, spk_shr1_add(wr, bk * sp.ygr));
+                const float xi = fmaf(kk, sp.y1i - z64i, spk_shr1_add(wi, bk * sp.ygi));
                 far = fmaf(f.ar, xr, -(f.ai * xi));
                 fai = fmaf(f.ar, xi, f.ai * xr);
                 // Doppler f_s t_p in cycles, the product split so that its

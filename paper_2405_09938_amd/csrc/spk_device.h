@@ -53,16 +53,6 @@ __device__ __forceinline__ float2 spk_draw(uint32_t key, uint32_t id, uint32_t s
     return make_float2(rho * __builtin_amdgcn_cosf(u2), rho * __builtin_amdgcn_sinf(u2));
 }
 
-// DPP lane moves (lanes without a source read 0).
-template <int CTRL, int ROWS>
-__device__ __forceinline__ float dpp_f(float v) {
-    return __int_as_float(
-        __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xf, true));
-}
-constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114,
-              kDppRowShr8 = 0x118, kDppWaveShr1 = 0x138, kDppBcast15 = 0x142,
-              kDppBcast31 = 0x143;
-
 // Per-lane weights of the wave-wide AR(1) prefix sum.
 struct SpkScanW {
     float b1, b2, b4, b8;   // b^s for the in-row shifts (uniform, in VGPRs)
@@ -70,18 +60,30 @@ struct SpkScanW {
     float w31;              // b^(lane - 31) in rows 2 and 3
 };
 
-// v_k <- sum_{i <= k} b^(k-i) v_i over the 64 lanes: shifts 1, 2, 4, 8 within
-// rows of 16, then row 0's total into row 1 and row 2's into row 3
-// (row_bcast:15), then the first two rows' total into rows 2 and 3
-// (row_bcast:31), each term weighted by b^(lane distance).
-__device__ __forceinline__ float spk_scan(float v, const SpkScanW &w) {
-    v = fmaf(w.b1, dpp_f<kDppRowShr1, 0xf>(v), v);
-    v = fmaf(w.b2, dpp_f<kDppRowShr2, 0xf>(v), v);
-    v = fmaf(w.b4, dpp_f<kDppRowShr4, 0xf>(v), v);
-    v = fmaf(w.b8, dpp_f<kDppRowShr8, 0xf>(v), v);
-    v = fmaf(w.w15, dpp_f<kDppBcast15, 0xa>(v), v);
-    v = fmaf(w.w31, dpp_f<kDppBcast31, 0xc>(v), v);
-    return v;
+// v_k <- sum_{i <= k} b^(k-i) v_i over the 64 lanes, for the real and the
+// imaginary part together: shifts 1, 2, 4, 8 within rows of 16, then row 0's
+// total into row 1 and row 2's into row 3 (row_bcast:15), then the first two
+// rows' total into rows 2 and 3 (row_bcast:31), each term weighted by
+// b^(lane distance).  Each step is an FMA whose first source goes through a
+// DPP lane move (a lane without a source reads 0 and keeps its value; lanes
+// of disabled rows are not written).  A DPP read needs two wait states after
+// the VALU write of its source, whatever instruction the compiler placed
+// before the step: each step opens with s_nop 1, and within a step the second
+// part's source was written two instructions earlier.  The caller runs this
+// with all 64 lanes active.
+__device__ __forceinline__ void spk_scan2(float &re, float &im, const SpkScanW &w) {
+#define HS_DPP_STEP(CTRL, ROWS)                                                            \
+    "v_fmac_f32_dpp %0, %0, %2 " CTRL " row_mask:" ROWS " bank_mask:0xf bound_ctrl:1\n\t"   \
+    "v_fmac_f32_dpp %1, %1, %2 " CTRL " row_mask:" ROWS " bank_mask:0xf bound_ctrl:1\n\t"
+    asm volatile("s_nop 1\n\t" HS_DPP_STEP("row_shr:1", "0xf") : "+v"(re), "+v"(im) : "v"(w.b1));
+    asm volatile("s_nop 1\n\t" HS_DPP_STEP("row_shr:2", "0xf") : "+v"(re), "+v"(im) : "v"(w.b2));
+    asm volatile("s_nop 1\n\t" HS_DPP_STEP("row_shr:4", "0xf") : "+v"(re), "+v"(im) : "v"(w.b4));
+    asm volatile("s_nop 1\n\t" HS_DPP_STEP("row_shr:8", "0xf") : "+v"(re), "+v"(im) : "v"(w.b8));
+    asm volatile("s_nop 1\n\t" HS_DPP_STEP("row_bcast:15", "0xa") : "+v"(re), "+v"(im)
+                 : "v"(w.w15));
+    asm volatile("s_nop 1\n\t" HS_DPP_STEP("row_bcast:31", "0xc") : "+v"(re), "+v"(im)
+                 : "v"(w.w31));
+#undef HS_DPP_STEP
 }
 
 // value of lane 63 (the readlane builtin moves 32-bit integers: reinterpret,
@@ -90,7 +92,14 @@ __device__ __forceinline__ float spk_lane63(float v) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
-// value of lane - 1 (0 in lane 0)
-__device__ __forceinline__ float spk_shr1(float v) { return dpp_f<kDppWaveShr1, 0xf>(v); }
+// a + (value of v in lane - 1; 0 in lane 0), one DPP add
+__device__ __forceinline__ float spk_shr1_add(float v, float a) {
+    float x;
+    asm volatile("s_nop 1\n\tv_add_f32_dpp %0, %1, %2 wave_shr:1 row_mask:0xf bank_mask:0xf "
+                 "bound_ctrl:1"
+                 : "=v"(x)
+                 : "v"(v), "v"(a));
+    return x;
+}
 
 }  // namespace hs
