@@ -30,6 +30,10 @@
  *                                      summing to one, variance kept; CWM:
  *                                      trochoid mean level and excursion,
  *                                      displacement rate = velocity)
+ *   steer_ant (time-dependent frames)  pinned (zero rate = stripmap, steered
+ *                                      gain = static gain of the facet rotated
+ *                                      back about el, back plane, finite
+ *                                      differences)
  *   og_echo_time, rx_exact model       pinned (50-digit mpmath root of the echo
  *                                      equation, static-receiver case, lone
  *                                      facet phase/delay shift, finite
@@ -73,6 +77,7 @@ typedef struct {
     int ch_rx[OG_MAXC];
     double ch_off[OG_MAXC][3];
     int rx_exact;   /* 1: receiver at each facet's own echo time (see facet_rx) */
+    double ant_steer[OG_MAXA];   /* steering rate about the elevation axis (rad/s) */
 } og_config;
 
 static const double OG_PI = 3.14159265358979323846;
@@ -284,6 +289,7 @@ typedef struct {
     double t, tau, rref;
     double ptx[3], prx[3];
     double rt_mid, rr_mid;
+    og_ant at, ar;   /* Tx and Rx antennas of the row's channel, steered */
 } og_row;
 
 /* Per-call constants: antenna frames and I0(beta). */
@@ -296,6 +302,29 @@ static void make_ctx(const og_config *g, og_ctx *cx) {
     double kap = og_kappa();
     for (int a = 0; a < g->n_ant; ++a) make_ant(g, a, kap, &cx->ant[a]);
     cx->i0b = bessel_i0(g->kaiser_beta);
+}
+
+/*
+ * Time-dependent antenna patterns (Sec. III.B: time dependent in the TOPSAR
+ * modes).  Reading: each antenna's frame turns about its elevation axis at
+ * the constant rate ant_steer: with phi = rate * t,
+ *   b(t) = b cos(phi) + az sin(phi),  az(t) = az cos(phi) - b sin(phi),
+ * el unchanged; the Tx antenna is taken at the pulse time t_p, the Rx antenna
+ * at t_p + tau_ref (one state per pulse and channel).
+ */
+static void steer_ant(const og_ant *a, double phi, og_ant *o) {
+    const double c = cos(phi), s = sin(phi);
+    *o = *a;
+    for (int k = 0; k < 3; ++k) {
+        o->b[k] = a->b[k] * c + a->az[k] * s;
+        o->az[k] = a->az[k] * c - a->b[k] * s;
+    }
+}
+
+static void steer_row(const og_config *g, const og_ctx *cx, int ch, og_row *r) {
+    const int ta = g->ch_tx[ch], ra = g->ch_rx[ch];
+    steer_ant(&cx->ant[ta], g->ant_steer[ta] * r->t, &r->at);
+    steer_ant(&cx->ant[ra], g->ant_steer[ra] * (r->t + r->tau), &r->ar);
 }
 
 static void make_row(const og_config *g, int ch, int p, og_row *r) {
@@ -357,7 +386,7 @@ static void rx_vel(const og_config *g, int ch, double *v) {
  *   S = (R_t,mid R_r,mid) / (R_t R_r)   (1/(r_t r_r) spreading, normalised
  *       to the scene-origin ranges at t = 0; other constants set to 1)
  */
-static void contribution(const og_config *g, const og_ctx *cx, int ch, const og_row *r,
+static void contribution(const og_config *g, int ch, const og_row *r,
                          const double *x0, const double *v, double are, double aim,
                          double dphi, double *wre, double *wim, double *u) {
     double X[3];
@@ -367,8 +396,8 @@ static void contribution(const og_config *g, const og_ctx *cx, int ch, const og_
     double dt[3] = {X[0] - r->ptx[0], X[1] - r->ptx[1], X[2] - r->ptx[2]};
     double dr[3] = {X[0] - prx[0], X[1] - prx[1], X[2] - prx[2]};
     double Rt = norm3(dt), Rr = norm3(dr), R = Rt + Rr;
-    double ft = gain(&cx->ant[g->ch_tx[ch]], r->ptx, X, NULL);
-    double fr = gain(&cx->ant[g->ch_rx[ch]], prx, X, NULL);
+    double ft = gain(&r->at, r->ptx, X, NULL);
+    double fr = gain(&r->ar, prx, X, NULL);
     double S = (r->rt_mid * r->rr_mid) / (Rt * Rr);
     double phi = -2.0 * OG_PI * g->f0 * R / g->c + dphi;
     double amp = ft * fr * S;
@@ -399,6 +428,7 @@ static void forward_impl(const og_config *g, long long nf, const double *x, cons
         int ch = (int)(row / np), p = p0 + (int)(row % np);
         og_row r;
         make_row(g, ch, p, &r);
+        steer_row(g, &cx, ch, &r);
         double *out = iq + 2 * (size_t)row * (size_t)N;
         for (long long i = 0; i < nf; ++i) {
             double X0[3] = {x[i], y[i], z[i]}, V[3] = {vx[i], vy[i], vz[i]};
@@ -410,7 +440,7 @@ static void forward_impl(const og_config *g, long long nf, const double *x, cons
                 dphi = fs ? 2.0 * OG_PI * fs[i] * r.t : 0.0;
             }
             double wre, wim, u;
-            contribution(g, &cx, ch, &r, X0, V, ar, ai, dphi, &wre, &wim, &u);
+            contribution(g, ch, &r, X0, V, ar, ai, dphi, &wre, &wim, &u);
             long long n0 = (long long)floor(u);
             for (long long n = n0 - 3; n <= n0 + 4; ++n) {
                 if (n < 0 || n >= N) continue;
@@ -452,11 +482,14 @@ static void adjoint_impl(const og_config *g, long long nf, const double *x, cons
                          double *dvz, double *dare, double *daim) {
     const int N = g->n_samples;
     const int rows = g->n_ch * np;
-    og_row *rw = (og_row *)malloc(sizeof(og_row) * (size_t)rows);
-    for (int row = 0; row < rows; ++row) make_row(g, row / np, p0 + row % np, &rw[row]);
-    const double K0 = 2.0 * OG_PI * g->f0 / g->c;
     og_ctx cx;
     make_ctx(g, &cx);
+    og_row *rw = (og_row *)malloc(sizeof(og_row) * (size_t)rows);
+    for (int row = 0; row < rows; ++row) {
+        make_row(g, row / np, p0 + row % np, &rw[row]);
+        steer_row(g, &cx, row / np, &rw[row]);
+    }
+    const double K0 = 2.0 * OG_PI * g->f0 / g->c;
 #pragma omp parallel for schedule(dynamic, 64)
     for (long long i = 0; i < nf; ++i) {
         double X0[3] = {x[i], y[i], z[i]}, V[3] = {vx[i], vy[i], vz[i]};
@@ -481,8 +514,8 @@ static void adjoint_impl(const og_config *g, long long nf, const double *x, cons
             double dr[3] = {X[0] - prx[0], X[1] - prx[1], X[2] - prx[2]};
             double Rt = norm3(dt), Rr = norm3(dr), R = Rt + Rr;
             double gft[3], gfr[3];
-            double ft = gain(&cx.ant[g->ch_tx[ch]], r->ptx, X, gft);
-            double fr = gain(&cx.ant[g->ch_rx[ch]], prx, X, gfr);
+            double ft = gain(&r->at, r->ptx, X, gft);
+            double fr = gain(&r->ar, prx, X, gfr);
             double S = (r->rt_mid * r->rr_mid) / (Rt * Rr);
             double T = ft * fr * S;
             double phi = -2.0 * OG_PI * g->f0 * R / g->c + dphi;

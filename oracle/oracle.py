@@ -40,6 +40,7 @@ class OgConfig(ctypes.Structure):
         ("ch_tx", ctypes.c_int * MAXC), ("ch_rx", ctypes.c_int * MAXC),
         ("ch_off", _d3 * MAXC),
         ("rx_exact", ctypes.c_int),
+        ("ant_steer", ctypes.c_double * MAXA),
     ]
 
 
@@ -145,6 +146,7 @@ def make_config(geom) -> OgConfig:
         c.ant_plat[i] = a.platform
         c.ant_beta_az[i] = a.beta_az
         c.ant_beta_el[i] = a.beta_el
+        c.ant_steer[i] = getattr(a, "steer_rate", 0.0)
     c.n_ch = len(geom.channels)
     for i, ch in enumerate(geom.channels):
         c.ch_tx[i], c.ch_rx[i] = ch.tx, ch.rx

@@ -67,6 +67,7 @@ class Antenna:
     platform: int
     beta_az: float                      # one-way 3-dB width in azimuth (rad)
     beta_el: float                      # one-way 3-dB width in elevation (rad)
+    steer_rate: float = 0.0             # azimuth steering rate about the el axis (rad/s)
 
 
 @dataclass(frozen=True)
@@ -341,6 +342,15 @@ def speckle_doppler(n: int, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed + 7919)
     sign = np.where(rng.random(n) < 0.5, -1.0, 1.0)
     return (sign * SPECKLE_FD_HZ + rng.normal(0.0, SPECKLE_FD_SPREAD_HZ, n)).astype(np.float32)
+
+
+def tops_geometry(g: Geometry, rate_deg_s: float = 1.5) -> Geometry:
+    """The same acquisition with the transmit antenna steered in azimuth at a
+    constant rate (TOPS-like burst sweep; Sentinel-1 IW sweeps its beam by
+    about +-0.6 deg over a burst of under a second)."""
+    ants = list(g.antennas)
+    ants[0] = replace(ants[0], steer_rate=math.radians(rate_deg_s))
+    return replace(g, antennas=tuple(ants))
 
 
 def with_pulses(g: Geometry, n_pulses: int) -> Geometry:
