@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--serial", action="store_true",
                     help="no step pipelining (one kernel at a time, for per-kernel counters)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--tops", type=float, default=0.0,
+                    help="steer the transmit antenna in azimuth at this rate (deg/s)")
     ap.add_argument("--rx-exact", action="store_true",
                     help="receiver at each facet's own echo time (eq. 3's r_r(t_r))")
     ap.add_argument("--speckle", action="store_true",
@@ -111,9 +113,12 @@ def main():
     import workloads as W
 
     wl = W.workload(args.workload)
-    if args.rx_exact:
+    if args.rx_exact or args.tops:
         from dataclasses import replace as _replace
-        wl = _replace(wl, geometry=_replace(wl.geometry, rx_exact=True))
+        g2 = _replace(wl.geometry, rx_exact=args.rx_exact)
+        if args.tops:
+            g2 = W.tops_geometry(g2, args.tops)
+        wl = _replace(wl, geometry=g2)
     geom, sea = wl.geometry, wl.sea
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
@@ -278,7 +283,8 @@ def main():
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
         if (tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == wl.name
-                and bool(tr.get("speckle", False)) == args.speckle and not args.rx_exact):
+                and bool(tr.get("speckle", False)) == args.speckle and not args.rx_exact
+                and not args.tops):
             traffic = tr.get("bytes_per_launch")
             valu = tr.get("valu_insts_per_launch")
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
@@ -365,7 +371,8 @@ def main():
                    "block_edge_m": wl.block_edge, "chunks": len(wl.chunks) or 1,
                    "speckle": ({"tau_s": W.SPECKLE_TAU_S, "f_s_hz": f"+-{W.SPECKLE_FD_HZ}"}
                                if args.speckle else None),
-                   "rx_at_facet_echo_time": args.rx_exact},
+                   "rx_at_facet_echo_time": args.rx_exact,
+                   "tx_steer_deg_s": args.tops or None},
         "fwd_adj": fwd_adj,
         "rel_l2_vs_fp64": rel,
         "roofline": roofline,

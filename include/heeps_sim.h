@@ -85,6 +85,12 @@ typedef struct {
     int platform;
     double beta_az;
     double beta_el;
+    /* Time-dependent pattern (TOPS-like azimuth steering, Sec. III.B): the
+     * frame turns about the elevation axis at this rate (rad/s), angle
+     * rate * t, so b(t) = b cos + az sin, az(t) = az cos - b sin; a transmit
+     * antenna at the pulse time, a receive antenna at t_p + tau_ref.  0 =
+     * fixed frame. */
+    double steer_rate;
 } sim_antenna;
 
 /* Channel: transmit antenna, receive antenna and the receive phase-centre

@@ -28,7 +28,7 @@ class SimTraj(ctypes.Structure):
 
 class SimAntenna(ctypes.Structure):
     _fields_ = [("platform", ctypes.c_int), ("beta_az", ctypes.c_double),
-                ("beta_el", ctypes.c_double)]
+                ("beta_el", ctypes.c_double), ("steer_rate", ctypes.c_double)]
 
 
 class SimChannel(ctypes.Structure):

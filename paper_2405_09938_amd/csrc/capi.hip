@@ -183,10 +183,13 @@ void antenna_frame(const sim_handle *h, int a, hs::AntArgs &ac) {
     ac.el[2] = ac.b[0] * ac.az[1] - ac.b[1] * ac.az[0];
     ac.ka = h->kappa / h->ants[a].beta_az;
     ac.ke = h->kappa / h->ants[a].beta_el;
+    ac.steer = h->ants[a].steer_rate;
     for (int k = 0; k < 3; ++k) {
         ac.kaz[k] = (float)(0.5 * ac.ka * ac.az[k]);
         ac.kel[k] = (float)(0.5 * ac.ke * ac.el[k]);
         ac.b32[k] = (float)ac.b[k];
+        ac.kb[k] = (float)(0.5 * ac.ka * ac.b[k]);
+        ac.az32[k] = (float)ac.az[k];
     }
     ac.pad = 0.0f;
 }
@@ -484,6 +487,14 @@ int sim_create(const sim_config *cfg, sim_handle **out) {
     h->rx_exact = cfg->rx_exact ? 1 : 0;
     h->kappa = half_power_kappa();
 
+    h->steer = 0;
+    for (const sim_antenna &an : h->ants) {
+        if (!std::isfinite(an.steer_rate)) {
+            delete h;
+            HS_FAIL(SIM_EINVAL, "antenna steer_rate must be finite");
+        }
+        if (an.steer_rate != 0.0) h->steer = 1;
+    }
     h->antc.resize(h->ants.size());
     for (size_t a = 0; a < h->ants.size(); ++a) {
         antenna_frame(h, (int)a, h->antc[a]);
@@ -1025,6 +1036,7 @@ static int forward_common(sim_handle *h, sim_plan *P, const sim_facets *f,
     a.n_patches = (int)P->n_patches;
     a.halo = P->halo;
     a.rx_exact = h->rx_exact;
+    a.steer = h->steer;
     a.inv_c = 1.0 / h->c;
     HS_HIP(hs::launch_forward(a, h->C, P->win, P->el_const, sp != nullptr, s), "forward");
     return SIM_OK;
@@ -1097,6 +1109,7 @@ static int backward_common(sim_handle *h, sim_plan *P, const sim_facets *f,
     a.n_blocks = P->n_blocks;
     a.accumulate = accumulate ? 1 : 0;
     a.rx_exact = h->rx_exact;
+    a.steer = h->steer;
     a.inv_c = 1.0 / h->c;
     HS_HIP(hs::launch_adjoint(a, P->el_const, sp != nullptr, s), "adjoint");
     return SIM_OK;

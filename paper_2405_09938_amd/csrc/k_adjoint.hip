@@ -46,17 +46,27 @@ enum {
     R_TLO        // t_p - float(t_p) (speckle: the Doppler phase)
 };
 
-// floats per staged pulse record (a multiple of 4)
+// floats per staged pulse record (a multiple of 4); with steering, four more
+// from R_ST0<SPK> on: cos, sin of the Tx and of the Rx steering angle
 template <bool SPK>
-constexpr int kNRef = SPK ? 48 : 44;
+constexpr int R_ST0 = SPK ? 48 : 44;
+template <bool SPK, bool STR>
+constexpr int kNRef = R_ST0<SPK> + (STR ? 4 : 0);
 
 // Gradient of one antenna's field pattern at the block centre (FP32 from the
 // FP64 geometry): dF/dX = ka sinc'(ka u) sinc(ke v) (az - u d)/R
 //                        + ke sinc(ka u) sinc'(ke v) (el - v d)/R.
+template <bool STR>
 __device__ __forceinline__ float ant_grad(const AntArgs &a, double d0, double d1, double d2,
-                                          double ir, float *gr) {
+                                          double ir, float *gr, double cs, double sn) {
     const double u0 = d0 * ir, u1 = d1 * ir, u2 = d2 * ir;
-    const double u = u0 * a.az[0] + u1 * a.az[1] + u2 * a.az[2];
+    // azimuth axis, turned by the steering angle if STR
+    double az[3] = {a.az[0], a.az[1], a.az[2]};
+    if constexpr (STR) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) az[k] = a.az[k] * cs - a.b[k] * sn;
+    }
+    const double u = u0 * az[0] + u1 * az[1] + u2 * az[2];
     const double v = u0 * a.el[0] + u1 * a.el[1] + u2 * a.el[2];
     const float xa = (float)(a.ka * u), xe = (float)(a.ke * v);
     const float su = sinc_f(xa), sv = sinc_f(xe);
@@ -65,7 +75,7 @@ __device__ __forceinline__ float ant_grad(const AntArgs &a, double d0, double d1
     const double uu[3] = {u0, u1, u2};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const float gu = (float)(a.az[k] - u * uu[k]) * irf;
+        const float gu = (float)(az[k] - u * uu[k]) * irf;
         const float gv = (float)(a.el[k] - v * uu[k]) * irf;
         gr[k] = dsu * sv * gu + su * dsv * gv;
     }
@@ -74,16 +84,18 @@ __device__ __forceinline__ float ant_grad(const AntArgs &a, double d0, double d1
 
 // grad T = grad(F_tx F_rx S) at the point (X, Y, Z), S = R_t,mid R_r,mid /
 // (R_t R_r) the spreading (without the mask).
+template <bool STR>
 __device__ __forceinline__ void grad_t(const AntArgs &ta, const AntArgs &ra, double rtrr_mid,
                                        double X, double Y, double Z, const double *ptx,
-                                       const double *prx, float *out) {
+                                       const double *prx, float *out, double cst, double snt,
+                                       double csr, double snr) {
     const double dt0 = X - ptx[0], dt1 = Y - ptx[1], dt2 = Z - ptx[2];
     const double dr0 = X - prx[0], dr1 = Y - prx[1], dr2 = Z - prx[2];
     const double irt = 1.0 / sqrt(dt0 * dt0 + dt1 * dt1 + dt2 * dt2);
     const double irr = 1.0 / sqrt(dr0 * dr0 + dr1 * dr1 + dr2 * dr2);
     float gft[3], gfr[3];
-    const float ft = ant_grad(ta, dt0, dt1, dt2, irt, gft);
-    const float fr = ant_grad(ra, dr0, dr1, dr2, irr, gfr);
+    const float ft = ant_grad<STR>(ta, dt0, dt1, dt2, irt, gft, cst, snt);
+    const float fr = ant_grad<STR>(ra, dr0, dr1, dr2, irr, gfr, csr, snr);
     const double sb = rtrr_mid * irt * irr;
     const double d[3][2] = {{dt0, dr0}, {dt1, dr1}, {dt2, dr2}};
 #pragma unroll
@@ -97,9 +109,12 @@ __device__ __forceinline__ void grad_t(const AntArgs &ta, const AntArgs &ra, dou
 // the Doppler f_s t_p (eq. 7).  Each lane follows its facet's process pulse by
 // pulse: at a group start x = y_g, then z = b z + sqrt(1 - b^2) e_p and
 // x = z + K_k D_g with (y_g, D_g) from the preparation pass.
-template <bool ELC, bool SPK>
+// STR: antenna frames turn with time (steering): the per-pulse angles are
+// staged with the references and the facet-part constants rebuilt per pulse.
+template <bool ELC, bool SPK, bool STR>
 __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
-    constexpr int kNR = kNRef<SPK>;
+    constexpr int kNR = kNRef<SPK, STR>;
+    constexpr int kSt = R_ST0<SPK>;
     __shared__ float4 refs[kStage * kNR / 4];
     __shared__ float2 gwin[kStage * kGW];
 
@@ -167,15 +182,18 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                 double prb[3] = {P.prx[0], P.prx[1], P.prx[2]};
                 double qr = 1.0;
                 if (A.rx_exact) rx_echo(xb, yb, P.ptx, P.prx, P.rref, chn.vr, A.inv_c, prb, qr);
+                [[maybe_unused]] double cst = 1.0, snt = 0.0, csr = 1.0, snr = 0.0;
+                if constexpr (STR)
+                    steer_angles(ta, ra, P.t, P.t + P.rref * A.inv_c, cst, snt, csr, snr);
                 Refs r;
-                block_refs<ELC>(xb, yb, P.ptx, prb, P.rref, ta, ra, chn.rtrr_mid, A.f0_c, A.fs_c,
-                           A.n_ref, live, r, qr);
+                block_refs<ELC, STR>(xb, yb, P.ptx, prb, P.rref, ta, ra, chn.rtrr_mid, A.f0_c,
+                                A.fs_c, A.n_ref, live, r, qr, cst, snt, csr, snr);
                 // grad T at the centre
                 const double dt0 = xb - P.ptx[0], dt1 = yb - P.ptx[1], dt2 = -P.ptx[2];
                 const double dr0 = xb - prb[0], dr1 = yb - prb[1], dr2 = -prb[2];
                 float gft[3], gfr[3];
-                const float ft = ant_grad(ta, dt0, dt1, dt2, (double)r.irt, gft);
-                const float fr = ant_grad(ra, dr0, dr1, dr2, (double)r.irr, gfr);
+                const float ft = ant_grad<STR>(ta, dt0, dt1, dt2, (double)r.irt, gft, cst, snt);
+                const float fr = ant_grad<STR>(ra, dr0, dr1, dr2, (double)r.irr, gfr, csr, snr);
                 float *o = rf + lane * kNR;
                 // spreading at the centre (r.sb also carries the sinc normalisation)
                 const float sbt = (r.mask != 0.0f || r.graze)
@@ -199,8 +217,10 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                         const double ox = j == 0 ? h : 0.0, oy = j == 1 ? h : 0.0,
                                      oz = j == 2 ? h : 0.0;
                         float gp[3], gm[3];
-                        grad_t(ta, ra, chn.rtrr_mid, xb + ox, yb + oy, oz, P.ptx, prb, gp);
-                        grad_t(ta, ra, chn.rtrr_mid, xb - ox, yb - oy, -oz, P.ptx, prb, gm);
+                        grad_t<STR>(ta, ra, chn.rtrr_mid, xb + ox, yb + oy, oz, P.ptx, prb, gp,
+                                    cst, snt, csr, snr);
+                        grad_t<STR>(ta, ra, chn.rtrr_mid, xb - ox, yb - oy, -oz, P.ptx, prb, gm,
+                                    cst, snt, csr, snr);
                         o[R_J0 + j] = s2h * (gp[0] - gm[0]);
                         o[R_J0 + 3 + j] = s2h * (gp[1] - gm[1]);
                         o[R_J0 + 6 + j] = s2h * (gp[2] - gm[2]);
@@ -211,6 +231,12 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                 o[R_LLO] = r.llo;
                 o[R_FSQ] = r.fsq;
                 o[R_Q] = (float)qr;
+                if constexpr (STR) {
+                    o[kSt] = (float)cst;
+                    o[kSt + 1] = (float)snt;
+                    o[kSt + 2] = (float)csr;
+                    o[kSt + 3] = (float)snr;
+                }
                 if constexpr (SPK) o[R_TLO] = (float)(P.t - (double)(float)P.t);
                 o[R_DTX] = r.dtx; o[R_DTY] = r.dty; o[R_DTZ] = r.dtz;
                 o[R_GX] = r.gx; o[R_GY] = r.gy; o[R_GZ] = r.gz;
@@ -275,8 +301,10 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                     const float dl = fmaf(sr.fs, o[R_TLO], fmaf(sr.fs, tf, -dh));
                     dop = __builtin_amdgcn_fractf(dh) + dl;
                 }
+                FacetConsts kq = kc;
+                if constexpr (STR) steer_consts(ta, ra, o[kSt], o[kSt + 1], o[kSt + 2], o[kSt + 3], kq);
                 Geo g;
-                facet_geo<ELC, SPK>(r, kc, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz, r.graze != 0,
+                facet_geo<ELC, SPK>(r, kq, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz, r.graze != 0,
                                o[R_LHI], o[R_LLO], o[R_FSQ], dop, g);
                 float tap[8], dtap[8];
                 taps_d8(tv, g.f, tap, dtap);
@@ -384,13 +412,25 @@ hipError_t launch_adjoint(const AdjArgs &a, bool el_const, bool speckle, hipStre
     const unsigned long long wgs = ((unsigned long long)a.n_blocks + 7) / 8 * 8;
     if (wgs > 0xffffffffULL) return hipErrorInvalidConfiguration;
     const dim3 grid((unsigned)wgs);
-    if (speckle) {
-        if (el_const) hipLaunchKernelGGL((k_adjoint<true, true>), grid, dim3(64), 0, s, a);
-        else hipLaunchKernelGGL((k_adjoint<false, true>), grid, dim3(64), 0, s, a);
+#define HS_ADJ(E, S, T) hipLaunchKernelGGL((k_adjoint<E, S, T>), grid, dim3(64), 0, s, a)
+    if (a.steer) {
+        if (speckle) {
+            if (el_const) HS_ADJ(true, true, true);
+            else HS_ADJ(false, true, true);
+        } else {
+            if (el_const) HS_ADJ(true, false, true);
+            else HS_ADJ(false, false, true);
+        }
     } else {
-        if (el_const) hipLaunchKernelGGL((k_adjoint<true, false>), grid, dim3(64), 0, s, a);
-        else hipLaunchKernelGGL((k_adjoint<false, false>), grid, dim3(64), 0, s, a);
+        if (speckle) {
+            if (el_const) HS_ADJ(true, true, false);
+            else HS_ADJ(false, true, false);
+        } else {
+            if (el_const) HS_ADJ(true, false, false);
+            else HS_ADJ(false, false, false);
+        }
     }
+#undef HS_ADJ
     return hipGetLastError();
 }
 

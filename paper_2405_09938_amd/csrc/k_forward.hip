@@ -104,7 +104,8 @@ constexpr int kFlushTransposeMax = 32;
 // on absolute pulse indices (multiples of 64), so that a wave holds exactly
 // one group of the speckle process; lanes before p0 or past the last pulse
 // take part in the prefix sum but deposit nothing.
-template <int WIN, bool ELC, bool SPK>
+// STR: antenna frames turn with time (steering): per-pulse frames.
+template <int WIN, bool ELC, bool SPK, bool STR>
 __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
     // [sample][lane] during the sum; [lane][WIN + 1] for the flush
     constexpr int kAcc = WIN <= kFlushTransposeMax ? 64 * (WIN + 1) : 64 * WIN;
@@ -171,6 +172,12 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
     for (int i = 0; i < WIN; ++i) col[64 * i] = make_float2(0.f, 0.f);
 
     const PulseRec &P = PR[plc];
+    // antenna frames of this pulse (time-dependent patterns)
+    [[maybe_unused]] double cst = 1.0, snt = 0.0, csr = 1.0, snr = 0.0;
+    if constexpr (STR) {
+        steer_angles(ta, ra, P.t, P.t + P.rref * A.inv_c, cst, snt, csr, snr);
+        steer_consts(ta, ra, (float)cst, (float)snt, (float)csr, (float)snr, kc);
+    }
     const double ptx[3] = {P.ptx[0], P.ptx[1], P.ptx[2]};
     const double prx[3] = {P.prx[0], P.prx[1], P.prx[2]};
     const double rref = P.rref;
@@ -210,8 +217,8 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
         double qr = 1.0;
         if (A.rx_exact)
             rx_echo((double)blk.xb, (double)blk.yb, ptx, prx, rref, A.ch[ch].vr, A.inv_c, prb, qr);
-        block_refs<ELC>((double)blk.xb, (double)blk.yb, ptx, prb, rref, ta, ra, chn.rtrr_mid, A.f0_c,
-                   A.fs_c, A.n_ref, live, r, qr);
+        block_refs<ELC, STR>((double)blk.xb, (double)blk.yb, ptx, prb, rref, ta, ra, chn.rtrr_mid,
+                        A.f0_c, A.fs_c, A.n_ref, live, r, qr, cst, snt, csr, snr);
         const bool graze_any = __any(r.graze);
         // the window offset of the first tap rides in the sample fraction, so
         // the floor of the sample position is the window index directly
@@ -334,14 +341,20 @@ hipError_t launch_forward(const FwdArgs &a, int C, int win, bool el_const, bool 
     const unsigned long long wgs = groups * (((unsigned long long)a.n_patches + 7) / 8 * 8);
     if (wgs > 0xffffffffULL) return hipErrorInvalidConfiguration;
     dim3 grid((unsigned)wgs, (unsigned)C);
+#define HS_FWD4(W, T)                                                                       \
+    if (speckle) {                                                                          \
+        if (el_const) hipLaunchKernelGGL((k_forward<W, true, true, T>), grid, dim3(64), 0, s, a); \
+        else hipLaunchKernelGGL((k_forward<W, false, true, T>), grid, dim3(64), 0, s, a);   \
+    } else {                                                                                \
+        if (el_const) hipLaunchKernelGGL((k_forward<W, true, false, T>), grid, dim3(64), 0, s, a); \
+        else hipLaunchKernelGGL((k_forward<W, false, false, T>), grid, dim3(64), 0, s, a);  \
+    }
 #define HS_FWD(W)                                                                           \
     case W:                                                                                 \
-        if (speckle) {                                                                      \
-            if (el_const) hipLaunchKernelGGL((k_forward<W, true, true>), grid, dim3(64), 0, s, a); \
-            else hipLaunchKernelGGL((k_forward<W, false, true>), grid, dim3(64), 0, s, a);  \
+        if (a.steer) {                                                                      \
+            HS_FWD4(W, true)                                                                \
         } else {                                                                            \
-            if (el_const) hipLaunchKernelGGL((k_forward<W, true, false>), grid, dim3(64), 0, s, a); \
-            else hipLaunchKernelGGL((k_forward<W, false, false>), grid, dim3(64), 0, s, a); \
+            HS_FWD4(W, false)                                                               \
         }                                                                                   \
         break;
     switch (win) {
@@ -352,6 +365,7 @@ hipError_t launch_forward(const FwdArgs &a, int C, int win, bool el_const, bool 
         default: return hipErrorInvalidValue;
     }
 #undef HS_FWD
+#undef HS_FWD4
     return hipGetLastError();
 }
 

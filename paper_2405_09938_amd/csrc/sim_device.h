@@ -90,12 +90,13 @@ __device__ __forceinline__ void rx_echo(double xb, double yb, const double *ptx,
 // ELC: the elevation pattern factors of both legs are taken at the block
 // centre and folded into the spreading terms (chosen on the host only where
 // a bound puts the relative error of that below 1e-6 for every facet).
-template <bool ELC>
+template <bool ELC, bool STR = false>
 __device__ __forceinline__ void block_refs(double xb, double yb, const double *ptx,
                                            const double *prx, double rref, const AntArgs &t,
                                            const AntArgs &q, double rtrr_mid, double f0_c,
                                            double fs_c, double n_ref, bool live, Refs &r,
-                                           double qr = 1.0) {
+                                           double qr = 1.0, double cst = 1.0, double snt = 0.0,
+                                           double csr = 1.0, double snr = 0.0) {
     const double dt0 = xb - ptx[0], dt1 = yb - ptx[1], dt2 = -ptx[2];
     const double dr0 = xb - prx[0], dr1 = yb - prx[1], dr2 = -prx[2];
     const double rt = sqrt(dt0 * dt0 + dt1 * dt1 + dt2 * dt2);
@@ -123,17 +124,28 @@ __device__ __forceinline__ void block_refs(double xb, double yb, const double *p
     const double fl = floor(ub);
     r.fb = (float)(ub - fl);
     r.nb = (int)fl;
-    r.gtaz = (float)(0.5 * t.ka * (dt0 * t.az[0] + dt1 * t.az[1] + dt2 * t.az[2]));
+    // azimuth axes and boresights turned by the steering angles (cos, sin):
+    // az' = az cos - b sin, b' = b cos + az sin (elevation axes unchanged)
+    const double dta = dt0 * t.az[0] + dt1 * t.az[1] + dt2 * t.az[2];
+    const double dtb = dt0 * t.b[0] + dt1 * t.b[1] + dt2 * t.b[2];
+    const double dra = dr0 * q.az[0] + dr1 * q.az[1] + dr2 * q.az[2];
+    const double drb = dr0 * q.b[0] + dr1 * q.b[1] + dr2 * q.b[2];
+    if constexpr (STR) {
+        r.gtaz = (float)(0.5 * t.ka * (dta * cst - dtb * snt));
+        r.graz = (float)(0.5 * q.ka * (dra * csr - drb * snr));
+    } else {
+        r.gtaz = (float)(0.5 * t.ka * dta);
+        r.graz = (float)(0.5 * q.ka * dra);
+    }
     r.gtel = (float)(0.5 * t.ke * (dt0 * t.el[0] + dt1 * t.el[1] + dt2 * t.el[2]));
-    r.graz = (float)(0.5 * q.ka * (dr0 * q.az[0] + dr1 * q.az[1] + dr2 * q.az[2]));
     r.grel = (float)(0.5 * q.ke * (dr0 * q.el[0] + dr1 * q.el[1] + dr2 * q.el[2]));
     r.irt = (float)irt;
     r.irt2 = (float)(irt * irt);
     r.irr = (float)irr;
     r.irr2 = (float)(irr * irr);
     const double sb = rtrr_mid * irt * irr;
-    const double dbt = dt0 * t.b[0] + dt1 * t.b[1] + dt2 * t.b[2];
-    const double dbr = dr0 * q.b[0] + dr1 * q.b[1] + dr2 * q.b[2];
+    const double dbt = STR ? dtb * cst + dta * snt : dtb;
+    const double dbr = STR ? drb * csr + dra * snr : drb;
     r.dbt = (float)dbt;
     r.dbr = (float)dbr;
     // Facets lie within ~100 m of the centre, so their direction cosines with a
@@ -178,6 +190,27 @@ __device__ __forceinline__ void facet_consts(const AntArgs &t, const AntArgs &q,
         k.bt[i] = t.b32[i];
         k.br[i] = q.b32[i];
     }
+}
+
+// The same constants for antennas turned by steering angles (cos, sin per
+// leg): azimuth axes az cos - b sin, boresights b cos + az sin.
+__device__ __forceinline__ void steer_consts(const AntArgs &t, const AntArgs &q, float ct,
+                                             float st, float cr, float sr, FacetConsts &k) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        k.kta[i] = fmaf(t.kaz[i], ct, -(t.kb[i] * st));
+        k.kra[i] = fmaf(q.kaz[i], cr, -(q.kb[i] * sr));
+        k.bt[i] = fmaf(t.b32[i], ct, t.az32[i] * st);
+        k.br[i] = fmaf(q.b32[i], cr, q.az32[i] * sr);
+    }
+}
+
+// Steering angles of one pulse: Tx at t_p, Rx at t_p + tau_ref.
+__device__ __forceinline__ void steer_angles(const AntArgs &t, const AntArgs &q, double tp,
+                                             double trx, double &cst, double &snt, double &csr,
+                                             double &snr) {
+    sincos(t.steer * tp, &snt, &cst);
+    sincos(q.steer * trx, &snr, &csr);
 }
 
 // Per-facet geometry of one (facet, pulse) pair.

@@ -59,10 +59,13 @@ struct Lattice {
 // Per-antenna constants, passed inside the kernel arguments (constant
 // address space, so uniform reads become scalar loads).
 struct AntArgs {
-    double az[3], el[3], b[3];  // frame
+    double az[3], el[3], b[3];  // frame at t = 0
     double ka, ke;              // kappa / beta_az, kappa / beta_el
+    double steer;               // rate of turn about el (rad/s), 0 = fixed frame
     float kaz[3], kel[3];       // (kappa/beta)/2 * axis, FP32, for the facet part
     float b32[3];               // boresight, FP32
+    float kb[3];                // (kappa/beta_az)/2 * boresight, FP32 (steering)
+    float az32[3];              // azimuth axis, FP32 (steering)
     float pad;
 };
 
@@ -109,6 +112,7 @@ struct FwdArgs {
     int n_patches;
     int halo;                   // bins added on each side of the patch span
     int rx_exact;               // receiver at each facet's own echo time
+    int steer;                  // some antenna frame turns with time
     double inv_c;               // 1 / c
     SpkArgs spk;                // speckle variant only
 };
@@ -130,6 +134,7 @@ struct AdjArgs {
     long long n_blocks;
     int accumulate;
     int rx_exact;               // receiver at each facet's own echo time
+    int steer;                  // some antenna frame turns with time
     double inv_c;               // 1 / c
     SpkArgs spk;                // speckle variant only
 };
@@ -149,6 +154,7 @@ struct sim_handle {
     std::vector<sim_channel> chans;
     int C;
     int rx_exact;
+    int steer;                  // some antenna has a nonzero steering rate
     // derived on the host in FP64
     double kappa;
     std::vector<hs::AntArgs> antc;

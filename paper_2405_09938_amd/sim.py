@@ -55,7 +55,8 @@ class Simulator:
             self._plats[i].v = N._d3(*p.v)
         self._ants = (N.SimAntenna * len(g.antennas))()
         for i, a in enumerate(g.antennas):
-            self._ants[i] = N.SimAntenna(a.platform, a.beta_az, a.beta_el)
+            self._ants[i] = N.SimAntenna(a.platform, a.beta_az, a.beta_el,
+                                         float(getattr(a, "steer_rate", 0.0)))
         self._chans = (N.SimChannel * len(g.channels))()
         for i, ch in enumerate(g.channels):
             self._chans[i] = N.SimChannel(ch.tx, ch.rx, N._d3(*ch.pc_offset))
