@@ -532,6 +532,13 @@ int sim_create(const sim_config *cfg, sim_handle **out) {
             }
             rx_pos(h, ch, r.t + tau, r.prx);
             r.rref = c * tau;
+            // steering angles (time-dependent antenna frames)
+            const double at = h->ants[h->chans[ch].tx_antenna].steer_rate * r.t;
+            const double ar = h->ants[h->chans[ch].rx_antenna].steer_rate * (r.t + tau);
+            r.cst = std::cos(at);
+            r.snt = std::sin(at);
+            r.csr = std::cos(ar);
+            r.snr = std::sin(ar);
             if (!std::isfinite(r.rref) || !(rt > 0)) {
                 delete h;
                 HS_FAIL(SIM_EINVAL, "pulse geometry is not finite");

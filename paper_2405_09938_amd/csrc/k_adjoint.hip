@@ -183,8 +183,12 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                 double qr = 1.0;
                 if (A.rx_exact) rx_echo(xb, yb, P.ptx, P.prx, P.rref, chn.vr, A.inv_c, prb, qr);
                 [[maybe_unused]] double cst = 1.0, snt = 0.0, csr = 1.0, snr = 0.0;
-                if constexpr (STR)
-                    steer_angles(ta, ra, P.t, P.t + P.rref * A.inv_c, cst, snt, csr, snr);
+                if constexpr (STR) {
+                    cst = P.cst;
+                    snt = P.snt;
+                    csr = P.csr;
+                    snr = P.snr;
+                }
                 Refs r;
                 block_refs<ELC, STR>(xb, yb, P.ptx, prb, P.rref, ta, ra, chn.rtrr_mid, A.f0_c,
                                 A.fs_c, A.n_ref, live, r, qr, cst, snt, csr, snr);
@@ -302,10 +306,15 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                     dop = __builtin_amdgcn_fractf(dh) + dl;
                 }
                 FacetConsts kq = kc;
-                if constexpr (STR) steer_consts(ta, ra, o[kSt], o[kSt + 1], o[kSt + 2], o[kSt + 3], kq);
+                [[maybe_unused]] float4 rot{1.f, 0.f, 1.f, 0.f};
+                if constexpr (STR) {
+                    rot = float4{o[kSt], o[kSt + 1], o[kSt + 2], o[kSt + 3]};
+                    steer_axes(ta, ra, rot.x, rot.y, rot.z, rot.w, kq);
+                }
                 Geo g;
-                facet_geo<ELC, SPK>(r, kq, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz, r.graze != 0,
-                               o[R_LHI], o[R_LLO], o[R_FSQ], dop, g);
+                facet_geo<ELC, SPK, STR>(r, kq, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz,
+                                         r.graze != 0, o[R_LHI], o[R_LLO], o[R_FSQ], dop, g, &ta,
+                                         &ra, rot);
                 float tap[8], dtap[8];
                 taps_d8(tv, g.f, tap, dtap);
                 // g at samples floor(u) - 3 .. floor(u) + 4

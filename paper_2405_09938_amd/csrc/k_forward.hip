@@ -173,10 +173,13 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
 
     const PulseRec &P = PR[plc];
     // antenna frames of this pulse (time-dependent patterns)
-    [[maybe_unused]] double cst = 1.0, snt = 0.0, csr = 1.0, snr = 0.0;
+    // (float cosines and sines: they scale projections whose float rounding
+    // stays below 1e-8 of the direction cosines; boresights are turned
+    // only in grazing blocks)
+    [[maybe_unused]] float4 rot{1.f, 0.f, 1.f, 0.f};
     if constexpr (STR) {
-        steer_angles(ta, ra, P.t, P.t + P.rref * A.inv_c, cst, snt, csr, snr);
-        steer_consts(ta, ra, (float)cst, (float)snt, (float)csr, (float)snr, kc);
+        rot = float4{(float)P.cst, (float)P.snt, (float)P.csr, (float)P.snr};
+        steer_axes(ta, ra, rot.x, rot.y, rot.z, rot.w, kc);
     }
     const double ptx[3] = {P.ptx[0], P.ptx[1], P.ptx[2]};
     const double prx[3] = {P.prx[0], P.prx[1], P.prx[2]};
@@ -218,7 +221,7 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
         if (A.rx_exact)
             rx_echo((double)blk.xb, (double)blk.yb, ptx, prx, rref, A.ch[ch].vr, A.inv_c, prb, qr);
         block_refs<ELC, STR>((double)blk.xb, (double)blk.yb, ptx, prb, rref, ta, ra, chn.rtrr_mid,
-                        A.f0_c, A.fs_c, A.n_ref, live, r, qr, cst, snt, csr, snr);
+                        A.f0_c, A.fs_c, A.n_ref, live, r, qr, rot.x, rot.y, rot.z, rot.w);
         const bool graze_any = __any(r.graze);
         // the window offset of the first tap rides in the sample fraction, so
         // the floor of the sample position is the window index directly
@@ -227,20 +230,20 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
         FacetV fn = load_facet(rs, 0);
         // speckle records and anchors of the block (unused without speckle)
         const int ng1 = S.n_groups + 1;
-        const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc(
+        const __amdgpu_buffer_rsrc_t rs_rec = __builtin_amdgcn_make_buffer_rsrc(
             (void *)(S.rec + blk.start), 0, (blk.count + 1) * (int)sizeof(SpkRec), 0x00020000);
-        const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+        const __amdgpu_buffer_rsrc_t rs_anc = __builtin_amdgcn_make_buffer_rsrc(
             (void *)(S.anch + (size_t)blk.start * ng1), 0,
             (blk.count + 1) * ng1 * (int)sizeof(float4), 0x00020000);
         [[maybe_unused]] SpkFacet sn{};
-        if constexpr (SPK) sn = load_spk(rr, ra, 0, ng1, gabs);
+        if constexpr (SPK) sn = load_spk(rs_rec, rs_anc, 0, ng1, gabs);
         for (int j = 0; j < blk.count; ++j) {
             const FacetV f = fn;
             fn = load_facet(rs, j + 1);
             float far = f.ar, fai = f.ai, dop = 0.0f;
             if constexpr (SPK) {
                 const SpkFacet sp = sn;
-                sn = load_spk(rr, ra, j + 1, ng1, gabs);
+                sn = load_spk(rs_rec, rs_anc, j + 1, ng1, gabs);
                 // free path of the group: innovations, prefix sum, end value
                 const float2 e = spk_draw(S.key, sp.id, slot, l1);
                 float wr = e.x, wi = e.y;
@@ -259,8 +262,8 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
                 dop = __builtin_amdgcn_fractf(dh) + dl;
             }
             Geo g;
-            facet_geo<ELC, SPK>(r, kc, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz, graze_any, r.lhi,
-                      r.llo, r.fsq, dop, g);
+            facet_geo<ELC, SPK, STR>(r, kc, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz, graze_any, r.lhi,
+                                r.llo, r.fsq, dop, g, &ta, &ra, rot);
             // Each lane owns its pulse row, so the deposit is a plain
             // read-modify-write of 8 consecutive complex samples.
             const int n0 = g.fl;                  // window index of the first tap

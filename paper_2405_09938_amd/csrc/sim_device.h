@@ -192,25 +192,16 @@ __device__ __forceinline__ void facet_consts(const AntArgs &t, const AntArgs &q,
     }
 }
 
-// The same constants for antennas turned by steering angles (cos, sin per
-// leg): azimuth axes az cos - b sin, boresights b cos + az sin.
-__device__ __forceinline__ void steer_consts(const AntArgs &t, const AntArgs &q, float ct,
-                                             float st, float cr, float sr, FacetConsts &k) {
+// Facet constants for antennas turned by steering angles (cos, sin per leg):
+// the azimuth axes az cos - b sin (scaled); the boresights b cos + az sin are
+// turned where they are used (facet_geo's back-plane test).
+__device__ __forceinline__ void steer_axes(const AntArgs &t, const AntArgs &q, float ct,
+                                           float st, float cr, float sr, FacetConsts &k) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         k.kta[i] = fmaf(t.kaz[i], ct, -(t.kb[i] * st));
         k.kra[i] = fmaf(q.kaz[i], cr, -(q.kb[i] * sr));
-        k.bt[i] = fmaf(t.b32[i], ct, t.az32[i] * st);
-        k.br[i] = fmaf(q.b32[i], cr, q.az32[i] * sr);
     }
-}
-
-// Steering angles of one pulse: Tx at t_p, Rx at t_p + tau_ref.
-__device__ __forceinline__ void steer_angles(const AntArgs &t, const AntArgs &q, double tp,
-                                             double trx, double &cst, double &snt, double &csr,
-                                             double &snr) {
-    sincos(t.steer * tp, &snt, &cst);
-    sincos(q.steer * trx, &snr, &csr);
 }
 
 // Per-facet geometry of one (facet, pulse) pair.
@@ -225,11 +216,16 @@ struct Geo {
     int fl;          // floor(fb + dR fs/c): sample offset from the centre's
 };
 
-template <bool ELC, bool DOP = false>
+// ROT: the boresights of cc are the fixed-frame ones and the back-plane test
+// (grazing blocks only) turns them by rot = (cos, sin) of the Tx and Rx
+// steering angles, with the antennas' FP32 axes (t, q).
+template <bool ELC, bool DOP = false, bool ROT = false>
 __device__ __forceinline__ void facet_geo(const Refs &r, const FacetConsts &cc, float tf,
                                           float fdx, float fdy, float fz, float fvx, float fvy,
                                           float fvz, bool graze_any, float linv_hi,
-                                          float linv_lo, float fs_c, float dop, Geo &o) {
+                                          float linv_lo, float fs_c, float dop, Geo &o,
+                                          const AntArgs *t = nullptr, const AntArgs *q = nullptr,
+                                          float4 rot = float4{1.f, 0.f, 1.f, 0.f}) {
     const float ex = fmaf(fvx, tf, fdx);
     const float ey = fmaf(fvy, tf, fdy);
     const float ez = fmaf(fvz, tf, fz);
@@ -278,8 +274,16 @@ __device__ __forceinline__ void facet_geo(const Refs &r, const FacetConsts &cc, 
     float amp = sp * __builtin_amdgcn_rcpf(yp) * s;
     o.mf = 1.0f;
     if (graze_any && r.graze) {
-        const float ct = fmaf(ez, cc.bt[2], fmaf(ey, cc.bt[1], fmaf(ex, cc.bt[0], r.dbt)));
-        const float cr = fmaf(ez, cc.br[2], fmaf(ey, cc.br[1], fmaf(ex, cc.br[0], r.dbr)));
+        float bt[3] = {cc.bt[0], cc.bt[1], cc.bt[2]}, br[3] = {cc.br[0], cc.br[1], cc.br[2]};
+        if constexpr (ROT) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                bt[i] = fmaf(t->b32[i], rot.x, t->az32[i] * rot.y);
+                br[i] = fmaf(q->b32[i], rot.z, q->az32[i] * rot.w);
+            }
+        }
+        const float ct = fmaf(ez, bt[2], fmaf(ey, bt[1], fmaf(ex, bt[0], r.dbt)));
+        const float cr = fmaf(ez, br[2], fmaf(ey, br[1], fmaf(ex, br[0], r.dbr)));
         if (!(ct > 0.0f && cr > 0.0f)) {
             amp = 0.0f;
             o.mf = 0.0f;

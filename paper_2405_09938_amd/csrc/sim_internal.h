@@ -19,6 +19,8 @@ struct PulseRec {
     double ptx[3];   // Tx phase centre at t_p
     double prx[3];   // Rx phase centre at t_p + tau_ref
     double rref;     // c * tau_ref: bistatic range of O
+    double cst, snt; // cos, sin of the Tx antenna's steering angle at t_p
+    double csr, snr; // cos, sin of the Rx antenna's steering angle at t_p + tau_ref
 };
 
 // Sorted facet copy, one record per facet in block order (32 bytes, so one
