@@ -273,6 +273,10 @@ int sim_plan_mode(const sim_plan *plan, int *el_const, double *el_bound);
  * of `sea` (row-major in the sub-rectangle).  Random draws use Philox4x32-10
  * keyed by `seed` with the global grid index as counter, so any chunking of
  * the grid yields the same facets.  out->n must equal cnx*cny.
+ * Errors: SIM_EINVAL (NULL arguments, sub-rectangle outside the grid, bad
+ * sea description: unknown mode, missing arrays, bad spectrum, a tile
+ * lattice that does not cover the grid, negative heights), checked before
+ * any device work; SIM_EHIP.
  */
 int sim_generate_facets(sim_handle *h, const sim_sea *sea, unsigned long long seed,
                         int ix0, int iy0, int cnx, int cny, const sim_facets_out *out,

@@ -837,10 +837,38 @@ int sim_plan_mode(const sim_plan *P, int *el_const, double *el_bound) {
     return SIM_OK;
 }
 
+// Validation of a sea description (before any device work).
+static int sea_ok(const sim_sea *sea) {
+    if (sea->mode < 0 || sea->mode > 2) HS_FAIL(SIM_EINVAL, "sea mode must be 0, 1 or 2");
+    if (sea->mode == 0) return SIM_OK;
+    const int nc = sea->n_comp;
+    if (nc < 1 || nc > 4096) HS_FAIL(SIM_EINVAL, "wave modes need 1..4096 components");
+    if (!(sea->k_min > 0) || !(sea->k_max >= sea->k_min) || !(sea->g > 0))
+        HS_FAIL(SIM_EINVAL, "bad wave spectrum parameters");
+    if (sea->mode == 1) {
+        if (!sea->dirs || !sea->phases || !(sea->hs >= 0))
+            HS_FAIL(SIM_EINVAL, "mode 1 needs dirs, phases and hs >= 0");
+        return SIM_OK;
+    }
+    if (sea->ntx < 1 || sea->nty < 1 || !(sea->tile_L > 0) || !sea->node_hs ||
+        !sea->node_dirs || !sea->node_phases)
+        HS_FAIL(SIM_EINVAL, "mode 2 needs ntx, nty >= 1, tile_L > 0 and node arrays");
+    const long long nodes = (long long)(sea->ntx + 1) * (sea->nty + 1);
+    if (nodes * nc > (1LL << 22)) HS_FAIL(SIM_EINVAL, "too many node components");
+    // the lattice must cover the grid
+    const double hx = 0.5 * (sea->nx - 1) * sea->dx, hy = 0.5 * (sea->ny - 1) * sea->dy;
+    if (!(sea->tile_x0 <= -hx) || !(sea->tile_y0 <= -hy) ||
+        !(sea->tile_x0 + sea->ntx * sea->tile_L >= hx) ||
+        !(sea->tile_y0 + sea->nty * sea->tile_L >= hy))
+        HS_FAIL(SIM_EINVAL, "mode 2: the tile lattice does not cover the grid");
+    for (long long q = 0; q < nodes; ++q)
+        if (!(sea->node_hs[q] >= 0)) HS_FAIL(SIM_EINVAL, "mode 2: node_hs must be >= 0");
+    return SIM_OK;
+}
+
 int sim_generate_facets(sim_handle *h, const sim_sea *sea, unsigned long long seed, int ix0,
                         int iy0, int cnx, int cny, const sim_facets_out *out, void *stream) {
     if (!h || !sea || !out) HS_FAIL(SIM_EINVAL, "handle, sea or out is NULL");
-    if (int rc = ensure_device(h)) return rc;
     if (sea->nx < 1 || sea->ny < 1 || !(sea->dx > 0) || !(sea->dy > 0))
         HS_FAIL(SIM_EINVAL, "grid size and spacing must be positive");
     if (ix0 < 0 || iy0 < 0 || cnx < 0 || cny < 0 || (long long)ix0 + cnx > sea->nx ||
@@ -850,7 +878,8 @@ int sim_generate_facets(sim_handle *h, const sim_sea *sea, unsigned long long se
     if (out->n > 0 && (!out->x || !out->y || !out->z || !out->vx || !out->vy || !out->vz ||
                        !out->a_re || !out->a_im))
         HS_FAIL(SIM_EINVAL, "an output array pointer is NULL");
-    if (sea->mode < 0 || sea->mode > 2) HS_FAIL(SIM_EINVAL, "sea mode must be 0, 1 or 2");
+    if (int rc = sea_ok(sea)) return rc;
+    if (int rc = ensure_device(h)) return rc;
     hs::GenArgs a{};
     a.nx = sea->nx;
     a.ny = sea->ny;
@@ -870,31 +899,13 @@ int sim_generate_facets(sim_handle *h, const sim_sea *sea, unsigned long long se
     a.cwm = sea->cwm ? 1 : 0;
     if (sea->mode >= 1) {
         const int nc = sea->n_comp;
-        if (nc < 1 || nc > 4096)
-            HS_FAIL(SIM_EINVAL, "wave modes need 1..4096 components");
-        if (!(sea->k_min > 0) || !(sea->k_max >= sea->k_min) || !(sea->g > 0))
-            HS_FAIL(SIM_EINVAL, "bad wave spectrum parameters");
         // one table per homogeneous field: mode 1 has one, mode 2 one per node
+        // (parameters checked by sea_ok)
         int nodes = 1;
         const double *hs_of = &sea->hs;
         const double *dirs = sea->dirs, *phases = sea->phases;
-        if (sea->mode == 1) {
-            if (!sea->dirs || !sea->phases || !(sea->hs >= 0))
-                HS_FAIL(SIM_EINVAL, "mode 1 needs dirs, phases and hs >= 0");
-        } else {
-            if (sea->ntx < 1 || sea->nty < 1 || !(sea->tile_L > 0) || !sea->node_hs ||
-                !sea->node_dirs || !sea->node_phases)
-                HS_FAIL(SIM_EINVAL, "mode 2 needs ntx, nty >= 1, tile_L > 0 and node arrays");
+        if (sea->mode == 2) {
             nodes = (sea->ntx + 1) * (sea->nty + 1);
-            if ((long long)nodes * nc > (1LL << 22)) HS_FAIL(SIM_EINVAL, "too many node components");
-            // the lattice must cover the grid
-            const double hx = 0.5 * (sea->nx - 1) * sea->dx, hy = 0.5 * (sea->ny - 1) * sea->dy;
-            if (sea->tile_x0 > -hx || sea->tile_y0 > -hy ||
-                sea->tile_x0 + sea->ntx * sea->tile_L < hx ||
-                sea->tile_y0 + sea->nty * sea->tile_L < hy)
-                HS_FAIL(SIM_EINVAL, "mode 2: the tile lattice does not cover the grid");
-            for (int q = 0; q < nodes; ++q)
-                if (!(sea->node_hs[q] >= 0)) HS_FAIL(SIM_EINVAL, "mode 2: node_hs must be >= 0");
             hs_of = sea->node_hs;
             dirs = sea->node_dirs;
             phases = sea->node_phases;

@@ -35,7 +35,7 @@ def _config(N, geom):
         plats[i].v = N._d3(*p.v)
     ants = (N.SimAntenna * len(geom.antennas))()
     for i, a in enumerate(geom.antennas):
-        ants[i] = N.SimAntenna(a.platform, a.beta_az, a.beta_el)
+        ants[i] = N.SimAntenna(a.platform, a.beta_az, a.beta_el, a.steer_rate)
     chans = (N.SimChannel * len(geom.channels))()
     for i, ch in enumerate(geom.channels):
         chans[i] = N.SimChannel(ch.tx, ch.rx, N._d3(*ch.pc_offset))
@@ -46,6 +46,7 @@ def _config(N, geom):
     cfg.n_platforms, cfg.platforms = len(geom.platforms), plats
     cfg.n_antennas, cfg.antennas = len(geom.antennas), ants
     cfg.n_channels, cfg.channels = len(geom.channels), chans
+    cfg.rx_exact = 1 if geom.rx_exact else 0
     return cfg, (plats, ants, chans)
 
 
@@ -77,6 +78,10 @@ def test_create_validates_before_any_device_call(native):
     cfg, keep = _config(native, g)
     keep[1][0].beta_az = 1e-4
     assert L.sim_create(ctypes.byref(cfg), ctypes.byref(h)) == native.SIM_EUNSUPPORTED
+    # a steering rate must be finite
+    cfg, keep = _config(native, g)
+    keep[1][0].steer_rate = float("nan")
+    assert L.sim_create(ctypes.byref(cfg), ctypes.byref(h)) == native.SIM_EINVAL
 
 
 def test_entry_points_reject_null(native):
@@ -164,5 +169,58 @@ def test_stream_entry_points_validate(native):
                                     ctypes.c_void_p(16), 0, None) == native.SIM_EINVAL
         assert L.sim_stream_backward(h, ctypes.byref(sea), 1, ok, 0, 8.0, 0, 8, None, None,
                                      None, None, None) == native.SIM_EINVAL
+    finally:
+        L.sim_destroy(h)
+
+
+def test_generate_validates_sea_before_any_device_call(native):
+    """Bad sea descriptions (unknown mode, missing arrays, a tile lattice not
+    covering the grid, a negative node height) are refused with SIM_EINVAL
+    before the device is touched (there is none here: a device call would
+    answer SIM_EHIP)."""
+    L = native.load()
+    g = W.harmony_geometry(8, 64)
+    cfg, keep = _config(native, g)
+    h = ctypes.c_void_p()
+    assert L.sim_create(ctypes.byref(cfg), ctypes.byref(h)) == native.SIM_OK
+    try:
+        n = 40 * 30
+        bufs = [np.zeros(n, np.float32) for _ in range(8)]
+        out = native.SimFacetsOut(n, *[b.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+                                       for b in bufs])
+        dp = ctypes.POINTER(ctypes.c_double)
+        het = W.hetero_sea(40, 30, 2.0, seed=1, tile_L=20.0)
+        hs_ = np.ascontiguousarray(het.node_hs, np.float64)
+        d = np.ascontiguousarray(het.node_dirs, np.float64).ravel()
+        ph = np.ascontiguousarray(het.node_phases, np.float64).ravel()
+
+        def sea2(**kw):
+            s = native.SimSea()
+            s.nx, s.ny, s.dx, s.dy, s.mode, s.n_comp = 40, 30, 2.0, 2.0, 2, het.n_comp
+            s.k_min, s.k_max, s.slope, s.hs, s.g = het.k_min, het.k_max, het.slope, 2.0, 9.81
+            s.ntx, s.nty, s.tile_L, s.tile_x0, s.tile_y0 = (het.ntx, het.nty, het.tile_L,
+                                                            het.tile_x0, het.tile_y0)
+            s.node_hs, s.node_dirs, s.node_phases = (hs_.ctypes.data_as(dp), d.ctypes.data_as(dp),
+                                                     ph.ctypes.data_as(dp))
+            for k, v in kw.items():
+                setattr(s, k, v)
+            return s
+
+        def rc(s):
+            return L.sim_generate_facets(h, ctypes.byref(s), 1, 0, 0, 40, 30, ctypes.byref(out),
+                                         None)
+
+        assert rc(sea2(mode=3)) == native.SIM_EINVAL
+        assert rc(sea2(tile_x0=het.tile_x0 + 5.0)) == native.SIM_EINVAL
+        assert b"cover" in L.sim_last_error()
+        assert rc(sea2(ntx=0)) == native.SIM_EINVAL
+        assert rc(sea2(node_hs=None)) == native.SIM_EINVAL
+        assert rc(sea2(n_comp=0)) == native.SIM_EINVAL
+        assert rc(sea2(mode=1)) == native.SIM_EINVAL       # mode 1 without dirs, phases
+        neg = hs_.copy()
+        neg[3] = -1.0
+        assert rc(sea2(node_hs=neg.ctypes.data_as(dp))) == native.SIM_EINVAL
+        # a valid description passes validation and then needs a device
+        assert rc(sea2()) != native.SIM_EINVAL
     finally:
         L.sim_destroy(h)
