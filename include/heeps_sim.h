@@ -384,6 +384,27 @@ int sim_stream_backward(sim_handle *h, const sim_sea *sea, unsigned long long se
                         const int *chunks, int n_chunks, double block_edge, int p0, int np,
                         const float *g_rc, float *dvx, float *dvy, float *dvz, void *stream);
 
+/*
+ * sim_stream_forward with the intra-facet speckle (Sec. III.A eq. 7 and
+ * eq. 10, as sim_forward_speckle) over a generated scene: the facet at grid
+ * point (ix, iy) takes the id speckle->first_index + iy * nx + ix (nx =
+ * sea->nx), whatever chunk it falls in, and speckle->f_s, if not NULL, is
+ * indexed the same way (device float32 [sea->nx * sea->ny], Hz).  So any
+ * split of the grid into chunks gives the speckle of the whole scene.
+ * Errors as sim_stream_forward and sim_forward_speckle.
+ */
+int sim_stream_forward_speckle(sim_handle *h, const sim_sea *sea, unsigned long long seed,
+                               const int *chunks, int n_chunks, double block_edge,
+                               const sim_speckle *speckle, int p0, int np, float *iq_rc,
+                               int accumulate, void *stream);
+
+/* Adjoint of sim_stream_forward_speckle with respect to the facet velocities
+ * (outputs as sim_stream_backward, speckle as sim_stream_forward_speckle). */
+int sim_stream_backward_speckle(sim_handle *h, const sim_sea *sea, unsigned long long seed,
+                                const int *chunks, int n_chunks, double block_edge,
+                                const sim_speckle *speckle, int p0, int np, const float *g_rc,
+                                float *dvx, float *dvy, float *dvz, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -92,7 +92,8 @@ EXPORTS = ("sim_create", "sim_destroy", "sim_last_error", "sim_pulse_info",
            "sim_plan_mode",
            "sim_generate_facets", "sim_forward", "sim_apply_waveform",
            "sim_apply_waveform_adjoint", "sim_backward", "sim_stream_forward",
-           "sim_stream_backward", "sim_forward_speckle", "sim_backward_speckle")
+           "sim_stream_backward", "sim_forward_speckle", "sim_backward_speckle",
+           "sim_stream_forward_speckle", "sim_stream_backward_speckle")
 
 _lib = None
 
@@ -141,6 +142,11 @@ def load(path: str = LIB_PATH):
                                      i, i, vp, i, vp]
     L.sim_stream_backward.argtypes = [vp, P(SimSea), ctypes.c_ulonglong, ip, i, ctypes.c_double,
                                       i, i, vp, vp, vp, vp, vp]
+    L.sim_stream_forward_speckle.argtypes = [vp, P(SimSea), ctypes.c_ulonglong, ip, i,
+                                             ctypes.c_double, P(SimSpeckle), i, i, vp, i, vp]
+    L.sim_stream_backward_speckle.argtypes = [vp, P(SimSea), ctypes.c_ulonglong, ip, i,
+                                              ctypes.c_double, P(SimSpeckle), i, i, vp, vp, vp,
+                                              vp, vp]
     for name in EXPORTS:
         if name not in ("sim_destroy", "sim_last_error", "sim_plan_destroy"):
             getattr(L, name).restype = ctypes.c_int

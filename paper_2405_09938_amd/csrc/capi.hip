@@ -974,8 +974,11 @@ static int speckle_ok(const sim_handle *h, const sim_speckle *sp) {
 // bridge gains K_k = b^(64-k) (1 - b^2k) / (1 - b^128) (k / 64 at a = 0) and
 // the innovation scales sqrt(1 - b^2), sqrt(1 - b^128); then the per-facet
 // records and anchors of the groups the pulse range covers.
+// chunk: (ix0, iy0, cnx, cny) of a generated chunk of a grid grid_nx wide, whose
+// facets take ids and Doppler by grid index; NULL for a caller's facet set.
 static int speckle_prepare(sim_handle *h, sim_plan *P, const sim_speckle *sp, int p0, int np,
-                           bool with_d, hipStream_t s, hs::SpkArgs &k) {
+                           bool with_d, const int *chunk, int grid_nx, hipStream_t s,
+                           hs::SpkArgs &k) {
     const double a = std::isinf(sp->tau_s) ? 0.0 : 1.0 / (h->prf * sp->tau_s);
     for (int m = 0; m <= 64; ++m) k.bpow[m] = (float)std::exp(-a * m);
     for (int j = 0; j < 64; ++j)
@@ -1009,13 +1012,19 @@ static int speckle_prepare(sim_handle *h, sim_plan *P, const sim_speckle *sp, in
     pp.g_lo = p0 >> 6;
     pp.g_hi = (p0 + np - 1) >> 6;
     pp.with_d = with_d;
+    if (chunk) {
+        pp.grid_nx = grid_nx;
+        pp.sub_x0 = chunk[0];
+        pp.sub_y0 = chunk[1];
+        pp.sub_nx = chunk[2];
+    }
     HS_HIP(hs::launch_speckle_prep(pp, k, P->spk, P->anch, s), "speckle preparation");
     return SIM_OK;
 }
 
 static int forward_common(sim_handle *h, sim_plan *P, const sim_facets *f,
                           const sim_speckle *sp, int p0, int np, float *iq, int accumulate,
-                          void *stream) {
+                          void *stream, const int *chunk = nullptr, int grid_nx = 0) {
     if (!h || !P) HS_FAIL(SIM_EINVAL, "handle or plan is NULL");
     if (P->h != h) HS_FAIL(SIM_EINVAL, "plan belongs to another handle");
     if (int rc = facets_ok(f, P->n)) return rc;
@@ -1029,7 +1038,8 @@ static int forward_common(sim_handle *h, sim_plan *P, const sim_facets *f,
     HS_HIP(hs::launch_gather(*f, P->perm, P->blocks, P->n_blocks, P->sorted, s), "gather");
     hs::FwdArgs a{};
     if (sp)
-        if (int rc = speckle_prepare(h, P, sp, p0, np, false, s, a.spk)) return rc;
+        if (int rc = speckle_prepare(h, P, sp, p0, np, false, chunk, grid_nx, s, a.spk))
+            return rc;
     if (!accumulate)
         HS_HIP(hs::launch_fill_zero(iq, 2LL * h->C * np * h->N, s), "zero iq");
     a.facets = P->sorted;
@@ -1074,7 +1084,8 @@ int sim_forward_speckle(sim_handle *h, sim_plan *P, const sim_facets *f,
 
 static int backward_common(sim_handle *h, sim_plan *P, const sim_facets *f,
                            const sim_speckle *sp, int p0, int np, const float *g,
-                           const sim_facet_grads *gr, int accumulate, void *stream) {
+                           const sim_facet_grads *gr, int accumulate, void *stream,
+                           const int *chunk = nullptr, int grid_nx = 0) {
     if (!h || !P) HS_FAIL(SIM_EINVAL, "handle or plan is NULL");
     if (P->h != h) HS_FAIL(SIM_EINVAL, "plan belongs to another handle");
     if (int rc = facets_ok(f, P->n)) return rc;
@@ -1097,7 +1108,8 @@ static int backward_common(sim_handle *h, sim_plan *P, const sim_facets *f,
     HS_HIP(hs::launch_gather(*f, P->perm, P->blocks, P->n_blocks, P->sorted, s), "gather");
     hs::AdjArgs a{};
     if (sp)
-        if (int rc = speckle_prepare(h, P, sp, p0, np, true, s, a.spk)) return rc;
+        if (int rc = speckle_prepare(h, P, sp, p0, np, true, chunk, grid_nx, s, a.spk))
+            return rc;
     a.facets = P->sorted;
     a.blocks = P->blocks;
     a.perm = P->perm;
@@ -1227,13 +1239,15 @@ sim_facets as_in(const sim_facets_out &o) {
 
 extern "C" {
 
-int sim_stream_forward(sim_handle *h, const sim_sea *sea, unsigned long long seed,
-                       const int *chunks, int n_chunks, double block_edge, int p0, int np,
-                       float *iq, int accumulate, void *stream) {
+static int stream_forward_common(sim_handle *h, const sim_sea *sea, unsigned long long seed,
+                                 const int *chunks, int n_chunks, double block_edge,
+                                 const sim_speckle *sp, int p0, int np, float *iq,
+                                 int accumulate, void *stream) {
     if (!h) HS_FAIL(SIM_EINVAL, "handle is NULL");
     long long max_n = 0;
     if (int rc = check_chunks(sea, chunks, n_chunks, &max_n)) return rc;
     if (p0 < 0 || np < 0 || (long long)p0 + np > h->Np) HS_FAIL(SIM_EINVAL, "pulse range");
+    if (int rc = speckle_ok(h, sp)) return rc;
     if (!iq) HS_FAIL(SIM_EINVAL, "iq is NULL");
     if (int rc = ensure_device(h)) return rc;
     hipStream_t s = (hipStream_t)stream;
@@ -1248,7 +1262,7 @@ int sim_stream_forward(sim_handle *h, const sim_sea *sea, unsigned long long see
         sim_plan *P = nullptr;
         if (int rc = sim_plan_create(h, o.x, o.y, n, block_edge, stream, &P)) return rc;
         const sim_facets f = as_in(o);
-        int rc = sim_forward(h, P, &f, p0, np, iq, 1, stream);
+        int rc = forward_common(h, P, &f, sp, p0, np, iq, 1, stream, c, sea->nx);
         // the plan's buffers are in use by the queued forward
         hipError_t e = hipStreamSynchronize(s);
         sim_plan_destroy(P);
@@ -1258,14 +1272,32 @@ int sim_stream_forward(sim_handle *h, const sim_sea *sea, unsigned long long see
     return SIM_OK;
 }
 
-int sim_stream_backward(sim_handle *h, const sim_sea *sea, unsigned long long seed,
-                        const int *chunks, int n_chunks, double block_edge, int p0, int np,
-                        const float *g, float *dvx, float *dvy, float *dvz, void *stream) {
+int sim_stream_forward(sim_handle *h, const sim_sea *sea, unsigned long long seed,
+                       const int *chunks, int n_chunks, double block_edge, int p0, int np,
+                       float *iq, int accumulate, void *stream) {
+    return stream_forward_common(h, sea, seed, chunks, n_chunks, block_edge, nullptr, p0, np,
+                                 iq, accumulate, stream);
+}
+
+int sim_stream_forward_speckle(sim_handle *h, const sim_sea *sea, unsigned long long seed,
+                               const int *chunks, int n_chunks, double block_edge,
+                               const sim_speckle *speckle, int p0, int np, float *iq,
+                               int accumulate, void *stream) {
+    if (!speckle) HS_FAIL(SIM_EINVAL, "speckle is NULL");
+    return stream_forward_common(h, sea, seed, chunks, n_chunks, block_edge, speckle, p0, np,
+                                 iq, accumulate, stream);
+}
+
+static int stream_backward_common(sim_handle *h, const sim_sea *sea, unsigned long long seed,
+                                  const int *chunks, int n_chunks, double block_edge,
+                                  const sim_speckle *sp, int p0, int np, const float *g,
+                                  float *dvx, float *dvy, float *dvz, void *stream) {
     if (!h) HS_FAIL(SIM_EINVAL, "handle is NULL");
     long long max_n = 0;
     if (int rc = check_chunks(sea, chunks, n_chunks, &max_n)) return rc;
     if (p0 < 0 || np < 0 || (long long)p0 + np > h->Np) HS_FAIL(SIM_EINVAL, "pulse range");
     if (!g) HS_FAIL(SIM_EINVAL, "g is NULL");
+    if (int rc = speckle_ok(h, sp)) return rc;
     if (int rc = ensure_device(h)) return rc;
     hipStream_t s = (hipStream_t)stream;
     ChunkWs ws;
@@ -1287,7 +1319,7 @@ int sim_stream_backward(sim_handle *h, const sim_sea *sea, unsigned long long se
         gr.dvz = dvz ? dvz + off : nullptr;
         gr.da_re = nullptr;
         gr.da_im = nullptr;
-        int rc = sim_backward(h, P, &f, p0, np, g, &gr, 0, stream);
+        int rc = backward_common(h, P, &f, sp, p0, np, g, &gr, 0, stream, c, sea->nx);
         hipError_t e = hipStreamSynchronize(s);
         sim_plan_destroy(P);
         if (rc) return rc;
@@ -1295,6 +1327,22 @@ int sim_stream_backward(sim_handle *h, const sim_sea *sea, unsigned long long se
         off += n;
     }
     return SIM_OK;
+}
+
+int sim_stream_backward(sim_handle *h, const sim_sea *sea, unsigned long long seed,
+                        const int *chunks, int n_chunks, double block_edge, int p0, int np,
+                        const float *g, float *dvx, float *dvy, float *dvz, void *stream) {
+    return stream_backward_common(h, sea, seed, chunks, n_chunks, block_edge, nullptr, p0, np,
+                                  g, dvx, dvy, dvz, stream);
+}
+
+int sim_stream_backward_speckle(sim_handle *h, const sim_sea *sea, unsigned long long seed,
+                                const int *chunks, int n_chunks, double block_edge,
+                                const sim_speckle *speckle, int p0, int np, const float *g,
+                                float *dvx, float *dvy, float *dvz, void *stream) {
+    if (!speckle) HS_FAIL(SIM_EINVAL, "speckle is NULL");
+    return stream_backward_common(h, sea, seed, chunks, n_chunks, block_edge, speckle, p0, np,
+                                  g, dvx, dvy, dvz, stream);
 }
 
 }  // extern "C"

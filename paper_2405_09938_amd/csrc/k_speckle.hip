@@ -5,7 +5,8 @@
 // walk the pulses one by one, also D_g = y_{g+1} - z_64 (the free path of
 // group g run to its end), so that x(p) = z_k + K_k D_g is known at each
 // pulse.  One lane per facet; anchors are few (one per 64 pulses), the D_g
-// pass draws every innovation once.
+// pass draws every innovation once.  Facets of a generated grid chunk take
+// their ids (and Doppler) from their grid index.
 #include "spk_device.h"
 
 namespace hs {
@@ -24,8 +25,11 @@ __global__ __launch_bounds__(256) void k_speckle_prep(SpkPrep P, SpkArgs K, SpkR
         return;
     }
     const int i = P.perm[j];
-    const uint32_t id = (uint32_t)(P.first_index + i);
-    rec[j] = SpkRec{id, P.fs ? P.fs[i] : 0.0f};
+    const long long gi = P.sub_nx > 0 ? (long long)(P.sub_y0 + i / P.sub_nx) * P.grid_nx +
+                                            P.sub_x0 + i % P.sub_nx
+                                      : (long long)i;
+    const uint32_t id = (uint32_t)(P.first_index + gi);
+    rec[j] = SpkRec{id, P.fs ? P.fs[gi] : 0.0f};
     const float l2 = 0.69314718055994531f;
     const float l64 = K.c64 * K.c64 * l2, l1 = K.c1 * K.c1 * l2;
     float2 y = spk_draw(K.key, id, kSpkAnchorSlot, l2);

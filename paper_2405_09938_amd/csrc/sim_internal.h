@@ -249,6 +249,11 @@ struct SpkPrep {
     long long first_index;
     int g_lo, g_hi;
     bool with_d;
+    // grid mapping of a generated chunk (sub_nx > 0): facet i of the chunk
+    // (row-major in its sub-rectangle) is grid point
+    // (sub_y0 + i / sub_nx) * grid_nx + sub_x0 + i % sub_nx, which gives its
+    // id (first_index + that index) and indexes fs
+    int grid_nx, sub_x0, sub_y0, sub_nx;
 };
 hipError_t launch_speckle_prep(const SpkPrep &p, const SpkArgs &k, SpkRec *rec, float4 *anch,
                                hipStream_t s);

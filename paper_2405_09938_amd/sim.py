@@ -166,8 +166,11 @@ class Simulator:
 
     def stream_forward(self, sea, seed: int, chunks, block_edge: float = 8.0, p0: int = 0,
                        np_: Optional[int] = None, out: Optional[torch.Tensor] = None,
-                       accumulate: bool = False) -> torch.Tensor:
-        """IQ_rc of the scene made of `chunks` = [(ix0, iy0, cnx, cny), ...]."""
+                       accumulate: bool = False, speckle=None,
+                       f_s: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """IQ_rc of the scene made of `chunks` = [(ix0, iy0, cnx, cny), ...];
+        with `speckle` the intra-facet speckle sum, facet ids and f_s (float32
+        device [ny * nx] or None) taken by grid index."""
         np_ = self.n_pulses - p0 if np_ is None else np_
         shape = (self.n_channels, np_, self.n_samples)
         if out is None:
@@ -177,16 +180,26 @@ class Simulator:
             raise ValueError(f"out must be a contiguous complex64 tensor of shape {shape}")
         s, keep = self._sea_struct(sea)
         ca, nc = self._chunk_array(chunks)
-        N.check(self.lib.sim_stream_forward(self.handle, ctypes.byref(s), int(seed), ca, nc,
-                                            float(block_edge), p0, np_,
-                                            ctypes.c_void_p(out.data_ptr()), int(accumulate),
-                                            _stream()), "sim_stream_forward")
+        if speckle is None:
+            N.check(self.lib.sim_stream_forward(self.handle, ctypes.byref(s), int(seed), ca, nc,
+                                                float(block_edge), p0, np_,
+                                                ctypes.c_void_p(out.data_ptr()),
+                                                int(accumulate), _stream()),
+                    "sim_stream_forward")
+        else:
+            sp, f_keep = self._speckle_struct(speckle, f_s, int(sea.nx) * int(sea.ny))
+            N.check(self.lib.sim_stream_forward_speckle(
+                self.handle, ctypes.byref(s), int(seed), ca, nc, float(block_edge),
+                ctypes.byref(sp), p0, np_, ctypes.c_void_p(out.data_ptr()), int(accumulate),
+                _stream()), "sim_stream_forward_speckle")
         return out
 
     def stream_backward(self, sea, seed: int, chunks, g_rc: torch.Tensor,
                         block_edge: float = 8.0, p0: int = 0,
-                        np_: Optional[int] = None) -> Dict[str, torch.Tensor]:
-        """dL/dV of every facet of the streamed scene, chunk after chunk."""
+                        np_: Optional[int] = None, speckle=None,
+                        f_s: Optional[torch.Tensor] = None) -> Dict[str, torch.Tensor]:
+        """dL/dV of every facet of the streamed scene, chunk after chunk
+        (speckle and f_s as in stream_forward)."""
         np_ = self.n_pulses - p0 if np_ is None else np_
         shape = (self.n_channels, np_, self.n_samples)
         if g_rc.shape != shape or g_rc.dtype != torch.complex64:
@@ -197,12 +210,18 @@ class Simulator:
                for k in ("vx", "vy", "vz")}
         s, keep = self._sea_struct(sea)
         ca, nc = self._chunk_array(chunks)
-        N.check(self.lib.sim_stream_backward(self.handle, ctypes.byref(s), int(seed), ca, nc,
-                                             float(block_edge), p0, np_,
-                                             ctypes.c_void_p(g_rc.data_ptr()),
-                                             *[ctypes.c_void_p(out[k].data_ptr())
-                                               for k in ("vx", "vy", "vz")], _stream()),
-                "sim_stream_backward")
+        outs = [ctypes.c_void_p(out[k].data_ptr()) for k in ("vx", "vy", "vz")]
+        if speckle is None:
+            N.check(self.lib.sim_stream_backward(self.handle, ctypes.byref(s), int(seed), ca, nc,
+                                                 float(block_edge), p0, np_,
+                                                 ctypes.c_void_p(g_rc.data_ptr()), *outs,
+                                                 _stream()), "sim_stream_backward")
+        else:
+            sp, f_keep = self._speckle_struct(speckle, f_s, int(sea.nx) * int(sea.ny))
+            N.check(self.lib.sim_stream_backward_speckle(
+                self.handle, ctypes.byref(s), int(seed), ca, nc, float(block_edge),
+                ctypes.byref(sp), p0, np_, ctypes.c_void_p(g_rc.data_ptr()), *outs, _stream()),
+                "sim_stream_backward_speckle")
         return out
 
     # -- the facet sum and its adjoint -----------------------------------------

@@ -169,6 +169,30 @@ def test_stream_entry_points_validate(native):
                                     ctypes.c_void_p(16), 0, None) == native.SIM_EINVAL
         assert L.sim_stream_backward(h, ctypes.byref(sea), 1, ok, 0, 8.0, 0, 8, None, None,
                                      None, None, None) == native.SIM_EINVAL
+        # speckle variants: NULL speckle, bad tau_s or first_index, then the
+        # stream checks as above
+        assert L.sim_stream_forward_speckle(h, ctypes.byref(sea), 1, ok, 1, 8.0, None, 0, 8,
+                                            ctypes.c_void_p(16), 0, None) == native.SIM_EINVAL
+        assert "speckle is NULL" in L.sim_last_error().decode()
+        assert L.sim_stream_backward_speckle(h, ctypes.byref(sea), 1, ok, 1, 8.0, None, 0, 8,
+                                             ctypes.c_void_p(16), None, None, None,
+                                             None) == native.SIM_EINVAL
+        for sp, msg in ((native.SimSpeckle(0.0, 1, 0, None), "tau_s"),
+                        (native.SimSpeckle(float("nan"), 1, 0, None), "tau_s"),
+                        (native.SimSpeckle(0.02, 1, -1, None), "first_index")):
+            assert L.sim_stream_forward_speckle(h, ctypes.byref(sea), 1, ok, 1, 8.0,
+                                                ctypes.byref(sp), 0, 8, ctypes.c_void_p(16), 0,
+                                                None) == native.SIM_EINVAL
+            assert msg in L.sim_last_error().decode()
+            assert L.sim_stream_backward_speckle(h, ctypes.byref(sea), 1, ok, 1, 8.0,
+                                                 ctypes.byref(sp), 0, 8, ctypes.c_void_p(16),
+                                                 None, None, None, None) == native.SIM_EINVAL
+        sp = native.SimSpeckle(0.02, 1, 0, None)
+        arr = (ctypes.c_int * 4)(90, 0, 20, 10)
+        assert L.sim_stream_forward_speckle(h, ctypes.byref(sea), 1, arr, 1, 8.0,
+                                            ctypes.byref(sp), 0, 8, ctypes.c_void_p(16), 0,
+                                            None) == native.SIM_EINVAL
+        assert "chunk" in L.sim_last_error().decode()
     finally:
         L.sim_destroy(h)
 
