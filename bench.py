@@ -47,6 +47,13 @@ if ROOT not in sys.path:
 # overhead, not counted.
 W_ALG_SLOTS = 116.0 + 7 * 4.0
 W_ALG_SLOTS_EL_CONST = 104.0 + 5 * 4.0
+# With u-v gridded patterns (--patterns) the four scaled direction cosines
+# become four cell coordinates (16 operations, no sines) and the sinc product
+# becomes two bilinear lookups of 17 operations each (2 floors, 2 fractions,
+# 4 bounds tests, index, 64-bit address, 3 lerps, select; one 16-byte load)
+# plus the field product, spreading and amplitude (4): 144 FP32 operations and
+# 2 transcendentals (sin, cos of the phase).
+W_ALG_SLOTS_GRID = 144.0 + 2 * 4.0
 # With the intra-facet speckle of eq. 7 (--speckle), per contribution: one
 # Philox2x32-10 evaluation (10 rounds of one 32 x 32 -> 64-bit product, which
 # gfx950 issues at about half the FMA rate (measured), and two XORs), the two
@@ -84,6 +91,8 @@ def main():
                     help="steer the transmit antenna in azimuth at this rate (deg/s)")
     ap.add_argument("--rx-exact", action="store_true",
                     help="receiver at each facet's own echo time (eq. 3's r_r(t_r))")
+    ap.add_argument("--patterns", action="store_true",
+                    help="u-v gridded antenna patterns (129 x 65 nodes per antenna)")
     ap.add_argument("--speckle", action="store_true",
                     help="intra-facet speckle (eq. 7, 10): tau_s 20 ms, f_s +-5.7 Hz per facet")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -113,11 +122,13 @@ def main():
     import workloads as W
 
     wl = W.workload(args.workload)
-    if args.rx_exact or args.tops:
+    if args.rx_exact or args.tops or args.patterns:
         from dataclasses import replace as _replace
         g2 = _replace(wl.geometry, rx_exact=args.rx_exact)
         if args.tops:
             g2 = W.tops_geometry(g2, args.tops)
+        if args.patterns:
+            g2 = W.gridded_geometry(g2, seed=wl.seed)
         wl = _replace(wl, geometry=g2)
     geom, sea = wl.geometry, wl.sea
     torch.cuda.set_device(0)
@@ -272,7 +283,11 @@ def main():
         del f0
     else:
         el_const = plan.el_const
-    w_alg = W_ALG_SLOTS_EL_CONST if el_const else W_ALG_SLOTS
+    if args.patterns:
+        el_const = False          # gridded patterns are evaluated per facet
+        w_alg = W_ALG_SLOTS_GRID
+    else:
+        w_alg = W_ALG_SLOTS_EL_CONST if el_const else W_ALG_SLOTS
     if args.speckle:
         w_alg += W_SPK_SLOTS
     achieved = w_alg * contrib / (kern_ms * 1e-3) / 1e12
@@ -284,7 +299,7 @@ def main():
             tr = json.load(fh)
         if (tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == wl.name
                 and bool(tr.get("speckle", False)) == args.speckle and not args.rx_exact
-                and not args.tops):
+                and not args.tops and not args.patterns):
             traffic = tr.get("bytes_per_launch")
             valu = tr.get("valu_insts_per_launch")
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
@@ -372,7 +387,8 @@ def main():
                    "speckle": ({"tau_s": W.SPECKLE_TAU_S, "f_s_hz": f"+-{W.SPECKLE_FD_HZ}"}
                                if args.speckle else None),
                    "rx_at_facet_echo_time": args.rx_exact,
-                   "tx_steer_deg_s": args.tops or None},
+                   "tx_steer_deg_s": args.tops or None,
+                   "antenna_patterns": "u-v grids 129x65" if args.patterns else "sinc"},
         "fwd_adj": fwd_adj,
         "rel_l2_vs_fp64": rel,
         "roofline": roofline,

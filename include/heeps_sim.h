@@ -91,6 +91,20 @@ typedef struct {
      * antenna at the pulse time, a receive antenna at t_p + tau_ref.  0 =
      * fixed frame. */
     double steer_rate;
+    /* u-v gridded field pattern (Sec. IV.B: patterns, whatever their source,
+     * become u-v grids in GPU memory), or NULL for the sinc pattern above.
+     * Host float32 [pattern_nv][pattern_nu] (u fastest), the real one-way
+     * field gain at direction cosines u = u0 + i du on the azimuth axis and
+     * v = v0 + j dv on the elevation axis (the turned axes when steered);
+     * bilinear between nodes, 0 outside [u0, u0 + (nu-1) du) x
+     * [v0, v0 + (nv-1) dv) and behind the antenna.  sim_create copies it
+     * (the caller's array may be freed afterwards).  nu, nv >= 2,
+     * (nu-1)(nv-1) <= 2^24, du, dv > 0, all values finite, else SIM_EINVAL.
+     * A handle with any gridded antenna evaluates every pattern per facet
+     * (no elevation factor at block centres, whatever sim_plan_mode says). */
+    const float *pattern;
+    int pattern_nu, pattern_nv;
+    double pattern_u0, pattern_du, pattern_v0, pattern_dv;
 } sim_antenna;
 
 /* Channel: transmit antenna, receive antenna and the receive phase-centre

@@ -38,6 +38,10 @@
  *                                      equation, static-receiver case, lone
  *                                      facet phase/delay shift, finite
  *                                      differences of the implicit gradient)
+ *   grid_field (u-v gridded patterns)  pinned (node values, exact on bilinear
+ *                                      functions, second-order convergence to
+ *                                      the sampled analytic pattern, zero
+ *                                      outside, finite differences)
  *   og_speckle_anchors, og_speckle_groups
  *                                      pinned (exact covariance of the
  *                                      construction = the AR(1) law of eq. 10;
@@ -78,6 +82,11 @@ typedef struct {
     double ch_off[OG_MAXC][3];
     int rx_exact;   /* 1: receiver at each facet's own echo time (see facet_rx) */
     double ant_steer[OG_MAXA];   /* steering rate about the elevation axis (rad/s) */
+    /* u-v gridded field patterns (see gain): NULL = the analytic sinc pattern;
+     * else values [nv][nu] (u fastest) at u = u0 + i du, v = v0 + j dv */
+    const double *ant_grid[OG_MAXA];
+    int ant_gnu[OG_MAXA], ant_gnv[OG_MAXA];
+    double ant_gu0[OG_MAXA], ant_gdu[OG_MAXA], ant_gv0[OG_MAXA], ant_gdv[OG_MAXA];
 } og_config;
 
 static const double OG_PI = 3.14159265358979323846;
@@ -186,12 +195,44 @@ void og_antenna_frame(const og_config *g, int ant, double *b, double *az, double
 typedef struct {
     double b[3], az[3], el[3];
     double ka, ke;            /* kappa / beta_az, kappa / beta_el */
+    const double *grid;       /* gridded pattern or NULL (og_config.ant_grid) */
+    int gnu, gnv;
+    double gu0, gdu, gv0, gdv;
 } og_ant;
 
 static void make_ant(const og_config *g, int ant, double kap, og_ant *a) {
     og_antenna_frame(g, ant, a->b, a->az, a->el);
     a->ka = kap / g->ant_beta_az[ant];
     a->ke = kap / g->ant_beta_el[ant];
+    a->grid = g->ant_grid[ant];
+    a->gnu = g->ant_gnu[ant];
+    a->gnv = g->ant_gnv[ant];
+    a->gu0 = g->ant_gu0[ant];
+    a->gdu = g->ant_gdu[ant];
+    a->gv0 = g->ant_gv0[ant];
+    a->gdv = g->ant_gdv[ant];
+}
+
+/*
+ * Gridded field pattern (Sec. IV.B: patterns, whatever their source, are
+ * converted into u-v grids held in GPU memory).  Reading: a real one-way field
+ * gain tabulated over the direction cosines u (azimuth axis) and v (elevation
+ * axis), interpolated bilinearly; the table covers the half-open cells
+ * [u0, u0 + (nu-1) du) x [v0, v0 + (nv-1) dv) and the field is 0 outside.
+ * dFu, dFv receive dF/du, dF/dv (piecewise constant along each axis).
+ */
+static double grid_field(const og_ant *a, double u, double v, double *dFu, double *dFv) {
+    double x = (u - a->gu0) / a->gdu, y = (v - a->gv0) / a->gdv;
+    *dFu = *dFv = 0.0;
+    if (!(x >= 0.0 && x < a->gnu - 1 && y >= 0.0 && y < a->gnv - 1)) return 0.0;
+    int i = (int)floor(x), j = (int)floor(y);
+    double fx = x - i, fy = y - j;
+    const double *r0 = a->grid + (size_t)j * a->gnu + i, *r1 = r0 + a->gnu;
+    double f00 = r0[0], f10 = r0[1], f01 = r1[0], f11 = r1[1];
+    *dFu = ((1.0 - fy) * (f10 - f00) + fy * (f11 - f01)) / a->gdu;
+    *dFv = ((1.0 - fx) * (f01 - f00) + fx * (f11 - f10)) / a->gdv;
+    return (1.0 - fx) * (1.0 - fy) * f00 + fx * (1.0 - fy) * f10 + (1.0 - fx) * fy * f01 +
+           fx * fy * f11;
 }
 
 /*
@@ -200,7 +241,8 @@ static void make_ant(const og_config *g, int ant, double kap, og_ant *a) {
  * the one-way power pattern with those 3-dB widths, so the field is
  * F = sinc(kappa*u/beta_az) * sinc(kappa*v/beta_el), u, v the direction
  * cosines of the unit vector antenna->facet on the az / el axes; F = 0 behind
- * the antenna.  grad (optional) receives dF/dX.
+ * the antenna.  grad (optional) receives dF/dX.  An antenna with a gridded
+ * pattern takes F from its grid instead (grid_field), same back plane.
  */
 static double gain(const og_ant *a, const double *pa, const double *x, double *grad) {
     double d[3] = {x[0] - pa[0], x[1] - pa[1], x[2] - pa[2]};
@@ -211,6 +253,14 @@ static double gain(const og_ant *a, const double *pa, const double *x, double *g
         return 0.0;
     }
     double u = dot3(rh, a->az), v = dot3(rh, a->el);
+    if (a->grid) {
+        double dFu, dFv;
+        double F = grid_field(a, u, v, &dFu, &dFv);
+        if (grad)
+            for (int k = 0; k < 3; ++k)
+                grad[k] = dFu * (a->az[k] - u * rh[k]) / r + dFv * (a->el[k] - v * rh[k]) / r;
+        return F;
+    }
     double su = sinc(a->ka * u), sv = sinc(a->ke * v);
     if (grad) {
         double dsu = a->ka * dsinc(a->ka * u), dsv = a->ke * dsinc(a->ke * v);

@@ -41,6 +41,10 @@ class OgConfig(ctypes.Structure):
         ("ch_off", _d3 * MAXC),
         ("rx_exact", ctypes.c_int),
         ("ant_steer", ctypes.c_double * MAXA),
+        ("ant_grid", ctypes.POINTER(ctypes.c_double) * MAXA),
+        ("ant_gnu", ctypes.c_int * MAXA), ("ant_gnv", ctypes.c_int * MAXA),
+        ("ant_gu0", ctypes.c_double * MAXA), ("ant_gdu", ctypes.c_double * MAXA),
+        ("ant_gv0", ctypes.c_double * MAXA), ("ant_gdv", ctypes.c_double * MAXA),
     ]
 
 
@@ -130,6 +134,8 @@ def _dptr(a: np.ndarray):
 def make_config(geom) -> OgConfig:
     """Marshal a workloads.Geometry into the oracle's C struct."""
     c = OgConfig()
+    keep = []
+    c._keep = keep          # gridded pattern tables referenced by the struct
     c.c, c.f0, c.fs, c.prf = geom.c, geom.f0, geom.fs, geom.prf
     c.n_samples, c.n_pulses = geom.n_samples, geom.n_pulses
     c.n_ref = geom.ref_sample
@@ -147,6 +153,15 @@ def make_config(geom) -> OgConfig:
         c.ant_beta_az[i] = a.beta_az
         c.ant_beta_el[i] = a.beta_el
         c.ant_steer[i] = getattr(a, "steer_rate", 0.0)
+        pat = getattr(a, "pattern", None)
+        if pat is not None:
+            vals = np.ascontiguousarray(np.asarray(pat.values).astype(np.float64))
+            assert vals.ndim == 2 and vals.shape[0] >= 2 and vals.shape[1] >= 2
+            keep.append(vals)
+            c.ant_grid[i] = _dptr(vals)
+            c.ant_gnv[i], c.ant_gnu[i] = vals.shape
+            c.ant_gu0[i], c.ant_gdu[i] = pat.u0, pat.du
+            c.ant_gv0[i], c.ant_gdv[i] = pat.v0, pat.dv
     c.n_ch = len(geom.channels)
     for i, ch in enumerate(geom.channels):
         c.ch_tx[i], c.ch_rx[i] = ch.tx, ch.rx

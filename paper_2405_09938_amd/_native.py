@@ -28,7 +28,11 @@ class SimTraj(ctypes.Structure):
 
 class SimAntenna(ctypes.Structure):
     _fields_ = [("platform", ctypes.c_int), ("beta_az", ctypes.c_double),
-                ("beta_el", ctypes.c_double), ("steer_rate", ctypes.c_double)]
+                ("beta_el", ctypes.c_double), ("steer_rate", ctypes.c_double),
+                ("pattern", ctypes.POINTER(ctypes.c_float)),
+                ("pattern_nu", ctypes.c_int), ("pattern_nv", ctypes.c_int),
+                ("pattern_u0", ctypes.c_double), ("pattern_du", ctypes.c_double),
+                ("pattern_v0", ctypes.c_double), ("pattern_dv", ctypes.c_double)]
 
 
 class SimChannel(ctypes.Structure):

@@ -192,6 +192,29 @@ void antenna_frame(const sim_handle *h, int a, hs::AntArgs &ac) {
         ac.az32[k] = (float)ac.az[k];
     }
     ac.pad = 0.0f;
+    const sim_antenna &an = h->ants[a];
+    ac.grid = nullptr;   // device cells, set when the tables are uploaded
+    ac.gidu = ac.gidv = 0.0;
+    ac.gu0 = ac.gv0 = ac.gnu1 = ac.gnv1 = 0.0f;
+    ac.gstride = 0;
+    ac.pad2 = 0;
+    if (an.pattern) {
+        // direction cosines in cell units: the scaled axes become axis / du
+        ac.gidu = 1.0 / an.pattern_du;
+        ac.gidv = 1.0 / an.pattern_dv;
+        ac.ka = 2.0 * ac.gidu;
+        ac.ke = 2.0 * ac.gidv;
+        for (int k = 0; k < 3; ++k) {
+            ac.kaz[k] = (float)(ac.az[k] * ac.gidu);
+            ac.kel[k] = (float)(ac.el[k] * ac.gidv);
+            ac.kb[k] = (float)(ac.b[k] * ac.gidu);
+        }
+        ac.gu0 = (float)(an.pattern_u0 * ac.gidu);
+        ac.gv0 = (float)(an.pattern_v0 * ac.gidv);
+        ac.gnu1 = (float)(an.pattern_nu - 1);
+        ac.gnv1 = (float)(an.pattern_nv - 1);
+        ac.gstride = an.pattern_nu - 1;
+    }
 }
 
 template <typename T>
@@ -364,6 +387,8 @@ void release_handle(sim_handle *h) {
     if (h->chirp_spec_d) (void)hipFree(h->chirp_spec_d);
     if (h->twiddle_d) (void)hipFree(h->twiddle_d);
     if (h->gen_tab_d) (void)hipFree(h->gen_tab_d);
+    for (float4 *p : h->pat_d)
+        if (p) (void)hipFree(p);
     for (auto &b : h->scratch_pool) (void)hipFree(b.first);
     for (auto &b : h->plan_pool) (void)hipFree(b.p);   // hipFree waits for the device
     h->plan_pool.clear();
@@ -394,6 +419,24 @@ int ensure_device(sim_handle *h) {
         if (e == hipSuccess)
             e = hipMemcpy(h->twiddle_d, h->tw_h.data(), sizeof(float) * h->tw_h.size(),
                           hipMemcpyHostToDevice);
+    }
+    // gridded patterns as cells of four corners (one 16-byte load per lookup)
+    for (size_t a = 0; a < h->ants.size() && e == hipSuccess; ++a) {
+        const sim_antenna &an = h->ants[a];
+        if (!an.pattern) continue;
+        const int nu = an.pattern_nu, nv = an.pattern_nv;
+        std::vector<float4> cells((size_t)(nu - 1) * (size_t)(nv - 1));
+        const float *g = h->pat_h[a].data();
+        for (int j = 0; j + 1 < nv; ++j)
+            for (int i = 0; i + 1 < nu; ++i) {
+                const float *r0 = g + (size_t)j * nu + i, *r1 = r0 + nu;
+                cells[(size_t)j * (nu - 1) + i] = make_float4(r0[0], r0[1], r1[0], r1[1]);
+            }
+        e = dalloc(&h->pat_d[a], cells.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(h->pat_d[a], cells.data(), sizeof(float4) * cells.size(),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess) h->antc[a].grid = h->pat_d[a];
     }
     if (e != hipSuccess) {
         HS_FAIL(e == hipErrorOutOfMemory ? SIM_ENOMEM : SIM_EHIP,
@@ -459,6 +502,19 @@ int sim_create(const sim_config *cfg, sim_handle **out) {
         if (!(r > 0)) HS_FAIL(SIM_EINVAL, "an antenna's platform sits on the scene origin");
         if (std::fabs(p[0]) / r > 1.0 - 1e-9)
             HS_FAIL(SIM_EINVAL, "boresight parallel to the along-track axis");
+        if (a.pattern) {
+            if (a.pattern_nu < 2 || a.pattern_nv < 2 ||
+                (long long)(a.pattern_nu - 1) * (a.pattern_nv - 1) > (1LL << 24))
+                HS_FAIL(SIM_EINVAL, "pattern grid needs 2..(2^24 cells) nodes per axis");
+            if (!(a.pattern_du > 0) || !(a.pattern_dv > 0) || !std::isfinite(a.pattern_du) ||
+                !std::isfinite(a.pattern_dv) || !std::isfinite(a.pattern_u0) ||
+                !std::isfinite(a.pattern_v0))
+                HS_FAIL(SIM_EINVAL, "pattern grid origin and steps must be finite, steps > 0");
+            const long long nn = (long long)a.pattern_nu * a.pattern_nv;
+            for (long long k = 0; k < nn; ++k)
+                if (!std::isfinite(a.pattern[k]))
+                    HS_FAIL(SIM_EINVAL, "pattern values must be finite");
+        }
     }
     for (int i = 0; i < cfg->n_channels; ++i) {
         const sim_channel &ch = cfg->channels[i];
@@ -495,10 +551,22 @@ int sim_create(const sim_config *cfg, sim_handle **out) {
         }
         if (an.steer_rate != 0.0) h->steer = 1;
     }
+    h->grid = 0;
+    h->pat_h.resize(h->ants.size());
+    h->pat_d.assign(h->ants.size(), nullptr);
+    for (size_t a = 0; a < h->ants.size(); ++a) {
+        sim_antenna &an = h->ants[a];
+        if (an.pattern) {
+            h->pat_h[a].assign(an.pattern,
+                               an.pattern + (size_t)an.pattern_nu * (size_t)an.pattern_nv);
+            an.pattern = h->pat_h[a].data();   // the caller's array is not kept
+            h->grid = 1;
+        }
+    }
     h->antc.resize(h->ants.size());
     for (size_t a = 0; a < h->ants.size(); ++a) {
         antenna_frame(h, (int)a, h->antc[a]);
-        if (h->antc[a].ka > 500.0 || h->antc[a].ke > 500.0) {
+        if (!h->ants[a].pattern && (h->antc[a].ka > 500.0 || h->antc[a].ke > 500.0)) {
             delete h;
             HS_FAIL(SIM_EUNSUPPORTED, "antenna 3-dB width below kappa/500 rad is not supported");
         }
@@ -1065,8 +1133,10 @@ static int forward_common(sim_handle *h, sim_plan *P, const sim_facets *f,
     a.halo = P->halo;
     a.rx_exact = h->rx_exact;
     a.steer = h->steer;
+    a.grid = h->grid;
     a.inv_c = 1.0 / h->c;
-    HS_HIP(hs::launch_forward(a, h->C, P->win, P->el_const, sp != nullptr, s), "forward");
+    HS_HIP(hs::launch_forward(a, h->C, P->win, P->el_const && !h->grid, sp != nullptr, s),
+           "forward");
     return SIM_OK;
 }
 
@@ -1141,7 +1211,8 @@ static int backward_common(sim_handle *h, sim_plan *P, const sim_facets *f,
     a.rx_exact = h->rx_exact;
     a.steer = h->steer;
     a.inv_c = 1.0 / h->c;
-    HS_HIP(hs::launch_adjoint(a, P->el_const, sp != nullptr, s), "adjoint");
+    a.grid = h->grid;
+    HS_HIP(hs::launch_adjoint(a, P->el_const && !h->grid, sp != nullptr, s), "adjoint");
     return SIM_OK;
 }
 

@@ -56,7 +56,10 @@ constexpr int kNRef = R_ST0<SPK> + (STR ? 4 : 0);
 // Gradient of one antenna's field pattern at the block centre (FP32 from the
 // FP64 geometry): dF/dX = ka sinc'(ka u) sinc(ke v) (az - u d)/R
 //                        + ke sinc(ka u) sinc'(ke v) (el - v d)/R.
-template <bool STR>
+// GRD: the field of an antenna with a u-v grid from that grid (the others keep
+// the sinc); dF/du, dF/dv are its cell slopes (bilinear: piecewise linear
+// along each axis).
+template <bool STR, bool GRD>
 __device__ __forceinline__ float ant_grad(const AntArgs &a, double d0, double d1, double d2,
                                           double ir, float *gr, double cs, double sn) {
     const double u0 = d0 * ir, u1 = d1 * ir, u2 = d2 * ir;
@@ -68,6 +71,27 @@ __device__ __forceinline__ float ant_grad(const AntArgs &a, double d0, double d1
     }
     const double u = u0 * az[0] + u1 * az[1] + u2 * az[2];
     const double v = u0 * a.el[0] + u1 * a.el[1] + u2 * a.el[2];
+    if (GRD && a.grid) {   // uniform: the antenna is the workgroup's channel's
+        const float x = (float)(u * a.gidu) - a.gu0, y = (float)(v * a.gidv) - a.gv0;
+        const bool in = x >= 0.0f && x < a.gnu1 && y >= 0.0f && y < a.gnv1;
+        const float fx = floorf(x), fy = floorf(y);
+        const int idx = in ? (int)fy * a.gstride + (int)fx : 0;
+        const float4 c = a.grid[idx];
+        const float ax = x - fx, ay = y - fy;
+        const float d10 = c.y - c.x, d32 = c.w - c.z;
+        const float lo = fmaf(ax, d10, c.x), hi = fmaf(ax, d32, c.z);
+        const float fu = in ? fmaf(ay, d32 - d10, d10) * (float)a.gidu : 0.0f;
+        const float fv = in ? (hi - lo) * (float)a.gidv : 0.0f;
+        const float irf = (float)ir;
+        const double uu[3] = {u0, u1, u2};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float gu = (float)(az[k] - u * uu[k]) * irf;
+            const float gv = (float)(a.el[k] - v * uu[k]) * irf;
+            gr[k] = fmaf(fu, gu, fv * gv);
+        }
+        return in ? fmaf(ay, hi - lo, lo) : 0.0f;
+    }
     const float xa = (float)(a.ka * u), xe = (float)(a.ke * v);
     const float su = sinc_f(xa), sv = sinc_f(xe);
     const float dsu = (float)a.ka * dsinc_f(xa), dsv = (float)a.ke * dsinc_f(xe);
@@ -84,7 +108,7 @@ __device__ __forceinline__ float ant_grad(const AntArgs &a, double d0, double d1
 
 // grad T = grad(F_tx F_rx S) at the point (X, Y, Z), S = R_t,mid R_r,mid /
 // (R_t R_r) the spreading (without the mask).
-template <bool STR>
+template <bool STR, bool GRD>
 __device__ __forceinline__ void grad_t(const AntArgs &ta, const AntArgs &ra, double rtrr_mid,
                                        double X, double Y, double Z, const double *ptx,
                                        const double *prx, float *out, double cst, double snt,
@@ -94,8 +118,8 @@ __device__ __forceinline__ void grad_t(const AntArgs &ta, const AntArgs &ra, dou
     const double irt = 1.0 / sqrt(dt0 * dt0 + dt1 * dt1 + dt2 * dt2);
     const double irr = 1.0 / sqrt(dr0 * dr0 + dr1 * dr1 + dr2 * dr2);
     float gft[3], gfr[3];
-    const float ft = ant_grad<STR>(ta, dt0, dt1, dt2, irt, gft, cst, snt);
-    const float fr = ant_grad<STR>(ra, dr0, dr1, dr2, irr, gfr, csr, snr);
+    const float ft = ant_grad<STR, GRD>(ta, dt0, dt1, dt2, irt, gft, cst, snt);
+    const float fr = ant_grad<STR, GRD>(ra, dr0, dr1, dr2, irr, gfr, csr, snr);
     const double sb = rtrr_mid * irt * irr;
     const double d[3][2] = {{dt0, dr0}, {dt1, dr1}, {dt2, dr2}};
 #pragma unroll
@@ -111,7 +135,7 @@ __device__ __forceinline__ void grad_t(const AntArgs &ta, const AntArgs &ra, dou
 // x = z + K_k D_g with (y_g, D_g) from the preparation pass.
 // STR: antenna frames turn with time (steering): the per-pulse angles are
 // staged with the references and the facet-part constants rebuilt per pulse.
-template <bool ELC, bool SPK, bool STR>
+template <bool ELC, bool SPK, bool STR, bool GRD>
 __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
     constexpr int kNR = kNRef<SPK, STR>;
     constexpr int kSt = R_ST0<SPK>;
@@ -190,14 +214,14 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                     snr = P.snr;
                 }
                 Refs r;
-                block_refs<ELC, STR>(xb, yb, P.ptx, prb, P.rref, ta, ra, chn.rtrr_mid, A.f0_c,
+                block_refs<ELC, STR, GRD>(xb, yb, P.ptx, prb, P.rref, ta, ra, chn.rtrr_mid, A.f0_c,
                                 A.fs_c, A.n_ref, live, r, qr, cst, snt, csr, snr);
                 // grad T at the centre
                 const double dt0 = xb - P.ptx[0], dt1 = yb - P.ptx[1], dt2 = -P.ptx[2];
                 const double dr0 = xb - prb[0], dr1 = yb - prb[1], dr2 = -prb[2];
                 float gft[3], gfr[3];
-                const float ft = ant_grad<STR>(ta, dt0, dt1, dt2, (double)r.irt, gft, cst, snt);
-                const float fr = ant_grad<STR>(ra, dr0, dr1, dr2, (double)r.irr, gfr, csr, snr);
+                const float ft = ant_grad<STR, GRD>(ta, dt0, dt1, dt2, (double)r.irt, gft, cst, snt);
+                const float fr = ant_grad<STR, GRD>(ra, dr0, dr1, dr2, (double)r.irr, gfr, csr, snr);
                 float *o = rf + lane * kNR;
                 // spreading at the centre (r.sb also carries the sinc normalisation)
                 const float sbt = (r.mask != 0.0f || r.graze)
@@ -221,9 +245,9 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                         const double ox = j == 0 ? h : 0.0, oy = j == 1 ? h : 0.0,
                                      oz = j == 2 ? h : 0.0;
                         float gp[3], gm[3];
-                        grad_t<STR>(ta, ra, chn.rtrr_mid, xb + ox, yb + oy, oz, P.ptx, prb, gp,
+                        grad_t<STR, GRD>(ta, ra, chn.rtrr_mid, xb + ox, yb + oy, oz, P.ptx, prb, gp,
                                     cst, snt, csr, snr);
-                        grad_t<STR>(ta, ra, chn.rtrr_mid, xb - ox, yb - oy, -oz, P.ptx, prb, gm,
+                        grad_t<STR, GRD>(ta, ra, chn.rtrr_mid, xb - ox, yb - oy, -oz, P.ptx, prb, gm,
                                     cst, snt, csr, snr);
                         o[R_J0 + j] = s2h * (gp[0] - gm[0]);
                         o[R_J0 + 3 + j] = s2h * (gp[1] - gm[1]);
@@ -312,7 +336,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                     steer_axes(ta, ra, rot.x, rot.y, rot.z, rot.w, kq);
                 }
                 Geo g;
-                facet_geo<ELC, SPK, STR>(r, kq, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz,
+                facet_geo<ELC, SPK, STR, GRD>(r, kq, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz,
                                          r.graze != 0, o[R_LHI], o[R_LLO], o[R_FSQ], dop, g, &ta,
                                          &ra, rot);
                 float tap[8], dtap[8];
@@ -421,8 +445,17 @@ hipError_t launch_adjoint(const AdjArgs &a, bool el_const, bool speckle, hipStre
     const unsigned long long wgs = ((unsigned long long)a.n_blocks + 7) / 8 * 8;
     if (wgs > 0xffffffffULL) return hipErrorInvalidConfiguration;
     const dim3 grid((unsigned)wgs);
-#define HS_ADJ(E, S, T) hipLaunchKernelGGL((k_adjoint<E, S, T>), grid, dim3(64), 0, s, a)
-    if (a.steer) {
+#define HS_ADJ(E, S, T) hipLaunchKernelGGL((k_adjoint<E, S, T, false>), grid, dim3(64), 0, s, a)
+#define HS_ADJG(S, T) hipLaunchKernelGGL((k_adjoint<false, S, T, true>), grid, dim3(64), 0, s, a)
+    if (a.grid) {   // gridded patterns: always per facet
+        if (a.steer) {
+            if (speckle) HS_ADJG(true, true);
+            else HS_ADJG(false, true);
+        } else {
+            if (speckle) HS_ADJG(true, false);
+            else HS_ADJG(false, false);
+        }
+    } else if (a.steer) {
         if (speckle) {
             if (el_const) HS_ADJ(true, true, true);
             else HS_ADJ(false, true, true);
@@ -440,6 +473,7 @@ hipError_t launch_adjoint(const AdjArgs &a, bool el_const, bool speckle, hipStre
         }
     }
 #undef HS_ADJ
+#undef HS_ADJG
     return hipGetLastError();
 }
 

@@ -40,6 +40,33 @@ __device__ __forceinline__ float dsinc_f(float x) {
     return (fabsf(x) < 1e-6f) ? 0.0f : r;
 }
 
+// Gridded field pattern at cell coordinates (x, y) = ((u - u0)/du, (v - v0)/dv):
+// bilinear in the cell's four corners (one 16-byte load), 0 outside the
+// half-open range [0, nu-1) x [0, nv-1) (NaN included: the index is then 0).
+__device__ __forceinline__ float grid_gain(const AntArgs &a, float x, float y) {
+    const bool in = x >= 0.0f && x < a.gnu1 && y >= 0.0f && y < a.gnv1;
+    const float fx = floorf(x), fy = floorf(y);
+    const int idx = in ? (int)fy * a.gstride + (int)fx : 0;
+    const float4 c = a.grid[idx];
+    const float ax = x - fx, ay = y - fy;
+    const float lo = fmaf(ax, c.y - c.x, c.x);
+    const float hi = fmaf(ax, c.w - c.z, c.z);
+    return in ? fmaf(ay, hi - lo, lo) : 0.0f;
+}
+
+// One antenna's field for the GRD kernels, from the projections pu, pv of the
+// facet direction (times R) on its scaled azimuth and elevation axes and the
+// first-order 1/R: the grid lookup for an antenna with a table (axes scaled
+// to cell units), else the sinc product (axes scaled by kappa/(2 beta)),
+// normalised here since GRD spreading terms carry no (2 pi)^k.  The branch is
+// uniform (the antenna is the workgroup's channel's).
+__device__ __forceinline__ float ant_field(const AntArgs &a, float pu, float pv, float irf) {
+    if (a.grid) return grid_gain(a, fmaf(pu, irf, -a.gu0), fmaf(pv, irf, -a.gv0));
+    const float y1 = fmaf(fabsf(pu), irf, 1e-9f), y2 = fmaf(fabsf(pv), irf, 1e-9f);
+    return (__builtin_amdgcn_sinf(y1) * __builtin_amdgcn_sinf(y2)) *
+           __builtin_amdgcn_rcpf((float)(kTwoPi * kTwoPi) * (y1 * y2));
+}
+
 // Per-(block, pulse) references of one lane (FP64 -> FP32).
 struct Refs {
     float dtx, dty, dtz;            // unit vector Tx -> block centre
@@ -90,7 +117,9 @@ __device__ __forceinline__ void rx_echo(double xb, double yb, const double *ptx,
 // ELC: the elevation pattern factors of both legs are taken at the block
 // centre and folded into the spreading terms (chosen on the host only where
 // a bound puts the relative error of that below 1e-6 for every facet).
-template <bool ELC, bool STR = false>
+// GRD: gridded patterns (never with ELC); the spreading terms then carry no
+// sinc normalisation and the azimuth/elevation references are in cell units.
+template <bool ELC, bool STR = false, bool GRD = false>
 __device__ __forceinline__ void block_refs(double xb, double yb, const double *ptx,
                                            const double *prx, double rref, const AntArgs &t,
                                            const AntArgs &q, double rtrr_mid, double f0_c,
@@ -160,7 +189,7 @@ __device__ __forceinline__ void block_refs(double xb, double yb, const double *p
     // the spreading terms carry the mask (grazing lanes are masked per facet)
     // and the 1/(2 pi)^k of the merged sinc product (k = number of factors
     // evaluated per facet), with the elevation factors at the centre in ELC
-    double sm = (r.mask != 0.0f || r.graze) ? kInvTwoPi4 * sb : 0.0;
+    double sm = (r.mask != 0.0f || r.graze) ? (GRD ? 1.0 : kInvTwoPi4) * sb : 0.0;
     if constexpr (ELC) {
         const float yt = (float)fabs(0.5 * t.ke * (dt0 * t.el[0] + dt1 * t.el[1] + dt2 * t.el[2]) * irt) + 1e-9f;
         const float yr = (float)fabs(0.5 * q.ke * (dr0 * q.el[0] + dr1 * q.el[1] + dr2 * q.el[2]) * irr) + 1e-9f;
@@ -219,7 +248,10 @@ struct Geo {
 // ROT: the boresights of cc are the fixed-frame ones and the back-plane test
 // (grazing blocks only) turns them by rot = (cos, sin) of the Tx and Rx
 // steering angles, with the antennas' FP32 axes (t, q).
-template <bool ELC, bool DOP = false, bool ROT = false>
+// GRD: field patterns from the antennas' u-v grids (t, q), with the direction
+// cosines in cell units (per-facet, first order in the offset like the sinc
+// arguments).
+template <bool ELC, bool DOP = false, bool ROT = false, bool GRD = false>
 __device__ __forceinline__ void facet_geo(const Refs &r, const FacetConsts &cc, float tf,
                                           float fdx, float fdy, float fz, float fvx, float fvy,
                                           float fvz, bool graze_any, float linv_hi,
@@ -256,22 +288,32 @@ __device__ __forceinline__ void facet_geo(const Refs &r, const FacetConsts &cc, 
     // product normal and never zero.  1/R per leg to first order in the offset.
     const float irtf = fmaf(-at, r.irt2, r.irt);
     const float irrf = fmaf(-ar, r.irr2, r.irr);
-    const float yta = fmaf(fabsf(fmaf(ez, cc.kta[2], fmaf(ey, cc.kta[1], fmaf(ex, cc.kta[0], r.gtaz)))), irtf, 1e-9f);
-    const float yra = fmaf(fabsf(fmaf(ez, cc.kra[2], fmaf(ey, cc.kra[1], fmaf(ex, cc.kra[0], r.graz)))), irrf, 1e-9f);
-    float sp, yp;
-    if constexpr (ELC) {
-        sp = __builtin_amdgcn_sinf(yta) * __builtin_amdgcn_sinf(yra);
-        yp = yta * yra;
-    } else {
-        const float yte = fmaf(fabsf(fmaf(ez, cc.kte[2], fmaf(ey, cc.kte[1], fmaf(ex, cc.kte[0], r.gtel)))), irtf, 1e-9f);
-        const float yre = fmaf(fabsf(fmaf(ez, cc.kre[2], fmaf(ey, cc.kre[1], fmaf(ex, cc.kre[0], r.grel)))), irrf, 1e-9f);
-        sp = (__builtin_amdgcn_sinf(yta) * __builtin_amdgcn_sinf(yte)) *
-             (__builtin_amdgcn_sinf(yra) * __builtin_amdgcn_sinf(yre));
-        yp = (yta * yte) * (yra * yre);
-    }
     // spreading R_mid^2 / (R_t R_r), first order in the offsets
     const float s = fmaf(-ar, r.sbr, fmaf(-at, r.sbt, r.sb));
-    float amp = sp * __builtin_amdgcn_rcpf(yp) * s;
+    float amp;
+    if constexpr (GRD) {
+        static_assert(!ELC, "gridded patterns are evaluated per facet");
+        const float pta = fmaf(ez, cc.kta[2], fmaf(ey, cc.kta[1], fmaf(ex, cc.kta[0], r.gtaz)));
+        const float pte = fmaf(ez, cc.kte[2], fmaf(ey, cc.kte[1], fmaf(ex, cc.kte[0], r.gtel)));
+        const float pra = fmaf(ez, cc.kra[2], fmaf(ey, cc.kra[1], fmaf(ex, cc.kra[0], r.graz)));
+        const float pre = fmaf(ez, cc.kre[2], fmaf(ey, cc.kre[1], fmaf(ex, cc.kre[0], r.grel)));
+        amp = (ant_field(*t, pta, pte, irtf) * ant_field(*q, pra, pre, irrf)) * s;
+    } else {
+        const float yta = fmaf(fabsf(fmaf(ez, cc.kta[2], fmaf(ey, cc.kta[1], fmaf(ex, cc.kta[0], r.gtaz)))), irtf, 1e-9f);
+        const float yra = fmaf(fabsf(fmaf(ez, cc.kra[2], fmaf(ey, cc.kra[1], fmaf(ex, cc.kra[0], r.graz)))), irrf, 1e-9f);
+        float sp, yp;
+        if constexpr (ELC) {
+            sp = __builtin_amdgcn_sinf(yta) * __builtin_amdgcn_sinf(yra);
+            yp = yta * yra;
+        } else {
+            const float yte = fmaf(fabsf(fmaf(ez, cc.kte[2], fmaf(ey, cc.kte[1], fmaf(ex, cc.kte[0], r.gtel)))), irtf, 1e-9f);
+            const float yre = fmaf(fabsf(fmaf(ez, cc.kre[2], fmaf(ey, cc.kre[1], fmaf(ex, cc.kre[0], r.grel)))), irrf, 1e-9f);
+            sp = (__builtin_amdgcn_sinf(yta) * __builtin_amdgcn_sinf(yte)) *
+                 (__builtin_amdgcn_sinf(yra) * __builtin_amdgcn_sinf(yre));
+            yp = (yta * yte) * (yra * yre);
+        }
+        amp = sp * __builtin_amdgcn_rcpf(yp) * s;
+    }
     o.mf = 1.0f;
     if (graze_any && r.graze) {
         float bt[3] = {cc.bt[0], cc.bt[1], cc.bt[2]}, br[3] = {cc.br[0], cc.br[1], cc.br[2]};

@@ -69,6 +69,15 @@ struct AntArgs {
     float kb[3];                // (kappa/beta_az)/2 * boresight, FP32 (steering)
     float az32[3];              // azimuth axis, FP32 (steering)
     float pad;
+    // u-v gridded field pattern (NULL = the analytic sinc pattern).  With a
+    // grid, ka = 2/du and ke = 2/dv, so the facet part's scaled direction
+    // cosines come out in cell units.
+    const float4 *grid;         // [nv-1][nu-1] cells: corners (i,j), (i+1,j), (i,j+1), (i+1,j+1)
+    double gidu, gidv;          // 1/du, 1/dv
+    float gu0, gv0;             // u0/du, v0/dv
+    float gnu1, gnv1;           // nu - 1, nv - 1
+    int gstride;                // nu - 1 (cells per row)
+    int pad2;
 };
 
 struct ChanArgs {
@@ -115,6 +124,7 @@ struct FwdArgs {
     int halo;                   // bins added on each side of the patch span
     int rx_exact;               // receiver at each facet's own echo time
     int steer;                  // some antenna frame turns with time
+    int grid;                   // some antenna has a gridded pattern
     double inv_c;               // 1 / c
     SpkArgs spk;                // speckle variant only
 };
@@ -137,9 +147,13 @@ struct AdjArgs {
     int accumulate;
     int rx_exact;               // receiver at each facet's own echo time
     int steer;                  // some antenna frame turns with time
+    int grid;                   // some antenna has a gridded pattern
     double inv_c;               // 1 / c
     SpkArgs spk;                // speckle variant only
 };
+
+// kernel arguments travel in the 4 KiB kernarg segment
+static_assert(sizeof(FwdArgs) <= 4096 && sizeof(AdjArgs) <= 4096, "kernel arguments too large");
 
 }  // namespace hs
 
@@ -157,6 +171,9 @@ struct sim_handle {
     int C;
     int rx_exact;
     int steer;                  // some antenna has a nonzero steering rate
+    int grid;                   // some antenna has a gridded pattern
+    std::vector<std::vector<float>> pat_h;   // per antenna: host copy of its grid (or empty)
+    std::vector<float4 *> pat_d;             // per antenna: device cells (or NULL)
     // derived on the host in FP64
     double kappa;
     std::vector<hs::AntArgs> antc;

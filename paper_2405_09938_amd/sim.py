@@ -54,9 +54,22 @@ class Simulator:
             self._plats[i].p0 = N._d3(*p.p0)
             self._plats[i].v = N._d3(*p.v)
         self._ants = (N.SimAntenna * len(g.antennas))()
+        pat_keep = []      # gridded patterns (sim_create copies them)
+        self._pat_keep = pat_keep
         for i, a in enumerate(g.antennas):
             self._ants[i] = N.SimAntenna(a.platform, a.beta_az, a.beta_el,
                                          float(getattr(a, "steer_rate", 0.0)))
+            pat = getattr(a, "pattern", None)
+            if pat is not None:
+                vals = np.ascontiguousarray(pat.values, dtype=np.float32)
+                if vals.ndim != 2:
+                    raise ValueError("pattern values must be a 2-D [nv, nu] array")
+                pat_keep.append(vals)
+                ant = self._ants[i]
+                ant.pattern = vals.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+                ant.pattern_nv, ant.pattern_nu = vals.shape
+                ant.pattern_u0, ant.pattern_du = float(pat.u0), float(pat.du)
+                ant.pattern_v0, ant.pattern_dv = float(pat.v0), float(pat.dv)
         self._chans = (N.SimChannel * len(g.channels))()
         for i, ch in enumerate(g.channels):
             self._chans[i] = N.SimChannel(ch.tx, ch.rx, N._d3(*ch.pc_offset))

@@ -84,6 +84,43 @@ def test_create_validates_before_any_device_call(native):
     assert L.sim_create(ctypes.byref(cfg), ctypes.byref(h)) == native.SIM_EINVAL
 
 
+def test_create_validates_pattern_grids(native):
+    """Gridded patterns: node counts, steps, origin and values are checked by
+    sim_create (no device work), a good grid is accepted and copied, and a
+    grid lifts the kappa/500 width limit of the analytic pattern."""
+    L = native.load()
+    g = W.harmony_geometry(8, 64)
+    vals = np.ones((5, 7), np.float32)
+
+    def with_grid(v, nu, nv, u0=-0.01, du=0.003, v0=-0.2, dv=0.1, beta_az=None):
+        cfg, keep = _config(native, g)
+        a = keep[1][0]
+        if beta_az is not None:
+            a.beta_az = beta_az
+        a.pattern = v.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        a.pattern_nu, a.pattern_nv = nu, nv
+        a.pattern_u0, a.pattern_du, a.pattern_v0, a.pattern_dv = u0, du, v0, dv
+        return cfg, keep
+
+    h = ctypes.c_void_p()
+    bad_vals = vals.copy()
+    bad_vals[2, 3] = np.nan
+    for kw, msg in (({"nu": 1, "nv": 5}, "nodes"), ({"nu": 7, "nv": 1}, "nodes"),
+                    ({"nu": 7, "nv": 5, "du": 0.0}, "steps"),
+                    ({"nu": 7, "nv": 5, "dv": float("inf")}, "steps"),
+                    ({"nu": 7, "nv": 5, "u0": float("nan")}, "origin")):
+        cfg, keep = with_grid(vals, **kw)
+        assert L.sim_create(ctypes.byref(cfg), ctypes.byref(h)) == native.SIM_EINVAL, kw
+        assert msg in L.sim_last_error().decode(), (kw, L.sim_last_error())
+    cfg, keep = with_grid(bad_vals, 7, 5)
+    assert L.sim_create(ctypes.byref(cfg), ctypes.byref(h)) == native.SIM_EINVAL
+    assert "finite" in L.sim_last_error().decode()
+    # accepted, also for a beam narrower than kappa/500 rad (no sinc argument)
+    cfg, keep = with_grid(vals, 7, 5, beta_az=1e-4)
+    assert L.sim_create(ctypes.byref(cfg), ctypes.byref(h)) == native.SIM_OK
+    L.sim_destroy(h)
+
+
 def test_entry_points_reject_null(native):
     L = native.load()
     p = ctypes.c_void_p()

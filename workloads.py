@@ -63,11 +63,24 @@ class Platform:
 
 
 @dataclass(frozen=True)
+class Pattern:
+    """A field pattern tabulated on a u-v grid (direction cosines on the
+    antenna's azimuth and elevation axes): values[j, i] at u = u0 + i du,
+    v = v0 + j dv (float32)."""
+    u0: float
+    du: float
+    v0: float
+    dv: float
+    values: np.ndarray                  # float32 [nv, nu]
+
+
+@dataclass(frozen=True)
 class Antenna:
     platform: int
     beta_az: float                      # one-way 3-dB width in azimuth (rad)
     beta_el: float                      # one-way 3-dB width in elevation (rad)
     steer_rate: float = 0.0             # azimuth steering rate about the el axis (rad/s)
+    pattern: Optional[Pattern] = None   # gridded field pattern (None: analytic)
 
 
 @dataclass(frozen=True)
@@ -351,6 +364,34 @@ def tops_geometry(g: Geometry, rate_deg_s: float = 1.5) -> Geometry:
     ants = list(g.antennas)
     ants[0] = replace(ants[0], steer_rate=math.radians(rate_deg_s))
     return replace(g, antennas=tuple(ants))
+
+
+def synthetic_pattern(beta_az: float, beta_el: float, seed: int, nu: int = 129,
+                      nv: int = 65, span_az: float = 4.0, span_el: float = 2.0,
+                      ripple: float = 0.03) -> Pattern:
+    """Stand-in for an industrial antenna model (the paper's patterns come
+    from phased-array models that are not available): a Gaussian main beam
+    with the given one-way 3-dB widths (field exp(-2 ln2 (x^2 + y^2)),
+    x = u / beta_az, y = v / beta_el), an az-el coupling term 0.15 x y, and
+    seeded per-node ripple of relative size `ripple` (element errors), on a
+    grid spanning +-span_az beam widths in u and +-span_el in v."""
+    rng = np.random.default_rng(seed + 104729)
+    u = np.linspace(-span_az * beta_az, span_az * beta_az, nu)
+    v = np.linspace(-span_el * beta_el, span_el * beta_el, nv)
+    x = u[None, :] / beta_az
+    y = v[:, None] / beta_el
+    f = np.exp(-2.0 * math.log(2.0) * (x * x + y * y) + 0.15 * x * y)
+    f = f * (1.0 + ripple * rng.standard_normal((nv, nu)))
+    return Pattern(float(u[0]), float(u[1] - u[0]), float(v[0]), float(v[1] - v[0]),
+                   f.astype(np.float32))
+
+
+def gridded_geometry(g: Geometry, seed: int = 0, **kw) -> Geometry:
+    """The same acquisition with every antenna's pattern given as a u-v grid
+    (synthetic_pattern of its beam widths)."""
+    ants = tuple(replace(a, pattern=synthetic_pattern(a.beta_az, a.beta_el, seed + i, **kw))
+                 for i, a in enumerate(g.antennas))
+    return replace(g, antennas=ants)
 
 
 def with_pulses(g: Geometry, n_pulses: int) -> Geometry:
