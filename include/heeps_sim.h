@@ -99,7 +99,9 @@ typedef struct {
      * bilinear between nodes, 0 outside [u0, u0 + (nu-1) du) x
      * [v0, v0 + (nv-1) dv) and behind the antenna.  sim_create copies it
      * (the caller's array may be freed afterwards).  nu, nv >= 2,
-     * (nu-1)(nv-1) <= 2^24, du, dv > 0, all values finite, else SIM_EINVAL.
+     * (nu-1)(nv-1) <= 2^24, du, dv > 0, all values finite, else SIM_EINVAL;
+     * |u| <= 2^14 du and |v| <= 2^14 dv over the whole table (cell
+     * coordinates are FP32), else SIM_EUNSUPPORTED.
      * A handle with any gridded antenna evaluates every pattern per facet
      * (no elevation factor at block centres, whatever sim_plan_mode says). */
     const float *pattern;

@@ -510,6 +510,13 @@ int sim_create(const sim_config *cfg, sim_handle **out) {
                 !std::isfinite(a.pattern_dv) || !std::isfinite(a.pattern_u0) ||
                 !std::isfinite(a.pattern_v0))
                 HS_FAIL(SIM_EINVAL, "pattern grid origin and steps must be finite, steps > 0");
+            // cell coordinates u/du - u0/du are FP32: at most 2^14 cells from
+            // u = 0 anywhere on the table keeps their rounding below 1e-3 cell
+            const double ue = a.pattern_u0 + (a.pattern_nu - 1) * a.pattern_du;
+            const double ve = a.pattern_v0 + (a.pattern_nv - 1) * a.pattern_dv;
+            if (std::max(std::fabs(a.pattern_u0), std::fabs(ue)) > 16384.0 * a.pattern_du ||
+                std::max(std::fabs(a.pattern_v0), std::fabs(ve)) > 16384.0 * a.pattern_dv)
+                HS_FAIL(SIM_EUNSUPPORTED, "pattern grid reaches more than 2^14 cells from u, v = 0");
             const long long nn = (long long)a.pattern_nu * a.pattern_nv;
             for (long long k = 0; k < nn; ++k)
                 if (!std::isfinite(a.pattern[k]))

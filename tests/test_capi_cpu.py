@@ -115,6 +115,10 @@ def test_create_validates_pattern_grids(native):
     cfg, keep = with_grid(bad_vals, 7, 5)
     assert L.sim_create(ctypes.byref(cfg), ctypes.byref(h)) == native.SIM_EINVAL
     assert "finite" in L.sim_last_error().decode()
+    # a table reaching 2^14 cells from u = 0 is refused (FP32 cell coordinates)
+    cfg, keep = with_grid(vals, 7, 5, u0=0.5, du=1e-5)
+    assert L.sim_create(ctypes.byref(cfg), ctypes.byref(h)) == native.SIM_EUNSUPPORTED
+    assert "2^14" in L.sim_last_error().decode()
     # accepted, also for a beam narrower than kappa/500 rad (no sinc argument)
     cfg, keep = with_grid(vals, 7, 5, beta_az=1e-4)
     assert L.sim_create(ctypes.byref(cfg), ctypes.byref(h)) == native.SIM_OK
