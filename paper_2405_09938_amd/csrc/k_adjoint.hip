@@ -73,7 +73,7 @@ __device__ __forceinline__ float ant_grad(const AntArgs &a, double d0, double d1
     const double v = u0 * a.el[0] + u1 * a.el[1] + u2 * a.el[2];
     if (GRD && a.grid) {   // uniform: the antenna is the workgroup's channel's
         const float x = (float)(u * a.gidu) - a.gu0, y = (float)(v * a.gidv) - a.gv0;
-        const bool in = x >= 0.0f && x < a.gnu1 && y >= 0.0f && y < a.gnv1;
+        const bool in = (x >= 0.0f) & (x < a.gnu1) & (y >= 0.0f) & (y < a.gnv1);
         const float fx = floorf(x), fy = floorf(y);
         const int idx = in ? (int)fy * a.gstride + (int)fx : 0;
         const float4 c = a.grid[idx];

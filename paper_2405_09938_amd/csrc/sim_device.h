@@ -40,31 +40,50 @@ __device__ __forceinline__ float dsinc_f(float x) {
     return (fabsf(x) < 1e-6f) ? 0.0f : r;
 }
 
-// Gridded field pattern at cell coordinates (x, y) = ((u - u0)/du, (v - v0)/dv):
-// bilinear in the cell's four corners (one 16-byte load), 0 outside the
-// half-open range [0, nu-1) x [0, nv-1) (NaN included: the index is then 0).
-__device__ __forceinline__ float grid_gain(const AntArgs &a, float x, float y) {
-    const bool in = x >= 0.0f && x < a.gnu1 && y >= 0.0f && y < a.gnv1;
-    const float fx = floorf(x), fy = floorf(y);
-    const int idx = in ? (int)fy * a.gstride + (int)fx : 0;
-    const float4 c = a.grid[idx];
-    const float ax = x - fx, ay = y - fy;
-    const float lo = fmaf(ax, c.y - c.x, c.x);
-    const float hi = fmaf(ax, c.w - c.z, c.z);
-    return in ? fmaf(ay, hi - lo, lo) : 0.0f;
+// One antenna's field for the GRD kernels, in two steps so that the table
+// load is in flight while the phase is computed.  fetch: from the projections
+// pu, pv of the facet direction (times R) on the antenna's scaled azimuth and
+// elevation axes and the first-order 1/R, an antenna with a u-v table gets
+// its cell coordinates ((u - u0)/du, (v - v0)/dv; axes scaled to cell units)
+// and issues the one 16-byte load of the cell's four corners (cell 0 when
+// outside the half-open range [0, nu-1) x [0, nv-1), NaN included); an
+// antenna without a table keeps the sinc arguments (axes scaled by
+// kappa/(2 beta)).  finish: the bilinear value (0 outside), or the sinc
+// product normalised here since GRD spreading terms carry no (2 pi)^k.  The
+// branch on the table pointer is uniform (the workgroup's channel's antenna).
+struct GridFetch {
+    float4 c;       // cell corners (i,j), (i+1,j), (i,j+1), (i+1,j+1)
+    float x, y;     // cell coordinates, or the two sinc arguments
+    bool in;
+};
+
+__device__ __forceinline__ GridFetch ant_fetch(const AntArgs &a, float pu, float pv, float irf) {
+    GridFetch g;
+    if (a.grid) {
+        g.x = fmaf(pu, irf, -a.gu0);
+        g.y = fmaf(pv, irf, -a.gv0);
+        // bitwise tests: no short-circuit branches in the facet loop
+        g.in = (g.x >= 0.0f) & (g.x < a.gnu1) & (g.y >= 0.0f) & (g.y < a.gnv1);
+        const int idx = g.in ? (int)floorf(g.y) * a.gstride + (int)floorf(g.x) : 0;
+        g.c = a.grid[idx];
+    } else {
+        g.x = fmaf(fabsf(pu), irf, 1e-9f);
+        g.y = fmaf(fabsf(pv), irf, 1e-9f);
+        g.in = true;
+        g.c = float4{0.f, 0.f, 0.f, 0.f};
+    }
+    return g;
 }
 
-// One antenna's field for the GRD kernels, from the projections pu, pv of the
-// facet direction (times R) on its scaled azimuth and elevation axes and the
-// first-order 1/R: the grid lookup for an antenna with a table (axes scaled
-// to cell units), else the sinc product (axes scaled by kappa/(2 beta)),
-// normalised here since GRD spreading terms carry no (2 pi)^k.  The branch is
-// uniform (the antenna is the workgroup's channel's).
-__device__ __forceinline__ float ant_field(const AntArgs &a, float pu, float pv, float irf) {
-    if (a.grid) return grid_gain(a, fmaf(pu, irf, -a.gu0), fmaf(pv, irf, -a.gv0));
-    const float y1 = fmaf(fabsf(pu), irf, 1e-9f), y2 = fmaf(fabsf(pv), irf, 1e-9f);
-    return (__builtin_amdgcn_sinf(y1) * __builtin_amdgcn_sinf(y2)) *
-           __builtin_amdgcn_rcpf((float)(kTwoPi * kTwoPi) * (y1 * y2));
+__device__ __forceinline__ float ant_finish(const AntArgs &a, const GridFetch &g) {
+    if (a.grid) {
+        const float ax = g.x - floorf(g.x), ay = g.y - floorf(g.y);
+        const float lo = fmaf(ax, g.c.y - g.c.x, g.c.x);
+        const float hi = fmaf(ax, g.c.w - g.c.z, g.c.z);
+        return g.in ? fmaf(ay, hi - lo, lo) : 0.0f;
+    }
+    return (__builtin_amdgcn_sinf(g.x) * __builtin_amdgcn_sinf(g.y)) *
+           __builtin_amdgcn_rcpf((float)(kTwoPi * kTwoPi) * (g.x * g.y));
 }
 
 // Per-(block, pulse) references of one lane (FP64 -> FP32).
@@ -270,6 +289,16 @@ __device__ __forceinline__ void facet_geo(const Refs &r, const FacetConsts &cc, 
     const float s1 = at * r.i2rt, s2 = ar * r.i2rr;
     const float h2 = fmaf(at, s1, ar * s2);
     const float dR = L + fmaf(ee, r.i2s, -h2);
+    [[maybe_unused]] GridFetch gt, gr;
+    if constexpr (GRD) {
+        static_assert(!ELC, "gridded patterns are evaluated per facet");
+        // table cells requested before the phase, used after it
+        const float it = fmaf(-at, r.irt2, r.irt), ir = fmaf(-ar, r.irr2, r.irr);
+        gt = ant_fetch(*t, fmaf(ez, cc.kta[2], fmaf(ey, cc.kta[1], fmaf(ex, cc.kta[0], r.gtaz))),
+                       fmaf(ez, cc.kte[2], fmaf(ey, cc.kte[1], fmaf(ex, cc.kte[0], r.gtel))), it);
+        gr = ant_fetch(*q, fmaf(ez, cc.kra[2], fmaf(ey, cc.kra[1], fmaf(ex, cc.kra[0], r.graz))),
+                       fmaf(ez, cc.kre[2], fmaf(ey, cc.kre[1], fmaf(ex, cc.kre[0], r.grel))), ir);
+    }
     // phase (cycles) = phib - dR f0/c (+ dop, the intra-facet Doppler of a
     // speckle sum, if DOP), product split so the integer part of the cycle
     // count is removed exactly
@@ -292,12 +321,7 @@ __device__ __forceinline__ void facet_geo(const Refs &r, const FacetConsts &cc, 
     const float s = fmaf(-ar, r.sbr, fmaf(-at, r.sbt, r.sb));
     float amp;
     if constexpr (GRD) {
-        static_assert(!ELC, "gridded patterns are evaluated per facet");
-        const float pta = fmaf(ez, cc.kta[2], fmaf(ey, cc.kta[1], fmaf(ex, cc.kta[0], r.gtaz)));
-        const float pte = fmaf(ez, cc.kte[2], fmaf(ey, cc.kte[1], fmaf(ex, cc.kte[0], r.gtel)));
-        const float pra = fmaf(ez, cc.kra[2], fmaf(ey, cc.kra[1], fmaf(ex, cc.kra[0], r.graz)));
-        const float pre = fmaf(ez, cc.kre[2], fmaf(ey, cc.kre[1], fmaf(ex, cc.kre[0], r.grel)));
-        amp = (ant_field(*t, pta, pte, irtf) * ant_field(*q, pra, pre, irrf)) * s;
+        amp = (ant_finish(*t, gt) * ant_finish(*q, gr)) * s;
     } else {
         const float yta = fmaf(fabsf(fmaf(ez, cc.kta[2], fmaf(ey, cc.kta[1], fmaf(ex, cc.kta[0], r.gtaz)))), irtf, 1e-9f);
         const float yra = fmaf(fabsf(fmaf(ez, cc.kra[2], fmaf(ey, cc.kra[1], fmaf(ex, cc.kra[0], r.graz)))), irrf, 1e-9f);
