@@ -103,7 +103,9 @@ typedef struct {
      * |u| <= 2^14 du and |v| <= 2^14 dv over the whole table (cell
      * coordinates are FP32), else SIM_EUNSUPPORTED.
      * A handle with any gridded antenna evaluates every pattern per facet
-     * (no elevation factor at block centres, whatever sim_plan_mode says). */
+     * (no elevation factor at block centres); sim_plan_mode's far-field mode
+     * then only drops the adjoint's first-order correction of the gain
+     * gradient across a block. */
     const float *pattern;
     int pattern_nu, pattern_nv;
     double pattern_u0, pattern_du, pattern_v0, pattern_dv;

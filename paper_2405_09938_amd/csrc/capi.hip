@@ -283,6 +283,9 @@ struct DevBufs {
 // most dx max|sinc'| / min sinc over [x_lo - dx, x_hi + dx], plus the
 // second-order term dx^2 max|sinc''| / 2 / min sinc (|sinc''| <= pi^2 / 3).
 // Returns +inf when the interval reaches |x| >= 0.9 (near the first null).
+// An antenna with a u-v table is bounded through its nominal elevation width
+// (the sinc of that width stands for its beam; the bound then only decides
+// whether the adjoint drops its first-order gain-gradient correction).
 double elevation_bound(const sim_handle *h, const float box[4], double e_max) {
     double worst = 0.0;
     const double xs[3] = {box[0], 0.5 * (box[0] + box[1]), box[1]};
@@ -290,7 +293,9 @@ double elevation_bound(const sim_handle *h, const float box[4], double e_max) {
     const int ps[3] = {0, h->Np / 2, h->Np - 1};
     for (int ch = 0; ch < h->C; ++ch)
         for (int leg = 0; leg < 2; ++leg) {
-            const hs::AntArgs &a = h->antc[leg == 0 ? h->chc[ch].tx : h->chc[ch].rx];
+            const int ai = leg == 0 ? h->chc[ch].tx : h->chc[ch].rx;
+            const hs::AntArgs &a = h->antc[ai];
+            const double ke = h->kappa / h->ants[ai].beta_el;   // the sinc's, grid or not
             double x_lo = 1e300, x_hi = -1e300, r_min = 1e300;
             for (int pi = 0; pi < 3; ++pi) {
                 const hs::PulseRec &r = h->pulses_h[(size_t)ch * h->Np + ps[pi]];
@@ -299,13 +304,13 @@ double elevation_bound(const sim_handle *h, const float box[4], double e_max) {
                     for (double yv : ys) {
                         const double d[3] = {xv - P[0], yv - P[1], -P[2]};
                         const double R = norm3(d);
-                        const double x = a.ke * (d[0] * a.el[0] + d[1] * a.el[1] + d[2] * a.el[2]) / R;
+                        const double x = ke * (d[0] * a.el[0] + d[1] * a.el[1] + d[2] * a.el[2]) / R;
                         x_lo = std::min(x_lo, x);
                         x_hi = std::max(x_hi, x);
                         r_min = std::min(r_min, R);
                     }
             }
-            const double dx = a.ke * e_max / r_min;
+            const double dx = ke * e_max / r_min;
             const double lo = x_lo - dx - 0.1 * (x_hi - x_lo), hi = x_hi + dx + 0.1 * (x_hi - x_lo);
             if (std::max(std::fabs(lo), std::fabs(hi)) >= 0.9)
                 return std::numeric_limits<double>::infinity();
@@ -1219,7 +1224,9 @@ static int backward_common(sim_handle *h, sim_plan *P, const sim_facets *f,
     a.steer = h->steer;
     a.inv_c = 1.0 / h->c;
     a.grid = h->grid;
-    HS_HIP(hs::launch_adjoint(a, P->el_const && !h->grid, sp != nullptr, s), "adjoint");
+    // (with gridded patterns the plan's far-field mode only drops the
+    // adjoint's Jacobian correction; the patterns stay per facet)
+    HS_HIP(hs::launch_adjoint(a, P->el_const, sp != nullptr, s), "adjoint");
     return SIM_OK;
 }
 

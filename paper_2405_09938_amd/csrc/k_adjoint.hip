@@ -135,8 +135,12 @@ __device__ __forceinline__ void grad_t(const AntArgs &ta, const AntArgs &ra, dou
 // x = z + K_k D_g with (y_g, D_g) from the preparation pass.
 // STR: antenna frames turn with time (steering): the per-pulse angles are
 // staged with the references and the facet-part constants rebuilt per pulse.
+// GRD: gridded patterns, always evaluated per facet; ELC then only drops the
+// first-order Jacobian correction of grad T (far-field plans, as for the
+// sinc pattern with its elevation factors at block centres).
 template <bool ELC, bool SPK, bool STR, bool GRD>
 __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
+    constexpr bool kElc = ELC && !GRD;   // elevation factors at block centres
     constexpr int kNR = kNRef<SPK, STR>;
     constexpr int kSt = R_ST0<SPK>;
     __shared__ float4 refs[kStage * kNR / 4];
@@ -214,7 +218,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                     snr = P.snr;
                 }
                 Refs r;
-                block_refs<ELC, STR, GRD>(xb, yb, P.ptx, prb, P.rref, ta, ra, chn.rtrr_mid, A.f0_c,
+                block_refs<kElc, STR, GRD>(xb, yb, P.ptx, prb, P.rref, ta, ra, chn.rtrr_mid, A.f0_c,
                                 A.fs_c, A.n_ref, live, r, qr, cst, snt, csr, snr);
                 // grad T at the centre
                 const double dt0 = xb - P.ptx[0], dt1 = yb - P.ptx[1], dt2 = -P.ptx[2];
@@ -336,7 +340,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                     steer_axes(ta, ra, rot.x, rot.y, rot.z, rot.w, kq);
                 }
                 Geo g;
-                facet_geo<ELC, SPK, STR, GRD>(r, kq, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz,
+                facet_geo<kElc, SPK, STR, GRD>(r, kq, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz,
                                          r.graze != 0, o[R_LHI], o[R_LLO], o[R_FSQ], dop, g, &ta,
                                          &ra, rot);
                 float tap[8], dtap[8];
@@ -446,14 +450,24 @@ hipError_t launch_adjoint(const AdjArgs &a, bool el_const, bool speckle, hipStre
     if (wgs > 0xffffffffULL) return hipErrorInvalidConfiguration;
     const dim3 grid((unsigned)wgs);
 #define HS_ADJ(E, S, T) hipLaunchKernelGGL((k_adjoint<E, S, T, false>), grid, dim3(64), 0, s, a)
-#define HS_ADJG(S, T) hipLaunchKernelGGL((k_adjoint<false, S, T, true>), grid, dim3(64), 0, s, a)
-    if (a.grid) {   // gridded patterns: always per facet
+#define HS_ADJG(E, S, T) hipLaunchKernelGGL((k_adjoint<E, S, T, true>), grid, dim3(64), 0, s, a)
+    if (a.grid) {   // gridded patterns: per facet; el_const drops the Jacobian
         if (a.steer) {
-            if (speckle) HS_ADJG(true, true);
-            else HS_ADJG(false, true);
+            if (speckle) {
+                if (el_const) HS_ADJG(true, true, true);
+                else HS_ADJG(false, true, true);
+            } else {
+                if (el_const) HS_ADJG(true, false, true);
+                else HS_ADJG(false, false, true);
+            }
         } else {
-            if (speckle) HS_ADJG(true, false);
-            else HS_ADJG(false, false);
+            if (speckle) {
+                if (el_const) HS_ADJG(true, true, false);
+                else HS_ADJG(false, true, false);
+            } else {
+                if (el_const) HS_ADJG(true, false, false);
+                else HS_ADJG(false, false, false);
+            }
         }
     } else if (a.steer) {
         if (speckle) {
