@@ -563,18 +563,19 @@ int sim_create(const sim_config *cfg, sim_handle **out) {
         }
         if (an.steer_rate != 0.0) h->steer = 1;
     }
-    h->grid = 0;
     h->pat_h.resize(h->ants.size());
     h->pat_d.assign(h->ants.size(), nullptr);
+    size_t n_grid = 0;
     for (size_t a = 0; a < h->ants.size(); ++a) {
         sim_antenna &an = h->ants[a];
         if (an.pattern) {
             h->pat_h[a].assign(an.pattern,
                                an.pattern + (size_t)an.pattern_nu * (size_t)an.pattern_nv);
             an.pattern = h->pat_h[a].data();   // the caller's array is not kept
-            h->grid = 1;
+            ++n_grid;
         }
     }
+    h->grid = n_grid == 0 ? 0 : (n_grid == h->ants.size() ? 2 : 1);
     h->antc.resize(h->ants.size());
     for (size_t a = 0; a < h->ants.size(); ++a) {
         antenna_frame(h, (int)a, h->antc[a]);

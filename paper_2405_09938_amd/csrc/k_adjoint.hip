@@ -59,7 +59,7 @@ constexpr int kNRef = R_ST0<SPK> + (STR ? 4 : 0);
 // GRD: the field of an antenna with a u-v grid from that grid (the others keep
 // the sinc); dF/du, dF/dv are its cell slopes (bilinear: piecewise linear
 // along each axis).
-template <bool STR, bool GRD>
+template <bool STR, int GRD>
 __device__ __forceinline__ float ant_grad(const AntArgs &a, double d0, double d1, double d2,
                                           double ir, float *gr, double cs, double sn) {
     const double u0 = d0 * ir, u1 = d1 * ir, u2 = d2 * ir;
@@ -71,7 +71,7 @@ __device__ __forceinline__ float ant_grad(const AntArgs &a, double d0, double d1
     }
     const double u = u0 * az[0] + u1 * az[1] + u2 * az[2];
     const double v = u0 * a.el[0] + u1 * a.el[1] + u2 * a.el[2];
-    if (GRD && a.grid) {   // uniform: the antenna is the workgroup's channel's
+    if (GRD == 2 || (GRD != 0 && a.grid)) {   // uniform: the workgroup's channel's antenna
         const float x = (float)(u * a.gidu) - a.gu0, y = (float)(v * a.gidv) - a.gv0;
         const bool in = (x >= 0.0f) & (x < a.gnu1) & (y >= 0.0f) & (y < a.gnv1);
         const float fx = floorf(x), fy = floorf(y);
@@ -108,7 +108,7 @@ __device__ __forceinline__ float ant_grad(const AntArgs &a, double d0, double d1
 
 // grad T = grad(F_tx F_rx S) at the point (X, Y, Z), S = R_t,mid R_r,mid /
 // (R_t R_r) the spreading (without the mask).
-template <bool STR, bool GRD>
+template <bool STR, int GRD>
 __device__ __forceinline__ void grad_t(const AntArgs &ta, const AntArgs &ra, double rtrr_mid,
                                        double X, double Y, double Z, const double *ptx,
                                        const double *prx, float *out, double cst, double snt,
@@ -135,12 +135,13 @@ __device__ __forceinline__ void grad_t(const AntArgs &ta, const AntArgs &ra, dou
 // x = z + K_k D_g with (y_g, D_g) from the preparation pass.
 // STR: antenna frames turn with time (steering): the per-pulse angles are
 // staged with the references and the facet-part constants rebuilt per pulse.
-// GRD: gridded patterns, always evaluated per facet; ELC then only drops the
-// first-order Jacobian correction of grad T (far-field plans, as for the
-// sinc pattern with its elevation factors at block centres).
-template <bool ELC, bool SPK, bool STR, bool GRD>
+// GRD: gridded patterns (1: on some antennas, 2: on all), always evaluated
+// per facet; ELC then only drops the first-order Jacobian correction of
+// grad T (far-field plans, as for the sinc pattern with its elevation
+// factors at block centres).
+template <bool ELC, bool SPK, bool STR, int GRD>
 __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
-    constexpr bool kElc = ELC && !GRD;   // elevation factors at block centres
+    constexpr bool kElc = ELC && GRD == 0;   // elevation factors at block centres
     constexpr int kNR = kNRef<SPK, STR>;
     constexpr int kSt = R_ST0<SPK>;
     __shared__ float4 refs[kStage * kNR / 4];
@@ -218,7 +219,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                     snr = P.snr;
                 }
                 Refs r;
-                block_refs<kElc, STR, GRD>(xb, yb, P.ptx, prb, P.rref, ta, ra, chn.rtrr_mid, A.f0_c,
+                block_refs<kElc, STR, GRD != 0>(xb, yb, P.ptx, prb, P.rref, ta, ra, chn.rtrr_mid, A.f0_c,
                                 A.fs_c, A.n_ref, live, r, qr, cst, snt, csr, snr);
                 // grad T at the centre
                 const double dt0 = xb - P.ptx[0], dt1 = yb - P.ptx[1], dt2 = -P.ptx[2];
@@ -449,8 +450,12 @@ hipError_t launch_adjoint(const AdjArgs &a, bool el_const, bool speckle, hipStre
     const unsigned long long wgs = ((unsigned long long)a.n_blocks + 7) / 8 * 8;
     if (wgs > 0xffffffffULL) return hipErrorInvalidConfiguration;
     const dim3 grid((unsigned)wgs);
-#define HS_ADJ(E, S, T) hipLaunchKernelGGL((k_adjoint<E, S, T, false>), grid, dim3(64), 0, s, a)
-#define HS_ADJG(E, S, T) hipLaunchKernelGGL((k_adjoint<E, S, T, true>), grid, dim3(64), 0, s, a)
+#define HS_ADJ(E, S, T) hipLaunchKernelGGL((k_adjoint<E, S, T, 0>), grid, dim3(64), 0, s, a)
+#define HS_ADJG(E, S, T)                                                                   \
+    do {                                                                                   \
+        if (a.grid == 2) hipLaunchKernelGGL((k_adjoint<E, S, T, 2>), grid, dim3(64), 0, s, a); \
+        else hipLaunchKernelGGL((k_adjoint<E, S, T, 1>), grid, dim3(64), 0, s, a);        \
+    } while (0)
     if (a.grid) {   // gridded patterns: per facet; el_const drops the Jacobian
         if (a.steer) {
             if (speckle) {

@@ -105,7 +105,7 @@ constexpr int kFlushTransposeMax = 32;
 // one group of the speckle process; lanes before p0 or past the last pulse
 // take part in the prefix sum but deposit nothing.
 // STR: antenna frames turn with time (steering): per-pulse frames.
-template <int WIN, bool ELC, bool SPK, bool STR, bool GRD>
+template <int WIN, bool ELC, bool SPK, bool STR, int GRD>
 __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
     // [sample][lane] during the sum; [lane][WIN + 1] for the flush
     constexpr int kAcc = WIN <= kFlushTransposeMax ? 64 * (WIN + 1) : 64 * WIN;
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
         double qr = 1.0;
         if (A.rx_exact)
             rx_echo((double)blk.xb, (double)blk.yb, ptx, prx, rref, A.ch[ch].vr, A.inv_c, prb, qr);
-        block_refs<ELC, STR, GRD>((double)blk.xb, (double)blk.yb, ptx, prb, rref, ta, ra, chn.rtrr_mid,
+        block_refs<ELC, STR, GRD != 0>((double)blk.xb, (double)blk.yb, ptx, prb, rref, ta, ra, chn.rtrr_mid,
                         A.f0_c, A.fs_c, A.n_ref, live, r, qr, rot.x, rot.y, rot.z, rot.w);
         const bool graze_any = __any(r.graze);
         // the window offset of the first tap rides in the sample fraction, so
@@ -345,17 +345,20 @@ hipError_t launch_forward(const FwdArgs &a, int C, int win, bool el_const, bool 
     if (wgs > 0xffffffffULL) return hipErrorInvalidConfiguration;
     dim3 grid((unsigned)wgs, (unsigned)C);
     // gridded patterns are always evaluated per facet (no elevation factor
-    // at block centres)
+    // at block centres); a.grid = 2 when every antenna has a table
 #define HS_FWD4(W, T)                                                                       \
-    if (a.grid) {                                                                           \
-        if (speckle) hipLaunchKernelGGL((k_forward<W, false, true, T, true>), grid, dim3(64), 0, s, a); \
-        else hipLaunchKernelGGL((k_forward<W, false, false, T, true>), grid, dim3(64), 0, s, a); \
+    if (a.grid == 2) {                                                                      \
+        if (speckle) hipLaunchKernelGGL((k_forward<W, false, true, T, 2>), grid, dim3(64), 0, s, a); \
+        else hipLaunchKernelGGL((k_forward<W, false, false, T, 2>), grid, dim3(64), 0, s, a); \
+    } else if (a.grid) {                                                                    \
+        if (speckle) hipLaunchKernelGGL((k_forward<W, false, true, T, 1>), grid, dim3(64), 0, s, a); \
+        else hipLaunchKernelGGL((k_forward<W, false, false, T, 1>), grid, dim3(64), 0, s, a); \
     } else if (speckle) {                                                                   \
-        if (el_const) hipLaunchKernelGGL((k_forward<W, true, true, T, false>), grid, dim3(64), 0, s, a); \
-        else hipLaunchKernelGGL((k_forward<W, false, true, T, false>), grid, dim3(64), 0, s, a); \
+        if (el_const) hipLaunchKernelGGL((k_forward<W, true, true, T, 0>), grid, dim3(64), 0, s, a); \
+        else hipLaunchKernelGGL((k_forward<W, false, true, T, 0>), grid, dim3(64), 0, s, a); \
     } else {                                                                                \
-        if (el_const) hipLaunchKernelGGL((k_forward<W, true, false, T, false>), grid, dim3(64), 0, s, a); \
-        else hipLaunchKernelGGL((k_forward<W, false, false, T, false>), grid, dim3(64), 0, s, a); \
+        if (el_const) hipLaunchKernelGGL((k_forward<W, true, false, T, 0>), grid, dim3(64), 0, s, a); \
+        else hipLaunchKernelGGL((k_forward<W, false, false, T, 0>), grid, dim3(64), 0, s, a); \
     }
 #define HS_FWD(W)                                                                           \
     case W:                                                                                 \

@@ -50,16 +50,18 @@ __device__ __forceinline__ float dsinc_f(float x) {
 // antenna without a table keeps the sinc arguments (axes scaled by
 // kappa/(2 beta)).  finish: the bilinear value (0 outside), or the sinc
 // product normalised here since GRD spreading terms carry no (2 pi)^k.  The
-// branch on the table pointer is uniform (the workgroup's channel's antenna).
+// branch on the table pointer is uniform (the workgroup's channel's
+// antenna); ALL (every antenna of the handle has a table) removes it.
 struct GridFetch {
     float4 c;       // cell corners (i,j), (i+1,j), (i,j+1), (i+1,j+1)
     float x, y;     // cell coordinates, or the two sinc arguments
     bool in;
 };
 
+template <bool ALL>
 __device__ __forceinline__ GridFetch ant_fetch(const AntArgs &a, float pu, float pv, float irf) {
     GridFetch g;
-    if (a.grid) {
+    if (ALL || a.grid) {
         g.x = fmaf(pu, irf, -a.gu0);
         g.y = fmaf(pv, irf, -a.gv0);
         // bitwise tests: no short-circuit branches in the facet loop
@@ -75,8 +77,9 @@ __device__ __forceinline__ GridFetch ant_fetch(const AntArgs &a, float pu, float
     return g;
 }
 
+template <bool ALL>
 __device__ __forceinline__ float ant_finish(const AntArgs &a, const GridFetch &g) {
-    if (a.grid) {
+    if (ALL || a.grid) {
         const float ax = g.x - floorf(g.x), ay = g.y - floorf(g.y);
         const float lo = fmaf(ax, g.c.y - g.c.x, g.c.x);
         const float hi = fmaf(ax, g.c.w - g.c.z, g.c.z);
@@ -269,8 +272,9 @@ struct Geo {
 // steering angles, with the antennas' FP32 axes (t, q).
 // GRD: field patterns from the antennas' u-v grids (t, q), with the direction
 // cosines in cell units (per-facet, first order in the offset like the sinc
-// arguments).
-template <bool ELC, bool DOP = false, bool ROT = false, bool GRD = false>
+// arguments); 1: antennas without a table keep the sinc, 2: every antenna
+// has a table.
+template <bool ELC, bool DOP = false, bool ROT = false, int GRD = 0>
 __device__ __forceinline__ void facet_geo(const Refs &r, const FacetConsts &cc, float tf,
                                           float fdx, float fdy, float fz, float fvx, float fvy,
                                           float fvz, bool graze_any, float linv_hi,
@@ -290,13 +294,13 @@ __device__ __forceinline__ void facet_geo(const Refs &r, const FacetConsts &cc, 
     const float h2 = fmaf(at, s1, ar * s2);
     const float dR = L + fmaf(ee, r.i2s, -h2);
     [[maybe_unused]] GridFetch gt, gr;
-    if constexpr (GRD) {
+    if constexpr (GRD != 0) {
         static_assert(!ELC, "gridded patterns are evaluated per facet");
         // table cells requested before the phase, used after it
         const float it = fmaf(-at, r.irt2, r.irt), ir = fmaf(-ar, r.irr2, r.irr);
-        gt = ant_fetch(*t, fmaf(ez, cc.kta[2], fmaf(ey, cc.kta[1], fmaf(ex, cc.kta[0], r.gtaz))),
+        gt = ant_fetch<GRD == 2>(*t, fmaf(ez, cc.kta[2], fmaf(ey, cc.kta[1], fmaf(ex, cc.kta[0], r.gtaz))),
                        fmaf(ez, cc.kte[2], fmaf(ey, cc.kte[1], fmaf(ex, cc.kte[0], r.gtel))), it);
-        gr = ant_fetch(*q, fmaf(ez, cc.kra[2], fmaf(ey, cc.kra[1], fmaf(ex, cc.kra[0], r.graz))),
+        gr = ant_fetch<GRD == 2>(*q, fmaf(ez, cc.kra[2], fmaf(ey, cc.kra[1], fmaf(ex, cc.kra[0], r.graz))),
                        fmaf(ez, cc.kre[2], fmaf(ey, cc.kre[1], fmaf(ex, cc.kre[0], r.grel))), ir);
     }
     // phase (cycles) = phib - dR f0/c (+ dop, the intra-facet Doppler of a
@@ -320,8 +324,8 @@ __device__ __forceinline__ void facet_geo(const Refs &r, const FacetConsts &cc, 
     // spreading R_mid^2 / (R_t R_r), first order in the offsets
     const float s = fmaf(-ar, r.sbr, fmaf(-at, r.sbt, r.sb));
     float amp;
-    if constexpr (GRD) {
-        amp = (ant_finish(*t, gt) * ant_finish(*q, gr)) * s;
+    if constexpr (GRD != 0) {
+        amp = (ant_finish<GRD == 2>(*t, gt) * ant_finish<GRD == 2>(*q, gr)) * s;
     } else {
         const float yta = fmaf(fabsf(fmaf(ez, cc.kta[2], fmaf(ey, cc.kta[1], fmaf(ex, cc.kta[0], r.gtaz)))), irtf, 1e-9f);
         const float yra = fmaf(fabsf(fmaf(ez, cc.kra[2], fmaf(ey, cc.kra[1], fmaf(ex, cc.kra[0], r.graz)))), irrf, 1e-9f);

@@ -124,7 +124,7 @@ struct FwdArgs {
     int halo;                   // bins added on each side of the patch span
     int rx_exact;               // receiver at each facet's own echo time
     int steer;                  // some antenna frame turns with time
-    int grid;                   // some antenna has a gridded pattern
+    int grid;                   // 0: no gridded pattern, 1: some antennas, 2: all
     double inv_c;               // 1 / c
     SpkArgs spk;                // speckle variant only
 };
@@ -147,7 +147,7 @@ struct AdjArgs {
     int accumulate;
     int rx_exact;               // receiver at each facet's own echo time
     int steer;                  // some antenna frame turns with time
-    int grid;                   // some antenna has a gridded pattern
+    int grid;                   // 0: no gridded pattern, 1: some antennas, 2: all
     double inv_c;               // 1 / c
     SpkArgs spk;                // speckle variant only
 };
@@ -171,7 +171,7 @@ struct sim_handle {
     int C;
     int rx_exact;
     int steer;                  // some antenna has a nonzero steering rate
-    int grid;                   // some antenna has a gridded pattern
+    int grid;                   // 0: no gridded pattern, 1: some antennas, 2: all
     std::vector<std::vector<float>> pat_h;   // per antenna: host copy of its grid (or empty)
     std::vector<float4 *> pat_d;             // per antenna: device cells (or NULL)
     // derived on the host in FP64
