@@ -229,3 +229,38 @@ def test_patterns_streamed_scene(env):
         ek = O.rel_l2(gr[k].cpu().numpy(), refg[k])
         say(f"gridded streamed adjoint {k} rel-L2 {ek:.3e}")
         assert ek < GRAD_TOL, k
+
+
+def test_patterns_edges(env):
+    """Gridded patterns on the edge cases of the plain path: a lone facet and
+    a ragged 63-facet set, accumulation onto an existing IQ, taps leaving a
+    narrow range window, an empty pulse range, and the adjoint of a lone
+    facet."""
+    torch, hs = env
+    say("case: gridded edges (1 and 63 facets, accumulate, narrow window, empty range)")
+    g = W.gridded_geometry(W.harmony_geometry(64, 128), seed=31)
+    sim = hs.Simulator(g)
+    rng = np.random.default_rng(32)
+    for n in (1, 63):
+        f = dict(x=rng.uniform(-300, 300, n), y=rng.uniform(-700, 700, n),
+                 z=rng.normal(0, 0.5, n), vx=rng.normal(0, 0.5, n), vy=rng.normal(0, 0.5, n),
+                 vz=rng.normal(0, 0.5, n), a_re=rng.normal(0, 0.7, n),
+                 a_im=rng.normal(0, 0.7, n))
+        f = {k: v.astype(np.float32) for k, v in f.items()}
+        d = dev(torch, f)
+        plan = sim.plan(d["x"], d["y"], 8.0)
+        base = torch.full((1, 64, 128), 0.5 - 0.25j, dtype=torch.complex64, device="cuda")
+        sim.forward(plan, d, 0, 64, out=base, accumulate=True)
+        torch.cuda.synchronize()
+        got = base.cpu().numpy().astype(np.complex128) - (0.5 - 0.25j)
+        F = f64(f)
+        ref = O.forward(g, F)
+        scale = np.abs(ref).max()
+        err = O.rel_l2(got, ref) if scale > 0 else np.abs(got).max()
+        say(f"{n} facet(s), accumulate, narrow window: rel-L2 {err:.3e}")
+        assert err < IQ_TOL
+        empty = sim.forward(plan, d, 10, 0)
+        assert empty.numel() == 0
+        if n == 1 and scale > 0:
+            check_adjoint(torch, sim, plan, d, F, g, sim.forward(plan, d).cpu().numpy(), 0, 64,
+                          33, label="gridded lone facet")
