@@ -13,9 +13,9 @@
 // airborne ranges where e/R reaches 1e-4); grad T, whose share of dL/dX is
 // ~1e-4 at 15 km and ~1e-6 at 850 km, is taken at the block centre, with a
 // first-order correction J e (J its Jacobian there, by central differences
-// in the stage prologue) where the plan evaluates every pattern factor per
-// facet (near-field geometries); everything else is recomputed exactly as in
-// the forward kernel.
+// in the stage prologue) where the plan's far-field bound fails (near-field
+// geometries, which also evaluate every pattern factor per facet);
+// everything else is recomputed exactly as in the forward kernel.
 //
 // Work decomposition: one wave per spatial block, lane = facet (<= 64 per
 // block).  The wave loops over channels and over stages of 32 pulses; per

@@ -6,8 +6,9 @@
 // Kaiser-windowed sinc (the range slices of eq. 17).
 //
 // Work decomposition (one workgroup = one wave):
-//   blockIdx.x = patch of spatial blocks, blockIdx.y = group of 64 pulses,
-//   blockIdx.z = channel.  Lane = pulse: every lane handles the same facet
+//   blockIdx.x = (patch of spatial blocks, group of 64 pulses), decoded so
+//   that the groups of one patch share an XCD (below); blockIdx.y = channel.
+//   Lane = pulse: every lane handles the same facet
 //   (its 32-byte record arrives by two uniform buffer loads) and deposits into
 //   its own pulse column of an LDS range window.  Since no other lane or wave
 //   touches that column, the deposit is a plain read-modify-write (8 x 64-bit
@@ -15,7 +16,8 @@
 //   writes) instead of LDS atomics, which serialise per lane on gfx950.  The
 //   window is stored sample-major ([sample][lane]), so the 64 lanes of one
 //   access always fall on distinct bank pairs whatever their sample indices:
-//   a lane-major layout conflicts as soon as the lanes' sample indices differ.  At the end the window is flushed to the
+//   a lane-major layout conflicts as soon as the lanes' sample indices
+//   differ.  At the end the window is flushed to the
 //   IQ lines with global float atomics, since neighbouring patches overlap in
 //   range.  A contribution whose taps leave the window (only for geometries
 //   the patch sizing did not foresee) goes straight to global memory.
@@ -105,6 +107,8 @@ constexpr int kFlushTransposeMax = 32;
 // one group of the speckle process; lanes before p0 or past the last pulse
 // take part in the prefix sum but deposit nothing.
 // STR: antenna frames turn with time (steering): per-pulse frames.
+// GRD: field patterns from u-v tables (1: on some antennas, 2: on all),
+// evaluated per facet (never with ELC).
 template <int WIN, bool ELC, bool SPK, bool STR, int GRD>
 __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
     // [sample][lane] during the sum; [lane][WIN + 1] for the flush

@@ -99,9 +99,11 @@ struct Refs {
     float fb;                       // fractional part of the centre's sample
     int nb;                         // integer part of the centre's sample
     float gtaz, gtel, graz, grel;   // (kappa/beta)/2 (D . axis) per antenna axis
+                                    // (D . axis / du or dv for a gridded antenna)
     float irt, irt2, irr, irr2;     // 1/R_b and 1/R_b^2 per leg
     float sb, sbt, sbr;             // spreading at the centre (and over R per leg),
-                                    // times the mask, divided by (2 pi)^4
+                                    // times the mask, divided by (2 pi)^4 (not
+                                    // with gridded patterns)
     float mask;                     // 1 if the lane's pulse is live and in front
     float dbt, dbr;                 // D . b per leg (grazing blocks only)
     int graze;                      // block straddles an antenna's back plane
