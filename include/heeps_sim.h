@@ -91,7 +91,7 @@ typedef struct {
      * antenna at the pulse time, a receive antenna at t_p + tau_ref.  0 =
      * fixed frame. */
     double steer_rate;
-    /* u-v gridded field pattern (Sec. IV.B: patterns, whatever their source,
+    /* u-v gridded field pattern (Sec. III.B: patterns, whatever their source,
      * become u-v grids in GPU memory), or NULL for the sinc pattern above.
      * Host float32 [pattern_nv][pattern_nu] (u fastest), the real one-way
      * field gain at direction cosines u = u0 + i du on the azimuth axis and

@@ -214,7 +214,7 @@ static void make_ant(const og_config *g, int ant, double kap, og_ant *a) {
 }
 
 /*
- * Gridded field pattern (Sec. IV.B: patterns, whatever their source, are
+ * Gridded field pattern (Sec. III.B: patterns, whatever their source, are
  * converted into u-v grids held in GPU memory).  Reading: a real one-way field
  * gain tabulated over the direction cosines u (azimuth axis) and v (elevation
  * axis), interpolated bilinearly; the table covers the half-open cells

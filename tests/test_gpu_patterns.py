@@ -1,4 +1,4 @@
-"""GPU parity of u-v gridded antenna patterns (Sec. IV.B: patterns converted
+"""GPU parity of u-v gridded antenna patterns (Sec. III.B: patterns converted
 into u-v grids in GPU memory) against the FP64 oracle, which interpolates the
 same float32 tables: forward and adjoint, with a grid on every antenna or on
 some, over six channels, combined with steering, speckle and the per-facet

@@ -1,4 +1,4 @@
-"""Pins of the oracle's u-v gridded antenna patterns (Sec. IV.B: patterns are
+"""Pins of the oracle's u-v gridded antenna patterns (Sec. III.B: patterns are
 converted into u-v grids held in GPU memory; reading: a real field gain over
 the direction cosines on the antenna's azimuth and elevation axes,
 interpolated bilinearly, zero outside the table's half-open cells).
