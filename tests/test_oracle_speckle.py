@@ -196,3 +196,28 @@ def test_speckle_adjoint_vs_richardson_fd(key):
         scale = max(abs(gr[key][i]), 1e-6 * np.abs(gr[key]).max())
         tol = 1e-4 if key.startswith("v") else 1e-5
         assert abs(rich - gr[key][i]) < tol * scale + 1e-9, (i, rich, gr[key][i])
+
+
+def test_grid_index_ids_make_chunking_invisible():
+    """A generated scene split into unequal chunks, each facet taking the id
+    first_index + (grid index) and the Doppler at that index, gives the
+    speckle sum of the whole scene (the streamed entry points' rule): ids
+    that restarted per chunk would not."""
+    g = W.harmony_geometry(96, 512)
+    sea = W.wave_sea(40, 30, 1.0, seed=2)
+    sp = W.Speckle(tau_s=0.02, seed=7, first_index=500)
+    fs_grid = W.speckle_doppler(sea.nx * sea.ny, 7).astype(np.float64)
+    whole = O.generate_facets(sea, 2)
+    ref = O.forward(g, whole, 10, 70, speckle=sp, f_s=fs_grid)
+    chunks = [(0, 0, 25, 12), (25, 0, 15, 12), (0, 12, 40, 18)]
+    parts = [O.generate_facets(sea, 2, *c) for c in chunks]
+    f = {k: np.concatenate([p[k] for p in parts]) for k in parts[0]}
+    gi = np.concatenate([(c[1] + np.arange(c[2] * c[3]) // c[2]) * sea.nx + c[0] +
+                         np.arange(c[2] * c[3]) % c[2] for c in chunks])
+    got = O.forward(g, f, 10, 70, speckle=sp, f_s=fs_grid[gi],
+                    ids=(sp.first_index + gi) & 0xFFFFFFFF)
+    assert O.rel_l2(got, ref) < 1e-13
+    # per-chunk ids (each chunk from first_index) change the speckle
+    bad_ids = np.concatenate([sp.first_index + np.arange(c[2] * c[3]) for c in chunks])
+    bad = O.forward(g, f, 10, 70, speckle=sp, f_s=fs_grid[gi], ids=bad_ids & 0xFFFFFFFF)
+    assert O.rel_l2(bad, ref) > 0.1
