@@ -21,9 +21,10 @@
  *                                      differences of og_forward)
  *   og_chirp, og_waveform[_adjoint]    pinned (numpy FFT convolution, matched
  *                                      filter peak, adjoint identity)
- *   og_philox4x32_10                   bit patterns: parity unpinned (no
- *                                      external known-answer vectors);
- *                                      statistical pins only
+ *   og_philox4x32_10                   pinned bit for bit against rocRAND's
+ *                                      header-only engine (an independent
+ *                                      implementation) on 56 counters and
+ *                                      keys; statistical pins besides
  *   og_generate_facets                 pinned (closed-form moments, dispersion,
  *                                      d(eta)/dt = w, chunk invariance; tiles of
  *                                      eq. 1-2: corner fields, squared weights
