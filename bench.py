@@ -1,27 +1,37 @@
 """Benchmark of the facet-sum hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 5]
 
-A step is one pass of the whole path over the workload's synthetic scene:
-facet generation on the device (Philox + linear waves), the range-binned
-block sort (plan), the fused forward sum and the per-pulse chirp
-convolution.  `value` is whole-job forward throughput in G facet-pulse
-contributions per second (facets x pulses x channels per step / step time),
-with every input generated in HBM inside the step.  Consecutive steps are
-pipelined: step i+1's generation and plan run on a side stream while step
-i's sum runs, and step i's chirp convolution runs on a third stream beside
-step i+1's sum; every step still does all of its work.  A second timed loop of K
-forward+adjoint steps (loss ||raw - T||^2 against a target from a perturbed
-current, chirp adjoint, adjoint sum) gives `fwd_adj`.
+Workload 5 (the default) is the largest single-GPU configuration: a streamed
+scene of 1.28e8 facets in 16 chunks of 8e6, 16384 pulses x 8192 samples x 3
+channels, chirp.  One step is one chunk of it: facet generation on the
+device (Philox + linear waves + current), the range-binned block sort
+(plan), the fused forward sum of every pulse and channel accumulated into
+the resident IQ (3 GiB), and the chirp convolution of a sixteenth of the
+lines, i.e. one sixteenth of the whole scene's forward work.  Steps cycle
+through the chunks.  Workloads 1-4 (``--workload k``) are single scenes:
+one step is the whole scene (generation, plan, sum, chirp).
+
+`value` is forward throughput in G facet-pulse-channel contributions per
+second (contributions per step / step time), every input generated in HBM
+inside the step.  Consecutive steps are pipelined: the generation and plan
+of step i+1 run on a side stream (default priority) while step i's sum runs;
+every step still does all of its work.  A second timed loop of
+forward+adjoint steps gives `fwd_adj`: the forward step, the loss gradient
+and chirp adjoint of the step's share of the lines, and the adjoint sum over
+the step's facets (workload 5: dL/dV of the chunk, loss 1/2 ||raw||^2;
+workloads 1-4: dL/d(z, V, a), loss ||raw - T||^2 against a target from a
+perturbed current).
 
 `roofline` reports the fused forward kernel against the FP32 vector ALU:
 achieved = W_alg slots per contribution x contributions per launch / average
 launch time (HIP events on the launch stream), where a slot is one FP32
 lane-operation of the full-rate FMA pipe and a transcendental costs four;
 peak = 256 CUs x 128 lanes x 2.4 GHz (the 157.3 TFLOP/s FP32 figure counted
-in FMAs).  `cpu_baseline` times the FP64 oracle on a bounded pulse
-subset of the same scene on the host's cores, and `rel_l2_vs_fp64` compares
-those oracle lines with the GPU's.
+in FMAs).  `roofline_adjoint` does the same for the adjoint kernel with its
+own frozen listing.  `cpu_baseline` times the FP64 oracle on a bounded pulse
+subset of the same scene (workload 5: its first chunk) on the host's cores,
+and `rel_l2_vs_fp64` compares those oracle lines with the GPU's.
 """
 import argparse
 import hashlib
@@ -62,8 +72,23 @@ W_ALG_SLOTS_GRID = 144.0 + 2 * 4.0
 # (2 + 2 FMAs), the amplitude times x (4) and the Doppler phase (6): 79 slots.
 MUL64_SLOTS = 2.0
 W_SPK_SLOTS = 10 * (MUL64_SLOTS + 2) + 6 + (4 * 4.0 + 3) + 4 + 4 + 6
+# Adjoint sum, per contribution (elevation factors at block centres): the
+# facet geometry of the forward (44 FP32 operations, 5 transcendentals: the
+# forward listing without taps, weight and deposit), the 8 taps with their
+# derivatives (76: per tap pair 5 + 5 Horner steps for the even and odd parts
+# and their y-derivatives, 8 for the pair and its derivative pair; 4 shared),
+# the two tap sums over the staged g (8 taps x 4 FMAs = 32), a E and B a E
+# (8), the delay and phase terms (6), the range gradient (14), the three
+# components of dL/dX (7), the accumulation into dL/dz and dL/dV (4) and
+# dL/da (6): 197 FP32 operations and 5 transcendentals.  Staged reference
+# and g reads from LDS, loop control and the per-block FP64 stage prologue
+# are overhead, not counted.
+W_ADJ_SLOTS_EL_CONST = 197.0 + 5 * 4.0
+# with every pattern factor per facet: two more direction cosines (8), their
+# two sines and four more products of the pattern (4)
+W_ADJ_SLOTS = W_ADJ_SLOTS_EL_CONST + 12.0 + 2 * 4.0
 PEAK_SLOTS = 256 * 128 * 2.4e9         # FP32 lane-operations per second (157.3 TFLOP/s / 2)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_forward_cfg2_traffic.json")
+PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2405_09938_amd", "csrc", f)
                   for f in ("k_forward.hip", "sim_device.h")]
 
@@ -76,12 +101,19 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def traffic_file(workload_name: str) -> str:
+    return os.path.join(PROFILES, f"k_forward_{workload_name.split('_')[0]}_traffic.json")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", type=int, default=2)
+    ap.add_argument("--workload", type=int, default=5)
+    ap.add_argument("--adj-steps", type=int, default=None,
+                    help="forward+adjoint steps timed (default: steps, at most 8 for the "
+                         "chunked workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--serial", action="store_true",
@@ -122,6 +154,11 @@ def main():
     import workloads as W
 
     wl = W.workload(args.workload)
+    chunked = bool(wl.chunks)
+    if chunked and (args.speckle or args.rx_exact or args.tops or args.patterns):
+        print("the chunked workload runs the plain sum only (no --speckle, --rx-exact, "
+              "--tops, --patterns)", file=sys.stderr)
+        sys.exit(2)
     if args.rx_exact or args.tops or args.patterns:
         from dataclasses import replace as _replace
         g2 = _replace(wl.geometry, rx_exact=args.rx_exact)
@@ -136,55 +173,69 @@ def main():
     hs.load()
     sim = hs.Simulator(geom)
     chirp = geom.chirp_T > 0
-    contrib = wl.contributions
+    C, Np, N = geom.n_channels, geom.n_pulses, geom.n_samples
     stream = torch.cuda.current_stream()
+    n_chunks = len(wl.chunks) if chunked else 1
+    # contributions of one step: a chunk of the chunked workload, else the scene
+    step_facets = (wl.chunks[0][2] * wl.chunks[0][3]) if chunked else wl.n_facets
+    contrib = step_facets * Np * C
+    if chunked:
+        assert all(c[2] * c[3] == step_facets for c in wl.chunks), "chunks of equal size"
 
-    fwd_ev = []
-    streamed = bool(wl.chunks)
-    if args.speckle and streamed:
-        print("--speckle: the streamed workload has no speckle path", file=sys.stderr)
-        sys.exit(2)
     # speckle inputs: one process per facet, Doppler drawn per facet (input,
     # resident in HBM for the whole run)
     spk = W.Speckle(tau_s=W.SPECKLE_TAU_S, seed=wl.seed, first_index=0) if args.speckle else None
     fs_dev = (torch.from_numpy(W.speckle_doppler(wl.n_facets, wl.seed)).to(dev)
               if args.speckle else None)
-    # Consecutive steps are pipelined: the scene generation and plan of step
-    # i + 1 run on a side stream (default priority) while step i's sum runs,
-    # so the plan's host synchronisations do not idle the GPU.  Every step
-    # still does all of its work.
-    side = torch.cuda.Stream(device=dev)
-    # the chirp convolution of step i runs on its own stream, beside step
-    # i+1's sum (the sum of step i+1 writes a fresh IQ buffer)
-    wave = torch.cuda.Stream(device=dev)
+    side = torch.cuda.Stream(device=dev)     # generation and plan of the next step
+    wave = torch.cuda.Stream(device=dev)     # chirp of a single scene beside the next sum
+    pipelined = not args.serial
 
-    def prepare():
+    # resident IQ of the chunked scene: range-compressed (accumulated over the
+    # chunks), raw (chirped) and the loss gradient g_rc
+    if chunked:
+        iq_rc = torch.zeros((C, Np, N), dtype=torch.complex64, device=dev)
+        iq_raw = torch.zeros_like(iq_rc) if chirp else iq_rc
+        g_rc = torch.zeros_like(iq_rc)
+        lines_per_step = (C * Np + n_chunks - 1) // n_chunks
+
+    def line_slice(i):
+        a = (i % n_chunks) * lines_per_step
+        return slice(a, min(a + lines_per_step, C * Np))
+
+    def prepare(i):
+        """Facets and plan of step i (a chunk, or the scene), on the side stream."""
         with torch.cuda.stream(side):
-            f = sim.generate(sea, wl.seed)
+            if chunked:
+                f = sim.generate(sea, wl.seed, *wl.chunks[i % n_chunks])
+            else:
+                f = sim.generate(sea, wl.seed)
             plan = sim.plan(f["x"], f["y"], wl.block_edge)
         for v in f.values():
             v.record_stream(stream)
         return f, plan
 
-    def fwd_step(record=False, prep=None, overlap=False):
+    fwd_ev, adj_ev = [], []
+
+    def fwd_step(i, prep, record=False, overlap=False):
+        f, plan = prep
+        stream.wait_stream(side)
         if record:
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        if streamed:
-            # chunks generated, planned and summed inside the library
-            if record:
-                e0.record(stream)
-            rc = sim.stream_forward(sea, wl.seed, wl.chunks, wl.block_edge)
-            f = plan = None
+            e0.record(stream)
+        if chunked:
+            rc = sim.forward(plan, f, out=iq_rc, accumulate=True)
         else:
-            f, plan = prep if prep is not None else prepare()
-            stream.wait_stream(side)
-            if record:
-                e0.record(stream)
             rc = sim.forward(plan, f, speckle=spk, f_s=fs_dev)
         if record:
             e1.record(stream)
             fwd_ev.append((e0, e1))
-        if chirp and overlap and not streamed:
+        if chunked:
+            s = line_slice(i)
+            if chirp:
+                sim.apply_waveform(iq_rc.view(-1, N)[s], out=iq_raw.view(-1, N)[s])
+            out = iq_raw
+        elif chirp and overlap:
             wave.wait_stream(stream)
             with torch.cuda.stream(wave):
                 out = sim.apply_waveform(rc, out=rc)
@@ -193,27 +244,28 @@ def main():
             out = sim.apply_waveform(rc, out=rc) if chirp else rc
         return f, plan, out
 
-    pipelined = not streamed and not args.serial
-
-    def fwd_steps(n, record=False):
+    def run_steps(n, step_fn, label, start=0):
         res = None
-        nxt = prepare() if pipelined else None
-        for i in range(n):
-            cur, nxt = nxt, None
-            res = fwd_step(record, cur, overlap=pipelined)
-            if pipelined and i + 1 < n:
-                nxt = prepare()
-            if streamed:
+        nxt = prepare(start) if pipelined else None
+        for i in range(start, start + n):
+            cur = nxt if pipelined else prepare(i)
+            nxt = None
+            res = step_fn(i, cur)
+            if pipelined and i + 1 < start + n:
+                nxt = prepare(i + 1)
+            if chunked:
                 torch.cuda.synchronize()
-                print(f"  forward step {i} done", flush=True)
+                print(f"  {label} step {i} done", flush=True)
         return res
 
-    print(f"workload {wl.name}: {contrib:.3e} contributions per step", flush=True)
+    print(f"workload {wl.name}: {contrib:.3e} contributions per step"
+          + (f" (one chunk of {n_chunks})" if chunked else ""), flush=True)
     if args.warmup:
-        fwd_steps(args.warmup)
+        run_steps(args.warmup, lambda i, p: fwd_step(i, p, overlap=pipelined), "warmup")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    f, plan, out = fwd_steps(args.steps, record=True)
+    f, plan, out = run_steps(args.steps, lambda i, p: fwd_step(i, p, True, overlap=pipelined),
+                             "forward", start=args.warmup)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     step_s = (t1 - t0) / args.steps
@@ -221,17 +273,27 @@ def main():
     kern_ms = sum(a.elapsed_time(b) for a, b in fwd_ev) / len(fwd_ev)
     print(f"forward step {step_s * 1e3:.3f} ms, {value:.2f} G/s; forward sum "
           f"{kern_ms:.3f} ms avg", flush=True)
-    gpu_iq = out
+    el_const = plan.el_const
 
     fwd_adj = None
+    adj_ms = None
     if not args.no_adjoint:
-        if streamed:
-            # loss 1/2 ||raw||^2: g = raw (the adjoint's cost does not depend
-            # on g); adjoint w.r.t. the facet velocities, chunk by chunk
-            def fa_step(prep=None, k=0):
-                _, _, o = fwd_step()
-                g = sim.apply_waveform(o, adjoint=True) if chirp else o
-                return sim.stream_backward(sea, wl.seed, wl.chunks, g, wl.block_edge)
+        if chunked:
+            def fa_step(i, prep):
+                f2, plan2, _ = fwd_step(i, prep)
+                s = line_slice(i)
+                # loss 1/2 ||raw||^2: g_raw = raw; chirp adjoint of the step's lines
+                if chirp:
+                    sim.apply_waveform(iq_raw.view(-1, N)[s], out=g_rc.view(-1, N)[s],
+                                       adjoint=True)
+                else:
+                    g_rc.view(-1, N)[s].copy_(iq_raw.view(-1, N)[s])
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                gr = sim.backward(plan2, f2, g_rc, need=("vx", "vy", "vz"))
+                e1.record(stream)
+                adj_ev.append((e0, e1))
+                return gr
         else:
             # target: same scene, velocities perturbed by a 0.1 m/s current
             psi = W.sea_draws(wl.seed)["perturb_heading"]
@@ -243,46 +305,37 @@ def main():
                 if chirp:
                     tgt = sim.apply_waveform(tgt, out=tgt)
 
-            def fa_step(prep=None, k=0):
-                f2, plan2, o = fwd_step(prep=prep)
+            def fa_step(i, prep):
+                f2, plan2, o = fwd_step(i, prep)
                 g = 2.0 * (o - tgt)
                 if chirp:
                     g = sim.apply_waveform(g, out=g, adjoint=True)
-                return sim.backward(plan2, f2, g, speckle=spk, f_s=fs_dev)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                gr = sim.backward(plan2, f2, g, speckle=spk, f_s=fs_dev)
+                e1.record(stream)
+                adj_ev.append((e0, e1))
+                return gr
 
-        def fa_steps(n):
-            nxt = prepare() if pipelined else None
-            for i in range(n):
-                cur, nxt = nxt, None
-                fa_step(cur, i)
-                if pipelined and i + 1 < n:
-                    nxt = prepare()
-                if streamed:
-                    torch.cuda.synchronize()
-                    print(f"  forward+adjoint step {i} done", flush=True)
-
+        n_adj = args.adj_steps
+        if n_adj is None:
+            n_adj = min(args.steps, 8) if chunked else args.steps
         if args.warmup:
-            fa_steps(args.warmup)
+            run_steps(min(args.warmup, 2), fa_step, "forward+adjoint warmup")
+        adj_ev.clear()
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        fa_steps(args.steps)
+        run_steps(n_adj, fa_step, "forward+adjoint")
         torch.cuda.synchronize()
         t3 = time.perf_counter()
-        fa_s = (t3 - t2) / args.steps
-        fwd_adj = {"value": contrib / fa_s / 1e9, "unit": "G contributions/s",
-                   "ms_per_step": fa_s * 1e3}
-        print(f"forward+adjoint step {fa_s * 1e3:.3f} ms, {fwd_adj['value']:.2f} G/s",
-              flush=True)
+        fa_s = (t3 - t2) / n_adj
+        adj_ms = sum(a.elapsed_time(b) for a, b in adj_ev) / len(adj_ev)
+        fwd_adj = {"value": round(contrib / fa_s / 1e9, 3), "unit": "G contributions/s",
+                   "ms_per_step": round(fa_s * 1e3, 4), "steps": n_adj,
+                   "adjoint_sum_ms": round(adj_ms, 4)}
+        print(f"forward+adjoint step {fa_s * 1e3:.3f} ms, {fwd_adj['value']:.2f} G/s; "
+              f"adjoint sum {adj_ms:.3f} ms avg", flush=True)
 
-    if streamed:
-        # evaluation mode of the first chunk's plan (the library plans each
-        # chunk the same way inside the streamed call)
-        c0 = wl.chunks[0]
-        f0 = sim.generate(sea, wl.seed, *c0)
-        el_const = sim.plan(f0["x"], f0["y"], wl.block_edge).el_const
-        del f0
-    else:
-        el_const = plan.el_const
     if args.patterns:
         el_const = False          # gridded patterns are evaluated per facet
         w_alg = W_ALG_SLOTS_GRID
@@ -294,8 +347,9 @@ def main():
     peak = PEAK_SLOTS / 1e12
     traffic = None
     valu = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as fh:
+    tf = traffic_file(wl.name)
+    if os.path.exists(tf):
+        with open(tf) as fh:
             tr = json.load(fh)
         if (tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == wl.name
                 and bool(tr.get("speckle", False)) == args.speckle and not args.rx_exact
@@ -312,17 +366,24 @@ def main():
         # kernel source) against the FP32 issue peak of two per CU per cycle
         # at 2.4 GHz
         roofline["valu_issue_frac"] = round(valu / (256 * 2 * 2.4e9 * kern_ms * 1e-3), 4)
+    roofline_adj = None
+    if adj_ms is not None and not args.speckle and not args.patterns and not args.tops:
+        w_adj = W_ADJ_SLOTS_EL_CONST if el_const else W_ADJ_SLOTS
+        a_adj = w_adj * contrib / (adj_ms * 1e-3) / 1e12
+        roofline_adj = {"bound": "alu", "achieved": round(a_adj, 3), "peak": round(peak, 3),
+                        "unit": "Tslot/s", "frac": round(a_adj / peak, 4), "traffic": None,
+                        "kernel": "k_adjoint", "w_alg_slots_per_contribution": w_adj,
+                        "contributions_per_launch": contrib,
+                        "avg_launch_ms": round(adj_ms, 4)}
 
     cpu = None
     rel = None
     if not args.no_cpu_baseline:
         import oracle as O
-        # bounded sample: the oracle's own scene (same seed and sea draws),
-        # all facets, pulses taken from the middle of the dwell until the
-        # time budget is spent
-        if streamed:
-            # the sample is the scene's first chunk; for the comparison the GPU
-            # recomputes that chunk's lines over the same pulses
+        # bounded sample: the oracle's own scene (same seed and sea draws;
+        # workload 5: its first chunk), all facets, pulses from the middle of
+        # the dwell until the time budget is spent
+        if chunked:
             sub = wl.chunks[0]
             fo = O.as_float32(O.generate_facets(sea, wl.seed, *sub))
             n_fac = sub[2] * sub[3]
@@ -330,12 +391,12 @@ def main():
             fo = O.as_float32(O.generate_facets(sea, wl.seed))
             n_fac = wl.n_facets
         fo = {k: v.astype(np.float64) for k, v in fo.items()}
-        p_mid = geom.n_pulses // 2
+        p_mid = Np // 2
         chunk = 4
         done = 0
         t_cpu = 0.0
         rows = []
-        while t_cpu < args.cpu_seconds and done + chunk <= geom.n_pulses // 2:
+        while t_cpu < args.cpu_seconds and done + chunk <= Np // 2:
             p0 = p_mid + done
             ta = time.perf_counter()
             if args.speckle:
@@ -347,16 +408,19 @@ def main():
             t_cpu += time.perf_counter() - ta
             rows.append((p0, line))
             done += chunk
-        n_contrib = n_fac * done * geom.n_channels
+        n_contrib = n_fac * done * C
         cpu = {"value": n_contrib / t_cpu / 1e9, "unit": "G contributions/s",
                "cores": O.num_threads(), "kind": "oracle",
                "sample": f"{n_fac} facets x {done} pulses (from pulse {p_mid}) x "
-                         f"{geom.n_channels} ch, FP64 direct sum + FFT waveform, {t_cpu:.1f} s"}
-        if streamed:
+                         f"{C} ch, FP64 direct sum + FFT waveform, {t_cpu:.1f} s"}
+        if chunked:
+            # the GPU recomputes the first chunk's lines over the same pulses
             gpu_iq = sim.stream_forward(sea, wl.seed, [wl.chunks[0]], wl.block_edge, p_mid, done)
             if chirp:
                 gpu_iq = sim.apply_waveform(gpu_iq, out=gpu_iq)
             rows = [(p0 - p_mid, line) for p0, line in rows]
+        else:
+            gpu_iq = out
         got = gpu_iq.cpu().numpy()
         num = den = 0.0
         for p0, line in rows:
@@ -379,11 +443,16 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": ("synthetic (on-device Philox facets, 64-component linear wave sea)"
+        "data": ("synthetic (on-device Philox facets, 64-component linear wave sea"
+                 + (" + current)" if sea.mode == 1 and any(sea.current) else ")")
                  if sea.mode == 1 else "synthetic (on-device Philox facets, flat sea)"),
-        "config": {"workload": wl.name, "facets": wl.n_facets, "pulses": geom.n_pulses,
-                   "samples": geom.n_samples, "channels": geom.n_channels, "chirp": chirp,
-                   "block_edge_m": wl.block_edge, "chunks": len(wl.chunks) or 1,
+        "config": {"workload": wl.name, "facets_per_step": step_facets,
+                   "scene_facets": wl.n_facets, "chunks": n_chunks,
+                   "step": ("one chunk: generate, plan, sum all pulses and channels into "
+                            "the resident IQ, chirp 1/16 of the lines") if chunked
+                   else "whole scene: generate, plan, sum, chirp",
+                   "pulses": Np, "samples": N, "channels": C, "chirp": chirp,
+                   "block_edge_m": wl.block_edge,
                    "speckle": ({"tau_s": W.SPECKLE_TAU_S, "f_s_hz": f"+-{W.SPECKLE_FD_HZ}"}
                                if args.speckle else None),
                    "rx_at_facet_echo_time": args.rx_exact,
@@ -392,6 +461,7 @@ def main():
         "fwd_adj": fwd_adj,
         "rel_l2_vs_fp64": rel,
         "roofline": roofline,
+        "roofline_adjoint": roofline_adj,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)

@@ -89,6 +89,64 @@ def test_streamed_workload5_pulse_subset(hs):
     assert e < IQ_TOL
 
 
+IQ_BUDGET = 5e-5
+
+
+@pytest.mark.parametrize("chunk_idx", [0, 15])
+def test_streamed_workload5_dwell_ends(hs, chunk_idx):
+    """Workload 5 at its own geometry where its precision is tightest: the
+    first and last pulses of the 9.6 s dwell (|t_p| = 4.82 s, so each facet
+    has drifted by V t_p from its position at t = 0), all 3 channels, on the
+    first chunk and on the far-corner chunk of the 16 km x 8 km scene."""
+    wl = W.workload(5)
+    g = wl.geometry
+    c = wl.chunks[chunk_idx]
+    sim = hs.Simulator(g)
+    say(f"case: workload 5, chunk {chunk_idx} {c}, dwell-end pulses, 3 channels")
+    fo = oracle_chunk_facets(wl.sea, wl.seed, [c])
+    for p0 in (0, g.n_pulses - 2):
+        rc = sim.stream_forward(wl.sea, wl.seed, [c], wl.block_edge, p0, 2).cpu().numpy()
+        ref = O.forward(g, fo, p0, 2)
+        e = O.rel_l2(rc, ref)
+        say(f"chunk {chunk_idx}, pulses {p0}..{p0 + 1}: rel-L2 {e:.3e}")
+        assert e < IQ_TOL and e < IQ_BUDGET
+        for ch in range(g.n_channels):
+            ec = O.rel_l2(rc[ch], ref[ch])
+            say(f"  channel {ch}: rel-L2 {ec:.3e}")
+            assert ec < IQ_TOL
+
+
+def test_streamed_workload5_velocity_adjoint_dwell_ends(hs):
+    """The streamed velocity adjoint of workload 5 at its own geometry:
+    32 pulses at each end of the dwell, all 3 channels, on a whole 8e6-facet
+    chunk; dL/dV of 256 seed-drawn facets of the chunk against the FP64
+    oracle adjoint of those facets alone (a facet's gradient depends only on
+    itself and g)."""
+    import torch
+    wl = W.workload(5)
+    g = wl.geometry
+    sim = hs.Simulator(g)
+    rng = np.random.default_rng(55)
+    npl = 32
+    for chunk_idx, p0 in ((0, g.n_pulses - npl), (15, 0)):
+        c = wl.chunks[chunk_idx]
+        say(f"case: workload 5 adjoint, chunk {chunk_idx} {c}, pulses [{p0}, {p0 + npl})")
+        gi = (rng.standard_normal((g.n_channels, npl, g.n_samples))
+              + 1j * rng.standard_normal((g.n_channels, npl, g.n_samples))).astype(np.complex64)
+        gr = sim.stream_backward(wl.sea, wl.seed, [c], torch.from_numpy(gi).cuda(),
+                                 wl.block_edge, p0, npl)
+        sel = np.sort(rng.choice(c[2] * c[3], 256, replace=False))
+        parts = [O.generate_facets(wl.sea, wl.seed, c[0] + int(s) % c[2], c[1] + int(s) // c[2],
+                                   1, 1) for s in sel]
+        fo = {k: np.concatenate([q[k] for q in parts]).astype(np.float32).astype(np.float64)
+              for k in parts[0]}
+        ref = O.adjoint(g, fo, gi.astype(np.complex128), p0, npl)
+        for k in ("vx", "vy", "vz"):
+            e = O.rel_l2(gr[k].cpu().numpy()[sel], ref[k])
+            say(f"  dL/d{k}: rel-L2 {e:.3e}")
+            assert e < GRAD_TOL
+
+
 def grid_index(sea, chunks):
     """Grid index (iy * nx + ix) of every facet, chunk after chunk, each chunk
     row-major in its sub-rectangle."""

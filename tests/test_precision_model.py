@@ -91,3 +91,43 @@ def test_single_reference_negative_control():
     e = phase_error_rms(g, x0, v, centres, (0, 1023, 2047))
     print(f"one reference for a 1 km scene: rms phase error {e:.2e} rad")
     assert e > 5e-4
+
+
+def test_block_references_at_the_streamed_dwell_ends():
+    """The streamed 16384-pulse workload: a 9.6 s dwell (|t_p| up to 4.82 s)
+    over a scene reaching 8 km along-track and 4 km across, facets moving
+    with wave orbital velocities plus a 0.5 m/s current, so the drift V t_p
+    stretches the offsets from the block centres to ~5-10 m at the dwell ends
+    and their float32 rounding grows with them (about ulp(|e|) of path per
+    component).  With the orbital velocity of the workload's sea (k^-4
+    spectrum scaled to Hs = 2 m over wavelengths 5-250 m: ~0.21 m/s rms per
+    horizontal axis) the model gives ~3.5e-5 rad at the dwell ends, in the
+    far corners as at the centre (2.3e-5 mid-dwell), inside the 5e-5 budget
+    guard; with twice that velocity it stays below the 1e-4 target."""
+    g = W.harmony_geometry(16384, 8192, receivers="A", n_pc=3)
+    rng = np.random.default_rng(5)
+    edge = 8.0
+    psi = 0.7
+    # orbital velocity rms per axis of the workload's sea: sum A^2 omega^2 / 2
+    # over its 64 components, a half on each horizontal axis
+    k = np.exp(np.linspace(np.log(W.SEA_K_MIN), np.log(W.SEA_K_MAX), W.SEA_N_COMP))
+    dl = math.log(W.SEA_K_MAX / W.SEA_K_MIN) / (W.SEA_N_COMP - 1)
+    a2 = 2.0 * k ** W.SEA_SLOPE * k * dl
+    a2 *= (W.SEA_HS / 4.0) ** 2 / np.sum(0.5 * a2)
+    sv = math.sqrt(np.sum(0.5 * a2 * W.SEA_G * k) / 2.0)
+    print(f"orbital velocity rms per horizontal axis {sv:.3f} m/s")
+    assert 0.2 < sv < 0.5
+    for scale, bound in ((1.0, 5e-5), (2.0, 1e-4)):
+        for corner in ((0.0, 0.0), (7500.0, 3500.0), (-7500.0, -3500.0)):
+            n = 128 * 128
+            x = corner[0] + rng.uniform(-400, 400, n)
+            y = corner[1] + rng.uniform(-400, 400, n)
+            x0 = np.stack([x, y, rng.normal(0, 0.5, n)], 1)
+            v = rng.normal(0, scale * sv, (n, 3))
+            v[:, 0] += 0.5 * math.cos(psi)
+            v[:, 1] += 0.5 * math.sin(psi)
+            centres = np.stack([(np.floor(x / edge) + 0.5) * edge,
+                                (np.floor(y / edge) + 0.5) * edge, np.zeros(n)], 1)
+            e = phase_error_rms(g, x0, v, centres, (0, 16383))
+            print(f"velocity x{scale}, scene at {corner}: dwell-end rms phase error {e:.2e} rad")
+            assert 1e-6 < e < bound
