@@ -206,13 +206,14 @@ def main():
     def prepare(i):
         """Facets and plan of step i (a chunk, or the scene), on the side stream."""
         with torch.cuda.stream(side):
-            if chunked:
-                f = sim.generate(sea, wl.seed, *wl.chunks[i % n_chunks])
-            else:
-                f = sim.generate(sea, wl.seed)
-            plan = sim.plan(f["x"], f["y"], wl.block_edge)
+            sub = wl.chunks[i % n_chunks] if chunked else (0, 0, sea.nx, sea.ny)
+            f = sim.generate(sea, wl.seed, *sub)
+            plan = sim.plan(f["x"], f["y"], wl.block_edge, box=sim.chunk_box(sea, *sub),
+                            speckle=args.speckle)
+        # the sum reads the facets and the plan's workspace on the main stream
         for v in f.values():
             v.record_stream(stream)
+        plan.workspace.record_stream(stream)
         return f, plan
 
     fwd_ev, adj_ev = [], []

@@ -44,12 +44,22 @@
  *  - Return value: SIM_OK (0) or a negative SIM_E* code; arguments are
  *    validated before anything is written or launched.  sim_last_error()
  *    returns a thread-local message describing the last failure.
- *  - Calls that use the same handle or plan from several host threads at
- *    once, or that overlap on the device through one plan's scratch (the
- *    sorted facet copy), race; serialise them (one stream per plan).
+ *  - Device memory: the caller owns every buffer, workspaces included
+ *    (sim_workspace_size, sim_sea_table_size, sim_stream_workspace_size give
+ *    their sizes; a workspace is 256-byte aligned device memory).  The
+ *    library itself holds only the handle's constant tables (per-pulse
+ *    geometry, waveform spectrum, pattern grids), uploaded once by
+ *    sim_device_init.  No other entry point allocates device memory or waits
+ *    for the device, except the queries marked "synchronises".
+ *  - Calls that use the same handle from several host threads at once, or
+ *    that overlap on the device through one workspace (a plan's sorted facet
+ *    copy is rewritten by every sum over the plan), race; serialise them
+ *    (one stream per plan or workspace).
  */
 #ifndef HEEPS_SIM_H
 #define HEEPS_SIM_H
+
+#include <stddef.h>
 
 #ifdef __cplusplus
 extern "C" {
@@ -66,7 +76,17 @@ extern "C" {
 #define SIM_MAX_CHANNELS 16
 
 typedef struct sim_handle sim_handle;   /* opaque, owned by the library */
-typedef struct sim_plan sim_plan;       /* opaque, owned by the library */
+typedef struct sim_plan sim_plan;       /* opaque host descriptor, owned by the library;
+                                           its device buffers are the caller's workspace */
+
+/* Plan flag: the workspace also holds the intra-facet speckle records and
+ * anchors (needed by sim_forward_speckle / sim_backward_speckle). */
+#define SIM_PLAN_SPECKLE 1
+
+/* Scene rectangle (metres) that every facet position (x, y) of a plan lies in. */
+typedef struct {
+    double x_min, x_max, y_min, y_max;
+} sim_box;
 
 /* Straight-line trajectory: position p0 (m) at t = 0, constant velocity v (m/s). */
 typedef struct {
@@ -213,18 +233,27 @@ typedef struct {
  * Create a simulator: validates `cfg` and derives in FP64 on the host the
  * per-(channel, pulse) geometry (t_p, P_tx, tau_ref, P_rx), antenna frames,
  * the interpolator's polynomial form and, if chirp_T > 0, the waveform
- * spectrum.  Host only: the tables are uploaded by the first call that uses
- * the GPU, to the device current at that time, and every later call on the
- * handle must run with that device current.
+ * spectrum.  Host only (a handle may be created without a GPU).
  * out: receives the handle (freed by sim_destroy).
  * Errors: SIM_EINVAL, SIM_ENOMEM, SIM_EUNSUPPORTED (antenna width below
  * kappa/500 rad).
  */
 int sim_create(const sim_config *cfg, sim_handle **out);
 
-/* Release a handle and its device tables.  NULL is ignored.  If plans of
- * the handle are still alive, the handle is released when the last of them
- * is destroyed (sim_plan_destroy). */
+/*
+ * Upload the handle's constant tables (per-pulse geometry, waveform spectrum
+ * and twiddles, pattern grids) to the current HIP device: the one set-up
+ * step that allocates device memory and synchronises.  Every later call on
+ * the handle must run with that device current.  A device call made before
+ * it performs it implicitly.  Repeated calls do nothing.
+ * Errors: SIM_EINVAL (NULL, or another device current than the first call's),
+ * SIM_ENOMEM, SIM_EHIP.
+ */
+int sim_device_init(sim_handle *h);
+
+/* Release a handle and its device tables (waits for the device).  NULL is
+ * ignored.  Plans of the handle must not be used afterwards (destroying them
+ * is still allowed). */
 void sim_destroy(sim_handle *h);
 
 /* Thread-local text of the last error ("" if none). */
@@ -243,34 +272,50 @@ int sim_pulse_info(const sim_handle *h, int ch, int p0, int np, double *t,
 int sim_waveform_info(const sim_handle *h, int *chirp_len, int *fft_len);
 
 /*
- * Plan a facet set (the range-binned block sort): facets are binned into
- * spatial blocks (cells of block_edge x block_edge metres on a lattice of
- * the horizontal plane, at most 64 facets per block; each block carries an
- * exact float32 centre used as its FP64 reference point), blocks are grouped
- * into patches of cells that share a range window, and the permutation is
- * kept in plan-owned device memory.  Depends only on x, y (device float32
- * [n]).  block_edge in (0, 64] metres; 8 suits 1 m grids.  Synchronises the
- * stream (it reads back the bounding box and block count).  Its temporary
- * device buffers are kept by the handle and reused by later calls (at most
- * 16 of them, released by sim_destroy); calls on one handle must not run
- * concurrently.
- * Errors: SIM_EINVAL, SIM_ENOMEM, SIM_EHIP, SIM_EUNSUPPORTED (lattice larger
- * than 2^28 cells).
+ * Bytes of device workspace for the plan of up to n facets whose positions
+ * lie in `box` (host), with lattice cells of block_edge metres and the given
+ * SIM_PLAN_* flags (see sim_plan_create).  Host only.
+ * Errors: SIM_EINVAL (NULL handle or bytes, n outside [1, 2^31 - 64),
+ * block_edge outside (0, 64], box not finite or empty in a direction,
+ * unknown flags), SIM_EUNSUPPORTED (lattice larger than 2^28 cells).
+ */
+int sim_workspace_size(const sim_handle *h, long long n, const sim_box *box, double block_edge,
+                       int flags, size_t *bytes);
+
+/*
+ * Plan a facet set (the range-binned block sort of the sum, eq. 17's range
+ * slices gathered per tile as in Sec. IV.A/B): facets are binned into
+ * spatial blocks (cells of block_edge x block_edge metres of a lattice
+ * covering `box`, at most 64 facets per block; each block carries an exact
+ * float32 centre used as its FP64 reference point), blocks are grouped into
+ * patches of cells that share a range window, and the permutation, blocks
+ * and patch offsets are written into `workspace` (caller-owned device
+ * memory, 256-byte aligned, at least sim_workspace_size bytes; it must stay
+ * allocated and untouched while the plan is used).  Depends only on x, y
+ * (device float32 [n]).  block_edge in (0, 64] metres; 8 suits 1 m grids.
+ * flags: 0, or SIM_PLAN_SPECKLE to make room for the intra-facet speckle.
+ * Asynchronous on `stream`: no allocation and no wait.  A facet outside
+ * `box` is placed in the nearest edge cell: it is still summed, but its
+ * offset from that block's centre may exceed what the FP32 precision scheme
+ * is bounded for; sim_plan_info counts such facets.  out receives a host
+ * descriptor (freed by sim_plan_destroy).
+ * Errors: as sim_workspace_size, and SIM_EINVAL for NULL x, y or out, a
+ * NULL, misaligned or too small workspace; SIM_EHIP.
  */
 int sim_plan_create(sim_handle *h, const float *x, const float *y, long long n,
-                    double block_edge, void *stream, sim_plan **out);
+                    const sim_box *box, double block_edge, int flags, void *workspace,
+                    size_t workspace_bytes, void *stream, sim_plan **out);
 
-/* Release a plan.  NULL is ignored.  Its device buffers go back to the
- * handle, which reuses them for later plans: the stream of a later
- * sim_plan_create waits, on the device, for the last work of this plan on
- * every stream that used it (events recorded by each call), so destroying a
- * plan does not synchronise and never lets a later plan overwrite data a
- * pending kernel still reads.  At most 16 buffers are kept. */
+/* Release a plan's host descriptor.  NULL is ignored.  Touches no device
+ * memory: the workspace stays the caller's. */
 void sim_plan_destroy(sim_plan *plan);
 
-/* Host outputs: number of facets, blocks and patches of a plan. */
+/* Host outputs: number of facets, blocks, patches and facets outside the
+ * plan's box.  n_blocks and n_outside are read back from the device:
+ * synchronises the stream the plan was created on (NULL pointers skip
+ * them, and then nothing waits). */
 int sim_plan_info(const sim_plan *plan, long long *n_facets, long long *n_blocks,
-                  long long *n_patches);
+                  long long *n_patches, long long *n_outside);
 
 /*
  * Host outputs: the plan's evaluation mode of the antenna elevation factors
@@ -286,26 +331,42 @@ int sim_plan_info(const sim_plan *plan, long long *n_facets, long long *n_blocks
  */
 int sim_plan_mode(const sim_plan *plan, int *el_const, double *el_bound);
 
+/* Bytes of device workspace sim_generate_facets needs for `sea` (its wave
+ * component table; 0 for a flat sea).  Host only.  Errors: SIM_EINVAL. */
+int sim_sea_table_size(const sim_sea *sea, size_t *bytes);
+
+/* Host output: a rectangle holding every facet sim_generate_facets makes for
+ * the grid sub-rectangle [ix0, ix0+cnx) x [iy0, iy0+cny) of `sea` (cell
+ * centres widened by the largest Choppy Wave Model displacement and a
+ * rounding margin): the box to plan such facets with.  Host only.
+ * Errors: SIM_EINVAL (empty or outside sub-rectangle, bad sea). */
+int sim_chunk_box(const sim_sea *sea, int ix0, int iy0, int cnx, int cny, sim_box *box);
+
 /*
  * Generate facets of the grid sub-rectangle [ix0, ix0+cnx) x [iy0, iy0+cny)
  * of `sea` (row-major in the sub-rectangle).  Random draws use Philox4x32-10
  * keyed by `seed` with the global grid index as counter, so any chunking of
- * the grid yields the same facets.  out->n must equal cnx*cny.
+ * the grid yields the same facets.  out->n must equal cnx*cny.  The sea's
+ * wave table is written into `workspace` (device, 256-byte aligned, at least
+ * sim_sea_table_size bytes; may be NULL for a flat sea) through the kernel
+ * arguments of small copy launches: asynchronous on `stream`, no allocation,
+ * no wait.  The workspace must stay allocated until the generation has run.
  * Errors: SIM_EINVAL (NULL arguments, sub-rectangle outside the grid, bad
  * sea description: unknown mode, missing arrays, bad spectrum, a tile
- * lattice that does not cover the grid, negative heights), checked before
- * any device work; SIM_EHIP.
+ * lattice that does not cover the grid, negative heights; NULL, misaligned
+ * or too small workspace), checked before any device work; SIM_EHIP.
  */
 int sim_generate_facets(sim_handle *h, const sim_sea *sea, unsigned long long seed,
                         int ix0, int iy0, int cnx, int cny, const sim_facets_out *out,
-                        void *stream);
+                        void *workspace, size_t workspace_bytes, void *stream);
 
 /*
  * Forward facet sum (eq. 3/16 summed into range slices, eq. 17) for pulses
  * [p0, p0+np) of every channel, into iq_rc (device complex64
  * [n_channels][np][N]).  accumulate = 0 overwrites iq_rc, 1 adds to it.
  * `facets` must be the facet set `plan` was made from (same n, same x, y);
- * z, V and a may change between calls.
+ * z, V and a may change between calls.  Rewrites the plan's sorted facet
+ * copy in its workspace; asynchronous on `stream`, no allocation, no wait.
  */
 int sim_forward(sim_handle *h, sim_plan *plan, const sim_facets *facets, int p0,
                 int np, float *iq_rc, int accumulate, void *stream);
@@ -334,10 +395,11 @@ typedef struct {
 
 /*
  * sim_forward with the intra-facet speckle `speckle` (same arguments
- * otherwise).  The plan keeps speckle buffers of (n + 1) * 16 *
- * (ceil(n_pulses / 64) + 1) bytes from its first speckle call on.
+ * otherwise).  The plan must have been made with SIM_PLAN_SPECKLE: its
+ * workspace then holds (n + 1) * 8 bytes of speckle records and
+ * (n + 1) * 16 * (ceil(n_pulses / 64) + 1) bytes of anchors.
  * Errors as sim_forward, and SIM_EINVAL for a NULL speckle, tau_s <= 0 or NaN,
- * or first_index < 0.
+ * first_index < 0, or a plan without SIM_PLAN_SPECKLE.
  */
 int sim_forward_speckle(sim_handle *h, sim_plan *plan, const sim_facets *facets,
                         const sim_speckle *speckle, int p0, int np, float *iq_rc,
@@ -377,30 +439,45 @@ int sim_backward_speckle(sim_handle *h, sim_plan *plan, const sim_facets *facets
                          const sim_facet_grads *grads, int accumulate, void *stream);
 
 /*
+ * Bytes of device workspace of the streamed calls below for the given sea,
+ * chunks and block_edge (flags: SIM_PLAN_SPECKLE for the speckle variants):
+ * the sea table, the facets of the largest chunk (32 bytes per facet) and
+ * the largest chunk's plan (sim_workspace_size over sim_chunk_box).  Host
+ * only.  Errors as sim_workspace_size and sim_chunk_box.
+ */
+int sim_stream_workspace_size(const sim_handle *h, const sim_sea *sea, const int *chunks,
+                              int n_chunks, double block_edge, int flags, size_t *bytes);
+
+/*
  * Streamed forward over a large generated scene (the paper processes the scene
  * as a sequence of tile batches on the GPU, Sec. IV.B, and generates it where
  * and when it is sensed, Sec. II.B): for each grid chunk k, given host
  * chunks[4k..4k+3] = (ix0, iy0, cnx, cny), the library generates the chunk's
- * facets (as sim_generate_facets), plans them with `block_edge` (as
- * sim_plan_create) and adds their sum for pulses [p0, p0+np) into iq_rc
- * (device complex64 [n_channels][np][N]); accumulate = 0 clears iq_rc first.
- * Facets live only in a library workspace of one chunk.  Synchronises the
- * stream once per chunk (planning).
+ * facets (as sim_generate_facets), plans them with `block_edge` over their
+ * sim_chunk_box (as sim_plan_create) and adds their sum for pulses
+ * [p0, p0+np) into iq_rc (device complex64 [n_channels][np][N]);
+ * accumulate = 0 clears iq_rc first.  Facets and plans live in `workspace`
+ * (caller-owned device memory, 256-byte aligned, at least
+ * sim_stream_workspace_size(..., flags = 0) bytes), reused chunk after chunk
+ * in stream order: asynchronous on `stream`, no allocation, no wait.
  */
 int sim_stream_forward(sim_handle *h, const sim_sea *sea, unsigned long long seed,
                        const int *chunks, int n_chunks, double block_edge, int p0, int np,
-                       float *iq_rc, int accumulate, void *stream);
+                       float *iq_rc, int accumulate, void *workspace, size_t workspace_bytes,
+                       void *stream);
 
 /*
  * Adjoint of sim_stream_forward with respect to the facet velocities: for
  * each chunk the facets are regenerated and replanned (geometry recomputed,
  * nothing stored), and dL/dvx, dL/dvy, dL/dvz are written (device float32,
  * chunk after chunk, each chunk row-major in its sub-rectangle; total length
- * sum of cnx*cny).  NULL outputs are skipped.  g_rc as in sim_backward.
+ * sum of cnx*cny).  NULL outputs are skipped.  g_rc as in sim_backward;
+ * workspace as sim_stream_forward.
  */
 int sim_stream_backward(sim_handle *h, const sim_sea *sea, unsigned long long seed,
                         const int *chunks, int n_chunks, double block_edge, int p0, int np,
-                        const float *g_rc, float *dvx, float *dvy, float *dvz, void *stream);
+                        const float *g_rc, float *dvx, float *dvy, float *dvz, void *workspace,
+                        size_t workspace_bytes, void *stream);
 
 /*
  * sim_stream_forward with the intra-facet speckle (Sec. III.A eq. 7 and
@@ -408,20 +485,24 @@ int sim_stream_backward(sim_handle *h, const sim_sea *sea, unsigned long long se
  * point (ix, iy) takes the id speckle->first_index + iy * nx + ix (nx =
  * sea->nx), whatever chunk it falls in, and speckle->f_s, if not NULL, is
  * indexed the same way (device float32 [sea->nx * sea->ny], Hz).  So any
- * split of the grid into chunks gives the speckle of the whole scene.
+ * split of the grid into chunks gives the speckle of the whole scene.  The
+ * workspace is sized with flags = SIM_PLAN_SPECKLE.
  * Errors as sim_stream_forward and sim_forward_speckle.
  */
 int sim_stream_forward_speckle(sim_handle *h, const sim_sea *sea, unsigned long long seed,
                                const int *chunks, int n_chunks, double block_edge,
                                const sim_speckle *speckle, int p0, int np, float *iq_rc,
-                               int accumulate, void *stream);
+                               int accumulate, void *workspace, size_t workspace_bytes,
+                               void *stream);
 
 /* Adjoint of sim_stream_forward_speckle with respect to the facet velocities
- * (outputs as sim_stream_backward, speckle as sim_stream_forward_speckle). */
+ * (outputs as sim_stream_backward, speckle and workspace as
+ * sim_stream_forward_speckle). */
 int sim_stream_backward_speckle(sim_handle *h, const sim_sea *sea, unsigned long long seed,
                                 const int *chunks, int n_chunks, double block_edge,
                                 const sim_speckle *speckle, int p0, int np, const float *g_rc,
-                                float *dvx, float *dvy, float *dvz, void *stream);
+                                float *dvx, float *dvy, float *dvz, void *workspace,
+                                size_t workspace_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -86,14 +86,23 @@ class SimSea(ctypes.Structure):
     ]
 
 
+class SimBox(ctypes.Structure):
+    _fields_ = [("x_min", ctypes.c_double), ("x_max", ctypes.c_double),
+                ("y_min", ctypes.c_double), ("y_max", ctypes.c_double)]
+
+
+SIM_PLAN_SPECKLE = 1
+
+
 class SimSpeckle(ctypes.Structure):
     _fields_ = [("tau_s", ctypes.c_double), ("seed", ctypes.c_ulonglong),
                 ("first_index", ctypes.c_longlong), ("f_s", _fp)]
 
 
-EXPORTS = ("sim_create", "sim_destroy", "sim_last_error", "sim_pulse_info",
-           "sim_waveform_info", "sim_plan_create", "sim_plan_destroy", "sim_plan_info",
-           "sim_plan_mode",
+EXPORTS = ("sim_create", "sim_destroy", "sim_last_error", "sim_device_init", "sim_pulse_info",
+           "sim_waveform_info", "sim_workspace_size", "sim_plan_create", "sim_plan_destroy",
+           "sim_plan_info", "sim_plan_mode", "sim_sea_table_size", "sim_chunk_box",
+           "sim_stream_workspace_size",
            "sim_generate_facets", "sim_forward", "sim_apply_waveform",
            "sim_apply_waveform_adjoint", "sim_backward", "sim_stream_forward",
            "sim_stream_backward", "sim_forward_speckle", "sim_backward_speckle",
@@ -127,13 +136,19 @@ def load(path: str = LIB_PATH):
     L.sim_last_error.restype = ctypes.c_char_p
     L.sim_pulse_info.argtypes = [vp, i, i, i, P(ctypes.c_double), P(ctypes.c_double)]
     L.sim_waveform_info.argtypes = [vp, P(i), P(i)]
-    L.sim_plan_create.argtypes = [vp, vp, vp, ll, ctypes.c_double, vp, P(vp)]
+    sz = ctypes.c_size_t
+    L.sim_device_init.argtypes = [vp]
+    L.sim_workspace_size.argtypes = [vp, ll, P(SimBox), ctypes.c_double, i, P(sz)]
+    L.sim_plan_create.argtypes = [vp, vp, vp, ll, P(SimBox), ctypes.c_double, i, vp, sz, vp,
+                                  P(vp)]
     L.sim_plan_destroy.argtypes = [vp]
     L.sim_plan_destroy.restype = None
-    L.sim_plan_info.argtypes = [vp, P(ll), P(ll), P(ll)]
+    L.sim_plan_info.argtypes = [vp, P(ll), P(ll), P(ll), P(ll)]
     L.sim_plan_mode.argtypes = [vp, P(i), P(ctypes.c_double)]
+    L.sim_sea_table_size.argtypes = [P(SimSea), P(sz)]
+    L.sim_chunk_box.argtypes = [P(SimSea), i, i, i, i, P(SimBox)]
     L.sim_generate_facets.argtypes = [vp, P(SimSea), ctypes.c_ulonglong, i, i, i, i,
-                                      P(SimFacetsOut), vp]
+                                      P(SimFacetsOut), vp, sz, vp]
     L.sim_forward.argtypes = [vp, vp, P(SimFacets), i, i, vp, i, vp]
     L.sim_apply_waveform.argtypes = [vp, vp, vp, ll, vp]
     L.sim_apply_waveform_adjoint.argtypes = [vp, vp, vp, ll, vp]
@@ -142,15 +157,17 @@ def load(path: str = LIB_PATH):
     L.sim_backward_speckle.argtypes = [vp, vp, P(SimFacets), P(SimSpeckle), i, i, vp,
                                        P(SimFacetGrads), i, vp]
     ip = P(ctypes.c_int)
+    L.sim_stream_workspace_size.argtypes = [vp, P(SimSea), ip, i, ctypes.c_double, i, P(sz)]
     L.sim_stream_forward.argtypes = [vp, P(SimSea), ctypes.c_ulonglong, ip, i, ctypes.c_double,
-                                     i, i, vp, i, vp]
+                                     i, i, vp, i, vp, sz, vp]
     L.sim_stream_backward.argtypes = [vp, P(SimSea), ctypes.c_ulonglong, ip, i, ctypes.c_double,
-                                      i, i, vp, vp, vp, vp, vp]
+                                      i, i, vp, vp, vp, vp, vp, sz, vp]
     L.sim_stream_forward_speckle.argtypes = [vp, P(SimSea), ctypes.c_ulonglong, ip, i,
-                                             ctypes.c_double, P(SimSpeckle), i, i, vp, i, vp]
+                                             ctypes.c_double, P(SimSpeckle), i, i, vp, i, vp, sz,
+                                             vp]
     L.sim_stream_backward_speckle.argtypes = [vp, P(SimSea), ctypes.c_ulonglong, ip, i,
                                               ctypes.c_double, P(SimSpeckle), i, i, vp, vp, vp,
-                                              vp, vp]
+                                              vp, vp, sz, vp]
     for name in EXPORTS:
         if name not in ("sim_destroy", "sim_last_error", "sim_plan_destroy"):
             getattr(L, name).restype = ctypes.c_int

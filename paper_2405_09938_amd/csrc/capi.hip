@@ -222,58 +222,6 @@ hipError_t dalloc(T **p, size_t count) {
     return hipMalloc((void **)p, sizeof(T) * (count > 0 ? count : 1));
 }
 
-// Temporaries of one sim_plan_create call.  They come from (and go back to)
-// the handle's pool, so steady-state planning makes no hipMalloc / hipFree
-// (hipFree synchronises the device).  Buffers return to the pool only after
-// the call's final stream synchronisation (`done()`); on an error path they
-// are freed instead, which waits for any kernel still using them.
-struct DevBufs {
-    sim_handle *h;
-    std::vector<std::pair<void *, size_t>> bufs;
-    bool finished = false;
-    explicit DevBufs(sim_handle *hh) : h(hh) {}
-    ~DevBufs() {
-        for (auto &b : bufs) {
-            if (finished) h->scratch_pool.push_back(b);
-            else (void)hipFree(b.first);
-        }
-        // keep the pool small: drop the smallest buffers beyond 16
-        auto &pool = h->scratch_pool;
-        while (pool.size() > 16) {
-            size_t k = 0;
-            for (size_t i = 1; i < pool.size(); ++i)
-                if (pool[i].second < pool[k].second) k = i;
-            (void)hipFree(pool[k].first);
-            pool.erase(pool.begin() + (long)k);
-        }
-    }
-    void done() { finished = true; }
-    template <typename T>
-    hipError_t alloc(T **p, size_t count) {
-        const size_t bytes = sizeof(T) * (count > 0 ? count : 1);
-        auto &pool = h->scratch_pool;
-        size_t best = pool.size();
-        for (size_t i = 0; i < pool.size(); ++i)
-            if (pool[i].second >= bytes && (best == pool.size() || pool[i].second < pool[best].second))
-                best = i;
-        if (best < pool.size()) {
-            bufs.push_back(pool[best]);
-            pool.erase(pool.begin() + (long)best);
-            *p = (T *)bufs.back().first;
-            return hipSuccess;
-        }
-        void *q = nullptr;
-        hipError_t e = hipMalloc(&q, bytes);
-        if (e != hipSuccess) {
-            *p = nullptr;
-            return e;
-        }
-        bufs.emplace_back(q, bytes);
-        *p = (T *)q;
-        return hipSuccess;
-    }
-};
-
 // Bound on the relative error of taking each antenna's elevation pattern
 // factor sinc(kappa v / beta_el) at the block centre instead of per facet.
 // Over the scene rectangle (z = 0) and the first, middle and last pulses,
@@ -286,7 +234,7 @@ struct DevBufs {
 // An antenna with a u-v table is bounded through its nominal elevation width
 // (the sinc of that width stands for its beam; the bound then only decides
 // whether the adjoint drops its first-order gain-gradient correction).
-double elevation_bound(const sim_handle *h, const float box[4], double e_max) {
+double elevation_bound(const sim_handle *h, const double box[4], double e_max) {
     double worst = 0.0;
     const double xs[3] = {box[0], 0.5 * (box[0] + box[1]), box[1]};
     const double ys[3] = {box[2], 0.5 * (box[2] + box[3]), box[3]};
@@ -331,72 +279,12 @@ double elevation_bound(const sim_handle *h, const float box[4], double e_max) {
     return worst;
 }
 
-// Plan buffers: from the handle's pool when one is large enough (the stream
-// then waits, on the device, for the work that used it under its previous
-// plan), otherwise from hipMalloc.
-template <typename T>
-hipError_t plan_alloc(sim_handle *h, T **p, size_t count, size_t *cap, hipStream_t s) {
-    const size_t bytes = sizeof(T) * (count > 0 ? count : 1);
-    auto &pool = h->plan_pool;
-    size_t best = pool.size();
-    for (size_t i = 0; i < pool.size(); ++i)
-        if (pool[i].bytes >= bytes && (best == pool.size() || pool[i].bytes < pool[best].bytes))
-            best = i;
-    if (best < pool.size()) {
-        for (hipEvent_t ev : *pool[best].after) {
-            hipError_t e = hipStreamWaitEvent(s, ev, 0);
-            if (e != hipSuccess) return e;
-        }
-        *p = (T *)pool[best].p;
-        *cap = pool[best].bytes;
-        pool.erase(pool.begin() + (long)best);
-        return hipSuccess;
-    }
-    void *q = nullptr;
-    hipError_t e = hipMalloc(&q, bytes);
-    if (e != hipSuccess) {
-        *p = nullptr;
-        return e;
-    }
-    *p = (T *)q;
-    *cap = bytes;
-    return hipSuccess;
-}
-
-// Record, on stream s, the end of the work just enqueued on the plan's
-// buffers (one event per stream, re-recorded at each use).  UseGuard does it
-// when a call returns, whatever path it returns by.
-void note_use(sim_plan *P, hipStream_t s) {
-    for (auto &u : P->uses)
-        if (u.first == s) {
-            if (hipEventRecord(u.second, s) != hipSuccess) P->uses_ok = false;
-            return;
-        }
-    hipEvent_t ev = nullptr;
-    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
-        P->uses_ok = false;
-        return;
-    }
-    if (hipEventRecord(ev, s) != hipSuccess) P->uses_ok = false;
-    P->uses.emplace_back(s, ev);
-}
-
-struct UseGuard {
-    sim_plan *P;
-    hipStream_t s;
-    ~UseGuard() { note_use(P, s); }
-};
-
 void release_handle(sim_handle *h) {
     if (h->pulses_d) (void)hipFree(h->pulses_d);
     if (h->chirp_spec_d) (void)hipFree(h->chirp_spec_d);
     if (h->twiddle_d) (void)hipFree(h->twiddle_d);
-    if (h->gen_tab_d) (void)hipFree(h->gen_tab_d);
     for (float4 *p : h->pat_d)
         if (p) (void)hipFree(p);
-    for (auto &b : h->scratch_pool) (void)hipFree(b.first);
-    for (auto &b : h->plan_pool) (void)hipFree(b.p);   // hipFree waits for the device
-    h->plan_pool.clear();
     delete h;
 }
 
@@ -680,10 +568,6 @@ int sim_create(const sim_config *cfg, sim_handle **out) {
 
 void sim_destroy(sim_handle *h) {
     if (!h) return;
-    if (h->live_plans > 0) {   // freed when its last plan is destroyed
-        h->destroy_pending = true;
-        return;
-    }
     release_handle(h);
 }
 
@@ -706,46 +590,45 @@ int sim_waveform_info(const sim_handle *h, int *chirp_len, int *fft_len) {
     return SIM_OK;
 }
 
-int sim_plan_create(sim_handle *h, const float *x, const float *y, long long n,
-                    double block_edge, void *stream, sim_plan **out) {
-    if (!h || !out) HS_FAIL(SIM_EINVAL, "handle or out is NULL");
-    *out = nullptr;
-    if (n < 1 || n >= (1LL << 31) - 64) HS_FAIL(SIM_EINVAL, "facet count must be in [1, 2^31 - 64)");
-    if (!x || !y) HS_FAIL(SIM_EINVAL, "x or y is NULL");
-    if (!(block_edge > 0) || block_edge > 64) HS_FAIL(SIM_EINVAL, "block_edge must be in (0, 64]");
-    if (int rc = ensure_device(h)) return rc;
-    hipStream_t s = (hipStream_t)stream;
+// ---- plan (range-binned block sort) in a caller-owned workspace ------------
 
-    DevBufs tmp(h);
-    int *bb = nullptr;
-    HS_HIP(tmp.alloc(&bb, 4), "plan alloc");
-    {
-        const int init[4] = {std::numeric_limits<int>::max(), std::numeric_limits<int>::min(),
-                             std::numeric_limits<int>::max(), std::numeric_limits<int>::min()};
-        HS_HIP(hipMemcpyAsync(bb, init, sizeof(init), hipMemcpyHostToDevice, s), "plan bbox init");
-    }
-    HS_HIP(hs::launch_bbox(x, y, n, bb, s), "plan bbox");
-    int keyv[4];
-    HS_HIP(hipMemcpyAsync(keyv, bb, sizeof(keyv), hipMemcpyDeviceToHost, s), "plan bbox read");
-    HS_HIP(hipStreamSynchronize(s), "plan sync");
-    float box[4];
-    for (int k = 0; k < 4; ++k) {
-        const unsigned u = (unsigned)keyv[k];
-        const unsigned bits = keyv[k] >= 0 ? u : 0x80000000u - u;
-        std::memcpy(&box[k], &bits, 4);
-        if (!std::isfinite(box[k])) HS_FAIL(SIM_EINVAL, "facet positions must be finite");
-    }
-
+// Host-side shape of a plan: the block lattice over the scene rectangle, the
+// patches of cells that share a range window, the window and halo of the
+// forward kernel, the elevation-factor mode, and the sizes the workspace
+// must hold.
+struct PlanGeom {
     hs::Lattice L;
+    long long n_keys, n_patches, nb_max;
+    int halo, win;
+    double el_bound;
+    bool el_const;
+};
+
+static int box_ok(const sim_box *box) {
+    if (!box) HS_FAIL(SIM_EINVAL, "box is NULL");
+    if (!std::isfinite(box->x_min) || !std::isfinite(box->x_max) || !std::isfinite(box->y_min) ||
+        !std::isfinite(box->y_max) || !(box->x_min <= box->x_max) || !(box->y_min <= box->y_max))
+        HS_FAIL(SIM_EINVAL, "box must be finite with x_min <= x_max and y_min <= y_max");
+    return SIM_OK;
+}
+
+static int plan_geometry(const sim_handle *h, long long n, const sim_box *bx, double block_edge,
+                         PlanGeom &G) {
+    if (n < 1 || n >= (1LL << 31) - 64) HS_FAIL(SIM_EINVAL, "facet count must be in [1, 2^31 - 64)");
+    if (!(block_edge > 0) || block_edge > 64) HS_FAIL(SIM_EINVAL, "block_edge must be in (0, 64]");
+    if (int rc = box_ok(bx)) return rc;
+    const double box[4] = {bx->x_min, bx->x_max, bx->y_min, bx->y_max};
+    hs::Lattice &L = G.L;
     L.edge = block_edge;
-    L.bx0 = (long long)std::floor((double)box[0] / block_edge);
-    L.by0 = (long long)std::floor((double)box[2] / block_edge);
-    const long long nbx = (long long)std::floor((double)box[1] / block_edge) - L.bx0 + 1;
-    const long long nby = (long long)std::floor((double)box[3] / block_edge) - L.by0 + 1;
-    if (nbx * nby > (1LL << 28) || nbx > (1 << 28) || nby > (1 << 28))
+    const double fx0 = std::floor(box[0] / block_edge), fx1 = std::floor(box[1] / block_edge);
+    const double fy0 = std::floor(box[2] / block_edge), fy1 = std::floor(box[3] / block_edge);
+    if (fx1 - fx0 + 1 > (double)(1 << 28) || fy1 - fy0 + 1 > (double)(1 << 28) ||
+        (fx1 - fx0 + 1) * (fy1 - fy0 + 1) > (double)(1LL << 28))
         HS_FAIL(SIM_EUNSUPPORTED, "facet lattice exceeds 2^28 cells");
-    L.nbx = (int)nbx;
-    L.nby = (int)nby;
+    L.bx0 = (long long)fx0;
+    L.by0 = (long long)fy0;
+    L.nbx = (int)(fx1 - fx0) + 1;
+    L.nby = (int)(fy1 - fy0) + 1;
 
     // Patch shape: gradients of the sample position along x and y over the
     // scene corners and the first / middle / last pulses of every channel.
@@ -772,16 +655,16 @@ int sim_plan_create(sim_handle *h, const float *x, const float *y, long long n,
     const double bins_per_m = h->fs / h->c;
     const double tmax = 0.5 * (double)(h->Np - 1) / h->prf;
     // halo: facet heights up to 4 m and drift at up to 2.5 m/s over the dwell
-    const int halo = (int)std::ceil((4.0 * gzm + 2.5 * tmax * gnm) * bins_per_m) + 1;
+    G.halo = (int)std::ceil((4.0 * gzm + 2.5 * tmax * gnm) * bins_per_m) + 1;
     // window of the forward kernel: the smallest instantiated width that
     // leaves room for a patch span after the halo and the taps
-    int win = 64;
+    G.win = 64;
     for (int w : {HEEPS_WIN_MIN, 24, 32, 48, 64})
-        if (w >= HEEPS_WIN_MIN && 2 * halo + 13 <= w) {
-            win = w;
+        if (w >= HEEPS_WIN_MIN && 2 * G.halo + 13 <= w) {
+            G.win = w;
             break;
         }
-    const double budget = std::max(2.0, (double)(win - 2 * halo - 11));
+    const double budget = std::max(2.0, (double)(G.win - 2 * G.halo - 11));
     const double gxb = gxm * bins_per_m * block_edge, gyb = gym * bins_per_m * block_edge;
     const double target = HEEPS_PATCH_CELLS;   // cells per patch
     double px = std::sqrt(target * gyb / gxb), py = target / px;
@@ -795,119 +678,172 @@ int sim_plan_create(sim_handle *h, const float *x, const float *y, long long n,
     L.py = std::max(1, std::min((int)py, L.nby));
     L.npx = (L.nbx + L.px - 1) / L.px;
     L.npy = (L.nby + L.py - 1) / L.py;
-    const long long n_patches = (long long)L.npx * L.npy;
-    const long long n_keys = n_patches * L.px * L.py;
-    if (n_keys > (1LL << 28)) HS_FAIL(SIM_EUNSUPPORTED, "facet lattice exceeds 2^28 cells");
-
-    // counting sort by key
-    int *keys, *rank, *count, *offset, *nblk, *blk_offset, *scan_tmp;
-    const long long stl = hs::scan_tmp_len(n_keys);
-    HS_HIP(tmp.alloc(&keys, n), "plan alloc");
-    HS_HIP(tmp.alloc(&rank, n), "plan alloc");
-    HS_HIP(tmp.alloc(&count, n_keys), "plan alloc");
-    HS_HIP(tmp.alloc(&offset, n_keys + 1), "plan alloc");
-    HS_HIP(tmp.alloc(&nblk, n_keys), "plan alloc");
-    HS_HIP(tmp.alloc(&blk_offset, n_keys + 1), "plan alloc");
-    HS_HIP(tmp.alloc(&scan_tmp, stl), "plan alloc");
-
-    sim_plan *P = new (std::nothrow) sim_plan();
-    if (!P) HS_FAIL(SIM_ENOMEM, "host allocation failed");
-    P->h = h;
-    ++h->live_plans;
-    P->n = n;
-    P->lat = L;
-    P->n_patches = n_patches;
-    P->halo = halo;
-    P->win = win;
+    G.n_patches = (long long)L.npx * L.npy;
+    G.n_keys = G.n_patches * L.px * L.py;
+    if (G.n_keys > (1LL << 28)) HS_FAIL(SIM_EUNSUPPORTED, "facet lattice exceeds 2^28 cells");
+    // a cell of c facets makes ceil(c / 64) blocks: at most one per non-empty
+    // cell plus one per 64 facets
+    G.nb_max = std::min(n, G.n_keys) + n / 64;
     // facets lie within half a block diagonal of their block centre, moved by
     // heights up to 4 m and drift at up to 2.5 m/s over the dwell (as the halo)
-    P->el_bound = elevation_bound(h, box, 0.5 * std::sqrt(2.0) * block_edge + 4.0 + 2.5 * tmax);
-    P->el_const = P->el_bound <= HEEPS_EL_CONST_TOL;
-    auto fail = [&](int code, const std::string &msg) {
-        P->uses_ok = false;   // kernels may still use the buffers: free them
-        sim_plan_destroy(P);
-        hs::set_error(msg);
-        return code;
+    G.el_bound = elevation_bound(h, box, 0.5 * std::sqrt(2.0) * block_edge + 4.0 + 2.5 * tmax);
+    G.el_const = G.el_bound <= HEEPS_EL_CONST_TOL;
+    return SIM_OK;
+}
+
+// Byte offsets of a plan's buffers in its workspace (each 256-byte aligned).
+struct PlanLayout {
+    size_t perm, sorted, blocks, patch_first, count, offset, nblk, blk_offset, scan_tmp, misc;
+    size_t spk, anch, total;
+};
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static PlanLayout plan_layout(const PlanGeom &G, long long n, int flags, int Np) {
+    PlanLayout Y{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += align256(bytes);
+        return at;
     };
+    const size_t nk = (size_t)G.n_keys;
+    Y.perm = take(sizeof(int) * (size_t)n);
+    // the sort's keys and ranks (8 bytes per facet) live in the first part of
+    // `sorted` until the first gather overwrites it
+    Y.sorted = take(sizeof(hs::FacetRec) * ((size_t)n + 1));
+    Y.blocks = take(sizeof(hs::BlockRec) * (size_t)std::max(1LL, G.nb_max));
+    Y.patch_first = take(sizeof(int) * ((size_t)G.n_patches + 1));
+    Y.count = take(sizeof(int) * nk);
+    Y.offset = take(sizeof(int) * (nk + 1));
+    Y.nblk = take(sizeof(int) * nk);
+    Y.blk_offset = take(sizeof(int) * (nk + 1));
+    Y.scan_tmp = take(sizeof(int) * (size_t)hs::scan_tmp_len(G.n_keys));
+    Y.misc = take(256);
+    if (flags & SIM_PLAN_SPECKLE) {
+        const size_t groups = (size_t)((Np + 63) / 64) + 1;
+        Y.spk = take(sizeof(hs::SpkRec) * ((size_t)n + 1));
+        Y.anch = take(sizeof(float4) * ((size_t)n + 1) * groups);
+    }
+    Y.total = o;
+    return Y;
+}
+
+static int workspace_ok(const void *ws, size_t ws_bytes, size_t need) {
+    if (!ws) HS_FAIL(SIM_EINVAL, "workspace is NULL");
+    if (((uintptr_t)ws & 255u) != 0) HS_FAIL(SIM_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < need)
+        HS_FAIL(SIM_EINVAL, "workspace too small: " + std::to_string(need) + " bytes needed, " +
+                                std::to_string(ws_bytes) + " given");
+    return SIM_OK;
+}
+
+// Builds the plan of facets (x, y) in the workspace `ws` (laid out by Y):
+// counting sort by (patch, cell), blocks of at most 64 facets, first block
+// of each patch.  Everything is enqueued on s; nothing is read back.
+static int plan_build(const sim_handle *h, const float *x, const float *y, long long n,
+                      const PlanGeom &G, const PlanLayout &Y, int flags, char *ws, hipStream_t s,
+                      sim_plan &P) {
+    P.h = h;
+    P.n = n;
+    P.nb_max = G.nb_max;
+    P.n_patches = G.n_patches;
+    P.flags = flags;
+    P.lat = G.L;
+    P.halo = G.halo;
+    P.win = G.win;
+    P.el_const = G.el_const;
+    P.el_bound = G.el_bound;
+    P.stream = s;
+    P.perm = (int *)(ws + Y.perm);
+    P.sorted = (hs::FacetRec *)(ws + Y.sorted);
+    P.blocks = (hs::BlockRec *)(ws + Y.blocks);
+    P.patch_first = (int *)(ws + Y.patch_first);
+    int *count = (int *)(ws + Y.count), *offset = (int *)(ws + Y.offset);
+    int *nblk = (int *)(ws + Y.nblk), *blk_offset = (int *)(ws + Y.blk_offset);
+    int *scan_tmp = (int *)(ws + Y.scan_tmp);
+    int *keys = (int *)(ws + Y.sorted);
+    int *rank = keys + n;
+    P.n_blocks = blk_offset + G.n_keys;
+    P.n_outside = (unsigned *)(ws + Y.misc);
+    P.spk = (flags & SIM_PLAN_SPECKLE) ? (hs::SpkRec *)(ws + Y.spk) : nullptr;
+    P.anch = (flags & SIM_PLAN_SPECKLE) ? (float4 *)(ws + Y.anch) : nullptr;
+    const long long stl = hs::scan_tmp_len(G.n_keys);
+    const long long nk = G.n_keys;
     hipError_t e = hipSuccess;
-    if ((e = plan_alloc(h, &P->perm, n, &P->perm_cap, s)) != hipSuccess ||
-        (e = plan_alloc(h, &P->patch_first, n_patches + 1, &P->patch_first_cap, s)) !=
+    if ((e = hs::launch_fill_zero((float *)count, nk, s)) != hipSuccess ||
+        (e = hs::launch_fill_zero((float *)P.n_outside, 1, s)) != hipSuccess ||
+        (e = hs::launch_cell_keys(x, y, n, G.L, keys, rank, count, P.n_outside, s)) !=
             hipSuccess ||
-        (e = plan_alloc(h, &P->sorted, n + 1, &P->sorted_cap, s)) != hipSuccess)
-        return fail(SIM_ENOMEM, std::string("plan alloc: ") + hipGetErrorString(e));
-    if ((e = hs::launch_fill_zero((float *)count, n_keys, s)) != hipSuccess ||
-        (e = hs::launch_fill_zero((float *)(P->sorted + n), 8, s)) != hipSuccess ||
-        (e = hs::launch_cell_keys(x, y, n, L, keys, rank, count, s)) != hipSuccess ||
-        (e = hs::launch_exclusive_scan(count, offset, n_keys, scan_tmp, stl, s)) != hipSuccess ||
-        (e = hs::launch_scatter(keys, rank, offset, n, P->perm, s)) != hipSuccess ||
-        (e = hs::launch_block_counts(count, n_keys, nblk, s)) != hipSuccess ||
-        (e = hs::launch_exclusive_scan(nblk, blk_offset, n_keys, scan_tmp, stl, s)) != hipSuccess)
-        return fail(SIM_EHIP, std::string("plan sort: ") + hipGetErrorString(e));
-    int nb_total = 0;
-    if ((e = hipMemcpyAsync(&nb_total, blk_offset + n_keys, sizeof(int), hipMemcpyDeviceToHost,
-                            s)) != hipSuccess ||
-        (e = hipStreamSynchronize(s)) != hipSuccess)
-        return fail(SIM_EHIP, std::string("plan sync: ") + hipGetErrorString(e));
-    P->n_blocks = nb_total;
-    if ((e = plan_alloc(h, &P->blocks, (size_t)nb_total, &P->blocks_cap, s)) != hipSuccess)
-        return fail(SIM_ENOMEM, std::string("plan alloc: ") + hipGetErrorString(e));
-    if ((e = hs::launch_make_blocks(count, offset, blk_offset, n_keys, L, P->blocks, s)) !=
+        (e = hs::launch_exclusive_scan(count, offset, nk, scan_tmp, stl, s)) != hipSuccess ||
+        (e = hs::launch_scatter(keys, rank, offset, n, P.perm, s)) != hipSuccess ||
+        (e = hs::launch_fill_zero((float *)(P.sorted + n), 8, s)) != hipSuccess ||
+        (e = hs::launch_block_counts(count, nk, nblk, s)) != hipSuccess ||
+        (e = hs::launch_exclusive_scan(nblk, blk_offset, nk, scan_tmp, stl, s)) != hipSuccess ||
+        (e = hs::launch_make_blocks(count, offset, blk_offset, nk, G.L, P.blocks, s)) !=
             hipSuccess ||
-        (e = hs::launch_patch_first(blk_offset, n_patches, L.px * L.py, n_keys, P->patch_first,
-                                    s)) != hipSuccess ||
-        (e = hipStreamSynchronize(s)) != hipSuccess)
-        return fail(SIM_EHIP, std::string("plan blocks: ") + hipGetErrorString(e));
-    tmp.done();
-    note_use(P, s);
+        (e = hs::launch_patch_first(blk_offset, G.n_patches, G.L.px * G.L.py, nk, P.patch_first,
+                                    s)) != hipSuccess)
+        HS_FAIL(SIM_EHIP, std::string("plan: ") + hipGetErrorString(e));
+    return SIM_OK;
+}
+
+int sim_device_init(sim_handle *h) {
+    if (!h) HS_FAIL(SIM_EINVAL, "handle is NULL");
+    return ensure_device(h);
+}
+
+int sim_workspace_size(const sim_handle *h, long long n, const sim_box *box, double block_edge,
+                       int flags, size_t *bytes) {
+    if (!h || !bytes) HS_FAIL(SIM_EINVAL, "handle or bytes is NULL");
+    if (flags & ~SIM_PLAN_SPECKLE) HS_FAIL(SIM_EINVAL, "unknown plan flags");
+    PlanGeom G;
+    if (int rc = plan_geometry(h, n, box, block_edge, G)) return rc;
+    *bytes = plan_layout(G, n, flags, h->Np).total;
+    return SIM_OK;
+}
+
+int sim_plan_create(sim_handle *h, const float *x, const float *y, long long n,
+                    const sim_box *box, double block_edge, int flags, void *workspace,
+                    size_t workspace_bytes, void *stream, sim_plan **out) {
+    if (!h || !out) HS_FAIL(SIM_EINVAL, "handle or out is NULL");
+    *out = nullptr;
+    if (!x || !y) HS_FAIL(SIM_EINVAL, "x or y is NULL");
+    if (flags & ~SIM_PLAN_SPECKLE) HS_FAIL(SIM_EINVAL, "unknown plan flags");
+    PlanGeom G;
+    if (int rc = plan_geometry(h, n, box, block_edge, G)) return rc;
+    const PlanLayout Y = plan_layout(G, n, flags, h->Np);
+    if (int rc = workspace_ok(workspace, workspace_bytes, Y.total)) return rc;
+    if (int rc = ensure_device(h)) return rc;
+    sim_plan *P = new (std::nothrow) sim_plan();
+    if (!P) HS_FAIL(SIM_ENOMEM, "host allocation failed");
+    if (int rc = plan_build(h, x, y, n, G, Y, flags, (char *)workspace, (hipStream_t)stream, *P)) {
+        delete P;
+        return rc;
+    }
     *out = P;
     return SIM_OK;
 }
 
-void sim_plan_destroy(sim_plan *P) {
-    if (!P) return;
-    sim_handle *h = P->h;
-    // The buffers go back to the handle's pool with the events that mark
-    // their last use on every stream; a later plan's stream waits for them.
-    // If a use could not be recorded, the buffers are freed instead (hipFree
-    // waits for the device).
-    std::shared_ptr<std::vector<hipEvent_t>> keep(new std::vector<hipEvent_t>(),
-                                                  [](std::vector<hipEvent_t> *v) {
-                                                      for (hipEvent_t ev : *v)
-                                                          (void)hipEventDestroy(ev);
-                                                      delete v;
-                                                  });
-    for (auto &u : P->uses) keep->push_back(u.second);
-    if (!P->uses_ok) keep.reset();
-    const std::pair<void *, size_t> bufs[6] = {{P->perm, P->perm_cap},
-                                               {P->blocks, P->blocks_cap},
-                                               {P->patch_first, P->patch_first_cap},
-                                               {P->sorted, P->sorted_cap},
-                                               {P->spk, P->spk_cap},
-                                               {P->anch, P->anch_cap}};
-    for (const auto &b : bufs) {
-        if (!b.first) continue;
-        if (keep) h->plan_pool.push_back({b.first, b.second, keep});
-        else (void)hipFree(b.first);
-    }
-    // keep the pool small: free the smallest buffers beyond 16
-    auto &pool = h->plan_pool;
-    while (pool.size() > 16) {
-        size_t k = 0;
-        for (size_t i = 1; i < pool.size(); ++i)
-            if (pool[i].bytes < pool[k].bytes) k = i;
-        (void)hipFree(pool[k].p);
-        pool.erase(pool.begin() + (long)k);
-    }
-    delete P;
-    if (--h->live_plans == 0 && h->destroy_pending) release_handle(h);
-}
+void sim_plan_destroy(sim_plan *P) { delete P; }
 
 int sim_plan_info(const sim_plan *P, long long *n_facets, long long *n_blocks,
-                  long long *n_patches) {
+                  long long *n_patches, long long *n_outside) {
     if (!P) HS_FAIL(SIM_EINVAL, "plan is NULL");
     if (n_facets) *n_facets = P->n;
-    if (n_blocks) *n_blocks = P->n_blocks;
     if (n_patches) *n_patches = P->n_patches;
+    if (n_blocks || n_outside) {
+        int nb = 0;
+        unsigned no = 0;
+        HS_HIP(hipMemcpyAsync(&nb, P->n_blocks, sizeof(int), hipMemcpyDeviceToHost, P->stream),
+               "plan info read");
+        HS_HIP(hipMemcpyAsync(&no, P->n_outside, sizeof(unsigned), hipMemcpyDeviceToHost,
+                              P->stream),
+               "plan info read");
+        HS_HIP(hipStreamSynchronize(P->stream), "plan info sync");
+        if (n_blocks) *n_blocks = nb;
+        if (n_outside) *n_outside = no;
+    }
     return SIM_OK;
 }
 
@@ -947,20 +883,88 @@ static int sea_ok(const sim_sea *sea) {
     return SIM_OK;
 }
 
-int sim_generate_facets(sim_handle *h, const sim_sea *sea, unsigned long long seed, int ix0,
-                        int iy0, int cnx, int cny, const sim_facets_out *out, void *stream) {
-    if (!h || !sea || !out) HS_FAIL(SIM_EINVAL, "handle, sea or out is NULL");
+// Wave-component table of a sea (one homogeneous field in mode 1, one per
+// lattice node in mode 2), rows (k, A, omega, cos psi, sin psi, phase):
+// wavenumbers log-spaced on [k_min, k_max]; A_m^2 = 2 Psi(k_m) dk_m with
+// Psi ~ k^slope and dk_m = k_m dlnk, scaled so sum A_m^2 / 2 = (hs/4)^2 per
+// field; omega^2 = g k (deep water).  Empty for mode 0.  Parameters checked
+// by sea_ok.
+static void sea_table(const sim_sea *sea, std::vector<double> &tab) {
+    tab.clear();
+    if (sea->mode < 1) return;
+    const int nc = sea->n_comp;
+    int nodes = 1;
+    const double *hs_of = &sea->hs;
+    const double *dirs = sea->dirs, *phases = sea->phases;
+    if (sea->mode == 2) {
+        nodes = (sea->ntx + 1) * (sea->nty + 1);
+        hs_of = sea->node_hs;
+        dirs = sea->node_dirs;
+        phases = sea->node_phases;
+    }
+    tab.assign((size_t)6 * nc * nodes, 0.0);
+    const double dl = nc > 1 ? std::log(sea->k_max / sea->k_min) / (nc - 1) : 1.0;
+    for (int q = 0; q < nodes; ++q) {
+        double energy = 0.0;
+        double *tq = &tab[(size_t)6 * nc * q];
+        for (int m = 0; m < nc; ++m) {
+            const double k = nc > 1 ? sea->k_min * std::exp(dl * m) : sea->k_min;
+            const double A = std::sqrt(2.0 * std::pow(k, sea->slope) * k * dl);
+            energy += 0.5 * A * A;
+            double *t = tq + 6 * m;
+            t[0] = k;
+            t[1] = A;
+            t[2] = std::sqrt(sea->g * k);
+            t[3] = std::cos(dirs[(size_t)q * nc + m]);
+            t[4] = std::sin(dirs[(size_t)q * nc + m]);
+            t[5] = phases[(size_t)q * nc + m];
+        }
+        const double scale = energy > 0 ? (hs_of[q] / 4.0) / std::sqrt(energy) : 0.0;
+        for (int m = 0; m < nc; ++m) tq[6 * m + 1] *= scale;
+    }
+}
+
+static int grid_ok(const sim_sea *sea, int ix0, int iy0, int cnx, int cny) {
     if (sea->nx < 1 || sea->ny < 1 || !(sea->dx > 0) || !(sea->dy > 0))
         HS_FAIL(SIM_EINVAL, "grid size and spacing must be positive");
     if (ix0 < 0 || iy0 < 0 || cnx < 0 || cny < 0 || (long long)ix0 + cnx > sea->nx ||
         (long long)iy0 + cny > sea->ny)
         HS_FAIL(SIM_EINVAL, "sub-rectangle outside the grid");
-    if (out->n != (long long)cnx * cny) HS_FAIL(SIM_EINVAL, "out->n must equal cnx*cny");
-    if (out->n > 0 && (!out->x || !out->y || !out->z || !out->vx || !out->vy || !out->vz ||
-                       !out->a_re || !out->a_im))
-        HS_FAIL(SIM_EINVAL, "an output array pointer is NULL");
-    if (int rc = sea_ok(sea)) return rc;
-    if (int rc = ensure_device(h)) return rc;
+    return SIM_OK;
+}
+
+// Rectangle holding every facet of a grid sub-rectangle: its cell centres,
+// widened by the largest Choppy Wave Model displacement (the sum of a
+// field's amplitudes, twice that for the four weighted fields of mode 2,
+// whose weights add up to at most 2) and by a rounding margin.
+static void chunk_box(const sim_sea *sea, const std::vector<double> &tab, int ix0, int iy0,
+                      int cnx, int cny, sim_box *box) {
+    const double cx = 0.5 * (double)(sea->nx - 1), cy = 0.5 * (double)(sea->ny - 1);
+    double x0 = ((double)ix0 - cx) * sea->dx, x1 = ((double)(ix0 + cnx - 1) - cx) * sea->dx;
+    double y0 = ((double)iy0 - cy) * sea->dy, y1 = ((double)(iy0 + cny - 1) - cy) * sea->dy;
+    double shift = 0.0;
+    if (sea->cwm && sea->mode >= 1 && !tab.empty()) {
+        const size_t rows = tab.size() / 6, nc = (size_t)sea->n_comp;
+        for (size_t q = 0; q < rows / nc; ++q) {
+            double s = 0.0;
+            for (size_t m = 0; m < nc; ++m) s += std::fabs(tab[6 * (q * nc + m) + 1]);
+            shift = std::max(shift, s);
+        }
+        if (sea->mode == 2) shift *= 2.0;
+    }
+    const double mx = 1e-3 + 1e-6 * std::max(std::max(std::fabs(x0), std::fabs(x1)),
+                                             std::max(std::fabs(y0), std::fabs(y1)));
+    box->x_min = x0 - shift - mx;
+    box->x_max = x1 + shift + mx;
+    box->y_min = y0 - shift - mx;
+    box->y_max = y1 + shift + mx;
+}
+
+// Launch of the generator for a sub-rectangle, its sea table already on the
+// device (tab_d; NULL in mode 0).
+static int generate_launch(const sim_sea *sea, unsigned long long seed, int ix0, int iy0,
+                           int cnx, int cny, const sim_facets_out *out, const double *tab_d,
+                           hipStream_t s) {
     hs::GenArgs a{};
     a.nx = sea->nx;
     a.ny = sea->ny;
@@ -976,68 +980,61 @@ int sim_generate_facets(sim_handle *h, const sim_sea *sea, unsigned long long se
     a.out = *out;
     a.cur0 = sea->current[0];
     a.cur1 = sea->current[1];
-    a.n_comp = 0;
+    a.n_comp = sea->mode >= 1 ? sea->n_comp : 0;
     a.cwm = sea->cwm ? 1 : 0;
-    if (sea->mode >= 1) {
-        const int nc = sea->n_comp;
-        // one table per homogeneous field: mode 1 has one, mode 2 one per node
-        // (parameters checked by sea_ok)
-        int nodes = 1;
-        const double *hs_of = &sea->hs;
-        const double *dirs = sea->dirs, *phases = sea->phases;
-        if (sea->mode == 2) {
-            nodes = (sea->ntx + 1) * (sea->nty + 1);
-            hs_of = sea->node_hs;
-            dirs = sea->node_dirs;
-            phases = sea->node_phases;
-            a.ntx = sea->ntx;
-            a.nty = sea->nty;
-            a.tile_L = sea->tile_L;
-            a.tile_x0 = sea->tile_x0;
-            a.tile_y0 = sea->tile_y0;
-        }
-        // wavenumbers log-spaced on [k_min, k_max]; A_m^2 = 2 Psi(k_m) dk_m with
-        // Psi ~ k^slope and dk_m = k_m dlnk, scaled so sum A_m^2 / 2 = (hs/4)^2
-        // per field; omega^2 = g k (deep water)
-        std::vector<double> &tab = h->gen_tab_h;
-        tab.assign((size_t)6 * nc * nodes, 0.0);
-        const double dl = nc > 1 ? std::log(sea->k_max / sea->k_min) / (nc - 1) : 1.0;
-        for (int q = 0; q < nodes; ++q) {
-            double energy = 0.0;
-            double *tq = &tab[(size_t)6 * nc * q];
-            for (int m = 0; m < nc; ++m) {
-                const double k = nc > 1 ? sea->k_min * std::exp(dl * m) : sea->k_min;
-                const double A = std::sqrt(2.0 * std::pow(k, sea->slope) * k * dl);
-                energy += 0.5 * A * A;
-                double *t = tq + 6 * m;
-                t[0] = k;
-                t[1] = A;
-                t[2] = std::sqrt(sea->g * k);
-                t[3] = std::cos(dirs[(size_t)q * nc + m]);
-                t[4] = std::sin(dirs[(size_t)q * nc + m]);
-                t[5] = phases[(size_t)q * nc + m];
-            }
-            const double scale = energy > 0 ? (hs_of[q] / 4.0) / std::sqrt(energy) : 0.0;
-            for (int m = 0; m < nc; ++m) tq[6 * m + 1] *= scale;
-        }
-        hipStream_t s = (hipStream_t)stream;
-        if (h->gen_tab_cap < tab.size()) {
-            // the previous table may still be read by queued work on this stream
-            HS_HIP(hipStreamSynchronize(s), "generate sync");
-            if (h->gen_tab_d) (void)hipFree(h->gen_tab_d);
-            h->gen_tab_d = nullptr;
-            h->gen_tab_cap = 0;
-            HS_HIP(dalloc(&h->gen_tab_d, tab.size()), "generate alloc");
-            h->gen_tab_cap = tab.size();
-        }
-        HS_HIP(hipMemcpyAsync(h->gen_tab_d, tab.data(), sizeof(double) * tab.size(),
-                              hipMemcpyHostToDevice, s),
-               "generate upload");
-        a.tab = h->gen_tab_d;
-        a.n_comp = nc;
+    a.tab = tab_d;
+    if (sea->mode == 2) {
+        a.ntx = sea->ntx;
+        a.nty = sea->nty;
+        a.tile_L = sea->tile_L;
+        a.tile_x0 = sea->tile_x0;
+        a.tile_y0 = sea->tile_y0;
     }
-    HS_HIP(hs::launch_generate(a, (hipStream_t)stream), "generate launch");
+    HS_HIP(hs::launch_generate(a, s), "generate launch");
     return SIM_OK;
+}
+
+int sim_sea_table_size(const sim_sea *sea, size_t *bytes) {
+    if (!sea || !bytes) HS_FAIL(SIM_EINVAL, "sea or bytes is NULL");
+    if (int rc = sea_ok(sea)) return rc;
+    long long nodes = sea->mode == 2 ? (long long)(sea->ntx + 1) * (sea->nty + 1) : 1;
+    *bytes = sea->mode >= 1 ? align256(sizeof(double) * 6 * (size_t)sea->n_comp * (size_t)nodes)
+                            : 0;
+    return SIM_OK;
+}
+
+int sim_chunk_box(const sim_sea *sea, int ix0, int iy0, int cnx, int cny, sim_box *box) {
+    if (!sea || !box) HS_FAIL(SIM_EINVAL, "sea or box is NULL");
+    if (int rc = grid_ok(sea, ix0, iy0, cnx, cny)) return rc;
+    if (cnx < 1 || cny < 1) HS_FAIL(SIM_EINVAL, "empty sub-rectangle");
+    if (int rc = sea_ok(sea)) return rc;
+    std::vector<double> tab;
+    sea_table(sea, tab);
+    chunk_box(sea, tab, ix0, iy0, cnx, cny, box);
+    return SIM_OK;
+}
+
+int sim_generate_facets(sim_handle *h, const sim_sea *sea, unsigned long long seed, int ix0,
+                        int iy0, int cnx, int cny, const sim_facets_out *out, void *workspace,
+                        size_t workspace_bytes, void *stream) {
+    if (!h || !sea || !out) HS_FAIL(SIM_EINVAL, "handle, sea or out is NULL");
+    if (int rc = grid_ok(sea, ix0, iy0, cnx, cny)) return rc;
+    if (out->n != (long long)cnx * cny) HS_FAIL(SIM_EINVAL, "out->n must equal cnx*cny");
+    if (out->n > 0 && (!out->x || !out->y || !out->z || !out->vx || !out->vy || !out->vz ||
+                       !out->a_re || !out->a_im))
+        HS_FAIL(SIM_EINVAL, "an output array pointer is NULL");
+    if (int rc = sea_ok(sea)) return rc;
+    size_t need = 0;
+    if (int rc = sim_sea_table_size(sea, &need)) return rc;
+    if (need > 0)
+        if (int rc = workspace_ok(workspace, workspace_bytes, need)) return rc;
+    if (int rc = ensure_device(h)) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<double> &tab = h->gen_tab_h;
+    sea_table(sea, tab);
+    double *tab_d = need > 0 ? (double *)workspace : nullptr;
+    if (tab_d) HS_HIP(hs::launch_upload(tab_d, tab.data(), (long long)tab.size(), s), "sea table");
+    return generate_launch(sea, seed, ix0, iy0, cnx, cny, out, tab_d, s);
 }
 
 // ---- intra-facet speckle (Sec. III.A eq. 7, eq. 10) ------------------------
@@ -1057,7 +1054,8 @@ static int speckle_ok(const sim_handle *h, const sim_speckle *sp) {
 // records and anchors of the groups the pulse range covers.
 // chunk: (ix0, iy0, cnx, cny) of a generated chunk of a grid grid_nx wide, whose
 // facets take ids and Doppler by grid index; NULL for a caller's facet set.
-static int speckle_prepare(sim_handle *h, sim_plan *P, const sim_speckle *sp, int p0, int np,
+static int speckle_prepare(const sim_handle *h, const sim_plan *P, const sim_speckle *sp,
+                           int p0, int np,
                            bool with_d, const int *chunk, int grid_nx, hipStream_t s,
                            hs::SpkArgs &k) {
     const double a = std::isinf(sp->tau_s) ? 0.0 : 1.0 / (h->prf * sp->tau_s);
@@ -1076,13 +1074,8 @@ static int speckle_prepare(sim_handle *h, sim_plan *P, const sim_speckle *sp, in
     k.key = (uint32_t)sp->seed ^ (uint32_t)(sp->seed >> 32);
     k.n_groups = (h->Np + 63) / 64;
     const long long n = P->n;
-    hipError_t e = hipSuccess;
-    if (!P->spk && (e = plan_alloc(h, &P->spk, (size_t)n + 1, &P->spk_cap, s)) != hipSuccess)
-        HS_FAIL(SIM_ENOMEM, std::string("speckle records: ") + hipGetErrorString(e));
-    if (!P->anch &&
-        (e = plan_alloc(h, &P->anch, ((size_t)n + 1) * (size_t)(k.n_groups + 1), &P->anch_cap,
-                        s)) != hipSuccess)
-        HS_FAIL(SIM_ENOMEM, std::string("speckle anchors: ") + hipGetErrorString(e));
+    if (!P->spk || !P->anch)
+        HS_FAIL(SIM_EINVAL, "the plan was made without SIM_PLAN_SPECKLE (no speckle space)");
     k.rec = P->spk;
     k.anch = P->anch;
     hs::SpkPrep pp{};
@@ -1111,12 +1104,14 @@ static int forward_common(sim_handle *h, sim_plan *P, const sim_facets *f,
     if (int rc = facets_ok(f, P->n)) return rc;
     if (p0 < 0 || np < 0 || (long long)p0 + np > h->Np) HS_FAIL(SIM_EINVAL, "pulse range");
     if (int rc = speckle_ok(h, sp)) return rc;
+    if (sp && !(P->flags & SIM_PLAN_SPECKLE))
+        HS_FAIL(SIM_EINVAL, "the plan was made without SIM_PLAN_SPECKLE (no speckle space)");
     if (np == 0) return SIM_OK;   // nothing to write (an empty IQ may have a NULL pointer)
     if (!iq) HS_FAIL(SIM_EINVAL, "iq is NULL");
     if (int rc = ensure_device(h)) return rc;
     hipStream_t s = (hipStream_t)stream;
-    UseGuard use{P, s};
-    HS_HIP(hs::launch_gather(*f, P->perm, P->blocks, P->n_blocks, P->sorted, s), "gather");
+    HS_HIP(hs::launch_gather(*f, P->perm, P->blocks, P->n_blocks, P->nb_max, P->sorted, s),
+           "gather");
     hs::FwdArgs a{};
     if (sp)
         if (int rc = speckle_prepare(h, P, sp, p0, np, false, chunk, grid_nx, s, a.spk))
@@ -1177,6 +1172,8 @@ static int backward_common(sim_handle *h, sim_plan *P, const sim_facets *f,
     if (!g && np > 0) HS_FAIL(SIM_EINVAL, "g is NULL");
     if (gr->n != P->n) HS_FAIL(SIM_EINVAL, "grads->n differs from the plan's facet count");
     if (int rc = speckle_ok(h, sp)) return rc;
+    if (sp && !(P->flags & SIM_PLAN_SPECKLE))
+        HS_FAIL(SIM_EINVAL, "the plan was made without SIM_PLAN_SPECKLE (no speckle space)");
     if (int rc = ensure_device(h)) return rc;
     hipStream_t s = (hipStream_t)stream;
     if (np == 0) {
@@ -1187,8 +1184,8 @@ static int backward_common(sim_handle *h, sim_plan *P, const sim_facets *f,
         }
         return SIM_OK;
     }
-    UseGuard use{P, s};
-    HS_HIP(hs::launch_gather(*f, P->perm, P->blocks, P->n_blocks, P->sorted, s), "gather");
+    HS_HIP(hs::launch_gather(*f, P->perm, P->blocks, P->n_blocks, P->nb_max, P->sorted, s),
+           "gather");
     hs::AdjArgs a{};
     if (sp)
         if (int rc = speckle_prepare(h, P, sp, p0, np, true, chunk, grid_nx, s, a.spk))
@@ -1220,6 +1217,7 @@ static int backward_common(sim_handle *h, sim_plan *P, const sim_facets *f,
     a.np = np;
     a.C = h->C;
     a.n_blocks = P->n_blocks;
+    a.nb_max = P->nb_max;
     a.accumulate = accumulate ? 1 : 0;
     a.rx_exact = h->rx_exact;
     a.steer = h->steer;
@@ -1272,33 +1270,6 @@ int sim_apply_waveform_adjoint(sim_handle *h, const float *g_raw, float *g_rc,
 
 namespace {
 
-// One chunk's facet workspace (8 float32 arrays), library-owned.
-struct ChunkWs {
-    float *buf = nullptr;
-    long long cap = 0;
-    ~ChunkWs() {
-        if (buf) (void)hipFree(buf);
-    }
-    hipError_t ensure(long long n) {
-        if (n <= cap) return hipSuccess;
-        if (buf) (void)hipFree(buf);
-        buf = nullptr;
-        cap = 0;
-        hipError_t e = hipMalloc((void **)&buf, sizeof(float) * 8 * (size_t)n);
-        if (e == hipSuccess) cap = n;
-        return e;
-    }
-    sim_facets_out out(long long n) const {
-        sim_facets_out o;
-        o.n = n;
-        float *q[8];
-        for (int k = 0; k < 8; ++k) q[k] = buf + (size_t)k * (size_t)cap;
-        o.x = q[0]; o.y = q[1]; o.z = q[2]; o.vx = q[3]; o.vy = q[4]; o.vz = q[5];
-        o.a_re = q[6]; o.a_im = q[7];
-        return o;
-    }
-};
-
 int check_chunks(const sim_sea *sea, const int *chunks, int n_chunks, long long *max_n) {
     if (!sea || !chunks || n_chunks < 1) HS_FAIL(SIM_EINVAL, "sea, chunks and n_chunks >= 1 needed");
     long long m = 0;
@@ -1325,77 +1296,156 @@ sim_facets as_in(const sim_facets_out &o) {
 
 extern "C" {
 
-static int stream_forward_common(sim_handle *h, const sim_sea *sea, unsigned long long seed,
-                                 const int *chunks, int n_chunks, double block_edge,
-                                 const sim_speckle *sp, int p0, int np, float *iq,
-                                 int accumulate, void *stream) {
+// Workspace of a streamed call: the sea table, one chunk's facets (8 float32
+// arrays of the largest chunk) and the plan of the largest chunk layout.
+struct StreamLayout {
+    size_t tab = 0, facets = 0, facet_stride = 0, plan = 0, total = 0;
+    std::vector<PlanGeom> geom;     // per chunk
+    std::vector<PlanLayout> lay;    // per chunk
+};
+
+static int stream_layout(const sim_handle *h, const sim_sea *sea, const int *chunks,
+                         int n_chunks, double block_edge, int flags,
+                         const std::vector<double> &tab, StreamLayout &Y) {
+    long long max_n = 0;
+    if (int rc = check_chunks(sea, chunks, n_chunks, &max_n)) return rc;
+    size_t plan_bytes = 0;
+    Y.geom.resize(n_chunks);
+    Y.lay.resize(n_chunks);
+    for (int k = 0; k < n_chunks; ++k) {
+        const int *c = chunks + 4 * k;
+        sim_box box;
+        chunk_box(sea, tab, c[0], c[1], c[2], c[3], &box);
+        const long long n = (long long)c[2] * c[3];
+        if (int rc = plan_geometry(h, n, &box, block_edge, Y.geom[k])) return rc;
+        Y.lay[k] = plan_layout(Y.geom[k], n, flags, h->Np);
+        plan_bytes = std::max(plan_bytes, Y.lay[k].total);
+    }
+    Y.tab = 0;
+    Y.facets = align256(sizeof(double) * tab.size());
+    Y.facet_stride = align256(sizeof(float) * (size_t)max_n);
+    Y.plan = Y.facets + 8 * Y.facet_stride;
+    Y.total = Y.plan + plan_bytes;
+    return SIM_OK;
+}
+
+static sim_facets_out chunk_facets(char *ws, const StreamLayout &Y, long long n) {
+    sim_facets_out o;
+    o.n = n;
+    float *q[8];
+    for (int k = 0; k < 8; ++k) q[k] = (float *)(ws + Y.facets + (size_t)k * Y.facet_stride);
+    o.x = q[0]; o.y = q[1]; o.z = q[2]; o.vx = q[3]; o.vy = q[4]; o.vz = q[5];
+    o.a_re = q[6]; o.a_im = q[7];
+    return o;
+}
+
+int sim_stream_workspace_size(const sim_handle *h, const sim_sea *sea, const int *chunks,
+                              int n_chunks, double block_edge, int flags, size_t *bytes) {
+    if (!h || !bytes) HS_FAIL(SIM_EINVAL, "handle or bytes is NULL");
+    if (flags & ~SIM_PLAN_SPECKLE) HS_FAIL(SIM_EINVAL, "unknown plan flags");
+    if (!sea) HS_FAIL(SIM_EINVAL, "sea is NULL");
+    if (int rc = sea_ok(sea)) return rc;
+    std::vector<double> tab;
+    sea_table(sea, tab);
+    StreamLayout Y;
+    if (int rc = stream_layout(h, sea, chunks, n_chunks, block_edge, flags, tab, Y)) return rc;
+    *bytes = Y.total;
+    return SIM_OK;
+}
+
+// Checks, lays out the workspace and uploads the sea table of a streamed call.
+static int stream_setup(sim_handle *h, const sim_sea *sea, const int *chunks, int n_chunks,
+                        double block_edge, const sim_speckle *sp, int p0, int np, void *ws,
+                        size_t ws_bytes, hipStream_t s, StreamLayout &Y) {
     if (!h) HS_FAIL(SIM_EINVAL, "handle is NULL");
+    if (!sea) HS_FAIL(SIM_EINVAL, "sea is NULL");
     long long max_n = 0;
     if (int rc = check_chunks(sea, chunks, n_chunks, &max_n)) return rc;
     if (p0 < 0 || np < 0 || (long long)p0 + np > h->Np) HS_FAIL(SIM_EINVAL, "pulse range");
     if (int rc = speckle_ok(h, sp)) return rc;
-    if (!iq) HS_FAIL(SIM_EINVAL, "iq is NULL");
+    if (int rc = sea_ok(sea)) return rc;
+    std::vector<double> &tab = h->gen_tab_h;
+    sea_table(sea, tab);
+    const int flags = sp ? SIM_PLAN_SPECKLE : 0;
+    if (int rc = stream_layout(h, sea, chunks, n_chunks, block_edge, flags, tab, Y)) return rc;
+    if (int rc = workspace_ok(ws, ws_bytes, Y.total)) return rc;
     if (int rc = ensure_device(h)) return rc;
+    if (!tab.empty())
+        HS_HIP(hs::launch_upload((double *)((char *)ws + Y.tab), tab.data(), (long long)tab.size(),
+                                 s),
+               "sea table");
+    return SIM_OK;
+}
+
+static int stream_forward_common(sim_handle *h, const sim_sea *sea, unsigned long long seed,
+                                 const int *chunks, int n_chunks, double block_edge,
+                                 const sim_speckle *sp, int p0, int np, float *iq,
+                                 int accumulate, void *ws, size_t ws_bytes, void *stream) {
+    if (!iq) HS_FAIL(SIM_EINVAL, "iq is NULL");
     hipStream_t s = (hipStream_t)stream;
-    ChunkWs ws;
-    HS_HIP(ws.ensure(max_n), "stream workspace");
+    StreamLayout Y;
+    if (int rc = stream_setup(h, sea, chunks, n_chunks, block_edge, sp, p0, np, ws, ws_bytes, s,
+                              Y))
+        return rc;
+    char *w = (char *)ws;
+    const double *tab_d = sea->mode >= 1 ? (const double *)(w + Y.tab) : nullptr;
     if (!accumulate) HS_HIP(hs::launch_fill_zero(iq, 2LL * h->C * np * h->N, s), "zero iq");
+    const int flags = sp ? SIM_PLAN_SPECKLE : 0;
     for (int k = 0; k < n_chunks; ++k) {
         const int *c = chunks + 4 * k;
         const long long n = (long long)c[2] * c[3];
-        const sim_facets_out o = ws.out(n);
-        if (int rc = sim_generate_facets(h, sea, seed, c[0], c[1], c[2], c[3], &o, stream)) return rc;
-        sim_plan *P = nullptr;
-        if (int rc = sim_plan_create(h, o.x, o.y, n, block_edge, stream, &P)) return rc;
+        const sim_facets_out o = chunk_facets(w, Y, n);
+        if (int rc = generate_launch(sea, seed, c[0], c[1], c[2], c[3], &o, tab_d, s)) return rc;
+        sim_plan P;
+        if (int rc = plan_build(h, o.x, o.y, n, Y.geom[k], Y.lay[k], flags, w + Y.plan, s, P))
+            return rc;
         const sim_facets f = as_in(o);
-        int rc = forward_common(h, P, &f, sp, p0, np, iq, 1, stream, c, sea->nx);
-        // the plan's buffers are in use by the queued forward
-        hipError_t e = hipStreamSynchronize(s);
-        sim_plan_destroy(P);
-        if (rc) return rc;
-        HS_HIP(e, "stream sync");
+        if (int rc = forward_common(h, &P, &f, sp, p0, np, iq, 1, stream, c, sea->nx)) return rc;
     }
     return SIM_OK;
 }
 
 int sim_stream_forward(sim_handle *h, const sim_sea *sea, unsigned long long seed,
                        const int *chunks, int n_chunks, double block_edge, int p0, int np,
-                       float *iq, int accumulate, void *stream) {
+                       float *iq, int accumulate, void *workspace, size_t workspace_bytes,
+                       void *stream) {
     return stream_forward_common(h, sea, seed, chunks, n_chunks, block_edge, nullptr, p0, np,
-                                 iq, accumulate, stream);
+                                 iq, accumulate, workspace, workspace_bytes, stream);
 }
 
 int sim_stream_forward_speckle(sim_handle *h, const sim_sea *sea, unsigned long long seed,
                                const int *chunks, int n_chunks, double block_edge,
                                const sim_speckle *speckle, int p0, int np, float *iq,
-                               int accumulate, void *stream) {
+                               int accumulate, void *workspace, size_t workspace_bytes,
+                               void *stream) {
     if (!speckle) HS_FAIL(SIM_EINVAL, "speckle is NULL");
     return stream_forward_common(h, sea, seed, chunks, n_chunks, block_edge, speckle, p0, np,
-                                 iq, accumulate, stream);
+                                 iq, accumulate, workspace, workspace_bytes, stream);
 }
 
 static int stream_backward_common(sim_handle *h, const sim_sea *sea, unsigned long long seed,
                                   const int *chunks, int n_chunks, double block_edge,
                                   const sim_speckle *sp, int p0, int np, const float *g,
-                                  float *dvx, float *dvy, float *dvz, void *stream) {
-    if (!h) HS_FAIL(SIM_EINVAL, "handle is NULL");
-    long long max_n = 0;
-    if (int rc = check_chunks(sea, chunks, n_chunks, &max_n)) return rc;
-    if (p0 < 0 || np < 0 || (long long)p0 + np > h->Np) HS_FAIL(SIM_EINVAL, "pulse range");
+                                  float *dvx, float *dvy, float *dvz, void *ws, size_t ws_bytes,
+                                  void *stream) {
     if (!g) HS_FAIL(SIM_EINVAL, "g is NULL");
-    if (int rc = speckle_ok(h, sp)) return rc;
-    if (int rc = ensure_device(h)) return rc;
     hipStream_t s = (hipStream_t)stream;
-    ChunkWs ws;
-    HS_HIP(ws.ensure(max_n), "stream workspace");
+    StreamLayout Y;
+    if (int rc = stream_setup(h, sea, chunks, n_chunks, block_edge, sp, p0, np, ws, ws_bytes, s,
+                              Y))
+        return rc;
+    char *w = (char *)ws;
+    const double *tab_d = sea->mode >= 1 ? (const double *)(w + Y.tab) : nullptr;
+    const int flags = sp ? SIM_PLAN_SPECKLE : 0;
     long long off = 0;
     for (int k = 0; k < n_chunks; ++k) {
         const int *c = chunks + 4 * k;
         const long long n = (long long)c[2] * c[3];
-        const sim_facets_out o = ws.out(n);
-        if (int rc = sim_generate_facets(h, sea, seed, c[0], c[1], c[2], c[3], &o, stream)) return rc;
-        sim_plan *P = nullptr;
-        if (int rc = sim_plan_create(h, o.x, o.y, n, block_edge, stream, &P)) return rc;
+        const sim_facets_out o = chunk_facets(w, Y, n);
+        if (int rc = generate_launch(sea, seed, c[0], c[1], c[2], c[3], &o, tab_d, s)) return rc;
+        sim_plan P;
+        if (int rc = plan_build(h, o.x, o.y, n, Y.geom[k], Y.lay[k], flags, w + Y.plan, s, P))
+            return rc;
         const sim_facets f = as_in(o);
         sim_facet_grads gr;
         gr.n = n;
@@ -1405,11 +1455,8 @@ static int stream_backward_common(sim_handle *h, const sim_sea *sea, unsigned lo
         gr.dvz = dvz ? dvz + off : nullptr;
         gr.da_re = nullptr;
         gr.da_im = nullptr;
-        int rc = backward_common(h, P, &f, sp, p0, np, g, &gr, 0, stream, c, sea->nx);
-        hipError_t e = hipStreamSynchronize(s);
-        sim_plan_destroy(P);
-        if (rc) return rc;
-        HS_HIP(e, "stream sync");
+        if (int rc = backward_common(h, &P, &f, sp, p0, np, g, &gr, 0, stream, c, sea->nx))
+            return rc;
         off += n;
     }
     return SIM_OK;
@@ -1417,18 +1464,20 @@ static int stream_backward_common(sim_handle *h, const sim_sea *sea, unsigned lo
 
 int sim_stream_backward(sim_handle *h, const sim_sea *sea, unsigned long long seed,
                         const int *chunks, int n_chunks, double block_edge, int p0, int np,
-                        const float *g, float *dvx, float *dvy, float *dvz, void *stream) {
+                        const float *g, float *dvx, float *dvy, float *dvz, void *workspace,
+                        size_t workspace_bytes, void *stream) {
     return stream_backward_common(h, sea, seed, chunks, n_chunks, block_edge, nullptr, p0, np,
-                                  g, dvx, dvy, dvz, stream);
+                                  g, dvx, dvy, dvz, workspace, workspace_bytes, stream);
 }
 
 int sim_stream_backward_speckle(sim_handle *h, const sim_sea *sea, unsigned long long seed,
                                 const int *chunks, int n_chunks, double block_edge,
                                 const sim_speckle *speckle, int p0, int np, const float *g,
-                                float *dvx, float *dvy, float *dvz, void *stream) {
+                                float *dvx, float *dvy, float *dvz, void *workspace,
+                                size_t workspace_bytes, void *stream) {
     if (!speckle) HS_FAIL(SIM_EINVAL, "speckle is NULL");
     return stream_backward_common(h, sea, seed, chunks, n_chunks, block_edge, speckle, p0, np,
-                                  g, dvx, dvy, dvz, stream);
+                                  g, dvx, dvy, dvz, workspace, workspace_bytes, stream);
 }
 
 }  // extern "C"

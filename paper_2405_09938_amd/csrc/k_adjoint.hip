@@ -149,10 +149,14 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
 
     // Workgroups go to the 8 XCDs round-robin by linear index; XCD x takes
     // the contiguous x-th eighth of the (patch-ordered) blocks, so blocks
-    // reading the same range samples of g share that XCD's L2.
-    const unsigned per = gridDim.x >> 3;
+    // reading the same range samples of g share that XCD's L2.  The launch
+    // covers the plan's bound on the block count; the count itself is read
+    // here, and workgroups beyond it return.
+    const int nb = *A.n_blocks;
+    const unsigned per = ((unsigned)nb + 7u) >> 3;
+    if ((blockIdx.x >> 3) >= per) return;
     const long long b = (long long)(blockIdx.x & 7u) * per + (blockIdx.x >> 3);
-    if (b >= A.n_blocks) return;
+    if (b >= nb) return;
     const BlockRec blk = A.blocks[b];
     const int lane = threadIdx.x;
     const bool have = lane < blk.count;
@@ -446,8 +450,8 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
 }  // namespace
 
 hipError_t launch_adjoint(const AdjArgs &a, bool el_const, bool speckle, hipStream_t s) {
-    if (a.n_blocks == 0 || a.np == 0) return hipSuccess;
-    const unsigned long long wgs = ((unsigned long long)a.n_blocks + 7) / 8 * 8;
+    if (a.nb_max == 0 || a.np == 0) return hipSuccess;
+    const unsigned long long wgs = ((unsigned long long)a.nb_max + 7) / 8 * 8;
     if (wgs > 0xffffffffULL) return hipErrorInvalidConfiguration;
     const dim3 grid((unsigned)wgs);
 #define HS_ADJ(E, S, T) hipLaunchKernelGGL((k_adjoint<E, S, T, 0>), grid, dim3(64), 0, s, a)

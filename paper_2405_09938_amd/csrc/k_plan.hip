@@ -19,60 +19,14 @@ __global__ void k_fill_zero(float *p, long long n) {
     for (; i < n; i += stride) p[i] = 0.0f;
 }
 
-// Bounding box: out4 = (min x, max x, min y, max y) as order-preserving
-// integer keys of the float bit patterns; pre-initialised by the host to
-// (INT_MAX, INT_MIN, INT_MAX, INT_MIN).  One atomic per workgroup and value.
-__device__ __forceinline__ int order_key(float v) {
-    const int b = __float_as_int(v);
-    return b >= 0 ? b : (int)(0x80000000u - (unsigned)b);
-}
-
-__global__ void k_bbox(const float *x, const float *y, long long n, int *out4) {
-    float mnx = INFINITY, mxx = -INFINITY, mny = INFINITY, mxy = -INFINITY;
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) {
-        const float a = x[i], b = y[i];
-        mnx = fminf(mnx, a);
-        mxx = fmaxf(mxx, a);
-        mny = fminf(mny, b);
-        mxy = fmaxf(mxy, b);
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        mnx = fminf(mnx, __shfl_xor(mnx, off));
-        mxx = fmaxf(mxx, __shfl_xor(mxx, off));
-        mny = fminf(mny, __shfl_xor(mny, off));
-        mxy = fmaxf(mxy, __shfl_xor(mxy, off));
-    }
-    __shared__ float part[4][4];
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        part[w][0] = mnx;
-        part[w][1] = mxx;
-        part[w][2] = mny;
-        part[w][3] = mxy;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int k = 1; k < 4; ++k) {
-            mnx = fminf(mnx, part[k][0]);
-            mxx = fmaxf(mxx, part[k][1]);
-            mny = fminf(mny, part[k][2]);
-            mxy = fmaxf(mxy, part[k][3]);
-        }
-        atomicMin(out4 + 0, order_key(mnx));
-        atomicMax(out4 + 1, order_key(mxx));
-        atomicMin(out4 + 2, order_key(mny));
-        atomicMax(out4 + 3, order_key(mxy));
-    }
-}
-
-__device__ __forceinline__ int cell_key(float xv, float yv, const Lattice &L) {
-    long long cx = (long long)floor((double)xv / L.edge) - L.bx0;
-    long long cy = (long long)floor((double)yv / L.edge) - L.by0;
-    cx = cx < 0 ? 0 : (cx >= L.nbx ? L.nbx - 1 : cx);
-    cy = cy < 0 ? 0 : (cy >= L.nby ? L.nby - 1 : cy);
+// Key of the cell holding (xv, yv).  A position outside the lattice (or not
+// finite) goes to the nearest edge cell and sets *out.
+__device__ __forceinline__ int cell_key(float xv, float yv, const Lattice &L, bool *out) {
+    const double fx = floor((double)xv / L.edge) - (double)L.bx0;
+    const double fy = floor((double)yv / L.edge) - (double)L.by0;
+    *out = !(fx >= 0.0 && fx < (double)L.nbx && fy >= 0.0 && fy < (double)L.nby);
+    long long cx = fx >= 0.0 ? (fx < (double)L.nbx ? (long long)fx : L.nbx - 1) : 0;
+    long long cy = fy >= 0.0 ? (fy < (double)L.nby ? (long long)fy : L.nby - 1) : 0;
     const long long px = cx / L.px, py = cy / L.py;
     const long long patch = py * L.npx + px;
     return (int)((patch * L.py + (cy - py * L.py)) * L.px + (cx - px * L.px));
@@ -80,13 +34,17 @@ __device__ __forceinline__ int cell_key(float xv, float yv, const Lattice &L) {
 
 // Lanes of a wave holding the same key take their ranks from one atomic:
 // facets arrive in grid order, so a wave covers only a few cells and the
-// per-facet atomics would serialise on the same counters.
+// per-facet atomics would serialise on the same counters.  Facets outside
+// the lattice are counted into *outside (one atomic per wave).
 __global__ void k_cell_keys(const float *x, const float *y, long long n, Lattice L, int *keys,
-                            int *rank, int *count) {
+                            int *rank, int *count, unsigned *outside) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = i < n;
-    const int k = valid ? cell_key(x[i], y[i], L) : -1;
+    bool off = false;
+    const int k = valid ? cell_key(x[i], y[i], L, &off) : -1;
     const int lane = threadIdx.x & 63;
+    const unsigned long long offm = __ballot(valid && off);
+    if (offm && lane == 0) atomicAdd(outside, (unsigned)__popcll(offm));
     const unsigned long long below = (1ull << lane) - 1ull;
     unsigned long long pending = __ballot(valid);
     int r = 0;
@@ -246,9 +204,9 @@ __global__ void k_patch_first(const int *blk_offset, long long n_patches, int ke
 // subtraction of two nearby floats).  The record after the last one is a zero
 // padding record written by the host-side allocation.
 __global__ void k_gather(sim_facets f, const int *perm, const BlockRec *blocks,
-                         long long n_blocks, FacetRec *sorted) {
+                         const int *n_blocks, FacetRec *sorted) {
     const long long b = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (b >= n_blocks) return;
+    if (b >= *n_blocks) return;
     const int lane = threadIdx.x & 63;
     const BlockRec blk = blocks[b];
     if (lane >= blk.count) return;
@@ -266,6 +224,20 @@ __global__ void k_gather(sim_facets f, const int *perm, const BlockRec *blocks,
     sorted[j] = r;
 }
 
+// Host-to-device copy through the kernel argument segment: each launch
+// carries up to kUploadChunk doubles by value.
+constexpr int kUploadChunk = 440;
+struct UploadArgs {
+    double *dst;
+    int n;
+    double v[kUploadChunk];
+};
+static_assert(sizeof(UploadArgs) <= 4096, "kernel arguments too large");
+
+__global__ void k_upload(UploadArgs a) {
+    for (int i = threadIdx.x; i < a.n; i += blockDim.x) a.dst[i] = a.v[i];
+}
+
 inline unsigned grid_for(long long n, int threads) {
     long long g = (n + threads - 1) / threads;
     return (unsigned)(g < 1 ? 1 : g);
@@ -281,18 +253,10 @@ hipError_t launch_fill_zero(float *p, long long n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_bbox(const float *x, const float *y, long long n, int *out4, hipStream_t s) {
-    long long g = (n + 255) / 256;
-    if (g > 256) g = 256;
-    if (g < 1) g = 1;
-    hipLaunchKernelGGL(k_bbox, dim3((unsigned)g), dim3(256), 0, s, x, y, n, out4);
-    return hipGetLastError();
-}
-
 hipError_t launch_cell_keys(const float *x, const float *y, long long n, const Lattice &L,
-                            int *keys, int *rank, int *count, hipStream_t s) {
+                            int *keys, int *rank, int *count, unsigned *outside, hipStream_t s) {
     hipLaunchKernelGGL(k_cell_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, n, L, keys,
-                       rank, count);
+                       rank, count, outside);
     return hipGetLastError();
 }
 
@@ -339,11 +303,25 @@ hipError_t launch_patch_first(const int *blk_offset, long long n_patches, int ke
 }
 
 hipError_t launch_gather(const sim_facets &f, const int *perm, const BlockRec *blocks,
-                         long long n_blocks, FacetRec *sorted, hipStream_t s) {
-    if (n_blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather, dim3(grid_for(n_blocks, 4)), dim3(256), 0, s, f, perm, blocks,
+                         const int *n_blocks, long long nb_max, FacetRec *sorted,
+                         hipStream_t s) {
+    if (nb_max == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(nb_max, 4)), dim3(256), 0, s, f, perm, blocks,
                        n_blocks, sorted);
     return hipGetLastError();
+}
+
+hipError_t launch_upload(double *dst, const double *src, long long n, hipStream_t s) {
+    for (long long o = 0; o < n; o += kUploadChunk) {
+        UploadArgs a;
+        a.dst = dst + o;
+        a.n = (int)(n - o < kUploadChunk ? n - o : kUploadChunk);
+        for (int i = 0; i < a.n; ++i) a.v[i] = src[o + i];
+        hipLaunchKernelGGL(k_upload, dim3(1), dim3(256), 0, s, a);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace hs

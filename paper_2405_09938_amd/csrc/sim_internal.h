@@ -143,7 +143,8 @@ struct AdjArgs {
     double f0_c, fs_c, n_ref;
     float linv_hi, linv_lo, fs_cf, k0;
     int N, Np, p0, np, C;
-    long long n_blocks;
+    const int *n_blocks;        // device: number of blocks (the plan's block count)
+    long long nb_max;           // host bound on it (the launch covers this many)
     int accumulate;
     int rx_exact;               // receiver at each facet's own echo time
     int steer;                  // some antenna frame turns with time
@@ -189,46 +190,30 @@ struct sim_handle {
     hs::PulseRec *pulses_d = nullptr;
     float *chirp_spec_d = nullptr;      // [M] complex64: FFT_M(chirp) / M
     float *twiddle_d = nullptr;         // [M] complex64: exp(-2 pi i m / M)
-    double *gen_tab_d = nullptr;        // wave component table of the generator
-    size_t gen_tab_cap = 0;
-    std::vector<double> gen_tab_h;
-    // device buffers reused by sim_plan_create for its temporaries
-    std::vector<std::pair<void *, size_t>> scratch_pool;
-    // device buffers of destroyed plans, reusable by later plans once the
-    // events recorded at their destruction (on every stream that read them)
-    // have completed; a later plan's stream waits for those events
-    struct PooledBuf {
-        void *p;
-        size_t bytes;
-        std::shared_ptr<std::vector<hipEvent_t>> after;
-    };
-    std::vector<PooledBuf> plan_pool;
-    int live_plans = 0;          // plans not yet destroyed
-    bool destroy_pending = false;   // sim_destroy called while plans were alive
+    std::vector<double> gen_tab_h;       // host scratch for sea tables
 };
 
 struct sim_plan {
-    sim_handle *h;
+    const sim_handle *h;
     long long n;                 // facets
-    long long n_blocks;
+    long long nb_max;            // bound on the block count (size of `blocks`)
     long long n_patches;
+    int flags;                   // SIM_PLAN_* flags the workspace was laid out for
     hs::Lattice lat;
     int halo;                    // range-window halo in samples (heights, drift)
     int win;                     // LDS range-window width of the forward kernel
     bool el_const = false;       // elevation factors taken at block centres
     double el_bound = 0.0;       // bound on the relative error of doing so
+    hipStream_t stream = nullptr;   // stream the plan was built on
+    // every buffer lies in the caller's workspace
     int *perm = nullptr;         // [n] sorted position -> facet index
-    hs::BlockRec *blocks = nullptr;     // [n_blocks]
+    hs::BlockRec *blocks = nullptr;     // [nb_max], the first *n_blocks valid
+    const int *n_blocks = nullptr;      // device: block count
+    unsigned *n_outside = nullptr;      // device: facets outside the plan's box
     int *patch_first = nullptr;  // [n_patches + 1]
-    hs::FacetRec *sorted = nullptr;     // [n] scratch refreshed by each call
-    hs::SpkRec *spk = nullptr;          // [n + 1] speckle records (speckle calls only)
+    hs::FacetRec *sorted = nullptr;     // [n + 1] scratch refreshed by each call
+    hs::SpkRec *spk = nullptr;          // [n + 1] speckle records (SIM_PLAN_SPECKLE)
     float4 *anch = nullptr;             // [n + 1][ceil(Np/64) + 1] speckle anchors
-    // byte capacity of each buffer (they may come from the handle's pool)
-    size_t perm_cap = 0, blocks_cap = 0, patch_first_cap = 0, sorted_cap = 0;
-    size_t spk_cap = 0, anch_cap = 0;
-    // per stream that used the buffers, an event recorded after its last use
-    std::vector<std::pair<hipStream_t, hipEvent_t>> uses;
-    bool uses_ok = true;         // every use could be recorded
 };
 
 // ---- launchers (each returns hipError_t of the launch) --------------------
@@ -239,10 +224,8 @@ void set_error(const std::string &msg);
 hipError_t launch_fill_zero(float *p, long long n_floats, hipStream_t s);
 
 // Plan construction kernels.
-hipError_t launch_bbox(const float *x, const float *y, long long n, int *out4,
-                       hipStream_t s);
 hipError_t launch_cell_keys(const float *x, const float *y, long long n, const Lattice &L,
-                            int *keys, int *rank, int *count, hipStream_t s);
+                            int *keys, int *rank, int *count, unsigned *outside, hipStream_t s);
 hipError_t launch_exclusive_scan(const int *in, int *out, long long n, int *tmp,
                                  long long tmp_len, hipStream_t s);
 long long scan_tmp_len(long long n);
@@ -255,7 +238,10 @@ hipError_t launch_make_blocks(const int *count, const int *offset, const int *bl
 hipError_t launch_patch_first(const int *blk_offset, long long n_patches, int keys_per_patch,
                               long long n_keys, int *patch_first, hipStream_t s);
 hipError_t launch_gather(const sim_facets &f, const int *perm, const BlockRec *blocks,
-                         long long n_blocks, FacetRec *sorted, hipStream_t s);
+                         const int *n_blocks, long long nb_max, FacetRec *sorted, hipStream_t s);
+// Copies n doubles from host memory to device memory through kernel
+// arguments (stream-ordered, no pinned buffer and no host wait).
+hipError_t launch_upload(double *dst, const double *src, long long n, hipStream_t s);
 
 // Speckle records and anchors of the sorted facets for absolute pulse groups
 // [g_lo, g_hi] (anchors g_lo .. g_hi + 1; with_d adds D_g = y_{g+1} - z_64).

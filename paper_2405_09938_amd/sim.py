@@ -30,6 +30,15 @@ def _fptr(t: Optional[torch.Tensor]):
     return ctypes.cast(t.data_ptr(), ctypes.POINTER(ctypes.c_float))
 
 
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    """Caller-owned device workspace (torch allocations are 512-byte aligned)."""
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def _box(b) -> "N.SimBox":
+    return N.SimBox(float(b[0]), float(b[1]), float(b[2]), float(b[3]))
+
+
 def _check_f32(t: torch.Tensor, n: int, name: str, device) -> torch.Tensor:
     if t.dtype != torch.float32 or t.device != device or t.numel() != n:
         raise ValueError(f"{name}: need a float32 tensor of {n} elements on {device}")
@@ -119,15 +128,52 @@ class Simulator:
         s = N.SimFacets(n, *[_fptr(t) for t in keep])
         return s, keep
 
-    def plan(self, x: torch.Tensor, y: torch.Tensor, block_edge: float = 8.0) -> "Plan":
+    def device_init(self):
+        """Upload the handle's constant tables (the one synchronising set-up step)."""
+        N.check(self.lib.sim_device_init(self.handle), "sim_device_init")
+
+    def workspace_size(self, n: int, box, block_edge: float = 8.0, speckle: bool = False) -> int:
+        b = ctypes.c_size_t()
+        bx = _box(box)
+        N.check(self.lib.sim_workspace_size(self.handle, int(n), ctypes.byref(bx),
+                                            float(block_edge),
+                                            N.SIM_PLAN_SPECKLE if speckle else 0,
+                                            ctypes.byref(b)), "sim_workspace_size")
+        return b.value
+
+    def plan(self, x: torch.Tensor, y: torch.Tensor, block_edge: float = 8.0, box=None,
+             speckle: bool = False) -> "Plan":
+        """Plan of the facet set (x, y) in a workspace allocated here.  box =
+        (x_min, x_max, y_min, y_max) of the positions (taken from x, y when
+        None, which waits for the stream); speckle makes room for the
+        intra-facet speckle."""
         n = x.numel()
         x = _check_f32(x, n, "x", self.device)
         y = _check_f32(y, n, "y", self.device)
+        if box is None:
+            xa, ya = torch.aminmax(x), torch.aminmax(y)
+            box = (float(xa.min), float(xa.max), float(ya.min), float(ya.max))
+        flags = N.SIM_PLAN_SPECKLE if speckle else 0
+        ws = _workspace(self.workspace_size(n, box, block_edge, speckle), self.device)
+        bx = _box(box)
         p = ctypes.c_void_p()
         N.check(self.lib.sim_plan_create(self.handle, ctypes.c_void_p(x.data_ptr()),
-                                         ctypes.c_void_p(y.data_ptr()), n, float(block_edge),
+                                         ctypes.c_void_p(y.data_ptr()), n, ctypes.byref(bx),
+                                         float(block_edge), flags,
+                                         ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                          _stream(), ctypes.byref(p)), "sim_plan_create")
-        return Plan(self, p, n)
+        return Plan(self, p, n, ws, tuple(box))
+
+    def chunk_box(self, sea, ix0: int = 0, iy0: int = 0, cnx: Optional[int] = None,
+                  cny: Optional[int] = None):
+        """Rectangle holding every facet generated for a grid sub-rectangle."""
+        cnx = sea.nx - ix0 if cnx is None else cnx
+        cny = sea.ny - iy0 if cny is None else cny
+        s, keep = self._sea_struct(sea)
+        bx = N.SimBox()
+        N.check(self.lib.sim_chunk_box(ctypes.byref(s), ix0, iy0, cnx, cny, ctypes.byref(bx)),
+                "sim_chunk_box")
+        return (bx.x_min, bx.x_max, bx.y_min, bx.y_max)
 
     @staticmethod
     def _sea_struct(sea):
@@ -164,9 +210,14 @@ class Simulator:
         n = cnx * cny
         out = {k: torch.empty(n, dtype=torch.float32, device=self.device) for k in FACET_KEYS}
         s, keep = self._sea_struct(sea)
+        b = ctypes.c_size_t()
+        N.check(self.lib.sim_sea_table_size(ctypes.byref(s), ctypes.byref(b)), "sim_sea_table_size")
+        ws = _workspace(b.value, self.device)
         fo = N.SimFacetsOut(n, *[_fptr(out[k]) for k in FACET_KEYS])
         N.check(self.lib.sim_generate_facets(self.handle, ctypes.byref(s), int(seed), ix0, iy0,
-                                             cnx, cny, ctypes.byref(fo), _stream()),
+                                             cnx, cny, ctypes.byref(fo),
+                                             ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                             _stream()),
                 "sim_generate_facets")
         del keep
         return out
@@ -177,13 +228,36 @@ class Simulator:
         flat = [int(v) for c in chunks for v in c]
         return (ctypes.c_int * len(flat))(*flat), len(chunks)
 
+    def stream_workspace_size(self, sea, chunks, block_edge: float = 8.0,
+                              speckle: bool = False) -> int:
+        s, keep = self._sea_struct(sea)
+        ca, nc = self._chunk_array(chunks)
+        b = ctypes.c_size_t()
+        N.check(self.lib.sim_stream_workspace_size(self.handle, ctypes.byref(s), ca, nc,
+                                                   float(block_edge),
+                                                   N.SIM_PLAN_SPECKLE if speckle else 0,
+                                                   ctypes.byref(b)),
+                "sim_stream_workspace_size")
+        return b.value
+
+    def _stream_ws(self, sea, chunks, block_edge, speckle, workspace):
+        need = self.stream_workspace_size(sea, chunks, block_edge, speckle)
+        if workspace is None:
+            workspace = _workspace(need, self.device)
+        elif workspace.numel() < need or workspace.device != self.device:
+            raise ValueError(f"workspace needs {need} bytes on {self.device}")
+        return workspace
+
     def stream_forward(self, sea, seed: int, chunks, block_edge: float = 8.0, p0: int = 0,
                        np_: Optional[int] = None, out: Optional[torch.Tensor] = None,
                        accumulate: bool = False, speckle=None,
-                       f_s: Optional[torch.Tensor] = None) -> torch.Tensor:
+                       f_s: Optional[torch.Tensor] = None,
+                       workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
         """IQ_rc of the scene made of `chunks` = [(ix0, iy0, cnx, cny), ...];
         with `speckle` the intra-facet speckle sum, facet ids and f_s (float32
-        device [ny * nx] or None) taken by grid index."""
+        device [ny * nx] or None) taken by grid index.  workspace: uint8
+        device tensor of at least stream_workspace_size bytes (allocated here
+        when None)."""
         np_ = self.n_pulses - p0 if np_ is None else np_
         shape = (self.n_channels, np_, self.n_samples)
         if out is None:
@@ -191,28 +265,31 @@ class Simulator:
             accumulate = False
         elif out.shape != shape or out.dtype != torch.complex64 or not out.is_contiguous():
             raise ValueError(f"out must be a contiguous complex64 tensor of shape {shape}")
+        ws = self._stream_ws(sea, chunks, block_edge, speckle is not None, workspace)
+        wsp, wsn = ctypes.c_void_p(ws.data_ptr()), ws.numel()
         s, keep = self._sea_struct(sea)
         ca, nc = self._chunk_array(chunks)
         if speckle is None:
             N.check(self.lib.sim_stream_forward(self.handle, ctypes.byref(s), int(seed), ca, nc,
                                                 float(block_edge), p0, np_,
                                                 ctypes.c_void_p(out.data_ptr()),
-                                                int(accumulate), _stream()),
+                                                int(accumulate), wsp, wsn, _stream()),
                     "sim_stream_forward")
         else:
             sp, f_keep = self._speckle_struct(speckle, f_s, int(sea.nx) * int(sea.ny))
             N.check(self.lib.sim_stream_forward_speckle(
                 self.handle, ctypes.byref(s), int(seed), ca, nc, float(block_edge),
                 ctypes.byref(sp), p0, np_, ctypes.c_void_p(out.data_ptr()), int(accumulate),
-                _stream()), "sim_stream_forward_speckle")
+                wsp, wsn, _stream()), "sim_stream_forward_speckle")
         return out
 
     def stream_backward(self, sea, seed: int, chunks, g_rc: torch.Tensor,
                         block_edge: float = 8.0, p0: int = 0,
                         np_: Optional[int] = None, speckle=None,
-                        f_s: Optional[torch.Tensor] = None) -> Dict[str, torch.Tensor]:
+                        f_s: Optional[torch.Tensor] = None,
+                        workspace: Optional[torch.Tensor] = None) -> Dict[str, torch.Tensor]:
         """dL/dV of every facet of the streamed scene, chunk after chunk
-        (speckle and f_s as in stream_forward)."""
+        (speckle, f_s and workspace as in stream_forward)."""
         np_ = self.n_pulses - p0 if np_ is None else np_
         shape = (self.n_channels, np_, self.n_samples)
         if g_rc.shape != shape or g_rc.dtype != torch.complex64:
@@ -221,6 +298,8 @@ class Simulator:
         n = sum(int(c[2]) * int(c[3]) for c in chunks)
         out = {k: torch.empty(n, dtype=torch.float32, device=self.device)
                for k in ("vx", "vy", "vz")}
+        ws = self._stream_ws(sea, chunks, block_edge, speckle is not None, workspace)
+        wsp, wsn = ctypes.c_void_p(ws.data_ptr()), ws.numel()
         s, keep = self._sea_struct(sea)
         ca, nc = self._chunk_array(chunks)
         outs = [ctypes.c_void_p(out[k].data_ptr()) for k in ("vx", "vy", "vz")]
@@ -228,13 +307,13 @@ class Simulator:
             N.check(self.lib.sim_stream_backward(self.handle, ctypes.byref(s), int(seed), ca, nc,
                                                  float(block_edge), p0, np_,
                                                  ctypes.c_void_p(g_rc.data_ptr()), *outs,
-                                                 _stream()), "sim_stream_backward")
+                                                 wsp, wsn, _stream()), "sim_stream_backward")
         else:
             sp, f_keep = self._speckle_struct(speckle, f_s, int(sea.nx) * int(sea.ny))
             N.check(self.lib.sim_stream_backward_speckle(
                 self.handle, ctypes.byref(s), int(seed), ca, nc, float(block_edge),
-                ctypes.byref(sp), p0, np_, ctypes.c_void_p(g_rc.data_ptr()), *outs, _stream()),
-                "sim_stream_backward_speckle")
+                ctypes.byref(sp), p0, np_, ctypes.c_void_p(g_rc.data_ptr()), *outs, wsp, wsn,
+                _stream()), "sim_stream_backward_speckle")
         return out
 
     # -- the facet sum and its adjoint -----------------------------------------
@@ -317,18 +396,35 @@ class Simulator:
 
 
 class Plan:
-    """Block decomposition of one facet set (depends on x, y only)."""
+    """Block decomposition of one facet set (depends on x, y only); its
+    device buffers are the workspace tensor it holds."""
 
-    def __init__(self, sim: Simulator, ptr: ctypes.c_void_p, n: int):
-        self.sim, self.ptr, self.n = sim, ptr, n
-        a, b, c = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_longlong()
-        N.check(sim.lib.sim_plan_info(ptr, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
-                "sim_plan_info")
-        self.n_blocks, self.n_patches = b.value, c.value
+    def __init__(self, sim: Simulator, ptr: ctypes.c_void_p, n: int, workspace: torch.Tensor,
+                 box):
+        self.sim, self.ptr, self.n, self.workspace, self.box = sim, ptr, n, workspace, box
+        c = ctypes.c_longlong()
+        N.check(sim.lib.sim_plan_info(ptr, None, None, ctypes.byref(c), None), "sim_plan_info")
+        self.n_patches = c.value
         m, bound = ctypes.c_int(), ctypes.c_double()
         N.check(sim.lib.sim_plan_mode(ptr, ctypes.byref(m), ctypes.byref(bound)), "sim_plan_mode")
         # elevation factors taken at block centres (error bound el_bound)
         self.el_const, self.el_bound = bool(m.value), bound.value
+
+    def _counts(self):
+        b, o = ctypes.c_longlong(), ctypes.c_longlong()
+        N.check(self.sim.lib.sim_plan_info(self.ptr, None, ctypes.byref(b), None,
+                                           ctypes.byref(o)), "sim_plan_info")
+        return b.value, o.value
+
+    @property
+    def n_blocks(self) -> int:
+        """Number of blocks (read back from the device: waits for the plan's stream)."""
+        return self._counts()[0]
+
+    @property
+    def n_outside(self) -> int:
+        """Facets outside the plan's box (read back from the device)."""
+        return self._counts()[1]
 
     def close(self):
         if getattr(self, "ptr", None):

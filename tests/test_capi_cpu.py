@@ -13,6 +13,11 @@ import pytest
 import workloads as W
 import oracle as O
 
+# A stand-in workspace (aligned address, ample size) for checks that fail
+# before any device work; nothing is ever written through it here.
+WS = ctypes.c_void_p(1 << 20)
+WSN = 1 << 40
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "heeps_sim.h")
 LIB = os.path.join(ROOT, "paper_2405_09938_amd", "libheeps_sim.so")
@@ -128,7 +133,10 @@ def test_create_validates_pattern_grids(native):
 def test_entry_points_reject_null(native):
     L = native.load()
     p = ctypes.c_void_p()
-    assert L.sim_plan_create(None, None, None, 10, 8.0, None, ctypes.byref(p)) == native.SIM_EINVAL
+    assert L.sim_plan_create(None, None, None, 10, None, 8.0, 0, None, 0, None,
+                             ctypes.byref(p)) == native.SIM_EINVAL
+    assert L.sim_device_init(None) == native.SIM_EINVAL
+    assert L.sim_plan_info(None, None, None, None, None) == native.SIM_EINVAL
     assert L.sim_forward(None, None, None, 0, 1, None, 0, None) == native.SIM_EINVAL
     assert L.sim_backward(None, None, None, 0, 1, None, None, 0, None) == native.SIM_EINVAL
     assert L.sim_apply_waveform(None, None, None, 1, None) == native.SIM_EINVAL
@@ -201,38 +209,50 @@ def test_stream_entry_points_validate(native):
         for c in bad:
             arr = (ctypes.c_int * 4)(*c)
             rc = L.sim_stream_forward(h, ctypes.byref(sea), 1, arr, 1, 8.0, 0, 8,
-                                      ctypes.c_void_p(16), 0, None)
+                                      ctypes.c_void_p(16), 0, WS, WSN, None)
             assert rc == native.SIM_EINVAL, c
         ok = (ctypes.c_int * 4)(0, 0, 10, 10)
         assert L.sim_stream_forward(h, None, 1, ok, 1, 8.0, 0, 8, ctypes.c_void_p(16), 0,
-                                    None) == native.SIM_EINVAL
+                                    WS, WSN, None) == native.SIM_EINVAL
         assert L.sim_stream_forward(h, ctypes.byref(sea), 1, ok, 1, 8.0, 4, 8,
-                                    ctypes.c_void_p(16), 0, None) == native.SIM_EINVAL
+                                    ctypes.c_void_p(16), 0, WS, WSN, None) == native.SIM_EINVAL
         assert L.sim_stream_backward(h, ctypes.byref(sea), 1, ok, 0, 8.0, 0, 8, None, None,
-                                     None, None, None) == native.SIM_EINVAL
+                                     None, None, WS, WSN, None) == native.SIM_EINVAL
+        # a workspace that is missing, misaligned or too small
+        need = ctypes.c_size_t()
+        assert L.sim_stream_workspace_size(h, ctypes.byref(sea), ok, 1, 8.0, 0,
+                                           ctypes.byref(need)) == native.SIM_OK
+        for ws, wsn, msg in ((None, WSN, "NULL"), (ctypes.c_void_p(4096 + 16), WSN, "aligned"),
+                             (WS, need.value - 1, "too small")):
+            assert L.sim_stream_forward(h, ctypes.byref(sea), 1, ok, 1, 8.0, 0, 8,
+                                        ctypes.c_void_p(16), 0, ws, wsn,
+                                        None) == native.SIM_EINVAL
+            assert msg in L.sim_last_error().decode(), msg
         # speckle variants: NULL speckle, bad tau_s or first_index, then the
         # stream checks as above
         assert L.sim_stream_forward_speckle(h, ctypes.byref(sea), 1, ok, 1, 8.0, None, 0, 8,
-                                            ctypes.c_void_p(16), 0, None) == native.SIM_EINVAL
+                                            ctypes.c_void_p(16), 0, WS, WSN,
+                                            None) == native.SIM_EINVAL
         assert "speckle is NULL" in L.sim_last_error().decode()
         assert L.sim_stream_backward_speckle(h, ctypes.byref(sea), 1, ok, 1, 8.0, None, 0, 8,
                                              ctypes.c_void_p(16), None, None, None,
-                                             None) == native.SIM_EINVAL
+                                             WS, WSN, None) == native.SIM_EINVAL
         for sp, msg in ((native.SimSpeckle(0.0, 1, 0, None), "tau_s"),
                         (native.SimSpeckle(float("nan"), 1, 0, None), "tau_s"),
                         (native.SimSpeckle(0.02, 1, -1, None), "first_index")):
             assert L.sim_stream_forward_speckle(h, ctypes.byref(sea), 1, ok, 1, 8.0,
                                                 ctypes.byref(sp), 0, 8, ctypes.c_void_p(16), 0,
-                                                None) == native.SIM_EINVAL
+                                                WS, WSN, None) == native.SIM_EINVAL
             assert msg in L.sim_last_error().decode()
             assert L.sim_stream_backward_speckle(h, ctypes.byref(sea), 1, ok, 1, 8.0,
                                                  ctypes.byref(sp), 0, 8, ctypes.c_void_p(16),
-                                                 None, None, None, None) == native.SIM_EINVAL
+                                                 None, None, None, WS, WSN,
+                                                 None) == native.SIM_EINVAL
         sp = native.SimSpeckle(0.02, 1, 0, None)
         arr = (ctypes.c_int * 4)(90, 0, 20, 10)
         assert L.sim_stream_forward_speckle(h, ctypes.byref(sea), 1, arr, 1, 8.0,
                                             ctypes.byref(sp), 0, 8, ctypes.c_void_p(16), 0,
-                                            None) == native.SIM_EINVAL
+                                            WS, WSN, None) == native.SIM_EINVAL
         assert "chunk" in L.sim_last_error().decode()
     finally:
         L.sim_destroy(h)
@@ -273,7 +293,7 @@ def test_generate_validates_sea_before_any_device_call(native):
 
         def rc(s):
             return L.sim_generate_facets(h, ctypes.byref(s), 1, 0, 0, 40, 30, ctypes.byref(out),
-                                         None)
+                                         WS, WSN, None)
 
         assert rc(sea2(mode=3)) == native.SIM_EINVAL
         assert rc(sea2(tile_x0=het.tile_x0 + 5.0)) == native.SIM_EINVAL
@@ -287,5 +307,81 @@ def test_generate_validates_sea_before_any_device_call(native):
         assert rc(sea2(node_hs=neg.ctypes.data_as(dp))) == native.SIM_EINVAL
         # a valid description passes validation and then needs a device
         assert rc(sea2()) != native.SIM_EINVAL
+        # ... and a workspace for its wave table
+        tb = ctypes.c_size_t()
+        assert L.sim_sea_table_size(ctypes.byref(sea2()), ctypes.byref(tb)) == native.SIM_OK
+        assert tb.value >= 8 * 6 * het.n_comp * (het.ntx + 1) * (het.nty + 1)
+        assert L.sim_generate_facets(h, ctypes.byref(sea2()), 1, 0, 0, 40, 30, ctypes.byref(out),
+                                     None, 0, None) == native.SIM_EINVAL
+        assert b"workspace" in L.sim_last_error()
+    finally:
+        L.sim_destroy(h)
+
+
+def test_workspace_sizes(native):
+    """Workspace size queries (host only): the plan's bytes grow with the
+    facet count and the scene rectangle, the speckle flag adds its records and
+    anchors, a generated chunk's box holds its cell centres (widened by the
+    CWM displacement), and plan creation refuses a missing, misaligned or
+    short workspace before any device work."""
+    L = native.load()
+    g = W.harmony_geometry(256, 512)
+    cfg, keep = _config(native, g)
+    h = ctypes.c_void_p()
+    assert L.sim_create(ctypes.byref(cfg), ctypes.byref(h)) == native.SIM_OK
+    try:
+        def size(n, box, edge=8.0, flags=0):
+            b = ctypes.c_size_t()
+            bx = native.SimBox(*box)
+            rc = L.sim_workspace_size(h, n, ctypes.byref(bx), edge, flags, ctypes.byref(b))
+            return rc, b.value
+        rc, s0 = size(4096, (-160.0, 160.0, -160.0, 160.0))
+        assert rc == native.SIM_OK
+        # permutation + sorted records alone are 36 bytes per facet
+        assert s0 >= 36 * 4096
+        assert size(8192, (-160.0, 160.0, -160.0, 160.0))[1] > s0
+        assert size(4096, (-640.0, 640.0, -640.0, 640.0))[1] > s0
+        rc, s1 = size(4096, (-160.0, 160.0, -160.0, 160.0), flags=native.SIM_PLAN_SPECKLE)
+        assert rc == native.SIM_OK
+        groups = (256 + 63) // 64 + 1
+        assert s1 - s0 >= 4097 * (8 + 16 * groups)
+        for bad in ((0, (-1.0, 1.0, -1.0, 1.0)), (10, (1.0, -1.0, -1.0, 1.0)),
+                    (10, (float("nan"), 1.0, -1.0, 1.0)), (10, (-1.0, float("inf"), -1.0, 1.0))):
+            assert size(*bad)[0] == native.SIM_EINVAL, bad
+        assert size(10, (-1.0, 1.0, -1.0, 1.0), edge=0.0)[0] == native.SIM_EINVAL
+        assert size(10, (-1.0, 1.0, -1.0, 1.0), flags=2)[0] == native.SIM_EINVAL
+        # a lattice of more than 2^28 cells
+        assert size(10, (-1e6, 1e6, -1e6, 1e6), edge=1.0)[0] == native.SIM_EUNSUPPORTED
+        # plan creation: workspace checks come before any device call
+        bx = native.SimBox(-160.0, 160.0, -160.0, 160.0)
+        p = ctypes.c_void_p()
+        fake = ctypes.c_void_p(1 << 24)
+        for ws, n_ws, msg in ((None, s0, "NULL"), (ctypes.c_void_p((1 << 24) + 64), s0, "aligned"),
+                              (fake, s0 - 1, "too small")):
+            assert L.sim_plan_create(h, fake, fake, 4096, ctypes.byref(bx), 8.0, 0, ws, n_ws,
+                                     None, ctypes.byref(p)) == native.SIM_EINVAL
+            assert msg in L.sim_last_error().decode(), msg
+        # generated chunks: the box holds the chunk's cell centres
+        sea = W.wave_sea(120, 80, 1.0, seed=5, current_speed=0.5)
+        from paper_2405_09938_amd.sim import Simulator   # the binding's struct marshalling
+        s, skeep = Simulator._sea_struct(sea)
+        b = native.SimBox()
+        assert L.sim_chunk_box(ctypes.byref(s), 60, 40, 60, 40, ctypes.byref(b)) == native.SIM_OK
+        xs = (np.arange(60, 120) - 59.5) * 1.0
+        ys = (np.arange(40, 80) - 39.5) * 1.0
+        assert b.x_min <= xs.min() and b.x_max >= xs.max()
+        assert b.y_min <= ys.min() and b.y_max >= ys.max()
+        assert b.x_max - b.x_min < 59.0 + 0.01 and b.y_max - b.y_min < 39.0 + 0.01
+        s.cwm = 1
+        bc = native.SimBox()
+        assert L.sim_chunk_box(ctypes.byref(s), 60, 40, 60, 40, ctypes.byref(bc)) == native.SIM_OK
+        assert bc.x_min < b.x_min - 0.1 and bc.y_max > b.y_max + 0.1
+        assert L.sim_chunk_box(ctypes.byref(s), 60, 40, 61, 40, ctypes.byref(bc)) == native.SIM_EINVAL
+        # streamed workspace: table + 8 arrays of the largest chunk + its plan
+        chunks = (ctypes.c_int * 8)(0, 0, 60, 40, 60, 40, 60, 40)
+        ns = ctypes.c_size_t()
+        assert L.sim_stream_workspace_size(h, ctypes.byref(s), chunks, 2, 8.0, 0,
+                                           ctypes.byref(ns)) == native.SIM_OK
+        assert ns.value >= 32 * 2400 + 36 * 2400
     finally:
         L.sim_destroy(h)

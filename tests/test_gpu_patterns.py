@@ -143,7 +143,7 @@ def test_patterns_with_steering_speckle_rx_exact(env):
     fsd = torch.from_numpy(fs).cuda()
     sim = hs.Simulator(g)
     d = dev(torch, f)
-    plan = sim.plan(d["x"], d["y"], 8.0)
+    plan = sim.plan(d["x"], d["y"], 8.0, speckle=True)
     got = sim.forward(plan, d, 20, 100, speckle=sp, f_s=fsd).cpu().numpy()
     F = f64(f)
     ref = O.forward(g, F, 20, 100, speckle=sp, f_s=fs.astype(np.float64))

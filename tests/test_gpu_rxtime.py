@@ -116,7 +116,7 @@ def test_rx_exact_with_speckle_exact_elevation_mode(env):
     fsd = torch.from_numpy(fs).cuda()
     sim = hs.Simulator(g)
     d = dev(torch, f)
-    plan = sim.plan(d["x"], d["y"], 2.0)
+    plan = sim.plan(d["x"], d["y"], 2.0, speckle=True)
     assert not plan.el_const
     got = sim.forward(plan, d, 3, 60, speckle=sp, f_s=fsd).cpu().numpy()
     F = f64(f)

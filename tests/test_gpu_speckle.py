@@ -60,7 +60,7 @@ def fs_pair(torch, n, seed):
 def speckle_forward(torch, hs, g, f, edge, sp, fs_dev, p0=0, np_=None):
     sim = hs.Simulator(g)
     d = dev(torch, f)
-    plan = sim.plan(d["x"], d["y"], edge)
+    plan = sim.plan(d["x"], d["y"], edge, speckle=True)
     iq = sim.forward(plan, d, p0, np_, speckle=sp, f_s=fs_dev)
     torch.cuda.synchronize()
     return iq.cpu().numpy().astype(np.complex128), sim, plan, d
@@ -167,7 +167,7 @@ def test_speckle_adjoint_vs_oracle_midgroup(env):
     gi = gi.astype(np.complex64)
     sim = hs.Simulator(g)
     d = dev(torch, f)
-    plan = sim.plan(d["x"], d["y"], 8.0)
+    plan = sim.plan(d["x"], d["y"], 8.0, speckle=True)
     gr = sim.backward(plan, d, torch.from_numpy(gi).cuda(), 37, 100, speckle=sp, f_s=fsd)
     torch.cuda.synchronize()
     ref = O.adjoint(g, f64(f), gi.astype(np.complex128), 37, 100, speckle=sp, f_s=fsh)
@@ -191,7 +191,7 @@ def test_speckle_autograd_vs_oracle_fd(env):
     sim = hs.Simulator(g)
     d = dev(torch, f)
     dt = dev(torch, ft)
-    plan = sim.plan(d["x"], d["y"], 8.0)
+    plan = sim.plan(d["x"], d["y"], 8.0, speckle=True)
     with torch.no_grad():
         tgt = sim.forward(plan, dt, speckle=sp, f_s=fsd)
     for k in GKEYS:
@@ -224,7 +224,7 @@ def test_speckle_workload2_full_rows(env):
     g = wl.geometry
     sim = hs.Simulator(g)
     f = sim.generate(wl.sea, wl.seed)
-    plan = sim.plan(f["x"], f["y"], wl.block_edge)
+    plan = sim.plan(f["x"], f["y"], wl.block_edge, speckle=True)
     sp = W.Speckle(tau_s=W.SPECKLE_TAU_S, seed=wl.seed, first_index=0)
     n = f["x"].numel()
     fsd, fsh = fs_pair(torch, n, wl.seed)
@@ -250,7 +250,7 @@ def test_speckle_edges(env):
     f = W.iid_facets(30, 30, 2.0, seed=9, sigma_z=0.3)
     sim = hs.Simulator(g)
     d = dev(torch, f)
-    plan = sim.plan(d["x"], d["y"], 8.0)
+    plan = sim.plan(d["x"], d["y"], 8.0, speckle=True)
     sp = W.Speckle(tau_s=0.02, seed=77, first_index=2 ** 32 - 450)
     zero = torch.zeros(900, dtype=torch.float32, device="cuda")
     a = sim.forward(plan, d, speckle=sp).cpu().numpy()

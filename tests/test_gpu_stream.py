@@ -188,7 +188,7 @@ def test_stream_speckle_matches_whole_scene(hs):
     one = sim.stream_forward(sea, 9, [(0, 0, sea.nx, sea.ny)], 8.0, p0, npl, speckle=sp,
                              f_s=fsd).cpu().numpy()
     whole = sim.generate(sea, 9)
-    plan = sim.plan(whole["x"], whole["y"], 8.0)
+    plan = sim.plan(whole["x"], whole["y"], 8.0, speckle=True)
     flat = sim.forward(plan, whole, p0, npl, speckle=sp, f_s=fsd).cpu().numpy()
     e1, e2 = O.rel_l2(got, one), O.rel_l2(got, flat)
     say(f"chunked vs one chunk {e1:.2e}, vs one plan {e2:.2e}")
