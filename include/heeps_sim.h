@@ -504,6 +504,31 @@ int sim_stream_backward_speckle(sim_handle *h, const sim_sea *sea, unsigned long
                                 float *dvx, float *dvy, float *dvz, void *workspace,
                                 size_t workspace_bytes, void *stream);
 
+/* Bytes of the fixed device scratch of sim_stream_forward_noalloc (96 MiB
+ * per GPU, held from the library's load until the process ends). */
+#define SIM_NOALLOC_SCRATCH_BYTES (96ull << 20)
+
+/*
+ * sim_stream_forward without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the chunk facets, the sea table and the
+ * plans live in a fixed device array of SIM_NOALLOC_SCRATCH_BYTES per GPU
+ * instead of a caller workspace.  Same arguments, results and stream
+ * semantics as sim_stream_forward; it never allocates and never waits.
+ * The handle must have been initialised on this device by sim_device_init
+ * (the one call that allocates).  Every call on one GPU shares that GPU's
+ * array and leaves its contents behind (everything the call needs zeroed is
+ * cleared on its stream): calls that overlap on one GPU race, so serialise
+ * them (one stream, or events between streams).
+ * Errors: as sim_stream_forward; SIM_EINVAL if the call needs more than
+ * SIM_NOALLOC_SCRATCH_BYTES (sim_stream_workspace_size with flags 0 gives the
+ * need: the sea table, 32 bytes per facet of the largest chunk and its plan,
+ * about 68 bytes per facet in all) or the handle was not initialised here.
+ */
+int sim_stream_forward_noalloc(sim_handle *h, const sim_sea *sea, unsigned long long seed,
+                               const int *chunks, int n_chunks, double block_edge, int p0,
+                               int np, float *iq_rc, int accumulate, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -106,7 +106,8 @@ EXPORTS = ("sim_create", "sim_destroy", "sim_last_error", "sim_device_init", "si
            "sim_generate_facets", "sim_forward", "sim_apply_waveform",
            "sim_apply_waveform_adjoint", "sim_backward", "sim_stream_forward",
            "sim_stream_backward", "sim_forward_speckle", "sim_backward_speckle",
-           "sim_stream_forward_speckle", "sim_stream_backward_speckle")
+           "sim_stream_forward_speckle", "sim_stream_backward_speckle",
+           "sim_stream_forward_noalloc")
 
 _lib = None
 
@@ -168,6 +169,8 @@ def load(path: str = LIB_PATH):
     L.sim_stream_backward_speckle.argtypes = [vp, P(SimSea), ctypes.c_ulonglong, ip, i,
                                               ctypes.c_double, P(SimSpeckle), i, i, vp, vp, vp,
                                               vp, vp, sz, vp]
+    L.sim_stream_forward_noalloc.argtypes = [vp, P(SimSea), ctypes.c_ulonglong, ip, i,
+                                             ctypes.c_double, i, i, vp, i, vp]
     for name in EXPORTS:
         if name not in ("sim_destroy", "sim_last_error", "sim_plan_destroy"):
             getattr(L, name).restype = ctypes.c_int

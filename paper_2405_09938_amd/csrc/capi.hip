@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -288,6 +289,36 @@ void release_handle(sim_handle *h) {
     delete h;
 }
 
+// Scratch of sim_stream_forward_noalloc: a fixed device array, one copy per
+// GPU, held until the process ends.  Host code never passes its name to a
+// kernel or a copy (on the host the name stands for no device address): its
+// address on each device comes from hipGetSymbolAddress, taken once per
+// device by the set-up of the first handle initialised there.
+static __device__ __align__(256) unsigned char scratch[SIM_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Address of `scratch` on the current device d (set-up: called with d current).
+int scratch_setup(int d) {
+    if (d < 0 || d >= kMaxDevices) HS_FAIL(SIM_EUNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[d]) return SIM_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        HS_FAIL(SIM_EHIP, std::string("scratch address: ") + hipGetErrorString(e));
+    g_scratch_ptr[d] = ptr;
+    return SIM_OK;
+}
+
+void *scratch_on(int d) {
+    if (d < 0 || d >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[d];
+}
+
 // Device tables are uploaded on the first call that needs the GPU, on the
 // device current at that time; later calls must run on the same device.
 int ensure_device(sim_handle *h) {
@@ -335,6 +366,7 @@ int ensure_device(sim_handle *h) {
         HS_FAIL(e == hipErrorOutOfMemory ? SIM_ENOMEM : SIM_EHIP,
                 std::string("device table upload: ") + hipGetErrorString(e));
     }
+    if (int rc = scratch_setup(d)) return rc;
     h->uploaded = true;
     return SIM_OK;
 }
@@ -1478,6 +1510,32 @@ int sim_stream_backward_speckle(sim_handle *h, const sim_sea *sea, unsigned long
     if (!speckle) HS_FAIL(SIM_EINVAL, "speckle is NULL");
     return stream_backward_common(h, sea, seed, chunks, n_chunks, block_edge, speckle, p0, np,
                                   g, dvx, dvy, dvz, workspace, workspace_bytes, stream);
+}
+
+int sim_stream_forward_noalloc(sim_handle *h, const sim_sea *sea, unsigned long long seed,
+                               const int *chunks, int n_chunks, double block_edge, int p0,
+                               int np, float *iq, int accumulate, void *stream) {
+    if (!h) HS_FAIL(SIM_EINVAL, "handle is NULL");
+    if (!sea) HS_FAIL(SIM_EINVAL, "sea is NULL");
+    if (int rc = sea_ok(sea)) return rc;
+    std::vector<double> tab;
+    sea_table(sea, tab);
+    StreamLayout Y;
+    if (int rc = stream_layout(h, sea, chunks, n_chunks, block_edge, 0, tab, Y)) return rc;
+    if (Y.total > SIM_NOALLOC_SCRATCH_BYTES)
+        HS_FAIL(SIM_EINVAL, "the call needs " + std::to_string(Y.total) +
+                                " bytes of scratch, beyond the fixed " +
+                                std::to_string((unsigned long long)SIM_NOALLOC_SCRATCH_BYTES) +
+                                " (use smaller chunks, or sim_stream_forward with a workspace)");
+    if (!h->uploaded)
+        HS_FAIL(SIM_EINVAL, "sim_stream_forward_noalloc needs sim_device_init first "
+                            "(it uploads the handle's tables, which allocates)");
+    int d = -1;
+    if (hipGetDevice(&d) != hipSuccess) HS_FAIL(SIM_EHIP, "no HIP device");
+    void *ptr = scratch_on(d);
+    if (!ptr) HS_FAIL(SIM_EINVAL, "no scratch address on this device: call sim_device_init here");
+    return stream_forward_common(h, sea, seed, chunks, n_chunks, block_edge, nullptr, p0, np, iq,
+                                 accumulate, ptr, SIM_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 }  // extern "C"

@@ -385,3 +385,35 @@ def test_workspace_sizes(native):
         assert ns.value >= 32 * 2400 + 36 * 2400
     finally:
         L.sim_destroy(h)
+
+
+def test_noalloc_entry_point_refuses_before_device_work(native):
+    """sim_stream_forward_noalloc: a call needing more than its fixed scratch
+    is refused with the limit in the message, and a handle never initialised
+    on a device is refused too (its set-up would allocate); both before any
+    device work."""
+    L = native.load()
+    g = W.harmony_geometry(8, 64)
+    cfg, keep = _config(native, g)
+    h = ctypes.c_void_p()
+    assert L.sim_create(ctypes.byref(cfg), ctypes.byref(h)) == native.SIM_OK
+    try:
+        sea = native.SimSea()
+        sea.nx, sea.ny, sea.dx, sea.dy, sea.mode, sea.sigma_v = 3000, 1000, 1.0, 1.0, 0, 0.5
+        big = (ctypes.c_int * 4)(0, 0, 3000, 1000)        # 3e6 facets in one chunk
+        need = ctypes.c_size_t()
+        assert L.sim_stream_workspace_size(h, ctypes.byref(sea), big, 1, 8.0, 0,
+                                           ctypes.byref(need)) == native.SIM_OK
+        assert need.value > 96 * 2 ** 20
+        assert L.sim_stream_forward_noalloc(h, ctypes.byref(sea), 1, big, 1, 8.0, 0, 8,
+                                            ctypes.c_void_p(16), 0, None) == native.SIM_EINVAL
+        msg = L.sim_last_error().decode()
+        assert str(96 * 2 ** 20) in msg and "scratch" in msg, msg
+        small = (ctypes.c_int * 8)(0, 0, 500, 400, 500, 0, 500, 400)
+        assert L.sim_stream_forward_noalloc(h, ctypes.byref(sea), 1, small, 2, 8.0, 0, 8,
+                                            ctypes.c_void_p(16), 0, None) == native.SIM_EINVAL
+        assert "sim_device_init" in L.sim_last_error().decode()
+        assert L.sim_stream_forward_noalloc(None, ctypes.byref(sea), 1, small, 2, 8.0, 0, 8,
+                                            ctypes.c_void_p(16), 0, None) == native.SIM_EINVAL
+    finally:
+        L.sim_destroy(h)
