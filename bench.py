@@ -127,6 +127,9 @@ def main():
                     help="u-v gridded antenna patterns (129 x 65 nodes per antenna)")
     ap.add_argument("--speckle", action="store_true",
                     help="intra-facet speckle (eq. 7, 10): tau_s 20 ms, f_s +-5.7 Hz per facet")
+    ap.add_argument("--fast", type=int, default=0,
+                    help="also time the fast mode (Sec. IV.B) with this node spacing n_fast "
+                         "(single-scene workloads): speed-up and Doppler-spectrum error")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of a known size (counter scale)")
     args = ap.parse_args()
@@ -155,6 +158,9 @@ def main():
 
     wl = W.workload(args.workload)
     chunked = bool(wl.chunks)
+    if chunked and args.fast:
+        print("--fast runs on the single-scene workloads (1-4)", file=sys.stderr)
+        sys.exit(2)
     if chunked and (args.speckle or args.rx_exact or args.tops or args.patterns):
         print("the chunked workload runs the plain sum only (no --speckle, --rx-exact, "
               "--tops, --patterns)", file=sys.stderr)
@@ -275,6 +281,50 @@ def main():
     print(f"forward step {step_s * 1e3:.3f} ms, {value:.2f} G/s; forward sum "
           f"{kern_ms:.3f} ms avg", flush=True)
     el_const = plan.el_const
+
+    fast = None
+    if args.fast:
+        # fast mode: windows of 64 full-rate pulses every n_fast pulses, the
+        # rest synthesized from the gates' Doppler spectra; same pipeline
+        fseed = 1000 + wl.seed
+
+        def fast_step(i, prep):
+            f2, plan2 = prep
+            stream.wait_stream(side)
+            rc2 = sim.forward_fast(plan2, f2, args.fast, fseed)
+            return sim.apply_waveform(rc2, out=rc2) if chirp else rc2
+
+        if args.warmup:
+            run_steps(args.warmup, fast_step, "fast warmup")
+        torch.cuda.synchronize()
+        tf0 = time.perf_counter()
+        run_steps(args.steps, fast_step, "fast", start=args.warmup)
+        torch.cuda.synchronize()
+        fast_s = (time.perf_counter() - tf0) / args.steps
+        # Doppler-spectrum error over the whole dwell: gate-averaged
+        # Hann-tapered 64-pulse periodograms (half-overlapping) of the
+        # range-compressed lines, fast mode against the full-rate sum
+        rc_full = sim.forward(plan, f)
+        rc_fast = sim.forward_fast(plan, f, args.fast, fseed)
+        m = torch.arange(64, device=dev, dtype=torch.float64)
+        hw = (math.sqrt(8.0 / 3.0) * torch.sin(math.pi * (m + 0.5) / 64) ** 2).to(torch.float32)
+
+        def doppler_spectrum(iq):
+            segs = iq[:, 64:Np - 64].unfold(1, 64, 32)          # [C, S, N, 64]
+            spec = torch.fft.fft(segs * hw, dim=-1).abs() ** 2
+            return spec.mean(dim=(0, 1, 2)).double()
+
+        S_full, S_fast = doppler_spectrum(rc_full), doppler_spectrum(rc_fast)
+        spec_err = float((S_fast - S_full).abs().sum() / S_full.sum())
+        n_win = (Np - 64) // args.fast + 1
+        fast = {"n_fast": args.fast, "windows": n_win,
+                "computed_pulse_fraction": round(64 * n_win / Np, 4),
+                "ms_per_step": round(fast_s * 1e3, 4),
+                "value_equivalent": round(contrib / fast_s / 1e9, 3),
+                "speedup_vs_full_rate": round(step_s / fast_s, 3),
+                "doppler_spectrum_rel_l1": round(spec_err, 4)}
+        print(f"fast mode n_fast {args.fast}: step {fast_s * 1e3:.3f} ms, speed-up "
+              f"{step_s / fast_s:.2f}x, Doppler spectrum rel L1 {spec_err:.4f}", flush=True)
 
     fwd_adj = None
     adj_ms = None
@@ -460,6 +510,7 @@ def main():
                    "tx_steer_deg_s": args.tops or None,
                    "antenna_patterns": "u-v grids 129x65" if args.patterns else "sinc"},
         "fwd_adj": fwd_adj,
+        "fast_mode": fast,
         "rel_l2_vs_fp64": rel,
         "roofline": roofline,
         "roofline_adjoint": roofline_adj,

@@ -504,6 +504,36 @@ int sim_stream_backward_speckle(sim_handle *h, const sim_sea *sea, unsigned long
                                 float *dvx, float *dvy, float *dvz, void *workspace,
                                 size_t workspace_bytes, void *stream);
 
+/*
+ * Fast mode (Sec. IV.B, the fast-mode paragraph): the Doppler spectrum of
+ * every range gate is estimated at PRF / n_fast, and the pulses in between
+ * are generated by inverse FFT and linear combination, as the heterogeneous
+ * sea of eq. 1-2 but in one dimension (slow time).  Windows of 64 full-rate
+ * pulses start every n_fast pulses (s_k = k n_fast, k < K =
+ * floor((n_pulses - 64) / n_fast) + 1); their rows of iq_rc are the facet sum
+ * of sim_forward.  Node k sits at p_k = s_k + 32.  Per gate and node, the
+ * window's Hann-tapered DFT X (taper sqrt(8/3) sin^2(pi (m + 1/2) / 64))
+ * gives the power |X|^2 / 64^2 per window bin; on L_s bins (L_s the power
+ * of two >= 2 n_fast + 64) the node's signal takes that power interpolated
+ * linearly and scaled by 64 / L_s, the argument of the interpolated
+ * X_c conj(X_0) as its phase relative to channel 0, and a bin phase
+ * 2 pi (w + 1/2) 2^-32 with w word (bin mod 4) of Philox4x32-10 keyed by
+ * `seed`, counter (bin / 4, gate, k, 0x46415354), shared by the channels;
+ * its inverse DFT g_k(tau) is taken at tau = p - p_k.  A pulse p between
+ * windows, with p_k < p < p_{k+1} and d = (p - p_k) / n_fast, gets
+ * sqrt(1 - d) g_k + sqrt(d) g_{k+1} (after the last node: g_{K-1}).
+ * n_fast in [64, 1024] (n_fast = 64 leaves no pulse out: the plain sum).
+ * sim_fast_workspace_size gives the workspace (the window spectra,
+ * 8 * C * K * 64 * N bytes); iq_rc is device complex64
+ * [n_channels][n_pulses][N], overwritten.  Asynchronous, no allocation, no
+ * wait.  Errors: as sim_forward, SIM_EINVAL for n_fast outside [64, 1024],
+ * fewer than 64 pulses, or a NULL, misaligned or too small workspace.
+ */
+int sim_fast_workspace_size(const sim_handle *h, int n_fast, size_t *bytes);
+int sim_forward_fast(sim_handle *h, sim_plan *plan, const sim_facets *facets, int n_fast,
+                     unsigned long long seed, float *iq_rc, void *workspace,
+                     size_t workspace_bytes, void *stream);
+
 /* Bytes of the fixed device scratch of sim_stream_forward_noalloc (96 MiB
  * per GPU, held from the library's load until the process ends). */
 #define SIM_NOALLOC_SCRATCH_BYTES (96ull << 20)

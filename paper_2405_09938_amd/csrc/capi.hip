@@ -1128,28 +1128,19 @@ static int speckle_prepare(const sim_handle *h, const sim_plan *P, const sim_spe
     return SIM_OK;
 }
 
-static int forward_common(sim_handle *h, sim_plan *P, const sim_facets *f,
-                          const sim_speckle *sp, int p0, int np, float *iq, int accumulate,
-                          void *stream, const int *chunk = nullptr, int grid_nx = 0) {
-    if (!h || !P) HS_FAIL(SIM_EINVAL, "handle or plan is NULL");
-    if (P->h != h) HS_FAIL(SIM_EINVAL, "plan belongs to another handle");
-    if (int rc = facets_ok(f, P->n)) return rc;
-    if (p0 < 0 || np < 0 || (long long)p0 + np > h->Np) HS_FAIL(SIM_EINVAL, "pulse range");
-    if (int rc = speckle_ok(h, sp)) return rc;
-    if (sp && !(P->flags & SIM_PLAN_SPECKLE))
-        HS_FAIL(SIM_EINVAL, "the plan was made without SIM_PLAN_SPECKLE (no speckle space)");
-    if (np == 0) return SIM_OK;   // nothing to write (an empty IQ may have a NULL pointer)
-    if (!iq) HS_FAIL(SIM_EINVAL, "iq is NULL");
-    if (int rc = ensure_device(h)) return rc;
-    hipStream_t s = (hipStream_t)stream;
+// Gather of the facet records and launch of the forward sum over n_groups
+// groups of 64 pulses starting gstride pulses apart from p0 (pulse p0 + j
+// writes row j of iq, np rows per channel); the IQ rows already hold what the
+// sum is added to.
+static int forward_launch(const sim_handle *h, const sim_plan *P, const sim_facets *f,
+                          const sim_speckle *sp, int p0, int np, int n_groups, int gstride,
+                          float *iq, hipStream_t s, const int *chunk, int grid_nx) {
     HS_HIP(hs::launch_gather(*f, P->perm, P->blocks, P->n_blocks, P->nb_max, P->sorted, s),
            "gather");
     hs::FwdArgs a{};
     if (sp)
         if (int rc = speckle_prepare(h, P, sp, p0, np, false, chunk, grid_nx, s, a.spk))
             return rc;
-    if (!accumulate)
-        HS_HIP(hs::launch_fill_zero(iq, 2LL * h->C * np * h->N, s), "zero iq");
     a.facets = P->sorted;
     a.blocks = P->blocks;
     a.patch_first = P->patch_first;
@@ -1169,6 +1160,8 @@ static int forward_common(sim_handle *h, sim_plan *P, const sim_facets *f,
     a.Np = h->Np;
     a.p0 = p0;
     a.np = np;
+    a.n_groups = n_groups;
+    a.gstride = gstride;
     a.n_patches = (int)P->n_patches;
     a.halo = P->halo;
     a.rx_exact = h->rx_exact;
@@ -1177,6 +1170,87 @@ static int forward_common(sim_handle *h, sim_plan *P, const sim_facets *f,
     a.inv_c = 1.0 / h->c;
     HS_HIP(hs::launch_forward(a, h->C, P->win, P->el_const && !h->grid, sp != nullptr, s),
            "forward");
+    return SIM_OK;
+}
+
+static int forward_common(sim_handle *h, sim_plan *P, const sim_facets *f,
+                          const sim_speckle *sp, int p0, int np, float *iq, int accumulate,
+                          void *stream, const int *chunk = nullptr, int grid_nx = 0) {
+    if (!h || !P) HS_FAIL(SIM_EINVAL, "handle or plan is NULL");
+    if (P->h != h) HS_FAIL(SIM_EINVAL, "plan belongs to another handle");
+    if (int rc = facets_ok(f, P->n)) return rc;
+    if (p0 < 0 || np < 0 || (long long)p0 + np > h->Np) HS_FAIL(SIM_EINVAL, "pulse range");
+    if (int rc = speckle_ok(h, sp)) return rc;
+    if (sp && !(P->flags & SIM_PLAN_SPECKLE))
+        HS_FAIL(SIM_EINVAL, "the plan was made without SIM_PLAN_SPECKLE (no speckle space)");
+    if (np == 0) return SIM_OK;   // nothing to write (an empty IQ may have a NULL pointer)
+    if (!iq) HS_FAIL(SIM_EINVAL, "iq is NULL");
+    if (int rc = ensure_device(h)) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (!accumulate)
+        HS_HIP(hs::launch_fill_zero(iq, 2LL * h->C * np * h->N, s), "zero iq");
+    // speckle groups are aligned on absolute pulse indices
+    const int poff = sp ? (p0 & 63) : 0;
+    return forward_launch(h, P, f, sp, p0, np, (poff + np + 63) / 64, 64, iq, s, chunk, grid_nx);
+}
+
+// ---- fast mode (Sec. IV.B) ----------------------------------------------------
+
+struct FastLayout {
+    int K, L_s, log_L;
+    size_t x_bytes;
+};
+
+static int fast_layout(const sim_handle *h, int n_fast, FastLayout &F) {
+    if (n_fast < 64 || n_fast > 1024) HS_FAIL(SIM_EINVAL, "n_fast must be in [64, 1024]");
+    if (h->Np < 64) HS_FAIL(SIM_EINVAL, "the fast mode needs at least 64 pulses");
+    F.K = (h->Np - 64) / n_fast + 1;
+    F.L_s = 1;
+    F.log_L = 0;
+    while (F.L_s < 2 * n_fast + 64) {
+        F.L_s <<= 1;
+        ++F.log_L;
+    }
+    F.x_bytes = align256(sizeof(float) * 2 * (size_t)h->C * F.K * 64 * (size_t)h->N);
+    return SIM_OK;
+}
+
+int sim_fast_workspace_size(const sim_handle *h, int n_fast, size_t *bytes) {
+    if (!h || !bytes) HS_FAIL(SIM_EINVAL, "handle or bytes is NULL");
+    FastLayout F;
+    if (int rc = fast_layout(h, n_fast, F)) return rc;
+    *bytes = F.x_bytes;
+    return SIM_OK;
+}
+
+int sim_forward_fast(sim_handle *h, sim_plan *P, const sim_facets *f, int n_fast,
+                     unsigned long long seed, float *iq, void *workspace, size_t workspace_bytes,
+                     void *stream) {
+    if (!h || !P) HS_FAIL(SIM_EINVAL, "handle or plan is NULL");
+    if (P->h != h) HS_FAIL(SIM_EINVAL, "plan belongs to another handle");
+    if (int rc = facets_ok(f, P->n)) return rc;
+    FastLayout F;
+    if (int rc = fast_layout(h, n_fast, F)) return rc;
+    if (!iq) HS_FAIL(SIM_EINVAL, "iq is NULL");
+    if (int rc = workspace_ok(workspace, workspace_bytes, F.x_bytes)) return rc;
+    if (int rc = ensure_device(h)) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    HS_HIP(hs::launch_fill_zero(iq, 2LL * h->C * h->Np * h->N, s), "zero iq");
+    // the windows: K groups of 64 pulses, n_fast apart, into their own rows
+    if (int rc = forward_launch(h, P, f, nullptr, 0, h->Np, F.K, n_fast, iq, s, nullptr, 0))
+        return rc;
+    hs::FastArgs a{};
+    a.iq = reinterpret_cast<float2 *>(iq);
+    a.X = reinterpret_cast<float2 *>(workspace);
+    a.C = h->C;
+    a.Np = h->Np;
+    a.N = h->N;
+    a.n_fast = n_fast;
+    a.K = F.K;
+    a.L_s = F.L_s;
+    a.log_L = F.log_L;
+    a.seed = seed;
+    HS_HIP(hs::launch_fast(a, s), "fast mode");
     return SIM_OK;
 }
 

@@ -15,29 +15,12 @@
 // identical facets.  Output words w map to (0,1) as (w + 1/2) 2^-32 and feed
 // Box-Muller pairs.  Heights and velocities are summed in FP64 and rounded
 // once to float32.
+#include "philox_device.h"
 #include "sim_internal.h"
 
 namespace hs {
 
 namespace {
-
-__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r > 0) {
-            k0 += 0x9E3779B9u;
-            k1 += 0xBB67AE85u;
-        }
-        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
-        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
-        const uint32_t n0 = hi1 ^ c[1] ^ k0;
-        const uint32_t n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0;
-        c[1] = lo1;
-        c[2] = n2;
-        c[3] = lo0;
-    }
-}
 
 __device__ __forceinline__ void normals4(unsigned long long seed, unsigned long long idx,
                                          uint32_t stream, double *n) {

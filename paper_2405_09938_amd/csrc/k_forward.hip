@@ -121,7 +121,7 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
     // on one XCD close in time and read the patch's facet records from its
     // L2 instead of HBM.
     const int poff = SPK ? (A.p0 & 63) : 0;     // lanes before p0 in the first group
-    const int G = (poff + A.np + 63) >> 6;
+    const int G = A.n_groups;
     const unsigned L = blockIdx.x, r8 = L >> 3;
     const int grp = (int)(r8 % (unsigned)G);
     const int patch = (int)((r8 / (unsigned)G) * 8u + (L & 7u));
@@ -132,7 +132,8 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
     const int b0 = patch_first[patch], b1 = patch_first[patch + 1];
     if (b0 == b1) return;
     const int lane = threadIdx.x;
-    const int pl = grp * 64 + lane - poff;   // pulse relative to p0
+    const int gbase = grp * A.gstride - poff;  // pulse (relative to p0) of lane 0
+    const int pl = gbase + lane;               // pulse relative to p0, also its output row
     const bool live = pl >= 0 && pl < A.np;
     const int plc = pl < 0 ? 0 : (pl < A.np ? pl : A.np - 1);
     const PulseRec *PR = A.pulses + (size_t)ch * A.Np + A.p0;
@@ -154,7 +155,7 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
             const double cy0 = (double)(L.by0 + (long long)py * L.py);
             const double xc = ((lane & 1) ? cx0 + L.px : cx0) * L.edge;
             const double yc = ((lane & 2) ? cy0 + L.py : cy0) * L.edge;
-            int pe = grp * 64 - poff + ((lane & 4) ? 63 : 0);
+            int pe = gbase + ((lane & 4) ? 63 : 0);
             pe = pe < 0 ? 0 : (pe < A.np ? pe : A.np - 1);
             const PulseRec &Q = PR[pe];
             const double a0 = xc - Q.ptx[0], a1 = yc - Q.ptx[1], a2 = -Q.ptx[2];
@@ -200,7 +201,7 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
     [[maybe_unused]] float thi = 0.f, tlo = 0.f, bk = 0.f, kk = 0.f, b64 = 0.f, l1 = 0.f;
     [[maybe_unused]] SpkScanW sw{};
     if constexpr (SPK) {
-        gabs = (A.p0 - poff) / 64 + grp;
+        gabs = (A.p0 + gbase) / 64;
         slot = (uint32_t)(64 * gabs + lane + 1);   // the lane draws e_{p + 1}
         thi = (float)P.t;
         tlo = (float)(P.t - (double)thi);
@@ -316,7 +317,7 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
         const float *accf = reinterpret_cast<const float *>(acc);
         const int n = lo + (lane >> 1);
         const bool lane_in = lane < 2 * WIN && n >= 0 && n < A.N;
-        const int rbase = grp * 64 - poff;     // line (relative to p0) of lane 0
+        const int rbase = gbase;               // line (relative to p0) of lane 0
         const int pbeg = rbase < 0 ? -rbase : 0;
         const int pend = (A.np - rbase) < 64 ? (A.np - rbase) : 64;
         float *line = A.iq + 2 * ((size_t)ch * A.np * (size_t)A.N) + 2 * (ptrdiff_t)lo + lane;
@@ -343,8 +344,7 @@ hipError_t launch_forward(const FwdArgs &a, int C, int win, bool el_const, bool 
     if (a.n_patches == 0 || a.np == 0) return hipSuccess;
     // (patch, pulse group) pairs, patches padded to a multiple of the 8 XCDs;
     // speckle groups are aligned on absolute pulse indices
-    const int poff = speckle ? (a.p0 & 63) : 0;
-    const unsigned long long groups = (unsigned long long)((poff + a.np + 63) / 64);
+    const unsigned long long groups = (unsigned long long)a.n_groups;
     const unsigned long long wgs = groups * (((unsigned long long)a.n_patches + 7) / 8 * 8);
     if (wgs > 0xffffffffULL) return hipErrorInvalidConfiguration;
     dim3 grid((unsigned)wgs, (unsigned)C);

@@ -120,6 +120,9 @@ struct FwdArgs {
     float linv_hi, linv_lo;     // f0/c split so that linv_hi + linv_lo ~ f0/c
     float fs_cf;                // fs/c in float
     int N, Np, p0, np;
+    int n_groups;               // pulse groups of 64 lanes in the launch
+    int gstride;                // pulses between the starts of consecutive groups (64:
+                                // contiguous; the fast mode's node spacing otherwise)
     int n_patches;
     int halo;                   // bins added on each side of the patch span
     int rx_exact;               // receiver at each facet's own echo time
@@ -269,6 +272,19 @@ hipError_t launch_adjoint(const AdjArgs &a, bool el_const, bool speckle, hipStre
 hipError_t launch_waveform(const float *in, float *out, long long n_lines, int N, int M,
                            int shift, const float *spec, const float *tw, int adjoint,
                            hipStream_t s);
+
+// Fast mode (Sec. IV.B): window spectra and synthesis of the pulses between
+// the windows of 64 full-rate pulses that start every n_fast pulses.
+struct FastArgs {
+    float2 *iq;                 // [C][Np][N]: window rows hold the full-rate sum
+    float2 *X;                  // [C][K][64][N] tapered window spectra
+    int C, Np, N;
+    int n_fast, K;              // node spacing, number of windows
+    int L_s, log_L;             // synthesis length (power of two) and its log2
+    unsigned long long seed;
+};
+size_t fast_synth_lds_bytes(int L_s, int n_fast);
+hipError_t launch_fast(const FastArgs &a, hipStream_t s);
 
 // Facet generation.
 struct GenArgs {

@@ -354,6 +354,31 @@ class Simulator:
                     "sim_forward_speckle")
         return out
 
+    def forward_fast(self, plan: "Plan", facets: Dict[str, torch.Tensor], n_fast: int,
+                     seed: int, out: Optional[torch.Tensor] = None,
+                     workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Fast-mode IQ_rc [C, N_p, N] over the whole acquisition: windows of 64
+        full-rate pulses every n_fast pulses, the pulses in between generated
+        from the windows' Doppler spectra (sim_forward_fast)."""
+        fs, keep = self._facets_struct(facets, plan.n)
+        shape = (self.n_channels, self.n_pulses, self.n_samples)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.complex64, device=self.device)
+        elif out.shape != shape or out.dtype != torch.complex64 or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous complex64 tensor of shape {shape}")
+        b = ctypes.c_size_t()
+        N.check(self.lib.sim_fast_workspace_size(self.handle, int(n_fast), ctypes.byref(b)),
+                "sim_fast_workspace_size")
+        if workspace is None:
+            workspace = _workspace(b.value, self.device)
+        elif workspace.numel() < b.value:
+            raise ValueError(f"workspace needs {b.value} bytes")
+        N.check(self.lib.sim_forward_fast(self.handle, plan.ptr, ctypes.byref(fs), int(n_fast),
+                                          int(seed), ctypes.c_void_p(out.data_ptr()),
+                                          ctypes.c_void_p(workspace.data_ptr()),
+                                          workspace.numel(), _stream()), "sim_forward_fast")
+        return out
+
     def backward(self, plan: "Plan", facets: Dict[str, torch.Tensor], g_rc: torch.Tensor,
                  p0: int = 0, np_: Optional[int] = None,
                  need: Iterable[str] = GRAD_KEYS, speckle=None,
