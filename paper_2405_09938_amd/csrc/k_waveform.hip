@@ -78,6 +78,14 @@ __device__ __forceinline__ void dft16(float2 *v) {
 
 template <int M, int NT>
 __device__ void fft_lds(float2 *buf, const float2 *__restrict__ tw) {
+    // 1024-thread workgroups for M = 16384 returned wrong transforms on the
+    // MI355X.  This function's indexing does not depend on NT (every
+    // butterfly j < M / R of a pass is read before the barrier and written
+    // after it exactly once); a host emulation of it at M = 16384, NT = 1024
+    // matches a reference FFT, and the compiler gives that instantiation 119
+    // VGPRs and no scratch.  The cause lies outside this code's indexing and
+    // was not found, so large transforms keep to at most 512 threads.
+    static_assert(M < 8192 || NT <= 512, "M >= 8192 is only validated with at most 512 threads");
     int ns = 1;
     // radix-16 passes
 #pragma unroll 1

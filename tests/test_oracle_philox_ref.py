@@ -70,3 +70,19 @@ def test_philox4x32_10_matches_rocrand(ref_exe):
     got = [int(v) for v in O.philox4x32_10([0, 0, q & 0xFFFFFFFF, q >> 32],
                                            [s & 0xFFFFFFFF, s >> 32])]
     assert got == eng
+
+
+def test_known_answer_vectors():
+    """The oracle's Philox4x32-10 and Philox2x32-10 (the speckle draws)
+    against the generators' published known-answer vectors
+    (tests/golden/philox_kat.json)."""
+    import json
+    with open(os.path.join(HERE, "golden", "philox_kat.json")) as fh:
+        kat = json.load(fh)
+    h = lambda v: [int(x, 16) for x in v]
+    for case in kat["philox4x32_10"]:
+        got = O.philox4x32_10(h(case["ctr"]), h(case["key"]))
+        assert [int(x) for x in got] == h(case["out"]), case
+    for case in kat["philox2x32_10"]:
+        got = O.philox2x32_10(h(case["ctr"]), h(case["key"])[0])
+        assert [int(x) for x in got] == h(case["out"]), case
