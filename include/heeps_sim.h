@@ -286,19 +286,26 @@ int sim_workspace_size(const sim_handle *h, long long n, const sim_box *box, dou
  * Plan a facet set (the range-binned block sort of the sum, eq. 17's range
  * slices gathered per tile as in Sec. IV.A/B): facets are binned into
  * spatial blocks (cells of block_edge x block_edge metres of a lattice
- * covering `box`, at most 64 facets per block; each block carries an exact
- * float32 centre used as its FP64 reference point), blocks are grouped into
- * patches of cells that share a range window, and the permutation, blocks
- * and patch offsets are written into `workspace` (caller-owned device
- * memory, 256-byte aligned, at least sim_workspace_size bytes; it must stay
- * allocated and untouched while the plan is used).  Depends only on x, y
- * (device float32 [n]).  block_edge in (0, 64] metres; 8 suits 1 m grids.
- * flags: 0, or SIM_PLAN_SPECKLE to make room for the intra-facet speckle.
- * Asynchronous on `stream`: no allocation and no wait.  A facet outside
- * `box` is placed in the nearest edge cell: it is still summed, but its
- * offset from that block's centre may exceed what the FP32 precision scheme
- * is bounded for; sim_plan_info counts such facets.  out receives a host
- * descriptor (freed by sim_plan_destroy).
+ * covering `box`, at most 64 facets per block, a cell's facets in ascending
+ * index; each block carries an exact float32 centre used as its FP64
+ * reference point), and for every band of pulse groups and every channel
+ * the blocks are binned by the sample position of their centre into range
+ * strips, listed in block order and cut into segments (sim_plan_geometry
+ * reports the bands, strips and segments); the forward sum gives each
+ * (segment, pulse group, channel) its own window and adds the windows in a
+ * fixed order, so its result does not depend on scheduling.  Cells of more
+ * than 1024 facets keep the order of an atomically ranked scatter, so sums
+ * over such cells may differ in the last bits from run to run.  Everything
+ * is written into
+ * `workspace` (caller-owned device memory, 256-byte aligned, at least
+ * sim_workspace_size bytes; it must stay allocated and untouched while the
+ * plan is used).  Depends only on x, y (device float32 [n]).  block_edge in
+ * (0, 64] metres; 8 suits 1 m grids.  flags: 0, or SIM_PLAN_SPECKLE to make
+ * room for the intra-facet speckle.  Asynchronous on `stream`: no allocation
+ * and no wait.  A facet outside `box` is placed in the nearest edge cell:
+ * it is still summed, but its offset from that block's centre may exceed
+ * what the FP32 precision scheme is bounded for; sim_plan_info counts such
+ * facets.  out receives a host descriptor (freed by sim_plan_destroy).
  * Errors: as sim_workspace_size, and SIM_EINVAL for NULL x, y or out, a
  * NULL, misaligned or too small workspace; SIM_EHIP.
  */
@@ -306,16 +313,35 @@ int sim_plan_create(sim_handle *h, const float *x, const float *y, long long n,
                     const sim_box *box, double block_edge, int flags, void *workspace,
                     size_t workspace_bytes, void *stream, sim_plan **out);
 
+/*
+ * Host outputs (host only, nothing allocated): the range-strip geometry a
+ * plan of these arguments would take.  win: LDS window of the forward kernel
+ * (samples); n_bands bands of band_groups pulse groups; n_strips: strips per
+ * band and channel (a bound); seg_len: blocks per work unit; seg_max: bound
+ * on the work units of a band and channel; bands (NULL to skip): host double
+ * [n_bands][n_channels][3] = (umin, S, margin): a block whose centre sits at
+ * sample position u at the band's reference pulse (64 band_groups b +
+ * 32 band_groups, capped at n_pulses - 1) is in strip floor((u - umin) / S),
+ * and the forward sum assumes its facets' taps within
+ * [umin + s S - margin - 3, umin + (s + 1) S + margin + 4] at every pulse of
+ * the band (facets within half a block diagonal of the centre, heights up to
+ * 4 m, speeds up to 2.5 m/s).  Errors as sim_workspace_size.
+ */
+int sim_plan_geometry(const sim_handle *h, long long n, const sim_box *box, double block_edge,
+                      int *win, int *n_bands, int *band_groups, int *n_strips, int *seg_len,
+                      int *seg_max, double *bands);
+
 /* Release a plan's host descriptor.  NULL is ignored.  Touches no device
  * memory: the workspace stays the caller's. */
 void sim_plan_destroy(sim_plan *plan);
 
-/* Host outputs: number of facets, blocks, patches and facets outside the
- * plan's box.  n_blocks and n_outside are read back from the device:
- * synchronises the stream the plan was created on (NULL pointers skip
- * them, and then nothing waits). */
+/* Host outputs: number of facets, blocks, range strips per band and channel
+ * (a bound; strips the scene does not reach hold no block) and facets
+ * outside the plan's box.  n_blocks and n_outside are read back from the
+ * device: synchronises the stream the plan was created on (NULL pointers
+ * skip them, and then nothing waits). */
 int sim_plan_info(const sim_plan *plan, long long *n_facets, long long *n_blocks,
-                  long long *n_patches, long long *n_outside);
+                  long long *n_strips, long long *n_outside);
 
 /*
  * Host outputs: the plan's evaluation mode of the antenna elevation factors

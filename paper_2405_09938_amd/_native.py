@@ -107,7 +107,8 @@ EXPORTS = ("sim_create", "sim_destroy", "sim_last_error", "sim_device_init", "si
            "sim_apply_waveform_adjoint", "sim_backward", "sim_stream_forward",
            "sim_stream_backward", "sim_forward_speckle", "sim_backward_speckle",
            "sim_stream_forward_speckle", "sim_stream_backward_speckle",
-           "sim_stream_forward_noalloc", "sim_fast_workspace_size", "sim_forward_fast")
+           "sim_stream_forward_noalloc", "sim_fast_workspace_size", "sim_forward_fast",
+           "sim_plan_geometry")
 
 _lib = None
 
@@ -172,6 +173,8 @@ def load(path: str = LIB_PATH):
     L.sim_stream_forward_noalloc.argtypes = [vp, P(SimSea), ctypes.c_ulonglong, ip, i,
                                              ctypes.c_double, i, i, vp, i, vp]
     L.sim_fast_workspace_size.argtypes = [vp, i, P(sz)]
+    L.sim_plan_geometry.argtypes = [vp, ll, P(SimBox), ctypes.c_double, P(i), P(i), P(i), P(i),
+                                    P(i), P(i), P(ctypes.c_double)]
     L.sim_forward_fast.argtypes = [vp, vp, P(SimFacets), i, ctypes.c_ulonglong, vp, vp, sz, vp]
     for name in EXPORTS:
         if name not in ("sim_destroy", "sim_last_error", "sim_plan_destroy"):

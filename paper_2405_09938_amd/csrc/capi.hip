@@ -12,16 +12,16 @@
 
 #include "sim_internal.h"
 
-// Forward-kernel tuning: smallest LDS range window (samples) and the target
-// number of lattice cells per patch.
+// Forward-kernel tuning: smallest LDS range window (samples) and the number
+// of work units (strip segments x pulse groups x channels) a launch aims at.
 #ifndef HEEPS_WIN_MIN
 #define HEEPS_WIN_MIN 24
 #endif
 #ifndef HEEPS_EL_CONST_TOL
 #define HEEPS_EL_CONST_TOL 5e-6
 #endif
-#ifndef HEEPS_PATCH_CELLS
-#define HEEPS_PATCH_CELLS 24.0
+#ifndef HEEPS_TARGET_UNITS
+#define HEEPS_TARGET_UNITS 16384
 #endif
 
 namespace {
@@ -625,13 +625,14 @@ int sim_waveform_info(const sim_handle *h, int *chirp_len, int *fft_len) {
 // ---- plan (range-binned block sort) in a caller-owned workspace ------------
 
 // Host-side shape of a plan: the block lattice over the scene rectangle, the
-// patches of cells that share a range window, the window and halo of the
-// forward kernel, the elevation-factor mode, and the sizes the workspace
-// must hold.
+// range strips of every band and channel, the window of the forward kernel,
+// the elevation-factor mode, and the sizes the workspace must hold.
 struct PlanGeom {
     hs::Lattice L;
-    long long n_keys, n_patches, nb_max;
-    int halo, win;
+    long long n_keys, nb_max;
+    int win;
+    int NB, B, NS, L_seg, seg_max, ng_max;
+    std::vector<double> band;    // [NB][C][3]: umin, S, margin
     double el_bound;
     bool el_const;
 };
@@ -641,6 +642,136 @@ static int box_ok(const sim_box *box) {
     if (!std::isfinite(box->x_min) || !std::isfinite(box->x_max) || !std::isfinite(box->y_min) ||
         !std::isfinite(box->y_max) || !(box->x_min <= box->x_max) || !(box->y_min <= box->y_max))
         HS_FAIL(SIM_EINVAL, "box must be finite with x_min <= x_max and y_min <= y_max");
+    return SIM_OK;
+}
+
+// Sample position u = n_ref + (|X - P_tx| + |X - P_rx| - c tau_ref) fs / c of
+// the point (x, y, 0) at pulse p of channel ch, and the bistatic range
+// gradient there (unit vectors from the antennas to the point, summed).
+static double sample_pos(const sim_handle *h, int ch, int p, double x, double y, double *g) {
+    const hs::PulseRec &r = h->pulses_h[(size_t)ch * h->Np + p];
+    const double dt[3] = {x - r.ptx[0], y - r.ptx[1], -r.ptx[2]};
+    const double dr[3] = {x - r.prx[0], y - r.prx[1], -r.prx[2]};
+    const double nt = norm3(dt), nr = norm3(dr);
+    if (g)
+        for (int k = 0; k < 3; ++k) g[k] = dt[k] / nt + dr[k] / nr;
+    return (double)h->n_ref + (nt + nr - r.rref) * h->fs / h->c;
+}
+
+// Range strips of the forward sum.  Bands of B pulse groups; per band and
+// channel, over a 17 x 17 grid of the lattice's block centres (z = 0):
+// umin, umax of the centres' sample positions at the band's reference pulse
+// (plus a curvature slack of 0.05 sample, far above the grid's error of
+// ~1e-3 for ranges of tens of km and spacings up to km); the migration M,
+// the largest |u(p) - u(p_ref)| over the band's pulses widened by a group on
+// each side (windows of a call need not start on a group boundary);
+// the halo of facet heights (4 m) and drift (2.5 m/s over the band's
+// largest |t|) along the range gradient; E, half a block diagonal along its
+// horizontal part.  margin = M + halo + E + 0.5, and the strip width
+// S = W - 2 margin - 9 keeps every tap of the strip's facets inside a window
+// of W samples.  W is the smallest instantiated width and B then the longest
+// band (a strip's blocks stay the same for all its groups, which share the
+// facet records through the L2) leaving S >= 4 in every band.
+struct BandStats {
+    std::vector<double> umin, umax, margin;   // [NB][C]
+};
+
+static void band_stats(const sim_handle *h, const hs::Lattice &L, int B, int NB, BandStats &bs) {
+    const int K = 17;
+    const double x0 = ((double)L.bx0 + 0.5) * L.edge, x1 = ((double)(L.bx0 + L.nbx) - 0.5) * L.edge;
+    const double y0 = ((double)L.by0 + 0.5) * L.edge, y1 = ((double)(L.by0 + L.nby) - 0.5) * L.edge;
+    const double bins = h->fs / h->c;
+    bs.umin.assign((size_t)NB * h->C, 0.0);
+    bs.umax.assign((size_t)NB * h->C, 0.0);
+    bs.margin.assign((size_t)NB * h->C, 0.0);
+    for (int b = 0; b < NB; ++b) {
+        const int pref = std::min(b * B * 64 + B * 32, h->Np - 1);
+        const int pa = std::max(0, b * B * 64 - 64);
+        const int pb = std::min(h->Np - 1, (b + 1) * B * 64 + 63);
+        const int pt[5] = {pa, (3 * pa + pb) / 4, (pa + pb) / 2, (pa + 3 * pb) / 4, pb};
+        for (int ch = 0; ch < h->C; ++ch) {
+            double lo = 1e300, hi = -1e300, m = 0.0, gz = 0.0, gn = 0.0, gh = 0.0;
+            for (int i = 0; i < K; ++i)
+                for (int j = 0; j < K; ++j) {
+                    const double x = x0 + (x1 - x0) * i / (K - 1), y = y0 + (y1 - y0) * j / (K - 1);
+                    double g[3];
+                    const double u = sample_pos(h, ch, pref, x, y, g);
+                    lo = std::min(lo, u);
+                    hi = std::max(hi, u);
+                    gh = std::max(gh, std::hypot(g[0], g[1]));
+                    for (int q = 0; q < 5; ++q) {
+                        double g2[3];
+                        m = std::max(m, std::fabs(sample_pos(h, ch, pt[q], x, y, g2) - u));
+                        gz = std::max(gz, std::fabs(g2[2]));
+                        gn = std::max(gn, norm3(g2));
+                        gh = std::max(gh, std::hypot(g2[0], g2[1]));
+                    }
+                }
+            const double ta = std::fabs(h->pulses_h[(size_t)ch * h->Np + pa].t);
+            const double tb = std::fabs(h->pulses_h[(size_t)ch * h->Np + pb].t);
+            const size_t k = (size_t)b * h->C + ch;
+            const double halo = (4.0 * gz + 2.5 * std::max(ta, tb) * gn) * bins;
+            const double E = 0.5 * std::sqrt(2.0) * L.edge * gh * bins;
+            bs.umin[k] = lo - 0.05;
+            bs.umax[k] = hi + 0.05;
+            bs.margin[k] = m + halo + E + 0.5;
+        }
+    }
+}
+
+static int strip_geometry(const sim_handle *h, PlanGeom &G) {
+    const hs::Lattice &L = G.L;
+    const int NG = (h->Np + 63) / 64;
+    G.ng_max = NG + 1;
+    // candidate band lengths, longest first
+    std::vector<int> Bs;
+    for (int b = 1; b < NG; b *= 4) Bs.push_back(b);
+    Bs.push_back(NG);
+    std::sort(Bs.rbegin(), Bs.rend());
+    const int wins[4] = {24, 32, 48, 64};
+    BandStats bs;
+    bool found = false;
+    for (int w : wins) {
+        if (w < HEEPS_WIN_MIN) continue;
+        for (int B : Bs) {
+            const int NB = (NG + B - 1) / B;
+            band_stats(h, L, B, NB, bs);
+            double smin = 1e300;
+            for (double mg : bs.margin) smin = std::min(smin, w - 2.0 * mg - 9.0);
+            if (smin >= 4.0) {
+                G.win = w;
+                G.B = B;
+                G.NB = NB;
+                found = true;
+                break;
+            }
+        }
+        if (found) break;
+    }
+    if (!found) {   // far outside the workloads' geometries: narrowest strips
+        G.win = 64;
+        G.B = 1;
+        G.NB = NG;
+        band_stats(h, L, G.B, G.NB, bs);
+    }
+    G.band.assign((size_t)3 * G.NB * h->C, 0.0);
+    G.NS = 1;
+    for (size_t k = 0; k < bs.umin.size(); ++k) {
+        double S = std::max(1.0, G.win - 2.0 * bs.margin[k] - 9.0);
+        // at most kStripMax strips: wider ones (facets may then leave the
+        // window and take the global path)
+        S = std::max(S, (bs.umax[k] - bs.umin[k]) / 8000.0);
+        G.band[3 * k] = bs.umin[k];
+        G.band[3 * k + 1] = S;
+        G.band[3 * k + 2] = bs.margin[k];
+        G.NS = std::max(G.NS, (int)std::floor((bs.umax[k] - bs.umin[k]) / S) + 1);
+    }
+    // segments: enough work units to fill the GPU, long enough to amortise
+    // the window flush
+    const long long per_band = std::max(1LL, (long long)HEEPS_TARGET_UNITS / ((long long)NG * h->C));
+    long long Ls = std::min(4096LL, std::max(16LL, (G.nb_max / 2 + per_band - 1) / per_band));
+    G.L_seg = (int)((Ls + hs::kFwdWaves - 1) / hs::kFwdWaves * hs::kFwdWaves);
+    G.seg_max = G.NS + (int)((G.nb_max + G.L_seg - 1) / G.L_seg);
     return SIM_OK;
 }
 
@@ -662,60 +793,12 @@ static int plan_geometry(const sim_handle *h, long long n, const sim_box *bx, do
     L.nbx = (int)(fx1 - fx0) + 1;
     L.nby = (int)(fy1 - fy0) + 1;
 
-    // Patch shape: gradients of the sample position along x and y over the
-    // scene corners and the first / middle / last pulses of every channel.
-    double gxm = 1e-12, gym = 1e-12, gzm = 0.0, gnm = 0.0;
-    const double xs[3] = {box[0], 0.5 * (box[0] + box[1]), box[1]};
-    const double ys[3] = {box[2], 0.5 * (box[2] + box[3]), box[3]};
-    const int ps[3] = {0, h->Np / 2, h->Np - 1};
-    for (int ch = 0; ch < h->C; ++ch)
-        for (int pi = 0; pi < 3; ++pi) {
-            const hs::PulseRec &r = h->pulses_h[(size_t)ch * h->Np + ps[pi]];
-            for (double xv : xs)
-                for (double yv : ys) {
-                    const double dt[3] = {xv - r.ptx[0], yv - r.ptx[1], -r.ptx[2]};
-                    const double dr[3] = {xv - r.prx[0], yv - r.prx[1], -r.prx[2]};
-                    const double nt = norm3(dt), nr = norm3(dr);
-                    double g[3];
-                    for (int k = 0; k < 3; ++k) g[k] = dt[k] / nt + dr[k] / nr;
-                    gxm = std::max(gxm, std::fabs(g[0]));
-                    gym = std::max(gym, std::fabs(g[1]));
-                    gzm = std::max(gzm, std::fabs(g[2]));
-                    gnm = std::max(gnm, norm3(g));
-                }
-        }
-    const double bins_per_m = h->fs / h->c;
-    const double tmax = 0.5 * (double)(h->Np - 1) / h->prf;
-    // halo: facet heights up to 4 m and drift at up to 2.5 m/s over the dwell
-    G.halo = (int)std::ceil((4.0 * gzm + 2.5 * tmax * gnm) * bins_per_m) + 1;
-    // window of the forward kernel: the smallest instantiated width that
-    // leaves room for a patch span after the halo and the taps
-    G.win = 64;
-    for (int w : {HEEPS_WIN_MIN, 24, 32, 48, 64})
-        if (w >= HEEPS_WIN_MIN && 2 * G.halo + 13 <= w) {
-            G.win = w;
-            break;
-        }
-    const double budget = std::max(2.0, (double)(G.win - 2 * G.halo - 11));
-    const double gxb = gxm * bins_per_m * block_edge, gyb = gym * bins_per_m * block_edge;
-    const double target = HEEPS_PATCH_CELLS;   // cells per patch
-    double px = std::sqrt(target * gyb / gxb), py = target / px;
-    px = std::max(1.0, std::min(px, 4096.0));
-    py = std::max(1.0, std::min(py, 4096.0));
-    while (px * gxb + py * gyb > budget && (px > 1.0 || py > 1.0)) {
-        if (px * gxb >= py * gyb && px > 1.0) px = std::max(1.0, std::floor(px * 0.8));
-        else py = std::max(1.0, std::floor(py * 0.8));
-    }
-    L.px = std::max(1, std::min((int)px, L.nbx));
-    L.py = std::max(1, std::min((int)py, L.nby));
-    L.npx = (L.nbx + L.px - 1) / L.px;
-    L.npy = (L.nby + L.py - 1) / L.py;
-    G.n_patches = (long long)L.npx * L.npy;
-    G.n_keys = G.n_patches * L.px * L.py;
-    if (G.n_keys > (1LL << 28)) HS_FAIL(SIM_EUNSUPPORTED, "facet lattice exceeds 2^28 cells");
+    G.n_keys = (long long)L.nbx * L.nby;
     // a cell of c facets makes ceil(c / 64) blocks: at most one per non-empty
     // cell plus one per 64 facets
     G.nb_max = std::min(n, G.n_keys) + n / 64;
+    if (int rc = strip_geometry(h, G)) return rc;
+    const double tmax = 0.5 * (double)(h->Np - 1) / h->prf;
     // facets lie within half a block diagonal of their block centre, moved by
     // heights up to 4 m and drift at up to 2.5 m/s over the dwell (as the halo)
     G.el_bound = elevation_bound(h, box, 0.5 * std::sqrt(2.0) * block_edge + 4.0 + 2.5 * tmax);
@@ -725,7 +808,8 @@ static int plan_geometry(const sim_handle *h, long long n, const sim_box *bx, do
 
 // Byte offsets of a plan's buffers in its workspace (each 256-byte aligned).
 struct PlanLayout {
-    size_t perm, sorted, blocks, patch_first, count, offset, nblk, blk_offset, scan_tmp, misc;
+    size_t perm, sorted, blocks, count, offset, nblk, blk_offset, scan_tmp, misc;
+    size_t band, ids, skey, scount, soff, segoff, wsum;
     size_t spk, anch, total;
 };
 
@@ -745,13 +829,22 @@ static PlanLayout plan_layout(const PlanGeom &G, long long n, int flags, int Np)
     // `sorted` until the first gather overwrites it
     Y.sorted = take(sizeof(hs::FacetRec) * ((size_t)n + 1));
     Y.blocks = take(sizeof(hs::BlockRec) * (size_t)std::max(1LL, G.nb_max));
-    Y.patch_first = take(sizeof(int) * ((size_t)G.n_patches + 1));
     Y.count = take(sizeof(int) * nk);
     Y.offset = take(sizeof(int) * (nk + 1));
     Y.nblk = take(sizeof(int) * nk);
     Y.blk_offset = take(sizeof(int) * (nk + 1));
     Y.scan_tmp = take(sizeof(int) * (size_t)hs::scan_tmp_len(G.n_keys));
     Y.misc = take(256);
+    const size_t bcn = G.band.size() / 3;   // bands x channels
+    const size_t nbm = (size_t)std::max(1LL, G.nb_max);
+    Y.band = take(sizeof(double) * G.band.size());
+    Y.ids = take(sizeof(int) * bcn * nbm);
+    Y.skey = take(sizeof(int) * bcn * nbm);
+    Y.scount = take(sizeof(int) * bcn * ((size_t)G.NS + 1));
+    Y.soff = take(sizeof(int) * bcn * ((size_t)G.NS + 1));
+    Y.segoff = take(sizeof(int) * bcn * ((size_t)G.NS + 1));
+    const size_t units = bcn / (size_t)G.NB * (size_t)G.ng_max * (size_t)G.seg_max;
+    Y.wsum = take(sizeof(float2) * units * 64 * (size_t)G.win);
     if (flags & SIM_PLAN_SPECKLE) {
         const size_t groups = (size_t)((Np + 63) / 64) + 1;
         Y.spk = take(sizeof(hs::SpkRec) * ((size_t)n + 1));
@@ -771,18 +864,17 @@ static int workspace_ok(const void *ws, size_t ws_bytes, size_t need) {
 }
 
 // Builds the plan of facets (x, y) in the workspace `ws` (laid out by Y):
-// counting sort by (patch, cell), blocks of at most 64 facets, first block
-// of each patch.  Everything is enqueued on s; nothing is read back.
+// counting sort by cell (each cell's facets then in ascending index), blocks
+// of at most 64 facets, and the range strips of every band and channel.
+// Everything is enqueued on s; nothing is read back.
 static int plan_build(const sim_handle *h, const float *x, const float *y, long long n,
                       const PlanGeom &G, const PlanLayout &Y, int flags, char *ws, hipStream_t s,
                       sim_plan &P) {
     P.h = h;
     P.n = n;
     P.nb_max = G.nb_max;
-    P.n_patches = G.n_patches;
     P.flags = flags;
     P.lat = G.L;
-    P.halo = G.halo;
     P.win = G.win;
     P.el_const = G.el_const;
     P.el_bound = G.el_bound;
@@ -790,7 +882,6 @@ static int plan_build(const sim_handle *h, const float *x, const float *y, long 
     P.perm = (int *)(ws + Y.perm);
     P.sorted = (hs::FacetRec *)(ws + Y.sorted);
     P.blocks = (hs::BlockRec *)(ws + Y.blocks);
-    P.patch_first = (int *)(ws + Y.patch_first);
     int *count = (int *)(ws + Y.count), *offset = (int *)(ws + Y.offset);
     int *nblk = (int *)(ws + Y.nblk), *blk_offset = (int *)(ws + Y.blk_offset);
     int *scan_tmp = (int *)(ws + Y.scan_tmp);
@@ -798,6 +889,31 @@ static int plan_build(const sim_handle *h, const float *x, const float *y, long 
     int *rank = keys + n;
     P.n_blocks = blk_offset + G.n_keys;
     P.n_outside = (unsigned *)(ws + Y.misc);
+    P.counter = (unsigned *)(ws + Y.misc + 64);
+    hs::StripPlan &st = P.st;
+    st.band = (const double *)(ws + Y.band);
+    st.ids = (int *)(ws + Y.ids);
+    st.soff = (int *)(ws + Y.soff);
+    st.segoff = (int *)(ws + Y.segoff);
+    st.NB = G.NB;
+    st.B = G.B;
+    st.NS = G.NS;
+    st.nbm = (int)std::max(1LL, G.nb_max);
+    st.L = G.L_seg;
+    st.seg_max = G.seg_max;
+    P.wsum = (float2 *)(ws + Y.wsum);
+    P.ng_max = G.ng_max;
+    // sample span of any band's windows, in tiles of the window reduction
+    {
+        long long span = 1;
+        for (size_t k = 0; k + 2 < G.band.size(); k += 3) {
+            const double umin = G.band[k], S = G.band[k + 1], mg = G.band[k + 2];
+            const long long lo0 = (long long)std::floor(umin - mg);
+            const long long lo1 = (long long)std::floor(umin + (double)(G.NS - 1) * S - mg);
+            span = std::max(span, lo1 - lo0 + G.win);
+        }
+        P.span_tiles = (int)((span + hs::kReduceTile - 1) / hs::kReduceTile);
+    }
     P.spk = (flags & SIM_PLAN_SPECKLE) ? (hs::SpkRec *)(ws + Y.spk) : nullptr;
     P.anch = (flags & SIM_PLAN_SPECKLE) ? (float4 *)(ws + Y.anch) : nullptr;
     const long long stl = hs::scan_tmp_len(G.n_keys);
@@ -814,8 +930,12 @@ static int plan_build(const sim_handle *h, const float *x, const float *y, long 
         (e = hs::launch_exclusive_scan(nblk, blk_offset, nk, scan_tmp, stl, s)) != hipSuccess ||
         (e = hs::launch_make_blocks(count, offset, blk_offset, nk, G.L, P.blocks, s)) !=
             hipSuccess ||
-        (e = hs::launch_patch_first(blk_offset, G.n_patches, G.L.px * G.L.py, nk, P.patch_first,
-                                    s)) != hipSuccess)
+        (e = hs::launch_cell_sort(count, offset, nk, P.perm, s)) != hipSuccess ||
+        (e = hs::launch_upload((double *)(ws + Y.band), G.band.data(), (long long)G.band.size(),
+                               s)) != hipSuccess ||
+        (e = hs::launch_strips(st, h->pulses_d, P.blocks, P.n_blocks, h->Np, h->C,
+                               (double)h->n_ref, h->fs / h->c, (int *)(ws + Y.skey),
+                               (int *)(ws + Y.scount), s)) != hipSuccess)
         HS_FAIL(SIM_EHIP, std::string("plan: ") + hipGetErrorString(e));
     return SIM_OK;
 }
@@ -832,6 +952,22 @@ int sim_workspace_size(const sim_handle *h, long long n, const sim_box *box, dou
     PlanGeom G;
     if (int rc = plan_geometry(h, n, box, block_edge, G)) return rc;
     *bytes = plan_layout(G, n, flags, h->Np).total;
+    return SIM_OK;
+}
+
+int sim_plan_geometry(const sim_handle *h, long long n, const sim_box *box, double block_edge,
+                      int *win, int *n_bands, int *band_groups, int *n_strips, int *seg_len,
+                      int *seg_max, double *bands) {
+    if (!h) HS_FAIL(SIM_EINVAL, "handle is NULL");
+    PlanGeom G;
+    if (int rc = plan_geometry(h, n, box, block_edge, G)) return rc;
+    if (win) *win = G.win;
+    if (n_bands) *n_bands = G.NB;
+    if (band_groups) *band_groups = G.B;
+    if (n_strips) *n_strips = G.NS;
+    if (seg_len) *seg_len = G.L_seg;
+    if (seg_max) *seg_max = G.seg_max;
+    if (bands) std::memcpy(bands, G.band.data(), sizeof(double) * G.band.size());
     return SIM_OK;
 }
 
@@ -860,10 +996,10 @@ int sim_plan_create(sim_handle *h, const float *x, const float *y, long long n,
 void sim_plan_destroy(sim_plan *P) { delete P; }
 
 int sim_plan_info(const sim_plan *P, long long *n_facets, long long *n_blocks,
-                  long long *n_patches, long long *n_outside) {
+                  long long *n_strips, long long *n_outside) {
     if (!P) HS_FAIL(SIM_EINVAL, "plan is NULL");
     if (n_facets) *n_facets = P->n;
-    if (n_patches) *n_patches = P->n_patches;
+    if (n_strips) *n_strips = P->st.NS;
     if (n_blocks || n_outside) {
         int nb = 0;
         unsigned no = 0;
@@ -1141,15 +1277,17 @@ static int forward_launch(const sim_handle *h, const sim_plan *P, const sim_face
     if (sp)
         if (int rc = speckle_prepare(h, P, sp, p0, np, false, chunk, grid_nx, s, a.spk))
             return rc;
+    if (n_groups > P->ng_max) HS_FAIL(SIM_EINVAL, "more pulse groups than the plan's windows");
     a.facets = P->sorted;
     a.blocks = P->blocks;
-    a.patch_first = P->patch_first;
+    a.st = P->st;
+    a.wsum = P->wsum;
+    a.counter = P->counter;
     a.pulses = h->pulses_d;
     a.iq = iq;
     for (size_t i = 0; i < h->antc.size(); ++i) a.ant[i] = h->antc[i];
     for (int i = 0; i < h->C; ++i) a.ch[i] = h->chc[i];
     a.tp = h->tp;
-    a.lat = P->lat;
     a.f0_c = h->f0 / h->c;
     a.fs_c = h->fs / h->c;
     a.n_ref = (double)h->n_ref;
@@ -1162,14 +1300,29 @@ static int forward_launch(const sim_handle *h, const sim_plan *P, const sim_face
     a.np = np;
     a.n_groups = n_groups;
     a.gstride = gstride;
-    a.n_patches = (int)P->n_patches;
-    a.halo = P->halo;
+    a.C = h->C;
     a.rx_exact = h->rx_exact;
     a.steer = h->steer;
     a.grid = h->grid;
     a.inv_c = 1.0 / h->c;
+    HS_HIP(hs::launch_fill_zero((float *)P->counter, hs::kFwdQueues, s), "work queues");
     HS_HIP(hs::launch_forward(a, h->C, P->win, P->el_const && !h->grid, sp != nullptr, s),
            "forward");
+    hs::ReduceArgs r{};
+    r.st = P->st;
+    r.wsum = P->wsum;
+    r.iq = reinterpret_cast<float2 *>(iq);
+    r.C = h->C;
+    r.N = h->N;
+    r.Np = h->Np;
+    r.p0 = p0;
+    r.np = np;
+    r.n_groups = n_groups;
+    r.gstride = gstride;
+    r.poff = sp ? (p0 & 63) : 0;
+    r.win = P->win;
+    r.n_tiles = P->span_tiles;
+    HS_HIP(hs::launch_window_reduce(r, s), "window reduce");
     return SIM_OK;
 }
 

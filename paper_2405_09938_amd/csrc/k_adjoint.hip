@@ -148,7 +148,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
     __shared__ float2 gwin[kStage * kGW];
 
     // Workgroups go to the 8 XCDs round-robin by linear index; XCD x takes
-    // the contiguous x-th eighth of the (patch-ordered) blocks, so blocks
+    // the contiguous x-th eighth of the (cell-ordered) blocks, so blocks
     // reading the same range samples of g share that XCD's L2.  The launch
     // covers the plan's bound on the block count; the count itself is read
     // here, and workgroups beyond it return.

@@ -5,22 +5,29 @@
 // facet's fractional sample u = n_ref + (R - c tau_ref) fs / c by an 8-tap
 // Kaiser-windowed sinc (the range slices of eq. 17).
 //
-// Work decomposition (one workgroup = one wave):
-//   blockIdx.x = (patch of spatial blocks, group of 64 pulses), decoded so
-//   that the groups of one patch share an XCD (below); blockIdx.y = channel.
+// Work decomposition: a work unit is (segment of a range strip, pulse group
+// of 64, channel).  A strip holds the blocks whose centres fall in a band of
+// S range samples at the reference pulse of the group's band (the plan's
+// range-binned sort), so one LDS range window covers that band plus a margin
+// and every facet of the strip lands in it.  A workgroup of K waves takes
+// one unit at a time from a work queue (below); wave k sums blocks k, k + K,
+// ... of the segment into its own window.
 //   Lane = pulse: every lane handles the same facet
 //   (its 32-byte record arrives by two uniform buffer loads) and deposits into
-//   its own pulse column of an LDS range window.  Since no other lane or wave
-//   touches that column, the deposit is a plain read-modify-write (8 x 64-bit
-//   reads issued as soon as the sample index is known, 16 FMAs, 8 x 64-bit
-//   writes) instead of LDS atomics, which serialise per lane on gfx950.  The
-//   window is stored sample-major ([sample][lane]), so the 64 lanes of one
+//   its own pulse column of the wave's LDS range window.  Since no other lane
+//   or wave touches that column, the deposit is a plain read-modify-write (8 x
+//   64-bit reads issued as soon as the sample index is known, 16 FMAs, 8 x
+//   64-bit writes) instead of LDS atomics, which serialise per lane on gfx950.
+//   The window is stored sample-major ([sample][lane]), so the 64 lanes of one
 //   access always fall on distinct bank pairs whatever their sample indices:
 //   a lane-major layout conflicts as soon as the lanes' sample indices
-//   differ.  At the end the window is flushed to the
-//   IQ lines with global float atomics, since neighbouring patches overlap in
-//   range.  A contribution whose taps leave the window (only for geometries
-//   the patch sizing did not foresee) goes straight to global memory.
+//   differ.  At the end the K windows are added in wave order and the sum
+//   goes to the unit's own slot of a scratch array with plain stores;
+//   k_window_reduce then adds, line by line, the windows of all segments in
+//   segment order, so the result does not depend on the order in which
+//   workgroups run and no global atomics are needed.  A contribution whose
+//   taps leave the window (only for facets beyond the plan's height and speed
+//   assumptions) goes straight to global memory.
 #include "sim_device.h"
 #include "spk_device.h"
 
@@ -97,9 +104,15 @@ __device__ __forceinline__ SpkFacet load_spk(__amdgpu_buffer_rsrc_t rr, __amdgpu
     return s;
 }
 
-// The flush of windows up to this width goes through a transposed copy in
-// LDS, so that one atomic instruction covers contiguous samples of one line.
-constexpr int kFlushTransposeMax = 32;
+// Windows up to this width take kFwdWaves waves per workgroup, each with its
+// own window; wider windows one wave per workgroup (whose LDS would
+// otherwise limit a compute unit to fewer waves).
+constexpr int kMultiWaveMaxWin = 32;
+
+template <int WIN>
+constexpr int fwd_waves() {
+    return WIN <= kMultiWaveMaxWin ? kFwdWaves : 1;
+}
 
 // SPK: the intra-facet speckle of eq. 7 multiplies each facet's amplitude by
 // x(p) and adds f_s t_p cycles to its phase.  Pulse groups are then aligned
@@ -109,30 +122,40 @@ constexpr int kFlushTransposeMax = 32;
 // STR: antenna frames turn with time (steering): per-pulse frames.
 // GRD: field patterns from u-v tables (1: on some antennas, 2: on all),
 // evaluated per facet (never with ELC).
+// One work unit: segment `seg` of a range strip of the band holding pulse
+// group `grp`, channel `ch`; accw holds the workgroup's LDS windows.
 template <int WIN, bool ELC, bool SPK, bool STR, int GRD>
-__global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
-    // [sample][lane] during the sum; [lane][WIN + 1] for the flush
-    constexpr int kAcc = WIN <= kFlushTransposeMax ? 64 * (WIN + 1) : 64 * WIN;
-    __shared__ float2 acc[kAcc];
-
-    // Workgroup -> (patch, pulse group).  Workgroups go to the 8 XCDs
-    // round-robin by linear index, so index L runs on XCD L % 8.  All pulse
-    // groups of one patch get the same L % 8 and consecutive L / 8: they run
-    // on one XCD close in time and read the patch's facet records from its
-    // L2 instead of HBM.
+__device__ __forceinline__ void forward_unit(const FwdArgs &A, float2 *accw, int seg, int grp,
+                                             int ch) {
+    constexpr int K = fwd_waves<WIN>();
+    constexpr int kAcc = 64 * WIN;
+    // the wave index, uniform (in an SGPR): block loads stay scalar
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    float2 *acc = accw + wave * kAcc;
     const int poff = SPK ? (A.p0 & 63) : 0;     // lanes before p0 in the first group
-    const int G = A.n_groups;
-    const unsigned L = blockIdx.x, r8 = L >> 3;
-    const int grp = (int)(r8 % (unsigned)G);
-    const int patch = (int)((r8 / (unsigned)G) * 8u + (L & 7u));
-    const int ch = blockIdx.y;
-    if (patch >= A.n_patches) return;
-    const cptr<int> patch_first = (cptr<int>)A.patch_first;
-    const cptr<BlockRec> blocks = (cptr<BlockRec>)A.blocks;
-    const int b0 = patch_first[patch], b1 = patch_first[patch + 1];
-    if (b0 == b1) return;
-    const int lane = threadIdx.x;
+    const StripPlan &st = A.st;
     const int gbase = grp * A.gstride - poff;  // pulse (relative to p0) of lane 0
+    int pc = A.p0 + gbase + 32;                 // the group's centre pulse
+    pc = pc < 0 ? 0 : (pc < A.Np ? pc : A.Np - 1);
+    int band = pc / (64 * st.B);
+    band = band < st.NB ? band : st.NB - 1;
+    const size_t bc = (size_t)band * A.C + ch;
+    const cptr<int> segoff = (cptr<int>)(st.segoff + bc * (st.NS + 1));
+    if (seg >= segoff[st.NS]) return;
+    // the segment's strip: the last s with segoff[s] <= seg
+    int s_lo = 0, s_hi = st.NS;
+    while (s_hi - s_lo > 1) {
+        const int mid = (s_lo + s_hi) >> 1;
+        if (segoff[mid] <= seg) s_lo = mid;
+        else s_hi = mid;
+    }
+    const int strip = s_lo;
+    const cptr<int> soff = (cptr<int>)(st.soff + bc * (st.NS + 1));
+    const int q0 = soff[strip] + (seg - segoff[strip]) * st.L;
+    const int q1 = soff[strip + 1] < q0 + st.L ? soff[strip + 1] : q0 + st.L;
+    const cptr<int> ids = (cptr<int>)(st.ids + bc * st.nbm);
+    const cptr<BlockRec> blocks = (cptr<BlockRec>)A.blocks;
+    const int lane = (int)(threadIdx.x & 63);
     const int pl = gbase + lane;               // pulse relative to p0, also its output row
     const bool live = pl >= 0 && pl < A.np;
     const int plc = pl < 0 ? 0 : (pl < A.np ? pl : A.np - 1);
@@ -142,37 +165,10 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
     FacetConsts kc;
     facet_consts(ta, ra, kc);
 
-    // Range window of this (patch, pulse group): sample positions of the
-    // patch corners at the group's first and last pulse (lanes 0..7), widened
-    // by the halo (facet heights, drift) and the taps.
-    int lo;
-    {
-        double umin = 1e300, umax = -1e300;
-        if (lane < 8) {
-            const Lattice &L = A.lat;
-            const int px = patch % L.npx, py = patch / L.npx;
-            const double cx0 = (double)(L.bx0 + (long long)px * L.px);
-            const double cy0 = (double)(L.by0 + (long long)py * L.py);
-            const double xc = ((lane & 1) ? cx0 + L.px : cx0) * L.edge;
-            const double yc = ((lane & 2) ? cy0 + L.py : cy0) * L.edge;
-            int pe = gbase + ((lane & 4) ? 63 : 0);
-            pe = pe < 0 ? 0 : (pe < A.np ? pe : A.np - 1);
-            const PulseRec &Q = PR[pe];
-            const double a0 = xc - Q.ptx[0], a1 = yc - Q.ptx[1], a2 = -Q.ptx[2];
-            const double c0 = xc - Q.prx[0], c1 = yc - Q.prx[1], c2 = -Q.prx[2];
-            const double R = sqrt(a0 * a0 + a1 * a1 + a2 * a2) + sqrt(c0 * c0 + c1 * c1 + c2 * c2);
-            umin = umax = A.n_ref + (R - Q.rref) * A.fs_c;
-        }
-#pragma unroll
-        for (int off = 1; off < 8; off <<= 1) {
-            umin = fmin(umin, __shfl_xor(umin, off));
-            umax = fmax(umax, __shfl_xor(umax, off));
-        }
-        int l = (int)floor(umin) - A.halo - 3;
-        const int h = (int)ceil(umax) + A.halo + 4;
-        if (h - l + 1 > WIN) l = ((l + h) >> 1) - WIN / 2;
-        lo = __builtin_amdgcn_readfirstlane(l);
-    }
+    // Range window of the strip: its band of samples at the reference
+    // pulse, widened by the margin and the taps.
+    const cptr<double> bd = (cptr<double>)(st.band + 3 * bc);
+    const int lo = (int)floor(bd[0] + (double)strip * bd[1] - bd[2]) - 3;
     float2 *col = acc + lane;
     for (int i = 0; i < WIN; ++i) col[64 * i] = make_float2(0.f, 0.f);
 
@@ -217,8 +213,8 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
         l1 = S.c1 * S.c1 * 0.69314718055994531f;
     }
 
-    for (int b = b0; b < b1; ++b) {
-        const BlockRec blk = load_block(blocks + b);
+    for (int q = q0 + wave; q < q1; q += K) {
+        const BlockRec blk = load_block(blocks + ids[q]);
         Refs r;
         // receiver at the block centre's own echo time (optional)
         double prb[3] = {prx[0], prx[1], prx[2]};
@@ -302,67 +298,155 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs A) {
         }
     }
 
-    // flush the window into the lines (zeros skipped); neighbouring patches
-    // overlap in range, hence the atomics
-    if constexpr (WIN <= kFlushTransposeMax) {
-        // each lane takes its pulse row into registers, then writes it back
-        // lane-major with one pad sample (conflict-free both ways); line p is
-        // then flushed by lanes 0 .. 2 WIN - 1, one float each
-        float2 v[WIN];
+    // the unit's window to its own slot of the scratch, sample-major like
+    // the LDS windows ([sample][pulse row]), plain coalesced stores: the
+    // waves' windows added in wave order
+    const size_t wslot = ((size_t)ch * A.n_groups + grp) * (size_t)st.seg_max + seg;
+    float2 *dst = A.wsum + wslot * 64 * WIN;
+    __syncthreads();
+    for (int e = (int)threadIdx.x; e < 64 * WIN; e += 64 * K) {
+        float2 t = accw[e];
 #pragma unroll
-        for (int i = 0; i < WIN; ++i) v[i] = col[64 * i];
-        float2 *rowp = acc + lane * (WIN + 1);
-#pragma unroll
-        for (int i = 0; i < WIN; ++i) rowp[i] = v[i];
-        const float *accf = reinterpret_cast<const float *>(acc);
-        const int n = lo + (lane >> 1);
-        const bool lane_in = lane < 2 * WIN && n >= 0 && n < A.N;
-        const int rbase = gbase;               // line (relative to p0) of lane 0
-        const int pbeg = rbase < 0 ? -rbase : 0;
-        const int pend = (A.np - rbase) < 64 ? (A.np - rbase) : 64;
-        float *line = A.iq + 2 * ((size_t)ch * A.np * (size_t)A.N) + 2 * (ptrdiff_t)lo + lane;
-        for (int p = pbeg; p < pend; ++p) {
-            const float x = lane < 2 * WIN ? accf[p * 2 * (WIN + 1) + lane] : 0.0f;
-            if (lane_in && x != 0.0f) unsafeAtomicAdd(line + 2 * (size_t)(rbase + p) * A.N, x);
+        for (int k = 1; k < K; ++k) {
+            const float2 w = accw[k * kAcc + e];
+            t.x += w.x;
+            t.y += w.y;
         }
-    } else if (live) {
-        float *dst = A.iq + 2 * (((size_t)ch * A.np + pl) * (size_t)A.N);
-        for (int bin = 0; bin < WIN; ++bin) {
-            const int n = lo + bin;
-            const float2 v = col[64 * bin];
-            if (n < 0 || n >= A.N || (v.x == 0.0f && v.y == 0.0f)) continue;
-            unsafeAtomicAdd(dst + 2 * n, v.x);
-            unsafeAtomicAdd(dst + 2 * n + 1, v.y);
+        dst[e] = t;
+    }
+}
+
+// Persistent workgroups with one work queue per XCD.  Workgroups go to the
+// 8 XCDs round-robin by linear index, so workgroup b starts on queue b % 8,
+// which holds the segments s with s % 8 == b % 8: all pulse groups of a
+// segment run on one XCD and read its facet records from that XCD's L2.  A
+// queue hands out (segment, channel, pulse group) units, groups fastest; a
+// workgroup whose queue is empty takes units from the next queues in turn.
+// Units of segments a band does not have return at once.  Each workgroup
+// leaves after one failed take per queue, so every workgroup ends; each unit
+// writes only its own window slot, so the result does not depend on who ran
+// it.
+template <int WIN, bool ELC, bool SPK, bool STR, int GRD>
+__global__ __launch_bounds__(64 * fwd_waves<WIN>()) void k_forward(FwdArgs A) {
+    __shared__ float2 acc[fwd_waves<WIN>() * 64 * WIN];
+    __shared__ unsigned s_unit;
+    const unsigned CG = (unsigned)A.C * (unsigned)A.n_groups;
+    const unsigned segs = (unsigned)A.st.seg_max;
+    for (unsigned k = 0; k < kFwdQueues; ++k) {
+        const unsigned q = (blockIdx.x + k) % kFwdQueues;
+        const unsigned units = (segs > q ? (segs - q + kFwdQueues - 1) / kFwdQueues : 0u) * CG;
+        for (;;) {
+            __syncthreads();   // the last unit's flush has read the windows
+            if (threadIdx.x == 0) s_unit = atomicAdd(A.counter + q, 1u);
+            __syncthreads();
+            const unsigned u = (unsigned)__builtin_amdgcn_readfirstlane((int)s_unit);
+            if (u >= units) break;
+            const unsigned r = u / (unsigned)A.n_groups;
+            forward_unit<WIN, ELC, SPK, STR, GRD>(A, acc, (int)(q + kFwdQueues * (r / (unsigned)A.C)),
+                                                 (int)(u - r * (unsigned)A.n_groups),
+                                                 (int)(r % (unsigned)A.C));
         }
     }
+}
+
+// One wave per (sample, pulse group, channel), lane = pulse row, over the
+// span of sample positions the windows of the group's band can reach: the
+// wave gathers, in strip order and within a strip in segment order, the
+// windows of the segments of every strip whose window holds the sample (one
+// coalesced 512-byte row of each slot) and adds the sums to the 64 lines.
+// Window origins follow from the strip index as in the forward kernel, so
+// the strips holding a sample are a run of consecutive strips, the same for
+// every lane.  Every sample of every line has one writer, and the order of
+// the additions is fixed.
+__global__ __launch_bounds__(64 * kReduceTile) void k_window_reduce(ReduceArgs A) {
+    // consecutive workgroups: consecutive sample tiles of one pulse group, so
+    // their partial writes to the same IQ lines meet in the L2
+    const int grp = (int)(blockIdx.x / (unsigned)A.n_tiles), ch = blockIdx.y;
+    const unsigned tile_id = blockIdx.x - (unsigned)grp * (unsigned)A.n_tiles;
+    const int row = (int)(threadIdx.x & 63);
+    const int gbase = grp * A.gstride - A.poff;
+    const int pl = gbase + row;
+    const StripPlan &st = A.st;
+    int pc = A.p0 + gbase + 32;
+    pc = pc < 0 ? 0 : (pc < A.Np ? pc : A.Np - 1);
+    int band = pc / (64 * st.B);
+    band = band < st.NB ? band : st.NB - 1;
+    const size_t bc = (size_t)band * A.C + ch;
+    const int *segoff = st.segoff + bc * (st.NS + 1);
+    if (segoff[st.NS] == 0) return;
+    const double *bd = st.band + 3 * bc;
+    const double umin = bd[0], S = bd[1], mg = bd[2];
+    // first sample of strip s's window (the forward kernel's expression)
+    const auto lo_of = [&](int s) { return (int)floor(umin + (double)s * S - mg) - 3; };
+    const int W = A.win;
+    const int n = lo_of(0) + (int)tile_id * kReduceTile +
+                  __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (n < 0 || n >= A.N) return;
+    // s1: the last strip with lo <= n; s0: the first whose window reaches n
+    int s1 = (int)floor(((double)n + 3.0 - umin + mg) / S);
+    s1 = s1 < 0 ? 0 : (s1 < st.NS ? s1 : st.NS - 1);
+    while (s1 + 1 < st.NS && lo_of(s1 + 1) <= n) ++s1;
+    while (s1 >= 0 && lo_of(s1) > n) --s1;
+    int s0 = s1 + 1;
+    while (s0 > 0 && lo_of(s0 - 1) + W > n) --s0;
+    const size_t slot0 = ((size_t)ch * A.n_groups + grp) * (size_t)st.seg_max;
+    const size_t seg_stride = (size_t)64 * W;
+    float2 acc = make_float2(0.f, 0.f);
+    bool any = false;
+    for (int s = s0; s <= s1; ++s) {
+        const int a = segoff[s], b = segoff[s + 1];
+        if (a == b) continue;
+        any = true;
+        const float2 *p = A.wsum + (slot0 + a) * seg_stride + (size_t)(n - lo_of(s)) * 64 + row;
+#pragma unroll 4
+        for (int q = 0; q < b - a; ++q) {
+            const float2 v = p[(size_t)q * seg_stride];
+            acc.x += v.x;
+            acc.y += v.y;
+        }
+    }
+    if (!any || pl < 0 || pl >= A.np) return;
+    float2 &o = A.iq[((size_t)ch * A.np + pl) * (size_t)A.N + n];
+    o = make_float2(o.x + acc.x, o.y + acc.y);
 }
 
 }  // namespace
 
 hipError_t launch_forward(const FwdArgs &a, int C, int win, bool el_const, bool speckle,
                           hipStream_t s) {
-    if (a.n_patches == 0 || a.np == 0) return hipSuccess;
-    // (patch, pulse group) pairs, patches padded to a multiple of the 8 XCDs;
-    // speckle groups are aligned on absolute pulse indices
-    const unsigned long long groups = (unsigned long long)a.n_groups;
-    const unsigned long long wgs = groups * (((unsigned long long)a.n_patches + 7) / 8 * 8);
-    if (wgs > 0xffffffffULL) return hipErrorInvalidConfiguration;
-    dim3 grid((unsigned)wgs, (unsigned)C);
+    if (a.st.seg_max == 0 || a.np == 0 || a.n_groups == 0) return hipSuccess;
+    const unsigned long long units =
+        (unsigned long long)a.st.seg_max * (unsigned long long)C * (unsigned long long)a.n_groups;
+    if (units > 0xffffffffULL) return hipErrorInvalidConfiguration;
+    // persistent workgroups: 16 waves per compute unit (at least as many as
+    // the LDS windows and the registers let run at once)
+    static int n_cu = 0;
+    if (n_cu == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            n_cu <= 0)
+            n_cu = 256;
+    }
+    const auto grid_for = [&](int waves) {
+        const unsigned long long cap = (unsigned long long)n_cu * 16ULL / (unsigned long long)waves;
+        return dim3((unsigned)(units < cap ? units : cap));
+    };
     // gridded patterns are always evaluated per facet (no elevation factor
     // at block centres); a.grid = 2 when every antenna has a table
 #define HS_FWD4(W, T)                                                                       \
     if (a.grid == 2) {                                                                      \
-        if (speckle) hipLaunchKernelGGL((k_forward<W, false, true, T, 2>), grid, dim3(64), 0, s, a); \
-        else hipLaunchKernelGGL((k_forward<W, false, false, T, 2>), grid, dim3(64), 0, s, a); \
+        if (speckle) hipLaunchKernelGGL((k_forward<W, false, true, T, 2>), grid_for(fwd_waves<W>()), dim3(64 * fwd_waves<W>()), 0, s, a); \
+        else hipLaunchKernelGGL((k_forward<W, false, false, T, 2>), grid_for(fwd_waves<W>()), dim3(64 * fwd_waves<W>()), 0, s, a); \
     } else if (a.grid) {                                                                    \
-        if (speckle) hipLaunchKernelGGL((k_forward<W, false, true, T, 1>), grid, dim3(64), 0, s, a); \
-        else hipLaunchKernelGGL((k_forward<W, false, false, T, 1>), grid, dim3(64), 0, s, a); \
+        if (speckle) hipLaunchKernelGGL((k_forward<W, false, true, T, 1>), grid_for(fwd_waves<W>()), dim3(64 * fwd_waves<W>()), 0, s, a); \
+        else hipLaunchKernelGGL((k_forward<W, false, false, T, 1>), grid_for(fwd_waves<W>()), dim3(64 * fwd_waves<W>()), 0, s, a); \
     } else if (speckle) {                                                                   \
-        if (el_const) hipLaunchKernelGGL((k_forward<W, true, true, T, 0>), grid, dim3(64), 0, s, a); \
-        else hipLaunchKernelGGL((k_forward<W, false, true, T, 0>), grid, dim3(64), 0, s, a); \
+        if (el_const) hipLaunchKernelGGL((k_forward<W, true, true, T, 0>), grid_for(fwd_waves<W>()), dim3(64 * fwd_waves<W>()), 0, s, a); \
+        else hipLaunchKernelGGL((k_forward<W, false, true, T, 0>), grid_for(fwd_waves<W>()), dim3(64 * fwd_waves<W>()), 0, s, a); \
     } else {                                                                                \
-        if (el_const) hipLaunchKernelGGL((k_forward<W, true, false, T, 0>), grid, dim3(64), 0, s, a); \
-        else hipLaunchKernelGGL((k_forward<W, false, false, T, 0>), grid, dim3(64), 0, s, a); \
+        if (el_const) hipLaunchKernelGGL((k_forward<W, true, false, T, 0>), grid_for(fwd_waves<W>()), dim3(64 * fwd_waves<W>()), 0, s, a); \
+        else hipLaunchKernelGGL((k_forward<W, false, false, T, 0>), grid_for(fwd_waves<W>()), dim3(64 * fwd_waves<W>()), 0, s, a); \
     }
 #define HS_FWD(W)                                                                           \
     case W:                                                                                 \
@@ -381,6 +465,15 @@ hipError_t launch_forward(const FwdArgs &a, int C, int win, bool el_const, bool 
     }
 #undef HS_FWD
 #undef HS_FWD4
+    return hipGetLastError();
+}
+
+hipError_t launch_window_reduce(const ReduceArgs &a, hipStream_t s) {
+    if (a.np == 0 || a.n_groups == 0) return hipSuccess;
+    const unsigned long long blocks = (unsigned long long)a.n_groups * (unsigned long long)a.n_tiles;
+    if (a.n_tiles <= 0 || blocks > 0xffffffffULL) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_window_reduce, dim3((unsigned)blocks, (unsigned)a.C),
+                       dim3(64 * kReduceTile), 0, s, a);
     return hipGetLastError();
 }
 

@@ -1,12 +1,15 @@
 // Range-binned block sort of a facet set (plan construction) and the per-call
 // gather of facet data into block order.
 //
-// Facets are binned into cells of a square lattice of the horizontal plane;
-// cells are grouped into patches (rectangles of cells whose facets share a
-// range window for a group of pulses, the counterpart of the paper's TL tiles
-// processed as a batch, Sec. IV.A/B); a counting sort over the key
-// (patch, row in patch, column in patch) orders the facets, and each
-// non-empty cell becomes one or more blocks of at most 64 facets.
+// Facets are binned into cells of a square lattice of the horizontal plane
+// (counting sort by cell, facets of a cell in ascending index so that every
+// sum over them runs in a fixed order); each non-empty cell becomes one or
+// more blocks of at most 64 facets.  Blocks are then binned by range: for
+// every band of pulse groups and every channel, the sample position of each
+// block centre at the band's reference pulse selects a range strip (eq. 17's
+// range slices, gathered per tile as the paper's tile batches, Sec.
+// IV.A/B), and each strip's blocks are listed in block order and cut into
+// segments, the units of work of the forward sum.
 #include "sim_internal.h"
 
 namespace hs {
@@ -19,17 +22,15 @@ __global__ void k_fill_zero(float *p, long long n) {
     for (; i < n; i += stride) p[i] = 0.0f;
 }
 
-// Key of the cell holding (xv, yv).  A position outside the lattice (or not
-// finite) goes to the nearest edge cell and sets *out.
+// Key (row-major index) of the cell holding (xv, yv).  A position outside
+// the lattice (or not finite) goes to the nearest edge cell and sets *out.
 __device__ __forceinline__ int cell_key(float xv, float yv, const Lattice &L, bool *out) {
     const double fx = floor((double)xv / L.edge) - (double)L.bx0;
     const double fy = floor((double)yv / L.edge) - (double)L.by0;
     *out = !(fx >= 0.0 && fx < (double)L.nbx && fy >= 0.0 && fy < (double)L.nby);
-    long long cx = fx >= 0.0 ? (fx < (double)L.nbx ? (long long)fx : L.nbx - 1) : 0;
-    long long cy = fy >= 0.0 ? (fy < (double)L.nby ? (long long)fy : L.nby - 1) : 0;
-    const long long px = cx / L.px, py = cy / L.py;
-    const long long patch = py * L.npx + px;
-    return (int)((patch * L.py + (cy - py * L.py)) * L.px + (cx - px * L.px));
+    const long long cx = fx >= 0.0 ? (fx < (double)L.nbx ? (long long)fx : L.nbx - 1) : 0;
+    const long long cy = fy >= 0.0 ? (fy < (double)L.nby ? (long long)fy : L.nby - 1) : 0;
+    return (int)(cy * L.nbx + cx);
 }
 
 // Lanes of a wave holding the same key take their ranks from one atomic:
@@ -174,10 +175,7 @@ __global__ void k_make_blocks(const int *count, const int *offset, const int *bl
     if (k >= n_keys) return;
     const int cnt = count[k];
     if (cnt == 0) return;
-    const long long per = (long long)L.px * L.py;
-    const long long patch = k / per, local = k % per;
-    const long long py = patch / L.npx, px = patch % L.npx;
-    const long long cy = py * L.py + local / L.px, cx = px * L.px + local % L.px;
+    const long long cy = k / L.nbx, cx = k - cy * L.nbx;
     const float xb = (float)(((double)(L.bx0 + cx) + 0.5) * L.edge);
     const float yb = (float)(((double)(L.by0 + cy) + 0.5) * L.edge);
     int b = blk_offset[k];
@@ -191,12 +189,172 @@ __global__ void k_make_blocks(const int *count, const int *offset, const int *bl
     }
 }
 
-__global__ void k_patch_first(const int *blk_offset, long long n_patches, int keys_per_patch,
-                              long long n_keys, int *patch_first) {
-    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p > n_patches) return;
-    const long long k = p * keys_per_patch;
-    patch_first[p] = blk_offset[k < n_keys ? k : n_keys];
+// The scatter takes ranks within a cell from atomics, so the order of a
+// cell's facets varies from run to run; these put them in ascending index.
+// Cells of up to 64 facets: one wave each, a bitonic sort across the lanes
+// in registers (no LDS, so the kernel runs beside a forward sum that holds
+// most of the LDS).  Cells of 65 to kCellSortMax facets: a bitonic sort in
+// LDS, one workgroup per cell, grid-stride over cells.  Larger cells keep
+// the scatter's order.
+constexpr int kCellSortMax = 1024;
+
+__global__ __launch_bounds__(256) void k_cell_sort64(const int *count, const int *offset,
+                                                     long long n_keys, int *perm) {
+    const long long k = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (k >= n_keys) return;
+    const int cnt = count[k];
+    if (cnt <= 1 || cnt > 64) return;
+    const int lane = (int)(threadIdx.x & 63);
+    int *seg = perm + offset[k];
+    int v = lane < cnt ? seg[lane] : 0x7fffffff;
+    for (int size = 2; size <= 64; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const int o = __shfl_xor(v, stride);
+            // ascending runs where (lane & size) == 0; the lower lane of a
+            // pair keeps the smaller value in those
+            const bool keep_min = ((lane & stride) == 0) == ((lane & size) == 0);
+            v = keep_min ? (v < o ? v : o) : (v > o ? v : o);
+        }
+    if (lane < cnt) seg[lane] = v;
+}
+
+__global__ __launch_bounds__(256) void k_cell_sort(const int *count, const int *offset,
+                                                   long long n_keys, int *perm) {
+    __shared__ int v[kCellSortMax];
+    for (long long k = blockIdx.x; k < n_keys; k += gridDim.x) {
+        const int cnt = count[k];
+        if (cnt <= 64 || cnt > kCellSortMax) continue;
+        int m = 128;
+        while (m < cnt) m <<= 1;
+        int *seg = perm + offset[k];
+        for (int i = threadIdx.x; i < m; i += blockDim.x) v[i] = i < cnt ? seg[i] : 0x7fffffff;
+        __syncthreads();
+        for (int size = 2; size <= m; size <<= 1)
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int i = threadIdx.x; i < m; i += blockDim.x) {
+                    const int j = i ^ stride;
+                    if (j > i) {
+                        const int a = v[i], b = v[j];
+                        if ((a > b) == ((i & size) == 0)) {
+                            v[i] = b;
+                            v[j] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        for (int i = threadIdx.x; i < cnt; i += blockDim.x) seg[i] = v[i];
+        __syncthreads();
+    }
+}
+
+// ---- range strips ------------------------------------------------------------
+
+// Strip of every block for band blockIdx.y and channel blockIdx.z: the block
+// centre's sample position at the band's reference pulse (FP64, z = 0),
+// relative to the band's lower edge, in strip widths, clamped to the strips.
+__global__ void k_strip_keys(StripPlan sp, const PulseRec *pulses, const BlockRec *blocks,
+                             const int *n_blocks, int Np, int C, double n_ref, double fs_c,
+                             int *skey, int *scount) {
+    const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= *n_blocks) return;
+    const int band = blockIdx.y, ch = blockIdx.z;
+    const int bc = band * C + ch;
+    int pref = band * sp.B * 64 + sp.B * 32;
+    pref = pref < Np - 1 ? pref : Np - 1;
+    const PulseRec &Q = pulses[(size_t)ch * Np + pref];
+    const BlockRec blk = blocks[b];
+    const double x = blk.xb, y = blk.yb;
+    const double a0 = x - Q.ptx[0], a1 = y - Q.ptx[1], a2 = -Q.ptx[2];
+    const double c0 = x - Q.prx[0], c1 = y - Q.prx[1], c2 = -Q.prx[2];
+    const double u = n_ref + (sqrt(a0 * a0 + a1 * a1 + a2 * a2) +
+                              sqrt(c0 * c0 + c1 * c1 + c2 * c2) - Q.rref) * fs_c;
+    const double *bd = sp.band + 3 * (size_t)bc;
+    double f = floor((u - bd[0]) / bd[1]);
+    f = f < 0.0 ? 0.0 : (f > (double)(sp.NS - 1) ? (double)(sp.NS - 1) : f);
+    const int key = (int)f;
+    skey[(size_t)bc * sp.nbm + b] = key;
+    atomicAdd(scount + (size_t)bc * (sp.NS + 1) + key, 1);
+}
+
+// Per (band, channel): list offsets of the strips (exclusive scan of the
+// counts) and their segment offsets (a strip of c blocks makes ceil(c / L)
+// segments); entry NS holds the totals.  One workgroup of 256 threads each.
+__global__ __launch_bounds__(256) void k_strip_offsets(StripPlan sp, const int *scount) {
+    const size_t bc = (size_t)blockIdx.x;
+    const int *cnt = scount + bc * (sp.NS + 1);
+    int *soff = sp.soff + bc * (sp.NS + 1);
+    int *sego = sp.segoff + bc * (sp.NS + 1);
+    __shared__ int carry[2];
+    if (threadIdx.x == 0) carry[0] = carry[1] = 0;
+    __syncthreads();
+    for (int base = 0; base < sp.NS; base += kScanBlock) {
+        int v[4], w[4];
+        for (int k = 0; k < 4; ++k) {
+            const int i = base + threadIdx.x * 4 + k;
+            v[k] = i < sp.NS ? cnt[i] : 0;
+            w[k] = (v[k] + sp.L - 1) / sp.L;
+        }
+        int tv, tw;
+        block_scan4(v, &tv);
+        block_scan4(w, &tw);
+        const int c0 = carry[0], c1 = carry[1];
+        for (int k = 0; k < 4; ++k) {
+            const int i = base + threadIdx.x * 4 + k;
+            if (i < sp.NS) {
+                soff[i] = v[k] + c0;
+                sego[i] = w[k] + c1;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            carry[0] = c0 + tv;
+            carry[1] = c1 + tw;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        soff[sp.NS] = carry[0];
+        sego[sp.NS] = carry[1];
+    }
+}
+
+// Per (band, channel) one wave lists the blocks strip after strip, each
+// strip's blocks in ascending block index: the wave walks the blocks in
+// order, 64 at a time, and lanes with equal strips take consecutive places
+// after that strip's running count (kept in LDS).  A fixed order, so every
+// run builds the same lists.
+constexpr int kStripMax = 8192;
+
+__global__ __launch_bounds__(64) void k_strip_lists(StripPlan sp, const int *skey,
+                                                    const int *n_blocks) {
+    extern __shared__ int run[];   // [NS]: LDS sized to the strips only
+    const size_t bc = (size_t)blockIdx.x;
+    const int *soff = sp.soff + bc * (sp.NS + 1);
+    const int lane = threadIdx.x;
+    for (int s = lane; s < sp.NS; s += 64) run[s] = soff[s];
+    __syncthreads();
+    const int nb = *n_blocks;
+    const int *key = skey + bc * sp.nbm;
+    int *ids = sp.ids + bc * sp.nbm;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int base = 0; base < nb; base += 64) {
+        const int b = base + lane;
+        const bool valid = b < nb;
+        const int k = valid ? key[b] : -1;
+        unsigned long long pending = __ballot(valid);
+        while (pending) {
+            const int leader = __ffsll((long long)pending) - 1;
+            const int kl = __shfl(k, leader);
+            const unsigned long long same = __ballot(valid && k == kl);
+            const int start = run[kl];
+            if (valid && k == kl) ids[start + __popcll(same & below)] = b;
+            __syncthreads();
+            if (lane == leader) run[kl] = start + __popcll(same);
+            __syncthreads();
+            pending &= ~same;
+        }
+    }
 }
 
 // One wave per block: lane i copies facet start + i into the sorted record,
@@ -295,10 +453,35 @@ hipError_t launch_make_blocks(const int *count, const int *offset, const int *bl
     return hipGetLastError();
 }
 
-hipError_t launch_patch_first(const int *blk_offset, long long n_patches, int keys_per_patch,
-                              long long n_keys, int *patch_first, hipStream_t s) {
-    hipLaunchKernelGGL(k_patch_first, dim3(grid_for(n_patches + 1, 256)), dim3(256), 0, s,
-                       blk_offset, n_patches, keys_per_patch, n_keys, patch_first);
+hipError_t launch_cell_sort(const int *count, const int *offset, long long n_keys, int *perm,
+                            hipStream_t s) {
+    if (n_keys <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cell_sort64, dim3(grid_for(n_keys, 4)), dim3(256), 0, s, count, offset,
+                       n_keys, perm);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // few workgroups: cells of more than 64 facets are rare
+    const long long g = n_keys < 1024 ? n_keys : 1024;
+    hipLaunchKernelGGL(k_cell_sort, dim3((unsigned)g), dim3(256), 0, s, count, offset, n_keys,
+                       perm);
+    return hipGetLastError();
+}
+
+hipError_t launch_strips(const StripPlan &sp, const PulseRec *pulses, const BlockRec *blocks,
+                         const int *n_blocks, int Np, int C, double n_ref, double fs_c, int *skey,
+                         int *scount, hipStream_t s) {
+    if (sp.NS > kStripMax) return hipErrorInvalidValue;
+    hipError_t e = launch_fill_zero((float *)scount, (long long)sp.NB * C * (sp.NS + 1), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_strip_keys, dim3(grid_for(sp.nbm, 256), (unsigned)sp.NB, (unsigned)C),
+                       dim3(256), 0, s, sp, pulses, blocks, n_blocks, Np, C, n_ref, fs_c, skey,
+                       scount);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_strip_offsets, dim3((unsigned)(sp.NB * C)), dim3(256), 0, s, sp,
+                       (const int *)scount);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_strip_lists, dim3((unsigned)(sp.NB * C)), dim3(64),
+                       sizeof(int) * (size_t)sp.NS, s, sp, (const int *)skey, n_blocks);
     return hipGetLastError();
 }
 

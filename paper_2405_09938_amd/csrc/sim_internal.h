@@ -49,13 +49,31 @@ struct TapPoly {
     float o[4][4];
 };
 
-// Lattice of spatial blocks and patches.
+// Lattice of spatial blocks: cell (cx, cy) covers [(bx0 + cx) B, (bx0 + cx + 1) B)
+// x [(by0 + cy) B, ...), key cy nbx + cx.
 struct Lattice {
     double edge;            // block edge B (m)
-    long long bx0, by0;     // lattice origin in cells: x = (bx0 + cx) B
+    long long bx0, by0;     // lattice origin in cells
     int nbx, nby;           // cells along x, y
-    int px, py;             // cells per patch along x, y
-    int npx, npy;           // patches along x, y
+};
+
+// Range strips of the forward sum.  Pulse groups (64 pulses, absolute index
+// p / 64) form bands of B groups.  For band b and channel c, a block belongs
+// to strip floor((u - umin) / S), u its centre's sample position at the
+// band's reference pulse min(64 B b + 32 B, Np - 1), and its facets reach the
+// samples [umin + s S - margin, umin + (s + 1) S + margin) of every pulse of
+// the band (margin: the centre's migration over the band, the facets'
+// offsets from it, heights and drift).  Each strip's blocks are listed in
+// block order and cut into segments of at most L blocks.
+struct StripPlan {
+    const double *band;         // [NB][C][3]: umin, S, margin (samples)
+    int *ids;                   // [NB][C][nbm]: block ids, strip after strip
+    int *soff;                  // [NB][C][NS + 1]: first list position per strip; [NS] total
+    int *segoff;                // [NB][C][NS + 1]: first segment per strip; [NS] total
+    int NB, B, NS;              // bands, groups per band, strips per band and channel
+    int nbm;                    // list stride (the plan's bound on blocks)
+    int L;                      // blocks per segment
+    int seg_max;                // bound on the segments of a band and channel
 };
 
 // Per-antenna constants, passed inside the kernel arguments (constant
@@ -106,16 +124,27 @@ struct SpkArgs {
 };
 
 // Arguments of the fused forward kernel.
+// forward work queues: one per XCD of the MI355X
+constexpr unsigned kFwdQueues = 8;
+
+// Waves of a forward workgroup (narrow windows): each sums every K-th block
+// of a segment into its own LDS window; segments are a multiple of K blocks.
+#ifndef HEEPS_FWD_WAVES
+#define HEEPS_FWD_WAVES 4
+#endif
+constexpr int kFwdWaves = HEEPS_FWD_WAVES;
+
 struct FwdArgs {
     const FacetRec *facets;
     const BlockRec *blocks;
-    const int *patch_first;     // [n_patches + 1] first block of each patch
+    StripPlan st;               // range strips (work units: strip segments)
+    float2 *wsum;               // [C][n_groups][seg_max][64][WIN] window of each work unit
+    unsigned *counter;          // [kFwdQueues] work-queue counters, zero at launch
     const PulseRec *pulses;     // [C][Np]
     float *iq;                  // [C][np][N] complex64 interleaved
     AntArgs ant[SIM_MAX_ANTENNAS];
     ChanArgs ch[SIM_MAX_CHANNELS];
     TapPoly tp;
-    Lattice lat;
     double f0_c, fs_c, n_ref;   // f0/c, fs/c, reference sample
     float linv_hi, linv_lo;     // f0/c split so that linv_hi + linv_lo ~ f0/c
     float fs_cf;                // fs/c in float
@@ -123,13 +152,25 @@ struct FwdArgs {
     int n_groups;               // pulse groups of 64 lanes in the launch
     int gstride;                // pulses between the starts of consecutive groups (64:
                                 // contiguous; the fast mode's node spacing otherwise)
-    int n_patches;
-    int halo;                   // bins added on each side of the patch span
+    int C;
     int rx_exact;               // receiver at each facet's own echo time
     int steer;                  // some antenna frame turns with time
     int grid;                   // 0: no gridded pattern, 1: some antennas, 2: all
     double inv_c;               // 1 / c
     SpkArgs spk;                // speckle variant only
+};
+
+// Arguments of the fixed-order sum of the forward windows into the lines.
+// samples per workgroup of the window reduction (one wave each)
+constexpr int kReduceTile = 4;
+
+struct ReduceArgs {
+    StripPlan st;
+    const float2 *wsum;
+    float2 *iq;                 // [C][np][N]
+    int C, N, Np, p0, np;
+    int n_groups, gstride, poff, win;
+    int n_tiles;                // sample tiles (kReduceTile) per line: the plan's span_tiles
 };
 
 // Arguments of the adjoint kernel.
@@ -200,10 +241,8 @@ struct sim_plan {
     const sim_handle *h;
     long long n;                 // facets
     long long nb_max;            // bound on the block count (size of `blocks`)
-    long long n_patches;
     int flags;                   // SIM_PLAN_* flags the workspace was laid out for
     hs::Lattice lat;
-    int halo;                    // range-window halo in samples (heights, drift)
     int win;                     // LDS range-window width of the forward kernel
     bool el_const = false;       // elevation factors taken at block centres
     double el_bound = 0.0;       // bound on the relative error of doing so
@@ -213,7 +252,11 @@ struct sim_plan {
     hs::BlockRec *blocks = nullptr;     // [nb_max], the first *n_blocks valid
     const int *n_blocks = nullptr;      // device: block count
     unsigned *n_outside = nullptr;      // device: facets outside the plan's box
-    int *patch_first = nullptr;  // [n_patches + 1]
+    unsigned *counter = nullptr;        // device: the forward's work-unit counter
+    hs::StripPlan st{};          // range strips
+    float2 *wsum = nullptr;      // forward windows, for up to ng_max pulse groups
+    int span_tiles = 0;          // tiles of kReduceTile samples covering any band's windows
+    int ng_max = 0;
     hs::FacetRec *sorted = nullptr;     // [n + 1] scratch refreshed by each call
     hs::SpkRec *spk = nullptr;          // [n + 1] speckle records (SIM_PLAN_SPECKLE)
     float4 *anch = nullptr;             // [n + 1][ceil(Np/64) + 1] speckle anchors
@@ -238,8 +281,11 @@ hipError_t launch_block_counts(const int *count, long long n_keys, int *nblk, hi
 hipError_t launch_make_blocks(const int *count, const int *offset, const int *blk_offset,
                               long long n_keys, const Lattice &L, BlockRec *blocks,
                               hipStream_t s);
-hipError_t launch_patch_first(const int *blk_offset, long long n_patches, int keys_per_patch,
-                              long long n_keys, int *patch_first, hipStream_t s);
+hipError_t launch_cell_sort(const int *count, const int *offset, long long n_keys, int *perm,
+                            hipStream_t s);
+hipError_t launch_strips(const StripPlan &sp, const PulseRec *pulses, const BlockRec *blocks,
+                         const int *n_blocks, int Np, int C, double n_ref, double fs_c, int *skey,
+                         int *scount, hipStream_t s);
 hipError_t launch_gather(const sim_facets &f, const int *perm, const BlockRec *blocks,
                          const int *n_blocks, long long nb_max, FacetRec *sorted, hipStream_t s);
 // Copies n doubles from host memory to device memory through kernel
@@ -267,6 +313,9 @@ hipError_t launch_speckle_prep(const SpkPrep &p, const SpkArgs &k, SpkRec *rec, 
 // Hot path.
 hipError_t launch_forward(const FwdArgs &a, int C, int win, bool el_const, bool speckle,
                           hipStream_t s);
+// Sums the forward windows into the lines in a fixed order (after
+// launch_forward on the same stream).
+hipError_t launch_window_reduce(const ReduceArgs &a, hipStream_t s);
 hipError_t launch_adjoint(const AdjArgs &a, bool el_const, bool speckle, hipStream_t s);
 // (the adjoint picks its reception-time variant from a.rx_exact)
 hipError_t launch_waveform(const float *in, float *out, long long n_lines, int N, int M,

@@ -429,7 +429,7 @@ class Plan:
         self.sim, self.ptr, self.n, self.workspace, self.box = sim, ptr, n, workspace, box
         c = ctypes.c_longlong()
         N.check(sim.lib.sim_plan_info(ptr, None, None, ctypes.byref(c), None), "sim_plan_info")
-        self.n_patches = c.value
+        self.n_strips = c.value          # range strips per band and channel (a bound)
         m, bound = ctypes.c_int(), ctypes.c_double()
         N.check(sim.lib.sim_plan_mode(ptr, ctypes.byref(m), ctypes.byref(bound)), "sim_plan_mode")
         # elevation factors taken at block centres (error bound el_bound)

@@ -417,3 +417,71 @@ def test_noalloc_entry_point_refuses_before_device_work(native):
                                             ctypes.c_void_p(16), 0, None) == native.SIM_EINVAL
     finally:
         L.sim_destroy(h)
+
+
+@pytest.mark.parametrize("k", [2, 5])
+def test_strip_windows_hold_every_tap(native, k):
+    """The plan's range strips (sim_plan_geometry) against the oracle's FP64
+    geometry: facets anywhere in a block (random points of the scene, heights
+    up to 4 m, speeds up to 2.5 m/s in any direction) at random pulses of
+    random bands put all 8 taps inside the window the forward sum gives
+    their block's strip, so none takes the global path.  Workload 2 and a
+    chunk of workload 5 (its 9.6 s dwell: the largest drift)."""
+    L = native.load()
+    wl = W.workload(k)
+    g = wl.geometry
+    cfg, keep = _config(native, g)
+    h = ctypes.c_void_p()
+    assert L.sim_create(ctypes.byref(cfg), ctypes.byref(h)) == native.SIM_OK
+    try:
+        from paper_2405_09938_amd.sim import Simulator
+        s, skeep = Simulator._sea_struct(wl.sea)
+        sub = wl.chunks[0] if wl.chunks else (0, 0, wl.sea.nx, wl.sea.ny)
+        bx = native.SimBox()
+        assert L.sim_chunk_box(ctypes.byref(s), *sub, ctypes.byref(bx)) == native.SIM_OK
+        n = sub[2] * sub[3]
+        v = [ctypes.c_int() for _ in range(6)]
+        assert L.sim_plan_geometry(h, n, ctypes.byref(bx), wl.block_edge,
+                                   *[ctypes.byref(x) for x in v], None) == native.SIM_OK
+        win, nb, bg, ns, _, _ = [x.value for x in v]
+        C = g.n_channels
+        bands = np.zeros(nb * C * 3)
+        assert L.sim_plan_geometry(h, n, ctypes.byref(bx), wl.block_edge, None, None, None, None,
+                                   None, None,
+                                   bands.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == 0
+        bands = bands.reshape(nb, C, 3)
+        fs_c = g.fs / g.c
+        n_ref = g.n_ref if g.n_ref >= 0 else g.n_samples // 2
+        rng = np.random.default_rng(k)
+        edge = wl.block_edge
+        worst = -1e9
+        for _ in range(400):
+            b = int(rng.integers(nb))
+            ch = int(rng.integers(C))
+            p = int(rng.integers(b * bg * 64, min((b + 1) * bg * 64, g.n_pulses)))
+            pref = min(b * bg * 64 + bg * 32, g.n_pulses - 1)
+            x = rng.uniform(bx.x_min, bx.x_max)
+            y = rng.uniform(bx.y_min, bx.y_max)
+            xc = (math.floor(x / edge) + 0.5) * edge
+            yc = (math.floor(y / edge) + 0.5) * edge
+            z = rng.uniform(-4.0, 4.0)
+            vel = rng.standard_normal(3)
+            vel *= rng.uniform(0.0, 2.5) / np.linalg.norm(vel)
+
+            def u_at(pp, X):
+                t, ptx, prx, tau = O.pulse_geometry(g, ch, pp)
+                R = np.linalg.norm(X - ptx) + np.linalg.norm(X - prx)
+                return n_ref + (R - g.c * tau) * fs_c, t
+
+            uc, _ = u_at(pref, np.array([xc, yc, 0.0]))
+            t_p = O.pulse_geometry(g, ch, p)[0]
+            uf, _ = u_at(p, np.array([x, y, z]) + vel * t_p)
+            umin, S, margin = bands[b, ch]
+            strip = min(max(int(math.floor((uc - umin) / S)), 0), ns - 1)
+            lo = math.floor(umin + strip * S - margin) - 3
+            first, last = math.floor(uf) - 3, math.floor(uf) + 4
+            assert first >= lo and last <= lo + win - 1, (b, ch, p, first, last, lo, win)
+            worst = max(worst, lo - first, last - (lo + win - 1))
+        print(f"workload {k}: window {win}, tightest tap {-worst} samples inside")
+    finally:
+        L.sim_destroy(h)

@@ -87,7 +87,7 @@ def test_cfg1_forward(torch_cuda, hs):
     got, sim, plan, _ = run_forward(torch_cuda, hs, wl.geometry, f, wl.block_edge)
     ref = O.forward(wl.geometry, f64(f))
     err = O.rel_l2(got, ref)
-    say(f"config 1 IQ rel-L2 {err:.3e} (blocks {plan.n_blocks}, patches {plan.n_patches})")
+    say(f"config 1 IQ rel-L2 {err:.3e} (blocks {plan.n_blocks}, strips per band {plan.n_strips})")
     assert err < IQ_TOL
     assert err < IQ_BUDGET, "precision budget of the block-reference scheme exceeded"
 
