@@ -23,6 +23,10 @@
 #ifndef HEEPS_TARGET_UNITS
 #define HEEPS_TARGET_UNITS 16384
 #endif
+// longest segment (blocks): bounds the facet records a work unit streams
+#ifndef HEEPS_SEG_MAX_BLOCKS
+#define HEEPS_SEG_MAX_BLOCKS 4096
+#endif
 
 namespace {
 
@@ -769,7 +773,8 @@ static int strip_geometry(const sim_handle *h, PlanGeom &G) {
     // segments: enough work units to fill the GPU, long enough to amortise
     // the window flush
     const long long per_band = std::max(1LL, (long long)HEEPS_TARGET_UNITS / ((long long)NG * h->C));
-    long long Ls = std::min(4096LL, std::max(16LL, (G.nb_max / 2 + per_band - 1) / per_band));
+    long long Ls = std::min((long long)HEEPS_SEG_MAX_BLOCKS,
+                            std::max(16LL, (G.nb_max / 2 + per_band - 1) / per_band));
     G.L_seg = (int)((Ls + hs::kFwdWaves - 1) / hs::kFwdWaves * hs::kFwdWaves);
     G.seg_max = G.NS + (int)((G.nb_max + G.L_seg - 1) / G.L_seg);
     return SIM_OK;

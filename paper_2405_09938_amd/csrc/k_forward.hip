@@ -318,33 +318,38 @@ __device__ __forceinline__ void forward_unit(const FwdArgs &A, float2 *accw, int
 
 // Persistent workgroups with one work queue per XCD.  Workgroups go to the
 // 8 XCDs round-robin by linear index, so workgroup b starts on queue b % 8,
-// which holds the segments s with s % 8 == b % 8: all pulse groups of a
-// segment run on one XCD and read its facet records from that XCD's L2.  A
-// queue hands out (segment, channel, pulse group) units, groups fastest; a
-// workgroup whose queue is empty takes units from the next queues in turn.
-// Units of segments a band does not have return at once.  Each workgroup
-// leaves after one failed take per queue, so every workgroup ends; each unit
-// writes only its own window slot, so the result does not depend on who ran
-// it.
+// which holds the segments s with s % 8 == b % 8.  A queue hands out the
+// (segment, channel, pulse group) units of a segment band after band (runs
+// of B groups, the plan's band length), and within a band channel by
+// channel: the units running at one time on an XCD share the segment's
+// facet records (the same blocks, or nearly, in neighbouring bands and
+// channels) through its L2.  A workgroup whose queue is empty takes units
+// from the next queues in turn.  Units of segments a band does not have,
+// or of groups past the last, return at once.  Each workgroup leaves after
+// one failed take per queue, so every workgroup ends; each unit writes only
+// its own window slot, so the result does not depend on who ran it.
 template <int WIN, bool ELC, bool SPK, bool STR, int GRD>
 __global__ __launch_bounds__(64 * fwd_waves<WIN>()) void k_forward(FwdArgs A) {
     __shared__ float2 acc[fwd_waves<WIN>() * 64 * WIN];
     __shared__ unsigned s_unit;
-    const unsigned CG = (unsigned)A.C * (unsigned)A.n_groups;
+    const unsigned B = (unsigned)A.st.B, C = (unsigned)A.C, G = (unsigned)A.n_groups;
+    const unsigned per_seg = C * ((G + B - 1) / B) * B;
     const unsigned segs = (unsigned)A.st.seg_max;
     for (unsigned k = 0; k < kFwdQueues; ++k) {
         const unsigned q = (blockIdx.x + k) % kFwdQueues;
-        const unsigned units = (segs > q ? (segs - q + kFwdQueues - 1) / kFwdQueues : 0u) * CG;
+        const unsigned units = (segs > q ? (segs - q + kFwdQueues - 1) / kFwdQueues : 0u) * per_seg;
         for (;;) {
             __syncthreads();   // the last unit's flush has read the windows
             if (threadIdx.x == 0) s_unit = atomicAdd(A.counter + q, 1u);
             __syncthreads();
             const unsigned u = (unsigned)__builtin_amdgcn_readfirstlane((int)s_unit);
             if (u >= units) break;
-            const unsigned r = u / (unsigned)A.n_groups;
-            forward_unit<WIN, ELC, SPK, STR, GRD>(A, acc, (int)(q + kFwdQueues * (r / (unsigned)A.C)),
-                                                 (int)(u - r * (unsigned)A.n_groups),
-                                                 (int)(r % (unsigned)A.C));
+            const unsigned j = u / per_seg, rest = u - j * per_seg;
+            const unsigned band = rest / (C * B), rem = rest - band * (C * B);
+            const unsigned ch = rem / B, grp = band * B + (rem - ch * B);
+            if (grp >= G) continue;
+            forward_unit<WIN, ELC, SPK, STR, GRD>(A, acc, (int)(q + kFwdQueues * j), (int)grp,
+                                                 (int)ch);
         }
     }
 }
@@ -415,9 +420,10 @@ __global__ __launch_bounds__(64 * kReduceTile) void k_window_reduce(ReduceArgs A
 hipError_t launch_forward(const FwdArgs &a, int C, int win, bool el_const, bool speckle,
                           hipStream_t s) {
     if (a.st.seg_max == 0 || a.np == 0 || a.n_groups == 0) return hipSuccess;
-    const unsigned long long units =
-        (unsigned long long)a.st.seg_max * (unsigned long long)C * (unsigned long long)a.n_groups;
-    if (units > 0xffffffffULL) return hipErrorInvalidConfiguration;
+    const unsigned long long B = (unsigned long long)(a.st.B > 0 ? a.st.B : 1);
+    const unsigned long long units = (unsigned long long)a.st.seg_max * (unsigned long long)C *
+                                     (((unsigned long long)a.n_groups + B - 1) / B * B);
+    if (a.st.B <= 0 || units > 0xffffffffULL) return hipErrorInvalidConfiguration;
     // persistent workgroups: 16 waves per compute unit (at least as many as
     // the LDS windows and the registers let run at once)
     static int n_cu = 0;
