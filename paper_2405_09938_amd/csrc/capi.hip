@@ -775,7 +775,8 @@ static int strip_geometry(const sim_handle *h, PlanGeom &G) {
     const long long per_band = std::max(1LL, (long long)HEEPS_TARGET_UNITS / ((long long)NG * h->C));
     long long Ls = std::min((long long)HEEPS_SEG_MAX_BLOCKS,
                             std::max(16LL, (G.nb_max / 2 + per_band - 1) / per_band));
-    G.L_seg = (int)((Ls + hs::kFwdWaves - 1) / hs::kFwdWaves * hs::kFwdWaves);
+    const int K = hs::fwd_waves(G.win);
+    G.L_seg = (int)((Ls + K - 1) / K * K);
     G.seg_max = G.NS + (int)((G.nb_max + G.L_seg - 1) / G.L_seg);
     return SIM_OK;
 }

@@ -104,14 +104,9 @@ __device__ __forceinline__ SpkFacet load_spk(__amdgpu_buffer_rsrc_t rr, __amdgpu
     return s;
 }
 
-// Windows up to this width take kFwdWaves waves per workgroup, each with its
-// own window; wider windows one wave per workgroup (whose LDS would
-// otherwise limit a compute unit to fewer waves).
-constexpr int kMultiWaveMaxWin = 32;
-
 template <int WIN>
 constexpr int fwd_waves() {
-    return WIN <= kMultiWaveMaxWin ? kFwdWaves : 1;
+    return hs::fwd_waves(WIN);
 }
 
 // SPK: the intra-facet speckle of eq. 7 multiplies each facet's amplitude by

@@ -127,12 +127,14 @@ struct SpkArgs {
 // forward work queues: one per XCD of the MI355X
 constexpr unsigned kFwdQueues = 8;
 
-// Waves of a forward workgroup (narrow windows): each sums every K-th block
-// of a segment into its own LDS window; segments are a multiple of K blocks.
-#ifndef HEEPS_FWD_WAVES
-#define HEEPS_FWD_WAVES 4
-#endif
-constexpr int kFwdWaves = HEEPS_FWD_WAVES;
+// Waves of a forward workgroup for an LDS window of W samples: each wave
+// sums every K-th block of a segment into a window of its own, and the
+// windows are added at the end of the unit.  Four waves, one per SIMD, for
+// windows of up to 32 samples (48 or 64 KB of LDS per workgroup); a
+// workgroup of three waves would put two of its waves on one SIMD and make
+// the others wait at the unit's end (measured 10 % slower on the 32-sample
+// window).  Wider windows: one wave.  Segments are a multiple of K blocks.
+constexpr int fwd_waves(int W) { return W <= 32 ? 4 : 1; }
 
 struct FwdArgs {
     const FacetRec *facets;
