@@ -83,9 +83,19 @@ typedef struct sim_plan sim_plan;       /* opaque host descriptor, owned by the 
  * anchors (needed by sim_forward_speckle / sim_backward_speckle). */
 #define SIM_PLAN_SPECKLE 1
 
-/* Scene rectangle (metres) that every facet position (x, y) of a plan lies in. */
+/* Scene rectangle (metres) that every facet position (x, y) of a plan lies
+ * in, and the plan's bounds on the facets' heights and speeds: z_max, the
+ * largest |z| (metres), and v_max, the largest |V| (m/s).  A zero bound
+ * takes the default (4 m, 2.5 m/s).  The bounds size the forward sum's
+ * range windows (the drift V t over the dwell) and decide whether antenna
+ * elevation factors may be taken at block centres (sim_plan_mode);
+ * sim_chunk_box derives them from a sea state.  A facet beyond them is
+ * still summed exactly (its taps outside a window go straight to the IQ
+ * lines), but the elevation-factor bound no longer covers it:
+ * sim_plan_beyond counts such facets. */
 typedef struct {
     double x_min, x_max, y_min, y_max;
+    double z_max, v_max;
 } sim_box;
 
 /* Straight-line trajectory: position p0 (m) at t = 0, constant velocity v (m/s). */
@@ -343,6 +353,13 @@ void sim_plan_destroy(sim_plan *plan);
 int sim_plan_info(const sim_plan *plan, long long *n_facets, long long *n_blocks,
                   long long *n_strips, long long *n_outside);
 
+/* Host output: the facets of the last sim_forward or sim_backward call on
+ * this plan (made on `stream`) whose |z| or |V| exceeds the bounds of the
+ * plan's box (z_max, v_max); counted by the gather kernel of every call.
+ * Synchronises `stream`.  Errors: SIM_EINVAL (NULL plan or output),
+ * SIM_EHIP. */
+int sim_plan_beyond(const sim_plan *plan, void *stream, long long *n_beyond);
+
 /*
  * Host outputs: the plan's evaluation mode of the antenna elevation factors
  * (Sec. III.B eq. 16 gains).  The field pattern of each antenna is the
@@ -351,7 +368,8 @@ int sim_plan_info(const sim_plan *plan, long long *n_facets, long long *n_blocks
  * block centre (per pulse) instead of per facet: sim_plan_create chooses
  * this only when its bound on the relative error of doing so, *el_bound,
  * is at most 5e-6 for every facet within reach of its block centre (half a
- * block diagonal plus 4 m of height and 2.5 m/s of drift over the dwell).
+ * block diagonal plus the box's z_max of height and v_max of drift over the
+ * dwell).
  * Otherwise *el_const = 0 and every factor is evaluated per facet.
  * Either output pointer may be NULL.  Errors: SIM_EINVAL (NULL plan).
  */
@@ -364,8 +382,13 @@ int sim_sea_table_size(const sim_sea *sea, size_t *bytes);
 /* Host output: a rectangle holding every facet sim_generate_facets makes for
  * the grid sub-rectangle [ix0, ix0+cnx) x [iy0, iy0+cny) of `sea` (cell
  * centres widened by the largest Choppy Wave Model displacement and a
- * rounding margin): the box to plan such facets with.  Host only.
- * Errors: SIM_EINVAL (empty or outside sub-rectangle, bad sea). */
+ * rounding margin), with bounds on the facets' heights and speeds: the sum
+ * of a field's amplitudes and the sum of amplitude x angular frequency plus
+ * the current's speed (twice the sums in mode 2, whose four weights add up
+ * to at most 2); in mode 0, z_max = 1 mm (flat) and v_max = 6 sigma_v (a
+ * speed exceeded with probability below 1e-7 per facet).  The box to plan such
+ * facets with.  Host only.  Errors: SIM_EINVAL (empty or outside
+ * sub-rectangle, bad sea). */
 int sim_chunk_box(const sim_sea *sea, int ix0, int iy0, int cnx, int cny, sim_box *box);
 
 /*

@@ -88,7 +88,8 @@ class SimSea(ctypes.Structure):
 
 class SimBox(ctypes.Structure):
     _fields_ = [("x_min", ctypes.c_double), ("x_max", ctypes.c_double),
-                ("y_min", ctypes.c_double), ("y_max", ctypes.c_double)]
+                ("y_min", ctypes.c_double), ("y_max", ctypes.c_double),
+                ("z_max", ctypes.c_double), ("v_max", ctypes.c_double)]
 
 
 SIM_PLAN_SPECKLE = 1
@@ -101,7 +102,7 @@ class SimSpeckle(ctypes.Structure):
 
 EXPORTS = ("sim_create", "sim_destroy", "sim_last_error", "sim_device_init", "sim_pulse_info",
            "sim_waveform_info", "sim_workspace_size", "sim_plan_create", "sim_plan_destroy",
-           "sim_plan_info", "sim_plan_mode", "sim_sea_table_size", "sim_chunk_box",
+           "sim_plan_info", "sim_plan_beyond", "sim_plan_mode", "sim_sea_table_size", "sim_chunk_box",
            "sim_stream_workspace_size",
            "sim_generate_facets", "sim_forward", "sim_apply_waveform",
            "sim_apply_waveform_adjoint", "sim_backward", "sim_stream_forward",
@@ -146,6 +147,7 @@ def load(path: str = LIB_PATH):
     L.sim_plan_destroy.argtypes = [vp]
     L.sim_plan_destroy.restype = None
     L.sim_plan_info.argtypes = [vp, P(ll), P(ll), P(ll), P(ll)]
+    L.sim_plan_beyond.argtypes = [vp, vp, P(ll)]
     L.sim_plan_mode.argtypes = [vp, P(i), P(ctypes.c_double)]
     L.sim_sea_table_size.argtypes = [P(SimSea), P(sz)]
     L.sim_chunk_box.argtypes = [P(SimSea), i, i, i, i, P(SimBox)]

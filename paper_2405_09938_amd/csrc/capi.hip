@@ -639,6 +639,7 @@ struct PlanGeom {
     std::vector<double> band;    // [NB][C][3]: umin, S, margin
     double el_bound;
     bool el_const;
+    double zlim, vlim;           // bounds on |z| and |V| (the box's or the defaults)
 };
 
 static int box_ok(const sim_box *box) {
@@ -646,8 +647,15 @@ static int box_ok(const sim_box *box) {
     if (!std::isfinite(box->x_min) || !std::isfinite(box->x_max) || !std::isfinite(box->y_min) ||
         !std::isfinite(box->y_max) || !(box->x_min <= box->x_max) || !(box->y_min <= box->y_max))
         HS_FAIL(SIM_EINVAL, "box must be finite with x_min <= x_max and y_min <= y_max");
+    if (!(box->z_max >= 0) || !(box->v_max >= 0) || !std::isfinite(box->z_max) ||
+        !std::isfinite(box->v_max))
+        HS_FAIL(SIM_EINVAL, "box z_max and v_max must be finite and >= 0");
     return SIM_OK;
 }
+
+// The plan's bounds on |z| (m) and |V| (m/s): the box's, or the defaults.
+static double z_limit(const sim_box *box) { return box->z_max > 0 ? box->z_max : 4.0; }
+static double v_limit(const sim_box *box) { return box->v_max > 0 ? box->v_max : 2.5; }
 
 // Sample position u = n_ref + (|X - P_tx| + |X - P_rx| - c tau_ref) fs / c of
 // the point (x, y, 0) at pulse p of channel ch, and the bistatic range
@@ -669,8 +677,9 @@ static double sample_pos(const sim_handle *h, int ch, int p, double x, double y,
 // ~1e-3 for ranges of tens of km and spacings up to km); the migration M,
 // the largest |u(p) - u(p_ref)| over the band's pulses widened by a group on
 // each side (windows of a call need not start on a group boundary);
-// the halo of facet heights (4 m) and drift (2.5 m/s over the band's
-// largest |t|) along the range gradient; E, half a block diagonal along its
+// the halo of facet heights (up to the plan's z bound, 4 m by default) and
+// drift (its speed bound, 2.5 m/s by default, over the band's largest |t|)
+// along the range gradient; E, half a block diagonal along its
 // horizontal part.  margin = M + halo + E + 0.5, and the strip width
 // S = W - 2 margin - 9 keeps every tap of the strip's facets inside a window
 // of W samples.  W is the smallest instantiated width and B then the longest
@@ -680,7 +689,8 @@ struct BandStats {
     std::vector<double> umin, umax, margin;   // [NB][C]
 };
 
-static void band_stats(const sim_handle *h, const hs::Lattice &L, int B, int NB, BandStats &bs) {
+static void band_stats(const sim_handle *h, const hs::Lattice &L, int B, int NB, double zlim,
+                       double vlim, BandStats &bs) {
     const int K = 17;
     const double x0 = ((double)L.bx0 + 0.5) * L.edge, x1 = ((double)(L.bx0 + L.nbx) - 0.5) * L.edge;
     const double y0 = ((double)L.by0 + 0.5) * L.edge, y1 = ((double)(L.by0 + L.nby) - 0.5) * L.edge;
@@ -714,7 +724,7 @@ static void band_stats(const sim_handle *h, const hs::Lattice &L, int B, int NB,
             const double ta = std::fabs(h->pulses_h[(size_t)ch * h->Np + pa].t);
             const double tb = std::fabs(h->pulses_h[(size_t)ch * h->Np + pb].t);
             const size_t k = (size_t)b * h->C + ch;
-            const double halo = (4.0 * gz + 2.5 * std::max(ta, tb) * gn) * bins;
+            const double halo = (zlim * gz + vlim * std::max(ta, tb) * gn) * bins;
             const double E = 0.5 * std::sqrt(2.0) * L.edge * gh * bins;
             bs.umin[k] = lo - 0.05;
             bs.umax[k] = hi + 0.05;
@@ -739,7 +749,7 @@ static int strip_geometry(const sim_handle *h, PlanGeom &G) {
         if (w < HEEPS_WIN_MIN) continue;
         for (int B : Bs) {
             const int NB = (NG + B - 1) / B;
-            band_stats(h, L, B, NB, bs);
+            band_stats(h, L, B, NB, G.zlim, G.vlim, bs);
             double smin = 1e300;
             for (double mg : bs.margin) smin = std::min(smin, w - 2.0 * mg - 9.0);
             if (smin >= 4.0) {
@@ -756,7 +766,7 @@ static int strip_geometry(const sim_handle *h, PlanGeom &G) {
         G.win = 64;
         G.B = 1;
         G.NB = NG;
-        band_stats(h, L, G.B, G.NB, bs);
+        band_stats(h, L, G.B, G.NB, G.zlim, G.vlim, bs);
     }
     G.band.assign((size_t)3 * G.NB * h->C, 0.0);
     G.NS = 1;
@@ -803,11 +813,13 @@ static int plan_geometry(const sim_handle *h, long long n, const sim_box *bx, do
     // a cell of c facets makes ceil(c / 64) blocks: at most one per non-empty
     // cell plus one per 64 facets
     G.nb_max = std::min(n, G.n_keys) + n / 64;
+    G.zlim = z_limit(bx);
+    G.vlim = v_limit(bx);
     if (int rc = strip_geometry(h, G)) return rc;
     const double tmax = 0.5 * (double)(h->Np - 1) / h->prf;
     // facets lie within half a block diagonal of their block centre, moved by
-    // heights up to 4 m and drift at up to 2.5 m/s over the dwell (as the halo)
-    G.el_bound = elevation_bound(h, box, 0.5 * std::sqrt(2.0) * block_edge + 4.0 + 2.5 * tmax);
+    // heights up to zlim and drift at up to vlim over the dwell (as the halo)
+    G.el_bound = elevation_bound(h, box, 0.5 * std::sqrt(2.0) * block_edge + G.zlim + G.vlim * tmax);
     G.el_const = G.el_bound <= HEEPS_EL_CONST_TOL;
     return SIM_OK;
 }
@@ -896,6 +908,9 @@ static int plan_build(const sim_handle *h, const float *x, const float *y, long 
     P.n_blocks = blk_offset + G.n_keys;
     P.n_outside = (unsigned *)(ws + Y.misc);
     P.counter = (unsigned *)(ws + Y.misc + 64);
+    P.beyond = (unsigned *)(ws + Y.misc + 128);
+    P.zlim = G.zlim;
+    P.vlim = G.vlim;
     hs::StripPlan &st = P.st;
     st.band = (const double *)(ws + Y.band);
     st.ids = (int *)(ws + Y.ids);
@@ -926,7 +941,7 @@ static int plan_build(const sim_handle *h, const float *x, const float *y, long 
     const long long nk = G.n_keys;
     hipError_t e = hipSuccess;
     if ((e = hs::launch_fill_zero((float *)count, nk, s)) != hipSuccess ||
-        (e = hs::launch_fill_zero((float *)P.n_outside, 1, s)) != hipSuccess ||
+        (e = hs::launch_fill_zero((float *)P.n_outside, 64, s)) != hipSuccess ||   // misc counters
         (e = hs::launch_cell_keys(x, y, n, G.L, keys, rank, count, P.n_outside, s)) !=
             hipSuccess ||
         (e = hs::launch_exclusive_scan(count, offset, nk, scan_tmp, stl, s)) != hipSuccess ||
@@ -1018,6 +1033,17 @@ int sim_plan_info(const sim_plan *P, long long *n_facets, long long *n_blocks,
         if (n_blocks) *n_blocks = nb;
         if (n_outside) *n_outside = no;
     }
+    return SIM_OK;
+}
+
+int sim_plan_beyond(const sim_plan *P, void *stream, long long *n_beyond) {
+    if (!P || !n_beyond) HS_FAIL(SIM_EINVAL, "plan or n_beyond is NULL");
+    unsigned v = 0;
+    hipStream_t s = (hipStream_t)stream;
+    HS_HIP(hipMemcpyAsync(&v, P->beyond, sizeof(unsigned), hipMemcpyDeviceToHost, s),
+           "plan beyond read");
+    HS_HIP(hipStreamSynchronize(s), "plan beyond sync");
+    *n_beyond = v;
     return SIM_OK;
 }
 
@@ -1132,6 +1158,34 @@ static void chunk_box(const sim_sea *sea, const std::vector<double> &tab, int ix
     box->x_max = x1 + shift + mx;
     box->y_min = y0 - shift - mx;
     box->y_max = y1 + shift + mx;
+    // heights and speeds: per field at most sum A and sum A omega (each
+    // component's velocity has magnitude A omega), weights adding up to at
+    // most 2 in mode 2, plus the current; a flat sea's Gaussian speeds
+    // exceed 6 sigma_v with probability below 1e-7
+    double zs = 0.0, vs = 0.0;
+    if (sea->mode >= 1 && !tab.empty()) {
+        const size_t rows = tab.size() / 6, nc = (size_t)sea->n_comp;
+        for (size_t q = 0; q < rows / nc; ++q) {
+            double a = 0.0, aw = 0.0;
+            for (size_t m = 0; m < nc; ++m) {
+                const double *t = &tab[6 * (q * nc + m)];
+                a += std::fabs(t[1]);
+                aw += std::fabs(t[1]) * t[2];
+            }
+            zs = std::max(zs, a);
+            vs = std::max(vs, aw);
+        }
+        if (sea->mode == 2) {
+            zs *= 2.0;
+            vs *= 2.0;
+        }
+        vs += std::hypot(sea->current[0], sea->current[1]);
+    } else {
+        vs = 6.0 * sea->sigma_v;
+    }
+    // float32 rounding of the generated values, and never 0 (the default)
+    box->z_max = std::max(1e-3, zs * (1.0 + 1e-5) + 1e-6);
+    box->v_max = std::max(1e-3, vs * (1.0 + 1e-5) + 1e-6);
 }
 
 // Launch of the generator for a sub-rectangle, its sea table already on the
@@ -1277,7 +1331,9 @@ static int speckle_prepare(const sim_handle *h, const sim_plan *P, const sim_spe
 static int forward_launch(const sim_handle *h, const sim_plan *P, const sim_facets *f,
                           const sim_speckle *sp, int p0, int np, int n_groups, int gstride,
                           float *iq, hipStream_t s, const int *chunk, int grid_nx) {
-    HS_HIP(hs::launch_gather(*f, P->perm, P->blocks, P->n_blocks, P->nb_max, P->sorted, s),
+    HS_HIP(hs::launch_gather(*f, P->perm, P->blocks, P->n_blocks, P->nb_max, P->sorted,
+                             (float)(P->zlim * (1.0 + 1e-6)), (float)(P->vlim * (1.0 + 1e-6)),
+                             P->beyond, s),
            "gather");
     hs::FwdArgs a{};
     if (sp)
@@ -1449,7 +1505,9 @@ static int backward_common(sim_handle *h, sim_plan *P, const sim_facets *f,
         }
         return SIM_OK;
     }
-    HS_HIP(hs::launch_gather(*f, P->perm, P->blocks, P->n_blocks, P->nb_max, P->sorted, s),
+    HS_HIP(hs::launch_gather(*f, P->perm, P->blocks, P->n_blocks, P->nb_max, P->sorted,
+                             (float)(P->zlim * (1.0 + 1e-6)), (float)(P->vlim * (1.0 + 1e-6)),
+                             P->beyond, s),
            "gather");
     hs::AdjArgs a{};
     if (sp)

@@ -362,7 +362,8 @@ __global__ __launch_bounds__(64) void k_strip_lists(StripPlan sp, const int *ske
 // subtraction of two nearby floats).  The record after the last one is a zero
 // padding record written by the host-side allocation.
 __global__ void k_gather(sim_facets f, const int *perm, const BlockRec *blocks,
-                         const int *n_blocks, FacetRec *sorted) {
+                         const int *n_blocks, FacetRec *sorted, float zlim, float vlim2,
+                         unsigned *beyond) {
     const long long b = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (b >= *n_blocks) return;
     const int lane = threadIdx.x & 63;
@@ -380,6 +381,8 @@ __global__ void k_gather(sim_facets f, const int *perm, const BlockRec *blocks,
     r.ar = f.a_re[i];
     r.ai = f.a_im[i];
     sorted[j] = r;
+    // facets beyond the plan's height and speed bounds (rare: one atomic each)
+    if (fabsf(r.z) > zlim || r.vx * r.vx + r.vy * r.vy + r.vz * r.vz > vlim2) atomicAdd(beyond, 1u);
 }
 
 // Host-to-device copy through the kernel argument segment: each launch
@@ -486,11 +489,12 @@ hipError_t launch_strips(const StripPlan &sp, const PulseRec *pulses, const Bloc
 }
 
 hipError_t launch_gather(const sim_facets &f, const int *perm, const BlockRec *blocks,
-                         const int *n_blocks, long long nb_max, FacetRec *sorted,
-                         hipStream_t s) {
-    if (nb_max == 0) return hipSuccess;
+                         const int *n_blocks, long long nb_max, FacetRec *sorted, float zlim,
+                         float vlim, unsigned *beyond, hipStream_t s) {
+    hipError_t e = launch_fill_zero((float *)beyond, 1, s);
+    if (e != hipSuccess || nb_max == 0) return e;
     hipLaunchKernelGGL(k_gather, dim3(grid_for(nb_max, 4)), dim3(256), 0, s, f, perm, blocks,
-                       n_blocks, sorted);
+                       n_blocks, sorted, zlim, vlim * vlim, beyond);
     return hipGetLastError();
 }
 

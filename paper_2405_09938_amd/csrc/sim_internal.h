@@ -254,7 +254,9 @@ struct sim_plan {
     hs::BlockRec *blocks = nullptr;     // [nb_max], the first *n_blocks valid
     const int *n_blocks = nullptr;      // device: block count
     unsigned *n_outside = nullptr;      // device: facets outside the plan's box
-    unsigned *counter = nullptr;        // device: the forward's work-unit counter
+    unsigned *counter = nullptr;        // device: the forward's work-queue counters
+    unsigned *beyond = nullptr;         // device: facets of the last call beyond zlim, vlim
+    double zlim = 4.0, vlim = 2.5;      // bounds on |z| and |V| the plan was sized for
     hs::StripPlan st{};          // range strips
     float2 *wsum = nullptr;      // forward windows, for up to ng_max pulse groups
     int span_tiles = 0;          // tiles of kReduceTile samples covering any band's windows
@@ -288,8 +290,11 @@ hipError_t launch_cell_sort(const int *count, const int *offset, long long n_key
 hipError_t launch_strips(const StripPlan &sp, const PulseRec *pulses, const BlockRec *blocks,
                          const int *n_blocks, int Np, int C, double n_ref, double fs_c, int *skey,
                          int *scount, hipStream_t s);
+// Gather into the sorted records; counts into *beyond (zeroed here) the
+// facets with |z| > zlim or |V| > vlim.
 hipError_t launch_gather(const sim_facets &f, const int *perm, const BlockRec *blocks,
-                         const int *n_blocks, long long nb_max, FacetRec *sorted, hipStream_t s);
+                         const int *n_blocks, long long nb_max, FacetRec *sorted, float zlim,
+                         float vlim, unsigned *beyond, hipStream_t s);
 // Copies n doubles from host memory to device memory through kernel
 // arguments (stream-ordered, no pinned buffer and no host wait).
 hipError_t launch_upload(double *dst, const double *src, long long n, hipStream_t s);

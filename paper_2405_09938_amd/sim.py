@@ -36,7 +36,10 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 
 
 def _box(b) -> "N.SimBox":
-    return N.SimBox(float(b[0]), float(b[1]), float(b[2]), float(b[3]))
+    """(x_min, x_max, y_min, y_max[, z_max, v_max]); missing or zero bounds on
+    |z| and |V| take the library's defaults."""
+    zv = (float(b[4]), float(b[5])) if len(b) > 4 else (0.0, 0.0)
+    return N.SimBox(float(b[0]), float(b[1]), float(b[2]), float(b[3]), *zv)
 
 
 def _check_f32(t: torch.Tensor, n: int, name: str, device) -> torch.Tensor:
@@ -166,14 +169,16 @@ class Simulator:
 
     def chunk_box(self, sea, ix0: int = 0, iy0: int = 0, cnx: Optional[int] = None,
                   cny: Optional[int] = None):
-        """Rectangle holding every facet generated for a grid sub-rectangle."""
+        """Rectangle holding every facet generated for a grid sub-rectangle,
+        with bounds on their |z| and |V|: (x_min, x_max, y_min, y_max, z_max,
+        v_max)."""
         cnx = sea.nx - ix0 if cnx is None else cnx
         cny = sea.ny - iy0 if cny is None else cny
         s, keep = self._sea_struct(sea)
         bx = N.SimBox()
         N.check(self.lib.sim_chunk_box(ctypes.byref(s), ix0, iy0, cnx, cny, ctypes.byref(bx)),
                 "sim_chunk_box")
-        return (bx.x_min, bx.x_max, bx.y_min, bx.y_max)
+        return (bx.x_min, bx.x_max, bx.y_min, bx.y_max, bx.z_max, bx.v_max)
 
     @staticmethod
     def _sea_struct(sea):
@@ -450,6 +455,16 @@ class Plan:
     def n_outside(self) -> int:
         """Facets outside the plan's box (read back from the device)."""
         return self._counts()[1]
+
+    def n_beyond(self, stream=None) -> int:
+        """Facets of the last forward or backward call (made on `stream`, the
+        current stream by default) beyond the plan's bounds on |z| and |V|
+        (read back from the device: waits for that stream)."""
+        st = torch.cuda.current_stream(self.sim.device) if stream is None else stream
+        v = ctypes.c_longlong()
+        N.check(self.sim.lib.sim_plan_beyond(self.ptr, ctypes.c_void_p(st.cuda_stream),
+                                             ctypes.byref(v)), "sim_plan_beyond")
+        return v.value
 
     def close(self):
         if getattr(self, "ptr", None):

@@ -423,10 +423,11 @@ def test_noalloc_entry_point_refuses_before_device_work(native):
 def test_strip_windows_hold_every_tap(native, k):
     """The plan's range strips (sim_plan_geometry) against the oracle's FP64
     geometry: facets anywhere in a block (random points of the scene, heights
-    up to 4 m, speeds up to 2.5 m/s in any direction) at random pulses of
-    random bands put all 8 taps inside the window the forward sum gives
-    their block's strip, so none takes the global path.  Workload 2 and a
-    chunk of workload 5 (its 9.6 s dwell: the largest drift)."""
+    and speeds in any direction up to the bounds sim_chunk_box derives from
+    the sea) at random pulses of random bands put all 8 taps inside the
+    window the forward sum gives their block's strip, so none takes the
+    global path.  Workload 2 and a chunk of workload 5 (its 9.6 s dwell: the
+    largest drift)."""
     L = native.load()
     wl = W.workload(k)
     g = wl.geometry
@@ -464,9 +465,9 @@ def test_strip_windows_hold_every_tap(native, k):
             y = rng.uniform(bx.y_min, bx.y_max)
             xc = (math.floor(x / edge) + 0.5) * edge
             yc = (math.floor(y / edge) + 0.5) * edge
-            z = rng.uniform(-4.0, 4.0)
+            z = rng.uniform(-bx.z_max, bx.z_max)
             vel = rng.standard_normal(3)
-            vel *= rng.uniform(0.0, 2.5) / np.linalg.norm(vel)
+            vel *= rng.uniform(0.0, bx.v_max) / np.linalg.norm(vel)
 
             def u_at(pp, X):
                 t, ptx, prx, tau = O.pulse_geometry(g, ch, pp)
@@ -483,5 +484,58 @@ def test_strip_windows_hold_every_tap(native, k):
             assert first >= lo and last <= lo + win - 1, (b, ch, p, first, last, lo, win)
             worst = max(worst, lo - first, last - (lo + win - 1))
         print(f"workload {k}: window {win}, tightest tap {-worst} samples inside")
+    finally:
+        L.sim_destroy(h)
+
+
+def test_chunk_box_height_and_speed_bounds(native):
+    """sim_chunk_box's bounds on |z| and |V| hold for every facet the oracle's
+    generator makes (the generator the GPU's is checked against): a wave sea
+    with a current, a tiled sea (mode 2) and a flat sea's Gaussian speeds
+    (6 sigma_v).  A gross overestimate fails too: each bound within 4x of
+    the sample's largest value (the triangle inequality over 64 components
+    of random phase gives about 2-3x), 6x in mode 2 (whose four corner
+    weights may add up to 2, and whose bound takes the roughest node).  Boxes with negative or non-finite
+    bounds are refused, and tighter bounds give fewer, wider strips."""
+    L = native.load()
+    from paper_2405_09938_amd.sim import Simulator
+    cases = [(W.wave_sea(200, 150, 1.0, seed=5, current_speed=0.5), (20, 10, 150, 120)),
+             (W.hetero_sea(300, 200, 1.3, seed=6, tile_L=80.0, current_speed=0.4), (0, 0, 300, 200)),
+             (W.flat_sea(300, 300, 1.0, sigma_v=0.5), (0, 0, 300, 300))]
+    for sea, sub in cases:
+        s, keep = Simulator._sea_struct(sea)
+        b = native.SimBox()
+        assert L.sim_chunk_box(ctypes.byref(s), *sub, ctypes.byref(b)) == native.SIM_OK
+        f = O.generate_facets(sea, 3, *sub)
+        zmax = float(np.abs(f["z"]).max())
+        vmax = float(np.sqrt(f["vx"] ** 2 + f["vy"] ** 2 + f["vz"] ** 2).max())
+        print(f"mode {sea.mode}: |z| <= {zmax:.3f} (bound {b.z_max:.3f}), "
+              f"|V| <= {vmax:.3f} (bound {b.v_max:.3f})")
+        assert zmax <= b.z_max and vmax <= b.v_max
+        loose = 6.0 if sea.mode == 2 else 4.0
+        assert b.v_max <= loose * vmax
+        if sea.mode >= 1:
+            assert b.z_max <= loose * zmax
+        else:
+            assert b.z_max <= 1e-3
+    g = W.harmony_geometry(64, 256)
+    cfg, keep = _config(native, g)
+    h = ctypes.c_void_p()
+    assert L.sim_create(ctypes.byref(cfg), ctypes.byref(h)) == native.SIM_OK
+    try:
+        n = ctypes.c_size_t()
+        for zv in ((-1.0, 0.0), (0.0, -0.5), (float("nan"), 1.0), (1.0, float("inf"))):
+            bx = native.SimBox(-100.0, 100.0, -100.0, 100.0, *zv)
+            assert L.sim_workspace_size(h, 1000, ctypes.byref(bx), 8.0, 0,
+                                        ctypes.byref(n)) == native.SIM_EINVAL
+            assert "z_max" in L.sim_last_error().decode()
+        # tighter bounds: narrower margins, so wider strips (fewer of them)
+        def strips(zv):
+            bx = native.SimBox(-500.0, 500.0, -500.0, 500.0, *zv)
+            v = [ctypes.c_int() for _ in range(6)]
+            assert L.sim_plan_geometry(h, 100000, ctypes.byref(bx), 8.0,
+                                       *[ctypes.byref(x) for x in v], None) == native.SIM_OK
+            return v[3].value
+        assert strips((0.5, 0.2)) < strips((0.0, 0.0)) < strips((8.0, 6.0))
     finally:
         L.sim_destroy(h)

@@ -300,3 +300,37 @@ def test_autograd_vs_oracle_fd(torch_cuda, hs):
         e = O.rel_l2(gpu[k][idx], np.array(fd))
         say(f"autograd {k} vs Richardson FD (h={h}): rel-L2 {e:.3e}")
         assert e < GRAD_TOL, k
+
+
+def test_facets_beyond_the_plan_bounds(torch_cuda, hs):
+    """A plan sized for |z| <= 0.5 m and |V| <= 0.5 m/s given facets with
+    larger heights and speeds: the gather counts exactly the facets past
+    either bound (sim_plan_beyond), and they are still summed to the oracle's
+    bar (their taps outside a window go straight to the lines)."""
+    torch = torch_cuda
+    say("case: 3000 scattered facets, plan bounds z 0.5 m / V 0.5 m/s, 200 pulses")
+    g = W.harmony_geometry(200, 512)
+    f = W.scattered_facets(3000, 150.0, seed=21, sigma_v=0.7, sigma_z=0.8)
+    sim = hs.Simulator(g)
+    d = to_dev(torch, f)
+    box = (-150.01, 150.01, -150.01, 150.01, 0.5, 0.5)
+    plan = sim.plan(d["x"], d["y"], 8.0, box=box)
+    iq = sim.forward(plan, d)
+    n_beyond = plan.n_beyond()
+    z = np.abs(np.asarray(f["z"], np.float32))
+    v2 = (np.asarray(f["vx"], np.float32) ** 2 + np.asarray(f["vy"], np.float32) ** 2
+          + np.asarray(f["vz"], np.float32) ** 2)
+
+    def count(zl, vl):
+        zl, vl = np.float32(zl * (1 + 1e-6)), np.float32(vl * (1 + 1e-6))
+        return int(np.count_nonzero((z > zl) | (v2 > vl * vl)))
+
+    want = count(0.5, 0.5)
+    err = O.rel_l2(iq.cpu().numpy().astype(np.complex128), O.forward(g, f64(f)))
+    say(f"beyond the bounds: {n_beyond} (host count {want}); rel-L2 {err:.3e}")
+    assert n_beyond == want and want > 1000
+    assert err < IQ_TOL
+    # the default bounds (4 m, 2.5 m/s): only the fastest few facets
+    plan2 = sim.plan(d["x"], d["y"], 8.0, box=box[:4])
+    sim.forward(plan2, d)
+    assert plan2.n_beyond() == count(4.0, 2.5)
