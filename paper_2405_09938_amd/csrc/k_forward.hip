@@ -223,7 +223,6 @@ __device__ __forceinline__ void forward_unit(const FwdArgs &A, float2 *accw, int
         // the floor of the sample position is the window index directly
         r.fb += (float)(r.nb - lo - 3);
         const __amdgpu_buffer_rsrc_t rs = facet_rsrc(A.facets + blk.start, blk.count);
-        FacetV fn = load_facet(rs, 0);
         // speckle records and anchors of the block (unused without speckle)
         const int ng1 = S.n_groups + 1;
         const __amdgpu_buffer_rsrc_t rs_rec = __builtin_amdgcn_make_buffer_rsrc(
@@ -231,15 +230,11 @@ __device__ __forceinline__ void forward_unit(const FwdArgs &A, float2 *accw, int
         const __amdgpu_buffer_rsrc_t rs_anc = __builtin_amdgcn_make_buffer_rsrc(
             (void *)(S.anch + (size_t)blk.start * ng1), 0,
             (blk.count + 1) * ng1 * (int)sizeof(float4), 0x00020000);
-        [[maybe_unused]] SpkFacet sn{};
-        if constexpr (SPK) sn = load_spk(rs_rec, rs_anc, 0, ng1, gabs);
-        for (int j = 0; j < blk.count; ++j) {
-            const FacetV f = fn;
-            fn = load_facet(rs, j + 1);
+        // one facet: its contributions to the lanes' pulses (sp: its speckle
+        // record, unused without speckle)
+        const auto one = [&](const FacetV &f, [[maybe_unused]] const SpkFacet &sp) {
             float far = f.ar, fai = f.ai, dop = 0.0f;
             if constexpr (SPK) {
-                const SpkFacet sp = sn;
-                sn = load_spk(rs_rec, rs_anc, j + 1, ng1, gabs);
                 // free path of the group: innovations, prefix sum, end value
                 const float2 e = spk_draw(S.key, sp.id, slot, l1);
                 float wr = e.x, wi = e.y;
@@ -290,7 +285,23 @@ __device__ __forceinline__ void forward_unit(const FwdArgs &A, float2 *accw, int
                     }
                 }
             }
+        };
+        // two facets per trip with the next record's loads issued a facet
+        // ahead, alternating between two register sets (no copies)
+        FacetV fa = load_facet(rs, 0);
+        [[maybe_unused]] SpkFacet sa{};
+        if constexpr (SPK) sa = load_spk(rs_rec, rs_anc, 0, ng1, gabs);
+        int j = 0;
+        for (; j + 1 < blk.count; j += 2) {
+            const FacetV fb = load_facet(rs, j + 1);
+            [[maybe_unused]] SpkFacet sb{};
+            if constexpr (SPK) sb = load_spk(rs_rec, rs_anc, j + 1, ng1, gabs);
+            one(fa, sa);
+            fa = load_facet(rs, j + 2);
+            if constexpr (SPK) sa = load_spk(rs_rec, rs_anc, j + 2, ng1, gabs);
+            one(fb, sb);
         }
+        if (j < blk.count) one(fa, sa);
     }
 
     // the unit's window to its own slot of the scratch, sample-major like
