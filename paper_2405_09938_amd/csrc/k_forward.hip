@@ -230,9 +230,16 @@ __device__ __forceinline__ void forward_unit(const FwdArgs &A, float2 *accw, int
         const __amdgpu_buffer_rsrc_t rs_anc = __builtin_amdgcn_make_buffer_rsrc(
             (void *)(S.anch + (size_t)blk.start * ng1), 0,
             (blk.count + 1) * ng1 * (int)sizeof(float4), 0x00020000);
-        // one facet: its contributions to the lanes' pulses (sp: its speckle
-        // record, unused without speckle)
-        const auto one = [&](const FacetV &f, [[maybe_unused]] const SpkFacet &sp) {
+        // A facet's contribution to the lanes' pulses: window index of its
+        // first tap, complex weight and tap fraction (sp: its speckle record,
+        // unused without speckle).
+        struct Dep {
+            int n0;            // window index of the first tap
+            float wr, wi;      // complex weight (amplitude x phase x gain)
+            float f;           // tap fraction (the taps are made at the deposit)
+        };
+        const auto inside = [](const Dep &d) { return (unsigned)d.n0 <= (unsigned)(WIN - 8); };
+        const auto prep = [&](const FacetV &f, [[maybe_unused]] const SpkFacet &sp, Dep &d) {
             float far = f.ar, fai = f.ai, dop = 0.0f;
             if constexpr (SPK) {
                 // free path of the group: innovations, prefix sum, end value
@@ -255,53 +262,93 @@ __device__ __forceinline__ void forward_unit(const FwdArgs &A, float2 *accw, int
             Geo g;
             facet_geo<ELC, SPK, STR, GRD>(r, kc, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz, graze_any, r.lhi,
                                 r.llo, r.fsq, dop, g, &ta, &ra, rot);
-            // Each lane owns its pulse row, so the deposit is a plain
-            // read-modify-write of 8 consecutive complex samples.
-            const int n0 = g.fl;                  // window index of the first tap
-            const bool inw = (unsigned)n0 <= (unsigned)(WIN - 8);
-            float2 *p = col + 64 * (inw ? n0 : 0);
+            d.n0 = g.fl;
+            d.wr = g.amp * fmaf(far, g.cs, -(fai * g.sn));
+            d.wi = g.amp * fmaf(far, g.sn, fai * g.cs);
+            d.f = g.f;
+        };
+        // Each lane owns its pulse row, so a deposit is a plain
+        // read-modify-write of 8 consecutive complex samples; a lane whose
+        // taps leave the window adds zero there and sends them straight to
+        // its line (taps inside [0, N)).
+        const auto deposit = [&](const Dep &d) {
+            const bool inw = inside(d);
+            float2 *p = col + 64 * (inw ? d.n0 : 0);
             float2 old[8];
 #pragma unroll
             for (int k = 0; k < 8; ++k) old[k] = p[64 * k];
-            // a lane outside the window adds zero to its row (and goes below)
-            const float al = inw ? g.amp : 0.0f;
-            const float wrl = al * fmaf(far, g.cs, -(fai * g.sn));
-            const float wil = al * fmaf(far, g.sn, fai * g.cs);
+            const float wrl = inw ? d.wr : 0.0f, wil = inw ? d.wi : 0.0f;
             float tap[8];
-            taps8(tv, g.f, tap);
+            taps8(tv, d.f, tap);
 #pragma unroll
             for (int k = 0; k < 8; ++k)
                 p[64 * k] = make_float2(fmaf(wrl, tap[k], old[k].x), fmaf(wil, tap[k], old[k].y));
             if (!inw && live) {
-                const float wr = g.amp * fmaf(far, g.cs, -(fai * g.sn));
-                const float wi = g.amp * fmaf(far, g.sn, fai * g.cs);
-                // outside the window: straight to the line, taps inside [0, N)
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
-                    const int n = n0 + lo + k;
+                    const int n = d.n0 + lo + k;
                     if (n >= 0 && n < A.N) {
-                        unsafeAtomicAdd(iq_row + 2 * n, wr * tap[k]);
-                        unsafeAtomicAdd(iq_row + 2 * n + 1, wi * tap[k]);
+                        unsafeAtomicAdd(iq_row + 2 * n, d.wr * tap[k]);
+                        unsafeAtomicAdd(iq_row + 2 * n + 1, d.wi * tap[k]);
                     }
                 }
             }
         };
-        // two facets per trip with the next record's loads issued a facet
-        // ahead, alternating between two register sets (no copies)
-        FacetV fa = load_facet(rs, 0);
-        [[maybe_unused]] SpkFacet sa{};
-        if constexpr (SPK) sa = load_spk(rs_rec, rs_anc, 0, ng1, gabs);
+        // Two facets whose taps start at the same window index on every lane
+        // (neighbours in a cell mostly do): one read-modify-write for both,
+        // with the same additions in the same order as two deposits.
+        const auto deposit2 = [&](const Dep &a, const Dep &b) {
+            float2 *p = col + 64 * a.n0;
+            float2 old[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) old[k] = p[64 * k];
+            float ta[8], tb[8];
+            taps8(tv, a.f, ta);
+            taps8(tv, b.f, tb);
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                p[64 * k] = make_float2(fmaf(b.wr, tb[k], fmaf(a.wr, ta[k], old[k].x)),
+                                        fmaf(b.wi, tb[k], fmaf(a.wi, ta[k], old[k].y)));
+        };
+        // Facets in pairs; each record's load is issued as soon as the one
+        // before it in its register set is used (about one facet ahead).
+        FacetV fa = load_facet(rs, 0), fb = load_facet(rs, 1);
+        [[maybe_unused]] SpkFacet sa{}, sb{};
+        if constexpr (SPK) {
+            sa = load_spk(rs_rec, rs_anc, 0, ng1, gabs);
+            sb = load_spk(rs_rec, rs_anc, 1, ng1, gabs);
+        }
+        // (Merging keeps both facets' results live across the second one's
+        // geometry: the variants that would lose a wave per SIMD to it, per
+        // facet elevation factors without speckle or steering, deposit each
+        // facet as soon as it is made.)
+        constexpr bool kMerge = ELC || SPK || STR;
         int j = 0;
         for (; j + 1 < blk.count; j += 2) {
-            const FacetV fb = load_facet(rs, j + 1);
-            [[maybe_unused]] SpkFacet sb{};
-            if constexpr (SPK) sb = load_spk(rs_rec, rs_anc, j + 1, ng1, gabs);
-            one(fa, sa);
+            Dep da, db;
+            prep(fa, sa, da);
             fa = load_facet(rs, j + 2);
             if constexpr (SPK) sa = load_spk(rs_rec, rs_anc, j + 2, ng1, gabs);
-            one(fb, sb);
+            if constexpr (!kMerge) deposit(da);
+            prep(fb, sb, db);
+            fb = load_facet(rs, j + 3);
+            if constexpr (SPK) sb = load_spk(rs_rec, rs_anc, j + 3, ng1, gabs);
+            if constexpr (kMerge) {
+                if (__all(inside(da) && da.n0 == db.n0)) {
+                    deposit2(da, db);
+                } else {
+                    deposit(da);
+                    deposit(db);
+                }
+            } else {
+                deposit(db);
+            }
         }
-        if (j < blk.count) one(fa, sa);
+        if (j < blk.count) {
+            Dep d;
+            prep(fa, sa, d);
+            deposit(d);
+        }
     }
 
     // the unit's window to its own slot of the scratch, sample-major like
@@ -334,8 +381,18 @@ __device__ __forceinline__ void forward_unit(const FwdArgs &A, float2 *accw, int
 // or of groups past the last, return at once.  Each workgroup leaves after
 // one failed take per queue, so every workgroup ends; each unit writes only
 // its own window slot, so the result does not depend on who ran it.
+// Variants that deposit facets one at a time (no pair merge: per-facet
+// elevation factors without speckle or steering) are held to three waves
+// per SIMD (168 VGPRs) where the LDS allows three (24-sample windows); the
+// others take what their registers allow.
+template <int WIN, bool ELC, bool SPK, bool STR>
+constexpr int fwd_min_waves() {
+    return (WIN <= 24 && !(ELC || SPK || STR)) ? 3 : 1;
+}
+
 template <int WIN, bool ELC, bool SPK, bool STR, int GRD>
-__global__ __launch_bounds__(64 * fwd_waves<WIN>()) void k_forward(FwdArgs A) {
+__global__ __launch_bounds__(64 * fwd_waves<WIN>())
+__attribute__((amdgpu_waves_per_eu(fwd_min_waves<WIN, ELC, SPK, STR>()))) void k_forward(FwdArgs A) {
     __shared__ float2 acc[fwd_waves<WIN>() * 64 * WIN];
     __shared__ unsigned s_unit;
     const unsigned B = (unsigned)A.st.B, C = (unsigned)A.C, G = (unsigned)A.n_groups;
