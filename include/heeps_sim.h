@@ -598,11 +598,15 @@ int sim_forward_fast(sim_handle *h, sim_plan *plan, const sim_facets *facets, in
  * (the one call that allocates).  Every call on one GPU shares that GPU's
  * array and leaves its contents behind (everything the call needs zeroed is
  * cleared on its stream): calls that overlap on one GPU race, so serialise
- * them (one stream, or events between streams).
- * Errors: as sim_stream_forward; SIM_EINVAL if the call needs more than
- * SIM_NOALLOC_SCRATCH_BYTES (sim_stream_workspace_size with flags 0 gives the
- * need: the sea table, 32 bytes per facet of the largest chunk and its plan,
- * about 68 bytes per facet in all) or the handle was not initialised here.
+ * them (one stream, or events between streams).  When the call's workspace
+ * (sim_stream_workspace_size with flags 0: the sea table, 32 bytes per facet
+ * of the largest chunk and its plan, whose window slots grow with the pulse
+ * groups and channels) exceeds the scratch, the plans hold window slots for
+ * as many pulse groups as fit and the sum runs in passes over the groups:
+ * the same bits, more launches.
+ * Errors: as sim_stream_forward; SIM_EINVAL if the call does not fit even
+ * with slots for one pulse group (about 1e6 facets per chunk over 16384
+ * pulses and 3 channels) or the handle was not initialised here.
  */
 int sim_stream_forward_noalloc(sim_handle *h, const sim_sea *sea, unsigned long long seed,
                                const int *chunks, int n_chunks, double block_edge, int p0,

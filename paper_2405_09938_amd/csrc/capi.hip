@@ -636,6 +636,7 @@ struct PlanGeom {
     long long n_keys, nb_max;
     int win;
     int NB, B, NS, L_seg, seg_max, ng_max;
+    int ng_slots;                // pulse groups the window slots hold (<= ng_max)
     std::vector<double> band;    // [NB][C][3]: umin, S, margin
     double el_bound;
     bool el_const;
@@ -737,6 +738,7 @@ static int strip_geometry(const sim_handle *h, PlanGeom &G) {
     const hs::Lattice &L = G.L;
     const int NG = (h->Np + 63) / 64;
     G.ng_max = NG + 1;
+    G.ng_slots = G.ng_max;
     // candidate band lengths, longest first
     std::vector<int> Bs;
     for (int b = 1; b < NG; b *= 4) Bs.push_back(b);
@@ -861,7 +863,7 @@ static PlanLayout plan_layout(const PlanGeom &G, long long n, int flags, int Np)
     Y.scount = take(sizeof(int) * bcn * ((size_t)G.NS + 1));
     Y.soff = take(sizeof(int) * bcn * ((size_t)G.NS + 1));
     Y.segoff = take(sizeof(int) * bcn * ((size_t)G.NS + 1));
-    const size_t units = bcn / (size_t)G.NB * (size_t)G.ng_max * (size_t)G.seg_max;
+    const size_t units = bcn / (size_t)G.NB * (size_t)G.ng_slots * (size_t)G.seg_max;
     Y.wsum = take(sizeof(float2) * units * 64 * (size_t)G.win);
     if (flags & SIM_PLAN_SPECKLE) {
         const size_t groups = (size_t)((Np + 63) / 64) + 1;
@@ -923,7 +925,7 @@ static int plan_build(const sim_handle *h, const float *x, const float *y, long 
     st.L = G.L_seg;
     st.seg_max = G.seg_max;
     P.wsum = (float2 *)(ws + Y.wsum);
-    P.ng_max = G.ng_max;
+    P.ng_slots = G.ng_slots;
     // sample span of any band's windows, in tiles of the window reduction
     {
         long long span = 1;
@@ -1339,7 +1341,7 @@ static int forward_launch(const sim_handle *h, const sim_plan *P, const sim_face
     if (sp)
         if (int rc = speckle_prepare(h, P, sp, p0, np, false, chunk, grid_nx, s, a.spk))
             return rc;
-    if (n_groups > P->ng_max) HS_FAIL(SIM_EINVAL, "more pulse groups than the plan's windows");
+    if (P->ng_slots < 1) HS_FAIL(SIM_EINVAL, "the plan has no window slots");
     a.facets = P->sorted;
     a.blocks = P->blocks;
     a.st = P->st;
@@ -1367,9 +1369,6 @@ static int forward_launch(const sim_handle *h, const sim_plan *P, const sim_face
     a.steer = h->steer;
     a.grid = h->grid;
     a.inv_c = 1.0 / h->c;
-    HS_HIP(hs::launch_fill_zero((float *)P->counter, hs::kFwdQueues, s), "work queues");
-    HS_HIP(hs::launch_forward(a, h->C, P->win, P->el_const && !h->grid, sp != nullptr, s),
-           "forward");
     hs::ReduceArgs r{};
     r.st = P->st;
     r.wsum = P->wsum;
@@ -1379,12 +1378,22 @@ static int forward_launch(const sim_handle *h, const sim_plan *P, const sim_face
     r.Np = h->Np;
     r.p0 = p0;
     r.np = np;
-    r.n_groups = n_groups;
     r.gstride = gstride;
     r.poff = sp ? (p0 & 63) : 0;
     r.win = P->win;
     r.n_tiles = P->span_tiles;
-    HS_HIP(hs::launch_window_reduce(r, s), "window reduce");
+    // the pulse groups in passes of as many as the window slots hold (one
+    // pass unless the plan was laid out for fewer groups), each summed and
+    // reduced before the next reuses the slots
+    for (int g0 = 0; g0 < n_groups; g0 += P->ng_slots) {
+        const int ng = std::min(P->ng_slots, n_groups - g0);
+        a.g0 = r.g0 = g0;
+        a.n_groups = r.n_groups = ng;
+        HS_HIP(hs::launch_fill_zero((float *)P->counter, hs::kFwdQueues, s), "work queues");
+        HS_HIP(hs::launch_forward(a, h->C, P->win, P->el_const && !h->grid, sp != nullptr, s),
+               "forward");
+        HS_HIP(hs::launch_window_reduce(r, s), "window reduce");
+    }
     return SIM_OK;
 }
 
@@ -1623,16 +1632,35 @@ extern "C" {
 // arrays of the largest chunk) and the plan of the largest chunk layout.
 struct StreamLayout {
     size_t tab = 0, facets = 0, facet_stride = 0, plan = 0, total = 0;
+    long long max_n = 0;
     std::vector<PlanGeom> geom;     // per chunk
     std::vector<PlanLayout> lay;    // per chunk
 };
 
+// Layouts of the chunks' plans with window slots for at most ng_cap pulse
+// groups, and the offsets and total of the streamed workspace.
+static void stream_relayout(const sim_handle *h, const int *chunks, int n_chunks, int flags,
+                            int ng_cap, long long max_n, size_t tab_doubles, StreamLayout &Y) {
+    size_t plan_bytes = 0;
+    for (int k = 0; k < n_chunks; ++k) {
+        const int *c = chunks + 4 * k;
+        Y.geom[k].ng_slots = std::max(1, std::min(Y.geom[k].ng_max, ng_cap));
+        Y.lay[k] = plan_layout(Y.geom[k], (long long)c[2] * c[3], flags, h->Np);
+        plan_bytes = std::max(plan_bytes, Y.lay[k].total);
+    }
+    Y.tab = 0;
+    Y.facets = align256(sizeof(double) * tab_doubles);
+    Y.facet_stride = align256(sizeof(float) * (size_t)max_n);
+    Y.plan = Y.facets + 8 * Y.facet_stride;
+    Y.total = Y.plan + plan_bytes;
+}
+
 static int stream_layout(const sim_handle *h, const sim_sea *sea, const int *chunks,
                          int n_chunks, double block_edge, int flags,
-                         const std::vector<double> &tab, StreamLayout &Y) {
+                         const std::vector<double> &tab, StreamLayout &Y,
+                         int ng_cap = 1 << 30) {
     long long max_n = 0;
     if (int rc = check_chunks(sea, chunks, n_chunks, &max_n)) return rc;
-    size_t plan_bytes = 0;
     Y.geom.resize(n_chunks);
     Y.lay.resize(n_chunks);
     for (int k = 0; k < n_chunks; ++k) {
@@ -1641,14 +1669,9 @@ static int stream_layout(const sim_handle *h, const sim_sea *sea, const int *chu
         chunk_box(sea, tab, c[0], c[1], c[2], c[3], &box);
         const long long n = (long long)c[2] * c[3];
         if (int rc = plan_geometry(h, n, &box, block_edge, Y.geom[k])) return rc;
-        Y.lay[k] = plan_layout(Y.geom[k], n, flags, h->Np);
-        plan_bytes = std::max(plan_bytes, Y.lay[k].total);
     }
-    Y.tab = 0;
-    Y.facets = align256(sizeof(double) * tab.size());
-    Y.facet_stride = align256(sizeof(float) * (size_t)max_n);
-    Y.plan = Y.facets + 8 * Y.facet_stride;
-    Y.total = Y.plan + plan_bytes;
+    Y.max_n = max_n;
+    stream_relayout(h, chunks, n_chunks, flags, ng_cap, max_n, tab.size(), Y);
     return SIM_OK;
 }
 
@@ -1679,7 +1702,7 @@ int sim_stream_workspace_size(const sim_handle *h, const sim_sea *sea, const int
 // Checks, lays out the workspace and uploads the sea table of a streamed call.
 static int stream_setup(sim_handle *h, const sim_sea *sea, const int *chunks, int n_chunks,
                         double block_edge, const sim_speckle *sp, int p0, int np, void *ws,
-                        size_t ws_bytes, hipStream_t s, StreamLayout &Y) {
+                        size_t ws_bytes, hipStream_t s, StreamLayout &Y, int ng_cap = 1 << 30) {
     if (!h) HS_FAIL(SIM_EINVAL, "handle is NULL");
     if (!sea) HS_FAIL(SIM_EINVAL, "sea is NULL");
     long long max_n = 0;
@@ -1690,7 +1713,8 @@ static int stream_setup(sim_handle *h, const sim_sea *sea, const int *chunks, in
     std::vector<double> &tab = h->gen_tab_h;
     sea_table(sea, tab);
     const int flags = sp ? SIM_PLAN_SPECKLE : 0;
-    if (int rc = stream_layout(h, sea, chunks, n_chunks, block_edge, flags, tab, Y)) return rc;
+    if (int rc = stream_layout(h, sea, chunks, n_chunks, block_edge, flags, tab, Y, ng_cap))
+        return rc;
     if (int rc = workspace_ok(ws, ws_bytes, Y.total)) return rc;
     if (int rc = ensure_device(h)) return rc;
     if (!tab.empty())
@@ -1703,12 +1727,13 @@ static int stream_setup(sim_handle *h, const sim_sea *sea, const int *chunks, in
 static int stream_forward_common(sim_handle *h, const sim_sea *sea, unsigned long long seed,
                                  const int *chunks, int n_chunks, double block_edge,
                                  const sim_speckle *sp, int p0, int np, float *iq,
-                                 int accumulate, void *ws, size_t ws_bytes, void *stream) {
+                                 int accumulate, void *ws, size_t ws_bytes, void *stream,
+                                 int ng_cap = 1 << 30) {
     if (!iq) HS_FAIL(SIM_EINVAL, "iq is NULL");
     hipStream_t s = (hipStream_t)stream;
     StreamLayout Y;
     if (int rc = stream_setup(h, sea, chunks, n_chunks, block_edge, sp, p0, np, ws, ws_bytes, s,
-                              Y))
+                              Y, ng_cap))
         return rc;
     char *w = (char *)ws;
     const double *tab_d = sea->mode >= 1 ? (const double *)(w + Y.tab) : nullptr;
@@ -1813,11 +1838,27 @@ int sim_stream_forward_noalloc(sim_handle *h, const sim_sea *sea, unsigned long 
     sea_table(sea, tab);
     StreamLayout Y;
     if (int rc = stream_layout(h, sea, chunks, n_chunks, block_edge, 0, tab, Y)) return rc;
-    if (Y.total > SIM_NOALLOC_SCRATCH_BYTES)
-        HS_FAIL(SIM_EINVAL, "the call needs " + std::to_string(Y.total) +
-                                " bytes of scratch, beyond the fixed " +
-                                std::to_string((unsigned long long)SIM_NOALLOC_SCRATCH_BYTES) +
-                                " (use smaller chunks, or sim_stream_forward with a workspace)");
+    // window slots for as many pulse groups as fit (the sum then runs in
+    // passes of that many groups); refused if one group does not fit
+    int ng_cap = 1 << 30;
+    if (Y.total > SIM_NOALLOC_SCRATCH_BYTES) {
+        int lo = 0, hi = 0;
+        for (const PlanGeom &G : Y.geom) hi = std::max(hi, G.ng_max);
+        while (lo < hi) {   // largest cap in [1, hi] that fits; lo = 0: none
+            const int mid = (lo + hi + 1) / 2;
+            stream_relayout(h, chunks, n_chunks, 0, mid, Y.max_n, tab.size(), Y);
+            if (Y.total <= SIM_NOALLOC_SCRATCH_BYTES) lo = mid;
+            else hi = mid - 1;
+        }
+        stream_relayout(h, chunks, n_chunks, 0, std::max(lo, 1), Y.max_n, tab.size(), Y);
+        if (lo == 0 || Y.total > SIM_NOALLOC_SCRATCH_BYTES)
+            HS_FAIL(SIM_EINVAL, "the call needs " + std::to_string(Y.total) +
+                                    " bytes of scratch with one pulse group per pass, beyond "
+                                    "the fixed " +
+                                    std::to_string((unsigned long long)SIM_NOALLOC_SCRATCH_BYTES) +
+                                    " (use smaller chunks, or sim_stream_forward with a workspace)");
+        ng_cap = lo;
+    }
     if (!h->uploaded)
         HS_FAIL(SIM_EINVAL, "sim_stream_forward_noalloc needs sim_device_init first "
                             "(it uploads the handle's tables, which allocates)");
@@ -1826,7 +1867,7 @@ int sim_stream_forward_noalloc(sim_handle *h, const sim_sea *sea, unsigned long 
     void *ptr = scratch_on(d);
     if (!ptr) HS_FAIL(SIM_EINVAL, "no scratch address on this device: call sim_device_init here");
     return stream_forward_common(h, sea, seed, chunks, n_chunks, block_edge, nullptr, p0, np, iq,
-                                 accumulate, ptr, SIM_NOALLOC_SCRATCH_BYTES, stream);
+                                 accumulate, ptr, SIM_NOALLOC_SCRATCH_BYTES, stream, ng_cap);
 }
 
 }  // extern "C"

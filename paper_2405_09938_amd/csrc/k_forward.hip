@@ -129,7 +129,8 @@ __device__ __forceinline__ void forward_unit(const FwdArgs &A, float2 *accw, int
     float2 *acc = accw + wave * kAcc;
     const int poff = SPK ? (A.p0 & 63) : 0;     // lanes before p0 in the first group
     const StripPlan &st = A.st;
-    const int gbase = grp * A.gstride - poff;  // pulse (relative to p0) of lane 0
+    // pulse (relative to p0) of lane 0; grp counts from the pass's first group
+    const int gbase = (A.g0 + grp) * A.gstride - poff;
     int pc = A.p0 + gbase + 32;                 // the group's centre pulse
     pc = pc < 0 ? 0 : (pc < A.Np ? pc : A.Np - 1);
     int band = pc / (64 * st.B);
@@ -432,7 +433,7 @@ __global__ __launch_bounds__(64 * kReduceTile) void k_window_reduce(ReduceArgs A
     const int grp = (int)(blockIdx.x / (unsigned)A.n_tiles), ch = blockIdx.y;
     const unsigned tile_id = blockIdx.x - (unsigned)grp * (unsigned)A.n_tiles;
     const int row = (int)(threadIdx.x & 63);
-    const int gbase = grp * A.gstride - A.poff;
+    const int gbase = (A.g0 + grp) * A.gstride - A.poff;
     const int pl = gbase + row;
     const StripPlan &st = A.st;
     int pc = A.p0 + gbase + 32;

@@ -142,6 +142,7 @@ struct FwdArgs {
     StripPlan st;               // range strips (work units: strip segments)
     float2 *wsum;               // [C][n_groups][seg_max][64][WIN] window of each work unit
     unsigned *counter;          // [kFwdQueues] work-queue counters, zero at launch
+    int g0;                     // first pulse group of this pass (units carry groups from 0)
     const PulseRec *pulses;     // [C][Np]
     float *iq;                  // [C][np][N] complex64 interleaved
     AntArgs ant[SIM_MAX_ANTENNAS];
@@ -173,6 +174,7 @@ struct ReduceArgs {
     int C, N, Np, p0, np;
     int n_groups, gstride, poff, win;
     int n_tiles;                // sample tiles (kReduceTile) per line: the plan's span_tiles
+    int g0;                     // first pulse group of this pass
 };
 
 // Arguments of the adjoint kernel.
@@ -258,9 +260,9 @@ struct sim_plan {
     unsigned *beyond = nullptr;         // device: facets of the last call beyond zlim, vlim
     double zlim = 4.0, vlim = 2.5;      // bounds on |z| and |V| the plan was sized for
     hs::StripPlan st{};          // range strips
-    float2 *wsum = nullptr;      // forward windows, for up to ng_max pulse groups
+    float2 *wsum = nullptr;      // forward windows, for ng_slots pulse groups at a time
     int span_tiles = 0;          // tiles of kReduceTile samples covering any band's windows
-    int ng_max = 0;
+    int ng_slots = 0;
     hs::FacetRec *sorted = nullptr;     // [n + 1] scratch refreshed by each call
     hs::SpkRec *spk = nullptr;          // [n + 1] speckle records (SIM_PLAN_SPECKLE)
     float4 *anch = nullptr;             // [n + 1][ceil(Np/64) + 1] speckle anchors

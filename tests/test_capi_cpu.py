@@ -389,9 +389,10 @@ def test_workspace_sizes(native):
 
 def test_noalloc_entry_point_refuses_before_device_work(native):
     """sim_stream_forward_noalloc: a call needing more than its fixed scratch
-    is refused with the limit in the message, and a handle never initialised
-    on a device is refused too (its set-up would allocate); both before any
-    device work."""
+    even with window slots for one pulse group is refused with the limit in
+    the message, and a handle never initialised on a device is refused too
+    (its set-up would allocate); both before any device work.  A call that
+    fits only with slots for fewer groups is taken."""
     L = native.load()
     g = W.harmony_geometry(8, 64)
     cfg, keep = _config(native, g)
@@ -415,6 +416,26 @@ def test_noalloc_entry_point_refuses_before_device_work(native):
         assert "sim_device_init" in L.sim_last_error().decode()
         assert L.sim_stream_forward_noalloc(None, ctypes.byref(sea), 1, small, 2, 8.0, 0, 8,
                                             ctypes.c_void_p(16), 0, None) == native.SIM_EINVAL
+    finally:
+        L.sim_destroy(h)
+    # a call whose one-pass workspace exceeds the scratch is taken (window
+    # slots for fewer pulse groups, summed in passes): refused here only for
+    # the missing device set-up
+    g = W.harmony_geometry(2048, 1024, receivers="A", n_pc=2)
+    cfg, keep = _config(native, g)
+    h = ctypes.c_void_p()
+    assert L.sim_create(ctypes.byref(cfg), ctypes.byref(h)) == native.SIM_OK
+    try:
+        from paper_2405_09938_amd.sim import Simulator
+        s, skeep = Simulator._sea_struct(W.wave_sea(400, 400, 1.0, seed=23, current_speed=0.3))
+        two = (ctypes.c_int * 8)(0, 0, 400, 200, 0, 200, 400, 200)
+        need = ctypes.c_size_t()
+        assert L.sim_stream_workspace_size(h, ctypes.byref(s), two, 2, 8.0, 0,
+                                           ctypes.byref(need)) == native.SIM_OK
+        assert need.value > 96 * 2 ** 20
+        assert L.sim_stream_forward_noalloc(h, ctypes.byref(s), 1, two, 2, 8.0, 0, 2048,
+                                            ctypes.c_void_p(16), 0, None) == native.SIM_EINVAL
+        assert "sim_device_init" in L.sim_last_error().decode()
     finally:
         L.sim_destroy(h)
 
