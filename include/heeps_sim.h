@@ -325,21 +325,24 @@ int sim_plan_create(sim_handle *h, const float *x, const float *y, long long n,
 
 /*
  * Host outputs (host only, nothing allocated): the range-strip geometry a
- * plan of these arguments would take.  win: LDS window of the forward kernel
- * (samples); n_bands bands of band_groups pulse groups; n_strips: strips per
- * band and channel (a bound); seg_len: blocks per work unit; seg_max: bound
- * on the work units of a band and channel; bands (NULL to skip): host double
- * [n_bands][n_channels][3] = (umin, S, margin): a block whose centre sits at
- * sample position u at the band's reference pulse (64 band_groups b +
- * 32 band_groups, capped at n_pulses - 1) is in strip floor((u - umin) / S),
- * and the forward sum assumes its facets' taps within
+ * plan of these arguments would take.  win: the widest LDS window of the
+ * forward kernel (samples); n_bands bands of band_groups pulse groups;
+ * n_strips: strips per band and channel (a bound); seg_len: blocks per work
+ * unit; seg_max: bound on the work units of a band and channel; bands (NULL
+ * to skip): host double [n_bands][n_channels][3] = (umin, S, margin): a
+ * block whose centre sits at sample position u at the band's reference pulse
+ * (64 band_groups b + 32 band_groups, capped at n_pulses - 1) is in strip
+ * floor((u - umin) / S), and the forward sum assumes its facets' taps within
  * [umin + s S - margin - 3, umin + (s + 1) S + margin + 4] at every pulse of
- * the band (facets within half a block diagonal of the centre, heights up to
- * 4 m, speeds up to 2.5 m/s).  Errors as sim_workspace_size.
+ * the band (facets within half a block diagonal of the centre, heights and
+ * speeds within the box's bounds); band_win (NULL to skip): host int
+ * [n_bands][n_channels], the band's window width W (the window of strip s
+ * covers W samples from floor(umin + s S - margin) - 3; at most win).
+ * Errors as sim_workspace_size.
  */
 int sim_plan_geometry(const sim_handle *h, long long n, const sim_box *box, double block_edge,
                       int *win, int *n_bands, int *band_groups, int *n_strips, int *seg_len,
-                      int *seg_max, double *bands);
+                      int *seg_max, double *bands, int *band_win);
 
 /* Release a plan's host descriptor.  NULL is ignored.  Touches no device
  * memory: the workspace stays the caller's. */

@@ -176,7 +176,7 @@ def load(path: str = LIB_PATH):
                                              ctypes.c_double, i, i, vp, i, vp]
     L.sim_fast_workspace_size.argtypes = [vp, i, P(sz)]
     L.sim_plan_geometry.argtypes = [vp, ll, P(SimBox), ctypes.c_double, P(i), P(i), P(i), P(i),
-                                    P(i), P(i), P(ctypes.c_double)]
+                                    P(i), P(i), P(ctypes.c_double), P(i)]
     L.sim_forward_fast.argtypes = [vp, vp, P(SimFacets), i, ctypes.c_ulonglong, vp, vp, sz, vp]
     for name in EXPORTS:
         if name not in ("sim_destroy", "sim_last_error", "sim_plan_destroy"):

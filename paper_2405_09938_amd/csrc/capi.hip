@@ -637,6 +637,7 @@ struct PlanGeom {
     int win;
     int NB, B, NS, L_seg, seg_max, ng_max;
     int ng_slots;                // pulse groups the window slots hold (<= ng_max)
+    int win_mask;                // window widths the bands use (hs::win_bit)
     std::vector<double> band;    // [NB][C][3]: umin, S, margin
     double el_bound;
     bool el_const;
@@ -770,16 +771,29 @@ static int strip_geometry(const sim_handle *h, PlanGeom &G) {
         G.NB = NG;
         band_stats(h, L, G.B, G.NB, G.zlim, G.vlim, bs);
     }
-    G.band.assign((size_t)3 * G.NB * h->C, 0.0);
+    // per band and channel the narrowest window (at most G.win) leaving
+    // S >= 4: bands near the middle of the dwell, with little drift, take
+    // narrower windows, so more waves share a compute unit
+    G.band.assign((size_t)4 * G.NB * h->C, 0.0);
     G.NS = 1;
+    G.win_mask = 0;
     for (size_t k = 0; k < bs.umin.size(); ++k) {
-        double S = std::max(1.0, G.win - 2.0 * bs.margin[k] - 9.0);
+        int wk = G.win;
+        if (found)
+            for (int w : wins)
+                if (w >= HEEPS_WIN_MIN && w < wk && w - 2.0 * bs.margin[k] - 9.0 >= 4.0) {
+                    wk = w;
+                    break;
+                }
+        double S = std::max(1.0, wk - 2.0 * bs.margin[k] - 9.0);
         // at most kStripMax strips: wider ones (facets may then leave the
         // window and take the global path)
         S = std::max(S, (bs.umax[k] - bs.umin[k]) / 8000.0);
-        G.band[3 * k] = bs.umin[k];
-        G.band[3 * k + 1] = S;
-        G.band[3 * k + 2] = bs.margin[k];
+        G.band[4 * k] = bs.umin[k];
+        G.band[4 * k + 1] = S;
+        G.band[4 * k + 2] = bs.margin[k];
+        G.band[4 * k + 3] = (double)wk;
+        G.win_mask |= hs::win_bit(wk);
         G.NS = std::max(G.NS, (int)std::floor((bs.umax[k] - bs.umin[k]) / S) + 1);
     }
     // segments: enough work units to fill the GPU, long enough to amortise
@@ -787,8 +801,8 @@ static int strip_geometry(const sim_handle *h, PlanGeom &G) {
     const long long per_band = std::max(1LL, (long long)HEEPS_TARGET_UNITS / ((long long)NG * h->C));
     long long Ls = std::min((long long)HEEPS_SEG_MAX_BLOCKS,
                             std::max(16LL, (G.nb_max / 2 + per_band - 1) / per_band));
-    const int K = hs::fwd_waves(G.win);
-    G.L_seg = (int)((Ls + K - 1) / K * K);
+    // a multiple of every window's wave count (4 or 1)
+    G.L_seg = (int)((Ls + 3) / 4 * 4);
     G.seg_max = G.NS + (int)((G.nb_max + G.L_seg - 1) / G.L_seg);
     return SIM_OK;
 }
@@ -855,7 +869,7 @@ static PlanLayout plan_layout(const PlanGeom &G, long long n, int flags, int Np)
     Y.blk_offset = take(sizeof(int) * (nk + 1));
     Y.scan_tmp = take(sizeof(int) * (size_t)hs::scan_tmp_len(G.n_keys));
     Y.misc = take(256);
-    const size_t bcn = G.band.size() / 3;   // bands x channels
+    const size_t bcn = G.band.size() / 4;   // bands x channels
     const size_t nbm = (size_t)std::max(1LL, G.nb_max);
     Y.band = take(sizeof(double) * G.band.size());
     Y.ids = take(sizeof(int) * bcn * nbm);
@@ -926,14 +940,15 @@ static int plan_build(const sim_handle *h, const float *x, const float *y, long 
     st.seg_max = G.seg_max;
     P.wsum = (float2 *)(ws + Y.wsum);
     P.ng_slots = G.ng_slots;
+    P.win_mask = G.win_mask;
     // sample span of any band's windows, in tiles of the window reduction
     {
         long long span = 1;
-        for (size_t k = 0; k + 2 < G.band.size(); k += 3) {
+        for (size_t k = 0; k + 3 < G.band.size(); k += 4) {
             const double umin = G.band[k], S = G.band[k + 1], mg = G.band[k + 2];
             const long long lo0 = (long long)std::floor(umin - mg);
             const long long lo1 = (long long)std::floor(umin + (double)(G.NS - 1) * S - mg);
-            span = std::max(span, lo1 - lo0 + G.win);
+            span = std::max(span, lo1 - lo0 + (long long)G.band[k + 3]);
         }
         P.span_tiles = (int)((span + hs::kReduceTile - 1) / hs::kReduceTile);
     }
@@ -980,7 +995,7 @@ int sim_workspace_size(const sim_handle *h, long long n, const sim_box *box, dou
 
 int sim_plan_geometry(const sim_handle *h, long long n, const sim_box *box, double block_edge,
                       int *win, int *n_bands, int *band_groups, int *n_strips, int *seg_len,
-                      int *seg_max, double *bands) {
+                      int *seg_max, double *bands, int *band_win) {
     if (!h) HS_FAIL(SIM_EINVAL, "handle is NULL");
     PlanGeom G;
     if (int rc = plan_geometry(h, n, box, block_edge, G)) return rc;
@@ -990,7 +1005,11 @@ int sim_plan_geometry(const sim_handle *h, long long n, const sim_box *box, doub
     if (n_strips) *n_strips = G.NS;
     if (seg_len) *seg_len = G.L_seg;
     if (seg_max) *seg_max = G.seg_max;
-    if (bands) std::memcpy(bands, G.band.data(), sizeof(double) * G.band.size());
+    for (size_t k = 0; k + 3 < G.band.size(); k += 4) {
+        if (bands)
+            for (int j = 0; j < 3; ++j) bands[3 * (k / 4) + j] = G.band[k + j];
+        if (band_win) band_win[k / 4] = (int)G.band[k + 3];
+    }
     return SIM_OK;
 }
 
@@ -1385,13 +1404,19 @@ static int forward_launch(const sim_handle *h, const sim_plan *P, const sim_face
     // the pulse groups in passes of as many as the window slots hold (one
     // pass unless the plan was laid out for fewer groups), each summed and
     // reduced before the next reuses the slots
+    a.slot_w = P->win;
     for (int g0 = 0; g0 < n_groups; g0 += P->ng_slots) {
         const int ng = std::min(P->ng_slots, n_groups - g0);
         a.g0 = r.g0 = g0;
         a.n_groups = r.n_groups = ng;
-        HS_HIP(hs::launch_fill_zero((float *)P->counter, hs::kFwdQueues, s), "work queues");
-        HS_HIP(hs::launch_forward(a, h->C, P->win, P->el_const && !h->grid, sp != nullptr, s),
-               "forward");
+        // one launch per window width the bands use (each takes the units
+        // of its own bands)
+        for (int w : {24, 32, 48, 64}) {
+            if (!(P->win_mask & hs::win_bit(w))) continue;
+            HS_HIP(hs::launch_fill_zero((float *)P->counter, hs::kFwdQueues, s), "work queues");
+            HS_HIP(hs::launch_forward(a, h->C, w, P->el_const && !h->grid, sp != nullptr, s),
+                   "forward");
+        }
         HS_HIP(hs::launch_window_reduce(r, s), "window reduce");
     }
     return SIM_OK;

@@ -136,6 +136,8 @@ __device__ __forceinline__ void forward_unit(const FwdArgs &A, float2 *accw, int
     int band = pc / (64 * st.B);
     band = band < st.NB ? band : st.NB - 1;
     const size_t bc = (size_t)band * A.C + ch;
+    const cptr<double> bd = (cptr<double>)(st.band + 4 * bc);
+    if ((int)bd[3] != WIN) return;   // the band's units run in the launch of its width
     const cptr<int> segoff = (cptr<int>)(st.segoff + bc * (st.NS + 1));
     if (seg >= segoff[st.NS]) return;
     // the segment's strip: the last s with segoff[s] <= seg
@@ -163,7 +165,6 @@ __device__ __forceinline__ void forward_unit(const FwdArgs &A, float2 *accw, int
 
     // Range window of the strip: its band of samples at the reference
     // pulse, widened by the margin and the taps.
-    const cptr<double> bd = (cptr<double>)(st.band + 3 * bc);
     const int lo = (int)floor(bd[0] + (double)strip * bd[1] - bd[2]) - 3;
     float2 *col = acc + lane;
     for (int i = 0; i < WIN; ++i) col[64 * i] = make_float2(0.f, 0.f);
@@ -356,7 +357,7 @@ __device__ __forceinline__ void forward_unit(const FwdArgs &A, float2 *accw, int
     // the LDS windows ([sample][pulse row]), plain coalesced stores: the
     // waves' windows added in wave order
     const size_t wslot = ((size_t)ch * A.n_groups + grp) * (size_t)st.seg_max + seg;
-    float2 *dst = A.wsum + wslot * 64 * WIN;
+    float2 *dst = A.wsum + wslot * 64 * (size_t)A.slot_w;
     __syncthreads();
     for (int e = (int)threadIdx.x; e < 64 * WIN; e += 64 * K) {
         float2 t = accw[e];
@@ -443,11 +444,11 @@ __global__ __launch_bounds__(64 * kReduceTile) void k_window_reduce(ReduceArgs A
     const size_t bc = (size_t)band * A.C + ch;
     const int *segoff = st.segoff + bc * (st.NS + 1);
     if (segoff[st.NS] == 0) return;
-    const double *bd = st.band + 3 * bc;
+    const double *bd = st.band + 4 * bc;
     const double umin = bd[0], S = bd[1], mg = bd[2];
     // first sample of strip s's window (the forward kernel's expression)
     const auto lo_of = [&](int s) { return (int)floor(umin + (double)s * S - mg) - 3; };
-    const int W = A.win;
+    const int W = (int)bd[3];   // the band's window width (slots are A.win wide)
     const int n = lo_of(0) + (int)tile_id * kReduceTile +
                   __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (n < 0 || n >= A.N) return;
@@ -459,7 +460,7 @@ __global__ __launch_bounds__(64 * kReduceTile) void k_window_reduce(ReduceArgs A
     int s0 = s1 + 1;
     while (s0 > 0 && lo_of(s0 - 1) + W > n) --s0;
     const size_t slot0 = ((size_t)ch * A.n_groups + grp) * (size_t)st.seg_max;
-    const size_t seg_stride = (size_t)64 * W;
+    const size_t seg_stride = (size_t)64 * A.win;
     float2 acc = make_float2(0.f, 0.f);
     bool any = false;
     for (int s = s0; s <= s1; ++s) {

@@ -269,7 +269,7 @@ __global__ void k_strip_keys(StripPlan sp, const PulseRec *pulses, const BlockRe
     const double c0 = x - Q.prx[0], c1 = y - Q.prx[1], c2 = -Q.prx[2];
     const double u = n_ref + (sqrt(a0 * a0 + a1 * a1 + a2 * a2) +
                               sqrt(c0 * c0 + c1 * c1 + c2 * c2) - Q.rref) * fs_c;
-    const double *bd = sp.band + 3 * (size_t)bc;
+    const double *bd = sp.band + 4 * (size_t)bc;
     double f = floor((u - bd[0]) / bd[1]);
     f = f < 0.0 ? 0.0 : (f > (double)(sp.NS - 1) ? (double)(sp.NS - 1) : f);
     const int key = (int)f;

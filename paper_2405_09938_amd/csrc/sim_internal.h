@@ -65,8 +65,11 @@ struct Lattice {
 // the band (margin: the centre's migration over the band, the facets'
 // offsets from it, heights and drift).  Each strip's blocks are listed in
 // block order and cut into segments of at most L blocks.
+// Bit of a window width in a plan's mask of the widths its bands use.
+constexpr int win_bit(int W) { return W <= 24 ? 1 : (W <= 32 ? 2 : (W <= 48 ? 4 : 8)); }
+
 struct StripPlan {
-    const double *band;         // [NB][C][3]: umin, S, margin (samples)
+    const double *band;         // [NB][C][4]: umin, S, margin (samples), window width W
     int *ids;                   // [NB][C][nbm]: block ids, strip after strip
     int *soff;                  // [NB][C][NS + 1]: first list position per strip; [NS] total
     int *segoff;                // [NB][C][NS + 1]: first segment per strip; [NS] total
@@ -143,6 +146,7 @@ struct FwdArgs {
     float2 *wsum;               // [C][n_groups][seg_max][64][WIN] window of each work unit
     unsigned *counter;          // [kFwdQueues] work-queue counters, zero at launch
     int g0;                     // first pulse group of this pass (units carry groups from 0)
+    int slot_w;                 // window samples per slot (the plan's widest window)
     const PulseRec *pulses;     // [C][Np]
     float *iq;                  // [C][np][N] complex64 interleaved
     AntArgs ant[SIM_MAX_ANTENNAS];
@@ -172,7 +176,7 @@ struct ReduceArgs {
     const float2 *wsum;
     float2 *iq;                 // [C][np][N]
     int C, N, Np, p0, np;
-    int n_groups, gstride, poff, win;
+    int n_groups, gstride, poff, win;   // win: window samples per slot
     int n_tiles;                // sample tiles (kReduceTile) per line: the plan's span_tiles
     int g0;                     // first pulse group of this pass
 };
@@ -247,7 +251,8 @@ struct sim_plan {
     long long nb_max;            // bound on the block count (size of `blocks`)
     int flags;                   // SIM_PLAN_* flags the workspace was laid out for
     hs::Lattice lat;
-    int win;                     // LDS range-window width of the forward kernel
+    int win;                     // widest LDS range window of the bands (the slot width)
+    int win_mask = 0;            // window widths the bands use (win_bit)
     bool el_const = false;       // elevation factors taken at block centres
     double el_bound = 0.0;       // bound on the relative error of doing so
     hipStream_t stream = nullptr;   // stream the plan was built on

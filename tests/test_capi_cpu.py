@@ -464,14 +464,20 @@ def test_strip_windows_hold_every_tap(native, k):
         n = sub[2] * sub[3]
         v = [ctypes.c_int() for _ in range(6)]
         assert L.sim_plan_geometry(h, n, ctypes.byref(bx), wl.block_edge,
-                                   *[ctypes.byref(x) for x in v], None) == native.SIM_OK
-        win, nb, bg, ns, _, _ = [x.value for x in v]
+                                   *[ctypes.byref(x) for x in v], None, None) == native.SIM_OK
+        win_max, nb, bg, ns, _, _ = [x.value for x in v]
         C = g.n_channels
         bands = np.zeros(nb * C * 3)
+        bwin = np.zeros(nb * C, np.int32)
         assert L.sim_plan_geometry(h, n, ctypes.byref(bx), wl.block_edge, None, None, None, None,
                                    None, None,
-                                   bands.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == 0
+                                   bands.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   bwin.ctypes.data_as(ctypes.POINTER(ctypes.c_int))) == 0
         bands = bands.reshape(nb, C, 3)
+        bwin = bwin.reshape(nb, C)
+        assert bwin.max() == win_max and set(np.unique(bwin)) <= {24, 32, 48, 64}
+        # each band's window is the narrowest leaving strips of at least 4 samples
+        assert np.all(bands[..., 1] >= 4.0 - 1e-9)
         fs_c = g.fs / g.c
         n_ref = g.n_ref if g.n_ref >= 0 else g.n_samples // 2
         rng = np.random.default_rng(k)
@@ -499,12 +505,14 @@ def test_strip_windows_hold_every_tap(native, k):
             t_p = O.pulse_geometry(g, ch, p)[0]
             uf, _ = u_at(p, np.array([x, y, z]) + vel * t_p)
             umin, S, margin = bands[b, ch]
+            win = int(bwin[b, ch])
             strip = min(max(int(math.floor((uc - umin) / S)), 0), ns - 1)
             lo = math.floor(umin + strip * S - margin) - 3
             first, last = math.floor(uf) - 3, math.floor(uf) + 4
             assert first >= lo and last <= lo + win - 1, (b, ch, p, first, last, lo, win)
             worst = max(worst, lo - first, last - (lo + win - 1))
-        print(f"workload {k}: window {win}, tightest tap {-worst} samples inside")
+        print(f"workload {k}: windows {sorted(set(bwin.ravel().tolist()))}, "
+              f"tightest tap {-worst} samples inside")
     finally:
         L.sim_destroy(h)
 
@@ -555,7 +563,8 @@ def test_chunk_box_height_and_speed_bounds(native):
             bx = native.SimBox(-500.0, 500.0, -500.0, 500.0, *zv)
             v = [ctypes.c_int() for _ in range(6)]
             assert L.sim_plan_geometry(h, 100000, ctypes.byref(bx), 8.0,
-                                       *[ctypes.byref(x) for x in v], None) == native.SIM_OK
+                                       *[ctypes.byref(x) for x in v], None,
+                                       None) == native.SIM_OK
             return v[3].value
         assert strips((0.5, 0.2)) < strips((0.0, 0.0)) < strips((8.0, 6.0))
     finally:
