@@ -23,6 +23,11 @@
 #ifndef HEEPS_TARGET_UNITS
 #define HEEPS_TARGET_UNITS 16384
 #endif
+// narrowest strips (samples) a band may take to use a narrower window than
+// the plan's widest
+#ifndef HEEPS_NARROW_S_MIN
+#define HEEPS_NARROW_S_MIN 2.0
+#endif
 // longest segment (blocks): bounds the facet records a work unit streams
 #ifndef HEEPS_SEG_MAX_BLOCKS
 #define HEEPS_SEG_MAX_BLOCKS 4096
@@ -772,8 +777,9 @@ static int strip_geometry(const sim_handle *h, PlanGeom &G) {
         band_stats(h, L, G.B, G.NB, G.zlim, G.vlim, bs);
     }
     // per band and channel the narrowest window (at most G.win) leaving
-    // S >= 4: bands near the middle of the dwell, with little drift, take
-    // narrower windows, so more waves share a compute unit
+    // strips of HEEPS_NARROW_S_MIN samples: bands near the middle of the
+    // dwell, with little drift, take narrower windows, so more waves share a
+    // compute unit (narrower strips cost more work units and window slots)
     G.band.assign((size_t)4 * G.NB * h->C, 0.0);
     G.NS = 1;
     G.win_mask = 0;
@@ -781,7 +787,8 @@ static int strip_geometry(const sim_handle *h, PlanGeom &G) {
         int wk = G.win;
         if (found)
             for (int w : wins)
-                if (w >= HEEPS_WIN_MIN && w < wk && w - 2.0 * bs.margin[k] - 9.0 >= 4.0) {
+                if (w >= HEEPS_WIN_MIN && w < wk &&
+                    w - 2.0 * bs.margin[k] - 9.0 >= HEEPS_NARROW_S_MIN) {
                     wk = w;
                     break;
                 }

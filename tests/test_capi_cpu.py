@@ -476,8 +476,9 @@ def test_strip_windows_hold_every_tap(native, k):
         bands = bands.reshape(nb, C, 3)
         bwin = bwin.reshape(nb, C)
         assert bwin.max() == win_max and set(np.unique(bwin)) <= {24, 32, 48, 64}
-        # each band's window is the narrowest leaving strips of at least 4 samples
-        assert np.all(bands[..., 1] >= 4.0 - 1e-9)
+        # narrower windows than the widest only for strips of at least 2 samples
+        assert np.all(bands[..., 1][bwin < win_max] >= 2.0 - 1e-9)
+        assert np.all(bands[..., 1] >= 1.0 - 1e-9)
         fs_c = g.fs / g.c
         n_ref = g.n_ref if g.n_ref >= 0 else g.n_samples // 2
         rng = np.random.default_rng(k)
