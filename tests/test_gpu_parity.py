@@ -334,3 +334,47 @@ def test_facets_beyond_the_plan_bounds(torch_cuda, hs):
     plan2 = sim.plan(d["x"], d["y"], 8.0, box=box[:4])
     sim.forward(plan2, d)
     assert plan2.n_beyond() == count(4.0, 2.5)
+
+
+def test_every_window_width_in_one_plan(torch_cuda, hs):
+    """A plan whose bands take all four window widths (workload 5's 9.6 s
+    dwell with plan bounds of 4 m and 10 m/s: 24 samples mid-dwell up to 64
+    at the ends), so the forward runs four launches, with four-wave and
+    one-wave workgroups: rows at the dwell's ends, middle and in between
+    against the oracle, and the same bits on a second launch."""
+    import ctypes
+    from paper_2405_09938_amd import _native as N
+    torch = torch_cuda
+    g = W.workload(5).geometry
+    box = (-8000.0, -4000.0, -4000.0, -2000.0, 4.0, 10.0)
+    sim = hs.Simulator(g)
+    bx = N.SimBox(*box)
+    v = [ctypes.c_int() for _ in range(6)]
+    assert sim.lib.sim_plan_geometry(sim.handle, 2000, ctypes.byref(bx), 8.0,
+                                     *[ctypes.byref(x) for x in v], None, None) == 0
+    nb, C = v[1].value, g.n_channels
+    bw = np.zeros(nb * C, np.int32)
+    assert sim.lib.sim_plan_geometry(sim.handle, 2000, ctypes.byref(bx), 8.0, None, None, None,
+                                     None, None, None, None,
+                                     bw.ctypes.data_as(ctypes.POINTER(ctypes.c_int))) == 0
+    assert set(np.unique(bw)) == {24, 32, 48, 64}
+    rng = np.random.default_rng(71)
+    n = 2000
+    # the widths follow the box's bounds; the facets stay within the FP32
+    # offset budget of the precision scheme (drift under 5 m over the dwell)
+    f = dict(x=rng.uniform(-6000, -5000, n), y=rng.uniform(-3500, -2500, n),
+             z=rng.uniform(-1.0, 1.0, n), vx=rng.uniform(-0.5, 0.5, n),
+             vy=rng.uniform(-0.5, 0.5, n), vz=rng.uniform(-0.3, 0.3, n),
+             a_re=rng.normal(0, 0.7, n), a_im=rng.normal(0, 0.7, n))
+    f = {k: v.astype(np.float32) for k, v in f.items()}
+    d = to_dev(torch, f)
+    plan = sim.plan(d["x"], d["y"], 8.0, box=box)
+    for p0 in (0, 3000, 8190, 13000, 16381):
+        say(f"case: window widths 24..64 in one plan, pulses [{p0}, {p0 + 3})")
+        a = sim.forward(plan, d, p0, 3).cpu().numpy()
+        b = sim.forward(plan, d, p0, 3).cpu().numpy()
+        assert np.array_equal(a, b)
+        e = O.rel_l2(a.astype(np.complex128), O.forward(g, f64(f), p0, 3))
+        say(f"rows [{p0}, {p0 + 3}): rel-L2 {e:.3e}")
+        assert e < IQ_TOL
+    assert plan.n_beyond() == 0
