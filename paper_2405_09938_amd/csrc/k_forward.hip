@@ -8,10 +8,13 @@
 // Work decomposition: a work unit is (segment of a range strip, pulse group
 // of 64, channel).  A strip holds the blocks whose centres fall in a band of
 // S range samples at the reference pulse of the group's band (the plan's
-// range-binned sort), so one LDS range window covers that band plus a margin
-// and every facet of the strip lands in it.  A workgroup of K waves takes
-// one unit at a time from a work queue (below); wave k sums blocks k, k + K,
-// ... of the segment into its own window.
+// range-binned sort), so one LDS range window of the band's width W covers
+// that band plus a margin and every facet of the strip lands in it.  One
+// launch per window width the bands use; a workgroup of K waves takes one
+// unit of its width at a time from a work queue (below); wave k sums blocks
+// k, k + K, ... of the segment into its own window, facets in pairs (one
+// read-modify-write for two facets whose taps start at the same sample on
+// every lane).
 //   Lane = pulse: every lane handles the same facet
 //   (its 32-byte record arrives by two uniform buffer loads) and deposits into
 //   its own pulse column of the wave's LDS range window.  Since no other lane
@@ -23,11 +26,11 @@
 //   a lane-major layout conflicts as soon as the lanes' sample indices
 //   differ.  At the end the K windows are added in wave order and the sum
 //   goes to the unit's own slot of a scratch array with plain stores;
-//   k_window_reduce then adds, line by line, the windows of all segments in
-//   segment order, so the result does not depend on the order in which
-//   workgroups run and no global atomics are needed.  A contribution whose
-//   taps leave the window (only for facets beyond the plan's height and speed
-//   assumptions) goes straight to global memory.
+//   k_window_reduce then adds, for every sample, the slots of the strips
+//   holding it in strip and segment order, so the result does not depend on
+//   the order in which workgroups run and no global atomics are needed.  A
+//   contribution whose taps leave the window (only for facets beyond the
+//   plan's height and speed bounds) goes straight to global memory.
 #include "sim_device.h"
 #include "spk_device.h"
 
