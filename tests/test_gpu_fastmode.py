@@ -123,3 +123,32 @@ def test_fast_mode_workload2_sampled_gates(env):
     say(f"workload 2: window rows vs full-rate {e_win:.3e}; synthesized rows of 12 gates "
         f"vs the oracle's synthesis {e_syn:.3e}")
     assert e_syn < 1e-5
+
+
+@pytest.mark.parametrize("option", ["steering", "patterns", "rx_exact"])
+def test_fast_mode_with_handle_options(env, option):
+    """The fast mode on handles with the forward's other options (the window
+    sums take the same kernel variants as the full-rate sum): a Tx beam
+    steered at 3 deg/s, u-v gridded patterns, the receiver at each facet's
+    echo time; against the oracle's fast mode on the same geometry."""
+    from dataclasses import replace
+    torch, hs = env
+    say(f"case: fast mode n_fast 256 with {option}")
+    g = W.harmony_geometry(900, 128, receivers="A", n_pc=1)
+    if option == "steering":
+        g = W.tops_geometry(g, 3.0)
+    elif option == "patterns":
+        g = W.gridded_geometry(g, seed=4)
+    else:
+        g = replace(g, rx_exact=True)
+    f = W.scattered_facets(2000, 150.0, seed=44, sigma_v=0.5, sigma_z=0.4)
+    sim = hs.Simulator(g)
+    d = dev(torch, f)
+    plan = sim.plan(d["x"], d["y"], 8.0)
+    got = sim.forward_fast(plan, d, 256, seed=77).cpu().numpy()
+    ref = FM.fast_forward(g, f64(f), 256, seed=77)
+    rows = window_rows(900, 256)
+    e_win = O.rel_l2(got[:, rows], ref[:, rows])
+    e_syn = O.rel_l2(got[:, ~rows], ref[:, ~rows])
+    say(f"{option}: window rows {e_win:.3e}, synthesized rows {e_syn:.3e}")
+    assert e_win < IQ_TOL and e_syn < IQ_TOL
