@@ -315,29 +315,26 @@ __device__ __forceinline__ void forward_unit(const FwdArgs &A, float2 *accw, int
                 p[64 * k] = make_float2(fmaf(b.wr, tb[k], fmaf(a.wr, ta[k], old[k].x)),
                                         fmaf(b.wi, tb[k], fmaf(a.wi, ta[k], old[k].y)));
         };
-        // Facets in pairs; each record's load is issued as soon as the one
-        // before it in its register set is used (about one facet ahead).
-        FacetV fa = load_facet(rs, 0), fb = load_facet(rs, 1);
-        [[maybe_unused]] SpkFacet sa{}, sb{};
-        if constexpr (SPK) {
-            sa = load_spk(rs_rec, rs_anc, 0, ng1, gabs);
-            sb = load_spk(rs_rec, rs_anc, 1, ng1, gabs);
-        }
+        // Facets in pairs (each pair's taps made and deposited together
+        // where they share a window index).  Each record's load is issued as
+        // soon as the one before it in its register set is used: with two
+        // sets about one facet ahead; with four (kDeep: the wide windows,
+        // whose LDS already holds a SIMD to two waves, so registers are
+        // there to spare) three facets ahead.
         // (Merging keeps both facets' results live across the second one's
         // geometry: the variants that would lose a wave per SIMD to it, per
         // facet elevation factors without speckle or steering, deposit each
         // facet as soon as it is made.)
         constexpr bool kMerge = ELC || SPK || STR;
-        int j = 0;
-        for (; j + 1 < blk.count; j += 2) {
+        const auto pair_step = [&](FacetV &x, SpkFacet &sx, FacetV &y, SpkFacet &sy, int nx) {
             Dep da, db;
-            prep(fa, sa, da);
-            fa = load_facet(rs, j + 2);
-            if constexpr (SPK) sa = load_spk(rs_rec, rs_anc, j + 2, ng1, gabs);
+            prep(x, sx, da);
+            x = load_facet(rs, nx);
+            if constexpr (SPK) sx = load_spk(rs_rec, rs_anc, nx, ng1, gabs);
             if constexpr (!kMerge) deposit(da);
-            prep(fb, sb, db);
-            fb = load_facet(rs, j + 3);
-            if constexpr (SPK) sb = load_spk(rs_rec, rs_anc, j + 3, ng1, gabs);
+            prep(y, sy, db);
+            y = load_facet(rs, nx + 1);
+            if constexpr (SPK) sy = load_spk(rs_rec, rs_anc, nx + 1, ng1, gabs);
             if constexpr (kMerge) {
                 if (__all(inside(da) && da.n0 == db.n0)) {
                     deposit2(da, db);
@@ -348,6 +345,34 @@ __device__ __forceinline__ void forward_unit(const FwdArgs &A, float2 *accw, int
             } else {
                 deposit(db);
             }
+        };
+        constexpr bool kDeep = WIN >= 32;
+        FacetV fa = load_facet(rs, 0), fb = load_facet(rs, 1);
+        [[maybe_unused]] SpkFacet sa{}, sb{}, sc{}, sd{};
+        if constexpr (SPK) {
+            sa = load_spk(rs_rec, rs_anc, 0, ng1, gabs);
+            sb = load_spk(rs_rec, rs_anc, 1, ng1, gabs);
+        }
+        int j = 0;
+        if constexpr (kDeep) {
+            FacetV fc = load_facet(rs, 2), fd = load_facet(rs, 3);
+            if constexpr (SPK) {
+                sc = load_spk(rs_rec, rs_anc, 2, ng1, gabs);
+                sd = load_spk(rs_rec, rs_anc, 3, ng1, gabs);
+            }
+            for (; j + 3 < blk.count; j += 4) {
+                pair_step(fa, sa, fb, sb, j + 4);
+                pair_step(fc, sc, fd, sd, j + 6);
+            }
+            // one to three facets left: j, j + 1 in (fa, fb), j + 2 in fc
+            if (j + 1 < blk.count) {
+                pair_step(fa, sa, fb, sb, j + 4);
+                j += 2;
+                fa = fc;
+                sa = sc;
+            }
+        } else {
+            for (; j + 1 < blk.count; j += 2) pair_step(fa, sa, fb, sb, j + 2);
         }
         if (j < blk.count) {
             Dep d;
