@@ -74,16 +74,18 @@ MUL64_SLOTS = 2.0
 W_SPK_SLOTS = 10 * (MUL64_SLOTS + 2) + 6 + (4 * 4.0 + 3) + 4 + 4 + 6
 # Adjoint sum, per contribution (elevation factors at block centres): the
 # facet geometry of the forward (44 FP32 operations, 5 transcendentals: the
-# forward listing without taps, weight and deposit), the 8 taps with their
-# derivatives (76: per tap pair 5 + 5 Horner steps for the even and odd parts
-# and their y-derivatives, 8 for the pair and its derivative pair; 4 shared),
-# the two tap sums over the staged g (8 taps x 4 FMAs = 32), a E and B a E
-# (8), the delay and phase terms (6), the range gradient (14), the three
-# components of dL/dX (7), the accumulation into dL/dz and dL/dV (4) and
-# dL/da (6): 197 FP32 operations and 5 transcendentals.  Staged reference
-# and g reads from LDS, loop control and the per-block FP64 stage prologue
-# are overhead, not counted.
-W_ADJ_SLOTS_EL_CONST = 197.0 + 5 * 4.0
+# forward listing without taps, weight and deposit), the two tap sums B and
+# dB/du from the per-(pulse, first-tap sample) coefficient table (32: the
+# fraction and its square, Horner's rule with the derivative for the even
+# and odd cubics in y, 5 per real polynomial, and their combination), the
+# table itself shared by a block's facets (8 entries per pulse, each 16
+# sums and 64 FMAs: 10 per contribution at 64 facets per block), a E and
+# B a E (8), the delay and phase terms (6), the range gradient (14), the
+# three components of dL/dX (7), the accumulation into dL/dz and dL/dV (4)
+# and dL/da (6): 131 FP32 operations and 5 transcendentals.  Staged
+# reference reads, the loads of g, loop control and the per-block FP64
+# stage prologue are overhead, not counted.
+W_ADJ_SLOTS_EL_CONST = 131.0 + 5 * 4.0
 # with every pattern factor per facet: two more direction cosines (8), their
 # two sines and four more products of the pattern (4)
 W_ADJ_SLOTS = W_ADJ_SLOTS_EL_CONST + 12.0 + 2 * 4.0

@@ -20,9 +20,14 @@
 // Work decomposition: one wave per spatial block, lane = facet (<= 64 per
 // block).  The wave loops over channels and over stages of 32 pulses; per
 // stage, lanes 0..31 compute the FP64 block references of one pulse each into
-// LDS, then the wave stages a 16-sample window of g around the block centre's
-// sample for each of those pulses, and finally every lane walks the 32 pulses
-// reading references and window rows as LDS broadcasts.  Each facet's
+// LDS.  Then, per sub-stage of 8 pulses, the wave builds a table of the two
+// tap sums' coefficients as polynomials in the facet's tap fraction, one
+// entry per (pulse, first-tap sample) for the 8 first-tap samples around the
+// block centre's (lane = entry, from the samples of g under its 8 taps), and
+// every lane walks the 8 pulses reading references as LDS broadcasts and its
+// own entry: the tap sums B and dB/du cost two short polynomials per facet
+// and pulse instead of 8 taps, their derivatives and 32 products.  A facet
+// whose taps start outside the table reads g from memory.  Each facet's
 // gradient accumulates in registers over all pulses and channels and is
 // written once: no atomics, deterministic.
 #include "sim_device.h"
@@ -33,7 +38,8 @@ namespace hs {
 namespace {
 
 constexpr int kStage = 32;   // pulses per stage
-constexpr int kGW = 16;      // staged samples per pulse: centre - 7 .. centre + 8
+constexpr int kSub = 8;      // pulses per coefficient table (a stage holds four)
+constexpr int kNI = 8;       // table intervals per pulse: first tap at window index 0 .. 7
 
 // staged record layout (floats)
 enum {
@@ -145,7 +151,9 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
     constexpr int kNR = kNRef<SPK, STR>;
     constexpr int kSt = R_ST0<SPK>;
     __shared__ float4 refs[kStage * kNR / 4];
-    __shared__ float2 gwin[kStage * kGW];
+    // per (pulse of the sub-stage, interval): the coefficients of the tap
+    // sum as polynomials in y = s^2, four float4 (see the table build)
+    __shared__ float4 ctab[kSub * kNI * 4];
 
     // Workgroups go to the 8 XCDs round-robin by linear index; XCD x takes
     // the contiguous x-th eighth of the (cell-ordered) blocks, so blocks
@@ -165,8 +173,6 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
 
     float gz_acc = 0.f, gvx = 0.f, gvy = 0.f, gvz = 0.f, gar = 0.f, gai = 0.f;
     float *rf = reinterpret_cast<float *>(refs);
-    TapV tv;
-    tap_all(A.tp, tv);
 
     // speckle: the lane's facet id and Doppler, its anchors, the draw scale
     const SpkArgs &S = A.spk;
@@ -287,24 +293,60 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                 o[R_GRAZE] = __int_as_float(r.graze);
             }
             __syncthreads();
-            // stage g: row = lane / 2 holds samples nb - 7 .. nb + 8 of its pulse
-            {
-                const int row = lane >> 1, half = lane & 1;
-                const int pl = ps + row;
-                const int nb = __float_as_int(rf[row * kNR + R_NB]);
-                const int base = nb - 7 + half * 8;
+            // The samples of g under lane (pulse qs + lane / 8, interval
+            // w = lane % 8) of a sub-stage's table: nb - 7 + w .. nb + w of
+            // that pulse, zero outside the line and past the call's pulses.
+            // Loaded one sub-stage ahead (the first at the stage's start).
+            const int nq = (A.np - ps) < kStage ? (A.np - ps) : kStage;
+            const int w = lane & (kNI - 1);
+            float2 gv[8];
+            const auto load_g = [&](int qsub) {
+                const int qq = qsub + (lane >> 3), pl = ps + qq;
+                const int base = __float_as_int(rf[qq * kNR + R_NB]) - 7 + w;
                 const float *gl = gline + 2 * (size_t)(pl < A.np ? pl : 0) * A.N;
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     const int n = base + k;
-                    float2 v = make_float2(0.f, 0.f);
-                    if (pl < A.np && n >= 0 && n < A.N) v = make_float2(gl[2 * n], gl[2 * n + 1]);
-                    gwin[row * kGW + half * 8 + k] = v;
+                    gv[k] = (pl < A.np && n >= 0 && n < A.N)
+                                ? make_float2(gl[2 * n], gl[2 * n + 1])
+                                : make_float2(0.f, 0.f);
                 }
+            };
+            load_g(0);
+            for (int qs = 0; qs < nq; qs += kSub) {
+            // Coefficient table of the sub-stage's 8 pulses, lane = (pulse,
+            // interval w): with G+_j = g[w + 4 + j] + g[w + 3 - j] and
+            // G-_j = g[w + 4 + j] - g[w + 3 - j] (the samples under taps
+            // j + 4 and 3 - j), the tap sum over the taps' even and odd parts
+            // is sum_j G+_j E_j(y) + s sum_j G-_j O_j(y), so its coefficients
+            // in y are C_E[m] = sum_j G+_j e_j[m] and C_O[m] =
+            // sum_j G-_j o_j[m].
+            {
+                float er[4] = {0.f, 0.f, 0.f, 0.f}, ei[4] = {0.f, 0.f, 0.f, 0.f};
+                float orr[4] = {0.f, 0.f, 0.f, 0.f}, oi[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float2 a = gv[4 + j], b = gv[3 - j];
+                    const float pr = a.x + b.x, pim = a.y + b.y;
+                    const float mr = a.x - b.x, mim = a.y - b.y;
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        er[m] = fmaf(pr, A.tp.e[j][m], er[m]);
+                        ei[m] = fmaf(pim, A.tp.e[j][m], ei[m]);
+                        orr[m] = fmaf(mr, A.tp.o[j][m], orr[m]);
+                        oi[m] = fmaf(mim, A.tp.o[j][m], oi[m]);
+                    }
+                }
+                float4 *ct = ctab + lane * 4;
+                ct[0] = make_float4(er[0], ei[0], er[1], ei[1]);
+                ct[1] = make_float4(er[2], ei[2], er[3], ei[3]);
+                ct[2] = make_float4(orr[0], oi[0], orr[1], oi[1]);
+                ct[3] = make_float4(orr[2], oi[2], orr[3], oi[3]);
             }
             __syncthreads();
-            const int nq = (A.np - ps) < kStage ? (A.np - ps) : kStage;
-            for (int q = 0; q < nq; ++q) {
+            if (qs + kSub < nq) load_g(qs + kSub);
+            const int qe = (qs + kSub) < nq ? (qs + kSub) : nq;
+            for (int q = qs; q < qe; ++q) {
                 const float *o = rf + q * kNR;
                 Refs r;
                 r.dtx = o[R_DTX]; r.dty = o[R_DTY]; r.dtz = o[R_DTZ];
@@ -348,22 +390,41 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                 facet_geo<kElc, SPK, STR, GRD>(r, kq, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz,
                                          r.graze != 0, o[R_LHI], o[R_LLO], o[R_FSQ], dop, g, &ta,
                                          &ra, rot);
-                float tap[8], dtap[8];
-                taps_d8(tv, g.f, tap, dtap);
                 // g at samples floor(u) - 3 .. floor(u) + 4
                 const int w0 = g.fl + 4;            // window index of the first tap
                 float br = 0.f, bi = 0.f, dr = 0.f, di = 0.f;
-                if ((unsigned)w0 <= (unsigned)(kGW - 8)) {
-                    const float2 *gw = gwin + q * kGW + w0;
-#pragma unroll
-                    for (int k = 0; k < 8; ++k) {
-                        const float2 v = gw[k];
-                        br = fmaf(v.x, tap[k], br);
-                        bi = fmaf(v.y, tap[k], bi);
-                        dr = fmaf(v.x, dtap[k], dr);
-                        di = fmaf(v.y, dtap[k], di);
-                    }
+                if ((unsigned)w0 < (unsigned)kNI) {
+                    // the tap sum B = P_E(y) + s P_O(y) from the table, and
+                    // its u-derivative dB/du = 2 dB/ds = 4 s P_E' + 2 P_O +
+                    // 4 y P_O' (Horner's rule carrying P and P' together)
+                    const float4 *ct = ctab + ((q - qs) * kNI + w0) * 4;
+                    const float4 e01 = ct[0], e23 = ct[1], o01 = ct[2], o23 = ct[3];
+                    const float sg = fmaf(g.f, 2.0f, -1.0f), y = sg * sg;
+                    float per = fmaf(e23.z, y, e23.x), pei = fmaf(e23.w, y, e23.y);
+                    float der = fmaf(e23.z, y, per), dei = fmaf(e23.w, y, pei);
+                    per = fmaf(per, y, e01.z);
+                    pei = fmaf(pei, y, e01.w);
+                    der = fmaf(der, y, per);
+                    dei = fmaf(dei, y, pei);
+                    per = fmaf(per, y, e01.x);
+                    pei = fmaf(pei, y, e01.y);
+                    float por = fmaf(o23.z, y, o23.x), poi = fmaf(o23.w, y, o23.y);
+                    float dor = fmaf(o23.z, y, por), doi = fmaf(o23.w, y, poi);
+                    por = fmaf(por, y, o01.z);
+                    poi = fmaf(poi, y, o01.w);
+                    dor = fmaf(dor, y, por);
+                    doi = fmaf(doi, y, poi);
+                    por = fmaf(por, y, o01.x);
+                    poi = fmaf(poi, y, o01.y);
+                    br = fmaf(sg, por, per);
+                    bi = fmaf(sg, poi, pei);
+                    dr = 2.0f * fmaf(2.0f, fmaf(sg, der, y * dor), por);
+                    di = 2.0f * fmaf(2.0f, fmaf(sg, dei, y * doi), poi);
                 } else {
+                    TapV tv;
+                    tap_all(A.tp, tv);
+                    float tap[8], dtap[8];
+                    taps_d8(tv, g.f, tap, dtap);
                     const float *gl = gline + 2 * (size_t)(ps + q) * A.N;
 #pragma unroll
                     for (int k = 0; k < 8; ++k) {
@@ -423,6 +484,8 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                     gar = fmaf(T, zbr, gar);
                     gai = fmaf(-T, zbi, gai);
                 }
+            }
+            __syncthreads();   // the sub-stage's table fully read
             }
         }
     }
