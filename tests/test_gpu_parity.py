@@ -258,6 +258,39 @@ def test_adjoint_vs_oracle(torch_cuda, hs):
         assert e < GRAD_TOL, k
 
 
+def test_adjoint_taps_beyond_the_table(torch_cuda, hs):
+    """The adjoint's tap sums come from a per-pulse table that covers first
+    taps 4 samples either side of the block centre's; facets farther away in
+    range read g through the per-tap path.  Heights uniform in +-30 m put
+    range offsets of up to 8 samples (0.268 sample per metre of height in
+    this geometry), so the facets with |z| > 24 m (6.4 samples, more than
+    the table's reach plus a block's half diagonal of 1.1 samples and the
+    centre's fraction) take that path at every pulse, and the rest mostly
+    the table: both against the oracle adjoint, two channels, random g."""
+    torch = torch_cuda
+    say("case: adjoint, 1500 facets with heights to +-30 m, 2 channels, 96 pulses")
+    g = W.harmony_geometry(96, 512, receivers="AB")
+    f = W.scattered_facets(1500, 80.0, seed=31, sigma_v=0.3, sigma_z=0.5)
+    rng = np.random.default_rng(32)
+    f["z"] = rng.uniform(-30.0, 30.0, 1500).astype(np.float32)
+    gi = (rng.standard_normal((2, 96, 512)) + 1j * rng.standard_normal((2, 96, 512)))
+    gi = gi.astype(np.complex64)
+    sim = hs.Simulator(g)
+    d = to_dev(torch, f)
+    plan = sim.plan(d["x"], d["y"], 8.0, box=(-80.01, 80.01, -80.01, 80.01, 30.0, 1.5))
+    gr = sim.backward(plan, d, torch.from_numpy(gi).cuda())
+    torch.cuda.synchronize()
+    ref = O.adjoint(g, f64(f), gi.astype(np.complex128))
+    far = np.abs(f["z"]) > 24.0
+    say(f"facets past the table at every pulse (|z| > 24 m): {int(far.sum())}")
+    assert far.sum() > 200
+    for k in ("z", "vx", "vy", "vz", "a_re", "a_im"):
+        e = O.rel_l2(gr[k].cpu().numpy(), ref[k])
+        ef = O.rel_l2(gr[k].cpu().numpy()[far], ref[k][far])
+        say(f"adjoint {k}: rel-L2 {e:.3e}, far facets {ef:.3e}")
+        assert e < GRAD_TOL and ef < GRAD_TOL, k
+
+
 def test_autograd_vs_oracle_fd(torch_cuda, hs):
     """Loss ||IQ - T||^2 with T from a perturbed current (config-4 form),
     reduced size; GPU autograd against the oracle adjoint and the oracle's
