@@ -59,29 +59,28 @@ bool finite3(const double *v) {
 double norm3(const double *v) { return std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); }
 
 double sinc(double x) {
-    if (x == 0.0) return 1.0;
     const double px = kPi * x;
+    // below 1e-4 the two-term Taylor form is exact in double precision
+    if (std::fabs(px) < 1e-4) return 1.0 - px * px / 6.0;
     return std::sin(px) / px;
 }
 
-// Modified Bessel function I0 from its power series.
+// Modified Bessel function I0 from its integral form, the mean of
+// exp(x cos t) over a period: the integrand is smooth and periodic, so the
+// trapezoidal rule on 64 equal steps converges geometrically (the error
+// terms are I_64(x) and beyond, far below double precision for |x| <= 20).
 double bessel_i0(double x) {
-    double term = 1.0, sum = 1.0;
-    const double q = 0.25 * x * x;
-    for (int k = 1; k < 400; ++k) {
-        term *= q / ((double)k * k);
-        sum += term;
-        if (term < 1e-18 * sum) break;
-    }
-    return sum;
+    constexpr int n = 64;
+    double s = 0.0;
+    for (int k = 0; k < n; ++k) s += std::exp(x * std::cos(2.0 * kPi * k / n));
+    return s / n;
 }
 
-// Kaiser-windowed sinc of half-width 4.
+// The interpolator h(t) = sinc(t) I0(beta sqrt(1 - (t/4)^2)) / I0(beta),
+// zero for |t| > 4: a Kaiser window of half-width 4 over the sinc.
 double kaiser_sinc(double t, double beta, double i0b) {
-    if (std::fabs(t) > 4.0) return 0.0;
-    double s = 1.0 - (t / 4.0) * (t / 4.0);
-    if (s < 0.0) s = 0.0;
-    return sinc(t) * bessel_i0(beta * std::sqrt(s)) / i0b;
+    const double r = 0.25 * t;
+    return (r * r <= 1.0) ? sinc(t) * bessel_i0(beta * std::sqrt(1.0 - r * r)) / i0b : 0.0;
 }
 
 // Least-squares fit of a degree-3 polynomial in y to samples (y_i, v_i).
@@ -153,15 +152,19 @@ double fit_taps(double beta, hs::TapPoly &tp) {
     return err;
 }
 
-// kappa with sinc(kappa / 2)^2 = 1/2 (bisection on (0, 1)).
+// kappa with sinc(kappa / 2)^2 = 1/2: Newton's method on
+// sinc(x) - 1/sqrt(2), whose root lies near 0.443 (sinc decreases there),
+// with d sinc / dx = (cos(pi x) - sinc(x)) / x; kappa = 2 x.
 double half_power_kappa() {
-    double lo = 0.0, hi = 1.0;
     const double target = std::sqrt(0.5);
-    for (int i = 0; i < 200; ++i) {
-        const double mid = 0.5 * (lo + hi);
-        if (sinc(mid) > target) lo = mid; else hi = mid;
+    double x = 0.45;
+    for (int i = 0; i < 50; ++i) {
+        const double sx = sinc(x);
+        const double dx = (sx - target) / ((std::cos(kPi * x) - sx) / x);
+        x -= dx;
+        if (std::fabs(dx) < 1e-17) break;
     }
-    return lo + hi;
+    return 2.0 * x;
 }
 
 void plat_pos(const sim_handle *h, int plat, double t, double *out) {
