@@ -685,8 +685,10 @@ static double sample_pos(const sim_handle *h, int ch, int p, double x, double y,
 // umin, umax of the centres' sample positions at the band's reference pulse
 // (plus a curvature slack of 0.05 sample, far above the grid's error of
 // ~1e-3 for ranges of tens of km and spacings up to km); the migration M,
-// the largest |u(p) - u(p_ref)| over the band's pulses widened by a group on
-// each side (windows of a call need not start on a group boundary);
+// the largest |u(p) - u(p_ref)| over the band's pulses widened by half a
+// group on each side (a call's groups need not start on a group boundary:
+// a unit takes the band of its group's centre pulse, so its 64 lanes reach
+// at most 32 pulses before the band and 31 after it);
 // the halo of facet heights (up to the plan's z bound, 4 m by default) and
 // drift (its speed bound, 2.5 m/s by default, over the band's largest |t|)
 // along the range gradient; E, half a block diagonal along its
@@ -710,8 +712,8 @@ static void band_stats(const sim_handle *h, const hs::Lattice &L, int B, int NB,
     bs.margin.assign((size_t)NB * h->C, 0.0);
     for (int b = 0; b < NB; ++b) {
         const int pref = std::min(b * B * 64 + B * 32, h->Np - 1);
-        const int pa = std::max(0, b * B * 64 - 64);
-        const int pb = std::min(h->Np - 1, (b + 1) * B * 64 + 63);
+        const int pa = std::max(0, b * B * 64 - 32);
+        const int pb = std::min(h->Np - 1, (b + 1) * B * 64 + 31);
         const int pt[5] = {pa, (3 * pa + pb) / 4, (pa + pb) / 2, (pa + 3 * pb) / 4, pb};
         for (int ch = 0; ch < h->C; ++ch) {
             double lo = 1e300, hi = -1e300, m = 0.0, gz = 0.0, gn = 0.0, gh = 0.0;
@@ -754,22 +756,53 @@ static int strip_geometry(const sim_handle *h, PlanGeom &G) {
     Bs.push_back(NG);
     std::sort(Bs.rbegin(), Bs.rend());
     const int wins[4] = {24, 32, 48, 64};
+    // per band and channel the narrowest window (at most wmax) leaving
+    // strips of HEEPS_NARROW_S_MIN samples: bands near the middle of the
+    // dwell, with little drift, take narrower windows, so more waves share a
+    // compute unit (narrower strips cost more work units and window slots)
+    const auto narrowest = [&](const BandStats &st, size_t k, int wmax) {
+        for (int w : wins)
+            if (w >= HEEPS_WIN_MIN && w < wmax &&
+                w - 2.0 * st.margin[k] - 9.0 >= HEEPS_NARROW_S_MIN)
+                return w;
+        return wmax;
+    };
+    // relative cost of a band-channel by window width (measured per band
+    // on the 9.6 s dwell: 32 samples 1.15x the 24-sample time; the one-wave
+    // 48 and 64 estimated from their occupancy)
+    const auto width_cost = [](int w) {
+        return w <= 24 ? 1.0 : (w <= 32 ? 1.15 : (w <= 48 ? 1.6 : 2.0));
+    };
     BandStats bs;
     bool found = false;
     for (int w : wins) {
         if (w < HEEPS_WIN_MIN) continue;
+        // the band lengths leaving S >= 4 at width w; of these the one whose
+        // per-band widths cost least, the longest on a tie (a strip's blocks
+        // stay the same for all groups of its band, which share their facet
+        // records through the L2)
+        double best = 1e300;
         for (int B : Bs) {
             const int NB = (NG + B - 1) / B;
-            band_stats(h, L, B, NB, G.zlim, G.vlim, bs);
+            BandStats cand;
+            band_stats(h, L, B, NB, G.zlim, G.vlim, cand);
             double smin = 1e300;
-            for (double mg : bs.margin) smin = std::min(smin, w - 2.0 * mg - 9.0);
-            if (smin >= 4.0) {
+            for (double mg : cand.margin) smin = std::min(smin, w - 2.0 * mg - 9.0);
+            if (smin < 4.0) continue;
+            double cost = 0.0;
+            for (size_t k = 0; k < cand.margin.size(); ++k)
+                cost += width_cost(narrowest(cand, k, w));
+            cost /= (double)cand.margin.size();
+            if (cost < best - 1e-9) {
+                best = cost;
                 G.win = w;
                 G.B = B;
                 G.NB = NB;
+                bs = cand;
                 found = true;
-                break;
             }
+            // every band at the narrowest width: no shorter band does better
+            if (best <= width_cost(std::max(24, HEEPS_WIN_MIN)) + 1e-9) break;
         }
         if (found) break;
     }
@@ -779,22 +812,11 @@ static int strip_geometry(const sim_handle *h, PlanGeom &G) {
         G.NB = NG;
         band_stats(h, L, G.B, G.NB, G.zlim, G.vlim, bs);
     }
-    // per band and channel the narrowest window (at most G.win) leaving
-    // strips of HEEPS_NARROW_S_MIN samples: bands near the middle of the
-    // dwell, with little drift, take narrower windows, so more waves share a
-    // compute unit (narrower strips cost more work units and window slots)
     G.band.assign((size_t)4 * G.NB * h->C, 0.0);
     G.NS = 1;
     G.win_mask = 0;
     for (size_t k = 0; k < bs.umin.size(); ++k) {
-        int wk = G.win;
-        if (found)
-            for (int w : wins)
-                if (w >= HEEPS_WIN_MIN && w < wk &&
-                    w - 2.0 * bs.margin[k] - 9.0 >= HEEPS_NARROW_S_MIN) {
-                    wk = w;
-                    break;
-                }
+        const int wk = found ? narrowest(bs, k, G.win) : G.win;
         double S = std::max(1.0, wk - 2.0 * bs.margin[k] - 9.0);
         // at most kStripMax strips: wider ones (facets may then leave the
         // window and take the global path)

@@ -445,7 +445,8 @@ def test_strip_windows_hold_every_tap(native, k):
     """The plan's range strips (sim_plan_geometry) against the oracle's FP64
     geometry: facets anywhere in a block (random points of the scene, heights
     and speeds in any direction up to the bounds sim_chunk_box derives from
-    the sea) at random pulses of random bands put all 8 taps inside the
+    the sea) at random pulses of random bands (and of the half groups either
+    side of a band that a unit of the band can reach) put all 8 taps inside the
     window the forward sum gives their block's strip, so none takes the
     global path.  Workload 2 and a chunk of workload 5 (its 9.6 s dwell: the
     largest drift)."""
@@ -490,7 +491,10 @@ def test_strip_windows_hold_every_tap(native, k):
         for _ in range(400):
             b = int(rng.integers(nb))
             ch = int(rng.integers(C))
-            p = int(rng.integers(b * bg * 64, min((b + 1) * bg * 64, g.n_pulses)))
+            # a unit takes the band of its group's centre pulse, so its
+            # lanes reach 32 pulses before the band and 31 after it
+            p = int(rng.integers(max(b * bg * 64 - 32, 0),
+                                 min((b + 1) * bg * 64 + 32, g.n_pulses)))
             pref = min(b * bg * 64 + bg * 32, g.n_pulses - 1)
             x = rng.uniform(bx.x_min, bx.x_max)
             y = rng.uniform(bx.y_min, bx.y_max)
