@@ -26,7 +26,7 @@
 // narrowest strips (samples) a band may take to use a narrower window than
 // the plan's widest
 #ifndef HEEPS_NARROW_S_MIN
-#define HEEPS_NARROW_S_MIN 2.0
+#define HEEPS_NARROW_S_MIN 1.0
 #endif
 // longest segment (blocks): bounds the facet records a work unit streams
 #ifndef HEEPS_SEG_MAX_BLOCKS
