@@ -755,7 +755,7 @@ static int strip_geometry(const sim_handle *h, PlanGeom &G) {
     for (int b = 1; b < NG; b *= 4) Bs.push_back(b);
     Bs.push_back(NG);
     std::sort(Bs.rbegin(), Bs.rend());
-    const int wins[4] = {24, 32, 48, 64};
+    const int wins[5] = {24, 26, 32, 48, 64};
     // per band and channel the narrowest window (at most wmax) leaving
     // strips of HEEPS_NARROW_S_MIN samples: bands near the middle of the
     // dwell, with little drift, take narrower windows, so more waves share a
@@ -768,13 +768,17 @@ static int strip_geometry(const sim_handle *h, PlanGeom &G) {
         return wmax;
     };
     // relative cost of a band-channel by window width (measured per band
-    // on the 9.6 s dwell: 32 samples 1.15x the 24-sample time; the one-wave
-    // 48 and 64 estimated from their occupancy)
+    // on the 9.6 s dwell: 32 samples 1.15x the 24-sample time; 26 samples
+    // keep three workgroups of four waves per compute unit like 24; the
+    // one-wave 48 and 64 estimated from their occupancy)
     const auto width_cost = [](int w) {
-        return w <= 24 ? 1.0 : (w <= 32 ? 1.15 : (w <= 48 ? 1.6 : 2.0));
+        return w <= 24 ? 1.0 : (w <= 26 ? 1.02 : (w <= 32 ? 1.15 : (w <= 48 ? 1.6 : 2.0)));
     };
     BandStats bs;
     bool found = false;
+    // band statistics by band length, made once (they do not depend on w)
+    std::vector<BandStats> stats(Bs.size());
+    std::vector<bool> have(Bs.size(), false);
     for (int w : wins) {
         if (w < HEEPS_WIN_MIN) continue;
         // the band lengths leaving S >= 4 at width w; of these the one whose
@@ -782,10 +786,14 @@ static int strip_geometry(const sim_handle *h, PlanGeom &G) {
         // stay the same for all groups of its band, which share their facet
         // records through the L2)
         double best = 1e300;
-        for (int B : Bs) {
+        for (size_t bi = 0; bi < Bs.size(); ++bi) {
+            const int B = Bs[bi];
             const int NB = (NG + B - 1) / B;
-            BandStats cand;
-            band_stats(h, L, B, NB, G.zlim, G.vlim, cand);
+            if (!have[bi]) {
+                band_stats(h, L, B, NB, G.zlim, G.vlim, stats[bi]);
+                have[bi] = true;
+            }
+            const BandStats &cand = stats[bi];
             double smin = 1e300;
             for (double mg : cand.margin) smin = std::min(smin, w - 2.0 * mg - 9.0);
             if (smin < 4.0) continue;
@@ -1443,7 +1451,7 @@ static int forward_launch(const sim_handle *h, const sim_plan *P, const sim_face
         a.n_groups = r.n_groups = ng;
         // one launch per window width the bands use (each takes the units
         // of its own bands)
-        for (int w : {24, 32, 48, 64}) {
+        for (int w : {24, 26, 32, 48, 64}) {
             if (!(P->win_mask & hs::win_bit(w))) continue;
             HS_HIP(hs::launch_fill_zero((float *)P->counter, hs::kFwdQueues, s), "work queues");
             HS_HIP(hs::launch_forward(a, h->C, w, P->el_const && !h->grid, sp != nullptr, s),

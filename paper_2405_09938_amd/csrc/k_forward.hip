@@ -413,11 +413,12 @@ __device__ __forceinline__ void forward_unit(const FwdArgs &A, float2 *accw, int
 // its own window slot, so the result does not depend on who ran it.
 // Variants that deposit facets one at a time (no pair merge: per-facet
 // elevation factors without speckle or steering) are held to three waves
-// per SIMD (168 VGPRs) where the LDS allows three (24-sample windows); the
-// others take what their registers allow.
+// per SIMD (168 VGPRs) where the LDS allows three (windows of up to 26
+// samples: three workgroups of 53 KB); the others take what their
+// registers allow.
 template <int WIN, bool ELC, bool SPK, bool STR>
 constexpr int fwd_min_waves() {
-    return (WIN <= 24 && !(ELC || SPK || STR)) ? 3 : 1;
+    return (WIN <= 26 && !(ELC || SPK || STR)) ? 3 : 1;
 }
 
 template <int WIN, bool ELC, bool SPK, bool STR, int GRD>
@@ -557,6 +558,7 @@ hipError_t launch_forward(const FwdArgs &a, int C, int win, bool el_const, bool 
         break;
     switch (win) {
         HS_FWD(24)
+        HS_FWD(26)
         HS_FWD(32)
         HS_FWD(48)
         HS_FWD(64)

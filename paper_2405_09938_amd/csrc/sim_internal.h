@@ -66,7 +66,9 @@ struct Lattice {
 // offsets from it, heights and drift).  Each strip's blocks are listed in
 // block order and cut into segments of at most L blocks.
 // Bit of a window width in a plan's mask of the widths its bands use.
-constexpr int win_bit(int W) { return W <= 24 ? 1 : (W <= 32 ? 2 : (W <= 48 ? 4 : 8)); }
+constexpr int win_bit(int W) {
+    return W <= 24 ? 1 : (W <= 26 ? 16 : (W <= 32 ? 2 : (W <= 48 ? 4 : 8)));
+}
 
 struct StripPlan {
     const double *band;         // [NB][C][4]: umin, S, margin (samples), window width W

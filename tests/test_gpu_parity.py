@@ -370,11 +370,11 @@ def test_facets_beyond_the_plan_bounds(torch_cuda, hs):
 
 
 def test_every_window_width_in_one_plan(torch_cuda, hs):
-    """A plan whose bands take all four window widths (workload 5's 9.6 s
-    dwell with plan bounds of 4 m and 10 m/s: 24 samples mid-dwell up to 64
-    at the ends), so the forward runs four launches, with four-wave and
-    one-wave workgroups: rows at the dwell's ends, middle and in between
-    against the oracle, and the same bits on a second launch."""
+    """A plan whose bands take every window width (workload 5's 9.6 s dwell
+    with plan bounds of 4 m and 10 m/s: 24 samples mid-dwell, then 26, 32,
+    48 and 64 towards the ends), so the forward runs five launches, with
+    four-wave and one-wave workgroups: rows at the dwell's ends, middle and
+    in between against the oracle, and the same bits on a second launch."""
     import ctypes
     from paper_2405_09938_amd import _native as N
     torch = torch_cuda
@@ -390,7 +390,7 @@ def test_every_window_width_in_one_plan(torch_cuda, hs):
     assert sim.lib.sim_plan_geometry(sim.handle, 2000, ctypes.byref(bx), 8.0, None, None, None,
                                      None, None, None, None,
                                      bw.ctypes.data_as(ctypes.POINTER(ctypes.c_int))) == 0
-    assert set(np.unique(bw)) == {24, 32, 48, 64}
+    assert set(np.unique(bw)) == {24, 26, 32, 48, 64}
     rng = np.random.default_rng(71)
     n = 2000
     # the widths follow the box's bounds; the facets stay within the FP32
