@@ -314,178 +314,178 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
             };
             load_g(0);
             for (int qs = 0; qs < nq; qs += kSub) {
-            // Coefficient table of the sub-stage's 8 pulses, lane = (pulse,
-            // interval w): with G+_j = g[w + 4 + j] + g[w + 3 - j] and
-            // G-_j = g[w + 4 + j] - g[w + 3 - j] (the samples under taps
-            // j + 4 and 3 - j), the tap sum over the taps' even and odd parts
-            // is sum_j G+_j E_j(y) + s sum_j G-_j O_j(y), so its coefficients
-            // in y are C_E[m] = sum_j G+_j e_j[m] and C_O[m] =
-            // sum_j G-_j o_j[m].
-            {
-                float er[4] = {0.f, 0.f, 0.f, 0.f}, ei[4] = {0.f, 0.f, 0.f, 0.f};
-                float orr[4] = {0.f, 0.f, 0.f, 0.f}, oi[4] = {0.f, 0.f, 0.f, 0.f};
+                // Coefficient table of the sub-stage's 8 pulses, lane = (pulse,
+                // interval w): with G+_j = g[w + 4 + j] + g[w + 3 - j] and
+                // G-_j = g[w + 4 + j] - g[w + 3 - j] (the samples under taps
+                // j + 4 and 3 - j), the tap sum over the taps' even and odd parts
+                // is sum_j G+_j E_j(y) + s sum_j G-_j O_j(y), so its coefficients
+                // in y are C_E[m] = sum_j G+_j e_j[m] and C_O[m] =
+                // sum_j G-_j o_j[m].
+                {
+                    float er[4] = {0.f, 0.f, 0.f, 0.f}, ei[4] = {0.f, 0.f, 0.f, 0.f};
+                    float orr[4] = {0.f, 0.f, 0.f, 0.f}, oi[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const float2 a = gv[4 + j], b = gv[3 - j];
-                    const float pr = a.x + b.x, pim = a.y + b.y;
-                    const float mr = a.x - b.x, mim = a.y - b.y;
+                    for (int j = 0; j < 4; ++j) {
+                        const float2 a = gv[4 + j], b = gv[3 - j];
+                        const float pr = a.x + b.x, pim = a.y + b.y;
+                        const float mr = a.x - b.x, mim = a.y - b.y;
 #pragma unroll
-                    for (int m = 0; m < 4; ++m) {
-                        er[m] = fmaf(pr, A.tp.e[j][m], er[m]);
-                        ei[m] = fmaf(pim, A.tp.e[j][m], ei[m]);
-                        orr[m] = fmaf(mr, A.tp.o[j][m], orr[m]);
-                        oi[m] = fmaf(mim, A.tp.o[j][m], oi[m]);
-                    }
-                }
-                float4 *ct = ctab + lane * 4;
-                ct[0] = make_float4(er[0], ei[0], er[1], ei[1]);
-                ct[1] = make_float4(er[2], ei[2], er[3], ei[3]);
-                ct[2] = make_float4(orr[0], oi[0], orr[1], oi[1]);
-                ct[3] = make_float4(orr[2], oi[2], orr[3], oi[3]);
-            }
-            __syncthreads();
-            if (qs + kSub < nq) load_g(qs + kSub);
-            const int qe = (qs + kSub) < nq ? (qs + kSub) : nq;
-            for (int q = qs; q < qe; ++q) {
-                const float *o = rf + q * kNR;
-                Refs r;
-                r.dtx = o[R_DTX]; r.dty = o[R_DTY]; r.dtz = o[R_DTZ];
-                r.gx = o[R_GX]; r.gy = o[R_GY]; r.gz = o[R_GZ];
-                r.i2rt = o[R_I2RT]; r.i2rr = o[R_I2RR]; r.i2s = o[R_I2S];
-                r.phib = o[R_PHIB]; r.fb = o[R_FB]; r.nb = __float_as_int(o[R_NB]);
-                r.gtaz = o[R_GTAZ]; r.gtel = o[R_GTEL]; r.graz = o[R_GRAZ]; r.grel = o[R_GREL];
-                r.irt = o[R_IRT]; r.irt2 = o[R_IRT2]; r.irr = o[R_IRR]; r.irr2 = o[R_IRR2];
-                r.sb = o[R_SB]; r.sbt = o[R_SBT]; r.sbr = o[R_SBR]; r.mask = o[R_MASK];
-                r.dbt = o[R_DBT]; r.dbr = o[R_DBR]; r.graze = __float_as_int(o[R_GRAZE]);
-                const float tf = o[R_T];
-                // speckle factor x(p) of this pulse and the Doppler phase (cycles)
-                float xr = 1.0f, xi = 0.0f, dop = 0.0f;
-                if constexpr (SPK) {
-                    const int pabs = A.p0 + ps + q, k = pabs & 63;
-                    if (k == 0) {
-                        const float4 yd = an[pabs >> 6];
-                        zr = yd.x;
-                        zi = yd.y;
-                        dxr = yd.z;
-                        dxi = yd.w;
-                    } else {
-                        const float2 e = spk_draw(S.key, sr.id, (uint32_t)pabs, l1);
-                        zr = fmaf(S.b1, zr, e.x);
-                        zi = fmaf(S.b1, zi, e.y);
-                    }
-                    const float K = S.gain[k];
-                    xr = fmaf(K, dxr, zr);
-                    xi = fmaf(K, dxi, zi);
-                    const float dh = sr.fs * tf;
-                    const float dl = fmaf(sr.fs, o[R_TLO], fmaf(sr.fs, tf, -dh));
-                    dop = __builtin_amdgcn_fractf(dh) + dl;
-                }
-                FacetConsts kq = kc;
-                [[maybe_unused]] float4 rot{1.f, 0.f, 1.f, 0.f};
-                if constexpr (STR) {
-                    rot = float4{o[kSt], o[kSt + 1], o[kSt + 2], o[kSt + 3]};
-                    steer_axes(ta, ra, rot.x, rot.y, rot.z, rot.w, kq);
-                }
-                Geo g;
-                facet_geo<kElc, SPK, STR, GRD>(r, kq, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz,
-                                         r.graze != 0, o[R_LHI], o[R_LLO], o[R_FSQ], dop, g, &ta,
-                                         &ra, rot);
-                // g at samples floor(u) - 3 .. floor(u) + 4
-                const int w0 = g.fl + 4;            // window index of the first tap
-                float br = 0.f, bi = 0.f, dr = 0.f, di = 0.f;
-                if ((unsigned)w0 < (unsigned)kNI) {
-                    // the tap sum B = P_E(y) + s P_O(y) from the table, and
-                    // its u-derivative dB/du = 2 dB/ds = 4 s P_E' + 2 P_O +
-                    // 4 y P_O' (Horner's rule carrying P and P' together)
-                    const float4 *ct = ctab + ((q - qs) * kNI + w0) * 4;
-                    const float4 e01 = ct[0], e23 = ct[1], o01 = ct[2], o23 = ct[3];
-                    const float sg = fmaf(g.f, 2.0f, -1.0f), y = sg * sg;
-                    float per = fmaf(e23.z, y, e23.x), pei = fmaf(e23.w, y, e23.y);
-                    float der = fmaf(e23.z, y, per), dei = fmaf(e23.w, y, pei);
-                    per = fmaf(per, y, e01.z);
-                    pei = fmaf(pei, y, e01.w);
-                    der = fmaf(der, y, per);
-                    dei = fmaf(dei, y, pei);
-                    per = fmaf(per, y, e01.x);
-                    pei = fmaf(pei, y, e01.y);
-                    float por = fmaf(o23.z, y, o23.x), poi = fmaf(o23.w, y, o23.y);
-                    float dor = fmaf(o23.z, y, por), doi = fmaf(o23.w, y, poi);
-                    por = fmaf(por, y, o01.z);
-                    poi = fmaf(poi, y, o01.w);
-                    dor = fmaf(dor, y, por);
-                    doi = fmaf(doi, y, poi);
-                    por = fmaf(por, y, o01.x);
-                    poi = fmaf(poi, y, o01.y);
-                    br = fmaf(sg, por, per);
-                    bi = fmaf(sg, poi, pei);
-                    dr = 2.0f * fmaf(2.0f, fmaf(sg, der, y * dor), por);
-                    di = 2.0f * fmaf(2.0f, fmaf(sg, dei, y * doi), poi);
-                } else {
-                    TapV tv;
-                    tap_all(A.tp, tv);
-                    float tap[8], dtap[8];
-                    taps_d8(tv, g.f, tap, dtap);
-                    const float *gl = gline + 2 * (size_t)(ps + q) * A.N;
-#pragma unroll
-                    for (int k = 0; k < 8; ++k) {
-                        const int n = r.nb + g.fl - 3 + k;
-                        if (n >= 0 && n < A.N) {
-                            const float vx = gl[2 * n], vy = gl[2 * n + 1];
-                            br = fmaf(vx, tap[k], br);
-                            bi = fmaf(vy, tap[k], bi);
-                            dr = fmaf(vx, dtap[k], dr);
-                            di = fmaf(vy, dtap[k], di);
+                        for (int m = 0; m < 4; ++m) {
+                            er[m] = fmaf(pr, A.tp.e[j][m], er[m]);
+                            ei[m] = fmaf(pim, A.tp.e[j][m], ei[m]);
+                            orr[m] = fmaf(mr, A.tp.o[j][m], orr[m]);
+                            oi[m] = fmaf(mim, A.tp.o[j][m], oi[m]);
                         }
                     }
+                    float4 *ct = ctab + lane * 4;
+                    ct[0] = make_float4(er[0], ei[0], er[1], ei[1]);
+                    ct[1] = make_float4(er[2], ei[2], er[3], ei[3]);
+                    ct[2] = make_float4(orr[0], oi[0], orr[1], oi[1]);
+                    ct[3] = make_float4(orr[2], oi[2], orr[3], oi[3]);
                 }
-                bi = -bi;     // B = sum conj(g) h
-                di = -di;     // B_u = sum conj(g) dh/du
-                const float T = g.amp;
-                // a x E (x = 1 without speckle)
-                const float axr = SPK ? fmaf(f.ar, xr, -(f.ai * xi)) : f.ar;
-                const float axi = SPK ? fmaf(f.ar, xi, f.ai * xr) : f.ai;
-                const float aer = fmaf(axr, g.cs, -(axi * g.sn));
-                const float aei = fmaf(axr, g.sn, axi * g.cs);
-                // P = B a E
-                const float pr = fmaf(br, aer, -(bi * aei));
-                const float pi = fmaf(br, aei, bi * aer);
-                // Re(B_u a E) T
-                const float bu = fmaf(dr, aer, -(di * aei)) * T;
-                // grad R carries q with the facet's own echo time
-                const float cR = fmaf(pi * T, A.k0, bu * A.fs_cf) * o[R_Q];
-                // grad R = g (1 - c2) + e (1/R_t + 1/R_r) - d_t (c1 - c2),
-                // c1 = (e.d_t)/R_t, c2 = (e.d_r)/R_r, d_r = g - d_t
-                const float c1 = g.at * r.irt, c2 = g.ar * r.irr;
-                const float s1 = r.irt + r.irr, u1 = 1.0f - c2, w1 = c1 - c2;
-                const float grx = fmaf(g.ex, s1, fmaf(r.gx, u1, -(r.dtx * w1)));
-                const float gry = fmaf(g.ey, s1, fmaf(r.gy, u1, -(r.dty * w1)));
-                const float grz = fmaf(g.ez, s1, fmaf(r.gz, u1, -(r.dtz * w1)));
-                const float pm = pr * g.mf;
-                float tgx = o[R_DTGX], tgy = o[R_DTGY], tgz = o[R_DTGZ];
-                if constexpr (!ELC) {
-                    // grad T at the facet, first order in its offset
-                    tgx = fmaf(o[R_J0 + 0], g.ex, fmaf(o[R_J0 + 1], g.ey, fmaf(o[R_J0 + 2], g.ez, tgx)));
-                    tgy = fmaf(o[R_J0 + 3], g.ex, fmaf(o[R_J0 + 4], g.ey, fmaf(o[R_J0 + 5], g.ez, tgy)));
-                    tgz = fmaf(o[R_J0 + 6], g.ex, fmaf(o[R_J0 + 7], g.ey, fmaf(o[R_J0 + 8], g.ez, tgz)));
+                __syncthreads();
+                if (qs + kSub < nq) load_g(qs + kSub);
+                const int qe = (qs + kSub) < nq ? (qs + kSub) : nq;
+                for (int q = qs; q < qe; ++q) {
+                    const float *o = rf + q * kNR;
+                    Refs r;
+                    r.dtx = o[R_DTX]; r.dty = o[R_DTY]; r.dtz = o[R_DTZ];
+                    r.gx = o[R_GX]; r.gy = o[R_GY]; r.gz = o[R_GZ];
+                    r.i2rt = o[R_I2RT]; r.i2rr = o[R_I2RR]; r.i2s = o[R_I2S];
+                    r.phib = o[R_PHIB]; r.fb = o[R_FB]; r.nb = __float_as_int(o[R_NB]);
+                    r.gtaz = o[R_GTAZ]; r.gtel = o[R_GTEL]; r.graz = o[R_GRAZ]; r.grel = o[R_GREL];
+                    r.irt = o[R_IRT]; r.irt2 = o[R_IRT2]; r.irr = o[R_IRR]; r.irr2 = o[R_IRR2];
+                    r.sb = o[R_SB]; r.sbt = o[R_SBT]; r.sbr = o[R_SBR]; r.mask = o[R_MASK];
+                    r.dbt = o[R_DBT]; r.dbr = o[R_DBR]; r.graze = __float_as_int(o[R_GRAZE]);
+                    const float tf = o[R_T];
+                    // speckle factor x(p) of this pulse and the Doppler phase (cycles)
+                    float xr = 1.0f, xi = 0.0f, dop = 0.0f;
+                    if constexpr (SPK) {
+                        const int pabs = A.p0 + ps + q, k = pabs & 63;
+                        if (k == 0) {
+                            const float4 yd = an[pabs >> 6];
+                            zr = yd.x;
+                            zi = yd.y;
+                            dxr = yd.z;
+                            dxi = yd.w;
+                        } else {
+                            const float2 e = spk_draw(S.key, sr.id, (uint32_t)pabs, l1);
+                            zr = fmaf(S.b1, zr, e.x);
+                            zi = fmaf(S.b1, zi, e.y);
+                        }
+                        const float K = S.gain[k];
+                        xr = fmaf(K, dxr, zr);
+                        xi = fmaf(K, dxi, zi);
+                        const float dh = sr.fs * tf;
+                        const float dl = fmaf(sr.fs, o[R_TLO], fmaf(sr.fs, tf, -dh));
+                        dop = __builtin_amdgcn_fractf(dh) + dl;
+                    }
+                    FacetConsts kq = kc;
+                    [[maybe_unused]] float4 rot{1.f, 0.f, 1.f, 0.f};
+                    if constexpr (STR) {
+                        rot = float4{o[kSt], o[kSt + 1], o[kSt + 2], o[kSt + 3]};
+                        steer_axes(ta, ra, rot.x, rot.y, rot.z, rot.w, kq);
+                    }
+                    Geo g;
+                    facet_geo<kElc, SPK, STR, GRD>(r, kq, tf, f.dx, f.dy, f.z, f.vx, f.vy, f.vz,
+                                             r.graze != 0, o[R_LHI], o[R_LLO], o[R_FSQ], dop, g, &ta,
+                                             &ra, rot);
+                    // g at samples floor(u) - 3 .. floor(u) + 4
+                    const int w0 = g.fl + 4;            // window index of the first tap
+                    float br = 0.f, bi = 0.f, dr = 0.f, di = 0.f;
+                    if ((unsigned)w0 < (unsigned)kNI) {
+                        // the tap sum B = P_E(y) + s P_O(y) from the table, and
+                        // its u-derivative dB/du = 2 dB/ds = 4 s P_E' + 2 P_O +
+                        // 4 y P_O' (Horner's rule carrying P and P' together)
+                        const float4 *ct = ctab + ((q - qs) * kNI + w0) * 4;
+                        const float4 e01 = ct[0], e23 = ct[1], o01 = ct[2], o23 = ct[3];
+                        const float sg = fmaf(g.f, 2.0f, -1.0f), y = sg * sg;
+                        float per = fmaf(e23.z, y, e23.x), pei = fmaf(e23.w, y, e23.y);
+                        float der = fmaf(e23.z, y, per), dei = fmaf(e23.w, y, pei);
+                        per = fmaf(per, y, e01.z);
+                        pei = fmaf(pei, y, e01.w);
+                        der = fmaf(der, y, per);
+                        dei = fmaf(dei, y, pei);
+                        per = fmaf(per, y, e01.x);
+                        pei = fmaf(pei, y, e01.y);
+                        float por = fmaf(o23.z, y, o23.x), poi = fmaf(o23.w, y, o23.y);
+                        float dor = fmaf(o23.z, y, por), doi = fmaf(o23.w, y, poi);
+                        por = fmaf(por, y, o01.z);
+                        poi = fmaf(poi, y, o01.w);
+                        dor = fmaf(dor, y, por);
+                        doi = fmaf(doi, y, poi);
+                        por = fmaf(por, y, o01.x);
+                        poi = fmaf(poi, y, o01.y);
+                        br = fmaf(sg, por, per);
+                        bi = fmaf(sg, poi, pei);
+                        dr = 2.0f * fmaf(2.0f, fmaf(sg, der, y * dor), por);
+                        di = 2.0f * fmaf(2.0f, fmaf(sg, dei, y * doi), poi);
+                    } else {
+                        TapV tv;
+                        tap_all(A.tp, tv);
+                        float tap[8], dtap[8];
+                        taps_d8(tv, g.f, tap, dtap);
+                        const float *gl = gline + 2 * (size_t)(ps + q) * A.N;
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) {
+                            const int n = r.nb + g.fl - 3 + k;
+                            if (n >= 0 && n < A.N) {
+                                const float vx = gl[2 * n], vy = gl[2 * n + 1];
+                                br = fmaf(vx, tap[k], br);
+                                bi = fmaf(vy, tap[k], bi);
+                                dr = fmaf(vx, dtap[k], dr);
+                                di = fmaf(vy, dtap[k], di);
+                            }
+                        }
+                    }
+                    bi = -bi;     // B = sum conj(g) h
+                    di = -di;     // B_u = sum conj(g) dh/du
+                    const float T = g.amp;
+                    // a x E (x = 1 without speckle)
+                    const float axr = SPK ? fmaf(f.ar, xr, -(f.ai * xi)) : f.ar;
+                    const float axi = SPK ? fmaf(f.ar, xi, f.ai * xr) : f.ai;
+                    const float aer = fmaf(axr, g.cs, -(axi * g.sn));
+                    const float aei = fmaf(axr, g.sn, axi * g.cs);
+                    // P = B a E
+                    const float pr = fmaf(br, aer, -(bi * aei));
+                    const float pi = fmaf(br, aei, bi * aer);
+                    // Re(B_u a E) T
+                    const float bu = fmaf(dr, aer, -(di * aei)) * T;
+                    // grad R carries q with the facet's own echo time
+                    const float cR = fmaf(pi * T, A.k0, bu * A.fs_cf) * o[R_Q];
+                    // grad R = g (1 - c2) + e (1/R_t + 1/R_r) - d_t (c1 - c2),
+                    // c1 = (e.d_t)/R_t, c2 = (e.d_r)/R_r, d_r = g - d_t
+                    const float c1 = g.at * r.irt, c2 = g.ar * r.irr;
+                    const float s1 = r.irt + r.irr, u1 = 1.0f - c2, w1 = c1 - c2;
+                    const float grx = fmaf(g.ex, s1, fmaf(r.gx, u1, -(r.dtx * w1)));
+                    const float gry = fmaf(g.ey, s1, fmaf(r.gy, u1, -(r.dty * w1)));
+                    const float grz = fmaf(g.ez, s1, fmaf(r.gz, u1, -(r.dtz * w1)));
+                    const float pm = pr * g.mf;
+                    float tgx = o[R_DTGX], tgy = o[R_DTGY], tgz = o[R_DTGZ];
+                    if constexpr (!ELC) {
+                        // grad T at the facet, first order in its offset
+                        tgx = fmaf(o[R_J0 + 0], g.ex, fmaf(o[R_J0 + 1], g.ey, fmaf(o[R_J0 + 2], g.ez, tgx)));
+                        tgy = fmaf(o[R_J0 + 3], g.ex, fmaf(o[R_J0 + 4], g.ey, fmaf(o[R_J0 + 5], g.ez, tgy)));
+                        tgz = fmaf(o[R_J0 + 6], g.ex, fmaf(o[R_J0 + 7], g.ey, fmaf(o[R_J0 + 8], g.ez, tgz)));
+                    }
+                    const float gxv = fmaf(pm, tgx, cR * grx);
+                    const float gyv = fmaf(pm, tgy, cR * gry);
+                    const float gzv = fmaf(pm, tgz, cR * grz);
+                    gz_acc += gzv;
+                    gvx = fmaf(tf, gxv, gvx);
+                    gvy = fmaf(tf, gyv, gvy);
+                    gvz = fmaf(tf, gzv, gvz);
+                    // dL/da = conj(B T E x)
+                    const float zbr = fmaf(br, g.cs, -(bi * g.sn)), zbi = fmaf(br, g.sn, bi * g.cs);
+                    if constexpr (SPK) {
+                        gar = fmaf(T, fmaf(zbr, xr, -(zbi * xi)), gar);
+                        gai = fmaf(-T, fmaf(zbr, xi, zbi * xr), gai);
+                    } else {
+                        gar = fmaf(T, zbr, gar);
+                        gai = fmaf(-T, zbi, gai);
+                    }
                 }
-                const float gxv = fmaf(pm, tgx, cR * grx);
-                const float gyv = fmaf(pm, tgy, cR * gry);
-                const float gzv = fmaf(pm, tgz, cR * grz);
-                gz_acc += gzv;
-                gvx = fmaf(tf, gxv, gvx);
-                gvy = fmaf(tf, gyv, gvy);
-                gvz = fmaf(tf, gzv, gvz);
-                // dL/da = conj(B T E x)
-                const float zbr = fmaf(br, g.cs, -(bi * g.sn)), zbi = fmaf(br, g.sn, bi * g.cs);
-                if constexpr (SPK) {
-                    gar = fmaf(T, fmaf(zbr, xr, -(zbi * xi)), gar);
-                    gai = fmaf(-T, fmaf(zbr, xi, zbi * xr), gai);
-                } else {
-                    gar = fmaf(T, zbr, gar);
-                    gai = fmaf(-T, zbi, gai);
-                }
-            }
-            __syncthreads();   // the sub-stage's table fully read
+                __syncthreads();   // the sub-stage's table fully read
             }
         }
     }
