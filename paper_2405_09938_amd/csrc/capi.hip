@@ -694,9 +694,9 @@ static double sample_pos(const sim_handle *h, int ch, int p, double x, double y,
 // along the range gradient; E, half a block diagonal along its
 // horizontal part.  margin = M + halo + E + 0.5, and the strip width
 // S = W - 2 margin - 9 keeps every tap of the strip's facets inside a window
-// of W samples.  W is the smallest instantiated width and B then the longest
-// band (a strip's blocks stay the same for all its groups, which share the
-// facet records through the L2) leaving S >= 4 in every band.
+// of W samples.  W (the widest window of the plan) is the smallest
+// instantiated width for which some band length leaves S >= 4 in every
+// band; each band then takes its own narrowest width (strip_geometry).
 struct BandStats {
     std::vector<double> umin, umax, margin;   // [NB][C]
 };
