@@ -33,6 +33,10 @@
 #include "sim_device.h"
 #include "spk_device.h"
 
+#ifndef HEEPS_ADJ_SPLIT
+#define HEEPS_ADJ_SPLIT 1
+#endif
+
 namespace hs {
 
 namespace {
@@ -148,6 +152,9 @@ __device__ __forceinline__ void grad_t(const AntArgs &ta, const AntArgs &ra, dou
 template <bool ELC, bool SPK, bool STR, int GRD>
 __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
     constexpr bool kElc = ELC && GRD == 0;   // elevation factors at block centres
+    // the stage's references computed two lanes per pulse (Tx and Rx legs)
+    constexpr bool kSplit = HEEPS_ADJ_SPLIT && kElc && !STR;
+    static_assert(!kSplit || 2 * kStage == 64, "a Tx and an Rx lane per pulse of the stage");
     constexpr int kNR = kNRef<SPK, STR>;
     constexpr int kSt = R_ST0<SPK>;
     __shared__ float4 refs[kStage * kNR / 4];
@@ -213,30 +220,14 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
         }
         for (int ps = 0; ps < A.np; ps += kStage) {
             __syncthreads();   // previous stage fully consumed
-            if (lane < kStage) {
-                const int pl = ps + lane;
-                const bool live = pl < A.np;
-                const PulseRec &P = PR[live ? pl : A.np - 1];
-                // receiver at the block centre's own echo time (optional)
-                double prb[3] = {P.prx[0], P.prx[1], P.prx[2]};
-                double qr = 1.0;
-                if (A.rx_exact) rx_echo(xb, yb, P.ptx, P.prx, P.rref, chn.vr, A.inv_c, prb, qr);
-                [[maybe_unused]] double cst = 1.0, snt = 0.0, csr = 1.0, snr = 0.0;
-                if constexpr (STR) {
-                    cst = P.cst;
-                    snt = P.snt;
-                    csr = P.csr;
-                    snr = P.snr;
-                }
-                Refs r;
-                block_refs<kElc, STR, GRD != 0>(xb, yb, P.ptx, prb, P.rref, ta, ra, chn.rtrr_mid, A.f0_c,
-                                A.fs_c, A.n_ref, live, r, qr, cst, snt, csr, snr);
-                // grad T at the centre
-                const double dt0 = xb - P.ptx[0], dt1 = yb - P.ptx[1], dt2 = -P.ptx[2];
-                const double dr0 = xb - prb[0], dr1 = yb - prb[1], dr2 = -prb[2];
-                float gft[3], gfr[3];
-                const float ft = ant_grad<STR, GRD>(ta, dt0, dt1, dt2, (double)r.irt, gft, cst, snt);
-                const float fr = ant_grad<STR, GRD>(ra, dr0, dr1, dr2, (double)r.irr, gfr, csr, snr);
+            // The stage's references, one pulse per lane of the first half:
+            // the per-pulse records of the facet loop and grad T at the
+            // centre (its Jacobian where the pattern factors are per facet).
+            const auto write_refs = [&](const Refs &r, float ft, const float *gft, float fr,
+                                        const float *gfr, double qr, const PulseRec &P,
+                                        [[maybe_unused]] const double *prb,
+                                        [[maybe_unused]] double cst, [[maybe_unused]] double snt,
+                                        [[maybe_unused]] double csr, [[maybe_unused]] double snr) {
                 float *o = rf + lane * kNR;
                 // spreading at the centre (r.sb also carries the sinc normalisation)
                 const float sbt = (r.mask != 0.0f || r.graze)
@@ -291,6 +282,120 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs A) {
                 o[R_SB] = r.sb; o[R_SBT] = r.sbt; o[R_SBR] = r.sbr; o[R_MASK] = r.mask;
                 o[R_DBT] = r.dbt; o[R_DBR] = r.dbr;
                 o[R_GRAZE] = __int_as_float(r.graze);
+            
+            };
+            if constexpr (kSplit) {
+                // Two lanes per pulse: lanes 0..31 take the Tx leg of pulse
+                // lane, lanes 32..63 the Rx leg of pulse lane - 32 (the FP64
+                // range, direction and pattern work of a leg), and the Rx
+                // leg's results move to the first half, which combines them
+                // in the same operations, in the same order, as block_refs.
+                const int qp = lane & (kStage - 1);
+                const bool rx = lane >= kStage;
+                const int pl = ps + qp;
+                const bool live = pl < A.np;
+                const PulseRec &P = PR[live ? pl : A.np - 1];
+                double prb[3] = {P.prx[0], P.prx[1], P.prx[2]};
+                double qr = 1.0;
+                if (A.rx_exact) rx_echo(xb, yb, P.ptx, P.prx, P.rref, chn.vr, A.inv_c, prb, qr);
+                const AntArgs &an = rx ? ra : ta;
+                const double *pp = rx ? prb : P.ptx;
+                const double d0 = xb - pp[0], d1 = yb - pp[1], d2 = -pp[2];
+                const double R = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+                const double iR = 1.0 / R;
+                const double u0 = d0 * iR, u1 = d1 * iR, u2 = d2 * iR;
+                const double dA = d0 * an.az[0] + d1 * an.az[1] + d2 * an.az[2];
+                const double dB = d0 * an.b[0] + d1 * an.b[1] + d2 * an.b[2];
+                const double dE = d0 * an.el[0] + d1 * an.el[1] + d2 * an.el[2];
+                const float gA = (float)(0.5 * an.ka * dA);
+                const float gE = (float)(0.5 * an.ke * dE);
+                const float y = (float)fabs(0.5 * an.ke * dE * iR) + 1e-9f;
+                const float sy = __builtin_amdgcn_sinf(y);
+                const double mB = dB * iR;
+                float gf[3];
+                const float F = ant_grad<false, 0>(an, d0, d1, d2, (double)(float)iR, gf, 1.0, 0.0);
+                // the Rx leg's values to the Tx lane of the same pulse
+                const double rr = __shfl_down(R, kStage), irr = __shfl_down(iR, kStage);
+                const double ur0 = __shfl_down(u0, kStage), ur1 = __shfl_down(u1, kStage);
+                const double ur2 = __shfl_down(u2, kStage), mr = __shfl_down(mB, kStage);
+                const float dbr = __shfl_down((float)dB, kStage);
+                const float graz = __shfl_down(gA, kStage), grel = __shfl_down(gE, kStage);
+                const float yr = __shfl_down(y, kStage), syr = __shfl_down(sy, kStage);
+                const float fr = __shfl_down(F, kStage);
+                float gfr[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) gfr[k] = __shfl_down(gf[k], kStage);
+                if (!rx) {
+                    const double rt = R, irt = iR, mt = mB;
+                    Refs r;
+                    r.dtx = (float)u0;
+                    r.dty = (float)u1;
+                    r.dtz = (float)u2;
+                    r.gx = (float)(u0 + ur0);
+                    r.gy = (float)(u1 + ur1);
+                    r.gz = (float)(u2 + ur2);
+                    r.i2rt = (float)(0.5 * irt);
+                    r.i2rr = (float)(0.5 * irr);
+                    r.i2s = (float)(0.5 * (irt + irr));
+                    const double rb = rt + rr;
+                    const double cyc = rb * A.f0_c;
+                    r.phib = (float)(rint(cyc) - cyc);
+                    const double lq = qr * A.f0_c;
+                    r.lhi = (float)lq;
+                    r.llo = (float)(lq - (double)r.lhi);
+                    r.fsq = (float)(qr * A.fs_c);
+                    const double ub = A.n_ref + (rb - P.rref) * A.fs_c;
+                    const double fl = floor(ub);
+                    r.fb = (float)(ub - fl);
+                    r.nb = (int)fl;
+                    r.gtaz = gA;
+                    r.graz = graz;
+                    r.gtel = gE;
+                    r.grel = grel;
+                    r.irt = (float)irt;
+                    r.irt2 = (float)(irt * irt);
+                    r.irr = (float)irr;
+                    r.irr2 = (float)(irr * irr);
+                    const double sb = chn.rtrr_mid * irt * irr;
+                    r.dbt = (float)dB;
+                    r.dbr = dbr;
+                    const double margin = 200.0 * (irt > irr ? irt : irr);
+                    const bool front = mt > margin && mr > margin;
+                    const bool behind = mt < -margin || mr < -margin;
+                    r.graze = (live && !front && !behind) ? 1 : 0;
+                    r.mask = (live && front) ? 1.0f : 0.0f;
+                    const float fe = (sy * syr) * __builtin_amdgcn_rcpf((float)(kTwoPi * kTwoPi) * (y * yr));
+                    const double sm = (r.mask != 0.0f || r.graze) ? kInvTwoPi2 * sb * (double)fe : 0.0;
+                    r.sb = (float)sm;
+                    r.sbt = (float)(sm * irt);
+                    r.sbr = (float)(sm * irr);
+                    write_refs(r, F, gf, fr, gfr, qr, P, prb, 1.0, 0.0, 1.0, 0.0);
+                }
+            } else if (lane < kStage) {
+                const int pl = ps + lane;
+                const bool live = pl < A.np;
+                const PulseRec &P = PR[live ? pl : A.np - 1];
+                // receiver at the block centre's own echo time (optional)
+                double prb[3] = {P.prx[0], P.prx[1], P.prx[2]};
+                double qr = 1.0;
+                if (A.rx_exact) rx_echo(xb, yb, P.ptx, P.prx, P.rref, chn.vr, A.inv_c, prb, qr);
+                [[maybe_unused]] double cst = 1.0, snt = 0.0, csr = 1.0, snr = 0.0;
+                if constexpr (STR) {
+                    cst = P.cst;
+                    snt = P.snt;
+                    csr = P.csr;
+                    snr = P.snr;
+                }
+                Refs r;
+                block_refs<kElc, STR, GRD != 0>(xb, yb, P.ptx, prb, P.rref, ta, ra, chn.rtrr_mid, A.f0_c,
+                                A.fs_c, A.n_ref, live, r, qr, cst, snt, csr, snr);
+                // grad T at the centre
+                const double dt0 = xb - P.ptx[0], dt1 = yb - P.ptx[1], dt2 = -P.ptx[2];
+                const double dr0 = xb - prb[0], dr1 = yb - prb[1], dr2 = -prb[2];
+                float gft[3], gfr[3];
+                const float ft = ant_grad<STR, GRD>(ta, dt0, dt1, dt2, (double)r.irt, gft, cst, snt);
+                const float fr = ant_grad<STR, GRD>(ra, dr0, dr1, dr2, (double)r.irr, gfr, csr, snr);
+                write_refs(r, ft, gft, fr, gfr, qr, P, prb, cst, snt, csr, snr);
             }
             __syncthreads();
             // The samples of g under lane (pulse qs + lane / 8, interval
